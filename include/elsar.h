@@ -1,0 +1,187 @@
+/*
+ * elsar.h -- C ABI of the MI355X (gfx950) learned-partition sort.
+ *
+ * The library sorts n fixed-length records by their leading key bytes in
+ * memcmp order, equal keys in input order, the way ELSAR does (Kristo and
+ * Kraska, "Parallel External Sorting of ASCII Records Using Learned Models"):
+ * a CDF model fitted on a sample of the keys (Section 3.1) places every record
+ * in one of B mutually exclusive, monotonic, equi-depth buckets (Section 3.3,
+ * Equation 1); each bucket is sorted on its own (Section 3.4); the sorted
+ * buckets are written at the exclusive prefix sums of their sizes
+ * (Section 3.5), so the output is a plain concatenation with no merge.
+ *
+ * Conventions for every call:
+ *  - Device pointers ("d_") are HIP device memory on the current device; host
+ *    pointers ("h_") are host memory.  The caller owns every buffer it passes;
+ *    the library owns only elsar_model objects (and their device storage).
+ *  - Record buffers are n * record_bytes bytes, 16-byte aligned; record i is at
+ *    byte i * record_bytes.  record_bytes is a multiple of 4 and >= 40;
+ *    8 <= key_bytes <= 12 (the tuned shape is 100-byte records, 10-byte keys).
+ *  - n < 2^32 for every call that takes records on the device, and at most
+ *    ELSAR_MAX_DEVICE_RECORDS for one in-HBM sort.
+ *  - Work is enqueued on `stream` and runs asynchronously unless a call says
+ *    otherwise.  Argument errors are returned before anything is enqueued;
+ *    a failed HIP launch returns ELSAR_E_HIP.  On error the outputs are
+ *    unspecified, and nothing outside the buffers passed in is written.
+ *  - No exception crosses the ABI.  Calls on different models/buffers may run
+ *    concurrently; calls that share a buffer must be ordered by the caller.
+ */
+#ifndef ELSAR_H
+#define ELSAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ELSAR_MAX_DEVICE_RECORDS 1000000000ull
+
+typedef enum {
+  ELSAR_OK = 0,
+  ELSAR_E_INVALID_ARG = 1,     /* null pointer, bad size or alignment, bad parameter */
+  ELSAR_E_NO_MEMORY = 2,       /* workspace or partition buffer too small, or allocation failed */
+  ELSAR_E_HIP = 3,             /* a HIP runtime call or kernel launch failed */
+  ELSAR_E_UNSUPPORTED = 4,     /* shape outside the supported range (e.g. n too large) */
+  ELSAR_E_MODEL_REJECTED = 5   /* the learned model failed its acceptance test (RMI kept) */
+} elsar_status;
+
+typedef enum {
+  ELSAR_MODEL_RMI = 0,  /* two-level RMI: linear root, linear-spline leaves */
+  ELSAR_MODEL_MLP = 1,  /* monotone MLP root over the same leaves */
+  ELSAR_MODEL_AUTO = 2  /* MLP if it passes the acceptance test, else RMI */
+} elsar_model_kind;
+
+/* Fit parameters.  Zero fields take the defaults noted. */
+typedef struct {
+  uint32_t record_bytes;  /* record length R (100) */
+  uint32_t key_bytes;     /* key length K (10) */
+  uint32_t num_buckets;   /* B, the paper's f; 0: largest power of two <= n/950, in [1, 2^21] */
+  uint32_t num_leaves;    /* L; 0: max(1, B/16) */
+  uint64_t sample_size;   /* S; 0: min(max(ceil(n/100), 1024), 10^7, n) (Section 3.1, Section 6) */
+  uint64_t seed;          /* seed of the sampler's Philox4x32-10 draws */
+  uint32_t kind;          /* elsar_model_kind */
+  float accept_ratio;     /* MLP accepted if its largest sample bucket <= ratio * ideal; 0: 1.5 */
+  uint32_t mlp_steps;     /* Adam steps of the MLP fit; 0: default */
+  uint32_t region_pct;    /* bucket j's region holds ceil(region_pct/100 * max(n*h_j/S, n/B)) + 16
+                             records (h_j: sample keys in bucket j), the rest spills; 0: 125 */
+} elsar_fit_params;
+
+/* Fills *p with the defaults for 100-byte records with 10-byte keys. */
+elsar_status elsar_fit_params_default(elsar_fit_params* p);
+
+typedef struct elsar_model elsar_model;
+
+/* Resolves the automatic parameters for n records (B, L, S) and allocates the
+ * model's device storage on the current device.  Synchronous. */
+elsar_status elsar_model_create(const elsar_fit_params* p, uint64_t n, elsar_model** out);
+void elsar_model_destroy(elsar_model* m);
+
+/* Device workspace elsar_sample_fit needs for n records (the sample, its sort
+ * buffers and the fit's partial sums). */
+elsar_status elsar_fit_workspace_size(const elsar_model* m, uint64_t n, size_t* bytes);
+
+/*
+ * Section 3.1: draws the sample (stratified, uniform within strata), sorts its
+ * base-95 codes (Section 4, first 8 key bytes, saturating outside
+ * 0x20..0x7E) and fits the monotone RMI -- root: least squares of L*rank/S on
+ * the FP32 code, slope >= 0; leaf j: the line through its first and last
+ * sample mapped to B*rank/S, clamped to the buckets its sample ranks span.
+ * d_records: n records on the device.  d_ws: elsar_fit_workspace_size bytes.
+ * The model's parameters live on the device; the call is asynchronous.
+ */
+elsar_status elsar_sample_fit(elsar_model* m, const void* d_records, uint64_t n, void* d_ws, size_t ws_bytes,
+                              hipStream_t stream);
+
+/* Bytes of the partition buffer elsar_partition fills for n records. */
+elsar_status elsar_partition_size(const elsar_model* m, uint64_t n, size_t* part_bytes);
+
+/*
+ * Section 3.3 / Algorithm 1's reader loop: places every record in bucket
+ * F(encode(key)) (Equation 1 holds for the buckets: every key of bucket j is
+ * <= every key of bucket j+1), counts the bucket sizes S_p and writes
+ * d_bucket_offsets[j] = sum_{k<j} S_k for j = 0..B (u64; d_bucket_offsets[B] = n),
+ * the output offsets of Section 3.5.
+ * d_part: elsar_partition_size bytes, opaque; it holds each record with its
+ * input index, grouped by bucket (in no order within a bucket).
+ * d_bucket_offsets: B + 1 u64 on the device.  Asynchronous.
+ */
+elsar_status elsar_partition(const elsar_model* m, const void* d_records, uint64_t n, void* d_part,
+                             size_t part_bytes, uint64_t* d_bucket_offsets, hipStream_t stream);
+
+/*
+ * Sections 3.4-3.5: sorts every bucket of d_part by (key in memcmp order, input
+ * index) and writes it to d_out + record_bytes * d_bucket_offsets[j].
+ * d_out: n records on the device; it may be the input of elsar_partition (the
+ * sort is then in place) but must not overlap d_part.  Asynchronous.
+ */
+elsar_status elsar_sort_buckets(const elsar_model* m, const void* d_part, size_t part_bytes, uint64_t n,
+                                const uint64_t* d_bucket_offsets, void* d_out, hipStream_t stream);
+
+/* Workspace of elsar_sort for n records. */
+elsar_status elsar_sort_workspace_size(const elsar_fit_params* p, uint64_t n, size_t* bytes);
+
+/*
+ * The whole method on device-resident records: sample + fit, partition, sort
+ * and concatenate.  d_out may equal d_in (in place).  d_ws: at least
+ * elsar_sort_workspace_size bytes; it holds the model, the partition buffer and
+ * the offsets.  Asynchronous; no host synchronisation inside.
+ */
+elsar_status elsar_sort(const void* d_in, uint64_t n, void* d_out, const elsar_fit_params* p, void* d_ws,
+                        size_t ws_bytes, hipStream_t stream);
+
+/* What a fitted model looks like; synchronises with the device. */
+typedef struct {
+  uint32_t kind_used;        /* elsar_model_kind actually in use (RMI or MLP) */
+  uint32_t mlp_rejected;     /* 1 if an MLP was fitted and failed the acceptance test */
+  uint32_t num_buckets, num_leaves;
+  uint64_t sample_size;
+  uint64_t n_fit;
+  float root_a0, root_a1;    /* linear root (leaf units): floor(fmaf(a1, x, a0)) */
+  uint32_t max_sample_bucket, opt_sample_bucket;  /* acceptance statistics (MLP fits) */
+} elsar_model_info;
+
+elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info);
+
+/* Copies the leaf table to host arrays of num_leaves entries each (any may be
+ * NULL).  Synchronises. */
+elsar_status elsar_model_leaves(const elsar_model* m, uint64_t* h_base, float* h_slope, float* h_icpt,
+                                uint32_t* h_lo, uint32_t* h_hi);
+
+/* Statistics of the last partition in d_part; synchronises. */
+typedef struct {
+  uint64_t n;
+  uint32_t num_buckets;
+  uint32_t spill_count;      /* records that overflowed their bucket's region */
+  uint32_t mid_buckets;      /* buckets sorted by the large LDS kernel */
+  uint32_t big_buckets;      /* buckets sorted through global memory */
+  uint32_t max_bucket;       /* largest bucket */
+  uint32_t reserved;
+} elsar_partition_stats;
+
+elsar_status elsar_partition_stats_get(const elsar_model* m, const void* d_part, size_t part_bytes,
+                                       elsar_partition_stats* st);
+
+/* Phase timing: when enabled (which also resets it), the library records HIP
+ * events around each phase on the stream it launches on; elsar_timings_get
+ * synchronises and returns the mean milliseconds per call of each phase. */
+typedef struct {
+  float sample_fit_ms;   /* sample, sample sort, fit, capacities */
+  float partition_ms;    /* the partition kernel */
+  float scan_ms;         /* offsets, spill fix-up */
+  float bucket_sort_ms;  /* in-bucket sort + concatenation (all bucket kernels) */
+  float total_ms;        /* first to last recorded boundary of a call */
+  uint32_t calls;        /* calls averaged over (the last 512 since enabling) */
+} elsar_timings;
+
+elsar_status elsar_set_timing(int enabled);
+elsar_status elsar_timings_get(elsar_timings* t);
+
+const char* elsar_status_string(elsar_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ELSAR_H */

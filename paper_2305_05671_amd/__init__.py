@@ -1,0 +1,273 @@
+"""Python binding of libelsar.so, the MI355X (gfx950) learned-partition sort.
+
+Argument marshalling only: every step of the sort runs in the library's HIP
+kernels.  PyTorch provides device memory (uint8 tensors on ``cuda``) and the
+current stream.  Importing this package on a machine without the built library
+raises; there is no CPU fallback.
+
+Names follow the C ABI in ``include/elsar.h``:
+
+* :func:`elsar_sort` -- the whole method (sample + fit, partition, in-bucket
+  sort, concatenation) on device-resident records.
+* :class:`Model` -- ``elsar_model_create`` / ``elsar_sample_fit`` /
+  ``elsar_partition`` / ``elsar_sort_buckets`` step by step, plus inspection.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libelsar.so")
+
+RMI, MLP, AUTO = 0, 1, 2
+OK, E_INVALID_ARG, E_NO_MEMORY, E_HIP, E_UNSUPPORTED, E_MODEL_REJECTED = range(6)
+
+
+class FitParams(ctypes.Structure):
+    _fields_ = [
+        ("record_bytes", ctypes.c_uint32),
+        ("key_bytes", ctypes.c_uint32),
+        ("num_buckets", ctypes.c_uint32),
+        ("num_leaves", ctypes.c_uint32),
+        ("sample_size", ctypes.c_uint64),
+        ("seed", ctypes.c_uint64),
+        ("kind", ctypes.c_uint32),
+        ("accept_ratio", ctypes.c_float),
+        ("mlp_steps", ctypes.c_uint32),
+        ("region_pct", ctypes.c_uint32),
+    ]
+
+
+class ModelInfo(ctypes.Structure):
+    _fields_ = [
+        ("kind_used", ctypes.c_uint32),
+        ("mlp_rejected", ctypes.c_uint32),
+        ("num_buckets", ctypes.c_uint32),
+        ("num_leaves", ctypes.c_uint32),
+        ("sample_size", ctypes.c_uint64),
+        ("n_fit", ctypes.c_uint64),
+        ("root_a0", ctypes.c_float),
+        ("root_a1", ctypes.c_float),
+        ("max_sample_bucket", ctypes.c_uint32),
+        ("opt_sample_bucket", ctypes.c_uint32),
+    ]
+
+
+class PartitionStats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint64),
+        ("num_buckets", ctypes.c_uint32),
+        ("spill_count", ctypes.c_uint32),
+        ("mid_buckets", ctypes.c_uint32),
+        ("big_buckets", ctypes.c_uint32),
+        ("max_bucket", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class Timings(ctypes.Structure):
+    _fields_ = [
+        ("sample_fit_ms", ctypes.c_float),
+        ("partition_ms", ctypes.c_float),
+        ("scan_ms", ctypes.c_float),
+        ("bucket_sort_ms", ctypes.c_float),
+        ("total_ms", ctypes.c_float),
+        ("calls", ctypes.c_uint32),
+    ]
+
+
+class ElsarError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn} failed: {status_string(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+_U64 = ctypes.c_uint64
+_SZ = ctypes.c_size_t
+
+
+def lib():
+    """Load libelsar.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        st = ctypes.c_int
+        sig = {
+            "elsar_fit_params_default": ([ctypes.POINTER(FitParams)], st),
+            "elsar_model_create": ([ctypes.POINTER(FitParams), _U64, ctypes.POINTER(_P)], st),
+            "elsar_model_destroy": ([_P], None),
+            "elsar_fit_workspace_size": ([_P, _U64, ctypes.POINTER(_SZ)], st),
+            "elsar_sample_fit": ([_P, _P, _U64, _P, _SZ, _P], st),
+            "elsar_partition_size": ([_P, _U64, ctypes.POINTER(_SZ)], st),
+            "elsar_partition": ([_P, _P, _U64, _P, _SZ, _P, _P], st),
+            "elsar_sort_buckets": ([_P, _P, _SZ, _U64, _P, _P, _P], st),
+            "elsar_sort_workspace_size": ([ctypes.POINTER(FitParams), _U64, ctypes.POINTER(_SZ)], st),
+            "elsar_sort": ([_P, _U64, _P, ctypes.POINTER(FitParams), _P, _SZ, _P], st),
+            "elsar_model_info_get": ([_P, ctypes.POINTER(ModelInfo)], st),
+            "elsar_model_leaves": ([_P, _P, _P, _P, _P, _P], st),
+            "elsar_partition_stats_get": ([_P, _P, _SZ, ctypes.POINTER(PartitionStats)], st),
+            "elsar_set_timing": ([ctypes.c_int], st),
+            "elsar_timings_get": ([ctypes.POINTER(Timings)], st),
+            "elsar_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().elsar_status_string(s).decode()
+
+
+def _check(fn: str, s: int):
+    if s != OK:
+        raise ElsarError(fn, s)
+
+
+def fit_params(record_bytes=100, key_bytes=10, num_buckets=0, num_leaves=0, sample_size=0, seed=0,
+               kind=RMI, accept_ratio=1.5, mlp_steps=0, region_pct=0) -> FitParams:
+    p = FitParams()
+    _check("elsar_fit_params_default", lib().elsar_fit_params_default(ctypes.byref(p)))
+    p.record_bytes, p.key_bytes = record_bytes, key_bytes
+    p.num_buckets, p.num_leaves = num_buckets, num_leaves
+    p.sample_size, p.seed, p.kind = sample_size, seed, kind
+    p.accept_ratio, p.mlp_steps = accept_ratio, mlp_steps
+    p.region_pct = region_pct
+    return p
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dev_bytes(nbytes: int, device):
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _check_records(t, record_bytes):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("records must be a contiguous uint8 CUDA tensor")
+    if t.numel() % record_bytes:
+        raise ValueError("tensor size is not a whole number of records")
+    return t.numel() // record_bytes
+
+
+def sort_workspace_size(n: int, params: FitParams) -> int:
+    sz = _SZ()
+    _check("elsar_sort_workspace_size", lib().elsar_sort_workspace_size(ctypes.byref(params), n, ctypes.byref(sz)))
+    return sz.value
+
+
+def elsar_sort(records, out=None, params: FitParams | None = None, workspace=None, stream=None):
+    """Sort device-resident records (uint8 tensor of n*R bytes) into ``out``
+    (a new tensor unless given; may be ``records`` itself for in place)."""
+    params = params or fit_params()
+    n = _check_records(records, params.record_bytes)
+    if out is None:
+        import torch
+        out = torch.empty_like(records)
+    if _check_records(out, params.record_bytes) != n:
+        raise ValueError("out must hold n records")
+    need = sort_workspace_size(n, params)
+    if workspace is None or workspace.numel() < need:
+        workspace = _dev_bytes(need, records.device)
+    _check("elsar_sort", lib().elsar_sort(records.data_ptr(), n, out.data_ptr(), ctypes.byref(params),
+                                          workspace.data_ptr(), workspace.numel(), _stream(stream)))
+    return out
+
+
+class Model:
+    """elsar_model: fit, partition and sort step by step."""
+
+    def __init__(self, n: int, params: FitParams | None = None):
+        self.params = params or fit_params()
+        self.n = n
+        h = _P()
+        _check("elsar_model_create", lib().elsar_model_create(ctypes.byref(self.params), n, ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.elsar_model_destroy(h)
+            self._h = None
+
+    def sample_fit(self, records, workspace=None, stream=None):
+        n = _check_records(records, self.params.record_bytes)
+        sz = _SZ()
+        _check("elsar_fit_workspace_size", lib().elsar_fit_workspace_size(self._h, n, ctypes.byref(sz)))
+        if workspace is None or workspace.numel() < sz.value:
+            workspace = _dev_bytes(sz.value, records.device)
+        _check("elsar_sample_fit", lib().elsar_sample_fit(self._h, records.data_ptr(), n, workspace.data_ptr(),
+                                                          workspace.numel(), _stream(stream)))
+        self._fit_ws = workspace  # keep alive until the stream has used it
+        return self
+
+    def partition_size(self, n: int) -> int:
+        sz = _SZ()
+        _check("elsar_partition_size", lib().elsar_partition_size(self._h, n, ctypes.byref(sz)))
+        return sz.value
+
+    def partition(self, records, part=None, offsets=None, stream=None):
+        import torch
+        n = _check_records(records, self.params.record_bytes)
+        need = self.partition_size(n)
+        if part is None or part.numel() < need:
+            part = _dev_bytes(need, records.device)
+        B = self.info().num_buckets
+        if offsets is None:
+            offsets = torch.empty(B + 1, dtype=torch.int64, device=records.device)
+        _check("elsar_partition", lib().elsar_partition(self._h, records.data_ptr(), n, part.data_ptr(),
+                                                        part.numel(), offsets.data_ptr(), _stream(stream)))
+        return part, offsets
+
+    def sort_buckets(self, part, offsets, n: int, out, stream=None):
+        _check("elsar_sort_buckets", lib().elsar_sort_buckets(self._h, part.data_ptr(), part.numel(), n,
+                                                              offsets.data_ptr(), out.data_ptr(),
+                                                              _stream(stream)))
+        return out
+
+    def info(self) -> ModelInfo:
+        i = ModelInfo()
+        _check("elsar_model_info_get", lib().elsar_model_info_get(self._h, ctypes.byref(i)))
+        return i
+
+    def leaves(self):
+        import numpy as np
+        L = self.info().num_leaves
+        base = np.zeros(L, np.uint64)
+        c = np.zeros(L, np.float32)
+        b = np.zeros(L, np.float32)
+        lo = np.zeros(L, np.uint32)
+        hi = np.zeros(L, np.uint32)
+        _check("elsar_model_leaves", lib().elsar_model_leaves(self._h, base.ctypes.data, c.ctypes.data,
+                                                              b.ctypes.data, lo.ctypes.data, hi.ctypes.data))
+        return base, c, b, lo, hi
+
+    def partition_stats(self, part) -> PartitionStats:
+        s = PartitionStats()
+        _check("elsar_partition_stats_get", lib().elsar_partition_stats_get(self._h, part.data_ptr(), part.numel(),
+                                                                            ctypes.byref(s)))
+        return s
+
+
+def set_timing(enabled: bool) -> None:
+    _check("elsar_set_timing", lib().elsar_set_timing(1 if enabled else 0))
+
+
+def timings() -> Timings:
+    t = Timings()
+    _check("elsar_timings_get", lib().elsar_timings_get(ctypes.byref(t)))
+    return t

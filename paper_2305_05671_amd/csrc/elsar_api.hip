@@ -1,0 +1,485 @@
+// Host runtime of the C ABI in include/elsar.h: parameter resolution,
+// workspace and partition-buffer layout, launch order and phase timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/elsar.h"
+#include "elsar_internal.h"
+
+using namespace elsar;
+
+struct elsar_model {
+  elsar_fit_params p;  // resolved parameters
+  uint32_t B, L;
+  uint64_t S, n;
+  void* dev;           // owned allocation (null for a model placed in a workspace)
+  ModelHeader* hdr;
+  Leaf* leaves;
+  uint32_t* hist;      // sample keys per bucket (B)
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+uint64_t default_sample_size(uint64_t n) {
+  uint64_t s = (n + 99) / 100;
+  s = std::max<uint64_t>(s, 1024);
+  s = std::min<uint64_t>(s, 10000000ull);
+  return std::min<uint64_t>(s, n);
+}
+
+uint32_t default_buckets(uint64_t n) {
+  uint64_t t = n / 950;
+  uint32_t b = 1;
+  while ((uint64_t)b * 2 <= t && b < kMaxBuckets) b *= 2;
+  return b;
+}
+
+elsar_status check_params(const elsar_fit_params* p) {
+  if (!p) return ELSAR_E_INVALID_ARG;
+  if (p->record_bytes % 4 != 0 || p->record_bytes < 40) return ELSAR_E_UNSUPPORTED;
+  if (p->key_bytes < kMinKeyBytes || p->key_bytes > kMaxKeyBytes || p->key_bytes > p->record_bytes)
+    return ELSAR_E_UNSUPPORTED;
+  if (p->num_buckets > kMaxBuckets) return ELSAR_E_INVALID_ARG;
+  if (p->num_leaves > (1u << 22)) return ELSAR_E_INVALID_ARG;
+  if (p->kind > ELSAR_MODEL_AUTO) return ELSAR_E_INVALID_ARG;
+  if (p->sample_size > 10000000ull * 4) return ELSAR_E_INVALID_ARG;
+  if (p->region_pct > 1000) return ELSAR_E_INVALID_ARG;
+  return ELSAR_OK;
+}
+
+// Resolved shape of a model for n records.
+struct Shape {
+  uint32_t B, L;
+  uint64_t S;
+};
+
+elsar_fit_params with_defaults(const elsar_fit_params& p) {
+  elsar_fit_params q = p;
+  if (q.region_pct == 0) q.region_pct = 125;
+  if (q.accept_ratio <= 0.0f) q.accept_ratio = 1.5f;
+  return q;
+}
+
+Shape resolve(const elsar_fit_params& p, uint64_t n) {
+  Shape s;
+  s.B = p.num_buckets ? p.num_buckets : default_buckets(n);
+  s.L = p.num_leaves ? p.num_leaves : std::max<uint32_t>(1, s.B / 16);
+  s.S = p.sample_size ? std::min<uint64_t>(p.sample_size, n) : default_sample_size(n);
+  if (n > 0 && s.S == 0) s.S = 1;
+  return s;
+}
+
+size_t model_dev_bytes(uint32_t L, uint32_t B) {
+  return align_up(sizeof(ModelHeader)) + align_up((size_t)L * sizeof(Leaf)) + align_up((size_t)B * 4);
+}
+
+void place_model(elsar_model* m, void* base) {
+  uint8_t* b = static_cast<uint8_t*>(base);
+  m->hdr = reinterpret_cast<ModelHeader*>(b);
+  b += align_up(sizeof(ModelHeader));
+  m->leaves = reinterpret_cast<Leaf*>(b);
+  b += align_up((size_t)m->L * sizeof(Leaf));
+  m->hist = reinterpret_cast<uint32_t*>(b);
+}
+
+size_t fit_ws_bytes(uint64_t S) {
+  return 2 * align_up((size_t)S * 8) + align_up(radix_u64_scratch_bytes(S)) + align_up(fit_scratch_bytes(S));
+}
+
+PartLayout part_layout(uint64_t n, uint32_t B, uint32_t R, uint32_t region_pct) {
+  PartLayout lay{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  lay.header = take(sizeof(PartHeader));
+  lay.counts = take((size_t)B * 4);
+  lay.caps = take((size_t)B * 4);
+  lay.rstart = take((size_t)B * 4);
+  lay.spill_off = take((size_t)B * 4);
+  lay.mid_list = take((size_t)B * 4);
+  lay.big_list = take((size_t)B * 4);
+  lay.spill_meta = take((size_t)n * 8);
+  lay.spill_map = take((size_t)n * 4);
+  // regions: sum_j ceil(f * max(n h_j / S, n / B)) + 17 <= 2 f n + 18 B,  f = region_pct / 100
+  lay.cap_slots = (n * 2 * region_pct + 99) / 100 + 18ull * B + 16;
+  lay.total_slots = lay.cap_slots + n;
+  lay.slot_bytes = R + 4;
+  lay.slots = take((size_t)lay.total_slots * lay.slot_bytes);
+  lay.bytes = off;
+  return lay;
+}
+
+// ------------------------------------------------------------ phase timing --
+constexpr int kTimedPhases = 5;  // boundaries: start, fit, partition, scan, sort
+constexpr int kTimingSlots = 512;
+
+struct Timing {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // kTimingSlots * kTimedPhases
+  std::vector<uint8_t> have;   // which boundaries of a slot were recorded
+  int next = 0, used = 0;
+} g_timing;
+
+struct PhaseMarks {  // events of the current call, or nulls when timing is off
+  hipEvent_t e[kTimedPhases] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int slot = -1;
+};
+
+PhaseMarks begin_marks() {
+  PhaseMarks pm;
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  if (!g_timing.on) return pm;
+  pm.slot = g_timing.next;
+  g_timing.next = (g_timing.next + 1) % kTimingSlots;
+  g_timing.used = std::min(g_timing.used + 1, kTimingSlots);
+  g_timing.have[pm.slot] = 0;
+  for (int i = 0; i < kTimedPhases; ++i) pm.e[i] = g_timing.ev[pm.slot * kTimedPhases + i];
+  return pm;
+}
+
+void mark(PhaseMarks& pm, int i, hipStream_t st) {
+  if (pm.slot < 0) return;
+  if (hipEventRecord(pm.e[i], st) == hipSuccess) g_timing.have[pm.slot] |= (uint8_t)(1u << i);
+}
+
+#define HIP_TRY(x)                                  \
+  do {                                              \
+    if ((x) != hipSuccess) return ELSAR_E_HIP;      \
+  } while (0)
+
+// --------------------------------------------------------------- pipeline --
+elsar_status do_fit(elsar_model* m, const void* d_records, uint64_t n, void* d_ws, size_t ws_bytes,
+                    hipStream_t st) {
+  if (n == 0) return ELSAR_OK;
+  const uint64_t S = m->S;
+  if (ws_bytes < fit_ws_bytes(S)) return ELSAR_E_NO_MEMORY;
+  uint8_t* w = static_cast<uint8_t*>(d_ws);
+  uint64_t* codes = reinterpret_cast<uint64_t*>(w);
+  uint64_t* tmp = reinterpret_cast<uint64_t*>(w + align_up(S * 8));
+  void* rscr = w + 2 * align_up(S * 8);
+  void* fscr = w + 2 * align_up(S * 8) + align_up(radix_u64_scratch_bytes(S));
+  HIP_TRY(launch_sample_codes(static_cast<const uint8_t*>(d_records), n, m->p.record_bytes, S, m->p.seed, codes,
+                              st));
+  uint64_t* sorted = nullptr;
+  // codes < 95^8 < 2^53: bytes 0..6 carry the value
+  HIP_TRY(launch_radix_sort_u64(codes, tmp, S, 0, 6, rscr, st, &sorted));
+  HIP_TRY(launch_fit_rmi(sorted, S, n, m->L, m->B, m->hdr, m->leaves, fscr, st));
+  HIP_TRY(launch_sample_hist(m->hdr, m->leaves, sorted, S, m->B, m->hist, st));
+  m->n = n;
+  return ELSAR_OK;
+}
+
+elsar_status do_partition(const elsar_model* m, const void* d_records, uint64_t n, void* d_part,
+                          size_t part_bytes, uint64_t* d_offsets, hipStream_t st, PhaseMarks* pm) {
+  PartLayout lay = part_layout(n, m->B, m->p.record_bytes, m->p.region_pct);
+  if (lay.total_slots >= (1ull << 32)) return ELSAR_E_UNSUPPORTED;  // slot indices are 32-bit
+  if (part_bytes < lay.bytes) return ELSAR_E_NO_MEMORY;
+  uint8_t* part = static_cast<uint8_t*>(d_part);
+  HIP_TRY(launch_capacities(m->hist, m->S, n, m->B, m->p.region_pct, part, lay, st));
+  if (pm) mark(*pm, 1, st);
+  HIP_TRY(launch_partition(m->hdr, m->leaves, static_cast<const uint8_t*>(d_records), n, m->p.record_bytes,
+                           m->p.key_bytes, part, lay, st));
+  if (pm) mark(*pm, 2, st);
+  HIP_TRY(launch_scan_counts(part, lay, m->B, d_offsets, st));
+  HIP_TRY(launch_spill_fixup(part, lay, n, st));
+  return ELSAR_OK;
+}
+
+elsar_status do_sort_buckets(const elsar_model* m, const void* d_part, size_t part_bytes, uint64_t n,
+                             const uint64_t* d_offsets, void* d_out, hipStream_t st) {
+  PartLayout lay = part_layout(n, m->B, m->p.record_bytes, m->p.region_pct);
+  if (part_bytes < lay.bytes) return ELSAR_E_NO_MEMORY;
+  HIP_TRY(launch_bucket_sort(static_cast<const uint8_t*>(d_part), lay, m->B, d_offsets, m->p.record_bytes,
+                             m->p.key_bytes, static_cast<uint8_t*>(d_out), st));
+  return ELSAR_OK;
+}
+
+struct SortLayout {
+  size_t model, fit, part, offsets, bytes;
+  PartLayout lay;
+};
+
+SortLayout sort_layout(const elsar_fit_params& p, const Shape& sh, uint64_t n) {
+  SortLayout sl{};
+  size_t off = 0;
+  sl.model = off;
+  off += align_up(model_dev_bytes(sh.L, sh.B));
+  sl.fit = off;
+  off += align_up(fit_ws_bytes(sh.S));
+  sl.offsets = off;
+  off += align_up(((size_t)sh.B + 1) * 8);
+  sl.lay = part_layout(n, sh.B, p.record_bytes, p.region_pct);
+  sl.part = off;
+  off += align_up(sl.lay.bytes);
+  sl.bytes = off;
+  return sl;
+}
+
+}  // namespace
+
+// ====================================================================== ABI ==
+extern "C" {
+
+elsar_status elsar_fit_params_default(elsar_fit_params* p) {
+  if (!p) return ELSAR_E_INVALID_ARG;
+  std::memset(p, 0, sizeof(*p));
+  p->record_bytes = 100;
+  p->key_bytes = 10;
+  p->kind = ELSAR_MODEL_RMI;
+  p->accept_ratio = 1.5f;
+  return ELSAR_OK;
+}
+
+elsar_status elsar_model_create(const elsar_fit_params* p, uint64_t n, elsar_model** out) {
+  if (!out) return ELSAR_E_INVALID_ARG;
+  *out = nullptr;
+  elsar_status s = check_params(p);
+  if (s != ELSAR_OK) return s;
+  if (n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;
+  Shape sh = resolve(*p, n);
+  elsar_model* m = new (std::nothrow) elsar_model();
+  if (!m) return ELSAR_E_NO_MEMORY;
+  m->p = with_defaults(*p);
+  m->B = sh.B;
+  m->L = sh.L;
+  m->S = sh.S;
+  m->n = 0;
+  if (hipMalloc(&m->dev, model_dev_bytes(m->L, m->B)) != hipSuccess) {
+    delete m;
+    return ELSAR_E_NO_MEMORY;
+  }
+  place_model(m, m->dev);
+  *out = m;
+  return ELSAR_OK;
+}
+
+void elsar_model_destroy(elsar_model* m) {
+  if (!m) return;
+  if (m->dev) (void)hipFree(m->dev);
+  delete m;
+}
+
+elsar_status elsar_fit_workspace_size(const elsar_model* m, uint64_t /*n*/, size_t* bytes) {
+  if (!m || !bytes) return ELSAR_E_INVALID_ARG;
+  *bytes = fit_ws_bytes(m->S);
+  return ELSAR_OK;
+}
+
+elsar_status elsar_sample_fit(elsar_model* m, const void* d_records, uint64_t n, void* d_ws, size_t ws_bytes,
+                              hipStream_t stream) {
+  if (!m) return ELSAR_E_INVALID_ARG;
+  if (n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;
+  if (n && (!d_records || !d_ws || !aligned16(d_records))) return ELSAR_E_INVALID_ARG;
+  Shape sh = resolve(m->p, n);
+  if (sh.B != m->B || sh.L != m->L) return ELSAR_E_INVALID_ARG;  // model shaped for another n
+  m->S = sh.S;
+  if (ws_bytes < fit_ws_bytes(m->S)) return ELSAR_E_NO_MEMORY;
+  return do_fit(m, d_records, n, d_ws, ws_bytes, stream);
+}
+
+elsar_status elsar_partition_size(const elsar_model* m, uint64_t n, size_t* part_bytes) {
+  if (!m || !part_bytes) return ELSAR_E_INVALID_ARG;
+  if (n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;
+  *part_bytes = part_layout(n, m->B, m->p.record_bytes, m->p.region_pct).bytes;
+  return ELSAR_OK;
+}
+
+elsar_status elsar_partition(const elsar_model* m, const void* d_records, uint64_t n, void* d_part,
+                             size_t part_bytes, uint64_t* d_bucket_offsets, hipStream_t stream) {
+  if (!m || !d_part || !d_bucket_offsets) return ELSAR_E_INVALID_ARG;
+  if (n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;
+  if (n && (!d_records || !aligned16(d_records))) return ELSAR_E_INVALID_ARG;
+  if (m->n == 0 && n > 0) return ELSAR_E_INVALID_ARG;  // not fitted
+  PhaseMarks pm = begin_marks();
+  mark(pm, 0, stream);
+  elsar_status s = do_partition(m, d_records, n, d_part, part_bytes, d_bucket_offsets, stream, &pm);
+  mark(pm, 3, stream);
+  return s;
+}
+
+elsar_status elsar_sort_buckets(const elsar_model* m, const void* d_part, size_t part_bytes, uint64_t n,
+                                const uint64_t* d_bucket_offsets, void* d_out, hipStream_t stream) {
+  if (!m || !d_part || !d_bucket_offsets) return ELSAR_E_INVALID_ARG;
+  if (n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;
+  if (n && (!d_out || !aligned16(d_out))) return ELSAR_E_INVALID_ARG;
+  return do_sort_buckets(m, d_part, part_bytes, n, d_bucket_offsets, d_out, stream);
+}
+
+elsar_status elsar_sort_workspace_size(const elsar_fit_params* p, uint64_t n, size_t* bytes) {
+  if (!bytes) return ELSAR_E_INVALID_ARG;
+  elsar_status s = check_params(p);
+  if (s != ELSAR_OK) return s;
+  if (n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;
+  elsar_fit_params q = with_defaults(*p);
+  *bytes = sort_layout(q, resolve(q, n), n).bytes;
+  return ELSAR_OK;
+}
+
+elsar_status elsar_sort(const void* d_in, uint64_t n, void* d_out, const elsar_fit_params* p, void* d_ws,
+                        size_t ws_bytes, hipStream_t stream) {
+  elsar_status s = check_params(p);
+  if (s != ELSAR_OK) return s;
+  if (n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;
+  if (n == 0) return ELSAR_OK;
+  if (!d_in || !d_out || !d_ws || !aligned16(d_in) || !aligned16(d_out) || !aligned16(d_ws))
+    return ELSAR_E_INVALID_ARG;
+  const elsar_fit_params q = with_defaults(*p);
+  Shape sh = resolve(q, n);
+  SortLayout sl = sort_layout(q, sh, n);
+  if (ws_bytes < sl.bytes) return ELSAR_E_NO_MEMORY;
+  if (n == 1) {
+    if (d_out != d_in) HIP_TRY(hipMemcpyAsync(d_out, d_in, p->record_bytes, hipMemcpyDeviceToDevice, stream));
+    return ELSAR_OK;
+  }
+  uint8_t* w = static_cast<uint8_t*>(d_ws);
+  elsar_model m{};
+  m.p = with_defaults(*p);
+  m.B = sh.B;
+  m.L = sh.L;
+  m.S = sh.S;
+  m.dev = nullptr;
+  place_model(&m, w + sl.model);
+  uint64_t* offsets = reinterpret_cast<uint64_t*>(w + sl.offsets);
+  PhaseMarks pm = begin_marks();
+  mark(pm, 0, stream);
+  s = do_fit(&m, d_in, n, w + sl.fit, fit_ws_bytes(sh.S), stream);
+  if (s != ELSAR_OK) return s;
+  s = do_partition(&m, d_in, n, w + sl.part, sl.lay.bytes, offsets, stream, &pm);
+  if (s != ELSAR_OK) return s;
+  mark(pm, 3, stream);
+  s = do_sort_buckets(&m, w + sl.part, sl.lay.bytes, n, offsets, d_out, stream);
+  mark(pm, 4, stream);
+  return s;
+}
+
+elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info) {
+  if (!m || !info) return ELSAR_E_INVALID_ARG;
+  ModelHeader h;
+  HIP_TRY(hipMemcpy(&h, m->hdr, sizeof(h), hipMemcpyDeviceToHost));
+  std::memset(info, 0, sizeof(*info));
+  info->kind_used = h.kind_used;
+  info->mlp_rejected = h.mlp_rejected;
+  info->num_buckets = m->B;
+  info->num_leaves = m->L;
+  info->sample_size = m->S;
+  info->n_fit = m->n;
+  info->root_a0 = h.a0;
+  info->root_a1 = h.a1;
+  info->max_sample_bucket = h.max_sample_bucket;
+  info->opt_sample_bucket = h.opt_sample_bucket;
+  return ELSAR_OK;
+}
+
+elsar_status elsar_model_leaves(const elsar_model* m, uint64_t* h_base, float* h_slope, float* h_icpt,
+                                uint32_t* h_lo, uint32_t* h_hi) {
+  if (!m) return ELSAR_E_INVALID_ARG;
+  std::vector<Leaf> lv(m->L);
+  HIP_TRY(hipMemcpy(lv.data(), m->leaves, lv.size() * sizeof(Leaf), hipMemcpyDeviceToHost));
+  for (uint32_t j = 0; j < m->L; ++j) {
+    if (h_base) h_base[j] = lv[j].base;
+    if (h_slope) h_slope[j] = lv[j].c;
+    if (h_icpt) h_icpt[j] = lv[j].b;
+    if (h_lo) h_lo[j] = lv[j].lo;
+    if (h_hi) h_hi[j] = lv[j].hi;
+  }
+  return ELSAR_OK;
+}
+
+elsar_status elsar_partition_stats_get(const elsar_model* m, const void* d_part, size_t part_bytes,
+                                       elsar_partition_stats* st) {
+  if (!m || !d_part || !st) return ELSAR_E_INVALID_ARG;
+  if (part_bytes < sizeof(PartHeader)) return ELSAR_E_NO_MEMORY;
+  PartHeader h;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(&h, d_part, sizeof(h), hipMemcpyDeviceToHost));
+  std::memset(st, 0, sizeof(*st));
+  st->n = h.n;
+  st->num_buckets = h.B;
+  st->spill_count = h.spill_count;
+  st->mid_buckets = h.n_mid;
+  st->big_buckets = h.n_big;
+  st->max_bucket = h.max_count;
+  return ELSAR_OK;
+}
+
+elsar_status elsar_set_timing(int enabled) {
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  if (enabled && g_timing.ev.empty()) {
+    g_timing.ev.resize((size_t)kTimingSlots * kTimedPhases);
+    g_timing.have.assign(kTimingSlots, 0);
+    for (auto& e : g_timing.ev)
+      if (hipEventCreate(&e) != hipSuccess) return ELSAR_E_HIP;
+  }
+  g_timing.on = enabled != 0;
+  g_timing.next = 0;
+  g_timing.used = 0;
+  return ELSAR_OK;
+}
+
+elsar_status elsar_timings_get(elsar_timings* t) {
+  if (!t) return ELSAR_E_INVALID_ARG;
+  std::memset(t, 0, sizeof(*t));
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  if (g_timing.ev.empty() || g_timing.used == 0) return ELSAR_OK;
+  double acc[4] = {0, 0, 0, 0}, tot = 0;
+  int cnt[4] = {0, 0, 0, 0}, ctot = 0;
+  for (int s = 0; s < g_timing.used; ++s) {
+    hipEvent_t* e = &g_timing.ev[(size_t)s * kTimedPhases];
+    uint8_t hv = g_timing.have[s];
+    for (int i = 0; i < kTimedPhases; ++i)
+      if ((hv >> i) & 1u) HIP_TRY(hipEventSynchronize(e[i]));
+    for (int i = 0; i < 4; ++i) {
+      if (((hv >> i) & 1u) && ((hv >> (i + 1)) & 1u)) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e[i], e[i + 1]));
+        acc[i] += ms;
+        cnt[i]++;
+      }
+    }
+    int first = -1, last = -1;
+    for (int i = 0; i < kTimedPhases; ++i)
+      if ((hv >> i) & 1u) { if (first < 0) first = i; last = i; }
+    if (first >= 0 && last > first) {
+      float ms = 0;
+      HIP_TRY(hipEventElapsedTime(&ms, e[first], e[last]));
+      tot += ms;
+      ctot++;
+    }
+  }
+  t->sample_fit_ms = cnt[0] ? (float)(acc[0] / cnt[0]) : 0.0f;
+  t->partition_ms = cnt[1] ? (float)(acc[1] / cnt[1]) : 0.0f;
+  t->scan_ms = cnt[2] ? (float)(acc[2] / cnt[2]) : 0.0f;
+  t->bucket_sort_ms = cnt[3] ? (float)(acc[3] / cnt[3]) : 0.0f;
+  t->total_ms = ctot ? (float)(tot / ctot) : 0.0f;
+  t->calls = (uint32_t)g_timing.used;
+  return ELSAR_OK;
+}
+
+const char* elsar_status_string(elsar_status s) {
+  switch (s) {
+    case ELSAR_OK: return "ok";
+    case ELSAR_E_INVALID_ARG: return "invalid argument";
+    case ELSAR_E_NO_MEMORY: return "workspace too small or allocation failed";
+    case ELSAR_E_HIP: return "HIP runtime error";
+    case ELSAR_E_UNSUPPORTED: return "unsupported shape";
+    case ELSAR_E_MODEL_REJECTED: return "learned model rejected; RMI kept";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

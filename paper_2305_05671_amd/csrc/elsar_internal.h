@@ -1,0 +1,172 @@
+// Internal declarations of the HIP/gfx950 ELSAR library: device data layouts,
+// device helpers shared by the kernels, and host launch wrappers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace elsar {
+
+// ---------------------------------------------------------------- layout --
+// One partition slot: the 100-byte record followed by its 32-bit input index.
+// Slots are 8-byte aligned (104 = 8 * 13); the index makes the in-bucket order
+// independent of the order in which the atomics handed out slots.
+constexpr uint32_t kMaxKeyBytes = 12;   // the LDS sort entry holds key + 4-byte index
+constexpr uint32_t kMinKeyBytes = 8;    // the code reads the first 8 key bytes
+constexpr uint32_t kSmallCap = 2048;    // largest bucket sorted by the small LDS kernel
+constexpr uint32_t kMidCap = 6144;      // largest bucket sorted by the large LDS kernel
+constexpr uint32_t kMaxBuckets = 1u << 21;
+
+struct Leaf {          // one RMI leaf: clamped line on the leaf-local code
+  uint64_t base;       // smallest sample code routed to the leaf
+  float c, b;          // slope (>= 0), intercept, bucket units
+  uint32_t lo, hi;     // bucket range the leaf's own sample ranks span
+  uint32_t pad[2];
+};
+static_assert(sizeof(Leaf) == 32, "leaf is two 16-byte vectors");
+
+struct ModelHeader {   // device-resident root of a fitted model
+  float a0, a1;        // linear root in leaf units
+  uint32_t L, B;       // leaves, buckets
+  uint32_t kind_used;  // 0 = RMI root, 1 = MLP root
+  uint32_t mlp_rejected;
+  uint64_t n_fit;      // records the model was fitted for
+  uint64_t S;          // sample size
+  uint32_t max_sample_bucket, opt_sample_bucket;
+  uint32_t pad[4];
+};
+
+struct PartHeader {    // device-resident state of one partition pass
+  uint64_t n;
+  uint64_t cap_slots;   // slots reserved for bucket regions (upper bound)
+  uint32_t B;
+  uint32_t spill_count; // records that overflowed their region
+  uint32_t n_mid;       // buckets with kSmallCap < count <= kMidCap
+  uint32_t n_big;       // buckets with count > kMidCap
+  uint32_t max_count;
+  uint32_t pad[9];
+};
+
+// Byte offsets of the partition buffer's parts for n records and B buckets.
+struct PartLayout {
+  size_t header, counts, caps, rstart, spill_off, mid_list, big_list;
+  size_t spill_meta, spill_map, slots;
+  uint64_t cap_slots;   // region slots
+  uint64_t total_slots; // regions + spill
+  size_t bytes;
+  uint32_t slot_bytes;
+};
+
+// ----------------------------------------------------------- device code --
+__device__ __forceinline__ uint32_t philox_x(uint64_t ctr_lo64, uint32_t c2, uint32_t c3, uint64_t key) {
+  // Philox4x32-10 (Salmon et al., SC'11); only the first output word is used.
+  uint32_t c0 = (uint32_t)ctr_lo64, c1 = (uint32_t)(ctr_lo64 >> 32);
+  uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c1 = lo1; c3 = lo0; c0 = n0; c2 = n2;
+  }
+  return c0;
+}
+
+// Base-95 code of the first 8 key bytes (little-endian dwords w0 = bytes 0..3,
+// w1 = bytes 4..7).  From the first byte outside 0x20..0x7E on, every digit
+// saturates to 0 (byte below 0x20) or 94 (above 0x7E): non-decreasing in
+// memcmp order for any bytes.  Two 4-digit halves, each < 95^4 < 2^27.
+__device__ __forceinline__ uint64_t key_code(uint32_t w0, uint32_t w1) {
+  uint32_t bad = 0, low = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    uint32_t c = ((i < 4 ? w0 : w1) >> (8 * (i & 3))) & 0xFFu;
+    bad |= (uint32_t)(c < 0x20u || c > 0x7Eu) << i;
+    low |= (uint32_t)(c < 0x20u) << i;
+  }
+  uint32_t p = bad ? (uint32_t)__builtin_ctz(bad) : 8u;
+  uint32_t sat = ((low >> p) & 1u) ? 0u : 94u;
+  uint32_t h = 0, l = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    uint32_t c = ((i < 4 ? w0 : w1) >> (8 * (i & 3))) & 0xFFu;
+    uint32_t d = (uint32_t)i < p ? c - 0x20u : sat;
+    if (i < 4) h = h * 95u + d; else l = l * 95u + d;
+  }
+  return (uint64_t)h * 81450625ull + l;  // 95^4
+}
+
+__device__ __forceinline__ float code_f32(uint64_t e) { return (float)(double)e; }
+
+__device__ __forceinline__ uint32_t rmi_leaf(float a0, float a1, uint32_t L, uint64_t e) {
+  float r = floorf(__builtin_fmaf(a1, code_f32(e), a0));
+  if (r < 0.0f) return 0;
+  if (r > (float)(L - 1)) return L - 1;
+  return (uint32_t)r;
+}
+
+__device__ __forceinline__ uint32_t leaf_bucket(const Leaf& lf, uint64_t e) {
+  uint64_t d = e >= lf.base ? e - lf.base : 0;
+  float y = floorf(__builtin_fmaf(lf.c, code_f32(d), lf.b));
+  if (y < (float)lf.lo) return lf.lo;
+  if (y > (float)lf.hi) return lf.hi;
+  return (uint32_t)y;
+}
+
+__device__ __forceinline__ Leaf load_leaf(const Leaf* __restrict__ leaves, uint32_t j) {
+  const uint4* p = reinterpret_cast<const uint4*>(leaves + j);
+  uint4 a = p[0], b = p[1];
+  Leaf lf;
+  lf.base = (uint64_t)a.x | ((uint64_t)a.y << 32);
+  lf.c = __uint_as_float(a.z);
+  lf.b = __uint_as_float(a.w);
+  lf.lo = b.x;
+  lf.hi = b.y;
+  return lf;
+}
+
+// Lanes of the wave holding the same 8-bit digit as this lane (valid lanes only).
+__device__ __forceinline__ uint64_t match_digit8(uint32_t d, bool valid) {
+  uint64_t m = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    bool bit = (d >> b) & 1u;
+    uint64_t bal = __ballot(bit);
+    m &= bit ? bal : ~bal;
+  }
+  return m;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// ---------------------------------------------------------- host wrappers --
+// sample / fit (k_fit.hip)
+hipError_t launch_sample_codes(const uint8_t* recs, uint64_t n, uint32_t rec_bytes, uint64_t S, uint64_t seed,
+                               uint64_t* codes, hipStream_t st);
+size_t radix_u64_scratch_bytes(uint64_t n);
+hipError_t launch_radix_sort_u64(uint64_t* keys, uint64_t* tmp, uint64_t n, int lo_byte, int hi_byte,
+                                 void* scratch, hipStream_t st, uint64_t** sorted);
+size_t fit_scratch_bytes(uint64_t S);
+hipError_t launch_fit_rmi(const uint64_t* sorted_codes, uint64_t S, uint64_t n, uint32_t L, uint32_t B,
+                          ModelHeader* hdr, Leaf* leaves, void* scratch, hipStream_t st);
+hipError_t launch_sample_hist(const ModelHeader* hdr, const Leaf* leaves, const uint64_t* sorted_codes,
+                              uint64_t S, uint32_t B, uint32_t* hist, hipStream_t st);
+hipError_t launch_capacities(const uint32_t* hist, uint64_t S, uint64_t n, uint32_t B, uint32_t region_pct,
+                             uint8_t* part, const PartLayout& lay, hipStream_t st);
+
+// partition (k_partition.hip)
+hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const uint8_t* recs, uint64_t n,
+                            uint32_t rec_bytes, uint32_t key_bytes, uint8_t* part, const PartLayout& lay,
+                            hipStream_t st);
+hipError_t launch_scan_counts(uint8_t* part, const PartLayout& lay, uint32_t B, uint64_t* offsets,
+                              hipStream_t st);
+hipError_t launch_spill_fixup(uint8_t* part, const PartLayout& lay, uint64_t n, hipStream_t st);
+
+// bucket sort (k_bucket_sort.hip)
+hipError_t launch_bucket_sort(const uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
+                              uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st);
+
+}  // namespace elsar

@@ -1,0 +1,371 @@
+// Sample, sample sort and RMI fit kernels (gfx950).
+//
+// Training sample (Section 3.1): S = min(max(ceil(n/100), 1024), 1e7, n) keys,
+// sample s drawn uniformly from the stratum [floor(s*n/S), floor((s+1)*n/S))
+// by a Philox4x32-10 draw keyed by the seed.  The sample's base-95 codes
+// (Section 4) are radix-sorted on the device; their ranks are the empirical
+// CDF the two-level RMI (Section 3.1) is fitted to.
+#include "elsar_internal.h"
+
+namespace elsar {
+
+// ------------------------------------------------------------- sampling --
+__global__ __launch_bounds__(256) void sample_codes_kernel(const uint8_t* __restrict__ recs, uint64_t n,
+                                                           uint32_t rec_bytes, uint64_t S, uint64_t seed,
+                                                           uint64_t* __restrict__ codes) {
+  uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  uint64_t lo = s * n / S, hi = (s + 1) * n / S;
+  uint32_t u = philox_x(s, 0x53414D50u, 0u, seed);
+  uint64_t i = lo + (((uint64_t)u * (hi - lo)) >> 32);
+  const uint32_t* r = reinterpret_cast<const uint32_t*>(recs + i * rec_bytes);
+  codes[s] = key_code(r[0], r[1]);
+}
+
+hipError_t launch_sample_codes(const uint8_t* recs, uint64_t n, uint32_t rec_bytes, uint64_t S, uint64_t seed,
+                               uint64_t* codes, hipStream_t st) {
+  if (S == 0) return hipSuccess;
+  uint32_t grid = (uint32_t)((S + 255) / 256);
+  sample_codes_kernel<<<grid, 256, 0, st>>>(recs, n, rec_bytes, S, seed, codes);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------- LSD radix sort of u64 keys --
+// Per pass (one byte): per-tile digit histograms (digit-major), one exclusive
+// scan over them, then a stable scatter where each wave ranks its own items in
+// order with ballot-matched digits.
+constexpr int kRadixThreads = 256;
+constexpr int kRadixRounds = 16;  // rounds of 64 items per wave
+constexpr int kRadixWaves = kRadixThreads / 64;
+constexpr int kRadixTile = kRadixThreads * kRadixRounds;  // 4096
+
+__global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const uint64_t* __restrict__ keys, uint64_t n,
+                                                                   int shift, uint32_t ntiles,
+                                                                   uint32_t* __restrict__ tile_hist) {
+  __shared__ uint32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
+  for (int k = 0; k < kRadixRounds; ++k) {
+    uint64_t i = base + (uint64_t)k * kRadixThreads + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 0xFFu], 1u);
+  }
+  __syncthreads();
+  tile_hist[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive scan of m u32 values in place, one block of 1024 threads.
+__global__ __launch_bounds__(1024) void scan_u32_kernel(uint32_t* __restrict__ v, uint64_t m) {
+  __shared__ uint32_t part[1024];
+  uint64_t per = (m + 1023) / 1024;
+  uint64_t b = threadIdx.x * per, e = b + per < m ? b + per : m;
+  uint32_t s = 0;
+  for (uint64_t i = b; i < e; ++i) s += v[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t x = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += x;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - s;
+  for (uint64_t i = b; i < e; ++i) {
+    uint32_t x = v[i];
+    v[i] = run;
+    run += x;
+  }
+}
+
+__global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(const uint64_t* __restrict__ in,
+                                                                      uint64_t* __restrict__ out, uint64_t n,
+                                                                      int shift, uint32_t ntiles,
+                                                                      const uint32_t* __restrict__ tile_off) {
+  __shared__ uint32_t wc[kRadixWaves][256];
+  __shared__ uint32_t gbase[256];
+  const uint32_t w = threadIdx.x >> 6;
+  for (uint32_t i = threadIdx.x; i < kRadixWaves * 256; i += kRadixThreads) (&wc[0][0])[i] = 0;
+  __syncthreads();
+  uint64_t base = (uint64_t)blockIdx.x * kRadixTile + (uint64_t)w * 64 * kRadixRounds;
+  uint64_t key[kRadixRounds];
+  uint32_t loc[kRadixRounds];
+#pragma unroll
+  for (int r = 0; r < kRadixRounds; ++r) {
+    uint64_t i = base + (uint64_t)r * 64 + lane_id();
+    bool valid = i < n;
+    key[r] = valid ? in[i] : 0;
+    uint32_t d = (uint32_t)(key[r] >> shift) & 0xFFu;
+    uint64_t peers = match_digit8(d, valid);
+    uint32_t rank = __popcll(peers & lanemask_lt());
+    uint32_t prev = valid ? wc[w][d] : 0u;
+    loc[r] = prev + rank;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == 0) wc[w][d] = prev + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    uint32_t d = threadIdx.x, run = 0;
+    for (int ww = 0; ww < kRadixWaves; ++ww) {
+      uint32_t c = wc[ww][d];
+      wc[ww][d] = run;
+      run += c;
+    }
+    gbase[d] = tile_off[(uint64_t)d * ntiles + blockIdx.x];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRadixRounds; ++r) {
+    uint64_t i = base + (uint64_t)r * 64 + lane_id();
+    if (i < n) {
+      uint32_t d = (uint32_t)(key[r] >> shift) & 0xFFu;
+      out[(uint64_t)gbase[d] + wc[w][d] + loc[r]] = key[r];
+    }
+  }
+}
+
+size_t radix_u64_scratch_bytes(uint64_t n) {
+  uint64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+  return (size_t)(ntiles * 256 * sizeof(uint32_t));
+}
+
+// Sort bytes lo_byte..hi_byte (inclusive) of keys; *sorted = buffer with the result.
+hipError_t launch_radix_sort_u64(uint64_t* keys, uint64_t* tmp, uint64_t n, int lo_byte, int hi_byte,
+                                 void* scratch, hipStream_t st, uint64_t** sorted) {
+  *sorted = keys;
+  if (n <= 1) return hipSuccess;
+  uint32_t ntiles = (uint32_t)((n + kRadixTile - 1) / kRadixTile);
+  uint32_t* th = static_cast<uint32_t*>(scratch);
+  uint64_t *a = keys, *b = tmp;
+  for (int byte = lo_byte; byte <= hi_byte; ++byte) {
+    int shift = 8 * byte;
+    radix_hist_kernel<<<ntiles, kRadixThreads, 0, st>>>(a, n, shift, ntiles, th);
+    scan_u32_kernel<<<1, 1024, 0, st>>>(th, (uint64_t)ntiles * 256);
+    radix_scatter_kernel<<<ntiles, kRadixThreads, 0, st>>>(a, b, n, shift, ntiles, th);
+    uint64_t* t = a;
+    a = b;
+    b = t;
+  }
+  *sorted = a;
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ RMI fitting --
+// Root: least squares (FP64, centred two-pass) of t = L*s/S on x = f32(code_s).
+// Deterministic: fixed block decomposition and fixed reduction trees.
+constexpr int kFitThreads = 256;
+constexpr int kFitBlocks = 256;
+
+__device__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = kFitThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < (unsigned)off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kFitThreads) void root_sum_x_kernel(const uint64_t* __restrict__ e, uint64_t S,
+                                                                 double* __restrict__ part_x) {
+  __shared__ double sh[kFitThreads];
+  double sx = 0;
+  for (uint64_t s = blockIdx.x * (uint64_t)kFitThreads + threadIdx.x; s < S; s += (uint64_t)kFitBlocks * kFitThreads)
+    sx += (double)code_f32(e[s]);
+  double t = block_sum(sx, sh);
+  if (threadIdx.x == 0) part_x[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kFitThreads) void root_moments_kernel(const uint64_t* __restrict__ e, uint64_t S,
+                                                                   uint32_t L, const double* __restrict__ part_x,
+                                                                   double* __restrict__ part_xx,
+                                                                   double* __restrict__ part_xt) {
+  __shared__ double sh[kFitThreads];
+  double mx = block_sum(part_x[threadIdx.x], sh) / (double)S;  // kFitBlocks == kFitThreads
+  double mt = (double)L * (double)(S - 1) / (2.0 * (double)S);
+  double sxx = 0, sxt = 0;
+  for (uint64_t s = blockIdx.x * (uint64_t)kFitThreads + threadIdx.x; s < S;
+       s += (uint64_t)kFitBlocks * kFitThreads) {
+    double dx = (double)code_f32(e[s]) - mx;
+    double dt = (double)L * (double)s / (double)S - mt;
+    sxx += dx * dx;
+    sxt += dx * dt;
+  }
+  double a = block_sum(sxx, sh);
+  double b = block_sum(sxt, sh);
+  if (threadIdx.x == 0) {
+    part_xx[blockIdx.x] = a;
+    part_xt[blockIdx.x] = b;
+  }
+}
+
+__global__ __launch_bounds__(kFitThreads) void root_final_kernel(uint64_t S, uint64_t n, uint32_t L, uint32_t B,
+                                                                 const double* __restrict__ part_x,
+                                                                 const double* __restrict__ part_xx,
+                                                                 const double* __restrict__ part_xt,
+                                                                 ModelHeader* __restrict__ hdr) {
+  __shared__ double sh[kFitThreads];
+  double mx = block_sum(part_x[threadIdx.x], sh) / (double)S;
+  double sxx = block_sum(part_xx[threadIdx.x], sh);
+  double sxt = block_sum(part_xt[threadIdx.x], sh);
+  if (threadIdx.x == 0) {
+    double mt = (double)L * (double)(S - 1) / (2.0 * (double)S);
+    double a1 = sxx > 0 ? sxt / sxx : 0.0;
+    double a0;
+    if (a1 < 0) {
+      a1 = 0;
+      a0 = mt;
+    } else {
+      a0 = mt - a1 * mx;
+    }
+    hdr->a0 = (float)a0;
+    hdr->a1 = (float)a1;
+    hdr->L = L;
+    hdr->B = B;
+    hdr->kind_used = 0;
+    hdr->mlp_rejected = 0;
+    hdr->n_fit = n;
+    hdr->S = S;
+  }
+}
+
+// Leaf j: samples f..g-1 routed to it by the root (contiguous: routing is
+// monotone).  Linear spline from (0, B*f/S) to (x(e[g-1]-e[f]), B*(g-1)/S);
+// bucket range [B*f/S, min(B*(g-1)/S, B-1)].  Empty leaves are constant at the
+// next non-empty leaf's first bucket.
+__device__ uint64_t first_in_leaf(const uint64_t* e, uint64_t S, float a0, float a1, uint32_t L, uint32_t j) {
+  uint64_t lo = 0, hi = S;
+  while (lo < hi) {
+    uint64_t mid = lo + ((hi - lo) >> 1);
+    if (rmi_leaf(a0, a1, L, e[mid]) < j) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void leaf_fit_kernel(const uint64_t* __restrict__ e, uint64_t S,
+                                                       const ModelHeader* __restrict__ hdr,
+                                                       Leaf* __restrict__ leaves) {
+  uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t L = hdr->L, B = hdr->B;
+  if (j >= L) return;
+  const float a0 = hdr->a0, a1 = hdr->a1;
+  uint64_t f = first_in_leaf(e, S, a0, a1, L, j);
+  uint64_t g = j + 1 < L ? first_in_leaf(e, S, a0, a1, L, j + 1) : S;
+  Leaf lf;
+  lf.pad[0] = lf.pad[1] = 0;
+  if (f == g) {
+    uint32_t v = f < S ? (uint32_t)(((uint64_t)B * f) / S) : B - 1;
+    lf.base = 0;
+    lf.c = 0.0f;
+    lf.b = (float)v;
+    lf.lo = lf.hi = v;
+  } else {
+    double tf = (double)B * (double)f / (double)S;
+    double tl = (double)B * (double)(g - 1) / (double)S;
+    double span = (double)code_f32(e[g - 1] - e[f]);
+    double cj = span > 0 ? (tl - tf) / span : 0.0;
+    lf.base = e[f];
+    lf.c = (float)cj;
+    lf.b = (float)tf;
+    lf.lo = (uint32_t)(((uint64_t)B * f) / S);
+    uint64_t h = ((uint64_t)B * (g - 1)) / S;
+    lf.hi = (uint32_t)(h < B - 1 ? h : B - 1);
+  }
+  leaves[j] = lf;
+}
+
+size_t fit_scratch_bytes(uint64_t /*S*/) { return 3 * kFitBlocks * sizeof(double); }
+
+hipError_t launch_fit_rmi(const uint64_t* e, uint64_t S, uint64_t n, uint32_t L, uint32_t B, ModelHeader* hdr,
+                          Leaf* leaves, void* scratch, hipStream_t st) {
+  double* px = static_cast<double*>(scratch);
+  double* pxx = px + kFitBlocks;
+  double* pxt = pxx + kFitBlocks;
+  root_sum_x_kernel<<<kFitBlocks, kFitThreads, 0, st>>>(e, S, px);
+  root_moments_kernel<<<kFitBlocks, kFitThreads, 0, st>>>(e, S, L, px, pxx, pxt);
+  root_final_kernel<<<1, kFitThreads, 0, st>>>(S, n, L, B, px, pxx, pxt, hdr);
+  leaf_fit_kernel<<<(L + 255) / 256, 256, 0, st>>>(e, S, hdr, leaves);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------- bucket capacity --
+// h_j = sample keys the fitted model puts in bucket j.  The partition reserves
+// ceil(f * max(n * h_j / S, n / B)) + 16 slots for bucket j (f = region_pct/100,
+// default 1.25), rounded up to even (16-byte aligned 104-byte slots); records
+// beyond continue in the spill.
+__global__ __launch_bounds__(256) void sample_bucket_hist_kernel(const uint64_t* __restrict__ e, uint64_t S,
+                                                                 const ModelHeader* __restrict__ hdr,
+                                                                 const Leaf* __restrict__ leaves,
+                                                                 uint32_t* __restrict__ hist) {
+  uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  uint64_t c = e[s];
+  uint32_t j = rmi_leaf(hdr->a0, hdr->a1, hdr->L, c);
+  atomicAdd(&hist[leaf_bucket(load_leaf(leaves, j), c)], 1u);
+}
+
+hipError_t launch_sample_hist(const ModelHeader* hdr, const Leaf* leaves, const uint64_t* e, uint64_t S,
+                              uint32_t B, uint32_t* hist, hipStream_t st) {
+  hipError_t err = hipMemsetAsync(hist, 0, (size_t)B * 4, st);
+  if (err != hipSuccess) return err;
+  if (S) sample_bucket_hist_kernel<<<(uint32_t)((S + 255) / 256), 256, 0, st>>>(e, S, hdr, leaves, hist);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(1024) void capacity_kernel(const uint32_t* __restrict__ hist, uint64_t S, uint64_t n,
+                                                        uint32_t B, double scale, uint32_t* __restrict__ caps,
+                                                        uint32_t* __restrict__ rstart, uint32_t* __restrict__ counts,
+                                                        PartHeader* __restrict__ ph, uint64_t cap_slots) {
+  __shared__ uint32_t part[1024];
+  uint32_t per = (B + 1023) / 1024;
+  uint32_t b = threadIdx.x * per, e = b + per < B ? b + per : B;
+  double ideal = (double)n / (double)B;
+  uint32_t s = 0;
+  for (uint32_t j = b; j < e; ++j) {
+    double expect = (double)hist[j] * (double)n / (double)S;
+    double m = expect > ideal ? expect : ideal;
+    uint32_t c = (uint32_t)ceil(scale * m) + 16u;
+    c = (c + 1u) & ~1u;
+    caps[j] = c;
+    counts[j] = 0;
+    s += c;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t x = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += x;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - s;
+  const bool over = part[1023] > cap_slots;  // cannot happen by construction; then everything spills
+  for (uint32_t j = b; j < e; ++j) {
+    uint32_t c = over ? 0u : caps[j];
+    rstart[j] = over ? 0u : run;
+    caps[j] = c;
+    run += c;
+  }
+  if (threadIdx.x == 0) {
+    ph->n = n;
+    ph->cap_slots = cap_slots;
+    ph->B = B;
+    ph->spill_count = 0;
+    ph->n_mid = 0;
+    ph->n_big = 0;
+    ph->max_count = 0;
+  }
+}
+
+hipError_t launch_capacities(const uint32_t* hist, uint64_t S, uint64_t n, uint32_t B, uint32_t region_pct,
+                             uint8_t* part, const PartLayout& lay, hipStream_t st) {
+  capacity_kernel<<<1, 1024, 0, st>>>(hist, S, n, B, region_pct / 100.0, reinterpret_cast<uint32_t*>(part + lay.caps),
+                                      reinterpret_cast<uint32_t*>(part + lay.rstart),
+                                      reinterpret_cast<uint32_t*>(part + lay.counts),
+                                      reinterpret_cast<PartHeader*>(part + lay.header), lay.cap_slots);
+  return hipGetLastError();
+}
+
+}  // namespace elsar

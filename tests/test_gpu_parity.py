@@ -1,0 +1,173 @@
+"""GPU parity: the HIP path through the C ABI against the oracle.
+
+Final output: byte-exact against the oracle's stable memcmp sort.  Model fit:
+root parameters within 1e-6 relative of the oracle's FP64 fit (the two sum in
+different orders), leaves bit-exact when the roots agree.  Bucket ids: the
+oracle's FP32 evaluation of the GPU's own parameters gives exactly the GPU's
+bucket counts.
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+R, K = 100, 10
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2305_05671_amd as elsar
+    assert torch.cuda.is_available()
+    return torch, elsar
+
+
+def _to_dev(torch, recs):
+    return torch.from_numpy(np.ascontiguousarray(recs).reshape(-1)).to("cuda")
+
+
+def _gpu_sort(env, recs, **kw):
+    torch, elsar = env
+    d = _to_dev(torch, recs)
+    out = elsar.elsar_sort(d, params=elsar.fit_params(**kw))
+    torch.cuda.synchronize()
+    return out.cpu().numpy().reshape(-1, R)
+
+
+def _assert_same(got, want):
+    assert got.shape == want.shape
+    if not np.array_equal(got, want):
+        bad = np.nonzero(np.any(got != want, axis=1))[0]
+        raise AssertionError(f"{bad.size} records differ, first at output position {bad[0]}")
+
+
+@pytest.mark.parametrize("kind,n,B,seed", [
+    ("uniform", 1_000_000, 1024, 0),     # the 1M-record, 1024-bucket workload
+    ("skewed", 300_000, 0, 2),
+    ("zipf", 200_000, 256, 3),
+    ("staircase", 200_000, 0, 4),
+    ("mixed", 250_000, 4096, 5),
+])
+def test_sort_matches_oracle(env, kind, n, B, seed):
+    recs = datagen.generate(datagen.spec(kind, seed=seed), n)
+    _assert_same(_gpu_sort(env, recs, num_buckets=B, seed=seed), oracle.sort_records(recs))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 100, 1000, 2047, 2048, 2049, 6144, 6145, 10_007, 65_537])
+def test_edge_sizes(env, n):
+    recs = datagen.generate(datagen.spec("uniform", seed=n), n)
+    _assert_same(_gpu_sort(env, recs), oracle.sort_records(recs))
+    _assert_same(_gpu_sort(env, recs, num_buckets=1), oracle.sort_records(recs))
+
+
+@pytest.mark.parametrize("n", [5000, 20_000])
+def test_all_equal_keys_order_by_index(env, n):
+    # one bucket holds everything; only the index bytes vary (early termination)
+    recs = datagen.generate(datagen.spec("uniform", seed=1, embed_idx=True), n)
+    recs[:, :K] = np.frombuffer(b"SAMEKEY!!!", np.uint8)
+    got = _gpu_sort(env, recs[::-1].copy())
+    _assert_same(got, oracle.sort_records(recs[::-1].copy()))
+
+
+def test_few_distinct_keys_large_buckets(env):
+    # 40 distinct keys over 200k records: buckets far above the LDS caps
+    rng = np.random.default_rng(0)
+    recs = datagen.generate(datagen.spec("uniform", seed=2), 200_000)
+    keys = datagen.generate(datagen.spec("uniform", seed=3), 40)[:, :K]
+    recs[:, :K] = keys[rng.integers(0, 40, size=recs.shape[0])]
+    _assert_same(_gpu_sort(env, recs, num_buckets=64), oracle.sort_records(recs))
+
+
+def test_arbitrary_key_bytes(env):
+    # bytes outside the printable range, including 0x00 and 0xFF, and keys that
+    # differ only in bytes 8..9 (beyond the 8-byte code)
+    rng = np.random.default_rng(7)
+    recs = datagen.generate(datagen.spec("uniform", seed=7), 100_000)
+    recs[:, :K] = rng.integers(0, 256, size=(recs.shape[0], K), dtype=np.uint8)
+    recs[::3, :8] = np.frombuffer(b"PREFIX!!", np.uint8)
+    _assert_same(_gpu_sort(env, recs, num_buckets=512), oracle.sort_records(recs))
+
+
+def test_forced_spill(env):
+    # regions of 1% of the expected load: nearly every record goes through the spill path
+    recs = datagen.generate(datagen.spec("skewed", seed=9), 200_000)
+    _assert_same(_gpu_sort(env, recs, num_buckets=128, region_pct=1), oracle.sort_records(recs))
+
+
+def test_in_place_and_deterministic(env):
+    torch, elsar = env
+    recs = datagen.generate(datagen.spec("skewed", seed=11), 150_000)
+    want = oracle.sort_records(recs)
+    d = _to_dev(torch, recs)
+    elsar.elsar_sort(d, out=d)
+    torch.cuda.synchronize()
+    _assert_same(d.cpu().numpy().reshape(-1, R), want)
+    a = _gpu_sort(env, recs)
+    b = _gpu_sort(env, recs)
+    assert np.array_equal(a, b)
+
+
+def _fit_and_partition(env, recs, **kw):
+    torch, elsar = env
+    n = recs.shape[0]
+    d = _to_dev(torch, recs)
+    m = elsar.Model(n, elsar.fit_params(**kw))
+    m.sample_fit(d)
+    part, offsets = m.partition(d)
+    torch.cuda.synchronize()
+    return m, part, offsets, d
+
+
+@pytest.mark.parametrize("kind,n,B,seed", [("uniform", 1_000_000, 1024, 0), ("skewed", 400_000, 2048, 2)])
+def test_fit_matches_oracle(env, kind, n, B, seed):
+    recs = datagen.generate(datagen.spec(kind, seed=seed), n)
+    m, part, offsets, _ = _fit_and_partition(env, recs, num_buckets=B, seed=seed)
+    info = m.info()
+    L = info.num_leaves
+    ref = oracle.fit_rmi(oracle.sample_codes(recs, seed=seed), L, B)
+    assert info.sample_size == oracle.sample_size(n)
+    assert info.root_a1 == pytest.approx(float(ref.root[1]), rel=1e-6)
+    assert info.root_a0 == pytest.approx(float(ref.root[0]), rel=1e-6, abs=1e-6)
+    base, c, b, lo, hi = m.leaves()
+    if info.root_a0 == ref.root[0] and info.root_a1 == ref.root[1]:
+        assert np.array_equal(base, ref.base) and np.array_equal(lo, ref.lo) and np.array_equal(hi, ref.hi)
+        assert np.array_equal(c, ref.c) and np.array_equal(b, ref.b)
+
+
+@pytest.mark.parametrize("kind,n,B,seed", [("uniform", 1_000_000, 1024, 0), ("skewed", 400_000, 2048, 2),
+                                           ("zipf", 300_000, 4096, 1)])
+def test_partition_counts_bit_exact(env, kind, n, B, seed):
+    recs = datagen.generate(datagen.spec(kind, seed=seed), n)
+    m, part, offsets, _ = _fit_and_partition(env, recs, num_buckets=B, seed=seed)
+    info = m.info()
+    ref = oracle.RMI(info.num_leaves, B)
+    ref.root[:] = [info.root_a0, info.root_a1]
+    ref.base[:], ref.c[:], ref.b[:], ref.lo[:], ref.hi[:] = m.leaves()
+    bk = ref.buckets(recs)
+    counts, want = oracle.counts_offsets(bk, B)
+    got = offsets.cpu().numpy().astype(np.uint64)
+    assert np.array_equal(got, want)
+    st = m.partition_stats(part)
+    assert st.n == n and st.max_bucket == counts.max()
+    # Equation 1 on the GPU's own bucket function
+    order = oracle.sort_order(recs)
+    assert np.all(np.diff(bk[order].astype(np.int64)) >= 0)
+
+
+def test_partition_then_sort_buckets(env):
+    torch, elsar = env
+    recs = datagen.generate(datagen.spec("zipf", seed=4), 300_000)
+    m, part, offsets, d = _fit_and_partition(env, recs, num_buckets=2048)
+    out = torch.empty_like(d)
+    m.sort_buckets(part, offsets, recs.shape[0], out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(-1, R)
+    want = oracle.sort_records(recs)
+    _assert_same(got, want)
+    # each bucket's slice is exactly the oracle's slice
+    off = offsets.cpu().numpy()
+    for j in [0, 1, 777, 2047]:
+        _assert_same(got[off[j]:off[j + 1]], want[off[j]:off[j + 1]])
