@@ -15,7 +15,7 @@
  *    pointers ("h_") are host memory.  The caller owns every buffer it passes;
  *    the library owns only elsar_model objects (and their device storage).
  *  - Record buffers are n * record_bytes bytes, 16-byte aligned; record i is at
- *    byte i * record_bytes.  record_bytes is a multiple of 4 and >= 40;
+ *    byte i * record_bytes.  record_bytes is a multiple of 4 in [40, 128];
  *    8 <= key_bytes <= 12 (the tuned shape is 100-byte records, 10-byte keys).
  *  - n < 2^32 for every call that takes records on the device, and at most
  *    ELSAR_MAX_DEVICE_RECORDS for one in-HBM sort.
@@ -158,7 +158,8 @@ typedef struct {
   uint32_t mid_buckets;      /* buckets sorted by the large LDS kernel */
   uint32_t big_buckets;      /* buckets sorted through global memory */
   uint32_t max_bucket;       /* largest bucket */
-  uint32_t reserved;
+  uint32_t mid_records;      /* records in the mid_buckets */
+  uint32_t big_records;      /* records in the big_buckets */
 } elsar_partition_stats;
 
 elsar_status elsar_partition_stats_get(const elsar_model* m, const void* d_part, size_t part_bytes,
@@ -171,7 +172,8 @@ typedef struct {
   float sample_fit_ms;   /* sample, sample sort, fit, capacities */
   float partition_ms;    /* the partition kernel */
   float scan_ms;         /* offsets, spill fix-up */
-  float bucket_sort_ms;  /* in-bucket sort + concatenation (all bucket kernels) */
+  float bucket_sort_lds_ms;   /* in-bucket sort + concatenation of buckets <= 2048 records (one kernel) */
+  float bucket_sort_rest_ms;  /* the larger buckets (LDS kernel up to 6144 records, then global memory) */
   float total_ms;        /* first to last recorded boundary of a call */
   uint32_t calls;        /* calls averaged over (the last 512 since enabling) */
 } elsar_timings;

@@ -62,7 +62,8 @@ class PartitionStats(ctypes.Structure):
         ("mid_buckets", ctypes.c_uint32),
         ("big_buckets", ctypes.c_uint32),
         ("max_bucket", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("mid_records", ctypes.c_uint32),
+        ("big_records", ctypes.c_uint32),
     ]
 
 
@@ -71,7 +72,8 @@ class Timings(ctypes.Structure):
         ("sample_fit_ms", ctypes.c_float),
         ("partition_ms", ctypes.c_float),
         ("scan_ms", ctypes.c_float),
-        ("bucket_sort_ms", ctypes.c_float),
+        ("bucket_sort_lds_ms", ctypes.c_float),
+        ("bucket_sort_rest_ms", ctypes.c_float),
         ("total_ms", ctypes.c_float),
         ("calls", ctypes.c_uint32),
     ]

@@ -9,7 +9,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/elsar.h"
+#include "elsar.h"
 #include "elsar_internal.h"
 
 using namespace elsar;
@@ -47,7 +47,7 @@ uint32_t default_buckets(uint64_t n) {
 
 elsar_status check_params(const elsar_fit_params* p) {
   if (!p) return ELSAR_E_INVALID_ARG;
-  if (p->record_bytes % 4 != 0 || p->record_bytes < 40) return ELSAR_E_UNSUPPORTED;
+  if (p->record_bytes % 4 != 0 || p->record_bytes < 40 || p->record_bytes > 128) return ELSAR_E_UNSUPPORTED;
   if (p->key_bytes < kMinKeyBytes || p->key_bytes > kMaxKeyBytes || p->key_bytes > p->record_bytes)
     return ELSAR_E_UNSUPPORTED;
   if (p->num_buckets > kMaxBuckets) return ELSAR_E_INVALID_ARG;
@@ -117,14 +117,14 @@ PartLayout part_layout(uint64_t n, uint32_t B, uint32_t R, uint32_t region_pct) 
   // regions: sum_j ceil(f * max(n h_j / S, n / B)) + 17 <= 2 f n + 18 B,  f = region_pct / 100
   lay.cap_slots = (n * 2 * region_pct + 99) / 100 + 18ull * B + 16;
   lay.total_slots = lay.cap_slots + n;
-  lay.slot_bytes = R + 4;
+  lay.slot_bytes = slot_bytes_for(R);
   lay.slots = take((size_t)lay.total_slots * lay.slot_bytes);
   lay.bytes = off;
   return lay;
 }
 
 // ------------------------------------------------------------ phase timing --
-constexpr int kTimedPhases = 5;  // boundaries: start, fit, partition, scan, sort
+constexpr int kTimedPhases = 6;  // boundaries: start, fit, partition, scan, LDS sort, all bucket kernels
 constexpr int kTimingSlots = 512;
 
 struct Timing {
@@ -136,7 +136,7 @@ struct Timing {
 } g_timing;
 
 struct PhaseMarks {  // events of the current call, or nulls when timing is off
-  hipEvent_t e[kTimedPhases] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t e[kTimedPhases] = {};
   int slot = -1;
 };
 
@@ -201,11 +201,15 @@ elsar_status do_partition(const elsar_model* m, const void* d_records, uint64_t 
 }
 
 elsar_status do_sort_buckets(const elsar_model* m, const void* d_part, size_t part_bytes, uint64_t n,
-                             const uint64_t* d_offsets, void* d_out, hipStream_t st) {
+                             const uint64_t* d_offsets, void* d_out, hipStream_t st, PhaseMarks* pm) {
   PartLayout lay = part_layout(n, m->B, m->p.record_bytes, m->p.region_pct);
   if (part_bytes < lay.bytes) return ELSAR_E_NO_MEMORY;
-  HIP_TRY(launch_bucket_sort(static_cast<const uint8_t*>(d_part), lay, m->B, d_offsets, m->p.record_bytes,
-                             m->p.key_bytes, static_cast<uint8_t*>(d_out), st));
+  const uint8_t* part = static_cast<const uint8_t*>(d_part);
+  uint8_t* out = static_cast<uint8_t*>(d_out);
+  HIP_TRY(launch_bucket_sort_small(part, lay, m->B, d_offsets, m->p.record_bytes, m->p.key_bytes, out, st));
+  if (pm) mark(*pm, 4, st);
+  HIP_TRY(launch_bucket_sort_large(part, lay, m->B, d_offsets, m->p.record_bytes, m->p.key_bytes, out, st));
+  if (pm) mark(*pm, 5, st);
   return ELSAR_OK;
 }
 
@@ -317,7 +321,9 @@ elsar_status elsar_sort_buckets(const elsar_model* m, const void* d_part, size_t
   if (!m || !d_part || !d_bucket_offsets) return ELSAR_E_INVALID_ARG;
   if (n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;
   if (n && (!d_out || !aligned16(d_out))) return ELSAR_E_INVALID_ARG;
-  return do_sort_buckets(m, d_part, part_bytes, n, d_bucket_offsets, d_out, stream);
+  PhaseMarks pm = begin_marks();
+  mark(pm, 3, stream);
+  return do_sort_buckets(m, d_part, part_bytes, n, d_bucket_offsets, d_out, stream, &pm);
 }
 
 elsar_status elsar_sort_workspace_size(const elsar_fit_params* p, uint64_t n, size_t* bytes) {
@@ -362,9 +368,7 @@ elsar_status elsar_sort(const void* d_in, uint64_t n, void* d_out, const elsar_f
   s = do_partition(&m, d_in, n, w + sl.part, sl.lay.bytes, offsets, stream, &pm);
   if (s != ELSAR_OK) return s;
   mark(pm, 3, stream);
-  s = do_sort_buckets(&m, w + sl.part, sl.lay.bytes, n, offsets, d_out, stream);
-  mark(pm, 4, stream);
-  return s;
+  return do_sort_buckets(&m, w + sl.part, sl.lay.bytes, n, offsets, d_out, stream, &pm);
 }
 
 elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info) {
@@ -414,6 +418,8 @@ elsar_status elsar_partition_stats_get(const elsar_model* m, const void* d_part,
   st->mid_buckets = h.n_mid;
   st->big_buckets = h.n_big;
   st->max_bucket = h.max_count;
+  st->mid_records = h.mid_records;
+  st->big_records = h.big_records;
   return ELSAR_OK;
 }
 
@@ -436,14 +442,14 @@ elsar_status elsar_timings_get(elsar_timings* t) {
   std::memset(t, 0, sizeof(*t));
   std::lock_guard<std::mutex> lk(g_timing.mu);
   if (g_timing.ev.empty() || g_timing.used == 0) return ELSAR_OK;
-  double acc[4] = {0, 0, 0, 0}, tot = 0;
-  int cnt[4] = {0, 0, 0, 0}, ctot = 0;
+  double acc[kTimedPhases - 1] = {}, tot = 0;
+  int cnt[kTimedPhases - 1] = {}, ctot = 0;
   for (int s = 0; s < g_timing.used; ++s) {
     hipEvent_t* e = &g_timing.ev[(size_t)s * kTimedPhases];
     uint8_t hv = g_timing.have[s];
     for (int i = 0; i < kTimedPhases; ++i)
       if ((hv >> i) & 1u) HIP_TRY(hipEventSynchronize(e[i]));
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i + 1 < kTimedPhases; ++i) {
       if (((hv >> i) & 1u) && ((hv >> (i + 1)) & 1u)) {
         float ms = 0;
         HIP_TRY(hipEventElapsedTime(&ms, e[i], e[i + 1]));
@@ -453,7 +459,10 @@ elsar_status elsar_timings_get(elsar_timings* t) {
     }
     int first = -1, last = -1;
     for (int i = 0; i < kTimedPhases; ++i)
-      if ((hv >> i) & 1u) { if (first < 0) first = i; last = i; }
+      if ((hv >> i) & 1u) {
+        if (first < 0) first = i;
+        last = i;
+      }
     if (first >= 0 && last > first) {
       float ms = 0;
       HIP_TRY(hipEventElapsedTime(&ms, e[first], e[last]));
@@ -461,10 +470,12 @@ elsar_status elsar_timings_get(elsar_timings* t) {
       ctot++;
     }
   }
-  t->sample_fit_ms = cnt[0] ? (float)(acc[0] / cnt[0]) : 0.0f;
-  t->partition_ms = cnt[1] ? (float)(acc[1] / cnt[1]) : 0.0f;
-  t->scan_ms = cnt[2] ? (float)(acc[2] / cnt[2]) : 0.0f;
-  t->bucket_sort_ms = cnt[3] ? (float)(acc[3] / cnt[3]) : 0.0f;
+  auto mean = [&](int i) { return cnt[i] ? (float)(acc[i] / cnt[i]) : 0.0f; };
+  t->sample_fit_ms = mean(0);
+  t->partition_ms = mean(1);
+  t->scan_ms = mean(2);
+  t->bucket_sort_lds_ms = mean(3);
+  t->bucket_sort_rest_ms = mean(4);
   t->total_ms = ctot ? (float)(tot / ctot) : 0.0f;
   t->calls = (uint32_t)g_timing.used;
   return ELSAR_OK;

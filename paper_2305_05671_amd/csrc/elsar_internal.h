@@ -8,9 +8,13 @@
 namespace elsar {
 
 // ---------------------------------------------------------------- layout --
-// One partition slot: the 100-byte record followed by its 32-bit input index.
-// Slots are 8-byte aligned (104 = 8 * 13); the index makes the in-bucket order
-// independent of the order in which the atomics handed out slots.
+// One partition slot: the record's 32-bit input index, then the record, zero
+// padding up to a whole number of 128-byte lines (one line for 100-byte
+// records).  A slot is written as full lines, so no write leaves a partial
+// line for the memory side to merge.  Its first 16 bytes hold the index and
+// the first 12 record bytes, so one load gives the whole sort key.  The index
+// makes the in-bucket order independent of the order in which the atomics
+// handed out slots.
 constexpr uint32_t kMaxKeyBytes = 12;   // the LDS sort entry holds key + 4-byte index
 constexpr uint32_t kMinKeyBytes = 8;    // the code reads the first 8 key bytes
 constexpr uint32_t kSmallCap = 2048;    // largest bucket sorted by the small LDS kernel
@@ -44,7 +48,9 @@ struct PartHeader {    // device-resident state of one partition pass
   uint32_t n_mid;       // buckets with kSmallCap < count <= kMidCap
   uint32_t n_big;       // buckets with count > kMidCap
   uint32_t max_count;
-  uint32_t pad[9];
+  uint32_t mid_records;  // records in the n_mid buckets
+  uint32_t big_records;  // records in the n_big buckets
+  uint32_t pad[7];
 };
 
 // Byte offsets of the partition buffer's parts for n records and B buckets.
@@ -54,10 +60,16 @@ struct PartLayout {
   uint64_t cap_slots;   // region slots
   uint64_t total_slots; // regions + spill
   size_t bytes;
-  uint32_t slot_bytes;
+  uint32_t slot_bytes;  // slot_bytes_for(record_bytes)
 };
 
+__host__ __device__ constexpr uint32_t slot_bytes_for(uint32_t rec_bytes) { return (rec_bytes + 4 + 127) / 128 * 128; }
+
 // ----------------------------------------------------------- device code --
+// Native 4 x u32 vector for register-held data: HIP's uint4 struct copies go
+// through memcpy, which can pin the value in scratch memory.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ uint32_t philox_x(uint64_t ctr_lo64, uint32_t c2, uint32_t c3, uint64_t key) {
   // Philox4x32-10 (Salmon et al., SC'11); only the first output word is used.
   uint32_t c0 = (uint32_t)ctr_lo64, c1 = (uint32_t)(ctr_lo64 >> 32);
@@ -142,6 +154,41 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int off) {
+  uint32_t lo = __shfl_up((uint32_t)v, off), hi = __shfl_up((uint32_t)(v >> 32), off);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Exclusive scan of one value per thread across a block of NT threads (NT a
+// multiple of 64, at most 1024).  *total gets the block's sum.  sh: NT/64 slots.
+template <typename T, uint32_t NT>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T* total) {
+  T x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    T y;
+    if constexpr (sizeof(T) == 8) y = (T)shfl_up_u64((uint64_t)x, off);
+    else y = (T)__shfl_up((uint32_t)x, off);
+    if (lane_id() >= (uint32_t)off) x += y;
+  }
+  const uint32_t w = threadIdx.x >> 6;
+  if (lane_id() == 63) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T run = 0;
+    for (uint32_t i = 0; i < NT / 64; ++i) {
+      T c = sh[i];
+      sh[i] = run;
+      run += c;
+    }
+    sh[NT / 64] = run;
+  }
+  __syncthreads();
+  T r = sh[w] + x - v;
+  *total = sh[NT / 64];
+  __syncthreads();
+  return r;
+}
+
 // ---------------------------------------------------------- host wrappers --
 // sample / fit (k_fit.hip)
 hipError_t launch_sample_codes(const uint8_t* recs, uint64_t n, uint32_t rec_bytes, uint64_t S, uint64_t seed,
@@ -166,7 +213,9 @@ hipError_t launch_scan_counts(uint8_t* part, const PartLayout& lay, uint32_t B, 
 hipError_t launch_spill_fixup(uint8_t* part, const PartLayout& lay, uint64_t n, hipStream_t st);
 
 // bucket sort (k_bucket_sort.hip)
-hipError_t launch_bucket_sort(const uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
-                              uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st);
+hipError_t launch_bucket_sort_small(const uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
+                                    uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st);
+hipError_t launch_bucket_sort_large(const uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
+                                    uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st);
 
 }  // namespace elsar

@@ -2,20 +2,27 @@
 // and Section 3.5 (write it at the exclusive prefix sum of the partition sizes,
 // coalescing the records in sorted order).
 //
-// A bucket's records sit in its region (and possibly the spill area).  Each is
-// reduced to a 16-byte sort entry: the key bytes and then the 32-bit input
-// index, as one big-endian composite, so sorting the composites orders by
-// key in memcmp order and breaks ties by input position.  An LSD radix sort
-// with 8-bit digits runs over the composite's bytes, skipping every byte that
-// is equal across the whole bucket (an all-equal-key bucket only sorts its
-// index bytes).  The records are then copied in sorted order to
-// out + R * offsets[j] with dword stores contiguous across lanes.
+// A bucket's records sit in its region (and possibly the spill area) as
+// 128-byte slots: record, 32-bit input index, padding.  Each record gives a
+// composite sort key: the key bytes and then the index, big-endian, so the
+// composite order is the key's memcmp order with ties broken by input
+// position, and all composites of a bucket differ.  Sorting uses stable LSD
+// radix passes with 8-bit digits over composite bytes; a byte that is equal
+// across the whole bucket needs no pass (an all-equal-key bucket only sorts
+// its index bytes -- early termination on duplicates).
 //
-//  * bucket_sort_lds<CAP, THREADS>: one block per bucket of at most CAP records;
-//    entries and the permutation live in LDS.
-//  * bucket_sort_global: buckets above the larger cap, one block each; the
-//    ping-pong entry buffers live in the bucket's own output range, which holds
-//    R*n bytes and is not yet written (R >= 40 gives 2 * 20n bytes of room).
+//  * bucket_sort_reg: buckets of up to 2048 records, one 1024-thread block
+//    each.  Every slot is read exactly once, as whole lines, into registers.
+//    The block first sorts on the 4 composite bytes after the bucket's common
+//    prefix; adjacent entries that tie on them are then ordered by the rest of
+//    the composite (insertion sort per short run, or a full LSD sort if a run
+//    is long).  The records leave through an LDS staging buffer in sorted
+//    order with stores contiguous across lanes.
+//  * bucket_sort_lds: buckets of up to 6144 records (all varying composite
+//    bytes, entries and permutation in LDS, records gathered from the slots).
+//  * bucket_sort_global: larger buckets, one block each; the ping-pong entry
+//    buffers live in the bucket's own output range, which holds R*n bytes and
+//    is not written yet (R >= 40 leaves room for 2 * 20n bytes).
 #include "elsar_internal.h"
 
 namespace elsar {
@@ -31,15 +38,23 @@ __device__ __forceinline__ uint32_t slot_of(const BucketRef& br, uint32_t p, con
   return p < br.nr ? br.rs + p : (uint32_t)cap_slots + spill_map[br.so + (p - br.nr)];
 }
 
-// Composite sort key of a slot: key bytes [0, K) then the index, big-endian,
-// as four words (word 0 most significant).  Bytes beyond K+4 are zero.
-__device__ __forceinline__ uint4 composite(const uint32_t* __restrict__ s, uint32_t W, uint32_t K) {
-  uint32_t w0 = s[0], w1 = s[1], w2 = s[2], idx = s[W - 1];
-  uint32_t tb = K - 8;  // key bytes in the third word, 0..4
-  uint32_t t = __builtin_bswap32(w2);
-  t = tb == 0 ? 0u : (tb >= 4 ? t : (t & (0xFFFFFFFFu << (32 - 8 * tb))));
+__device__ __forceinline__ uint32_t key_tail_mask(uint32_t K) {  // key bytes 8..K-1, big-endian in a word
+  uint32_t tb = K - 8;
+  return tb == 0 ? 0u : (tb >= 4 ? ~0u : (0xFFFFFFFFu << (32 - 8 * tb)));
+}
+
+// Composite sort key of a slot as four words, word 0 most significant: key
+// bytes [0, K) then the 4 index bytes, big-endian, zero beyond.  Slot dword 0
+// is the index, dwords 1.. the record.
+__device__ __forceinline__ uint4 composite_words(uint32_t idx, uint32_t r0, uint32_t r1, uint32_t r2, uint32_t K) {
+  uint32_t tb = K - 8;
+  uint32_t t = __builtin_bswap32(r2) & key_tail_mask(K);
   uint64_t low = ((uint64_t)t << 32) | ((uint64_t)idx << (32 - 8 * tb));
-  return make_uint4(__builtin_bswap32(w0), __builtin_bswap32(w1), (uint32_t)(low >> 32), (uint32_t)low);
+  return make_uint4(__builtin_bswap32(r0), __builtin_bswap32(r1), (uint32_t)(low >> 32), (uint32_t)low);
+}
+
+__device__ __forceinline__ uint4 composite(const uint32_t* __restrict__ s, uint32_t /*RW*/, uint32_t K) {
+  return composite_words(s[0], s[1], s[2], s[3], K);
 }
 
 __device__ __forceinline__ uint32_t digit_of(const uint4& c, uint32_t p) {
@@ -47,9 +62,10 @@ __device__ __forceinline__ uint32_t digit_of(const uint4& c, uint32_t p) {
   return (w >> (24 - 8 * (p & 3))) & 0xFFu;
 }
 
-// OR and AND across the block; *vary gets the composite bytes that differ.
+// OR ^ AND of every thread's composite words across the block: the bits that
+// differ somewhere in the bucket.
 template <uint32_t THREADS>
-__device__ uint32_t varying_bytes(uint4 o, uint4 a, uint4* sh_or, uint4* sh_and) {
+__device__ uint4 block_diff(uint4 o, uint4 a, uint4* sh_or, uint4* sh_and) {
   const uint32_t w = threadIdx.x >> 6;
   for (int off = 32; off > 0; off >>= 1) {
     o.x |= __shfl_xor(o.x, off); o.y |= __shfl_xor(o.y, off);
@@ -65,11 +81,29 @@ __device__ uint32_t varying_bytes(uint4 o, uint4 a, uint4* sh_or, uint4* sh_and)
     O.x |= x.x; O.y |= x.y; O.z |= x.z; O.w |= x.w;
     A.x &= y.x; A.y &= y.y; A.z &= y.z; A.w &= y.w;
   }
-  uint4 d = make_uint4(O.x ^ A.x, O.y ^ A.y, O.z ^ A.z, O.w ^ A.w);
+  __syncthreads();
+  return make_uint4(O.x ^ A.x, O.y ^ A.y, O.z ^ A.z, O.w ^ A.w);
+}
+
+// Bit p set when composite byte p (0..15) varies.
+__device__ __forceinline__ uint32_t vary_mask(const uint4& d) {
   uint32_t vary = 0;
   for (uint32_t p = 0; p < 16; ++p) vary |= (uint32_t)(digit_of(d, p) != 0) << p;
-  __syncthreads();
   return vary;
+}
+
+// First varying bit of the composite (0 = most significant); 128 if none.
+__device__ __forceinline__ uint32_t first_bit(const uint4& d) {
+  if (d.x) return __builtin_clz(d.x);
+  if (d.y) return 32 + __builtin_clz(d.y);
+  if (d.z) return 64 + __builtin_clz(d.z);
+  if (d.w) return 96 + __builtin_clz(d.w);
+  return 128;
+}
+
+template <uint32_t THREADS>
+__device__ uint32_t varying_bytes(uint4 o, uint4 a, uint4* sh_or, uint4* sh_and) {
+  return vary_mask(block_diff<THREADS>(o, a, sh_or, sh_and));
 }
 
 // Exclusive scan over the 256 digits of per-wave counts wc[w][d] -> start
@@ -83,8 +117,7 @@ __device__ void digit_wave_offsets(uint32_t (*wc)[256], uint32_t* tot) {
       wc[w][d] = run;
       run += c;
     }
-    // inclusive scan of run over the 4 waves of the first 256 threads
-    uint32_t v = run;
+    uint32_t v = run;  // inclusive scan of the digit totals over the first 4 waves
     for (int off = 1; off < 64; off <<= 1) {
       uint32_t x = __shfl_up(v, off);
       if (lane_id() >= (uint32_t)off) v += x;
@@ -100,6 +133,208 @@ __device__ void digit_wave_offsets(uint32_t (*wc)[256], uint32_t* tot) {
   }
 }
 
+// One stable counting pass of perm[cur][0..n) on the digit dg(e) of each entry
+// e; the result goes to perm[cur ^ 1].  Each wave ranks a contiguous segment
+// of ROUNDS*64 positions in order, so ties keep their order.
+template <uint32_t CAP, uint32_t THREADS, typename Digit>
+__device__ void lsd_pass(uint16_t (*perm)[CAP], uint32_t cur, uint32_t n, uint32_t (*wc)[256], uint32_t* tot,
+                         Digit dg) {
+  constexpr uint32_t WAVES = THREADS / 64;
+  constexpr uint32_t ROUNDS = CAP / THREADS;
+  const uint32_t w = threadIdx.x >> 6;
+  for (uint32_t i = threadIdx.x; i < WAVES * 256; i += THREADS) (&wc[0][0])[i] = 0;
+  __syncthreads();
+  uint32_t dv[ROUNDS], lc[ROUNDS];
+  uint16_t ev[ROUNDS];
+#pragma unroll
+  for (uint32_t r = 0; r < ROUNDS; ++r) {
+    uint32_t i = w * (ROUNDS * 64) + r * 64 + lane_id();
+    bool valid = i < n;
+    uint16_t e = valid ? perm[cur][i] : 0;
+    uint32_t d = valid ? dg(e) : 0u;
+    uint64_t peers = match_digit8(d, valid);
+    uint32_t rank = __popcll(peers & lanemask_lt());
+    uint32_t prev = valid ? wc[w][d] : 0u;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == 0) wc[w][d] = prev + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    dv[r] = d;
+    lc[r] = prev + rank;
+    ev[r] = e;
+  }
+  __syncthreads();
+  digit_wave_offsets<WAVES>(wc, tot);
+  __syncthreads();
+#pragma unroll
+  for (uint32_t r = 0; r < ROUNDS; ++r) {
+    uint32_t i = w * (ROUNDS * 64) + r * 64 + lane_id();
+    if (i < n) perm[cur ^ 1][wc[w][dv[r]] + lc[r]] = ev[r];
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------- buckets of up to 2048 records --
+constexpr uint32_t kSmThreads = 512;
+constexpr uint32_t kSmWaves = kSmThreads / 64;
+constexpr uint32_t kSmCap = kSmallCap;
+constexpr uint32_t kSmBits = 11;     // counting-sort digit: 2048 bins
+constexpr uint32_t kSmStage = 128;   // records per output batch
+constexpr uint32_t kRunMax = 32;     // longest bin sorted by insertion
+
+// D bits of a 128-bit big-endian composite starting at bit cb (0 = most significant).
+__device__ __forceinline__ uint32_t bits_at(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t cb,
+                                            uint32_t D) {
+  uint64_t hi = ((uint64_t)c0 << 32) | c1, lo = ((uint64_t)c2 << 32) | c3;
+  uint64_t top = cb == 0 ? hi : (cb < 64 ? (hi << cb) | (lo >> (64 - cb)) : lo << (cb - 64));
+  return (uint32_t)(top >> (64 - D));
+}
+
+template <uint32_t RW>  // record dwords
+__global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
+    const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map, const uint4* __restrict__ slots,
+    uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t K, uint32_t* __restrict__ out, uint32_t B) {
+  constexpr uint32_t SC = slot_bytes_for(RW * 4) / 16;  // 16-byte chunks per slot
+  constexpr uint32_t LC = (RW + 1 + 3) / 4;             // chunks holding the index or record bytes
+  constexpr uint32_t AR = kSmCap / kSmThreads;          // entries per thread
+  constexpr uint32_t CR = (kSmStage * LC + kSmThreads - 1) / kSmThreads;  // chunk loads per thread per batch
+  __shared__ uint32_t cw[4][kSmCap];                    // composite words of every entry
+  __shared__ uint16_t perm[2][kSmCap];
+  __shared__ uint32_t bins[1u << kSmBits];              // also the LSD fallback's per-wave counters
+  __shared__ uint32_t stage[kSmStage * RW];
+  __shared__ uint4 sh_or[kSmWaves], sh_and[kSmWaves];
+  __shared__ uint32_t sh_scan[kSmThreads / 64 + 1];
+  __shared__ uint32_t tot[4];
+  static_assert((1u << kSmBits) == kSmWaves * 256, "bins double as the LSD counters");
+  const uint32_t tid = threadIdx.x;
+  const uint32_t j = blockIdx.x;
+  if (j >= B) return;
+  BucketRef br;
+  br.n = counts[j];
+  if (br.n == 0 || br.n > kSmCap) return;
+  const uint32_t cap = caps[j];
+  br.nr = br.n < cap ? br.n : cap;
+  br.rs = rstart[j];
+  br.so = spill_off[j];
+  br.out0 = offsets[j];
+  const uint32_t n = br.n;
+
+  // 1. the first 16 bytes of every slot: index and key
+  uint4 v[AR];
+#pragma unroll
+  for (uint32_t i = 0; i < AR; ++i) {
+    uint32_t p = tid + i * kSmThreads;
+    if (p < n) v[i] = slots[(uint64_t)slot_of(br, p, spill_map, cap_slots) * SC];
+  }
+  uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
+#pragma unroll
+  for (uint32_t i = 0; i < AR; ++i) {
+    uint32_t p = tid + i * kSmThreads;
+    if (p < n) {
+      uint4 c = composite_words(v[i].x, v[i].y, v[i].z, v[i].w, K);
+      cw[0][p] = c.x; cw[1][p] = c.y; cw[2][p] = c.z; cw[3][p] = c.w;
+      o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
+      a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+    }
+  }
+  // bits that vary across the bucket (syncs; the entries are visible afterwards)
+  const uint4 diff = block_diff<kSmThreads>(o, a, sh_or, sh_and);
+  const uint32_t vary = vary_mask(diff);
+  auto less = [&](uint32_t x, uint32_t y) -> bool {
+    if (cw[0][x] != cw[0][y]) return cw[0][x] < cw[0][y];
+    if (cw[1][x] != cw[1][y]) return cw[1][x] < cw[1][y];
+    if (cw[2][x] != cw[2][y]) return cw[2][x] < cw[2][y];
+    return cw[3][x] < cw[3][y];
+  };
+  uint32_t cur = 0;
+  if (n == 1) {
+    if (tid == 0) perm[0][0] = 0;
+  } else {
+    // 2. one counting pass on the kSmBits bits after the bucket's common bit
+    //    prefix (the bits before are equal across the bucket, so the digit is
+    //    a non-decreasing function of the composite)
+    const uint32_t cb = first_bit(diff);
+    for (uint32_t i = tid; i < (1u << kSmBits); i += kSmThreads) bins[i] = 0;
+    __syncthreads();
+    auto digit = [&](uint32_t e) { return bits_at(cw[0][e], cw[1][e], cw[2][e], cw[3][e], cb, kSmBits); };
+    for (uint32_t p = tid; p < n; p += kSmThreads) atomicAdd(&bins[digit(p)], 1u);
+    __syncthreads();
+    {  // exclusive scan of the bins: 4 contiguous per thread
+      constexpr uint32_t PER = (1u << kSmBits) / kSmThreads;
+      uint32_t c[PER], sum = 0;
+#pragma unroll
+      for (uint32_t i = 0; i < PER; ++i) { c[i] = bins[tid * PER + i]; sum += c[i]; }
+      uint32_t total;
+      uint32_t run = block_exclusive_scan<uint32_t, kSmThreads>(sum, sh_scan, &total);
+#pragma unroll
+      for (uint32_t i = 0; i < PER; ++i) { bins[tid * PER + i] = run; run += c[i]; }
+    }
+    __syncthreads();
+    for (uint32_t p = tid; p < n; p += kSmThreads) perm[0][atomicAdd(&bins[digit(p)], 1u)] = (uint16_t)p;
+    __syncthreads();
+    // bins[b] is now the end of bin b; the start is the end of bin b-1
+    bool long_bin = false;
+    for (uint32_t b = tid; b < (1u << kSmBits); b += kSmThreads) {
+      uint32_t s0 = b ? bins[b - 1] : 0u, s1 = bins[b];
+      if (s1 - s0 < 2) continue;
+      if (s1 - s0 > kRunMax) { long_bin = true; continue; }
+      for (uint32_t x = s0 + 1; x < s1; ++x) {  // insertion sort by the whole composite
+        uint16_t e = perm[0][x];
+        uint32_t y = x;
+        while (y > s0 && less(e, perm[0][y - 1])) {
+          perm[0][y] = perm[0][y - 1];
+          --y;
+        }
+        perm[0][y] = e;
+      }
+    }
+    long_bin = __syncthreads_or(long_bin);
+    if (long_bin) {  // stable LSD over every varying composite byte
+      auto wc = reinterpret_cast<uint32_t(*)[256]>(bins);
+      for (int pb = 15; pb >= 0; --pb) {
+        if (!((vary >> pb) & 1u)) continue;
+        lsd_pass<kSmCap, kSmThreads>(perm, cur, n, wc, tot, [&](uint32_t e) {
+          return (cw[pb >> 2][e] >> (24 - 8 * (pb & 3))) & 0xFFu;
+        });
+        cur ^= 1;
+      }
+    }
+  }
+  __syncthreads();
+  // 3. gather the records in sorted order, kSmStage at a time, through LDS
+  uint32_t* o_dw = out + br.out0 * RW;
+  for (uint32_t k0 = 0; k0 < n; k0 += kSmStage) {
+    const uint32_t kb = n - k0 < kSmStage ? n - k0 : kSmStage;
+    const uint32_t nq = kb * LC;
+    uint4 g[CR];
+#pragma unroll
+    for (uint32_t i = 0; i < CR; ++i) {
+      uint32_t q = tid + i * kSmThreads;
+      if (q < nq) {
+        uint32_t kk = q / LC, c = q - kk * LC;
+        g[i] = slots[(uint64_t)slot_of(br, perm[cur][k0 + kk], spill_map, cap_slots) * SC + c];
+      }
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < CR; ++i) {
+      uint32_t q = tid + i * kSmThreads;
+      if (q < nq) {
+        uint32_t kk = q / LC, c = q - kk * LC;
+        uint32_t x[4] = {g[i].x, g[i].y, g[i].z, g[i].w};
+#pragma unroll
+        for (uint32_t t = 0; t < 4; ++t) {
+          uint32_t sd = 4 * c + t;  // slot dword: 0 index, 1..RW record
+          if (sd >= 1 && sd <= RW) stage[kk * RW + sd - 1] = x[t];
+        }
+      }
+    }
+    __syncthreads();
+    for (uint32_t f = tid; f < kb * RW; f += kSmThreads) o_dw[(uint64_t)k0 * RW + f] = stage[f];
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------- buckets of up to 6144 records --
 template <uint32_t CAP, uint32_t THREADS>
 __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
@@ -108,15 +343,13 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
     uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
     uint32_t B) {
   constexpr uint32_t WAVES = THREADS / 64;
-  constexpr uint32_t ROUNDS = CAP / THREADS;
   static_assert(CAP % THREADS == 0, "cap is whole rounds");
   __shared__ uint4 ent[CAP];
   __shared__ uint16_t perm[2][CAP];
   __shared__ uint32_t wc[WAVES][256];
   __shared__ uint4 sh_or[WAVES], sh_and[WAVES];
   __shared__ uint32_t tot[4];
-  const uint32_t W = RW + 1;
-  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t W = slot_bytes_for(RW * 4) / 4;  // slot stride in dwords
   const uint32_t nitems = list ? *list_n : B;
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const uint32_t j = list ? list[it] : it;
@@ -132,7 +365,7 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
     uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
     for (uint32_t p = threadIdx.x; p < br.n; p += THREADS) {
       uint32_t sl = slot_of(br, p, spill_map, cap_slots);
-      uint4 c = composite(slots + (uint64_t)sl * W, W, K);
+      uint4 c = composite(slots + (uint64_t)sl * W, RW, K);
       ent[p] = c;
       perm[0][p] = (uint16_t)p;
       o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
@@ -144,35 +377,8 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
     const uint32_t nb = K + 4;
     for (int pbyte = (int)nb - 1; pbyte >= 0; --pbyte) {
       if (!((vary >> pbyte) & 1u)) continue;
-      for (uint32_t i = threadIdx.x; i < WAVES * 256; i += THREADS) (&wc[0][0])[i] = 0;
-      __syncthreads();
-      uint32_t dg[ROUNDS], lc[ROUNDS];
-      uint16_t ev[ROUNDS];
-#pragma unroll
-      for (uint32_t r = 0; r < ROUNDS; ++r) {
-        uint32_t i = w * (ROUNDS * 64) + r * 64 + lane_id();
-        bool valid = i < br.n;
-        uint16_t e = valid ? perm[cur][i] : 0;
-        uint32_t d = valid ? digit_of(ent[e], (uint32_t)pbyte) : 0u;
-        uint64_t peers = match_digit8(d, valid);
-        uint32_t rank = __popcll(peers & lanemask_lt());
-        uint32_t prev = valid ? wc[w][d] : 0u;
-        __builtin_amdgcn_wave_barrier();
-        if (valid && rank == 0) wc[w][d] = prev + (uint32_t)__popcll(peers);
-        __builtin_amdgcn_wave_barrier();
-        dg[r] = d;
-        lc[r] = prev + rank;
-        ev[r] = e;
-      }
-      __syncthreads();
-      digit_wave_offsets<WAVES>(wc, tot);
-      __syncthreads();
-#pragma unroll
-      for (uint32_t r = 0; r < ROUNDS; ++r) {
-        uint32_t i = w * (ROUNDS * 64) + r * 64 + lane_id();
-        if (i < br.n) perm[cur ^ 1][wc[w][dg[r]] + lc[r]] = ev[r];
-      }
-      __syncthreads();
+      lsd_pass<CAP, THREADS>(perm, cur, br.n, wc, tot,
+                             [&](uint32_t e) { return digit_of(ent[e], (uint32_t)pbyte); });
       cur ^= 1;
     }
     // 3. copy records in sorted order to the output
@@ -181,7 +387,7 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
     for (uint32_t f = threadIdx.x; f < total; f += THREADS) {
       uint32_t k = f / RW, d = f - k * RW;
       uint32_t sl = slot_of(br, perm[cur][k], spill_map, cap_slots);
-      o_dw[f] = slots[(uint64_t)sl * W + d];
+      o_dw[f] = slots[(uint64_t)sl * W + d + 1];
     }
     __syncthreads();
   }
@@ -214,7 +420,7 @@ __global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
   __shared__ uint4 sh_or[kBigWaves], sh_and[kBigWaves];
   __shared__ uint32_t tot[4];
   __shared__ uint32_t chunk_slot[kBigTile];
-  const uint32_t W = RW + 1;
+  const uint32_t W = slot_bytes_for(RW * 4) / 4;  // slot stride in dwords
   const uint32_t w = threadIdx.x >> 6;
   const uint32_t nitems = *list_n;
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -226,13 +432,13 @@ __global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
     br.rs = rstart[j];
     br.so = spill_off[j];
     br.out0 = offsets[j];
-    uint32_t* o_dw = out + br.out0 * RW;           // R*n bytes = RW*n dwords
+    uint32_t* o_dw = out + br.out0 * RW;                  // R*n bytes = RW*n dwords
     uint32_t* buf0 = o_dw + (uint64_t)(RW - 10) * br.n;  // (R-40)*n bytes in
     uint32_t* buf1 = o_dw + (uint64_t)(RW - 5) * br.n;   // (R-20)*n bytes in
     // 1. which composite bytes vary
     uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
     for (uint32_t p = threadIdx.x; p < br.n; p += kBigThreads) {
-      uint4 c = composite(slots + (uint64_t)slot_of(br, p, spill_map, cap_slots) * W, W, K);
+      uint4 c = composite(slots + (uint64_t)slot_of(br, p, spill_map, cap_slots) * W, RW, K);
       o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
       a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
     }
@@ -244,7 +450,7 @@ __global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
     uint32_t* nxt = (passes & 1u) ? buf1 : buf0;
     for (uint32_t p = threadIdx.x; p < br.n; p += kBigThreads) {
       uint32_t sl = slot_of(br, p, spill_map, cap_slots);
-      put_entry(cur, p, composite(slots + (uint64_t)sl * W, W, K), sl);
+      put_entry(cur, p, composite(slots + (uint64_t)sl * W, RW, K), sl);
     }
     __syncthreads();
     // 2. stable LSD passes through global memory
@@ -326,33 +532,59 @@ __global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
       const uint32_t total = m * RW;
       for (uint32_t f = threadIdx.x; f < total; f += kBigThreads) {
         uint32_t k = f / RW, d = f - k * RW;
-        o_dw[(uint64_t)k0 * RW + f] = slots[(uint64_t)chunk_slot[k] * W + d];
+        o_dw[(uint64_t)k0 * RW + f] = slots[(uint64_t)chunk_slot[k] * W + d + 1];
       }
       __syncthreads();
     }
   }
 }
 
-hipError_t launch_bucket_sort(const uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
-                              uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st) {
-  const uint32_t RW = rec_bytes / 4;
-  auto* counts = reinterpret_cast<const uint32_t*>(part + lay.counts);
-  auto* caps = reinterpret_cast<const uint32_t*>(part + lay.caps);
-  auto* rstart = reinterpret_cast<const uint32_t*>(part + lay.rstart);
-  auto* soff = reinterpret_cast<const uint32_t*>(part + lay.spill_off);
-  auto* smap = reinterpret_cast<const uint32_t*>(part + lay.spill_map);
-  auto* slots = reinterpret_cast<const uint32_t*>(part + lay.slots);
-  auto* ph = reinterpret_cast<const PartHeader*>(part + lay.header);
-  auto* o = reinterpret_cast<uint32_t*>(out);
-  bucket_sort_lds_kernel<kSmallCap, 256><<<B, 256, 0, st>>>(counts, caps, rstart, soff, smap, slots, lay.cap_slots,
-                                                             offsets, RW, key_bytes, o, nullptr, nullptr, B);
+struct SortArgs {
+  const uint32_t *counts, *caps, *rstart, *soff, *smap, *slots;
+  const PartHeader* ph;
+  uint32_t* out;
+  uint32_t RW;
+};
+
+static SortArgs sort_args(const uint8_t* part, const PartLayout& lay, uint32_t rec_bytes, uint8_t* out) {
+  SortArgs a;
+  a.counts = reinterpret_cast<const uint32_t*>(part + lay.counts);
+  a.caps = reinterpret_cast<const uint32_t*>(part + lay.caps);
+  a.rstart = reinterpret_cast<const uint32_t*>(part + lay.rstart);
+  a.soff = reinterpret_cast<const uint32_t*>(part + lay.spill_off);
+  a.smap = reinterpret_cast<const uint32_t*>(part + lay.spill_map);
+  a.slots = reinterpret_cast<const uint32_t*>(part + lay.slots);
+  a.ph = reinterpret_cast<const PartHeader*>(part + lay.header);
+  a.out = reinterpret_cast<uint32_t*>(out);
+  a.RW = rec_bytes / 4;
+  return a;
+}
+
+hipError_t launch_bucket_sort_small(const uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
+                                    uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st) {
+  SortArgs a = sort_args(part, lay, rec_bytes, out);
+  if (rec_bytes == 100) {
+    bucket_sort_small_kernel<25><<<B, kSmThreads, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap,
+                                                           reinterpret_cast<const uint4*>(a.slots), lay.cap_slots,
+                                                           offsets, key_bytes, a.out, B);
+  } else {
+    bucket_sort_lds_kernel<kSmallCap, 256><<<B, 256, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots,
+                                                               lay.cap_slots, offsets, a.RW, key_bytes, a.out,
+                                                               nullptr, nullptr, B);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bucket_sort_large(const uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
+                                    uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st) {
+  SortArgs a = sort_args(part, lay, rec_bytes, out);
   bucket_sort_lds_kernel<kMidCap, 512><<<256, 512, 0, st>>>(
-      counts, caps, rstart, soff, smap, slots, lay.cap_slots, offsets, RW, key_bytes, o,
-      reinterpret_cast<const uint32_t*>(part + lay.mid_list), &ph->n_mid, B);
-  bucket_sort_global_kernel<<<256, kBigThreads, 0, st>>>(counts, caps, rstart, soff, smap, slots, lay.cap_slots,
-                                                         offsets, RW, key_bytes, o,
+      a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
+      reinterpret_cast<const uint32_t*>(part + lay.mid_list), &a.ph->n_mid, B);
+  bucket_sort_global_kernel<<<256, kBigThreads, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots,
+                                                         lay.cap_slots, offsets, a.RW, key_bytes, a.out,
                                                          reinterpret_cast<const uint32_t*>(part + lay.big_list),
-                                                         &ph->n_big);
+                                                         &a.ph->n_big);
   return hipGetLastError();
 }
 

@@ -54,35 +54,42 @@ __global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const uint64_
   tile_hist[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Exclusive scan of m u32 values in place, one block of 1024 threads.
-__global__ __launch_bounds__(1024) void scan_u32_kernel(uint32_t* __restrict__ v, uint64_t m) {
-  __shared__ uint32_t part[1024];
-  uint64_t per = (m + 1023) / 1024;
-  uint64_t b = threadIdx.x * per, e = b + per < m ? b + per : m;
-  uint32_t s = 0;
-  for (uint64_t i = b; i < e; ++i) s += v[i];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t x = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += x;
-    __syncthreads();
+// Per digit d (one block each): exclusive scan over the tiles of d's counts,
+// in place; digit_tot[d] gets d's total.
+__global__ __launch_bounds__(256) void radix_digit_scan_kernel(uint32_t* __restrict__ tile_hist, uint32_t ntiles,
+                                                               uint32_t* __restrict__ digit_tot) {
+  __shared__ uint32_t sh[256 / 64 + 1];
+  uint32_t* v = tile_hist + (uint64_t)blockIdx.x * ntiles;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < ntiles; base += 256 * 4) {
+    uint32_t c[4], s = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) {
+      uint32_t t = base + threadIdx.x * 4 + i;
+      c[i] = t < ntiles ? v[t] : 0u;
+      s += c[i];
+    }
+    uint32_t tot;
+    uint32_t run = carry + block_exclusive_scan<uint32_t, 256>(s, sh, &tot);
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) {
+      uint32_t t = base + threadIdx.x * 4 + i;
+      if (t < ntiles) v[t] = run;
+      run += c[i];
+    }
+    carry += tot;
   }
-  uint32_t run = part[threadIdx.x] - s;
-  for (uint64_t i = b; i < e; ++i) {
-    uint32_t x = v[i];
-    v[i] = run;
-    run += x;
-  }
+  if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
 __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(const uint64_t* __restrict__ in,
                                                                       uint64_t* __restrict__ out, uint64_t n,
                                                                       int shift, uint32_t ntiles,
-                                                                      const uint32_t* __restrict__ tile_off) {
+                                                                      const uint32_t* __restrict__ tile_off,
+                                                                      const uint32_t* __restrict__ digit_tot) {
   __shared__ uint32_t wc[kRadixWaves][256];
   __shared__ uint32_t gbase[256];
+  __shared__ uint32_t sh[kRadixThreads / 64 + 1];
   const uint32_t w = threadIdx.x >> 6;
   for (uint32_t i = threadIdx.x; i < kRadixWaves * 256; i += kRadixThreads) (&wc[0][0])[i] = 0;
   __syncthreads();
@@ -104,14 +111,16 @@ __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(const uint
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  if (threadIdx.x < 256) {
+  uint32_t dtot;
+  uint32_t dbase = block_exclusive_scan<uint32_t, kRadixThreads>(digit_tot[threadIdx.x], sh, &dtot);
+  {
     uint32_t d = threadIdx.x, run = 0;
     for (int ww = 0; ww < kRadixWaves; ++ww) {
       uint32_t c = wc[ww][d];
       wc[ww][d] = run;
       run += c;
     }
-    gbase[d] = tile_off[(uint64_t)d * ntiles + blockIdx.x];
+    gbase[d] = dbase + tile_off[(uint64_t)d * ntiles + blockIdx.x];
   }
   __syncthreads();
 #pragma unroll
@@ -126,7 +135,7 @@ __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(const uint
 
 size_t radix_u64_scratch_bytes(uint64_t n) {
   uint64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
-  return (size_t)(ntiles * 256 * sizeof(uint32_t));
+  return (size_t)((ntiles + 1) * 256 * sizeof(uint32_t));
 }
 
 // Sort bytes lo_byte..hi_byte (inclusive) of keys; *sorted = buffer with the result.
@@ -136,12 +145,13 @@ hipError_t launch_radix_sort_u64(uint64_t* keys, uint64_t* tmp, uint64_t n, int 
   if (n <= 1) return hipSuccess;
   uint32_t ntiles = (uint32_t)((n + kRadixTile - 1) / kRadixTile);
   uint32_t* th = static_cast<uint32_t*>(scratch);
+  uint32_t* dtot = th + (uint64_t)ntiles * 256;
   uint64_t *a = keys, *b = tmp;
   for (int byte = lo_byte; byte <= hi_byte; ++byte) {
     int shift = 8 * byte;
     radix_hist_kernel<<<ntiles, kRadixThreads, 0, st>>>(a, n, shift, ntiles, th);
-    scan_u32_kernel<<<1, 1024, 0, st>>>(th, (uint64_t)ntiles * 256);
-    radix_scatter_kernel<<<ntiles, kRadixThreads, 0, st>>>(a, b, n, shift, ntiles, th);
+    radix_digit_scan_kernel<<<256, 256, 0, st>>>(th, ntiles, dtot);
+    radix_scatter_kernel<<<ntiles, kRadixThreads, 0, st>>>(a, b, n, shift, ntiles, th, dtot);
     uint64_t* t = a;
     a = b;
     b = t;
@@ -314,39 +324,50 @@ hipError_t launch_sample_hist(const ModelHeader* hdr, const Leaf* leaves, const 
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(1024) void capacity_kernel(const uint32_t* __restrict__ hist, uint64_t S, uint64_t n,
-                                                        uint32_t B, double scale, uint32_t* __restrict__ caps,
-                                                        uint32_t* __restrict__ rstart, uint32_t* __restrict__ counts,
-                                                        PartHeader* __restrict__ ph, uint64_t cap_slots) {
-  __shared__ uint32_t part[1024];
-  uint32_t per = (B + 1023) / 1024;
-  uint32_t b = threadIdx.x * per, e = b + per < B ? b + per : B;
-  double ideal = (double)n / (double)B;
-  uint32_t s = 0;
-  for (uint32_t j = b; j < e; ++j) {
-    double expect = (double)hist[j] * (double)n / (double)S;
-    double m = expect > ideal ? expect : ideal;
-    uint32_t c = (uint32_t)ceil(scale * m) + 16u;
-    c = (c + 1u) & ~1u;
-    caps[j] = c;
-    counts[j] = 0;
-    s += c;
-  }
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t x = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += x;
-    __syncthreads();
-  }
-  uint32_t run = part[threadIdx.x] - s;
-  const bool over = part[1023] > cap_slots;  // cannot happen by construction; then everything spills
-  for (uint32_t j = b; j < e; ++j) {
-    uint32_t c = over ? 0u : caps[j];
-    rstart[j] = over ? 0u : run;
-    caps[j] = c;
-    run += c;
+// One block; rounds of 1024 x 8 buckets, each thread 8 consecutive buckets
+// (coalesced loads, no dependent chains).
+constexpr uint32_t kScanThreads = 1024;
+constexpr uint32_t kScanPer = 8;
+
+__global__ __launch_bounds__(kScanThreads) void capacity_kernel(const uint32_t* __restrict__ hist, uint64_t S,
+                                                                uint64_t n, uint32_t B, double scale,
+                                                                uint32_t* __restrict__ caps,
+                                                                uint32_t* __restrict__ rstart,
+                                                                uint32_t* __restrict__ counts,
+                                                                PartHeader* __restrict__ ph, uint64_t cap_slots) {
+  __shared__ uint64_t sh[kScanThreads / 64 + 1];
+  const double ideal = (double)n / (double)B;
+  uint64_t carry = 0;
+  for (uint32_t base = 0; base < B; base += kScanThreads * kScanPer) {
+    uint32_t c[kScanPer];
+    uint64_t s = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kScanPer; ++i) {
+      uint32_t j = base + threadIdx.x * kScanPer + i;
+      c[i] = 0;
+      if (j < B) {
+        double expect = (double)hist[j] * (double)n / (double)S;
+        double m = expect > ideal ? expect : ideal;
+        c[i] = ((uint32_t)ceil(scale * m) + 16u + 1u) & ~1u;
+      }
+      s += c[i];
+    }
+    uint64_t tot;
+    uint64_t run = carry + block_exclusive_scan<uint64_t, kScanThreads>(s, sh, &tot);
+#pragma unroll
+    for (uint32_t i = 0; i < kScanPer; ++i) {
+      uint32_t j = base + threadIdx.x * kScanPer + i;
+      if (j < B) {
+        // regions past the reserved slot count cannot happen by construction; such a
+        // bucket gets no region and its records all spill
+        bool fits = run + c[i] <= cap_slots;
+        caps[j] = fits ? c[i] : 0u;
+        rstart[j] = fits ? (uint32_t)run : 0u;
+        counts[j] = 0;
+      }
+      run += c[i];
+    }
+    carry += tot;
   }
   if (threadIdx.x == 0) {
     ph->n = n;
@@ -356,12 +377,14 @@ __global__ __launch_bounds__(1024) void capacity_kernel(const uint32_t* __restri
     ph->n_mid = 0;
     ph->n_big = 0;
     ph->max_count = 0;
+    ph->mid_records = 0;
+    ph->big_records = 0;
   }
 }
 
 hipError_t launch_capacities(const uint32_t* hist, uint64_t S, uint64_t n, uint32_t B, uint32_t region_pct,
                              uint8_t* part, const PartLayout& lay, hipStream_t st) {
-  capacity_kernel<<<1, 1024, 0, st>>>(hist, S, n, B, region_pct / 100.0, reinterpret_cast<uint32_t*>(part + lay.caps),
+  capacity_kernel<<<1, kScanThreads, 0, st>>>(hist, S, n, B, region_pct / 100.0, reinterpret_cast<uint32_t*>(part + lay.caps),
                                       reinterpret_cast<uint32_t*>(part + lay.rstart),
                                       reinterpret_cast<uint32_t*>(part + lay.counts),
                                       reinterpret_cast<PartHeader*>(part + lay.header), lay.cap_slots);

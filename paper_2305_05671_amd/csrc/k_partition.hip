@@ -5,7 +5,7 @@
 // Each block stages a tile of records in LDS with coalesced 16-byte loads,
 // computes every record's base-95 code and RMI bucket, reserves a slot in the
 // bucket's region with one atomic, and writes the record plus its input index
-// (a 104-byte slot) with dword stores that are contiguous across lanes.  A
+// as one whole 128-byte slot (eight lanes, one 16-byte store each).  A
 // bucket that outgrows its region continues in a shared spill area; the
 // spill entry remembers (bucket, rank within the bucket's overflow) so the
 // fix-up can group the spill without sorting it.
@@ -16,36 +16,131 @@ namespace elsar {
 constexpr int kPartThreads = 256;
 constexpr int kPartTile = 256;  // records per tile (one per thread for the model step)
 
+// Chunk c (16 bytes) of the slot of tile record k: the index, the record
+// dwords, then zeros.
+__device__ __forceinline__ uint4 slot_chunk(const uint32_t* tile, uint32_t RW, uint32_t k, uint32_t c, uint32_t idx) {
+  uint32_t v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    uint32_t d = 4 * c + i;  // slot dword
+    v[i] = d == 0 ? idx : (d <= RW ? tile[k * RW + d - 1] : 0u);
+  }
+  return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
+// Tile t of records held in registers as RV <= 8 named 16-byte vectors per
+// thread plus one dword of tail (named members, not an array, so the compiler
+// never demotes them to scratch memory).
+struct TileRegs {
+  u32x4 v0, v1, v2, v3, v4, v5, v6, v7;
+  uint32_t tail;
+};
+#define ELSAR_FOR8(M) M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7)
+
+template <uint32_t RV>
+__device__ __forceinline__ void load_tile_regs(const uint32_t* __restrict__ rec_dw, uint64_t t, uint32_t cnt,
+                                               uint32_t RW, TileRegs& R) {
+  static_assert(RV <= 8, "at most 8 vectors per thread");
+  const uint32_t ndw = cnt * RW, nvec = ndw >> 2;  // nvec >= 1
+  const uint32_t* base = rec_dw + t * kPartTile * RW;
+  const u32x4* src4 = reinterpret_cast<const u32x4*>(base);  // 16-byte aligned
+  // unconditional loads (index clamped to the last vector): no branches
+#define ELSAR_LD(I)                                              \
+  if constexpr (I < RV) {                                        \
+    uint32_t v = threadIdx.x + (I) * kPartThreads;               \
+    R.v##I = src4[v < nvec ? v : nvec - 1];                      \
+  }
+  ELSAR_FOR8(ELSAR_LD)
+#undef ELSAR_LD
+  uint32_t d = (nvec << 2) + threadIdx.x;
+  R.tail = d < ndw ? base[d] : 0u;
+}
+
+template <uint32_t RV>
+__device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const TileRegs& R, uint32_t* b) {
+  const uint32_t ndw = cnt * RW, nvec = ndw >> 2;
+  u32x4* b4 = reinterpret_cast<u32x4*>(b);
+  // a clamped index rewrites the last vector with the value its owner writes too
+#define ELSAR_ST(I)                                              \
+  if constexpr (I < RV) {                                        \
+    uint32_t v = threadIdx.x + (I) * kPartThreads;               \
+    b4[v < nvec ? v : nvec - 1] = R.v##I;                        \
+  }
+  ELSAR_FOR8(ELSAR_ST)
+#undef ELSAR_ST
+  uint32_t d = (nvec << 2) + threadIdx.x;
+  if (d < ndw) b[d] = R.tail;
+}
+
+// Software pipeline per block over its tiles t = blockIdx.x, + gridDim.x, ...:
+// the loads of tile t+1 are in flight while the atomics of tile t reserve
+// slots and the slots of tile t-1 are written, so neither the load latency nor
+// the atomic latency stalls the block.  Two LDS tile buffers alternate.
 template <int RW_T>
 __global__ __launch_bounds__(kPartThreads) void partition_kernel(
     const ModelHeader* __restrict__ hdr, const Leaf* __restrict__ leaves, const uint8_t* __restrict__ recs,
     uint64_t n, uint32_t rw_rt, uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps,
     const uint32_t* __restrict__ rstart, PartHeader* __restrict__ ph, uint2* __restrict__ spill_meta,
-    uint32_t* __restrict__ slots, uint64_t cap_slots) {
+    uint4* __restrict__ slots, uint64_t cap_slots) {
   const uint32_t RW = RW_T ? (uint32_t)RW_T : rw_rt;  // record dwords
-  const uint32_t W = RW + 1;                           // slot dwords
-  extern __shared__ uint4 tile4[];                     // kPartTile * RW dwords
-  __shared__ uint32_t dst[kPartTile];
-  uint32_t* tile = reinterpret_cast<uint32_t*>(tile4);
+  const uint32_t SC = slot_bytes_for(RW * 4) / 16;     // 16-byte chunks per slot
+  constexpr uint32_t RV = RW_T ? (kPartTile * RW_T / 4 + kPartThreads - 1) / kPartThreads : 8;
+  extern __shared__ uint4 lds4[];                      // 2 tiles of kPartTile * RW dwords
+  __shared__ uint32_t dst[2][kPartTile];
+  const uint32_t tile_dw = kPartTile * RW;
   const float a0 = hdr->a0, a1 = hdr->a1;
   const uint32_t L = hdr->L;
   const uint64_t ntiles = (n + kPartTile - 1) / kPartTile;
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const uint64_t r0 = t * kPartTile;
-    const uint32_t cnt = (uint32_t)(n - r0 < (uint64_t)kPartTile ? n - r0 : (uint64_t)kPartTile);
-    const uint32_t ndw = cnt * RW;
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(recs) + r0 * RW;  // 16-byte aligned
-    const uint32_t nvec = ndw >> 2;
-    const uint4* src4 = reinterpret_cast<const uint4*>(src);
-    for (uint32_t v = threadIdx.x; v < nvec; v += kPartThreads) tile4[v] = src4[v];
-    for (uint32_t d = (nvec << 2) + threadIdx.x; d < ndw; d += kPartThreads) tile[d] = src[d];
-    __syncthreads();
+  const uint32_t* rec_dw = reinterpret_cast<const uint32_t*>(recs);
+  auto tile_count = [&](uint64_t t) {
+    uint64_t r0 = t * kPartTile;
+    return (uint32_t)(n - r0 < (uint64_t)kPartTile ? n - r0 : (uint64_t)kPartTile);
+  };
+  auto buf = [&](uint32_t i) { return reinterpret_cast<uint32_t*>(lds4) + i * tile_dw; };
+  // SC consecutive lanes write one slot as whole 16-byte chunks (whole lines)
+  auto write_tile = [&](uint64_t t, const uint32_t* b, const uint32_t* dslot) {
+    const uint32_t total = tile_count(t) * SC;
+    const uint32_t r0 = (uint32_t)(t * kPartTile);
+    for (uint32_t f = threadIdx.x; f < total; f += kPartThreads) {
+      uint32_t k = f / SC, c = f - k * SC;
+      slots[(uint64_t)dslot[k] * SC + c] = slot_chunk(b, RW, k, c, r0 + k);
+    }
+  };
+
+  uint64_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  // tile t is copied through registers: RV 16-byte vectors per thread plus a dword tail
+  {
+    TileRegs R;
+    load_tile_regs<RV>(rec_dw, t, tile_count(t), RW, R);
+    store_tile_regs<RV>(tile_count(t), RW, R, buf(0));
+  }
+  __syncthreads();
+  uint32_t cur = 0;
+  bool have_prev = false;
+  uint64_t tprev = 0;
+  for (;;) {
+    const uint64_t tn = t + gridDim.x;
+    const bool have_next = tn < ntiles;
+    // 1. loads of the next tile
+    // (the last iteration reloads its own tile instead: no branch around the loads)
+    const uint64_t tl = have_next ? tn : t;
+    TileRegs R;
+    load_tile_regs<RV>(rec_dw, tl, tile_count(tl), RW, R);
+    // 2. bucket of each record of tile t and its slot reservation
+    const uint32_t cnt = tile_count(t);
+    uint32_t b = 0, s = 0;
     if (threadIdx.x < cnt) {
-      const uint32_t* r = tile + threadIdx.x * RW;
+      const uint32_t* r = buf(cur) + threadIdx.x * RW;
       uint64_t e = key_code(r[0], r[1]);
       uint32_t j = rmi_leaf(a0, a1, L, e);
-      uint32_t b = leaf_bucket(load_leaf(leaves, j), e);
-      uint32_t s = atomicAdd(&counts[b], 1u);
+      b = leaf_bucket(load_leaf(leaves, j), e);
+      s = atomicAdd(&counts[b], 1u);
+    }
+    // 3. the previous tile's slots, while the atomics are in flight
+    if (have_prev) write_tile(tprev, buf(cur ^ 1), dst[cur ^ 1]);
+    // 4. this tile's slots
+    if (threadIdx.x < cnt) {
       uint32_t cap = caps[b];
       uint32_t slot;
       if (s < cap) {
@@ -55,17 +150,20 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
         spill_meta[q] = make_uint2(b, s - cap);
         slot = (uint32_t)cap_slots + q;
       }
-      dst[threadIdx.x] = slot;
+      dst[cur][threadIdx.x] = slot;
     }
     __syncthreads();
-    const uint32_t total = cnt * W;
-    for (uint32_t f = threadIdx.x; f < total; f += kPartThreads) {
-      uint32_t k = f / W, d = f - k * W;
-      uint32_t v = d < RW ? tile[k * RW + d] : (uint32_t)(r0 + k);
-      slots[(uint64_t)dst[k] * W + d] = v;
-    }
+    // 5. the next tile into the buffer the previous tile has left (on the last
+    //    iteration a copy of tile t lands there unused; again no branch)
+    store_tile_regs<RV>(tile_count(tl), RW, R, buf(cur ^ 1));
     __syncthreads();
+    have_prev = true;
+    tprev = t;
+    if (!have_next) break;
+    t = tn;
+    cur ^= 1;
   }
+  write_tile(tprev, buf(cur), dst[cur]);
 }
 
 hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const uint8_t* recs, uint64_t n,
@@ -73,15 +171,15 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const ui
                             hipStream_t st) {
   if (n == 0) return hipSuccess;
   const uint32_t RW = rec_bytes / 4;
-  const size_t lds = (size_t)kPartTile * RW * 4;
+  const size_t lds = 2 * (size_t)kPartTile * RW * 4;
   uint64_t ntiles = (n + kPartTile - 1) / kPartTile;
-  uint32_t grid = (uint32_t)(ntiles < 8192 ? ntiles : 8192);
+  uint32_t grid = (uint32_t)(ntiles < 2048 ? ntiles : 2048);
   auto* counts = reinterpret_cast<uint32_t*>(part + lay.counts);
   auto* caps = reinterpret_cast<const uint32_t*>(part + lay.caps);
   auto* rstart = reinterpret_cast<const uint32_t*>(part + lay.rstart);
   auto* ph = reinterpret_cast<PartHeader*>(part + lay.header);
   auto* meta = reinterpret_cast<uint2*>(part + lay.spill_meta);
-  auto* slots = reinterpret_cast<uint32_t*>(part + lay.slots);
+  auto* slots = reinterpret_cast<uint4*>(part + lay.slots);
   if (RW == 25)
     partition_kernel<25><<<grid, kPartThreads, lds, st>>>(hdr, leaves, recs, n, RW, counts, caps, rstart, ph, meta,
                                                           slots, lay.cap_slots);
@@ -93,62 +191,73 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const ui
 
 // offsets[j] = sum_{k<j} counts[k] (u64), offsets[B] = n; spill_off[j] = sum_{k<j}
 // max(counts[k] - caps[k], 0); buckets above the small LDS cap go to lists.
-__global__ __launch_bounds__(1024) void scan_counts_kernel(const uint32_t* __restrict__ counts,
-                                                           const uint32_t* __restrict__ caps, uint32_t B,
-                                                           uint64_t* __restrict__ offsets,
-                                                           uint32_t* __restrict__ spill_off,
-                                                           uint32_t* __restrict__ mid_list,
-                                                           uint32_t* __restrict__ big_list,
-                                                           PartHeader* __restrict__ ph) {
-  __shared__ uint64_t pc[1024];
-  __shared__ uint32_t ps[1024];
-  __shared__ uint32_t mx[1024];
-  uint32_t per = (B + 1023) / 1024;
-  uint32_t b = threadIdx.x * per, e = b + per < B ? b + per : B;
-  uint64_t sc = 0;
-  uint32_t ss = 0, m = 0;
-  for (uint32_t j = b; j < e; ++j) {
-    uint32_t c = counts[j], cap = caps[j];
-    sc += c;
-    ss += c > cap ? c - cap : 0u;
-    m = c > m ? c : m;
-    if (c > kSmallCap) {
-      if (c <= kMidCap) mid_list[atomicAdd(&ph->n_mid, 1u)] = j;
-      else big_list[atomicAdd(&ph->n_big, 1u)] = j;
+constexpr uint32_t kScanThreads = 1024;
+constexpr uint32_t kScanPer = 8;
+
+__global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_t* __restrict__ counts,
+                                                                   const uint32_t* __restrict__ caps, uint32_t B,
+                                                                   uint64_t* __restrict__ offsets,
+                                                                   uint32_t* __restrict__ spill_off,
+                                                                   uint32_t* __restrict__ mid_list,
+                                                                   uint32_t* __restrict__ big_list,
+                                                                   PartHeader* __restrict__ ph) {
+  __shared__ uint64_t shc[kScanThreads / 64 + 1];
+  __shared__ uint32_t shs[kScanThreads / 64 + 1];
+  uint64_t carry_c = 0;
+  uint32_t carry_s = 0, m = 0, mr = 0, br = 0;
+  for (uint32_t base = 0; base < B; base += kScanThreads * kScanPer) {
+    uint32_t c[kScanPer], sp[kScanPer];
+    uint64_t sc = 0;
+    uint32_t ss = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kScanPer; ++i) {
+      uint32_t j = base + threadIdx.x * kScanPer + i;
+      c[i] = 0;
+      sp[i] = 0;
+      if (j < B) {
+        uint32_t cap = caps[j];
+        c[i] = counts[j];
+        sp[i] = c[i] > cap ? c[i] - cap : 0u;
+        m = c[i] > m ? c[i] : m;
+        if (c[i] > kSmallCap) {
+          if (c[i] <= kMidCap) {
+            mid_list[atomicAdd(&ph->n_mid, 1u)] = j;
+            mr += c[i];
+          } else {
+            big_list[atomicAdd(&ph->n_big, 1u)] = j;
+            br += c[i];
+          }
+        }
+      }
+      sc += c[i];
+      ss += sp[i];
     }
+    uint64_t tc;
+    uint32_t ts;
+    uint64_t rc = carry_c + block_exclusive_scan<uint64_t, kScanThreads>(sc, shc, &tc);
+    uint32_t rs = carry_s + block_exclusive_scan<uint32_t, kScanThreads>(ss, shs, &ts);
+#pragma unroll
+    for (uint32_t i = 0; i < kScanPer; ++i) {
+      uint32_t j = base + threadIdx.x * kScanPer + i;
+      if (j < B) {
+        offsets[j] = rc;
+        spill_off[j] = rs;
+      }
+      rc += c[i];
+      rs += sp[i];
+    }
+    carry_c += tc;
+    carry_s += ts;
   }
-  pc[threadIdx.x] = sc;
-  ps[threadIdx.x] = ss;
-  mx[threadIdx.x] = m;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint64_t x = threadIdx.x >= (unsigned)off ? pc[threadIdx.x - off] : 0ull;
-    uint32_t y = threadIdx.x >= (unsigned)off ? ps[threadIdx.x - off] : 0u;
-    uint32_t z = threadIdx.x >= (unsigned)off ? mx[threadIdx.x - off] : 0u;
-    __syncthreads();
-    pc[threadIdx.x] += x;
-    ps[threadIdx.x] += y;
-    mx[threadIdx.x] = z > mx[threadIdx.x] ? z : mx[threadIdx.x];
-    __syncthreads();
-  }
-  uint64_t rc = pc[threadIdx.x] - sc;
-  uint32_t rs = ps[threadIdx.x] - ss;
-  for (uint32_t j = b; j < e; ++j) {
-    uint32_t c = counts[j], cap = caps[j];
-    offsets[j] = rc;
-    spill_off[j] = rs;
-    rc += c;
-    rs += c > cap ? c - cap : 0u;
-  }
-  if (threadIdx.x == 1023) {
-    offsets[B] = pc[1023];
-    ph->max_count = mx[1023];
-  }
+  if (mr) atomicAdd(&ph->mid_records, mr);
+  if (br) atomicAdd(&ph->big_records, br);
+  if (m) atomicMax(&ph->max_count, m);
+  if (threadIdx.x == 0) offsets[B] = carry_c;
 }
 
 hipError_t launch_scan_counts(uint8_t* part, const PartLayout& lay, uint32_t B, uint64_t* offsets,
                               hipStream_t st) {
-  scan_counts_kernel<<<1, 1024, 0, st>>>(
+  scan_counts_kernel<<<1, kScanThreads, 0, st>>>(
       reinterpret_cast<const uint32_t*>(part + lay.counts), reinterpret_cast<const uint32_t*>(part + lay.caps), B,
       offsets, reinterpret_cast<uint32_t*>(part + lay.spill_off), reinterpret_cast<uint32_t*>(part + lay.mid_list),
       reinterpret_cast<uint32_t*>(part + lay.big_list), reinterpret_cast<PartHeader*>(part + lay.header));

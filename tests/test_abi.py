@@ -73,5 +73,14 @@ def test_workspace_grows_linearly(elsar):
         sz = ctypes.c_size_t()
         assert lib.elsar_sort_workspace_size(ctypes.byref(p), n, ctypes.byref(sz)) == elsar.OK
         out.append(sz.value / n)
-    # regions (<= 2.5n slots) + spill (n slots) of 104 bytes, plus small arrays
-    assert all(350 < b < 450 for b in out), out
+    # regions (<= 2.5n slots) + spill (n slots) of 128 bytes, plus small arrays
+    assert all(420 < b < 520 for b in out), out
+
+
+def test_record_size_limits(elsar):
+    lib = elsar.lib()
+    sz = ctypes.c_size_t()
+    for R, ok in [(40, True), (100, True), (128, True), (132, False), (36, False), (102, False)]:
+        p = elsar.fit_params(record_bytes=R, key_bytes=10)
+        rc = lib.elsar_sort_workspace_size(ctypes.byref(p), 1000, ctypes.byref(sz))
+        assert (rc == elsar.OK) == ok, (R, rc)

@@ -171,3 +171,15 @@ def test_partition_then_sort_buckets(env):
     off = offsets.cpu().numpy()
     for j in [0, 1, 777, 2047]:
         _assert_same(got[off[j]:off[j + 1]], want[off[j]:off[j + 1]])
+
+
+@pytest.mark.parametrize("R,K", [(40, 8), (64, 12), (128, 10)])
+def test_other_record_shapes(env, R, K):
+    torch, elsar = env
+    rng = np.random.default_rng(R)
+    recs = rng.integers(0x20, 0x7F, size=(30_000, R), dtype=np.uint8)
+    recs[1::2, :K] = recs[0::2, :K]  # every key twice: ties broken by input index
+    d = torch.from_numpy(recs.reshape(-1)).to("cuda")
+    out = elsar.elsar_sort(d, params=elsar.fit_params(record_bytes=R, key_bytes=K, num_buckets=64))
+    torch.cuda.synchronize()
+    _assert_same(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs, key_bytes=K))
