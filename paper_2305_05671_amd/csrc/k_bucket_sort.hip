@@ -11,13 +11,12 @@
 // across the whole bucket needs no pass (an all-equal-key bucket only sorts
 // its index bytes -- early termination on duplicates).
 //
-//  * bucket_sort_reg: buckets of up to 2048 records, one 1024-thread block
-//    each.  Every slot is read exactly once, as whole lines, into registers.
-//    The block first sorts on the 4 composite bytes after the bucket's common
-//    prefix; adjacent entries that tie on them are then ordered by the rest of
-//    the composite (insertion sort per short run, or a full LSD sort if a run
-//    is long).  The records leave through an LDS staging buffer in sorted
-//    order with stores contiguous across lanes.
+//  * bucket_sort_small: buckets of up to 2048 records, one 512-thread block
+//    each.  The first 16 bytes of every slot (index and key) go to LDS; one
+//    counting pass on the key's base-95 code scaled over the bucket's code
+//    range into 2048 bins, then an insertion sort by the whole composite
+//    inside each bin (a full LSD sort if a bin is long), orders them.  The records are then gathered in
+//    sorted order, each slot read once, straight into the output.
 //  * bucket_sort_lds: buckets of up to 6144 records (all varying composite
 //    bytes, entries and permutation in LDS, records gathered from the slots).
 //  * bucket_sort_global: larger buckets, one block each; the ping-pong entry
@@ -85,20 +84,31 @@ __device__ uint4 block_diff(uint4 o, uint4 a, uint4* sh_or, uint4* sh_and) {
   return make_uint4(O.x ^ A.x, O.y ^ A.y, O.z ^ A.z, O.w ^ A.w);
 }
 
+// Block-wide min and max of one u64 per thread; every thread gets both.
+template <uint32_t THREADS>
+__device__ void block_min_max_u64(uint64_t& mn, uint64_t& mx, uint64_t* sh) {
+  for (int off = 32; off > 0; off >>= 1) {
+    uint64_t a = shfl_xor_u64(mn, off), b = shfl_xor_u64(mx, off);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  const uint32_t w = threadIdx.x >> 6;
+  if (lane_id() == 0) { sh[2 * w] = mn; sh[2 * w + 1] = mx; }
+  __syncthreads();
+  mn = sh[0];
+  mx = sh[1];
+  for (uint32_t i = 1; i < THREADS / 64; ++i) {
+    mn = sh[2 * i] < mn ? sh[2 * i] : mn;
+    mx = sh[2 * i + 1] > mx ? sh[2 * i + 1] : mx;
+  }
+  __syncthreads();
+}
+
 // Bit p set when composite byte p (0..15) varies.
 __device__ __forceinline__ uint32_t vary_mask(const uint4& d) {
   uint32_t vary = 0;
   for (uint32_t p = 0; p < 16; ++p) vary |= (uint32_t)(digit_of(d, p) != 0) << p;
   return vary;
-}
-
-// First varying bit of the composite (0 = most significant); 128 if none.
-__device__ __forceinline__ uint32_t first_bit(const uint4& d) {
-  if (d.x) return __builtin_clz(d.x);
-  if (d.y) return 32 + __builtin_clz(d.y);
-  if (d.z) return 64 + __builtin_clz(d.z);
-  if (d.w) return 96 + __builtin_clz(d.w);
-  return 128;
 }
 
 template <uint32_t THREADS>
@@ -177,17 +187,9 @@ __device__ void lsd_pass(uint16_t (*perm)[CAP], uint32_t cur, uint32_t n, uint32
 constexpr uint32_t kSmThreads = 512;
 constexpr uint32_t kSmWaves = kSmThreads / 64;
 constexpr uint32_t kSmCap = kSmallCap;
-constexpr uint32_t kSmBits = 11;     // counting-sort digit: 2048 bins
-constexpr uint32_t kSmStage = 128;   // records per output batch
+constexpr uint32_t kSmBits = 11;     // counting-sort digit: 2048 bins of the bucket's code range
+constexpr uint32_t kSmGroup = 7;     // gathered chunks in flight per thread
 constexpr uint32_t kRunMax = 32;     // longest bin sorted by insertion
-
-// D bits of a 128-bit big-endian composite starting at bit cb (0 = most significant).
-__device__ __forceinline__ uint32_t bits_at(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t cb,
-                                            uint32_t D) {
-  uint64_t hi = ((uint64_t)c0 << 32) | c1, lo = ((uint64_t)c2 << 32) | c3;
-  uint64_t top = cb == 0 ? hi : (cb < 64 ? (hi << cb) | (lo >> (64 - cb)) : lo << (cb - 64));
-  return (uint32_t)(top >> (64 - D));
-}
 
 template <uint32_t RW>  // record dwords
 __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
@@ -197,13 +199,12 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
   constexpr uint32_t SC = slot_bytes_for(RW * 4) / 16;  // 16-byte chunks per slot
   constexpr uint32_t LC = (RW + 1 + 3) / 4;             // chunks holding the index or record bytes
   constexpr uint32_t AR = kSmCap / kSmThreads;          // entries per thread
-  constexpr uint32_t CR = (kSmStage * LC + kSmThreads - 1) / kSmThreads;  // chunk loads per thread per batch
   __shared__ uint32_t cw[4][kSmCap];                    // composite words of every entry
   __shared__ uint16_t perm[2][kSmCap];
   __shared__ uint32_t bins[1u << kSmBits];              // also the LSD fallback's per-wave counters
-  __shared__ uint32_t stage[kSmStage * RW];
   __shared__ uint4 sh_or[kSmWaves], sh_and[kSmWaves];
   __shared__ uint32_t sh_scan[kSmThreads / 64 + 1];
+  __shared__ uint64_t sh_mm[2 * kSmWaves];
   __shared__ uint32_t tot[4];
   static_assert((1u << kSmBits) == kSmWaves * 256, "bins double as the LSD counters");
   const uint32_t tid = threadIdx.x;
@@ -227,6 +228,7 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
     if (p < n) v[i] = slots[(uint64_t)slot_of(br, p, spill_map, cap_slots) * SC];
   }
   uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
+  uint64_t cmin = ~0ull, cmax = 0;  // base-95 codes of the first 8 key bytes
 #pragma unroll
   for (uint32_t i = 0; i < AR; ++i) {
     uint32_t p = tid + i * kSmThreads;
@@ -235,11 +237,15 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
       cw[0][p] = c.x; cw[1][p] = c.y; cw[2][p] = c.z; cw[3][p] = c.w;
       o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
       a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+      uint64_t e = key_code(v[i].y, v[i].z);
+      cmin = e < cmin ? e : cmin;
+      cmax = e > cmax ? e : cmax;
     }
   }
   // bits that vary across the bucket (syncs; the entries are visible afterwards)
   const uint4 diff = block_diff<kSmThreads>(o, a, sh_or, sh_and);
   const uint32_t vary = vary_mask(diff);
+  block_min_max_u64<kSmThreads>(cmin, cmax, sh_mm);
   auto less = [&](uint32_t x, uint32_t y) -> bool {
     if (cw[0][x] != cw[0][y]) return cw[0][x] < cw[0][y];
     if (cw[1][x] != cw[1][y]) return cw[1][x] < cw[1][y];
@@ -250,16 +256,27 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
   if (n == 1) {
     if (tid == 0) perm[0][0] = 0;
   } else {
-    // 2. one counting pass on the kSmBits bits after the bucket's common bit
-    //    prefix (the bits before are equal across the bucket, so the digit is
-    //    a non-decreasing function of the composite)
-    const uint32_t cb = first_bit(diff);
+    // 2. one counting pass on a digit of the key's base-95 code scaled over the
+    //    bucket's code range: (code - min) * 2^kSmBits / (max - min + 1).  It is
+    //    a non-decreasing function of the key, and near uniform over an
+    //    equi-depth bucket.  Entries with equal digits are then ordered by the
+    //    whole composite.
+    const double scale = (double)(1u << kSmBits) / ((double)(cmax - cmin) + 1.0);
+    uint16_t* dig = perm[1];  // the digits, until a fallback needs the buffer
     for (uint32_t i = tid; i < (1u << kSmBits); i += kSmThreads) bins[i] = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < AR; ++i) {
+      uint32_t p = tid + i * kSmThreads;
+      if (p < n) {
+        uint64_t e = key_code(v[i].y, v[i].z);
+        uint32_t d = (uint32_t)((double)(e - cmin) * scale);
+        dig[p] = (uint16_t)(d < (1u << kSmBits) ? d : (1u << kSmBits) - 1);
+      }
+    }
     __syncthreads();
-    auto digit = [&](uint32_t e) { return bits_at(cw[0][e], cw[1][e], cw[2][e], cw[3][e], cb, kSmBits); };
-    for (uint32_t p = tid; p < n; p += kSmThreads) atomicAdd(&bins[digit(p)], 1u);
+    for (uint32_t p = tid; p < n; p += kSmThreads) atomicAdd(&bins[dig[p]], 1u);
     __syncthreads();
-    {  // exclusive scan of the bins: 4 contiguous per thread
+    {  // exclusive scan of the bins: PER contiguous per thread
       constexpr uint32_t PER = (1u << kSmBits) / kSmThreads;
       uint32_t c[PER], sum = 0;
 #pragma unroll
@@ -270,7 +287,7 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
       for (uint32_t i = 0; i < PER; ++i) { bins[tid * PER + i] = run; run += c[i]; }
     }
     __syncthreads();
-    for (uint32_t p = tid; p < n; p += kSmThreads) perm[0][atomicAdd(&bins[digit(p)], 1u)] = (uint16_t)p;
+    for (uint32_t p = tid; p < n; p += kSmThreads) perm[0][atomicAdd(&bins[dig[p]], 1u)] = (uint16_t)p;
     __syncthreads();
     // bins[b] is now the end of bin b; the start is the end of bin b-1
     bool long_bin = false;
@@ -301,36 +318,34 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
     }
   }
   __syncthreads();
-  // 3. gather the records in sorted order, kSmStage at a time, through LDS
+  // 3. gather the records in sorted order straight into the output: lane q
+  //    moves 16-byte chunk q % LC of the record at sorted position q / LC, so
+  //    the lanes of a wave cover a contiguous stretch of the output.  Loads go
+  //    out kSmGroup per thread before any store waits on them.
   uint32_t* o_dw = out + br.out0 * RW;
-  for (uint32_t k0 = 0; k0 < n; k0 += kSmStage) {
-    const uint32_t kb = n - k0 < kSmStage ? n - k0 : kSmStage;
-    const uint32_t nq = kb * LC;
-    uint4 g[CR];
+  const uint32_t nq = n * LC;
+  for (uint32_t q0 = 0; q0 < nq; q0 += kSmGroup * kSmThreads) {
+    u32x4 g[kSmGroup];
 #pragma unroll
-    for (uint32_t i = 0; i < CR; ++i) {
-      uint32_t q = tid + i * kSmThreads;
-      if (q < nq) {
-        uint32_t kk = q / LC, c = q - kk * LC;
-        g[i] = slots[(uint64_t)slot_of(br, perm[cur][k0 + kk], spill_map, cap_slots) * SC + c];
-      }
+    for (uint32_t i = 0; i < kSmGroup; ++i) {
+      uint32_t q = q0 + tid + i * kSmThreads;
+      uint32_t qq = q < nq ? q : nq - 1;  // clamped: no branch around the loads
+      uint32_t k = qq / LC, c = qq - k * LC;
+      g[i] = reinterpret_cast<const u32x4*>(slots)[(uint64_t)slot_of(br, perm[cur][k], spill_map, cap_slots) * SC + c];
     }
 #pragma unroll
-    for (uint32_t i = 0; i < CR; ++i) {
-      uint32_t q = tid + i * kSmThreads;
+    for (uint32_t i = 0; i < kSmGroup; ++i) {
+      uint32_t q = q0 + tid + i * kSmThreads;
       if (q < nq) {
-        uint32_t kk = q / LC, c = q - kk * LC;
-        uint32_t x[4] = {g[i].x, g[i].y, g[i].z, g[i].w};
+        uint32_t k = q / LC, c = q - k * LC;
+        uint32_t* o = o_dw + k * RW;
 #pragma unroll
         for (uint32_t t = 0; t < 4; ++t) {
-          uint32_t sd = 4 * c + t;  // slot dword: 0 index, 1..RW record
-          if (sd >= 1 && sd <= RW) stage[kk * RW + sd - 1] = x[t];
+          uint32_t sd = 4 * c + t;  // slot dword: 0 is the index, 1..RW the record
+          if (sd >= 1 && sd <= RW) o[sd - 1] = g[i][t];
         }
       }
     }
-    __syncthreads();
-    for (uint32_t f = tid; f < kb * RW; f += kSmThreads) o_dw[(uint64_t)k0 * RW + f] = stage[f];
-    __syncthreads();
   }
 }
 
