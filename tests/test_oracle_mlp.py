@@ -1,0 +1,114 @@
+"""Pins for the oracle's monotone MLP (CPU only): central finite differences,
+monotonicity, closed forms of the forward pass and of bfloat16 rounding."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from oracle import mlp
+
+
+def _params(seed=0, scale=1.0):
+    rng = np.random.default_rng(seed)
+    P = {k: rng.normal(0, scale, s) for k, s in mlp.PARAM_SHAPES.items()}
+    for k in mlp.NONNEG:
+        P[k] = np.abs(P[k])
+    return P
+
+
+def test_parameter_count():
+    assert mlp.N_PARAMS == 4801
+    P = _params()
+    assert np.array_equal(mlp.pack(mlp.unpack(mlp.pack(P))), mlp.pack(P))
+
+
+def test_gradients_match_central_differences():
+    rng = np.random.default_rng(1)
+    P = _params(2, 0.5)
+    P["w3"] *= 0.05  # output of order 1, so the loss is too
+    X = rng.uniform(0, 1, (32, 8))
+    t = rng.uniform(0, 1, 32)
+    loss, g = mlp.loss_and_grads(P, X, t)
+    assert loss < 10
+    h = 1e-5
+    for k, s in mlp.PARAM_SHAPES.items():
+        flat = P[k].ravel()
+        for i in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            Pp = {kk: vv.copy() for kk, vv in P.items()}
+            Pm = {kk: vv.copy() for kk, vv in P.items()}
+            Pp[k].ravel()[i] += h
+            Pm[k].ravel()[i] -= h
+            num = (mlp.loss_and_grads(Pp, X, t)[0] - mlp.loss_and_grads(Pm, X, t)[0]) / (2 * h)
+            # central differences: O(h^2) truncation plus ~eps*loss/h round-off
+            assert g[k].ravel()[i] == pytest.approx(num, rel=1e-4, abs=1e-9), (k, i)
+
+
+def test_forward_closed_form():
+    # W2 = 0 and W1 = 0: every unit sees only its bias
+    P = {k: np.zeros(s) for k, s in mlp.PARAM_SHAPES.items()}
+    P["b2"][:] = np.linspace(-2, 2, mlp.H)
+    P["w3"][:] = 0.5
+    P["b3"][0] = 0.25
+    y = mlp.forward(P, np.random.default_rng(0).uniform(0, 1, (5, 8)))["y"]
+    want = 0.5 * (1 / (1 + np.exp(-P["b2"]))).sum() + 0.25
+    assert np.allclose(y, want)
+
+
+def test_monotone_in_the_key():
+    recs = datagen.generate(datagen.spec("skewed", seed=3), 50_000)
+    codes = np.sort(oracle.e8_records(recs))
+    q, w = mlp.knots(codes[::7])
+    X = mlp.features(codes, q, w)
+    assert np.all(np.diff(X, axis=0) >= 0)
+    for seed in range(3):
+        y = mlp.forward(_params(seed), X, bf16_layer2=True)["y"]
+        assert np.all(np.diff(y) >= -1e-12)
+
+
+def test_features_closed_form():
+    codes = np.arange(0, 9000, 1000, dtype=np.uint64)  # 9 sorted codes
+    q, w = mlp.knots(codes)
+    assert list(q) == [0, 1000, 2000, 3000, 4000, 5000, 6000, 7000, 8000]
+    X = mlp.features(np.array([0, 1500, 8000, 9999], np.uint64), q, w)
+    assert np.allclose(X[0], 0) and np.allclose(X[2], 1) and np.allclose(X[3], 1)
+    assert np.allclose(X[1], [1, 0.5, 0, 0, 0, 0, 0, 0])
+
+
+def test_bf16_rounding():
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 2 ** -7, 1.0 + 3 * 2 ** -8, -2.5, 3.1415927])
+    r = mlp.bf16(x)
+    assert r[0] == 1.0 and r[1] == 1.0            # tie rounds to even
+    assert r[2] == 1.0 + 2 ** -7
+    assert r[3] == 1.0 + 2 ** -6                  # tie rounds to even (up)
+    assert r[4] == -2.5 and abs(r[5] - 3.140625) < 1e-12
+
+
+def test_adam_projection_keeps_weights_nonnegative():
+    P = _params(4)
+    m = {k: np.zeros_like(v) for k, v in P.items()}
+    v = {k: np.zeros_like(x) for k, x in P.items()}
+    g = {k: np.ones_like(x) * 10 for k, x in P.items()}
+    mlp.adam_step(P, m, v, g, 1, lr=100.0)
+    for k in mlp.NONNEG:
+        assert P[k].min() >= 0
+
+
+def test_training_reduces_loss_and_leaves_are_monotone():
+    recs = datagen.generate(datagen.spec("skewed", seed=5), 100_000)
+    codes = oracle.sample_codes(recs, seed=1, S=20_000)
+    q, w = mlp.knots(codes)
+    X = mlp.features(codes, q, w)
+    t = np.arange(codes.size) / codes.size
+    rng = np.random.default_rng(7)
+    P = mlp.initial_params(rng.uniform(0, 1, mlp.N_PARAMS))
+    m = {k: np.zeros_like(x) for k, x in P.items()}
+    v = {k: np.zeros_like(x) for k, x in P.items()}
+    l0 = mlp.loss_and_grads(P, X, t)[0]
+    for step in range(1, 301):
+        idx = rng.integers(0, codes.size, 512)
+        _, g = mlp.loss_and_grads(P, X[idx], t[idx])
+        mlp.adam_step(P, m, v, g, step, lr=1e-2)
+    l1 = mlp.loss_and_grads(P, X, t)[0]
+    assert l1 < 0.1 * l0 and l1 < 2e-3
+    lv = mlp.leaves_of_sorted(mlp.forward(P, X)["y"], 256)
+    assert np.all(np.diff(lv) >= 0) and lv.min() >= 0 and lv.max() < 256
