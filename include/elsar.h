@@ -38,6 +38,8 @@ extern "C" {
 #endif
 
 #define ELSAR_MAX_DEVICE_RECORDS 1000000000ull
+#define ELSAR_MLP_PARAMS 4801      /* W1 (64x8), b1 (64), W2 (64x64), b2 (64), w3 (64), b3, row-major */
+#define ELSAR_MLP_GRAD_ROWS 128    /* rows of one MLP training step */
 
 typedef enum {
   ELSAR_OK = 0,
@@ -50,8 +52,8 @@ typedef enum {
 
 typedef enum {
   ELSAR_MODEL_RMI = 0,  /* two-level RMI: linear root, linear-spline leaves */
-  ELSAR_MODEL_MLP = 1,  /* monotone MLP root over the same leaves */
-  ELSAR_MODEL_AUTO = 2  /* MLP if it passes the acceptance test, else RMI */
+  ELSAR_MODEL_MLP = 1,  /* monotone MLP root over the same kind of leaves; RMI if it fails acceptance */
+  ELSAR_MODEL_AUTO = 2  /* MLP if it passes acceptance or has the smaller largest sample bucket, else RMI */
 } elsar_model_kind;
 
 /* Fit parameters.  Zero fields take the defaults noted. */
@@ -63,8 +65,9 @@ typedef struct {
   uint64_t sample_size;   /* S; 0: min(max(ceil(n/100), 1024), 10^7, n) (Section 3.1, Section 6) */
   uint64_t seed;          /* seed of the sampler's Philox4x32-10 draws */
   uint32_t kind;          /* elsar_model_kind */
-  float accept_ratio;     /* MLP accepted if its largest sample bucket <= ratio * ideal; 0: 1.5 */
-  uint32_t mlp_steps;     /* Adam steps of the MLP fit; 0: default */
+  float accept_ratio;     /* MLP accepted if its largest sample bucket <= ratio * ideal, ideal =
+                             max(ceil(S/B), longest run of equal codes in the sample); 0: 1.5 */
+  uint32_t mlp_steps;     /* Adam steps (128 sample rows each) of the MLP fit; 0: 400 */
   uint32_t region_pct;    /* bucket j's region holds ceil(region_pct/100 * max(n*h_j/S, n/B)) + 16
                              records (h_j: sample keys in bucket j), the rest spills; 0: 125 */
 } elsar_fit_params;
@@ -91,6 +94,14 @@ elsar_status elsar_fit_workspace_size(const elsar_model* m, uint64_t n, size_t* 
  * sample mapped to B*rank/S, clamped to the buckets its sample ranks span.
  * d_records: n records on the device.  d_ws: elsar_fit_workspace_size bytes.
  * The model's parameters live on the device; the call is asynchronous.
+ *
+ * kind MLP or AUTO also fits the monotone MLP root (8 quantile-ramp features
+ * of the code -> 64 -> 64 -> 1, sigmoid units, non-negative weights; MSE to
+ * rank/S on the sample; Adam), fixes its leaves on the sorted sample (leaf of
+ * sample s = running maximum of floor(L*y)), fits the same spline leaves over
+ * those ranges, and chooses the root on the device (see elsar_model_kind).
+ * With kind MLP the call then synchronises with `stream` and returns
+ * ELSAR_E_MODEL_REJECTED when the linear root was kept (the model stays valid).
  */
 elsar_status elsar_sample_fit(elsar_model* m, const void* d_records, uint64_t n, void* d_ws, size_t ws_bytes,
                               hipStream_t stream);
@@ -127,7 +138,9 @@ elsar_status elsar_sort_workspace_size(const elsar_fit_params* p, uint64_t n, si
  * The whole method on device-resident records: sample + fit, partition, sort
  * and concatenate.  d_out may equal d_in (in place).  d_ws: at least
  * elsar_sort_workspace_size bytes; it holds the model, the partition buffer and
- * the offsets.  Asynchronous; no host synchronisation inside.
+ * the offsets.  Asynchronous; no host synchronisation inside (the MLP/RMI
+ * choice of kind MLP or AUTO is made on the device; a rejected MLP falls back
+ * to the RMI without an error).
  */
 elsar_status elsar_sort(const void* d_in, uint64_t n, void* d_out, const elsar_fit_params* p, void* d_ws,
                         size_t ws_bytes, hipStream_t stream);
@@ -145,10 +158,29 @@ typedef struct {
 
 elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info);
 
-/* Copies the leaf table to host arrays of num_leaves entries each (any may be
- * NULL).  Synchronises. */
+/* Copies the leaf table of the root in use to host arrays of num_leaves
+ * entries each (any may be NULL).  Synchronises. */
 elsar_status elsar_model_leaves(const elsar_model* m, uint64_t* h_base, float* h_slope, float* h_icpt,
                                 uint32_t* h_lo, uint32_t* h_hi);
+
+/* The MLP root of a model created with kind MLP or AUTO (ELSAR_E_INVALID_ARG
+ * otherwise): h_params[ELSAR_MLP_PARAMS] (FP32 master copy), h_knots[9]
+ * (q_0..q_8), h_bound[num_leaves + 1] (leaf j takes the codes in
+ * [bound[j], bound[j+1])), h_first[num_leaves + 1] (first sample rank of each
+ * leaf; first[L] = S).  Any pointer may be NULL.  Synchronises. */
+elsar_status elsar_model_mlp_get(const elsar_model* m, float* h_params, uint64_t* h_knots, uint64_t* h_bound,
+                                 uint32_t* h_first);
+
+/* Verification entry points of the MLP kernels; host buffers, synchronous,
+ * they allocate and free their own device memory.
+ * elsar_mlp_forward: y of n codes under h_params / h_knots (the evaluation the
+ * partition uses).  elsar_mlp_gradient: MSE loss and its gradient (flat
+ * parameter order) on ELSAR_MLP_GRAD_ROWS rows of codes and targets (one
+ * training step's backward pass). */
+elsar_status elsar_mlp_forward(const float* h_params, const uint64_t* h_knots, const uint64_t* h_codes, uint64_t n,
+                               float* h_y);
+elsar_status elsar_mlp_gradient(const float* h_params, const uint64_t* h_knots, const uint64_t* h_codes,
+                                const float* h_targets, float* h_grad, float* h_loss);
 
 /* Statistics of the last partition in d_part; synchronises. */
 typedef struct {

@@ -69,6 +69,10 @@ def lib():
                                 _f32p, _u32p, _u32p], ctypes.c_int),
             "oracle_rmi_buckets": ([_u8p, ctypes.c_uint64, ctypes.c_uint32, _f32p, ctypes.c_uint32, _u64p, _f32p,
                                     _f32p, _u32p, _u32p, _u32p], None),
+            "oracle_spline_leaves": ([_u64p, ctypes.c_uint64, _u64p, ctypes.c_uint32, ctypes.c_uint32, _u64p,
+                                      _f32p, _f32p, _u32p, _u32p], None),
+            "oracle_routed_buckets": ([_u8p, ctypes.c_uint64, ctypes.c_uint32, _u64p, ctypes.c_uint32, _u64p,
+                                       _f32p, _f32p, _u32p, _u32p, _u32p], None),
             "oracle_counts_offsets": ([_u32p, ctypes.c_uint64, ctypes.c_uint32, _u64p, _u64p], ctypes.c_int),
             "oracle_opt_max_bucket": ([_u64p, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_uint64),
         }
@@ -220,6 +224,33 @@ def fit_rmi(codes: np.ndarray, L: int, B: int) -> RMI:
     if rc != 0:
         raise ValueError("fit_rmi: codes must be sorted and S, L, B > 0")
     return m
+
+
+def spline_leaves(codes: np.ndarray, first: np.ndarray, B: int) -> RMI:
+    """Leaves over given ranges of the sorted sample: leaf j holds samples
+    first[j] .. first[j+1]-1 (len(first) = L + 1, first[L] = S).  The returned
+    RMI's root fields are unused."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint64)
+    first = np.ascontiguousarray(first, dtype=np.uint64)
+    L = first.size - 1
+    if L < 1 or first[-1] != codes.size or np.any(np.diff(first.astype(np.int64)) < 0):
+        raise ValueError("first must be non-decreasing with first[L] = S")
+    m = RMI(L, B)
+    lib().oracle_spline_leaves(_p(codes, _u64p), codes.size, _p(first, _u64p), L, B, _p(m.base, _u64p),
+                               _p(m.c, _f32p), _p(m.b, _f32p), _p(m.lo, _u32p), _p(m.hi, _u32p))
+    return m
+
+
+def routed_buckets(recs: np.ndarray, bound: np.ndarray, leaves: RMI) -> np.ndarray:
+    """Bucket of every record with the leaf found among boundary codes (leaf j
+    takes codes in [bound[j], bound[j+1])) and the leaf's FP32 line."""
+    recs = _records(recs)
+    bound = np.ascontiguousarray(bound, dtype=np.uint64)
+    out = np.empty(recs.shape[0], dtype=np.uint32)
+    lib().oracle_routed_buckets(_p(recs, _u8p), recs.shape[0], recs.shape[1], _p(bound, _u64p), leaves.L,
+                                _p(leaves.base, _u64p), _p(leaves.c, _f32p), _p(leaves.b, _f32p),
+                                _p(leaves.lo, _u32p), _p(leaves.hi, _u32p), _p(out, _u32p))
+    return out
 
 
 def counts_offsets(buckets: np.ndarray, B: int):

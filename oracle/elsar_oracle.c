@@ -234,6 +234,9 @@ uint32_t oracle_leaf_bucket(uint64_t base, float c, float b, uint32_t lo, uint32
   return (uint32_t)y;
 }
 
+void oracle_spline_leaves(const uint64_t* e, uint64_t S, const uint64_t* first, uint32_t L, uint32_t B,
+                          uint64_t* base, float* c, float* b, uint32_t* lo, uint32_t* hi);
+
 /* Least squares of t on x in FP64 (two-pass, centred).  Returns slope and
  * intercept; the slope is 0 when all x are equal. */
 static void lsq(const double* x, const double* t, uint64_t m, double* slope, double* icpt) {
@@ -284,10 +287,26 @@ int oracle_fit_rmi(const uint64_t* e, uint64_t S, uint32_t L, uint32_t B, float*
     first[j] = s;
   }
   first[L] = S;
+  oracle_spline_leaves(e, S, first, L, B, base, c, b, lo, hi);
+  free(first);
+  free(x);
+  free(t);
+  return 0;
+}
 
+/*
+ * Leaves over given sample ranges: leaf j holds the sorted samples
+ * first[j] .. first[j+1]-1 (first non-decreasing, first[L] = S).  The line
+ * through the leaf's first and last sample, mapped to B*rank/S, clamped to the
+ * buckets those ranks span; an empty leaf is the constant next bucket.  Used
+ * by both roots: the linear root's ranges come from its routing, the MLP
+ * root's from the running maximum of floor(L*y) over the sorted sample.
+ */
+void oracle_spline_leaves(const uint64_t* e, uint64_t S, const uint64_t* first, uint32_t L, uint32_t B,
+                          uint64_t* base, float* c, float* b, uint32_t* lo, uint32_t* hi) {
   for (uint32_t j = 0; j < L; ++j) {
     uint64_t f = first[j], g = first[j + 1];
-    if (f == g) { /* empty leaf: constant at the next non-empty leaf's first bucket */
+    if (f >= g) { /* empty leaf: constant at the next non-empty leaf's first bucket */
       uint32_t v = f < S ? (uint32_t)(((uint64_t)B * f) / S) : B - 1;
       base[j] = 0; c[j] = 0.0f; b[j] = (float)v; lo[j] = v; hi[j] = v;
       continue;
@@ -306,10 +325,23 @@ int oracle_fit_rmi(const uint64_t* e, uint64_t S, uint32_t L, uint32_t B, float*
     uint64_t h = ((uint64_t)B * (g - 1)) / S;
     hi[j] = (uint32_t)(h < B - 1 ? h : B - 1);
   }
-  free(first);
-  free(x);
-  free(t);
-  return 0;
+}
+
+/* Bucket of every record when the leaf is found from boundary codes: leaf j
+ * takes the codes in [bound[j], bound[j+1]), bound[0] = 0, bound[L] beyond
+ * every code (binary search for the last bound <= code). */
+void oracle_routed_buckets(const uint8_t* recs, uint64_t n, uint32_t rec, const uint64_t* bound, uint32_t L,
+                           const uint64_t* base, const float* c, const float* b, const uint32_t* lo,
+                           const uint32_t* hi, uint32_t* out) {
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t e = oracle_e8(recs + i * rec);
+    uint32_t l0 = 0, h0 = L;
+    while (h0 - l0 > 1) {
+      uint32_t mid = (l0 + h0) / 2;
+      if (bound[mid] <= e) l0 = mid; else h0 = mid;
+    }
+    out[i] = oracle_leaf_bucket(base[l0], c[l0], b[l0], lo[l0], hi[l0], e);
+  }
 }
 
 /* Bucket of every record under an RMI. */

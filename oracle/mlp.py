@@ -69,8 +69,10 @@ def forward(P: dict, X: np.ndarray, bf16_layer2: bool = False):
     return {"z1": z1, "h1": h1, "h1q": h1q, "W2q": W2, "z2": z2, "h2": h2, "y": y}
 
 
-def loss_and_grads(P: dict, X: np.ndarray, t: np.ndarray, bf16_layer2: bool = False):
-    """Mean squared error to the targets t and its gradient w.r.t. every parameter."""
+def loss_and_grads(P: dict, X: np.ndarray, t: np.ndarray, bf16_layer2: bool = False, bf16_dz2: bool = False):
+    """Mean squared error to the targets t and its gradient w.r.t. every parameter.
+    ``bf16_dz2`` rounds dL/dz2 to bfloat16 where it enters the two 64x64
+    products of the backward pass (dW2 and dh1), as the GPU's matrix cores take it."""
     f = forward(P, X, bf16_layer2)
     M = X.shape[0]
     r = f["y"] - t
@@ -78,9 +80,10 @@ def loss_and_grads(P: dict, X: np.ndarray, t: np.ndarray, bf16_layer2: bool = Fa
     dy = 2.0 * r / M
     g = {"w3": f["h2"].T @ dy, "b3": np.array([dy.sum()])}
     dz2 = np.outer(dy, P["w3"]) * f["h2"] * (1.0 - f["h2"])
-    g["W2"] = dz2.T @ f["h1q"]
+    dz2q = bf16(dz2) if bf16_dz2 else dz2
+    g["W2"] = dz2q.T @ f["h1q"]
     g["b2"] = dz2.sum(0)
-    dh1 = dz2 @ f["W2q"]
+    dh1 = dz2q @ f["W2q"]
     dz1 = dh1 * f["h1"] * (1.0 - f["h1"])
     g["W1"] = dz1.T @ X
     g["b1"] = dz1.sum(0)
@@ -124,6 +127,12 @@ def unpack(flat: np.ndarray) -> dict:
 
 def pack(P: dict) -> np.ndarray:
     return np.concatenate([np.asarray(P[k], dtype=np.float64).ravel() for k in PARAM_SHAPES])
+
+
+def first_of_leaves(leaves: np.ndarray, L: int) -> np.ndarray:
+    """first[j] = first sample whose leaf is >= j, for non-decreasing per-sample
+    leaves; first[L] = S."""
+    return np.searchsorted(np.asarray(leaves), np.arange(L + 1), side="left").astype(np.uint64)
 
 
 def leaves_of_sorted(y: np.ndarray, L: int) -> np.ndarray:

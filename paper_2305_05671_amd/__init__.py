@@ -21,6 +21,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libelsar.so")
 
 RMI, MLP, AUTO = 0, 1, 2
+MLP_PARAMS = 4801
+MLP_GRAD_ROWS = 128
 OK, E_INVALID_ARG, E_NO_MEMORY, E_HIP, E_UNSUPPORTED, E_MODEL_REJECTED = range(6)
 
 
@@ -113,6 +115,9 @@ def lib():
             "elsar_model_info_get": ([_P, ctypes.POINTER(ModelInfo)], st),
             "elsar_model_leaves": ([_P, _P, _P, _P, _P, _P], st),
             "elsar_partition_stats_get": ([_P, _P, _SZ, ctypes.POINTER(PartitionStats)], st),
+            "elsar_model_mlp_get": ([_P, _P, _P, _P, _P], st),
+            "elsar_mlp_forward": ([_P, _P, _P, _U64, _P], st),
+            "elsar_mlp_gradient": ([_P, _P, _P, _P, _P, _P], st),
             "elsar_set_timing": ([ctypes.c_int], st),
             "elsar_timings_get": ([ctypes.POINTER(Timings)], st),
             "elsar_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -212,9 +217,13 @@ class Model:
         _check("elsar_fit_workspace_size", lib().elsar_fit_workspace_size(self._h, n, ctypes.byref(sz)))
         if workspace is None or workspace.numel() < sz.value:
             workspace = _dev_bytes(sz.value, records.device)
-        _check("elsar_sample_fit", lib().elsar_sample_fit(self._h, records.data_ptr(), n, workspace.data_ptr(),
-                                                          workspace.numel(), _stream(stream)))
+        s = lib().elsar_sample_fit(self._h, records.data_ptr(), n, workspace.data_ptr(), workspace.numel(),
+                                   _stream(stream))
         self._fit_ws = workspace  # keep alive until the stream has used it
+        # kind MLP reports a rejected network (the linear root is kept and usable)
+        self.rejected = s == E_MODEL_REJECTED
+        if not self.rejected:
+            _check("elsar_sample_fit", s)
         return self
 
     def partition_size(self, n: int) -> int:
@@ -258,6 +267,18 @@ class Model:
                                                               b.ctypes.data, lo.ctypes.data, hi.ctypes.data))
         return base, c, b, lo, hi
 
+    def mlp(self):
+        """(params[4801] f32, knots[9] u64, bound[L+1] u64, first[L+1] u32) of the MLP root."""
+        import numpy as np
+        L = self.info().num_leaves
+        params = np.zeros(MLP_PARAMS, np.float32)
+        knots = np.zeros(9, np.uint64)
+        bound = np.zeros(L + 1, np.uint64)
+        first = np.zeros(L + 1, np.uint32)
+        _check("elsar_model_mlp_get", lib().elsar_model_mlp_get(self._h, params.ctypes.data, knots.ctypes.data,
+                                                                bound.ctypes.data, first.ctypes.data))
+        return params, knots, bound, first
+
     def partition_stats(self, part) -> PartitionStats:
         s = PartitionStats()
         _check("elsar_partition_stats_get", lib().elsar_partition_stats_get(self._h, part.data_ptr(), part.numel(),
@@ -273,3 +294,33 @@ def timings() -> Timings:
     t = Timings()
     _check("elsar_timings_get", lib().elsar_timings_get(ctypes.byref(t)))
     return t
+
+
+def mlp_forward(params, knots, codes):
+    """elsar_mlp_forward: y of every code (host arrays in, float32 array out)."""
+    import numpy as np
+    params = np.ascontiguousarray(params, np.float32)
+    knots = np.ascontiguousarray(knots, np.uint64)
+    codes = np.ascontiguousarray(codes, np.uint64)
+    if params.size != MLP_PARAMS or knots.size != 9:
+        raise ValueError("params must hold 4801 values and knots 9")
+    y = np.zeros(codes.size, np.float32)
+    _check("elsar_mlp_forward", lib().elsar_mlp_forward(params.ctypes.data, knots.ctypes.data, codes.ctypes.data,
+                                                        codes.size, y.ctypes.data))
+    return y
+
+
+def mlp_gradient(params, knots, codes, targets):
+    """elsar_mlp_gradient: (loss, gradient[4801]) on MLP_GRAD_ROWS rows."""
+    import numpy as np
+    params = np.ascontiguousarray(params, np.float32)
+    knots = np.ascontiguousarray(knots, np.uint64)
+    codes = np.ascontiguousarray(codes, np.uint64)
+    targets = np.ascontiguousarray(targets, np.float32)
+    if params.size != MLP_PARAMS or knots.size != 9 or codes.size != MLP_GRAD_ROWS or targets.size != MLP_GRAD_ROWS:
+        raise ValueError("params 4801, knots 9, codes and targets MLP_GRAD_ROWS each")
+    g = np.zeros(MLP_PARAMS, np.float32)
+    loss = np.zeros(1, np.float32)
+    _check("elsar_mlp_gradient", lib().elsar_mlp_gradient(params.ctypes.data, knots.ctypes.data, codes.ctypes.data,
+                                                          targets.ctypes.data, g.ctypes.data, loss.ctypes.data))
+    return float(loss[0]), g

@@ -21,12 +21,16 @@ struct elsar_model {
   void* dev;           // owned allocation (null for a model placed in a workspace)
   ModelHeader* hdr;
   Leaf* leaves;
-  uint32_t* hist;      // sample keys per bucket (B)
+  uint32_t* hist;      // sample keys per bucket (B) under the root in use
+  bool has_mlp;        // kind MLP or AUTO: the MLP state below is placed
+  MlpState ms;
 };
 
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr uint32_t kDefaultMlpSteps = 400;
+constexpr float kMlpLearningRate = 0.01f;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -68,6 +72,7 @@ elsar_fit_params with_defaults(const elsar_fit_params& p) {
   elsar_fit_params q = p;
   if (q.region_pct == 0) q.region_pct = 125;
   if (q.accept_ratio <= 0.0f) q.accept_ratio = 1.5f;
+  if (q.mlp_steps == 0) q.mlp_steps = kDefaultMlpSteps;
   return q;
 }
 
@@ -80,8 +85,12 @@ Shape resolve(const elsar_fit_params& p, uint64_t n) {
   return s;
 }
 
-size_t model_dev_bytes(uint32_t L, uint32_t B) {
-  return align_up(sizeof(ModelHeader)) + align_up((size_t)L * sizeof(Leaf)) + align_up((size_t)B * 4);
+bool wants_mlp(uint32_t kind) { return kind == ELSAR_MODEL_MLP || kind == ELSAR_MODEL_AUTO; }
+
+size_t model_dev_bytes(uint32_t L, uint32_t B, uint32_t kind) {
+  size_t b = align_up(sizeof(ModelHeader)) + align_up((size_t)L * sizeof(Leaf)) + align_up((size_t)B * 4);
+  if (wants_mlp(kind)) b += align_up(mlp_state_bytes(L, B));
+  return b;
 }
 
 void place_model(elsar_model* m, void* base) {
@@ -91,6 +100,10 @@ void place_model(elsar_model* m, void* base) {
   m->leaves = reinterpret_cast<Leaf*>(b);
   b += align_up((size_t)m->L * sizeof(Leaf));
   m->hist = reinterpret_cast<uint32_t*>(b);
+  b += align_up((size_t)m->B * 4);
+  m->has_mlp = wants_mlp(m->p.kind);
+  m->ms = MlpState{};
+  if (m->has_mlp) place_mlp_state(&m->ms, b, m->L, m->B);
 }
 
 size_t fit_ws_bytes(uint64_t S) {
@@ -180,6 +193,10 @@ elsar_status do_fit(elsar_model* m, const void* d_records, uint64_t n, void* d_w
   HIP_TRY(launch_radix_sort_u64(codes, tmp, S, 0, 6, rscr, st, &sorted));
   HIP_TRY(launch_fit_rmi(sorted, S, n, m->L, m->B, m->hdr, m->leaves, fscr, st));
   HIP_TRY(launch_sample_hist(m->hdr, m->leaves, sorted, S, m->B, m->hist, st));
+  if (m->has_mlp)
+    HIP_TRY(launch_mlp_fit(sorted, S, m->L, m->B, m->p.seed, m->p.mlp_steps, kMlpLearningRate, m->hdr, m->ms, st));
+  HIP_TRY(launch_decide_root(m->hist, m->has_mlp ? &m->ms : nullptr, m->B, S, m->p.accept_ratio, m->p.kind,
+                             m->hdr, m->hist, st));
   m->n = n;
   return ELSAR_OK;
 }
@@ -192,8 +209,8 @@ elsar_status do_partition(const elsar_model* m, const void* d_records, uint64_t 
   uint8_t* part = static_cast<uint8_t*>(d_part);
   HIP_TRY(launch_capacities(m->hist, m->S, n, m->B, m->p.region_pct, part, lay, st));
   if (pm) mark(*pm, 1, st);
-  HIP_TRY(launch_partition(m->hdr, m->leaves, static_cast<const uint8_t*>(d_records), n, m->p.record_bytes,
-                           m->p.key_bytes, part, lay, st));
+  HIP_TRY(launch_partition(m->hdr, m->leaves, m->has_mlp ? &m->ms : nullptr, static_cast<const uint8_t*>(d_records),
+                           n, m->p.record_bytes, m->p.key_bytes, part, lay, st));
   if (pm) mark(*pm, 2, st);
   HIP_TRY(launch_scan_counts(part, lay, m->B, d_offsets, st));
   HIP_TRY(launch_spill_fixup(part, lay, n, st));
@@ -222,7 +239,7 @@ SortLayout sort_layout(const elsar_fit_params& p, const Shape& sh, uint64_t n) {
   SortLayout sl{};
   size_t off = 0;
   sl.model = off;
-  off += align_up(model_dev_bytes(sh.L, sh.B));
+  off += align_up(model_dev_bytes(sh.L, sh.B, p.kind));
   sl.fit = off;
   off += align_up(fit_ws_bytes(sh.S));
   sl.offsets = off;
@@ -263,7 +280,7 @@ elsar_status elsar_model_create(const elsar_fit_params* p, uint64_t n, elsar_mod
   m->L = sh.L;
   m->S = sh.S;
   m->n = 0;
-  if (hipMalloc(&m->dev, model_dev_bytes(m->L, m->B)) != hipSuccess) {
+  if (hipMalloc(&m->dev, model_dev_bytes(m->L, m->B, m->p.kind)) != hipSuccess) {
     delete m;
     return ELSAR_E_NO_MEMORY;
   }
@@ -293,7 +310,12 @@ elsar_status elsar_sample_fit(elsar_model* m, const void* d_records, uint64_t n,
   if (sh.B != m->B || sh.L != m->L) return ELSAR_E_INVALID_ARG;  // model shaped for another n
   m->S = sh.S;
   if (ws_bytes < fit_ws_bytes(m->S)) return ELSAR_E_NO_MEMORY;
-  return do_fit(m, d_records, n, d_ws, ws_bytes, stream);
+  elsar_status s = do_fit(m, d_records, n, d_ws, ws_bytes, stream);
+  if (s != ELSAR_OK || m->p.kind != ELSAR_MODEL_MLP || n == 0) return s;
+  ModelHeader h;
+  HIP_TRY(hipMemcpyAsync(&h, m->hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  return h.kind_used == 1 ? ELSAR_OK : ELSAR_E_MODEL_REJECTED;
 }
 
 elsar_status elsar_partition_size(const elsar_model* m, uint64_t n, size_t* part_bytes) {
@@ -392,8 +414,11 @@ elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info) 
 elsar_status elsar_model_leaves(const elsar_model* m, uint64_t* h_base, float* h_slope, float* h_icpt,
                                 uint32_t* h_lo, uint32_t* h_hi) {
   if (!m) return ELSAR_E_INVALID_ARG;
+  ModelHeader h;
+  HIP_TRY(hipMemcpy(&h, m->hdr, sizeof(h), hipMemcpyDeviceToHost));
+  const Leaf* src = (m->has_mlp && h.kind_used == 1) ? m->ms.leaves : m->leaves;
   std::vector<Leaf> lv(m->L);
-  HIP_TRY(hipMemcpy(lv.data(), m->leaves, lv.size() * sizeof(Leaf), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(lv.data(), src, lv.size() * sizeof(Leaf), hipMemcpyDeviceToHost));
   for (uint32_t j = 0; j < m->L; ++j) {
     if (h_base) h_base[j] = lv[j].base;
     if (h_slope) h_slope[j] = lv[j].c;
@@ -401,6 +426,83 @@ elsar_status elsar_model_leaves(const elsar_model* m, uint64_t* h_base, float* h
     if (h_lo) h_lo[j] = lv[j].lo;
     if (h_hi) h_hi[j] = lv[j].hi;
   }
+  return ELSAR_OK;
+}
+
+elsar_status elsar_model_mlp_get(const elsar_model* m, float* h_params, uint64_t* h_knots, uint64_t* h_bound,
+                                 uint32_t* h_first) {
+  if (!m || !m->has_mlp) return ELSAR_E_INVALID_ARG;
+  if (h_params) HIP_TRY(hipMemcpy(h_params, m->ms.master, (size_t)kMlpParams * 4, hipMemcpyDeviceToHost));
+  if (h_knots) HIP_TRY(hipMemcpy(h_knots, m->ms.M->h.q, 9 * 8, hipMemcpyDeviceToHost));
+  if (h_bound) HIP_TRY(hipMemcpy(h_bound, m->ms.bound, ((size_t)m->L + 1) * 8, hipMemcpyDeviceToHost));
+  if (h_first) HIP_TRY(hipMemcpy(h_first, m->ms.first, ((size_t)m->L + 1) * 4, hipMemcpyDeviceToHost));
+  return ELSAR_OK;
+}
+
+namespace {
+// Device scratch of the verification entry points, freed on every path.
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+elsar_status mlp_block_from_host(const float* h_params, const uint64_t* h_knots, DevBuf& buf, size_t extra,
+                                 MlpBlock** M, uint8_t** rest) {
+  const size_t head = align_up(sizeof(MlpBlock)) + align_up((size_t)kMlpParams * 4) + align_up(9 * 8);
+  if (hipMalloc(&buf.p, head + extra) != hipSuccess) return ELSAR_E_NO_MEMORY;
+  uint8_t* b = static_cast<uint8_t*>(buf.p);
+  *M = reinterpret_cast<MlpBlock*>(b);
+  float* d_params = reinterpret_cast<float*>(b + align_up(sizeof(MlpBlock)));
+  uint64_t* d_q = reinterpret_cast<uint64_t*>(b + align_up(sizeof(MlpBlock)) + align_up((size_t)kMlpParams * 4));
+  *rest = b + head;
+  HIP_TRY(hipMemcpy(d_params, h_params, (size_t)kMlpParams * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d_q, h_knots, 9 * 8, hipMemcpyHostToDevice));
+  HIP_TRY(launch_mlp_params_to_block(d_params, d_q, *M, nullptr));
+  return ELSAR_OK;
+}
+}  // namespace
+
+elsar_status elsar_mlp_forward(const float* h_params, const uint64_t* h_knots, const uint64_t* h_codes, uint64_t n,
+                               float* h_y) {
+  if (!h_params || !h_knots || (n && (!h_codes || !h_y))) return ELSAR_E_INVALID_ARG;
+  if (n > (1ull << 32)) return ELSAR_E_UNSUPPORTED;
+  if (n == 0) return ELSAR_OK;
+  DevBuf buf;
+  MlpBlock* M = nullptr;
+  uint8_t* rest = nullptr;
+  elsar_status s = mlp_block_from_host(h_params, h_knots, buf, align_up(n * 8) + align_up(n * 4), &M, &rest);
+  if (s != ELSAR_OK) return s;
+  uint64_t* d_codes = reinterpret_cast<uint64_t*>(rest);
+  float* d_y = reinterpret_cast<float*>(rest + align_up(n * 8));
+  HIP_TRY(hipMemcpy(d_codes, h_codes, n * 8, hipMemcpyHostToDevice));
+  HIP_TRY(launch_mlp_eval(M, d_codes, n, d_y, nullptr));
+  HIP_TRY(hipMemcpy(h_y, d_y, n * 4, hipMemcpyDeviceToHost));
+  return ELSAR_OK;
+}
+
+elsar_status elsar_mlp_gradient(const float* h_params, const uint64_t* h_knots, const uint64_t* h_codes,
+                                const float* h_targets, float* h_grad, float* h_loss) {
+  if (!h_params || !h_knots || !h_codes || !h_targets || !h_grad) return ELSAR_E_INVALID_ARG;
+  const size_t rows = kMlpGradRows;
+  DevBuf buf;
+  MlpBlock* M = nullptr;
+  uint8_t* rest = nullptr;
+  elsar_status s = mlp_block_from_host(h_params, h_knots, buf,
+                                       align_up(rows * 8) + align_up(rows * 4) + align_up((size_t)kMlpParams * 4) + 256,
+                                       &M, &rest);
+  if (s != ELSAR_OK) return s;
+  uint64_t* d_codes = reinterpret_cast<uint64_t*>(rest);
+  float* d_t = reinterpret_cast<float*>(rest + align_up(rows * 8));
+  float* d_g = reinterpret_cast<float*>(rest + align_up(rows * 8) + align_up(rows * 4));
+  float* d_loss = reinterpret_cast<float*>(rest + align_up(rows * 8) + align_up(rows * 4) +
+                                           align_up((size_t)kMlpParams * 4));
+  HIP_TRY(hipMemcpy(d_codes, h_codes, rows * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d_t, h_targets, rows * 4, hipMemcpyHostToDevice));
+  HIP_TRY(launch_mlp_grad(M, d_codes, d_t, d_g, d_loss, nullptr));
+  HIP_TRY(hipMemcpy(h_grad, d_g, (size_t)kMlpParams * 4, hipMemcpyDeviceToHost));
+  if (h_loss) HIP_TRY(hipMemcpy(h_loss, d_loss, 4, hipMemcpyDeviceToHost));
   return ELSAR_OK;
 }
 

@@ -37,8 +37,30 @@ struct ModelHeader {   // device-resident root of a fitted model
   uint64_t n_fit;      // records the model was fitted for
   uint64_t S;          // sample size
   uint32_t max_sample_bucket, opt_sample_bucket;
-  uint32_t pad[4];
+  uint32_t max_sample_run;  // longest run of equal codes in the sorted sample
+  uint32_t pad[3];
 };
+
+// Monotone MLP root (8 -> 64 -> 64 -> 1), flat parameter order W1 (64x8),
+// b1, W2 (64x64), b2, w3, b3.
+constexpr uint32_t kMlpH = 64;
+constexpr uint32_t kOffW1 = 0, kOffB1 = 512, kOffW2 = 576, kOffB2 = 4672, kOffW3 = 4736, kOffB3 = 4800;
+constexpr uint32_t kMlpParams = 4801;
+
+struct MlpHead {       // what the vector ALUs read: knots and the FP32 layers
+  uint64_t q[9];       // knots: codes at the sample's 1/8 quantiles, and the largest
+  float inv_w[8];      // 1 / max(q[k+1] - q[k], 1)
+  float W1[512];       // [unit][feature]
+  float b1[64], b2[64], w3[64];
+  float b3;
+  float pad[3];
+};
+struct MlpBlock {      // evaluation copy of the parameters
+  MlpHead h;
+  uint16_t W2bf[4096];   // bfloat16 W2[j][u], row-major
+  uint16_t W2bfT[4096];  // bfloat16 W2[j][u] at [u][j]
+};
+static_assert(sizeof(MlpHead) % 8 == 0, "W2 copies stay 8-byte aligned");
 
 struct PartHeader {    // device-resident state of one partition pass
   uint64_t n;
@@ -209,10 +231,33 @@ hipError_t launch_sample_hist(const ModelHeader* hdr, const Leaf* leaves, const 
 hipError_t launch_capacities(const uint32_t* hist, uint64_t S, uint64_t n, uint32_t B, uint32_t region_pct,
                              uint8_t* part, const PartLayout& lay, hipStream_t st);
 
+// MLP root (k_mlp.hip).  The model state beyond the RMI's.
+struct MlpState {
+  MlpBlock* M;
+  Leaf* leaves;      // L leaves under the MLP root
+  uint64_t* bound;   // L + 1 routing boundaries: leaf j takes codes in [bound[j], bound[j+1])
+  uint32_t* first;   // L + 1: first sample rank of each leaf
+  uint32_t* hist;    // B: sample keys per bucket under the MLP root
+  float* master;     // kMlpParams FP32 parameters
+  float* adam;       // 2 * kMlpParams moments
+};
+size_t mlp_state_bytes(uint32_t L, uint32_t B);
+void place_mlp_state(MlpState* s, void* base, uint32_t L, uint32_t B);
+hipError_t launch_mlp_fit(const uint64_t* sorted_codes, uint64_t S, uint32_t L, uint32_t B, uint64_t seed,
+                          uint32_t steps, float lr, ModelHeader* hdr, const MlpState& ms, hipStream_t st);
+hipError_t launch_decide_root(const uint32_t* hist_rmi, const MlpState* ms, uint32_t B, uint64_t S,
+                              float accept_ratio, uint32_t kind, ModelHeader* hdr, uint32_t* hist_used,
+                              hipStream_t st);
+hipError_t launch_mlp_params_to_block(const float* d_params, const uint64_t* d_q9, MlpBlock* M, hipStream_t st);
+hipError_t launch_mlp_eval(const MlpBlock* M, const uint64_t* codes, uint64_t n, float* y, hipStream_t st);
+hipError_t launch_mlp_grad(const MlpBlock* M, const uint64_t* codes, const float* targets, float* grad,
+                           float* loss, hipStream_t st);
+constexpr uint32_t kMlpGradRows = 128;  // rows of one training step
+
 // partition (k_partition.hip)
-hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const uint8_t* recs, uint64_t n,
-                            uint32_t rec_bytes, uint32_t key_bytes, uint8_t* part, const PartLayout& lay,
-                            hipStream_t st);
+hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const MlpState* ms, const uint8_t* recs,
+                            uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint8_t* part,
+                            const PartLayout& lay, hipStream_t st);
 hipError_t launch_scan_counts(uint8_t* part, const PartLayout& lay, uint32_t B, uint64_t* offsets,
                               hipStream_t st);
 hipError_t launch_spill_fixup(uint8_t* part, const PartLayout& lay, uint64_t n, hipStream_t st);

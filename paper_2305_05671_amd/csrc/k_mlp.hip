@@ -1,0 +1,578 @@
+// The learned root (gfx950): a monotone MLP CDF trained on the sample by this
+// file's own forward and backward kernels, used as the root of the RMI.
+//
+// The paper's CDF model is an RMI of linear models fitted to a sample of the
+// keys (Section 3.1).  Here the root may instead be a small monotone network
+// fitted to the same target, the sample's empirical CDF rank/S:
+//   phi_k = min(1, max(code - q_k, 0) / w_k)   k = 0..7, quantile knots q_k
+//   h1 = sigmoid(W1 phi + b1)    8 -> 64, FP32 vector ALUs, W1 >= 0
+//   h2 = sigmoid(W2 h1 + b2)     64 -> 64, bfloat16 matrix cores, FP32 accumulate, W2 >= 0
+//   y  = w3 . h2 + b3            64 -> 1, w3 >= 0
+// Non-negative weights and increasing activations make y non-decreasing in
+// the key.  The leaves are fixed on the sorted sample: the leaf of sample s is
+// the running maximum of floor(L y) up to s, and the first sample code of each
+// leaf becomes a routing boundary.  A record's leaf is the number of
+// boundaries at or below its code; the network's own floor(L y) is only the
+// starting point of that search.  Routing is therefore exactly monotone
+// whatever the rounding inside the matrix cores, and each leaf's linear model
+// is the same two-point spline as under the linear root.
+#include "mlp_device.h"
+
+namespace elsar {
+
+// ------------------------------------------------------------------ state --
+namespace {
+constexpr size_t kA = 256;
+inline size_t al(size_t x) { return (x + kA - 1) & ~(kA - 1); }
+}  // namespace
+
+size_t mlp_state_bytes(uint32_t L, uint32_t B) {
+  return al(sizeof(MlpBlock)) + al((size_t)L * sizeof(Leaf)) + al(((size_t)L + 1) * 8) + al(((size_t)L + 1) * 4) +
+         al((size_t)B * 4) + al((size_t)kMlpParams * 4) + al((size_t)kMlpParams * 8);
+}
+
+void place_mlp_state(MlpState* s, void* base, uint32_t L, uint32_t B) {
+  uint8_t* b = static_cast<uint8_t*>(base);
+  s->M = reinterpret_cast<MlpBlock*>(b);
+  b += al(sizeof(MlpBlock));
+  s->leaves = reinterpret_cast<Leaf*>(b);
+  b += al((size_t)L * sizeof(Leaf));
+  s->bound = reinterpret_cast<uint64_t*>(b);
+  b += al(((size_t)L + 1) * 8);
+  s->first = reinterpret_cast<uint32_t*>(b);
+  b += al(((size_t)L + 1) * 4);
+  s->hist = reinterpret_cast<uint32_t*>(b);
+  b += al((size_t)B * 4);
+  s->master = reinterpret_cast<float*>(b);
+  b += al((size_t)kMlpParams * 4);
+  s->adam = reinterpret_cast<float*>(b);
+}
+
+// ------------------------------------------------------------------ setup --
+__device__ __forceinline__ float philox_unit(uint64_t i, uint32_t stream, uint64_t seed) {
+  return (float)(philox_x(i, stream, 0u, seed) >> 8) * (1.0f / 16777216.0f);
+}
+
+__device__ void set_knots(const uint64_t* q9, MlpHead* h) {
+  if (threadIdx.x < 9) h->q[threadIdx.x] = q9[threadIdx.x];
+  if (threadIdx.x < 8) {
+    const uint64_t a = q9[threadIdx.x], b = q9[threadIdx.x + 1];
+    h->inv_w[threadIdx.x] = (float)(1.0 / (b > a ? (double)(b - a) : 1.0));
+  }
+}
+
+// Knots q_k = e[k S / 8] (k < 8), q_8 = e[S-1]; initial weights from Philox
+// draws u: W1 = u, b1 = -4u, W2 = 0.1u, b2 = -3, w3 = 0.05u, b3 = 0 (small
+// positive weights, hidden units off saturation); Adam moments zero.
+__global__ void mlp_setup_kernel(const uint64_t* __restrict__ e, uint64_t S, uint64_t seed, MlpBlock* __restrict__ M,
+                                 float* __restrict__ master, float* __restrict__ adam, ModelHeader* __restrict__ hdr) {
+  __shared__ uint64_t q9[9];
+  if (threadIdx.x < 9) q9[threadIdx.x] = e[threadIdx.x < 8 ? (threadIdx.x * S) / 8 : S - 1];
+  if (threadIdx.x == 0) hdr->max_sample_run = 0;
+  __syncthreads();
+  set_knots(q9, &M->h);
+  for (uint32_t p = threadIdx.x; p < kMlpParams; p += blockDim.x) {
+    const float u = philox_unit(p, 0x4D4C5049u /* "MLPI" */, seed);
+    float v;
+    if (p < kOffB1) v = u;
+    else if (p < kOffW2) v = -4.0f * u;
+    else if (p < kOffB2) v = 0.1f * u;
+    else if (p < kOffW3) v = -3.0f;
+    else if (p < kOffB3) v = 0.05f * u;
+    else v = 0.0f;
+    master[p] = v;
+    adam[p] = 0.0f;
+    adam[kMlpParams + p] = 0.0f;
+  }
+}
+
+// Evaluation copy of one FP32 parameter (W2 in bfloat16, both orientations).
+__device__ __forceinline__ void publish_one(uint32_t p, float v, MlpBlock* __restrict__ M) {
+  if (p < kOffB1) M->h.W1[p] = v;
+  else if (p < kOffW2) M->h.b1[p - kOffB1] = v;
+  else if (p < kOffB2) {
+    const uint32_t j = (p - kOffW2) / 64, u = (p - kOffW2) % 64;
+    const uint16_t b = f32_to_bf16(v);
+    M->W2bf[j * 64 + u] = b;
+    M->W2bfT[u * 64 + j] = b;
+  } else if (p < kOffW3) M->h.b2[p - kOffB2] = v;
+  else if (p < kOffB3) M->h.w3[p - kOffW3] = v;
+  else M->h.b3 = v;
+}
+
+__device__ void publish(const float* __restrict__ master, MlpBlock* __restrict__ M) {
+  for (uint32_t p = threadIdx.x; p < kMlpParams; p += blockDim.x) publish_one(p, master[p], M);
+}
+
+__global__ void mlp_publish_kernel(const float* __restrict__ master, const uint64_t* __restrict__ q9,
+                                   MlpBlock* __restrict__ M) {
+  if (q9) set_knots(q9, &M->h);
+  publish(master, M);
+}
+
+// --------------------------------------------------------------- training --
+// One step on kMlpGradRows rows: forward, MSE gradient with targets t, backward
+// into G (flat parameter order).  Block of 256 threads; wave w owns rows
+// 32w .. 32w + 31 in two 16-row chunks.  The 64x64 products (forward, dW2 and
+// dh1) run on the matrix cores in bfloat16 with FP32 accumulation; everything
+// else is FP32.
+constexpr uint32_t kTrainThreads = 256;
+constexpr uint32_t kRows = kMlpGradRows;
+static_assert(kRows == 32 * (kTrainThreads / 64), "two 16-row chunks per wave");
+
+struct TrainLds {
+  MlpBlock M;
+  float H1T[64 * kRows];       // h1 (FP32), [unit][row]
+  uint16_t DZ2[kRows * 64];    // dL/dz2 (bf16), [row][j]
+  uint16_t DZ2T[64 * kRows];   // dL/dz2 (bf16), [j][row]
+  float PHI[kRows * 8];
+  float T[kRows], DY[kRows];
+  float G[kMlpParams];
+  float loss;
+};
+
+__device__ void step_grad(TrainLds& sm) {
+  const uint32_t tid = threadIdx.x, w = tid >> 6, l = __lane_id(), r = l & 15u, g = l >> 4;
+  const MlpHead& M = sm.M.h;
+  float h2[2][4][4];  // [chunk][ct][e]: row 32w + 16c + 4g + e, column 16ct + r
+  // forward
+#pragma unroll
+  for (uint32_t c = 0; c < 2; ++c) {
+    const uint32_t r0 = 32 * w + 16 * c;
+    float phi[8], h1[16];
+    s16x4 a[4];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) phi[k] = sm.PHI[(r0 + r) * 8 + k];
+    mlp_layer1_frags(phi, M, g, a, h1);
+#pragma unroll
+    for (uint32_t ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (uint32_t e = 0; e < 4; ++e) sm.H1T[(16 * ks + 4 * g + e) * kRows + r0 + r] = h1[4 * ks + e];
+    float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (uint32_t ct = 0; ct < 4; ++ct) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (uint32_t ks = 0; ks < 4; ++ks) {
+        const s16x4 b = load4_bf16(sm.M.W2bf + (16 * ct + r) * 64 + 16 * ks + 4 * g);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ks], b, acc, 0, 0, 0);
+      }
+      const uint32_t col = 16 * ct + r;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float v = sigm(acc[e] + M.b2[col]);
+        h2[c][ct][e] = v;
+        part[e] = __builtin_fmaf(M.w3[col], v, part[e]);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) part[e] += __shfl_xor(part[e], off);
+      if (r == 0) {
+        const uint32_t row = r0 + 4 * g + e;
+        const float res = part[e] + M.b3 - sm.T[row];
+        sm.DY[row] = 2.0f * res / (float)kRows;
+        atomicAdd(&sm.loss, res * res / (float)kRows);
+      }
+    }
+  }
+  __syncthreads();
+  // output layer: dw3, db2, db3 and dz2 = dy w3 h2 (1 - h2)
+  {
+    float gb3 = tid < kRows ? sm.DY[tid] : 0.0f;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) gb3 += __shfl_xor(gb3, off);
+    if (l == 0 && tid < kRows) atomicAdd(&sm.G[kOffB3], gb3);
+#pragma unroll
+    for (uint32_t ct = 0; ct < 4; ++ct) {
+      const uint32_t col = 16 * ct + r;
+      float gw3 = 0.f, gb2 = 0.f;
+#pragma unroll
+      for (uint32_t c = 0; c < 2; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t row = 32 * w + 16 * c + 4 * g + e;
+          const float dy = sm.DY[row], v = h2[c][ct][e];
+          const float dz2 = dy * M.w3[col] * v * (1.0f - v);
+          gw3 = __builtin_fmaf(dy, v, gw3);
+          gb2 += dz2;
+          const uint16_t hz = f32_to_bf16(dz2);
+          sm.DZ2[row * 64 + col] = hz;
+          sm.DZ2T[col * kRows + row] = hz;
+        }
+      gw3 += __shfl_xor(gw3, 16);
+      gw3 += __shfl_xor(gw3, 32);
+      gb2 += __shfl_xor(gb2, 16);
+      gb2 += __shfl_xor(gb2, 32);
+      if (g == 0) {
+        atomicAdd(&sm.G[kOffW3 + col], gw3);
+        atomicAdd(&sm.G[kOffB2 + col], gb2);
+      }
+    }
+  }
+  __syncthreads();
+  // dW2[j][u] = sum_t dz2[t][j] h1q[t][u]; wave w takes j = 16w .. 16w + 15
+#pragma unroll
+  for (uint32_t ct = 0; ct < 4; ++ct) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (uint32_t ks = 0; ks < kRows / 16; ++ks) {
+      const s16x4 a = load4_bf16(sm.DZ2T + (16 * w + r) * kRows + 16 * ks + 4 * g);
+      const float* h = sm.H1T + (16 * ct + r) * kRows + 16 * ks + 4 * g;
+      const s16x4 b = pack4_bf16(h[0], h[1], h[2], h[3]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sm.G[kOffW2 + (16 * w + 4 * g + e) * 64 + 16 * ct + r] = acc[e];
+  }
+  // dh1[t][u] = sum_j dz2[t][j] W2q[j][u]; dz1 = dh1 h1 (1 - h1); dW1 = dz1^T phi, db1
+#pragma unroll
+  for (uint32_t c = 0; c < 2; ++c) {
+    const uint32_t r0 = 32 * w + 16 * c;
+#pragma unroll
+    for (uint32_t ct = 0; ct < 4; ++ct) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (uint32_t ks = 0; ks < 4; ++ks) {
+        const s16x4 a = load4_bf16(sm.DZ2 + (r0 + r) * 64 + 16 * ks + 4 * g);
+        const s16x4 b = load4_bf16(sm.M.W2bfT + (16 * ct + r) * 64 + 16 * ks + 4 * g);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+      }
+      const uint32_t u = 16 * ct + r;
+      float gw[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, gb = 0.f;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t row = r0 + 4 * g + e;
+        const float h = sm.H1T[u * kRows + row];
+        const float dz1 = acc[e] * h * (1.0f - h);
+        gb += dz1;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) gw[k] = __builtin_fmaf(dz1, sm.PHI[row * 8 + k], gw[k]);
+      }
+      gb += __shfl_xor(gb, 16);
+      gb += __shfl_xor(gb, 32);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        gw[k] += __shfl_xor(gw[k], 16);
+        gw[k] += __shfl_xor(gw[k], 32);
+      }
+      if (g == 0) {
+        atomicAdd(&sm.G[kOffB1 + u], gb);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) atomicAdd(&sm.G[kOffW1 + u * 8 + k], gw[k]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__device__ void load_block(const MlpBlock* __restrict__ src, MlpBlock& dst) {
+  const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+  uint32_t* d = reinterpret_cast<uint32_t*>(&dst);
+  for (uint32_t i = threadIdx.x; i < sizeof(MlpBlock) / 4; i += blockDim.x) d[i] = s[i];
+}
+
+__device__ void clear_grad(TrainLds& sm) {
+  for (uint32_t p = threadIdx.x; p < kMlpParams; p += blockDim.x) sm.G[p] = 0.0f;
+  if (threadIdx.x == 0) sm.loss = 0.0f;
+}
+
+// All training steps in one block: per step kRows sample positions drawn with
+// Philox, the gradient, then Adam (beta1 0.9, beta2 0.999, eps 1e-8) with
+// W1, W2, w3 projected onto >= 0, and a fresh evaluation copy.
+__global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(const uint64_t* __restrict__ e, uint64_t S,
+                                                                  uint32_t steps, float lr, uint64_t seed,
+                                                                  float* __restrict__ master,
+                                                                  float* __restrict__ adam,
+                                                                  MlpBlock* __restrict__ Mout) {
+  extern __shared__ uint4 lds_raw[];
+  TrainLds& sm = *reinterpret_cast<TrainLds*>(lds_raw);
+  const uint32_t tid = threadIdx.x;
+  load_block(Mout, sm.M);
+  float* m1 = adam;
+  float* m2 = adam + kMlpParams;
+  float p1 = 1.0f, p2 = 1.0f;  // beta^step
+  __syncthreads();
+  for (uint32_t step = 1; step <= steps; ++step) {
+    clear_grad(sm);
+    if (tid < kRows) {
+      const uint64_t ctr = (uint64_t)step * kRows + tid;
+      const uint64_t s = ((uint64_t)philox_x(ctr, 0x4D4C5042u /* "MLPB" */, 0u, seed) * S) >> 32;
+      sm.T[tid] = (float)((double)s / (double)S);
+      float phi[8];
+      mlp_features(e[s], sm.M.h, phi);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sm.PHI[tid * 8 + k] = phi[k];
+    }
+    __syncthreads();
+    step_grad(sm);
+    p1 *= 0.9f;
+    p2 *= 0.999f;
+    const float c1 = 1.0f / (1.0f - p1), c2 = 1.0f / (1.0f - p2);
+    for (uint32_t p = tid; p < kMlpParams; p += kTrainThreads) {
+      const float gr = sm.G[p];
+      const float a1 = 0.9f * m1[p] + 0.1f * gr;
+      const float a2 = 0.999f * m2[p] + 0.001f * gr * gr;
+      m1[p] = a1;
+      m2[p] = a2;
+      float v = master[p] - lr * (a1 * c1) / (sqrtf(a2 * c2) + 1e-8f);
+      const bool nonneg = p < kOffB1 || (p >= kOffW2 && p < kOffB2) || (p >= kOffW3 && p < kOffB3);
+      if (nonneg) v = fmaxf(v, 0.0f);
+      master[p] = v;
+      publish_one(p, v, &sm.M);
+    }
+    __syncthreads();
+  }
+  // the knots were in the copy loaded at the start; write everything back
+  const uint32_t* s = reinterpret_cast<const uint32_t*>(&sm.M);
+  uint32_t* d = reinterpret_cast<uint32_t*>(Mout);
+  for (uint32_t i = tid; i < sizeof(MlpBlock) / 4; i += kTrainThreads) d[i] = s[i];
+}
+
+// One gradient on caller-supplied rows (codes and targets), for verification.
+__global__ __launch_bounds__(kTrainThreads) void mlp_grad_kernel(const MlpBlock* __restrict__ Mg,
+                                                                 const uint64_t* __restrict__ codes,
+                                                                 const float* __restrict__ targets,
+                                                                 float* __restrict__ grad, float* __restrict__ loss) {
+  extern __shared__ uint4 lds_raw[];
+  TrainLds& sm = *reinterpret_cast<TrainLds*>(lds_raw);
+  const uint32_t tid = threadIdx.x;
+  load_block(Mg, sm.M);
+  clear_grad(sm);
+  __syncthreads();
+  if (tid < kRows) {
+    sm.T[tid] = targets[tid];
+    float phi[8];
+    mlp_features(codes[tid], sm.M.h, phi);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sm.PHI[tid * 8 + k] = phi[k];
+  }
+  __syncthreads();
+  step_grad(sm);
+  for (uint32_t p = tid; p < kMlpParams; p += kTrainThreads) grad[p] = sm.G[p];
+  if (tid == 0) *loss = sm.loss;
+}
+
+// ------------------------------------------------------- leaves and bounds --
+__device__ __forceinline__ void load_head(const MlpBlock* __restrict__ Mg, MlpHead& mh) {
+  for (uint32_t i = threadIdx.x; i < sizeof(MlpHead) / 4; i += blockDim.x)
+    reinterpret_cast<uint32_t*>(&mh)[i] = reinterpret_cast<const uint32_t*>(&Mg->h)[i];
+}
+
+// y of n codes (64 per wave; the tail wave clamps its reads).
+__global__ __launch_bounds__(256) void mlp_eval_kernel(const MlpBlock* __restrict__ Mg,
+                                                       const uint64_t* __restrict__ codes, uint64_t n,
+                                                       float* __restrict__ y) {
+  __shared__ MlpHead mh;
+  load_head(Mg, mh);
+  W2Frags w;
+  mlp_load_w2(Mg->W2bf, w);
+  __syncthreads();
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const float v = mlp_y64(codes[i < n ? i : n - 1], mh, w);
+  if (i < n) y[i] = v;
+}
+
+// Raw leaf of every sorted sample, floor(L y) clamped; first_exact[j] gets
+// the smallest sample with raw leaf j (atomic minimum).
+__global__ __launch_bounds__(256) void mlp_sample_leaves_kernel(const uint64_t* __restrict__ e, uint64_t S,
+                                                                uint32_t L, const MlpBlock* __restrict__ Mg,
+                                                                uint32_t* __restrict__ first_exact) {
+  __shared__ MlpHead mh;
+  load_head(Mg, mh);
+  W2Frags w;
+  mlp_load_w2(Mg->W2bf, w);
+  __syncthreads();
+  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const float y = mlp_y64(e[s < S ? s : S - 1], mh, w);
+  if (s < S) atomicMin(&first_exact[mlp_leaf_guess(y, L)], (uint32_t)s);
+}
+
+// first[j] = min over j' >= j of first_exact[j'] (the running maximum of the
+// raw leaves, seen from the leaf side); first[L] = S.  One block.
+__global__ __launch_bounds__(1024) void suffix_min_kernel(uint32_t* __restrict__ v, uint32_t L, uint32_t S) {
+  __shared__ uint32_t sh[1024];
+  const uint32_t per = (L + 1023) / 1024;
+  const uint32_t b = threadIdx.x * per < L ? threadIdx.x * per : L;
+  const uint32_t end = b + per < L ? b + per : L;
+  uint32_t m = S;
+  for (uint32_t i = b; i < end; ++i) m = v[i] < m ? v[i] : m;
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (uint32_t off = 1; off < 1024; off <<= 1) {
+    const uint32_t x = threadIdx.x + off < 1024 ? sh[threadIdx.x + off] : S;
+    __syncthreads();
+    if (x < sh[threadIdx.x]) sh[threadIdx.x] = x;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x + 1 < 1024 ? sh[threadIdx.x + 1] : S;
+  for (uint32_t i = end; i > b; --i) {
+    run = v[i - 1] < run ? v[i - 1] : run;
+    v[i - 1] = run;
+  }
+  if (threadIdx.x == 0) v[L] = S;
+}
+
+// Leaf j covers samples first[j] .. first[j+1]-1: the same two-point spline
+// and bucket range as a leaf of the linear root.  bound[j] = code of the
+// leaf's first sample (0 for leaf 0; past every code for leaves after the
+// last sample); bound[L] is past every code.
+__global__ __launch_bounds__(256) void mlp_leaf_fit_kernel(const uint64_t* __restrict__ e, uint64_t S, uint32_t L,
+                                                           uint32_t B, const uint32_t* __restrict__ first,
+                                                           Leaf* __restrict__ leaves, uint64_t* __restrict__ bound) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j == 0) bound[L] = ~0ull;
+  if (j >= L) return;
+  const uint64_t f = first[j], gg = first[j + 1];
+  bound[j] = j == 0 ? 0ull : (f < S ? e[f] : ~0ull);
+  Leaf lf;
+  lf.pad[0] = lf.pad[1] = 0;
+  if (f >= gg) {
+    const uint32_t v = f < S ? (uint32_t)(((uint64_t)B * f) / S) : B - 1;
+    lf.base = 0;
+    lf.c = 0.0f;
+    lf.b = (float)v;
+    lf.lo = lf.hi = v;
+  } else {
+    const double tf = (double)B * (double)f / (double)S;
+    const double tl = (double)B * (double)(gg - 1) / (double)S;
+    const double span = (double)code_f32(e[gg - 1] - e[f]);
+    lf.base = e[f];
+    lf.c = (float)(span > 0 ? (tl - tf) / span : 0.0);
+    lf.b = (float)tf;
+    lf.lo = (uint32_t)(((uint64_t)B * f) / S);
+    const uint64_t h = ((uint64_t)B * (gg - 1)) / S;
+    lf.hi = (uint32_t)(h < B - 1 ? h : B - 1);
+  }
+  leaves[j] = lf;
+}
+
+// Per sample: its bucket under the MLP root (leaf found from first[]), and
+// the longest run of equal codes (no monotone bucketing can split a run).
+__global__ __launch_bounds__(256) void mlp_sample_stats_kernel(const uint64_t* __restrict__ e, uint64_t S,
+                                                               uint32_t L, const uint32_t* __restrict__ first,
+                                                               const Leaf* __restrict__ leaves,
+                                                               uint32_t* __restrict__ hist,
+                                                               ModelHeader* __restrict__ hdr) {
+  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const uint64_t c = e[s];
+  if (s + 1 == S || e[s + 1] != c) {
+    uint64_t lo = 0, hi = s;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (e[mid] < c) lo = mid + 1; else hi = mid;
+    }
+    atomicMax(&hdr->max_sample_run, (uint32_t)(s + 1 - lo));
+  }
+  uint32_t lo = 0, hi = L;  // last j with first[j] <= s
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (first[mid] <= s) lo = mid; else hi = mid;
+  }
+  atomicAdd(&hist[leaf_bucket(load_leaf(leaves, lo), c)], 1u);
+}
+
+// Choice of the root.  The MLP passes when its largest sample bucket is at
+// most accept_ratio times the ideal max(ceil(S/B), longest equal-code run).
+// kind 1 (MLP): the MLP if it passes, else the linear root.  kind 2 (automatic):
+// the MLP if it passes or beats the linear root's largest sample bucket.
+// The chosen root's sample histogram is copied to hist_used.
+__global__ __launch_bounds__(256) void decide_root_kernel(const uint32_t* __restrict__ hist_rmi,
+                                                          const uint32_t* __restrict__ hist_mlp, uint32_t B,
+                                                          uint64_t S, float accept_ratio, uint32_t kind,
+                                                          ModelHeader* __restrict__ hdr,
+                                                          uint32_t* __restrict__ hist_used) {
+  __shared__ uint32_t mr[256], mm[256];
+  __shared__ uint32_t use_mlp;
+  uint32_t a = 0, b = 0;
+  for (uint32_t j = threadIdx.x; j < B; j += 256) {
+    a = hist_rmi[j] > a ? hist_rmi[j] : a;
+    if (hist_mlp) b = hist_mlp[j] > b ? hist_mlp[j] : b;
+  }
+  mr[threadIdx.x] = a;
+  mm[threadIdx.x] = b;
+  __syncthreads();
+  for (uint32_t off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      if (mr[threadIdx.x + off] > mr[threadIdx.x]) mr[threadIdx.x] = mr[threadIdx.x + off];
+      if (mm[threadIdx.x + off] > mm[threadIdx.x]) mm[threadIdx.x] = mm[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    uint32_t ideal = (uint32_t)((S + B - 1) / B);
+    if (hist_mlp && hdr->max_sample_run > ideal) ideal = hdr->max_sample_run;
+    uint32_t u = 0, rejected = 0;
+    if (hist_mlp) {
+      const bool pass = (double)mm[0] <= (double)accept_ratio * (double)ideal;
+      rejected = pass ? 0u : 1u;
+      u = (pass || (kind == 2 && mm[0] < mr[0])) ? 1u : 0u;
+    }
+    hdr->kind_used = u;
+    hdr->mlp_rejected = rejected;
+    hdr->max_sample_bucket = u ? mm[0] : mr[0];
+    hdr->opt_sample_bucket = ideal;
+    use_mlp = u;
+  }
+  __syncthreads();
+  if (use_mlp)
+    for (uint32_t j = threadIdx.x; j < B; j += 256) hist_used[j] = hist_mlp[j];
+}
+
+// ------------------------------------------------------------------- host --
+static hipError_t allow_big_lds(const void* fn) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(TrainLds));
+}
+
+hipError_t launch_mlp_fit(const uint64_t* e, uint64_t S, uint32_t L, uint32_t B, uint64_t seed, uint32_t steps,
+                          float lr, ModelHeader* hdr, const MlpState& ms, hipStream_t st) {
+  if (S == 0) return hipSuccess;
+  mlp_setup_kernel<<<1, 256, 0, st>>>(e, S, seed, ms.M, ms.master, ms.adam, hdr);
+  mlp_publish_kernel<<<1, 256, 0, st>>>(ms.master, nullptr, ms.M);
+  if (steps) {
+    hipError_t err = allow_big_lds(reinterpret_cast<const void*>(mlp_train_kernel));
+    if (err != hipSuccess) return err;
+    mlp_train_kernel<<<1, kTrainThreads, sizeof(TrainLds), st>>>(e, S, steps, lr, seed, ms.master, ms.adam, ms.M);
+  }
+  hipError_t err = hipMemsetAsync(ms.first, 0xFF, ((size_t)L + 1) * 4, st);
+  if (err != hipSuccess) return err;
+  const uint32_t nb = (uint32_t)((S + 255) / 256);
+  mlp_sample_leaves_kernel<<<nb, 256, 0, st>>>(e, S, L, ms.M, ms.first);
+  suffix_min_kernel<<<1, 1024, 0, st>>>(ms.first, L, (uint32_t)S);
+  mlp_leaf_fit_kernel<<<(L + 255) / 256, 256, 0, st>>>(e, S, L, B, ms.first, ms.leaves, ms.bound);
+  err = hipMemsetAsync(ms.hist, 0, (size_t)B * 4, st);
+  if (err != hipSuccess) return err;
+  mlp_sample_stats_kernel<<<nb, 256, 0, st>>>(e, S, L, ms.first, ms.leaves, ms.hist, hdr);
+  return hipGetLastError();
+}
+
+hipError_t launch_decide_root(const uint32_t* hist_rmi, const MlpState* ms, uint32_t B, uint64_t S,
+                              float accept_ratio, uint32_t kind, ModelHeader* hdr, uint32_t* hist_used,
+                              hipStream_t st) {
+  decide_root_kernel<<<1, 256, 0, st>>>(hist_rmi, ms ? ms->hist : nullptr, B, S, accept_ratio, kind, hdr,
+                                        hist_used);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_params_to_block(const float* d_params, const uint64_t* d_q9, MlpBlock* M, hipStream_t st) {
+  mlp_publish_kernel<<<1, 256, 0, st>>>(d_params, d_q9, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_eval(const MlpBlock* M, const uint64_t* codes, uint64_t n, float* y, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  mlp_eval_kernel<<<(uint32_t)((n + 255) / 256), 256, 0, st>>>(M, codes, n, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const MlpBlock* M, const uint64_t* codes, const float* targets, float* grad, float* loss,
+                           hipStream_t st) {
+  hipError_t err = allow_big_lds(reinterpret_cast<const void*>(mlp_grad_kernel));
+  if (err != hipSuccess) return err;
+  mlp_grad_kernel<<<1, kTrainThreads, sizeof(TrainLds), st>>>(M, codes, targets, grad, loss);
+  return hipGetLastError();
+}
+
+}  // namespace elsar

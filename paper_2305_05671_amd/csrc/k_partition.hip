@@ -9,7 +9,9 @@
 // bucket that outgrows its region continues in a shared spill area; the
 // spill entry remembers (bucket, rank within the bucket's overflow) so the
 // fix-up can group the spill without sorting it.
-#include "elsar_internal.h"
+#include <type_traits>
+
+#include "mlp_device.h"
 
 namespace elsar {
 
@@ -76,9 +78,15 @@ __device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const
 // the loads of tile t+1 are in flight while the atomics of tile t reserve
 // slots and the slots of tile t-1 are written, so neither the load latency nor
 // the atomic latency stalls the block.  Two LDS tile buffers alternate.
-template <int RW_T>
+//
+// MLP: the root is the monotone network (kind_used == 1): its floor(L y) is the
+// guess from which the exact leaf is found among the routing boundaries.  The
+// linear-root and the MLP-root kernels are both launched when a fit may
+// choose either; each returns at once unless the header names its root.
+template <int RW_T, bool MLP>
 __global__ __launch_bounds__(kPartThreads) void partition_kernel(
-    const ModelHeader* __restrict__ hdr, const Leaf* __restrict__ leaves, const uint8_t* __restrict__ recs,
+    const ModelHeader* __restrict__ hdr, const Leaf* __restrict__ leaves, const MlpBlock* __restrict__ mlp,
+    const uint64_t* __restrict__ bound, const uint8_t* __restrict__ recs,
     uint64_t n, uint32_t rw_rt, uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps,
     const uint32_t* __restrict__ rstart, PartHeader* __restrict__ ph, uint2* __restrict__ spill_meta,
     uint4* __restrict__ slots, uint64_t cap_slots) {
@@ -87,9 +95,17 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
   constexpr uint32_t RV = RW_T ? (kPartTile * RW_T / 4 + kPartThreads - 1) / kPartThreads : 8;
   extern __shared__ uint4 lds4[];                      // 2 tiles of kPartTile * RW dwords
   __shared__ uint32_t dst[2][kPartTile];
+  if ((hdr->kind_used == 1u) != MLP) return;
   const uint32_t tile_dw = kPartTile * RW;
   const float a0 = hdr->a0, a1 = hdr->a1;
   const uint32_t L = hdr->L;
+  __shared__ typename std::conditional<MLP, MlpHead, uint32_t>::type mh_;
+  W2Frags w2;
+  if constexpr (MLP) {
+    for (uint32_t i = threadIdx.x; i < sizeof(MlpHead) / 4; i += kPartThreads)
+      reinterpret_cast<uint32_t*>(&mh_)[i] = reinterpret_cast<const uint32_t*>(&mlp->h)[i];
+    mlp_load_w2(mlp->W2bf, w2);
+  }
   const uint64_t ntiles = (n + kPartTile - 1) / kPartTile;
   const uint32_t* rec_dw = reinterpret_cast<const uint32_t*>(recs);
   auto tile_count = [&](uint64_t t) {
@@ -130,7 +146,18 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
     // 2. bucket of each record of tile t and its slot reservation
     const uint32_t cnt = tile_count(t);
     uint32_t b = 0, s = 0;
-    if (threadIdx.x < cnt) {
+    if constexpr (MLP) {
+      // every lane takes part in the matrix products; lanes past the tile's
+      // end read stale tile bytes and discard the result
+      const uint32_t* r = buf(cur) + threadIdx.x * RW;
+      const uint64_t e = key_code(r[0], r[1]);
+      const float y = mlp_y64(e, mh_, w2);
+      if (threadIdx.x < cnt) {
+        const uint32_t j = mlp_exact_leaf(bound, L, e, mlp_leaf_guess(y, L));
+        b = leaf_bucket(load_leaf(leaves, j), e);
+        s = atomicAdd(&counts[b], 1u);
+      }
+    } else if (threadIdx.x < cnt) {
       const uint32_t* r = buf(cur) + threadIdx.x * RW;
       uint64_t e = key_code(r[0], r[1]);
       uint32_t j = rmi_leaf(a0, a1, L, e);
@@ -166,9 +193,23 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
   write_tile(tprev, buf(cur), dst[cur]);
 }
 
-hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const uint8_t* recs, uint64_t n,
-                            uint32_t rec_bytes, uint32_t /*key_bytes*/, uint8_t* part, const PartLayout& lay,
-                            hipStream_t st) {
+template <bool MLP>
+static void launch_partition_root(uint32_t grid, size_t lds, hipStream_t st, uint32_t RW, const ModelHeader* hdr,
+                                  const Leaf* leaves, const MlpBlock* mlp, const uint64_t* bound,
+                                  const uint8_t* recs, uint64_t n, uint32_t* counts, const uint32_t* caps,
+                                  const uint32_t* rstart, PartHeader* ph, uint2* meta, uint4* slots,
+                                  uint64_t cap_slots) {
+  if (RW == 25)
+    partition_kernel<25, MLP><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, recs, n, RW, counts, caps,
+                                                               rstart, ph, meta, slots, cap_slots);
+  else
+    partition_kernel<0, MLP><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, recs, n, RW, counts, caps,
+                                                              rstart, ph, meta, slots, cap_slots);
+}
+
+hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const MlpState* ms, const uint8_t* recs,
+                            uint64_t n, uint32_t rec_bytes, uint32_t /*key_bytes*/, uint8_t* part,
+                            const PartLayout& lay, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const uint32_t RW = rec_bytes / 4;
   const size_t lds = 2 * (size_t)kPartTile * RW * 4;
@@ -180,12 +221,11 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const ui
   auto* ph = reinterpret_cast<PartHeader*>(part + lay.header);
   auto* meta = reinterpret_cast<uint2*>(part + lay.spill_meta);
   auto* slots = reinterpret_cast<uint4*>(part + lay.slots);
-  if (RW == 25)
-    partition_kernel<25><<<grid, kPartThreads, lds, st>>>(hdr, leaves, recs, n, RW, counts, caps, rstart, ph, meta,
-                                                          slots, lay.cap_slots);
-  else
-    partition_kernel<0><<<grid, kPartThreads, lds, st>>>(hdr, leaves, recs, n, RW, counts, caps, rstart, ph, meta,
-                                                         slots, lay.cap_slots);
+  launch_partition_root<false>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, recs, n, counts, caps, rstart, ph,
+                               meta, slots, lay.cap_slots);
+  if (ms)
+    launch_partition_root<true>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, recs, n, counts, caps,
+                                rstart, ph, meta, slots, lay.cap_slots);
   return hipGetLastError();
 }
 

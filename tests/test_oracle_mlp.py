@@ -112,3 +112,54 @@ def test_training_reduces_loss_and_leaves_are_monotone():
     assert l1 < 0.1 * l0 and l1 < 2e-3
     lv = mlp.leaves_of_sorted(mlp.forward(P, X)["y"], 256)
     assert np.all(np.diff(lv) >= 0) and lv.min() >= 0 and lv.max() < 256
+
+
+def test_bf16_backward_close_to_fp64():
+    # the rounding points of the matrix-core products move the gradient by
+    # about one bfloat16 ulp (2^-8) relative, never more than a few percent
+    rng = np.random.default_rng(11)
+    P = mlp.initial_params(rng.uniform(0, 1, mlp.N_PARAMS))
+    X = rng.uniform(0, 1, (128, 8))
+    t = np.sort(rng.uniform(0, 1, 128))
+    _, g = mlp.loss_and_grads(P, X, t)
+    _, gq = mlp.loss_and_grads(P, X, t, bf16_layer2=True, bf16_dz2=True)
+    for k in mlp.PARAM_SHAPES:
+        scale = np.abs(g[k]).max()
+        assert np.abs(gq[k] - g[k]).max() <= 3e-2 * scale, k
+
+
+def test_first_of_leaves():
+    lv = np.array([0, 0, 2, 2, 2, 3, 5])
+    assert list(mlp.first_of_leaves(lv, 6)) == [0, 2, 2, 5, 6, 6, 7]
+
+
+def test_spline_leaves_exact_on_linear_codes():
+    # codes linear in rank: every leaf's spline is the exact CDF, so the bucket
+    # of sample s is floor(B s / S), or one less where B s / S is an integer
+    # and the FP32 line lands just below it
+    S, B, L = 4096, 64, 8
+    codes = (1000 + 7 * np.arange(S)).astype(np.uint64)
+    first = np.arange(L + 1, dtype=np.uint64) * (S // L)
+    m = oracle.spline_leaves(codes, first, B)
+    got = np.array([int(oracle.lib().oracle_leaf_bucket(int(m.base[j]), float(m.c[j]), float(m.b[j]),
+                                                         int(m.lo[j]), int(m.hi[j]), int(codes[s])))
+                    for s in range(S) for j in [s // (S // L)]])
+    want = (B * np.arange(S)) // S
+    exact = (B * np.arange(S)) % S == 0
+    assert np.all(got[~exact] == want[~exact])
+    assert np.all((got[exact] == want[exact]) | (got[exact] == want[exact] - 1))
+
+
+def test_routed_buckets_equal_root_routing():
+    # boundaries read off the linear root's own routing give the same buckets
+    recs = datagen.generate(datagen.spec("zipf", seed=6), 30_000)
+    codes = oracle.sample_codes(recs, seed=6)
+    m = oracle.fit_rmi(codes, 16, 256)
+    allc = oracle.e8_records(recs)
+    leaf = np.array([m.leaf_of(c) for c in allc])
+    bound = np.full(m.L + 1, np.iinfo(np.uint64).max, dtype=np.uint64)
+    for j in range(m.L - 1, -1, -1):
+        sel = allc[leaf >= j]
+        bound[j] = sel.min() if sel.size else bound[j + 1]
+    bound[0] = 0
+    assert np.array_equal(oracle.routed_buckets(recs, bound, m), m.buckets(recs))
