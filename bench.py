@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform-100M", choices=sorted(WORKLOADS))
     ap.add_argument("--model", default="rmi", choices=["rmi", "mlp", "auto"])
+    ap.add_argument("--leaves", type=int, default=0, help="RMI leaves L (0: buckets / 16)")
+    ap.add_argument("--mlp-steps", type=int, default=0, help="Adam steps of the MLP fit (0: library default)")
+    ap.add_argument("--accept-ratio", type=float, default=1.5,
+                    help="MLP acceptance: largest sample bucket <= ratio * ideal")
     ap.add_argument("--cpu-records", type=int, default=16_000_000,
                     help="records of the bounded CPU-baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
@@ -115,7 +119,8 @@ def main():
     wl = WORKLOADS[args.workload]
     n = wl["n"]
     kind = {"rmi": elsar.RMI, "mlp": elsar.MLP, "auto": elsar.AUTO}[args.model]
-    params = elsar.fit_params(num_buckets=wl["buckets"], seed=wl["seed"], kind=kind)
+    params = elsar.fit_params(num_buckets=wl["buckets"], num_leaves=args.leaves, seed=wl["seed"], kind=kind,
+                              mlp_steps=args.mlp_steps, accept_ratio=args.accept_ratio)
 
     host = torch.empty(n * RECORD_BYTES, dtype=torch.uint8, pin_memory=True)
     datagen.generate_into(datagen.spec(wl["kind"], seed=wl["seed"]), host.data_ptr(), 0, n)
@@ -177,6 +182,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "records": n, "record_bytes": RECORD_BYTES, "buckets": wl["buckets"],
                    "model": args.model, "model_used": ["rmi", "mlp"][info.kind_used],
+                   "leaves": info.num_leaves, "sample": info.sample_size,
+                   "max_sample_bucket": info.max_sample_bucket, "ideal_sample_bucket": info.opt_sample_bucket,
                    "parallelism": "single GPU"},
         "algorithmic_GBps": round(2 * PASS_BYTES * n / (ms_per_step * 1e-3) / 1e9, 1),
         "hbm_frac_whole_path": round(2 * PASS_BYTES * n / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

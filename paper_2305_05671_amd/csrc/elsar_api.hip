@@ -127,6 +127,13 @@ PartLayout part_layout(uint64_t n, uint32_t B, uint32_t R, uint32_t region_pct) 
   lay.big_list = take((size_t)B * 4);
   lay.spill_meta = take((size_t)n * 8);
   lay.spill_map = take((size_t)n * 4);
+  // split of buckets above the LDS caps: every split of c entries gives at most
+  // 3c / 2048 + 1 segments, one split per composite byte and level
+  lay.seg_leaf_cap = (uint32_t)std::min<uint64_t>(n / 32 + 4096, 0xFFFFFFFFull);
+  lay.seg_next_cap = (uint32_t)std::min<uint64_t>(n / 2048 + 1024, 0xFFFFFFFFull);
+  lay.seg_leaf = take((size_t)lay.seg_leaf_cap * 16);
+  lay.seg_next[0] = take((size_t)lay.seg_next_cap * 16);
+  lay.seg_next[1] = take((size_t)lay.seg_next_cap * 16);
   // regions: sum_j ceil(f * max(n h_j / S, n / B)) + 17 <= 2 f n + 18 B,  f = region_pct / 100
   lay.cap_slots = (n * 2 * region_pct + 99) / 100 + 18ull * B + 16;
   lay.total_slots = lay.cap_slots + n;
@@ -217,11 +224,11 @@ elsar_status do_partition(const elsar_model* m, const void* d_records, uint64_t 
   return ELSAR_OK;
 }
 
-elsar_status do_sort_buckets(const elsar_model* m, const void* d_part, size_t part_bytes, uint64_t n,
+elsar_status do_sort_buckets(const elsar_model* m, void* d_part, size_t part_bytes, uint64_t n,
                              const uint64_t* d_offsets, void* d_out, hipStream_t st, PhaseMarks* pm) {
   PartLayout lay = part_layout(n, m->B, m->p.record_bytes, m->p.region_pct);
   if (part_bytes < lay.bytes) return ELSAR_E_NO_MEMORY;
-  const uint8_t* part = static_cast<const uint8_t*>(d_part);
+  uint8_t* part = static_cast<uint8_t*>(d_part);
   uint8_t* out = static_cast<uint8_t*>(d_out);
   HIP_TRY(launch_bucket_sort_small(part, lay, m->B, d_offsets, m->p.record_bytes, m->p.key_bytes, out, st));
   if (pm) mark(*pm, 4, st);
@@ -338,7 +345,7 @@ elsar_status elsar_partition(const elsar_model* m, const void* d_records, uint64
   return s;
 }
 
-elsar_status elsar_sort_buckets(const elsar_model* m, const void* d_part, size_t part_bytes, uint64_t n,
+elsar_status elsar_sort_buckets(const elsar_model* m, void* d_part, size_t part_bytes, uint64_t n,
                                 const uint64_t* d_bucket_offsets, void* d_out, hipStream_t stream) {
   if (!m || !d_part || !d_bucket_offsets) return ELSAR_E_INVALID_ARG;
   if (n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;

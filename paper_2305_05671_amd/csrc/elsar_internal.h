@@ -72,13 +72,16 @@ struct PartHeader {    // device-resident state of one partition pass
   uint32_t max_count;
   uint32_t mid_records;  // records in the n_mid buckets
   uint32_t big_records;  // records in the n_big buckets
-  uint32_t pad[7];
+  uint32_t seg_n[4];     // split of the n_big buckets: segments, next-level pieces (2), spare
+  uint32_t pad[3];
 };
 
 // Byte offsets of the partition buffer's parts for n records and B buckets.
 struct PartLayout {
   size_t header, counts, caps, rstart, spill_off, mid_list, big_list;
   size_t spill_meta, spill_map, slots;
+  size_t seg_leaf, seg_next[2];  // segment lists of the big-bucket split
+  uint32_t seg_leaf_cap, seg_next_cap;
   uint64_t cap_slots;   // region slots
   uint64_t total_slots; // regions + spill
   size_t bytes;
@@ -263,9 +266,9 @@ hipError_t launch_scan_counts(uint8_t* part, const PartLayout& lay, uint32_t B, 
 hipError_t launch_spill_fixup(uint8_t* part, const PartLayout& lay, uint64_t n, hipStream_t st);
 
 // bucket sort (k_bucket_sort.hip)
-hipError_t launch_bucket_sort_small(const uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
+hipError_t launch_bucket_sort_small(uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
                                     uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st);
-hipError_t launch_bucket_sort_large(const uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
+hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
                                     uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st);
 
 }  // namespace elsar

@@ -191,6 +191,68 @@ constexpr uint32_t kSmBits = 11;     // counting-sort digit: 2048 bins of the bu
 constexpr uint32_t kSmGroup = 7;     // gathered chunks in flight per thread
 constexpr uint32_t kRunMax = 32;     // longest bin sorted by insertion
 
+// Steps after the digits: the digit of entry p is in perm[1][p] (2^kSmBits
+// bins, non-decreasing in the composite).  A counting pass on the digit, then
+// insertion sort by the whole composite inside each bin, or stable LSD passes
+// over every varying composite byte when a bin is longer than kRunMax.
+// Returns the perm buffer that holds the sorted order.
+__device__ __forceinline__ uint32_t small_sort_core(uint32_t n, uint32_t vary, uint32_t (*cw)[kSmCap], uint16_t (*perm)[kSmCap],
+                                    uint32_t* bins, uint32_t* sh_scan, uint32_t* tot) {
+  const uint32_t tid = threadIdx.x;
+  const uint16_t* dig = perm[1];
+  auto less = [&](uint32_t x, uint32_t y) -> bool {
+    if (cw[0][x] != cw[0][y]) return cw[0][x] < cw[0][y];
+    if (cw[1][x] != cw[1][y]) return cw[1][x] < cw[1][y];
+    if (cw[2][x] != cw[2][y]) return cw[2][x] < cw[2][y];
+    return cw[3][x] < cw[3][y];
+  };
+  __syncthreads();
+  for (uint32_t p = tid; p < n; p += kSmThreads) atomicAdd(&bins[dig[p]], 1u);
+  __syncthreads();
+  {  // exclusive scan of the bins: PER contiguous per thread
+    constexpr uint32_t PER = (1u << kSmBits) / kSmThreads;
+    uint32_t c[PER], sum = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < PER; ++i) { c[i] = bins[tid * PER + i]; sum += c[i]; }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan<uint32_t, kSmThreads>(sum, sh_scan, &total);
+#pragma unroll
+    for (uint32_t i = 0; i < PER; ++i) { bins[tid * PER + i] = run; run += c[i]; }
+  }
+  __syncthreads();
+  for (uint32_t p = tid; p < n; p += kSmThreads) perm[0][atomicAdd(&bins[dig[p]], 1u)] = (uint16_t)p;
+  __syncthreads();
+  // bins[b] is now the end of bin b; the start is the end of bin b-1
+  bool long_bin = false;
+  for (uint32_t b = tid; b < (1u << kSmBits); b += kSmThreads) {
+    uint32_t s0 = b ? bins[b - 1] : 0u, s1 = bins[b];
+    if (s1 - s0 < 2) continue;
+    if (s1 - s0 > kRunMax) { long_bin = true; continue; }
+    for (uint32_t x = s0 + 1; x < s1; ++x) {  // insertion sort by the whole composite
+      uint16_t e = perm[0][x];
+      uint32_t y = x;
+      while (y > s0 && less(e, perm[0][y - 1])) {
+        perm[0][y] = perm[0][y - 1];
+        --y;
+      }
+      perm[0][y] = e;
+    }
+  }
+  long_bin = __syncthreads_or(long_bin);
+  uint32_t cur = 0;
+  if (long_bin) {  // stable LSD over every varying composite byte
+    auto wc = reinterpret_cast<uint32_t(*)[256]>(bins);
+    for (int pb = 15; pb >= 0; --pb) {
+      if (!((vary >> pb) & 1u)) continue;
+      lsd_pass<kSmCap, kSmThreads>(perm, cur, n, wc, tot, [&](uint32_t e) {
+        return (cw[pb >> 2][e] >> (24 - 8 * (pb & 3))) & 0xFFu;
+      });
+      cur ^= 1;
+    }
+  }
+  return cur;
+}
+
 template <uint32_t RW>  // record dwords
 __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
@@ -246,12 +308,6 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
   const uint4 diff = block_diff<kSmThreads>(o, a, sh_or, sh_and);
   const uint32_t vary = vary_mask(diff);
   block_min_max_u64<kSmThreads>(cmin, cmax, sh_mm);
-  auto less = [&](uint32_t x, uint32_t y) -> bool {
-    if (cw[0][x] != cw[0][y]) return cw[0][x] < cw[0][y];
-    if (cw[1][x] != cw[1][y]) return cw[1][x] < cw[1][y];
-    if (cw[2][x] != cw[2][y]) return cw[2][x] < cw[2][y];
-    return cw[3][x] < cw[3][y];
-  };
   uint32_t cur = 0;
   if (n == 1) {
     if (tid == 0) perm[0][0] = 0;
@@ -273,49 +329,7 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
         dig[p] = (uint16_t)(d < (1u << kSmBits) ? d : (1u << kSmBits) - 1);
       }
     }
-    __syncthreads();
-    for (uint32_t p = tid; p < n; p += kSmThreads) atomicAdd(&bins[dig[p]], 1u);
-    __syncthreads();
-    {  // exclusive scan of the bins: PER contiguous per thread
-      constexpr uint32_t PER = (1u << kSmBits) / kSmThreads;
-      uint32_t c[PER], sum = 0;
-#pragma unroll
-      for (uint32_t i = 0; i < PER; ++i) { c[i] = bins[tid * PER + i]; sum += c[i]; }
-      uint32_t total;
-      uint32_t run = block_exclusive_scan<uint32_t, kSmThreads>(sum, sh_scan, &total);
-#pragma unroll
-      for (uint32_t i = 0; i < PER; ++i) { bins[tid * PER + i] = run; run += c[i]; }
-    }
-    __syncthreads();
-    for (uint32_t p = tid; p < n; p += kSmThreads) perm[0][atomicAdd(&bins[dig[p]], 1u)] = (uint16_t)p;
-    __syncthreads();
-    // bins[b] is now the end of bin b; the start is the end of bin b-1
-    bool long_bin = false;
-    for (uint32_t b = tid; b < (1u << kSmBits); b += kSmThreads) {
-      uint32_t s0 = b ? bins[b - 1] : 0u, s1 = bins[b];
-      if (s1 - s0 < 2) continue;
-      if (s1 - s0 > kRunMax) { long_bin = true; continue; }
-      for (uint32_t x = s0 + 1; x < s1; ++x) {  // insertion sort by the whole composite
-        uint16_t e = perm[0][x];
-        uint32_t y = x;
-        while (y > s0 && less(e, perm[0][y - 1])) {
-          perm[0][y] = perm[0][y - 1];
-          --y;
-        }
-        perm[0][y] = e;
-      }
-    }
-    long_bin = __syncthreads_or(long_bin);
-    if (long_bin) {  // stable LSD over every varying composite byte
-      auto wc = reinterpret_cast<uint32_t(*)[256]>(bins);
-      for (int pb = 15; pb >= 0; --pb) {
-        if (!((vary >> pb) & 1u)) continue;
-        lsd_pass<kSmCap, kSmThreads>(perm, cur, n, wc, tot, [&](uint32_t e) {
-          return (cw[pb >> 2][e] >> (24 - 8 * (pb & 3))) & 0xFFu;
-        });
-        cur ^= 1;
-      }
-    }
+    cur = small_sort_core(n, vary, cw, perm, bins, sh_scan, tot);
   }
   __syncthreads();
   // 3. gather the records in sorted order straight into the output: lane q
@@ -554,6 +568,295 @@ __global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
   }
 }
 
+// ---------------------------------- buckets above the LDS caps: MSD split --
+// A bucket of more than kMidCap records is split, most significant varying
+// composite byte first, into pieces that the small-bucket sort can finish:
+//  * msd_first: per bucket, its entries {composite, slot} go to buffer B and
+//    are scattered by the first varying byte into buffer A.
+//  * msd_split (repeated): a piece still larger than kSegCap is scattered by
+//    its own first varying byte into the other buffer.
+//  Consecutive digits whose pieces fit kSegCap together form one segment; a
+//  segment only needs sorting within itself.
+//  * seg_sort: each segment sorted in LDS as a small bucket; its slot numbers
+//    go, in sorted order, to the bucket's reference list.
+//  * big_gather: each bucket's records copied out in the order of its list.
+// Buffers live in the bucket's own output range (R*n bytes, not written yet):
+// A = [0, 20n), B = [20n, 40n), reference list = [(R-4)n, Rn), R >= 44.  The
+// gather reads list chunk k0.. before writing records k0.., and record k ends
+// at byte R(k+1) <= (R-4)n + 4(k+1) only for k = n-1, inside its own chunk.
+constexpr uint32_t kSegCap = kSmallCap;
+constexpr uint32_t kMsdThreads = 1024;
+constexpr uint32_t kMsdWaves = kMsdThreads / 64;
+
+__device__ __forceinline__ uint32_t first_varying_byte(uint32_t vary) {  // vary != 0
+  return (uint32_t)__builtin_ctz(vary);  // bit p = composite byte p, byte 0 most significant
+}
+
+struct MsdShared {
+  uint32_t hist[256];
+  uint32_t base[256];
+  uint32_t cursor[256];
+  uint4 sh_or[kMsdWaves], sh_and[kMsdWaves];
+  uint32_t sh_scan[kMsdWaves + 1];
+};
+
+// Scatter X[s, s+c) into Y[s, s+c) by composite byte p (digit order, any
+// order within a digit) and record the pieces: runs of whole digits of at
+// most kSegCap entries become segments, larger digits go to the next level.
+__device__ void msd_scatter(MsdShared& sh, const uint32_t* __restrict__ X, uint32_t* __restrict__ Y, uint32_t j,
+                            uint32_t s, uint32_t c, uint32_t p, uint32_t yflag, uint4* __restrict__ leaf,
+                            uint32_t* __restrict__ leaf_n, uint32_t leaf_cap, uint4* __restrict__ next,
+                            uint32_t* __restrict__ next_n, uint32_t next_cap) {
+  const uint32_t tid = threadIdx.x;
+  if (tid < 256) sh.hist[tid] = 0;
+  __syncthreads();
+  for (uint32_t i0 = 0; i0 < c; i0 += kMsdThreads) {
+    const uint32_t i = i0 + tid;
+    const bool valid = i < c;
+    const uint32_t d = valid ? digit_of(get_key(X, s + i), p) : 0u;
+    const uint64_t peers = match_digit8(d, valid);
+    if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&sh.hist[d], (uint32_t)__popcll(peers));
+  }
+  __syncthreads();
+  // exclusive scan of the 256 digit counts by the first four waves
+  if (tid < 256) {
+    const uint32_t v = sh.hist[tid];
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off);
+      if (lane_id() >= (uint32_t)off) x += y;
+    }
+    if (lane_id() == 63) sh.sh_scan[tid >> 6] = x;
+    sh.base[tid] = x - v;
+  }
+  __syncthreads();
+  if (tid < 256) {
+    uint32_t add = 0;
+    for (uint32_t q = 0; q < (tid >> 6); ++q) add += sh.sh_scan[q];
+    sh.base[tid] += add;
+    sh.cursor[tid] = sh.base[tid];
+  }
+  __syncthreads();
+  for (uint32_t i0 = 0; i0 < c; i0 += kMsdThreads) {
+    const uint32_t i = i0 + tid;
+    const bool valid = i < c;
+    uint32_t e0 = 0, e1 = 0, e2 = 0, e3 = 0, e4 = 0, d = 0;
+    if (valid) {
+      const uint32_t* src = X + 5ull * (s + i);
+      e0 = src[0]; e1 = src[1]; e2 = src[2]; e3 = src[3]; e4 = src[4];
+      d = digit_of(make_uint4(e0, e1, e2, e3), p);
+    }
+    const uint64_t peers = match_digit8(d, valid);
+    const uint32_t leader = peers ? (uint32_t)__builtin_ctzll(peers) : 0u;
+    uint32_t got = 0;
+    if (valid && lane_id() == leader) got = atomicAdd(&sh.cursor[d], (uint32_t)__popcll(peers));
+    got = __shfl(got, (int)leader);
+    if (valid) {
+      uint32_t* dst = Y + 5ull * (s + got + (uint32_t)__popcll(peers & lanemask_lt()));
+      dst[0] = e0; dst[1] = e1; dst[2] = e2; dst[3] = e3; dst[4] = e4;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {  // pieces, in digit order
+    uint32_t run_s = 0, run_c = 0;
+    auto flush = [&]() {
+      if (run_c) {
+        const uint32_t q = atomicAdd(leaf_n, 1u);
+        if (q < leaf_cap) leaf[q] = make_uint4(j, s + run_s, run_c, yflag);
+      }
+      run_c = 0;
+    };
+    for (uint32_t d = 0; d < 256; ++d) {
+      const uint32_t cd = sh.hist[d], bd = sh.base[d];
+      if (cd == 0) continue;
+      if (cd > kSegCap) {
+        flush();
+        const uint32_t q = atomicAdd(next_n, 1u);
+        if (q < next_cap) next[q] = make_uint4(j, s + bd, cd, yflag);
+        continue;
+      }
+      if (run_c + cd > kSegCap) flush();
+      if (run_c == 0) run_s = bd;
+      run_c += cd;
+    }
+    flush();
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void bucket_bufs(uint32_t* out, uint64_t out0, uint32_t n, uint32_t RW, uint32_t** A,
+                                            uint32_t** B) {
+  uint32_t* o_dw = out + out0 * RW;
+  *A = o_dw;
+  *B = o_dw + 5ull * n;
+}
+
+__global__ __launch_bounds__(kMsdThreads) void msd_first_kernel(
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
+    const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
+    const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
+    uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
+    uint4* __restrict__ leaf, uint32_t* __restrict__ leaf_n, uint32_t leaf_cap, uint4* __restrict__ next,
+    uint32_t* __restrict__ next_n, uint32_t next_cap) {
+  __shared__ MsdShared sh;
+  const uint32_t W = slot_bytes_for(RW * 4) / 4;
+  const uint32_t nitems = *list_n;
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const uint32_t j = list[it];
+    BucketRef br;
+    br.n = counts[j];
+    const uint32_t cap = caps[j];
+    br.nr = br.n < cap ? br.n : cap;
+    br.rs = rstart[j];
+    br.so = spill_off[j];
+    br.out0 = offsets[j];
+    uint32_t *A, *Bf;
+    bucket_bufs(out, br.out0, br.n, RW, &A, &Bf);
+    uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
+    for (uint32_t q = threadIdx.x; q < br.n; q += kMsdThreads) {
+      const uint32_t sl = slot_of(br, q, spill_map, cap_slots);
+      const uint4 c = composite(slots + (uint64_t)sl * W, RW, K);
+      put_entry(Bf, q, c, sl);
+      o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
+      a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+    }
+    const uint32_t vary = varying_bytes<kMsdThreads>(o, a, sh.sh_or, sh.sh_and);  // syncs
+    msd_scatter(sh, Bf, A, j, 0, br.n, first_varying_byte(vary), 0u, leaf, leaf_n, leaf_cap, next, next_n,
+                next_cap);
+  }
+}
+
+__global__ __launch_bounds__(kMsdThreads) void msd_split_kernel(
+    const uint32_t* __restrict__ counts, const uint64_t* __restrict__ offsets, uint32_t RW, uint32_t* __restrict__ out,
+    const uint4* __restrict__ in, const uint32_t* __restrict__ in_n, uint4* __restrict__ leaf,
+    uint32_t* __restrict__ leaf_n, uint32_t leaf_cap, uint4* __restrict__ next, uint32_t* __restrict__ next_n,
+    uint32_t next_cap) {
+  __shared__ MsdShared sh;
+  const uint32_t nitems = *in_n < next_cap ? *in_n : next_cap;  // the lists share one capacity
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const uint4 sg = in[it];  // bucket, start, count, buffer
+    uint32_t *A, *Bf;
+    bucket_bufs(out, offsets[sg.x], counts[sg.x], RW, &A, &Bf);
+    const uint32_t* X = sg.w ? Bf : A;
+    uint32_t* Y = sg.w ? A : Bf;
+    uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
+    for (uint32_t q = threadIdx.x; q < sg.z; q += kMsdThreads) {
+      const uint4 c = get_key(X, sg.y + q);
+      o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
+      a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+    }
+    const uint32_t vary = varying_bytes<kMsdThreads>(o, a, sh.sh_or, sh.sh_and);
+    msd_scatter(sh, X, Y, sg.x, sg.y, sg.z, first_varying_byte(vary), sg.w ^ 1u, leaf, leaf_n, leaf_cap, next,
+                next_n, next_cap);
+  }
+}
+
+// One segment per block: the small-bucket sort on entries from the buffer;
+// the sorted slot numbers go to the bucket's reference list.
+__global__ __launch_bounds__(kSmThreads) void seg_sort_kernel(const uint32_t* __restrict__ counts,
+                                                              const uint64_t* __restrict__ offsets, uint32_t RW,
+                                                              uint32_t* __restrict__ out,
+                                                              const uint4* __restrict__ segs,
+                                                              const uint32_t* __restrict__ segs_n, uint32_t segs_cap) {
+  constexpr uint32_t AR = kSmCap / kSmThreads;
+  __shared__ uint32_t cw[4][kSmCap];
+  __shared__ uint16_t perm[2][kSmCap];
+  __shared__ uint32_t bins[1u << kSmBits];
+  __shared__ uint4 sh_or[kSmWaves], sh_and[kSmWaves];
+  __shared__ uint32_t sh_scan[kSmThreads / 64 + 1];
+  __shared__ uint64_t sh_mm[2 * kSmWaves];
+  __shared__ uint32_t tot[4];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t nseg = *segs_n < segs_cap ? *segs_n : segs_cap;
+  for (uint32_t it = blockIdx.x; it < nseg; it += gridDim.x) {
+    const uint4 sg = segs[it];
+    const uint32_t nb = counts[sg.x], n = sg.z;
+    uint32_t *A, *Bf;
+    bucket_bufs(out, offsets[sg.x], nb, RW, &A, &Bf);
+    const uint32_t* X = (sg.w ? Bf : A) + 5ull * sg.y;
+    uint32_t* refs = out + offsets[sg.x] * RW + (uint64_t)(RW - 1) * nb + sg.y;
+    uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
+    uint64_t cmin = ~0ull, cmax = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < AR; ++i) {
+      const uint32_t q = tid + i * kSmThreads;
+      if (q < n) {
+        const uint4 c = get_key(X, q);
+        cw[0][q] = c.x; cw[1][q] = c.y; cw[2][q] = c.z; cw[3][q] = c.w;
+        o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
+        a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+        const uint64_t e = key_code(__builtin_bswap32(c.x), __builtin_bswap32(c.y));
+        cmin = e < cmin ? e : cmin;
+        cmax = e > cmax ? e : cmax;
+      }
+    }
+    const uint32_t vary = vary_mask(block_diff<kSmThreads>(o, a, sh_or, sh_and));
+    block_min_max_u64<kSmThreads>(cmin, cmax, sh_mm);
+    uint32_t cur = 0;
+    if (n == 1) {
+      if (tid == 0) perm[0][0] = 0;
+    } else {
+      const double scale = (double)(1u << kSmBits) / ((double)(cmax - cmin) + 1.0);
+      for (uint32_t i = tid; i < (1u << kSmBits); i += kSmThreads) bins[i] = 0;
+      for (uint32_t q = tid; q < n; q += kSmThreads) {
+        const uint64_t e = key_code(__builtin_bswap32(cw[0][q]), __builtin_bswap32(cw[1][q]));
+        const uint32_t d = (uint32_t)((double)(e - cmin) * scale);
+        perm[1][q] = (uint16_t)(d < (1u << kSmBits) ? d : (1u << kSmBits) - 1);
+      }
+      cur = small_sort_core(n, vary, cw, perm, bins, sh_scan, tot);
+    }
+    __syncthreads();
+    for (uint32_t k = tid; k < n; k += kSmThreads) refs[k] = X[5ull * perm[cur][k] + 4];
+    __syncthreads();
+  }
+}
+
+// Each bucket's records in the order of its reference list: lane q moves
+// 16-byte chunk q % LC of record q / LC (one slot line per record).
+constexpr uint32_t kGatherChunk = 4096;
+
+__global__ __launch_bounds__(kMsdThreads) void big_gather_kernel(const uint32_t* __restrict__ counts,
+                                                                 const uint64_t* __restrict__ offsets, uint32_t RW,
+                                                                 const uint4* __restrict__ slots,
+                                                                 uint32_t* __restrict__ out,
+                                                                 const uint32_t* __restrict__ list,
+                                                                 const uint32_t* __restrict__ list_n) {
+  __shared__ uint32_t chunk_slot[kGatherChunk];
+  const uint32_t SC = slot_bytes_for(RW * 4) / 16;
+  const uint32_t LC = (RW + 1 + 3) / 4;
+  const uint32_t nitems = *list_n;
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const uint32_t j = list[it], n = counts[j];
+    uint32_t* o_dw = out + offsets[j] * RW;
+    const uint32_t* refs = o_dw + (uint64_t)(RW - 1) * n;
+    for (uint32_t k0 = 0; k0 < n; k0 += kGatherChunk) {
+      const uint32_t m = n - k0 < kGatherChunk ? n - k0 : kGatherChunk;
+      for (uint32_t i = threadIdx.x; i < m; i += kMsdThreads) chunk_slot[i] = refs[k0 + i];
+      __syncthreads();
+      const uint32_t nq = m * LC;
+      for (uint32_t q = threadIdx.x; q < nq; q += kMsdThreads) {
+        const uint32_t k = q / LC, c = q - k * LC;
+        const u32x4 g = reinterpret_cast<const u32x4*>(slots)[(uint64_t)chunk_slot[k] * SC + c];
+        uint32_t* o = o_dw + (uint64_t)(k0 + k) * RW;
+#pragma unroll
+        for (uint32_t t = 0; t < 4; ++t) {
+          const uint32_t sd = 4 * c + t;  // slot dword: 0 is the index, 1..RW the record
+          if (sd >= 1 && sd <= RW) o[sd - 1] = g[t];
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void msd_reset_kernel(PartHeader* __restrict__ ph) {
+  if (threadIdx.x < 4) ph->seg_n[threadIdx.x] = 0;
+}
+
+__global__ void msd_clear_kernel(uint32_t* __restrict__ c) {
+  if (threadIdx.x == 0) *c = 0;
+}
+
 struct SortArgs {
   const uint32_t *counts, *caps, *rstart, *soff, *smap, *slots;
   const PartHeader* ph;
@@ -575,7 +878,7 @@ static SortArgs sort_args(const uint8_t* part, const PartLayout& lay, uint32_t r
   return a;
 }
 
-hipError_t launch_bucket_sort_small(const uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
+hipError_t launch_bucket_sort_small(uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
                                     uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st) {
   SortArgs a = sort_args(part, lay, rec_bytes, out);
   if (rec_bytes == 100) {
@@ -590,16 +893,39 @@ hipError_t launch_bucket_sort_small(const uint8_t* part, const PartLayout& lay, 
   return hipGetLastError();
 }
 
-hipError_t launch_bucket_sort_large(const uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
+hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
                                     uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st) {
   SortArgs a = sort_args(part, lay, rec_bytes, out);
   bucket_sort_lds_kernel<kMidCap, 512><<<256, 512, 0, st>>>(
       a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
       reinterpret_cast<const uint32_t*>(part + lay.mid_list), &a.ph->n_mid, B);
-  bucket_sort_global_kernel<<<256, kBigThreads, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots,
-                                                         lay.cap_slots, offsets, a.RW, key_bytes, a.out,
-                                                         reinterpret_cast<const uint32_t*>(part + lay.big_list),
-                                                         &a.ph->n_big);
+  const uint32_t* big_list = reinterpret_cast<const uint32_t*>(part + lay.big_list);
+  if (rec_bytes < 44) {  // no room for the split's buffers beside the reference list
+    bucket_sort_global_kernel<<<256, kBigThreads, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots,
+                                                           lay.cap_slots, offsets, a.RW, key_bytes, a.out, big_list,
+                                                           &a.ph->n_big);
+    return hipGetLastError();
+  }
+  PartHeader* ph = reinterpret_cast<PartHeader*>(part + lay.header);
+  uint4* leaf = reinterpret_cast<uint4*>(part + lay.seg_leaf);
+  uint4* nxt[2] = {reinterpret_cast<uint4*>(part + lay.seg_next[0]), reinterpret_cast<uint4*>(part + lay.seg_next[1])};
+  uint32_t* leaf_n = &ph->seg_n[0];
+  uint32_t* next_n[2] = {&ph->seg_n[1], &ph->seg_n[2]};
+  const uint32_t leaf_cap = lay.seg_leaf_cap, next_cap = lay.seg_next_cap;
+  msd_reset_kernel<<<1, 64, 0, st>>>(ph);
+  msd_first_kernel<<<512, kMsdThreads, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots,
+                                                offsets, a.RW, key_bytes, a.out, big_list, &a.ph->n_big, leaf,
+                                                leaf_n, leaf_cap, nxt[0], next_n[0], next_cap);
+  // each split fixes one more composite byte: at most key_bytes + 3 further levels
+  for (uint32_t lev = 1; lev < key_bytes + 4; ++lev) {
+    const uint32_t in = (lev - 1) & 1u, o = lev & 1u;
+    msd_clear_kernel<<<1, 64, 0, st>>>(next_n[o]);
+    msd_split_kernel<<<512, kMsdThreads, 0, st>>>(a.counts, offsets, a.RW, a.out, nxt[in], next_n[in], leaf, leaf_n,
+                                                  leaf_cap, nxt[o], next_n[o], next_cap);
+  }
+  seg_sort_kernel<<<2048, kSmThreads, 0, st>>>(a.counts, offsets, a.RW, a.out, leaf, leaf_n, leaf_cap);
+  big_gather_kernel<<<512, kMsdThreads, 0, st>>>(a.counts, offsets, a.RW, reinterpret_cast<const uint4*>(a.slots),
+                                                 a.out, big_list, &a.ph->n_big);
   return hipGetLastError();
 }
 

@@ -280,7 +280,11 @@ __device__ void clear_grad(TrainLds& sm) {
 
 // All training steps in one block: per step kRows sample positions drawn with
 // Philox, the gradient, then Adam (beta1 0.9, beta2 0.999, eps 1e-8) with
-// W1, W2, w3 projected onto >= 0, and a fresh evaluation copy.
+// W1, W2, w3 projected onto >= 0, and a fresh evaluation copy.  Thread t owns
+// parameters t, t + 256, ...: their FP32 values and Adam moments stay in its
+// registers for the whole fit.
+constexpr uint32_t kOwn = (kMlpParams + kTrainThreads - 1) / kTrainThreads;
+
 __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(const uint64_t* __restrict__ e, uint64_t S,
                                                                   uint32_t steps, float lr, uint64_t seed,
                                                                   float* __restrict__ master,
@@ -290,8 +294,15 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(const uint64_t
   TrainLds& sm = *reinterpret_cast<TrainLds*>(lds_raw);
   const uint32_t tid = threadIdx.x;
   load_block(Mout, sm.M);
-  float* m1 = adam;
-  float* m2 = adam + kMlpParams;
+  float pv[kOwn], a1[kOwn], a2[kOwn];
+#pragma unroll
+  for (uint32_t k = 0; k < kOwn; ++k) {
+    const uint32_t p = tid + k * kTrainThreads;
+    const bool ok = p < kMlpParams;
+    pv[k] = ok ? master[p] : 0.0f;
+    a1[k] = ok ? adam[p] : 0.0f;
+    a2[k] = ok ? adam[kMlpParams + p] : 0.0f;
+  }
   float p1 = 1.0f, p2 = 1.0f;  // beta^step
   __syncthreads();
   for (uint32_t step = 1; step <= steps; ++step) {
@@ -310,24 +321,35 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(const uint64_t
     p1 *= 0.9f;
     p2 *= 0.999f;
     const float c1 = 1.0f / (1.0f - p1), c2 = 1.0f / (1.0f - p2);
-    for (uint32_t p = tid; p < kMlpParams; p += kTrainThreads) {
-      const float gr = sm.G[p];
-      const float a1 = 0.9f * m1[p] + 0.1f * gr;
-      const float a2 = 0.999f * m2[p] + 0.001f * gr * gr;
-      m1[p] = a1;
-      m2[p] = a2;
-      float v = master[p] - lr * (a1 * c1) / (sqrtf(a2 * c2) + 1e-8f);
-      const bool nonneg = p < kOffB1 || (p >= kOffW2 && p < kOffB2) || (p >= kOffW3 && p < kOffB3);
-      if (nonneg) v = fmaxf(v, 0.0f);
-      master[p] = v;
-      publish_one(p, v, &sm.M);
+#pragma unroll
+    for (uint32_t k = 0; k < kOwn; ++k) {
+      const uint32_t p = tid + k * kTrainThreads;
+      if (p < kMlpParams) {
+        const float gr = sm.G[p];
+        a1[k] = 0.9f * a1[k] + 0.1f * gr;
+        a2[k] = 0.999f * a2[k] + 0.001f * gr * gr;
+        float v = pv[k] - lr * (a1[k] * c1) / (sqrtf(a2[k] * c2) + 1e-8f);
+        const bool nonneg = p < kOffB1 || (p >= kOffW2 && p < kOffB2) || (p >= kOffW3 && p < kOffB3);
+        if (nonneg) v = fmaxf(v, 0.0f);
+        pv[k] = v;
+        publish_one(p, v, &sm.M);
+      }
     }
     __syncthreads();
   }
+#pragma unroll
+  for (uint32_t k = 0; k < kOwn; ++k) {
+    const uint32_t p = tid + k * kTrainThreads;
+    if (p < kMlpParams) {
+      master[p] = pv[k];
+      adam[p] = a1[k];
+      adam[kMlpParams + p] = a2[k];
+    }
+  }
   // the knots were in the copy loaded at the start; write everything back
-  const uint32_t* s = reinterpret_cast<const uint32_t*>(&sm.M);
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&sm.M);
   uint32_t* d = reinterpret_cast<uint32_t*>(Mout);
-  for (uint32_t i = tid; i < sizeof(MlpBlock) / 4; i += kTrainThreads) d[i] = s[i];
+  for (uint32_t i = tid; i < sizeof(MlpBlock) / 4; i += kTrainThreads) d[i] = src[i];
 }
 
 // One gradient on caller-supplied rows (codes and targets), for verification.

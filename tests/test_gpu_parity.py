@@ -183,3 +183,25 @@ def test_other_record_shapes(env, R, K):
     out = elsar.elsar_sort(d, params=elsar.fit_params(record_bytes=R, key_bytes=K, num_buckets=64))
     torch.cuda.synchronize()
     _assert_same(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs, key_bytes=K))
+
+
+@pytest.mark.parametrize("kind,n,B,seed,region", [
+    ("skewed", 1_000_000, 64, 21, 0),      # every bucket far above the LDS caps; hot keys
+    ("zipf", 600_000, 16, 22, 0),          # few huge buckets, long shared prefixes
+    ("uniform", 400_000, 8, 23, 1),        # huge buckets mostly in the spill area
+])
+def test_big_buckets_split(env, kind, n, B, seed, region):
+    recs = datagen.generate(datagen.spec(kind, seed=seed), n)
+    _assert_same(_gpu_sort(env, recs, num_buckets=B, seed=seed, region_pct=region), oracle.sort_records(recs))
+
+
+def test_big_bucket_equal_keys_and_prefixes(env):
+    # one bucket: 30k copies of one key, 30k keys sharing 9 of 10 bytes, and
+    # 30k sharing the first 8 bytes (beyond the 8-byte code)
+    recs = datagen.generate(datagen.spec("uniform", seed=24, embed_idx=True), 90_000)
+    recs[:30_000, :K] = np.frombuffer(b"HOTKEY!!!!", np.uint8)
+    recs[30_000:60_000, :9] = np.frombuffer(b"PREFIX9!!", np.uint8)
+    recs[60_000:, :8] = np.frombuffer(b"PREFIX8!", np.uint8)
+    rng = np.random.default_rng(24)
+    recs = recs[rng.permutation(recs.shape[0])]
+    _assert_same(_gpu_sort(env, recs, num_buckets=1), oracle.sort_records(recs))
