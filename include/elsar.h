@@ -147,6 +147,34 @@ elsar_status elsar_sort_workspace_size(const elsar_fit_params* p, uint64_t n, si
 elsar_status elsar_sort(const void* d_in, uint64_t n, void* d_out, const elsar_fit_params* p, void* d_ws,
                         size_t ws_bytes, hipStream_t stream);
 
+/* One job of a batch: n records at d_in, sorted into d_out (may equal d_in). */
+typedef struct {
+  const void* d_in;
+  void* d_out;
+  uint64_t n;
+} elsar_job;
+
+/* Workspace of elsar_sort_batch for this job table and parameters. */
+elsar_status elsar_sort_batch_workspace_size(const elsar_job* h_jobs, uint32_t njobs, const elsar_fit_params* p,
+                                             size_t* bytes);
+
+/*
+ * Independent sorts of many jobs of uneven sizes in one launch (the method
+ * applied per job; uneven work is balanced the way the paper balances uneven
+ * partitions over threads with dynamic scheduling, Section 7.3, here over
+ * jobs and concurrent lanes).  h_jobs: host array of njobs jobs.  p applies to every job, except
+ * that num_buckets / num_leaves of 0 are chosen per job from the tuned table,
+ * and job j's sampler seed is p->seed + j.  Jobs of up to 2048 records are
+ * sorted whole, one block each, in a single kernel; the others run the full
+ * pipeline on four concurrent lanes, each lane reusing one slice of d_ws
+ * sized for its largest job (scratch is bounded by four jobs, not by the
+ * batch).  The first call with a given (table, parameters, workspace) records
+ * the whole batch as one HIP graph; that call and every later one with the
+ * same arguments is a single graph launch on `stream`.  Asynchronous.
+ */
+elsar_status elsar_sort_batch(const elsar_job* h_jobs, uint32_t njobs, const elsar_fit_params* p, void* d_ws,
+                              size_t ws_bytes, hipStream_t stream);
+
 /* What a fitted model looks like; synchronises with the device. */
 typedef struct {
   uint32_t kind_used;        /* elsar_model_kind actually in use (RMI or MLP) */

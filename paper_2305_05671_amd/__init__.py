@@ -81,6 +81,10 @@ class Timings(ctypes.Structure):
     ]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("d_in", ctypes.c_void_p), ("d_out", ctypes.c_void_p), ("n", ctypes.c_uint64)]
+
+
 class ElsarError(RuntimeError):
     def __init__(self, fn: str, status: int):
         super().__init__(f"{fn} failed: {status_string(status)} ({status})")
@@ -116,6 +120,9 @@ def lib():
             "elsar_model_leaves": ([_P, _P, _P, _P, _P, _P], st),
             "elsar_partition_stats_get": ([_P, _P, _SZ, ctypes.POINTER(PartitionStats)], st),
             "elsar_model_mlp_get": ([_P, _P, _P, _P, _P], st),
+            "elsar_sort_batch_workspace_size": ([ctypes.POINTER(Job), ctypes.c_uint32, ctypes.POINTER(FitParams),
+                                                 ctypes.POINTER(_SZ)], st),
+            "elsar_sort_batch": ([ctypes.POINTER(Job), ctypes.c_uint32, ctypes.POINTER(FitParams), _P, _SZ, _P], st),
             "elsar_mlp_forward": ([_P, _P, _P, _U64, _P], st),
             "elsar_mlp_gradient": ([_P, _P, _P, _P, _P, _P], st),
             "elsar_set_timing": ([ctypes.c_int], st),
@@ -193,6 +200,46 @@ def elsar_sort(records, out=None, params: FitParams | None = None, workspace=Non
     _check("elsar_sort", lib().elsar_sort(records.data_ptr(), n, out.data_ptr(), ctypes.byref(params),
                                           workspace.data_ptr(), workspace.numel(), _stream(stream)))
     return out
+
+
+def _job_table(inputs, outputs, record_bytes):
+    if outputs is None:
+        outputs = inputs
+    if len(outputs) != len(inputs):
+        raise ValueError("one output per input")
+    table = (Job * max(len(inputs), 1))()
+    for i, (a, b) in enumerate(zip(inputs, outputs)):
+        n = _check_records(a, record_bytes)
+        if _check_records(b, record_bytes) != n:
+            raise ValueError(f"job {i}: output size differs from input")
+        table[i].d_in, table[i].d_out, table[i].n = a.data_ptr(), b.data_ptr(), n
+    return table
+
+
+def sort_batch_workspace_size(inputs, params: FitParams | None = None, outputs=None) -> int:
+    params = params or fit_params()
+    table = _job_table(inputs, outputs, params.record_bytes)
+    sz = _SZ()
+    _check("elsar_sort_batch_workspace_size",
+           lib().elsar_sort_batch_workspace_size(table, len(inputs), ctypes.byref(params), ctypes.byref(sz)))
+    return sz.value
+
+
+def sort_batch(inputs, outputs=None, params: FitParams | None = None, workspace=None, stream=None):
+    """elsar_sort_batch: sort every job (a uint8 CUDA tensor of n*R bytes) into
+    the matching output (in place when ``outputs`` is None).  Returns the
+    workspace so that a later call with the same tensors can reuse it (and
+    with it the recorded graph)."""
+    params = params or fit_params()
+    table = _job_table(inputs, outputs, params.record_bytes)
+    sz = _SZ()
+    _check("elsar_sort_batch_workspace_size",
+           lib().elsar_sort_batch_workspace_size(table, len(inputs), ctypes.byref(params), ctypes.byref(sz)))
+    if workspace is None or workspace.numel() < sz.value:
+        workspace = _dev_bytes(sz.value, inputs[0].device)
+    _check("elsar_sort_batch", lib().elsar_sort_batch(table, len(inputs), ctypes.byref(params),
+                                                      workspace.data_ptr(), workspace.numel(), _stream(stream)))
+    return workspace
 
 
 class Model:

@@ -5,10 +5,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <list>
 #include <mutex>
 #include <new>
+#include <numeric>
 #include <vector>
 
+#include "autotune_table.h"
 #include "elsar.h"
 #include "elsar_internal.h"
 
@@ -365,6 +368,215 @@ elsar_status elsar_sort_workspace_size(const elsar_fit_params* p, uint64_t n, si
   return ELSAR_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One whole sort on device-resident records; q has its defaults filled in.
+elsar_status sort_job(const void* d_in, uint64_t n, void* d_out, const elsar_fit_params& q, void* d_ws,
+                      size_t ws_bytes, hipStream_t stream, bool timed) {
+  Shape sh = resolve(q, n);
+  SortLayout sl = sort_layout(q, sh, n);
+  if (ws_bytes < sl.bytes) return ELSAR_E_NO_MEMORY;
+  if (n == 1) {
+    if (d_out != d_in) HIP_TRY(hipMemcpyAsync(d_out, d_in, q.record_bytes, hipMemcpyDeviceToDevice, stream));
+    return ELSAR_OK;
+  }
+  uint8_t* w = static_cast<uint8_t*>(d_ws);
+  elsar_model m{};
+  m.p = q;
+  m.B = sh.B;
+  m.L = sh.L;
+  m.S = sh.S;
+  m.dev = nullptr;
+  place_model(&m, w + sl.model);
+  uint64_t* offsets = reinterpret_cast<uint64_t*>(w + sl.offsets);
+  PhaseMarks pm = timed ? begin_marks() : PhaseMarks{};
+  mark(pm, 0, stream);
+  elsar_status s = do_fit(&m, d_in, n, w + sl.fit, fit_ws_bytes(sh.S), stream);
+  if (s != ELSAR_OK) return s;
+  s = do_partition(&m, d_in, n, w + sl.part, sl.lay.bytes, offsets, stream, &pm);
+  if (s != ELSAR_OK) return s;
+  mark(pm, 3, stream);
+  return do_sort_buckets(&m, w + sl.part, sl.lay.bytes, n, offsets, d_out, stream, &pm);
+}
+
+// ------------------------------------------------------------------ batch --
+constexpr uint32_t kBatchLanes = 4;
+constexpr size_t kMaxPlans = 8;
+
+uint32_t ceil_log2(uint64_t n) {
+  uint32_t r = 0;
+  while ((1ull << r) < n) ++r;
+  return r;
+}
+
+uint32_t tuned_buckets(uint64_t n) {
+  const uint32_t r = ceil_log2(n);
+  const uint32_t b = r < kAutotuneRows ? kAutotuneBuckets[r] : 0u;
+  return b ? b : default_buckets(n);
+}
+
+elsar_fit_params job_params(const elsar_fit_params& p, uint64_t n, uint32_t j) {
+  elsar_fit_params q = p;
+  if (q.num_buckets == 0) q.num_buckets = tuned_buckets(n);
+  q.seed = p.seed + j;
+  return with_defaults(q);
+}
+
+struct BatchLayout {
+  std::vector<TinyJob> tiny;
+  std::vector<std::vector<uint32_t>> lanes;  // job indices per lane, largest first
+  size_t tiny_desc = 0, tiny_stage = 0, bytes = 0;
+  std::vector<size_t> lane_off, lane_bytes;
+};
+
+elsar_status batch_layout(const elsar_job* jobs, uint32_t njobs, const elsar_fit_params& p, BatchLayout* bl) {
+  const uint32_t RW = p.record_bytes / 4;
+  std::vector<uint32_t> big;
+  uint64_t stage_dw = 0;
+  for (uint32_t j = 0; j < njobs; ++j) {
+    const elsar_job& J = jobs[j];
+    if (J.n == 0) continue;
+    if (J.n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;
+    if (!J.d_in || !J.d_out || !aligned16(J.d_in) || !aligned16(J.d_out)) return ELSAR_E_INVALID_ARG;
+    if (J.n <= kSmallCap) {
+      TinyJob t{};
+      t.in = static_cast<const uint32_t*>(J.d_in);
+      t.out = static_cast<uint32_t*>(J.d_out);
+      t.n = (uint32_t)J.n;
+      t.staging_dw = stage_dw;
+      if (J.d_in == J.d_out) stage_dw += (J.n * RW + 3) & ~3ull;
+      bl->tiny.push_back(t);
+    } else {
+      big.push_back(j);
+    }
+  }
+  // longest job first to the least loaded lane
+  std::stable_sort(big.begin(), big.end(), [&](uint32_t a, uint32_t b) { return jobs[a].n > jobs[b].n; });
+  const uint32_t nl = std::min<uint32_t>(kBatchLanes, (uint32_t)big.size());
+  bl->lanes.assign(nl, {});
+  std::vector<uint64_t> load(nl, 0);
+  bl->lane_bytes.assign(nl, 0);
+  for (uint32_t j : big) {
+    const uint32_t l = (uint32_t)(std::min_element(load.begin(), load.end()) - load.begin());
+    bl->lanes[l].push_back(j);
+    load[l] += jobs[j].n;
+    const elsar_fit_params q = job_params(p, jobs[j].n, j);
+    const size_t need = sort_layout(q, resolve(q, jobs[j].n), jobs[j].n).bytes;
+    bl->lane_bytes[l] = std::max(bl->lane_bytes[l], need);
+  }
+  size_t off = 0;
+  bl->tiny_desc = off;
+  off += align_up(bl->tiny.size() * sizeof(TinyJob));
+  bl->tiny_stage = off;
+  off += align_up(stage_dw * 4);
+  bl->lane_off.assign(nl, 0);
+  for (uint32_t l = 0; l < nl; ++l) {
+    bl->lane_off[l] = off;
+    off += align_up(bl->lane_bytes[l]);
+  }
+  bl->bytes = std::max<size_t>(off, 256);
+  return ELSAR_OK;
+}
+
+struct BatchPlan {
+  std::vector<uint8_t> key;
+  std::vector<TinyJob> tiny;  // source of the per-launch descriptor upload
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+std::mutex g_batch_mu;
+std::list<BatchPlan> g_plans;  // most recently used first
+
+std::vector<uint8_t> plan_key(const elsar_job* jobs, uint32_t njobs, const elsar_fit_params& p, const void* ws,
+                              size_t ws_bytes) {
+  std::vector<uint8_t> k(sizeof(elsar_fit_params) + sizeof(void*) + sizeof(size_t) + (size_t)njobs * sizeof(elsar_job));
+  uint8_t* o = k.data();
+  std::memcpy(o, &p, sizeof(p));
+  o += sizeof(p);
+  std::memcpy(o, &ws, sizeof(ws));
+  o += sizeof(ws);
+  std::memcpy(o, &ws_bytes, sizeof(ws_bytes));
+  o += sizeof(ws_bytes);
+  if (njobs) std::memcpy(o, jobs, (size_t)njobs * sizeof(elsar_job));
+  return k;
+}
+
+// Every kernel of the batch on `cap` (small jobs) and on lane streams forked
+// from it and joined back.
+elsar_status enqueue_batch(const elsar_job* jobs, const elsar_fit_params& p, const BatchLayout& bl, uint8_t* w,
+                           hipStream_t cap, hipStream_t* lanes, hipEvent_t fork, hipEvent_t* done) {
+  if (!bl.tiny.empty())
+    HIP_TRY(launch_tiny_jobs(reinterpret_cast<const TinyJob*>(w + bl.tiny_desc), (uint32_t)bl.tiny.size(),
+                             p.record_bytes, p.key_bytes, reinterpret_cast<uint32_t*>(w + bl.tiny_stage), cap));
+  HIP_TRY(hipEventRecord(fork, cap));
+  for (size_t l = 0; l < bl.lanes.size(); ++l) {
+    HIP_TRY(hipStreamWaitEvent(lanes[l], fork, 0));
+    for (uint32_t j : bl.lanes[l]) {
+      const elsar_fit_params q = job_params(p, jobs[j].n, j);
+      elsar_status s = sort_job(jobs[j].d_in, jobs[j].n, jobs[j].d_out, q, w + bl.lane_off[l], bl.lane_bytes[l],
+                                lanes[l], false);
+      if (s != ELSAR_OK) return s;
+    }
+    HIP_TRY(hipEventRecord(done[l], lanes[l]));
+    HIP_TRY(hipStreamWaitEvent(cap, done[l], 0));
+  }
+  return ELSAR_OK;
+}
+
+elsar_status build_plan(const elsar_job* jobs, const elsar_fit_params& p, const BatchLayout& bl, uint8_t* w,
+                        BatchPlan* plan) {
+  hipStream_t cap = nullptr, lanes[kBatchLanes] = {};
+  hipEvent_t fork = nullptr, done[kBatchLanes] = {};
+  elsar_status s = ELSAR_OK;
+  auto cleanup = [&]() {
+    if (cap) (void)hipStreamDestroy(cap);
+    for (auto& x : lanes)
+      if (x) (void)hipStreamDestroy(x);
+    if (fork) (void)hipEventDestroy(fork);
+    for (auto& e : done)
+      if (e) (void)hipEventDestroy(e);
+  };
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) {
+    cleanup();
+    return ELSAR_E_HIP;
+  }
+  for (uint32_t l = 0; l < kBatchLanes; ++l)
+    if (hipStreamCreateWithFlags(&lanes[l], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&done[l], hipEventDisableTiming) != hipSuccess) {
+      cleanup();
+      return ELSAR_E_HIP;
+    }
+  if (p.kind != ELSAR_MODEL_RMI && mlp_prepare_kernels() != hipSuccess) {
+    cleanup();
+    return ELSAR_E_HIP;
+  }
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    cleanup();
+    return ELSAR_E_HIP;
+  }
+  s = enqueue_batch(jobs, p, bl, w, cap, lanes, fork, done);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cap, &g);
+  if (s == ELSAR_OK && ec != hipSuccess) s = ELSAR_E_HIP;
+  if (s == ELSAR_OK && hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0) != hipSuccess) s = ELSAR_E_HIP;
+  if (s != ELSAR_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    plan->exec = nullptr;
+  } else {
+    plan->graph = g;
+  }
+  cleanup();
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
 elsar_status elsar_sort(const void* d_in, uint64_t n, void* d_out, const elsar_fit_params* p, void* d_ws,
                         size_t ws_bytes, hipStream_t stream) {
   elsar_status s = check_params(p);
@@ -373,31 +585,62 @@ elsar_status elsar_sort(const void* d_in, uint64_t n, void* d_out, const elsar_f
   if (n == 0) return ELSAR_OK;
   if (!d_in || !d_out || !d_ws || !aligned16(d_in) || !aligned16(d_out) || !aligned16(d_ws))
     return ELSAR_E_INVALID_ARG;
-  const elsar_fit_params q = with_defaults(*p);
-  Shape sh = resolve(q, n);
-  SortLayout sl = sort_layout(q, sh, n);
-  if (ws_bytes < sl.bytes) return ELSAR_E_NO_MEMORY;
-  if (n == 1) {
-    if (d_out != d_in) HIP_TRY(hipMemcpyAsync(d_out, d_in, p->record_bytes, hipMemcpyDeviceToDevice, stream));
-    return ELSAR_OK;
-  }
+  return sort_job(d_in, n, d_out, with_defaults(*p), d_ws, ws_bytes, stream, true);
+}
+
+elsar_status elsar_sort_batch_workspace_size(const elsar_job* h_jobs, uint32_t njobs, const elsar_fit_params* p,
+                                             size_t* bytes) {
+  if (!bytes || (njobs && !h_jobs)) return ELSAR_E_INVALID_ARG;
+  elsar_status s = check_params(p);
+  if (s != ELSAR_OK) return s;
+  BatchLayout bl;
+  s = batch_layout(h_jobs, njobs, *p, &bl);
+  if (s != ELSAR_OK) return s;
+  *bytes = bl.bytes;
+  return ELSAR_OK;
+}
+
+elsar_status elsar_sort_batch(const elsar_job* h_jobs, uint32_t njobs, const elsar_fit_params* p, void* d_ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  if (njobs && !h_jobs) return ELSAR_E_INVALID_ARG;
+  elsar_status s = check_params(p);
+  if (s != ELSAR_OK) return s;
+  if (njobs == 0) return ELSAR_OK;
+  if (!d_ws || !aligned16(d_ws)) return ELSAR_E_INVALID_ARG;
+  BatchLayout bl;
+  s = batch_layout(h_jobs, njobs, *p, &bl);
+  if (s != ELSAR_OK) return s;
+  if (ws_bytes < bl.bytes) return ELSAR_E_NO_MEMORY;
   uint8_t* w = static_cast<uint8_t*>(d_ws);
-  elsar_model m{};
-  m.p = with_defaults(*p);
-  m.B = sh.B;
-  m.L = sh.L;
-  m.S = sh.S;
-  m.dev = nullptr;
-  place_model(&m, w + sl.model);
-  uint64_t* offsets = reinterpret_cast<uint64_t*>(w + sl.offsets);
-  PhaseMarks pm = begin_marks();
-  mark(pm, 0, stream);
-  s = do_fit(&m, d_in, n, w + sl.fit, fit_ws_bytes(sh.S), stream);
-  if (s != ELSAR_OK) return s;
-  s = do_partition(&m, d_in, n, w + sl.part, sl.lay.bytes, offsets, stream, &pm);
-  if (s != ELSAR_OK) return s;
-  mark(pm, 3, stream);
-  return do_sort_buckets(&m, w + sl.part, sl.lay.bytes, n, offsets, d_out, stream, &pm);
+  std::vector<uint8_t> key = plan_key(h_jobs, njobs, *p, d_ws, ws_bytes);
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  auto it = std::find_if(g_plans.begin(), g_plans.end(), [&](const BatchPlan& x) { return x.key == key; });
+  if (it == g_plans.end()) {
+    BatchPlan plan;
+    plan.key = std::move(key);
+    plan.tiny = bl.tiny;
+    s = build_plan(h_jobs, *p, bl, w, &plan);
+    if (s != ELSAR_OK) return s;
+    if (g_plans.size() >= kMaxPlans) {  // the oldest plan may still run: wait before freeing it
+      HIP_TRY(hipDeviceSynchronize());
+      BatchPlan& old = g_plans.back();
+      (void)hipGraphExecDestroy(old.exec);
+      (void)hipGraphDestroy(old.graph);
+      g_plans.pop_back();
+    }
+    g_plans.push_front(std::move(plan));
+    it = g_plans.begin();
+  } else if (it != g_plans.begin()) {
+    g_plans.splice(g_plans.begin(), g_plans, it);
+    it = g_plans.begin();
+  }
+  // the small jobs' descriptors go to the workspace before every launch: the
+  // caller may have used the workspace for something else in between
+  if (!it->tiny.empty())
+    HIP_TRY(hipMemcpyAsync(w + bl.tiny_desc, it->tiny.data(), it->tiny.size() * sizeof(TinyJob),
+                           hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipGraphLaunch(it->exec, stream));
+  return ELSAR_OK;
 }
 
 elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info) {

@@ -221,6 +221,7 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T* total) {
 
 // ---------------------------------------------------------- host wrappers --
 // sample / fit (k_fit.hip)
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_sample_codes(const uint8_t* recs, uint64_t n, uint32_t rec_bytes, uint64_t S, uint64_t seed,
                                uint64_t* codes, hipStream_t st);
 size_t radix_u64_scratch_bytes(uint64_t n);
@@ -251,6 +252,7 @@ hipError_t launch_mlp_fit(const uint64_t* sorted_codes, uint64_t S, uint32_t L, 
 hipError_t launch_decide_root(const uint32_t* hist_rmi, const MlpState* ms, uint32_t B, uint64_t S,
                               float accept_ratio, uint32_t kind, ModelHeader* hdr, uint32_t* hist_used,
                               hipStream_t st);
+hipError_t mlp_prepare_kernels();
 hipError_t launch_mlp_params_to_block(const float* d_params, const uint64_t* d_q9, MlpBlock* M, hipStream_t st);
 hipError_t launch_mlp_eval(const MlpBlock* M, const uint64_t* codes, uint64_t n, float* y, hipStream_t st);
 hipError_t launch_mlp_grad(const MlpBlock* M, const uint64_t* codes, const float* targets, float* grad,
@@ -268,6 +270,15 @@ hipError_t launch_spill_fixup(uint8_t* part, const PartLayout& lay, uint64_t n, 
 // bucket sort (k_bucket_sort.hip)
 hipError_t launch_bucket_sort_small(uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
                                     uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st);
+// whole jobs of up to kSmallCap records, one block each (batch)
+struct TinyJob {
+  const uint32_t* in;   // n records
+  uint32_t* out;        // n records (may equal in)
+  uint32_t n, pad;
+  uint64_t staging_dw;  // dword offset of the job's staging copy (in-place jobs)
+};
+hipError_t launch_tiny_jobs(const TinyJob* d_jobs, uint32_t njobs, uint32_t rec_bytes, uint32_t key_bytes,
+                            uint32_t* staging, hipStream_t st);
 hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
                                     uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st);
 

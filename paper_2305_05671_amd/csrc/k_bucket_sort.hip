@@ -857,6 +857,80 @@ __global__ void msd_clear_kernel(uint32_t* __restrict__ c) {
   if (threadIdx.x == 0) *c = 0;
 }
 
+// ------------------------------------------- whole jobs of up to 2048 records --
+// A batch's small jobs need no partition: one block sorts a whole job the way
+// the small-bucket kernel sorts a bucket, reading the keys straight from the
+// job's records.  An in-place job is first copied to its staging area.
+__global__ __launch_bounds__(kSmThreads) void tiny_jobs_kernel(const TinyJob* __restrict__ jobs, uint32_t njobs,
+                                                               uint32_t RW, uint32_t K, uint32_t* __restrict__ staging) {
+  constexpr uint32_t AR = kSmCap / kSmThreads;
+  __shared__ uint32_t cw[4][kSmCap];
+  __shared__ uint16_t perm[2][kSmCap];
+  __shared__ uint32_t bins[1u << kSmBits];
+  __shared__ uint4 sh_or[kSmWaves], sh_and[kSmWaves];
+  __shared__ uint32_t sh_scan[kSmThreads / 64 + 1];
+  __shared__ uint64_t sh_mm[2 * kSmWaves];
+  __shared__ uint32_t tot[4];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
+    const TinyJob J = jobs[jb];
+    const uint32_t n = J.n;
+    const uint32_t* src = J.in;
+    if (J.in == J.out) {  // in place: keep a copy to gather from
+      uint32_t* stg = staging + J.staging_dw;
+      for (uint32_t f = tid; f < n * RW; f += kSmThreads) stg[f] = J.in[f];
+      __syncthreads();
+      src = stg;
+    }
+    uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
+    uint64_t cmin = ~0ull, cmax = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < AR; ++i) {
+      const uint32_t q = tid + i * kSmThreads;
+      if (q < n) {
+        const uint32_t* r = src + (uint64_t)q * RW;
+        const uint4 c = composite_words(q, r[0], r[1], r[2], K);
+        cw[0][q] = c.x; cw[1][q] = c.y; cw[2][q] = c.z; cw[3][q] = c.w;
+        o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
+        a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+        const uint64_t e = key_code(r[0], r[1]);
+        cmin = e < cmin ? e : cmin;
+        cmax = e > cmax ? e : cmax;
+      }
+    }
+    const uint32_t vary = vary_mask(block_diff<kSmThreads>(o, a, sh_or, sh_and));
+    block_min_max_u64<kSmThreads>(cmin, cmax, sh_mm);
+    uint32_t cur = 0;
+    if (n == 1) {
+      if (tid == 0) perm[0][0] = 0;
+    } else {
+      const double scale = (double)(1u << kSmBits) / ((double)(cmax - cmin) + 1.0);
+      for (uint32_t i = tid; i < (1u << kSmBits); i += kSmThreads) bins[i] = 0;
+      for (uint32_t q = tid; q < n; q += kSmThreads) {
+        const uint32_t* r = src + (uint64_t)q * RW;
+        const uint64_t e = key_code(r[0], r[1]);
+        const uint32_t d = (uint32_t)((double)(e - cmin) * scale);
+        perm[1][q] = (uint16_t)(d < (1u << kSmBits) ? d : (1u << kSmBits) - 1);
+      }
+      cur = small_sort_core(n, vary, cw, perm, bins, sh_scan, tot);
+    }
+    __syncthreads();
+    for (uint32_t f = tid; f < n * RW; f += kSmThreads) {
+      const uint32_t k = f / RW, d = f - k * RW;
+      J.out[f] = src[(uint64_t)perm[cur][k] * RW + d];
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_tiny_jobs(const TinyJob* d_jobs, uint32_t njobs, uint32_t rec_bytes, uint32_t key_bytes,
+                            uint32_t* staging, hipStream_t st) {
+  if (njobs == 0) return hipSuccess;
+  tiny_jobs_kernel<<<njobs < 4096 ? njobs : 4096, kSmThreads, 0, st>>>(d_jobs, njobs, rec_bytes / 4, key_bytes,
+                                                                       staging);
+  return hipGetLastError();
+}
+
 struct SortArgs {
   const uint32_t *counts, *caps, *rstart, *soff, *smap, *slots;
   const PartHeader* ph;

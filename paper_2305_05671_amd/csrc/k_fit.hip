@@ -316,9 +316,23 @@ __global__ __launch_bounds__(256) void sample_bucket_hist_kernel(const uint64_t*
   atomicAdd(&hist[leaf_bucket(load_leaf(leaves, j), c)], 1u);
 }
 
+// A plain fill: it records as a kernel node under graph capture, which a
+// memset does not do reliably.
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  fill_u32_kernel<<<(uint32_t)(blocks < 1024 ? blocks : 1024), 256, 0, st>>>(p, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_sample_hist(const ModelHeader* hdr, const Leaf* leaves, const uint64_t* e, uint64_t S,
                               uint32_t B, uint32_t* hist, hipStream_t st) {
-  hipError_t err = hipMemsetAsync(hist, 0, (size_t)B * 4, st);
+  hipError_t err = launch_fill_u32(hist, B, 0u, st);
   if (err != hipSuccess) return err;
   if (S) sample_bucket_hist_kernel<<<(uint32_t)((S + 255) / 256), 256, 0, st>>>(e, S, hdr, leaves, hist);
   return hipGetLastError();

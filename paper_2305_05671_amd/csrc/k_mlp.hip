@@ -544,8 +544,19 @@ __global__ __launch_bounds__(256) void decide_root_kernel(const uint32_t* __rest
 }
 
 // ------------------------------------------------------------------- host --
+// The training kernels' LDS exceeds the default limit; the attribute is set
+// once per process (not while a stream is being captured).
 static hipError_t allow_big_lds(const void* fn) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(TrainLds));
+}
+
+hipError_t mlp_prepare_kernels() {
+  static hipError_t once = [] {
+    hipError_t e = allow_big_lds(reinterpret_cast<const void*>(mlp_train_kernel));
+    if (e == hipSuccess) e = allow_big_lds(reinterpret_cast<const void*>(mlp_grad_kernel));
+    return e;
+  }();
+  return once;
 }
 
 hipError_t launch_mlp_fit(const uint64_t* e, uint64_t S, uint32_t L, uint32_t B, uint64_t seed, uint32_t steps,
@@ -554,17 +565,17 @@ hipError_t launch_mlp_fit(const uint64_t* e, uint64_t S, uint32_t L, uint32_t B,
   mlp_setup_kernel<<<1, 256, 0, st>>>(e, S, seed, ms.M, ms.master, ms.adam, hdr);
   mlp_publish_kernel<<<1, 256, 0, st>>>(ms.master, nullptr, ms.M);
   if (steps) {
-    hipError_t err = allow_big_lds(reinterpret_cast<const void*>(mlp_train_kernel));
+    hipError_t err = mlp_prepare_kernels();
     if (err != hipSuccess) return err;
     mlp_train_kernel<<<1, kTrainThreads, sizeof(TrainLds), st>>>(e, S, steps, lr, seed, ms.master, ms.adam, ms.M);
   }
-  hipError_t err = hipMemsetAsync(ms.first, 0xFF, ((size_t)L + 1) * 4, st);
+  hipError_t err = launch_fill_u32(ms.first, (uint64_t)L + 1, 0xFFFFFFFFu, st);
   if (err != hipSuccess) return err;
   const uint32_t nb = (uint32_t)((S + 255) / 256);
   mlp_sample_leaves_kernel<<<nb, 256, 0, st>>>(e, S, L, ms.M, ms.first);
   suffix_min_kernel<<<1, 1024, 0, st>>>(ms.first, L, (uint32_t)S);
   mlp_leaf_fit_kernel<<<(L + 255) / 256, 256, 0, st>>>(e, S, L, B, ms.first, ms.leaves, ms.bound);
-  err = hipMemsetAsync(ms.hist, 0, (size_t)B * 4, st);
+  err = launch_fill_u32(ms.hist, B, 0u, st);
   if (err != hipSuccess) return err;
   mlp_sample_stats_kernel<<<nb, 256, 0, st>>>(e, S, L, ms.first, ms.leaves, ms.hist, hdr);
   return hipGetLastError();
@@ -591,7 +602,7 @@ hipError_t launch_mlp_eval(const MlpBlock* M, const uint64_t* codes, uint64_t n,
 
 hipError_t launch_mlp_grad(const MlpBlock* M, const uint64_t* codes, const float* targets, float* grad, float* loss,
                            hipStream_t st) {
-  hipError_t err = allow_big_lds(reinterpret_cast<const void*>(mlp_grad_kernel));
+  hipError_t err = mlp_prepare_kernels();
   if (err != hipSuccess) return err;
   mlp_grad_kernel<<<1, kTrainThreads, sizeof(TrainLds), st>>>(M, codes, targets, grad, loss);
   return hipGetLastError();

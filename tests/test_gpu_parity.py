@@ -205,3 +205,52 @@ def test_big_bucket_equal_keys_and_prefixes(env):
     rng = np.random.default_rng(24)
     recs = recs[rng.permutation(recs.shape[0])]
     _assert_same(_gpu_sort(env, recs, num_buckets=1), oracle.sort_records(recs))
+
+
+def _batch_inputs(torch, rng, sizes, kinds, seed0):
+    host, dev = [], []
+    for j, (n, kind) in enumerate(zip(sizes, kinds)):
+        r = datagen.generate(datagen.spec(kind, seed=seed0 + j), int(n))
+        host.append(r)
+        dev.append(torch.from_numpy(np.ascontiguousarray(r).reshape(-1)).to("cuda"))
+    return host, dev
+
+
+def test_batch_matches_oracle_and_replays(env):
+    torch, elsar = env
+    rng = np.random.default_rng(31)
+    # log-uniform sizes (small jobs sorted whole, larger ones through the
+    # pipeline lanes), even jobs uniform, odd jobs first-byte Zipf; one empty job
+    sizes = np.round(np.exp(rng.uniform(np.log(1), np.log(300_000), 96))).astype(int)
+    sizes[5] = 0
+    sizes[7] = 1
+    sizes[9] = 2048
+    sizes[11] = 2049
+    kinds = ["uniform" if j % 2 == 0 else "zipf" for j in range(sizes.size)]
+    host, dev = _batch_inputs(torch, rng, sizes, kinds, 100)
+    want = [oracle.sort_records(h) if h.shape[0] else h for h in host]
+    # out of place first, then in place; each launched twice (the second is a
+    # replay of the recorded graph), with other GPU work in between
+    outs = [torch.empty_like(d) for d in dev]
+    ws = elsar.sort_batch(dev, outs)
+    torch.cuda.synchronize()
+    for j in range(sizes.size):
+        _assert_same(outs[j].cpu().numpy().reshape(-1, R), want[j])
+    for o in outs:
+        o.zero_()
+    junk = torch.randn(1 << 20, device="cuda").sum()
+    ws = elsar.sort_batch(dev, outs, workspace=ws)
+    torch.cuda.synchronize()
+    for j in range(sizes.size):
+        _assert_same(outs[j].cpu().numpy().reshape(-1, R), want[j])
+    for rep in range(2):
+        fresh = [torch.from_numpy(np.ascontiguousarray(h).reshape(-1)).to("cuda") for h in host]
+        if rep == 1:
+            for d, f in zip(dev, fresh):
+                d.copy_(f)
+            fresh = dev
+        ws = elsar.sort_batch(fresh, params=elsar.fit_params(), workspace=ws)
+        torch.cuda.synchronize()
+        for j in range(sizes.size):
+            _assert_same(fresh[j].cpu().numpy().reshape(-1, R), want[j])
+    del junk
