@@ -30,6 +30,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libelsar_gen.so")
+_GPU_LIB_PATH = os.path.join(_HERE, "libelsar_gen_gpu.so")
 
 UNIFORM, NORMAL_HOT, ZIPF_FIRST, MIX, STAIRCASE = 0, 1, 2, 3, 4
 
@@ -62,7 +63,47 @@ def build(quiet: bool = True) -> str:
     return _LIB_PATH
 
 
+def build_gpu(quiet: bool = True) -> str:
+    """Compile the GPU generator (gen_gpu.hip, gfx950) into datagen/libelsar_gen_gpu.so."""
+    src = os.path.join(_HERE, "gen_gpu.hip")
+    tmp = _GPU_LIB_PATH + ".tmp"
+    cmd = ["hipcc", "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-o", tmp, src]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
+    os.replace(tmp, _GPU_LIB_PATH)
+    return _GPU_LIB_PATH
+
+
 _lib = None
+_gpu_lib = None
+
+
+def gpu_lib():
+    global _gpu_lib
+    if _gpu_lib is None:
+        if not os.path.exists(_GPU_LIB_PATH):
+            raise ImportError(f"{_GPU_LIB_PATH} is missing: build it with datagen.build_gpu()")
+        L = ctypes.CDLL(_GPU_LIB_PATH)
+        L.gen_records_device.argtypes = [ctypes.POINTER(GenSpec), ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64, ctypes.c_uint64,
+                                         ctypes.c_void_p, ctypes.c_void_p]
+        L.gen_records_device.restype = ctypes.c_int
+        _gpu_lib = L
+    return _gpu_lib
+
+
+def generate_device(sp: GenSpec, ptr: int, start: int, count: int, stream: int = 0) -> None:
+    """Write records start..start+count-1 to device memory at ``ptr`` (same
+    bytes as :func:`generate_into`), asynchronously on ``stream``."""
+    normal = rank_law("normal", sp.mean_rank, sp.sigma)
+    zipf = rank_law("zipf", sp.zipf_s)
+    P = ctypes.POINTER(ctypes.c_uint64)
+    rc = gpu_lib().gen_records_device(ctypes.byref(sp), normal.ctypes.data_as(P), zipf.ctypes.data_as(P),
+                                      start, count, ctypes.c_void_p(ptr), ctypes.c_void_p(stream))
+    if rc != 0:
+        raise ValueError(f"gen_records_device failed ({rc})")
 
 
 def lib():

@@ -133,10 +133,7 @@ PartLayout part_layout(uint64_t n, uint32_t B, uint32_t R, uint32_t region_pct) 
   // split of buckets above the LDS caps: every split of c entries gives at most
   // 3c / 2048 + 1 segments, one split per composite byte and level
   lay.seg_leaf_cap = (uint32_t)std::min<uint64_t>(n / 32 + 4096, 0xFFFFFFFFull);
-  lay.seg_next_cap = (uint32_t)std::min<uint64_t>(n / 2048 + 1024, 0xFFFFFFFFull);
   lay.seg_leaf = take((size_t)lay.seg_leaf_cap * 16);
-  lay.seg_next[0] = take((size_t)lay.seg_next_cap * 16);
-  lay.seg_next[1] = take((size_t)lay.seg_next_cap * 16);
   // regions: sum_j ceil(f * max(n h_j / S, n / B)) + 17 <= 2 f n + 18 B,  f = region_pct / 100
   lay.cap_slots = (n * 2 * region_pct + 99) / 100 + 18ull * B + 16;
   lay.total_slots = lay.cap_slots + n;

@@ -72,7 +72,7 @@ struct PartHeader {    // device-resident state of one partition pass
   uint32_t max_count;
   uint32_t mid_records;  // records in the n_mid buckets
   uint32_t big_records;  // records in the n_big buckets
-  uint32_t seg_n[4];     // split of the n_big buckets: segments, next-level pieces (2), spare
+  uint32_t seg_n[4];     // split of the n_big buckets: segments, stack overflow flag, spare (2)
   uint32_t pad[3];
 };
 
@@ -80,8 +80,8 @@ struct PartHeader {    // device-resident state of one partition pass
 struct PartLayout {
   size_t header, counts, caps, rstart, spill_off, mid_list, big_list;
   size_t spill_meta, spill_map, slots;
-  size_t seg_leaf, seg_next[2];  // segment lists of the big-bucket split
-  uint32_t seg_leaf_cap, seg_next_cap;
+  size_t seg_leaf;               // segment list of the big-bucket split
+  uint32_t seg_leaf_cap;
   uint64_t cap_slots;   // region slots
   uint64_t total_slots; // regions + spill
   size_t bytes;

@@ -571,19 +571,23 @@ __global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
 // ---------------------------------- buckets above the LDS caps: MSD split --
 // A bucket of more than kMidCap records is split, most significant varying
 // composite byte first, into pieces that the small-bucket sort can finish:
-//  * msd_first: per bucket, its entries {composite, slot} go to buffer B and
-//    are scattered by the first varying byte into buffer A.
-//  * msd_split (repeated): a piece still larger than kSegCap is scattered by
-//    its own first varying byte into the other buffer.
-//  Consecutive digits whose pieces fit kSegCap together form one segment; a
-//  segment only needs sorting within itself.
+//  * msd_split: one block per bucket.  Its entries {composite, slot} go to
+//    buffer B and are scattered by the first varying byte into buffer A; a
+//    piece still larger than kSegCap is pushed on the bucket's own stack and
+//    later scattered by its own first varying byte into the other buffer,
+//    depth first, until no piece is left.  Consecutive digits whose pieces fit
+//    kSegCap together form one segment; a segment only needs sorting within
+//    itself.
 //  * seg_sort: each segment sorted in LDS as a small bucket; its slot numbers
 //    go, in sorted order, to the bucket's reference list.
 //  * big_gather: each bucket's records copied out in the order of its list.
-// Buffers live in the bucket's own output range (R*n bytes, not written yet):
-// A = [0, 20n), B = [20n, 40n), reference list = [(R-4)n, Rn), R >= 44.  The
-// gather reads list chunk k0.. before writing records k0.., and record k ends
-// at byte R(k+1) <= (R-4)n + 4(k+1) only for k = n-1, inside its own chunk.
+// Everything lives in the bucket's own output range (R*n bytes, not written
+// yet): A = [0, 20n), B = [20n, 40n), the stack = [40n, (R-4)n), the
+// reference list = [(R-4)n, Rn), R >= 64.  A split of c entries pushes at most
+// c / kSegCap pieces, so the stack holds at most 14 n / 2048 entries of 16
+// bytes.  The gather reads list chunk k0.. before writing records k0.., and
+// record k ends at byte R(k+1) <= (R-4)n + 4(k+1) only for k = n-1, inside
+// its own chunk.
 constexpr uint32_t kSegCap = kSmallCap;
 constexpr uint32_t kMsdThreads = 1024;
 constexpr uint32_t kMsdWaves = kMsdThreads / 64;
@@ -593,6 +597,8 @@ __device__ __forceinline__ uint32_t first_varying_byte(uint32_t vary) {  // vary
 }
 
 struct MsdShared {
+  uint32_t top, overflow;  // the bucket's piece stack
+  uint4 seg;               // piece being split
   uint32_t hist[256];
   uint32_t base[256];
   uint32_t cursor[256];
@@ -605,8 +611,8 @@ struct MsdShared {
 // most kSegCap entries become segments, larger digits go to the next level.
 __device__ void msd_scatter(MsdShared& sh, const uint32_t* __restrict__ X, uint32_t* __restrict__ Y, uint32_t j,
                             uint32_t s, uint32_t c, uint32_t p, uint32_t yflag, uint4* __restrict__ leaf,
-                            uint32_t* __restrict__ leaf_n, uint32_t leaf_cap, uint4* __restrict__ next,
-                            uint32_t* __restrict__ next_n, uint32_t next_cap) {
+                            uint32_t* __restrict__ leaf_n, uint32_t leaf_cap, uint32_t* __restrict__ stack,
+                            uint32_t stack_cap) {
   const uint32_t tid = threadIdx.x;
   if (tid < 256) sh.hist[tid] = 0;
   __syncthreads();
@@ -669,10 +675,17 @@ __device__ void msd_scatter(MsdShared& sh, const uint32_t* __restrict__ X, uint3
     for (uint32_t d = 0; d < 256; ++d) {
       const uint32_t cd = sh.hist[d], bd = sh.base[d];
       if (cd == 0) continue;
-      if (cd > kSegCap) {
+      if (cd > kSegCap) {  // pushed on the bucket's stack: {start, count, buffer}
         flush();
-        const uint32_t q = atomicAdd(next_n, 1u);
-        if (q < next_cap) next[q] = make_uint4(j, s + bd, cd, yflag);
+        const uint32_t q = sh.top;
+        if (q < stack_cap) {
+          stack[3 * q] = s + bd;
+          stack[3 * q + 1] = cd;
+          stack[3 * q + 2] = yflag;
+          sh.top = q + 1;
+        } else {
+          sh.overflow = 1;
+        }
         continue;
       }
       if (run_c + cd > kSegCap) flush();
@@ -691,13 +704,12 @@ __device__ __forceinline__ void bucket_bufs(uint32_t* out, uint64_t out0, uint32
   *B = o_dw + 5ull * n;
 }
 
-__global__ __launch_bounds__(kMsdThreads) void msd_first_kernel(
+__global__ __launch_bounds__(kMsdThreads) void msd_split_kernel(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
     const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
     uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
-    uint4* __restrict__ leaf, uint32_t* __restrict__ leaf_n, uint32_t leaf_cap, uint4* __restrict__ next,
-    uint32_t* __restrict__ next_n, uint32_t next_cap) {
+    uint4* __restrict__ leaf, uint32_t* __restrict__ leaf_n, uint32_t leaf_cap, uint32_t* __restrict__ error) {
   __shared__ MsdShared sh;
   const uint32_t W = slot_bytes_for(RW * 4) / 4;
   const uint32_t nitems = *list_n;
@@ -712,6 +724,12 @@ __global__ __launch_bounds__(kMsdThreads) void msd_first_kernel(
     br.out0 = offsets[j];
     uint32_t *A, *Bf;
     bucket_bufs(out, br.out0, br.n, RW, &A, &Bf);
+    uint32_t* stack = out + br.out0 * RW + 10ull * br.n;                 // byte 40n
+    const uint32_t stack_cap = (uint32_t)(((uint64_t)(RW - 11) * br.n) / 3);  // dwords [10n, (RW-1)n)
+    if (threadIdx.x == 0) {
+      sh.top = 0;
+      sh.overflow = 0;
+    }
     uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
     for (uint32_t q = threadIdx.x; q < br.n; q += kMsdThreads) {
       const uint32_t sl = slot_of(br, q, spill_map, cap_slots);
@@ -720,34 +738,37 @@ __global__ __launch_bounds__(kMsdThreads) void msd_first_kernel(
       o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
       a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
     }
-    const uint32_t vary = varying_bytes<kMsdThreads>(o, a, sh.sh_or, sh.sh_and);  // syncs
-    msd_scatter(sh, Bf, A, j, 0, br.n, first_varying_byte(vary), 0u, leaf, leaf_n, leaf_cap, next, next_n,
-                next_cap);
-  }
-}
-
-__global__ __launch_bounds__(kMsdThreads) void msd_split_kernel(
-    const uint32_t* __restrict__ counts, const uint64_t* __restrict__ offsets, uint32_t RW, uint32_t* __restrict__ out,
-    const uint4* __restrict__ in, const uint32_t* __restrict__ in_n, uint4* __restrict__ leaf,
-    uint32_t* __restrict__ leaf_n, uint32_t leaf_cap, uint4* __restrict__ next, uint32_t* __restrict__ next_n,
-    uint32_t next_cap) {
-  __shared__ MsdShared sh;
-  const uint32_t nitems = *in_n < next_cap ? *in_n : next_cap;  // the lists share one capacity
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const uint4 sg = in[it];  // bucket, start, count, buffer
-    uint32_t *A, *Bf;
-    bucket_bufs(out, offsets[sg.x], counts[sg.x], RW, &A, &Bf);
-    const uint32_t* X = sg.w ? Bf : A;
-    uint32_t* Y = sg.w ? A : Bf;
-    uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
-    for (uint32_t q = threadIdx.x; q < sg.z; q += kMsdThreads) {
-      const uint4 c = get_key(X, sg.y + q);
-      o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
-      a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+    uint32_t vary = varying_bytes<kMsdThreads>(o, a, sh.sh_or, sh.sh_and);  // syncs
+    msd_scatter(sh, Bf, A, j, 0, br.n, first_varying_byte(vary), 0u, leaf, leaf_n, leaf_cap, stack, stack_cap);
+    // depth first over the pieces still above kSegCap
+    for (;;) {
+      if (threadIdx.x == 0) {
+        if (sh.top > 0) {
+          const uint32_t q = --sh.top;
+          sh.seg = make_uint4(stack[3 * q], stack[3 * q + 1], stack[3 * q + 2], 1u);
+        } else {
+          sh.seg = make_uint4(0, 0, 0, 0);
+        }
+      }
+      __syncthreads();
+      const uint4 sg = sh.seg;  // start, count, buffer, valid
+      __syncthreads();
+      if (!sg.w) break;
+      const uint32_t* X = sg.z ? Bf : A;
+      uint32_t* Y = sg.z ? A : Bf;
+      o = make_uint4(0, 0, 0, 0);
+      a = make_uint4(~0u, ~0u, ~0u, ~0u);
+      for (uint32_t q = threadIdx.x; q < sg.y; q += kMsdThreads) {
+        const uint4 c = get_key(X, sg.x + q);
+        o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
+        a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+      }
+      vary = varying_bytes<kMsdThreads>(o, a, sh.sh_or, sh.sh_and);
+      msd_scatter(sh, X, Y, j, sg.x, sg.y, first_varying_byte(vary), sg.z ^ 1u, leaf, leaf_n, leaf_cap, stack,
+                  stack_cap);
     }
-    const uint32_t vary = varying_bytes<kMsdThreads>(o, a, sh.sh_or, sh.sh_and);
-    msd_scatter(sh, X, Y, sg.x, sg.y, sg.z, first_varying_byte(vary), sg.w ^ 1u, leaf, leaf_n, leaf_cap, next,
-                next_n, next_cap);
+    if (threadIdx.x == 0 && sh.overflow) atomicOr(error, 1u);
+    __syncthreads();
   }
 }
 
@@ -853,9 +874,7 @@ __global__ void msd_reset_kernel(PartHeader* __restrict__ ph) {
   if (threadIdx.x < 4) ph->seg_n[threadIdx.x] = 0;
 }
 
-__global__ void msd_clear_kernel(uint32_t* __restrict__ c) {
-  if (threadIdx.x == 0) *c = 0;
-}
+
 
 // ------------------------------------------- whole jobs of up to 2048 records --
 // A batch's small jobs need no partition: one block sorts a whole job the way
@@ -974,7 +993,7 @@ hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32
       a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
       reinterpret_cast<const uint32_t*>(part + lay.mid_list), &a.ph->n_mid, B);
   const uint32_t* big_list = reinterpret_cast<const uint32_t*>(part + lay.big_list);
-  if (rec_bytes < 44) {  // no room for the split's buffers beside the reference list
+  if (rec_bytes < 64) {  // too little room for the split's buffers, stack and reference list
     bucket_sort_global_kernel<<<256, kBigThreads, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots,
                                                            lay.cap_slots, offsets, a.RW, key_bytes, a.out, big_list,
                                                            &a.ph->n_big);
@@ -982,21 +1001,12 @@ hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32
   }
   PartHeader* ph = reinterpret_cast<PartHeader*>(part + lay.header);
   uint4* leaf = reinterpret_cast<uint4*>(part + lay.seg_leaf);
-  uint4* nxt[2] = {reinterpret_cast<uint4*>(part + lay.seg_next[0]), reinterpret_cast<uint4*>(part + lay.seg_next[1])};
   uint32_t* leaf_n = &ph->seg_n[0];
-  uint32_t* next_n[2] = {&ph->seg_n[1], &ph->seg_n[2]};
-  const uint32_t leaf_cap = lay.seg_leaf_cap, next_cap = lay.seg_next_cap;
+  const uint32_t leaf_cap = lay.seg_leaf_cap;
   msd_reset_kernel<<<1, 64, 0, st>>>(ph);
-  msd_first_kernel<<<512, kMsdThreads, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots,
+  msd_split_kernel<<<512, kMsdThreads, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots,
                                                 offsets, a.RW, key_bytes, a.out, big_list, &a.ph->n_big, leaf,
-                                                leaf_n, leaf_cap, nxt[0], next_n[0], next_cap);
-  // each split fixes one more composite byte: at most key_bytes + 3 further levels
-  for (uint32_t lev = 1; lev < key_bytes + 4; ++lev) {
-    const uint32_t in = (lev - 1) & 1u, o = lev & 1u;
-    msd_clear_kernel<<<1, 64, 0, st>>>(next_n[o]);
-    msd_split_kernel<<<512, kMsdThreads, 0, st>>>(a.counts, offsets, a.RW, a.out, nxt[in], next_n[in], leaf, leaf_n,
-                                                  leaf_cap, nxt[o], next_n[o], next_cap);
-  }
+                                                leaf_n, leaf_cap, &ph->seg_n[1]);
   seg_sort_kernel<<<2048, kSmThreads, 0, st>>>(a.counts, offsets, a.RW, a.out, leaf, leaf_n, leaf_cap);
   big_gather_kernel<<<512, kMsdThreads, 0, st>>>(a.counts, offsets, a.RW, reinterpret_cast<const uint4*>(a.slots),
                                                  a.out, big_list, &a.ph->n_big);
