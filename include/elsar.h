@@ -175,6 +175,42 @@ elsar_status elsar_sort_batch_workspace_size(const elsar_job* h_jobs, uint32_t n
 elsar_status elsar_sort_batch(const elsar_job* h_jobs, uint32_t njobs, const elsar_fit_params* p, void* d_ws,
                               size_t ws_bytes, hipStream_t stream);
 
+/* Host tier. */
+typedef struct {
+  uint64_t chunk_records;     /* records per streamed chunk */
+  uint64_t pass_records;      /* most records one pass can hold in HBM */
+  uint32_t passes;            /* passes over the input after the counting pass */
+  uint32_t num_buckets;
+  float fit_ms, count_ms, passes_ms, total_ms;  /* host wall time of each part */
+} elsar_host_stats;
+
+/* Device workspace of elsar_sort_host for n records streamed in chunks of
+ * chunk_records (0: 40M, 4 GB of 100-byte records), when one pass may hold
+ * up to pass_records records in HBM (0: n, a single pass). */
+elsar_status elsar_sort_host_workspace_size(const elsar_fit_params* p, uint64_t n, uint64_t chunk_records,
+                                            uint64_t pass_records, size_t* bytes);
+
+/*
+ * The external tier (the paper's larger-than-memory setting, Section 3, with
+ * host memory in the role of the external store): n records in pinned host
+ * memory h_in (allocated with hipHostMalloc or another pinned allocator, so
+ * that the device can read it) are sorted into host memory h_out, which must
+ * not overlap h_in (pinned for full copy speed).  The sample is read by the
+ * GPU straight from h_in; a counting pass streams every chunk to HBM and
+ * counts its records per bucket; then each pass streams the chunks again and
+ * places only a range of consecutive buckets whose records fit the workspace,
+ * in regions of exact size, sorts them and copies them to h_out at their
+ * offsets -- the concatenation of Section 3.5 at host level.  Copies run on
+ * streams of their own, double buffered against the kernels on `stream`.
+ * d_ws: workspace; its size bounds the records held in HBM at once (see
+ * elsar_sort_host_workspace_size).  Synchronous: returns when h_out is
+ * complete.  n < 2^32.  ELSAR_E_NO_MEMORY when one bucket alone exceeds what
+ * a pass can hold.  stats may be NULL.
+ */
+elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, const elsar_fit_params* p,
+                             uint64_t chunk_records, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                             elsar_host_stats* stats);
+
 /* What a fitted model looks like; synchronises with the device. */
 typedef struct {
   uint32_t kind_used;        /* elsar_model_kind actually in use (RMI or MLP) */

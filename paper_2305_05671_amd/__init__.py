@@ -85,6 +85,19 @@ class Job(ctypes.Structure):
     _fields_ = [("d_in", ctypes.c_void_p), ("d_out", ctypes.c_void_p), ("n", ctypes.c_uint64)]
 
 
+class HostStats(ctypes.Structure):
+    _fields_ = [
+        ("chunk_records", ctypes.c_uint64),
+        ("pass_records", ctypes.c_uint64),
+        ("passes", ctypes.c_uint32),
+        ("num_buckets", ctypes.c_uint32),
+        ("fit_ms", ctypes.c_float),
+        ("count_ms", ctypes.c_float),
+        ("passes_ms", ctypes.c_float),
+        ("total_ms", ctypes.c_float),
+    ]
+
+
 class ElsarError(RuntimeError):
     def __init__(self, fn: str, status: int):
         super().__init__(f"{fn} failed: {status_string(status)} ({status})")
@@ -123,6 +136,10 @@ def lib():
             "elsar_sort_batch_workspace_size": ([ctypes.POINTER(Job), ctypes.c_uint32, ctypes.POINTER(FitParams),
                                                  ctypes.POINTER(_SZ)], st),
             "elsar_sort_batch": ([ctypes.POINTER(Job), ctypes.c_uint32, ctypes.POINTER(FitParams), _P, _SZ, _P], st),
+            "elsar_sort_host_workspace_size": ([ctypes.POINTER(FitParams), _U64, _U64, _U64, ctypes.POINTER(_SZ)],
+                                               st),
+            "elsar_sort_host": ([_P, _U64, _P, ctypes.POINTER(FitParams), _U64, _P, _SZ, _P,
+                                 ctypes.POINTER(HostStats)], st),
             "elsar_mlp_forward": ([_P, _P, _P, _U64, _P], st),
             "elsar_mlp_gradient": ([_P, _P, _P, _P, _P, _P], st),
             "elsar_set_timing": ([ctypes.c_int], st),
@@ -240,6 +257,41 @@ def sort_batch(inputs, outputs=None, params: FitParams | None = None, workspace=
     _check("elsar_sort_batch", lib().elsar_sort_batch(table, len(inputs), ctypes.byref(params),
                                                       workspace.data_ptr(), workspace.numel(), _stream(stream)))
     return workspace
+
+
+def sort_host_workspace_size(n: int, params: FitParams | None = None, chunk_records: int = 0,
+                             pass_records: int = 0) -> int:
+    params = params or fit_params()
+    sz = _SZ()
+    _check("elsar_sort_host_workspace_size",
+           lib().elsar_sort_host_workspace_size(ctypes.byref(params), n, chunk_records, pass_records,
+                                                ctypes.byref(sz)))
+    return sz.value
+
+
+def sort_host(h_in, h_out, params: FitParams | None = None, chunk_records: int = 0, pass_records: int = 0,
+              workspace=None, stream=None) -> HostStats:
+    """elsar_sort_host: records in pinned host memory (uint8 CPU tensors made
+    with pin_memory=True) sorted into h_out.  The device workspace is sized
+    for passes of ``pass_records`` records (0: the whole input in one pass)
+    unless one is given.  Synchronous; returns the call's statistics."""
+    import torch
+    params = params or fit_params()
+    for t in (h_in, h_out):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or t.is_cuda or not t.is_contiguous():
+            raise TypeError("host records must be contiguous uint8 CPU tensors")
+    if not h_in.is_pinned():
+        raise TypeError("the input must be pinned host memory")
+    n = h_in.numel() // params.record_bytes
+    if h_in.numel() % params.record_bytes or h_out.numel() != h_in.numel():
+        raise ValueError("input and output must hold the same whole number of records")
+    if workspace is None:
+        workspace = _dev_bytes(sort_host_workspace_size(n, params, chunk_records, pass_records), "cuda")
+    st = HostStats()
+    _check("elsar_sort_host", lib().elsar_sort_host(h_in.data_ptr(), n, h_out.data_ptr(), ctypes.byref(params),
+                                                    chunk_records, workspace.data_ptr(), workspace.numel(),
+                                                    _stream(stream), ctypes.byref(st)))
+    return st
 
 
 class Model:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <list>
@@ -637,6 +638,264 @@ elsar_status elsar_sort_batch(const elsar_job* h_jobs, uint32_t njobs, const els
     HIP_TRY(hipMemcpyAsync(w + bl.tiny_desc, it->tiny.data(), it->tiny.size() * sizeof(TinyJob),
                            hipMemcpyHostToDevice, stream));
   HIP_TRY(hipGraphLaunch(it->exec, stream));
+  return ELSAR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// ------------------------------------------------------------- host tier --
+constexpr uint64_t kDefaultChunkRecords = 40000000ull;  // 4 GB of 100-byte records
+
+// Partition buffer of one pass: P records in exact regions for up to B
+// buckets, no spill area.
+PartLayout pass_layout(uint64_t P, uint32_t B, uint32_t R) {
+  PartLayout lay{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  lay.header = take(sizeof(PartHeader));
+  lay.counts = take((size_t)B * 4);
+  lay.caps = take((size_t)B * 4);
+  lay.rstart = take((size_t)B * 4);
+  lay.spill_off = take((size_t)B * 4);
+  lay.mid_list = take((size_t)B * 4);
+  lay.big_list = take((size_t)B * 4);
+  lay.spill_meta = take(0);
+  lay.spill_map = take(0);
+  lay.seg_leaf_cap = (uint32_t)std::min<uint64_t>(P / 32 + 4096, 0xFFFFFFFFull);
+  lay.seg_leaf = take((size_t)lay.seg_leaf_cap * 16);
+  lay.cap_slots = P;
+  lay.total_slots = P;
+  lay.slot_bytes = slot_bytes_for(R);
+  lay.slots = take((size_t)P * lay.slot_bytes);
+  lay.bytes = off;
+  return lay;
+}
+
+struct HostLayout {
+  Shape sh;
+  uint64_t C = 0, P = 0;
+  size_t model = 0, fit = 0, counts = 0, offsets = 0, chunk[2] = {0, 0}, part = 0, stage = 0, bytes = 0;
+  PartLayout lay;
+};
+
+HostLayout host_layout(const elsar_fit_params& q, uint64_t n, uint64_t C, uint64_t P) {
+  HostLayout h;
+  h.sh = resolve(q, n);
+  h.C = std::max<uint64_t>(1, std::min<uint64_t>(C ? C : kDefaultChunkRecords, n));
+  h.P = std::max<uint64_t>(1, P);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  h.model = take(model_dev_bytes(h.sh.L, h.sh.B, q.kind));
+  h.fit = take(fit_ws_bytes(h.sh.S));
+  h.counts = take((size_t)h.sh.B * 4);
+  h.offsets = take(((size_t)h.sh.B + 1) * 8);
+  h.chunk[0] = take((size_t)h.C * q.record_bytes);
+  h.chunk[1] = take((size_t)h.C * q.record_bytes);
+  h.lay = pass_layout(h.P, h.sh.B, q.record_bytes);
+  h.part = take(h.lay.bytes);
+  h.stage = take((size_t)h.P * q.record_bytes);
+  h.bytes = off;
+  return h;
+}
+
+// Largest pass that fits ws_bytes (0 if not even one record does).
+uint64_t pass_capacity(const elsar_fit_params& q, uint64_t n, uint64_t C, size_t ws_bytes) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint64_t mid = lo + (hi - lo + 1) / 2;
+    if (host_layout(q, n, C, mid).bytes <= ws_bytes) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct Streams {  // two copy streams and their events, released on every path
+  hipStream_t h2d = nullptr, d2h = nullptr;
+  hipEvent_t loaded[2] = {}, freed[2] = {}, sorted = nullptr, copied = nullptr;
+  ~Streams() {
+    if (h2d) (void)hipStreamDestroy(h2d);
+    if (d2h) (void)hipStreamDestroy(d2h);
+    for (auto e : loaded)
+      if (e) (void)hipEventDestroy(e);
+    for (auto e : freed)
+      if (e) (void)hipEventDestroy(e);
+    if (sorted) (void)hipEventDestroy(sorted);
+    if (copied) (void)hipEventDestroy(copied);
+  }
+  bool init() {
+    if (hipStreamCreateWithFlags(&h2d, hipStreamNonBlocking) != hipSuccess) return false;
+    if (hipStreamCreateWithFlags(&d2h, hipStreamNonBlocking) != hipSuccess) return false;
+    for (int i = 0; i < 2; ++i)
+      if (hipEventCreateWithFlags(&loaded[i], hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&freed[i], hipEventDisableTiming) != hipSuccess)
+        return false;
+    return hipEventCreateWithFlags(&sorted, hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&copied, hipEventDisableTiming) == hipSuccess;
+  }
+};
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Every chunk of the input through HBM: copy chunk c into buffer c % 2 on the
+// copy stream once the kernels that used the buffer are done, then run
+// body(buffer, first record, records) on the compute stream.
+template <typename Body>
+elsar_status stream_chunks(const uint8_t* h_in, uint64_t n, uint32_t R, const HostLayout& hl, uint8_t* w,
+                           Streams& ss, hipStream_t st, Body body) {
+  const uint64_t nchunks = (n + hl.C - 1) / hl.C;
+  for (uint64_t c = 0; c < nchunks; ++c) {
+    const int k = (int)(c & 1u);
+    const uint64_t first = c * hl.C, cnt = std::min<uint64_t>(hl.C, n - first);
+    uint8_t* buf = w + hl.chunk[k];
+    if (c >= 2) HIP_TRY(hipStreamWaitEvent(ss.h2d, ss.freed[k], 0));
+    HIP_TRY(hipMemcpyAsync(buf, h_in + first * R, cnt * R, hipMemcpyHostToDevice, ss.h2d));
+    HIP_TRY(hipEventRecord(ss.loaded[k], ss.h2d));
+    HIP_TRY(hipStreamWaitEvent(st, ss.loaded[k], 0));
+    elsar_status s = body(buf, first, cnt);
+    if (s != ELSAR_OK) return s;
+    HIP_TRY(hipEventRecord(ss.freed[k], st));
+  }
+  // the next user of the buffers is ordered after the last kernels
+  HIP_TRY(hipStreamWaitEvent(ss.h2d, ss.freed[0], 0));
+  if (nchunks > 1) HIP_TRY(hipStreamWaitEvent(ss.h2d, ss.freed[1], 0));
+  return ELSAR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+elsar_status elsar_sort_host_workspace_size(const elsar_fit_params* p, uint64_t n, uint64_t chunk_records,
+                                            uint64_t pass_records, size_t* bytes) {
+  if (!bytes) return ELSAR_E_INVALID_ARG;
+  elsar_status s = check_params(p);
+  if (s != ELSAR_OK) return s;
+  if (n > 0xFFFFFFFFull) return ELSAR_E_UNSUPPORTED;
+  const elsar_fit_params q = with_defaults(*p);
+  *bytes = host_layout(q, std::max<uint64_t>(n, 1), chunk_records, pass_records ? pass_records : n).bytes;
+  return ELSAR_OK;
+}
+
+elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, const elsar_fit_params* p,
+                             uint64_t chunk_records, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                             elsar_host_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  elsar_status s = check_params(p);
+  if (s != ELSAR_OK) return s;
+  if (n > 0xFFFFFFFFull) return ELSAR_E_UNSUPPORTED;  // input indices are 32-bit
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (n == 0) return ELSAR_OK;
+  if (!h_in || !h_out || !d_ws || !aligned16(d_ws) || !aligned16(h_in) || !aligned16(h_out))
+    return ELSAR_E_INVALID_ARG;
+  const elsar_fit_params q = with_defaults(*p);
+  const uint32_t R = q.record_bytes;
+  const uint8_t* in = static_cast<const uint8_t*>(h_in);
+  uint8_t* out = static_cast<uint8_t*>(h_out);
+  if (in < out + n * R && out < in + n * R) return ELSAR_E_INVALID_ARG;  // overlapping
+  const uint64_t P = pass_capacity(q, n, chunk_records, ws_bytes);
+  if (P == 0) return ELSAR_E_NO_MEMORY;
+  const HostLayout hl = host_layout(q, n, chunk_records, P);
+  uint8_t* w = static_cast<uint8_t*>(d_ws);
+  void* d_in_view = nullptr;  // the device's address of the pinned input
+  if (hipHostGetDevicePointer(&d_in_view, const_cast<void*>(h_in), 0) != hipSuccess || !d_in_view)
+    return ELSAR_E_INVALID_ARG;
+  Streams ss;
+  if (!ss.init()) return ELSAR_E_HIP;
+  // 1. sample (read from host memory by the device) and fit
+  elsar_model m{};
+  m.p = q;
+  m.B = hl.sh.B;
+  m.L = hl.sh.L;
+  m.S = hl.sh.S;
+  place_model(&m, w + hl.model);
+  s = do_fit(&m, d_in_view, n, w + hl.fit, fit_ws_bytes(hl.sh.S), stream);
+  if (s != ELSAR_OK) return s;
+  HIP_TRY(hipStreamSynchronize(stream));
+  const double t_fit = ms_since(t0);
+  // 2. counting pass
+  uint32_t* counts_all = reinterpret_cast<uint32_t*>(w + hl.counts);
+  HIP_TRY(launch_fill_u32(counts_all, m.B, 0u, stream));
+  const MlpState* ms = m.has_mlp ? &m.ms : nullptr;
+  s = stream_chunks(in, n, R, hl, w, ss, stream, [&](uint8_t* buf, uint64_t, uint64_t cnt) {
+    return launch_count(m.hdr, m.leaves, ms, buf, cnt, R, counts_all, stream) == hipSuccess ? ELSAR_OK
+                                                                                         : ELSAR_E_HIP;
+  });
+  if (s != ELSAR_OK) return s;
+  std::vector<uint32_t> counts(m.B);
+  HIP_TRY(hipMemcpyAsync(counts.data(), counts_all, (size_t)m.B * 4, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  const double t_count = ms_since(t0);
+  // 3. passes: consecutive bucket ranges whose records fit one pass
+  struct Pass {
+    uint32_t lo, hi;
+    uint64_t first, total;
+  };
+  std::vector<Pass> passes;
+  uint64_t done = 0;
+  for (uint32_t b = 0; b < m.B;) {
+    Pass ps{b, b, done, 0};
+    while (ps.hi < m.B && ps.total + counts[ps.hi] <= hl.P) ps.total += counts[ps.hi++];
+    if (ps.hi == ps.lo) return ELSAR_E_NO_MEMORY;  // one bucket is larger than a pass
+    passes.push_back(ps);
+    done += ps.total;
+    b = ps.hi;
+  }
+  if (done != n) return ELSAR_E_HIP;  // the counts must cover every record
+  uint8_t* part = w + hl.part;
+  uint8_t* stage = w + hl.stage;
+  uint64_t* offsets = reinterpret_cast<uint64_t*>(w + hl.offsets);
+  bool stage_busy = false;
+  for (const Pass& ps : passes) {
+    if (ps.total == 0) continue;
+    const uint32_t nb = ps.hi - ps.lo;
+    HIP_TRY(launch_exact_regions(counts_all, ps.lo, nb, ps.total, part, hl.lay, stream));
+    s = stream_chunks(in, n, R, hl, w, ss, stream, [&](uint8_t* buf, uint64_t first, uint64_t cnt) {
+      PassFilter f{first, ps.lo, ps.hi};
+      return launch_partition(m.hdr, m.leaves, ms, buf, cnt, R, q.key_bytes, part, hl.lay, stream, &f) ==
+                     hipSuccess
+                 ? ELSAR_OK
+                 : ELSAR_E_HIP;
+    });
+    if (s != ELSAR_OK) return s;
+    // the regions are exact: a record that found its region full means the
+    // counting and placing passes disagree; stop before anything reads it
+    PartHeader ph;
+    HIP_TRY(hipMemcpyAsync(&ph, part + hl.lay.header, sizeof(ph), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (ph.spill_count != 0) return ELSAR_E_HIP;
+    HIP_TRY(launch_scan_counts(part, hl.lay, nb, offsets, stream));
+    if (stage_busy) HIP_TRY(hipStreamWaitEvent(stream, ss.copied, 0));  // the previous pass's output is out
+    HIP_TRY(launch_bucket_sort_small(part, hl.lay, nb, offsets, R, q.key_bytes, stage, stream));
+    HIP_TRY(launch_bucket_sort_large(part, hl.lay, nb, offsets, R, q.key_bytes, stage, stream));
+    HIP_TRY(hipEventRecord(ss.sorted, stream));
+    HIP_TRY(hipStreamWaitEvent(ss.d2h, ss.sorted, 0));
+    HIP_TRY(hipMemcpyAsync(out + ps.first * R, stage, ps.total * R, hipMemcpyDeviceToHost, ss.d2h));
+    HIP_TRY(hipEventRecord(ss.copied, ss.d2h));
+    stage_busy = true;
+  }
+  HIP_TRY(hipStreamSynchronize(ss.d2h));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (stats) {
+    stats->chunk_records = hl.C;
+    stats->pass_records = hl.P;
+    stats->passes = (uint32_t)passes.size();
+    stats->num_buckets = m.B;
+    stats->fit_ms = (float)t_fit;
+    stats->count_ms = (float)(t_count - t_fit);
+    stats->total_ms = (float)ms_since(t0);
+    stats->passes_ms = stats->total_ms - (float)t_count;
+  }
   return ELSAR_OK;
 }
 

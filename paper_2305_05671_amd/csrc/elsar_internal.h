@@ -260,9 +260,18 @@ hipError_t launch_mlp_grad(const MlpBlock* M, const uint64_t* codes, const float
 constexpr uint32_t kMlpGradRows = 128;  // rows of one training step
 
 // partition (k_partition.hip)
+struct PassFilter {     // host tier: a chunk at input index idx_base, buckets lo .. hi-1 only
+  uint64_t idx_base;
+  uint32_t lo, hi;
+};
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const MlpState* ms, const uint8_t* recs,
                             uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint8_t* part,
-                            const PartLayout& lay, hipStream_t st);
+                            const PartLayout& lay, hipStream_t st, const PassFilter* filter = nullptr);
+hipError_t launch_count(const ModelHeader* hdr, const Leaf* leaves, const MlpState* ms, const uint8_t* recs,
+                        uint64_t n, uint32_t rec_bytes, uint32_t* counts, hipStream_t st);
+hipError_t launch_exact_regions(const uint32_t* counts_all, uint32_t lo, uint32_t nb, uint64_t total, uint8_t* part,
+                                const PartLayout& lay, hipStream_t st);
 hipError_t launch_scan_counts(uint8_t* part, const PartLayout& lay, uint32_t B, uint64_t* offsets,
                               hipStream_t st);
 hipError_t launch_spill_fixup(uint8_t* part, const PartLayout& lay, uint64_t n, hipStream_t st);

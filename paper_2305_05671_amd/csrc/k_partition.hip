@@ -9,6 +9,7 @@
 // bucket that outgrows its region continues in a shared spill area; the
 // spill entry remembers (bucket, rank within the bucket's overflow) so the
 // fix-up can group the spill without sorting it.
+#include <algorithm>
 #include <type_traits>
 
 #include "mlp_device.h"
@@ -83,13 +84,17 @@ __device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const
 // guess from which the exact leaf is found among the routing boundaries.  The
 // linear-root and the MLP-root kernels are both launched when a fit may
 // choose either; each returns at once unless the header names its root.
-template <int RW_T, bool MLP>
+//
+// FILTER (host tier): the records are one chunk of a larger input whose first
+// record has index f.idx_base; only buckets f.lo .. f.hi-1 are placed (bucket
+// b at local bucket b - f.lo), the others are skipped.
+template <int RW_T, bool MLP, bool FILTER>
 __global__ __launch_bounds__(kPartThreads) void partition_kernel(
     const ModelHeader* __restrict__ hdr, const Leaf* __restrict__ leaves, const MlpBlock* __restrict__ mlp,
     const uint64_t* __restrict__ bound, const uint8_t* __restrict__ recs,
     uint64_t n, uint32_t rw_rt, uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps,
     const uint32_t* __restrict__ rstart, PartHeader* __restrict__ ph, uint2* __restrict__ spill_meta,
-    uint4* __restrict__ slots, uint64_t cap_slots) {
+    uint4* __restrict__ slots, uint64_t cap_slots, PassFilter f) {
   const uint32_t RW = RW_T ? (uint32_t)RW_T : rw_rt;  // record dwords
   const uint32_t SC = slot_bytes_for(RW * 4) / 16;     // 16-byte chunks per slot
   constexpr uint32_t RV = RW_T ? (kPartTile * RW_T / 4 + kPartThreads - 1) / kPartThreads : 8;
@@ -116,9 +121,10 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
   // SC consecutive lanes write one slot as whole 16-byte chunks (whole lines)
   auto write_tile = [&](uint64_t t, const uint32_t* b, const uint32_t* dslot) {
     const uint32_t total = tile_count(t) * SC;
-    const uint32_t r0 = (uint32_t)(t * kPartTile);
-    for (uint32_t f = threadIdx.x; f < total; f += kPartThreads) {
-      uint32_t k = f / SC, c = f - k * SC;
+    const uint32_t r0 = (uint32_t)(FILTER ? f.idx_base + t * kPartTile : t * kPartTile);
+    for (uint32_t q = threadIdx.x; q < total; q += kPartThreads) {
+      uint32_t k = q / SC, c = q - k * SC;
+      if (FILTER && dslot[k] == kNoSlot) continue;
       slots[(uint64_t)dslot[k] * SC + c] = slot_chunk(b, RW, k, c, r0 + k);
     }
   };
@@ -155,23 +161,31 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
       if (threadIdx.x < cnt) {
         const uint32_t j = mlp_exact_leaf(bound, L, e, mlp_leaf_guess(y, L));
         b = leaf_bucket(load_leaf(leaves, j), e);
-        s = atomicAdd(&counts[b], 1u);
       }
     } else if (threadIdx.x < cnt) {
       const uint32_t* r = buf(cur) + threadIdx.x * RW;
       uint64_t e = key_code(r[0], r[1]);
       uint32_t j = rmi_leaf(a0, a1, L, e);
       b = leaf_bucket(load_leaf(leaves, j), e);
-      s = atomicAdd(&counts[b], 1u);
     }
+    bool keep = threadIdx.x < cnt;
+    if (FILTER) {
+      keep = keep && b >= f.lo && b < f.hi;
+      b -= f.lo;
+    }
+    if (keep) s = atomicAdd(&counts[b], 1u);
     // 3. the previous tile's slots, while the atomics are in flight
     if (have_prev) write_tile(tprev, buf(cur ^ 1), dst[cur ^ 1]);
     // 4. this tile's slots
-    if (threadIdx.x < cnt) {
+    if (FILTER && threadIdx.x < cnt && !keep) dst[cur][threadIdx.x] = kNoSlot;
+    if (keep) {
       uint32_t cap = caps[b];
       uint32_t slot;
       if (s < cap) {
         slot = rstart[b] + s;
+      } else if (FILTER) {  // exact regions leave no room: counted as an error, never placed
+        atomicAdd(&ph->spill_count, 1u);
+        slot = kNoSlot;
       } else {
         uint32_t q = atomicAdd(&ph->spill_count, 1u);
         spill_meta[q] = make_uint2(b, s - cap);
@@ -193,23 +207,23 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
   write_tile(tprev, buf(cur), dst[cur]);
 }
 
-template <bool MLP>
+template <bool MLP, bool FILTER>
 static void launch_partition_root(uint32_t grid, size_t lds, hipStream_t st, uint32_t RW, const ModelHeader* hdr,
                                   const Leaf* leaves, const MlpBlock* mlp, const uint64_t* bound,
                                   const uint8_t* recs, uint64_t n, uint32_t* counts, const uint32_t* caps,
                                   const uint32_t* rstart, PartHeader* ph, uint2* meta, uint4* slots,
-                                  uint64_t cap_slots) {
+                                  uint64_t cap_slots, PassFilter f) {
   if (RW == 25)
-    partition_kernel<25, MLP><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, recs, n, RW, counts, caps,
-                                                               rstart, ph, meta, slots, cap_slots);
+    partition_kernel<25, MLP, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, recs, n, RW, counts,
+                                                                       caps, rstart, ph, meta, slots, cap_slots, f);
   else
-    partition_kernel<0, MLP><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, recs, n, RW, counts, caps,
-                                                              rstart, ph, meta, slots, cap_slots);
+    partition_kernel<0, MLP, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, recs, n, RW, counts,
+                                                                      caps, rstart, ph, meta, slots, cap_slots, f);
 }
 
 hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const MlpState* ms, const uint8_t* recs,
                             uint64_t n, uint32_t rec_bytes, uint32_t /*key_bytes*/, uint8_t* part,
-                            const PartLayout& lay, hipStream_t st) {
+                            const PartLayout& lay, hipStream_t st, const PassFilter* filter) {
   if (n == 0) return hipSuccess;
   const uint32_t RW = rec_bytes / 4;
   const size_t lds = 2 * (size_t)kPartTile * RW * 4;
@@ -221,11 +235,128 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const Ml
   auto* ph = reinterpret_cast<PartHeader*>(part + lay.header);
   auto* meta = reinterpret_cast<uint2*>(part + lay.spill_meta);
   auto* slots = reinterpret_cast<uint4*>(part + lay.slots);
-  launch_partition_root<false>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, recs, n, counts, caps, rstart, ph,
-                               meta, slots, lay.cap_slots);
-  if (ms)
-    launch_partition_root<true>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, recs, n, counts, caps,
-                                rstart, ph, meta, slots, lay.cap_slots);
+  const PassFilter f = filter ? *filter : PassFilter{0, 0, 0};
+  if (filter) {
+    launch_partition_root<false, true>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, recs, n, counts, caps,
+                                       rstart, ph, meta, slots, lay.cap_slots, f);
+    if (ms)
+      launch_partition_root<true, true>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, recs, n, counts, caps,
+                                        rstart, ph, meta, slots, lay.cap_slots, f);
+  } else {
+    launch_partition_root<false, false>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, recs, n, counts, caps,
+                                        rstart, ph, meta, slots, lay.cap_slots, f);
+    if (ms)
+      launch_partition_root<true, false>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, recs, n, counts,
+                                         caps, rstart, ph, meta, slots, lay.cap_slots, f);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- host tier --
+// Bucket counts of one chunk of records (no placement).  A wave takes 64
+// consecutive records; lanes past the end evaluate a clamped copy and drop it.
+template <bool MLP>
+__global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restrict__ hdr,
+                                                    const Leaf* __restrict__ leaves, const MlpBlock* __restrict__ mlp,
+                                                    const uint64_t* __restrict__ bound, const uint32_t* __restrict__ rec,
+                                                    uint64_t n, uint32_t RW, uint32_t* __restrict__ counts) {
+  if ((hdr->kind_used == 1u) != MLP) return;
+  __shared__ typename std::conditional<MLP, MlpHead, uint32_t>::type mh_;
+  W2Frags w2;
+  if constexpr (MLP) {
+    for (uint32_t i = threadIdx.x; i < sizeof(MlpHead) / 4; i += blockDim.x)
+      reinterpret_cast<uint32_t*>(&mh_)[i] = reinterpret_cast<const uint32_t*>(&mlp->h)[i];
+    mlp_load_w2(mlp->W2bf, w2);
+    __syncthreads();
+  }
+  const float a0 = hdr->a0, a1 = hdr->a1;
+  const uint32_t L = hdr->L;
+  const uint64_t wave0 = ((uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u));
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = wave0; base < n; base += stride) {  // uniform per wave
+    const uint64_t i = base + lane_id();
+    const uint32_t* r = rec + (i < n ? i : n - 1) * RW;
+    const uint64_t e = key_code(r[0], r[1]);
+    uint32_t b;
+    if constexpr (MLP) {
+      const float y = mlp_y64(e, mh_, w2);
+      b = leaf_bucket(load_leaf(leaves, mlp_exact_leaf(bound, L, e, mlp_leaf_guess(y, L))), e);
+    } else {
+      b = leaf_bucket(load_leaf(leaves, rmi_leaf(a0, a1, L, e)), e);
+    }
+    if (i < n) atomicAdd(&counts[b], 1u);
+  }
+}
+
+hipError_t launch_count(const ModelHeader* hdr, const Leaf* leaves, const MlpState* ms, const uint8_t* recs,
+                        uint64_t n, uint32_t rec_bytes, uint32_t* counts, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const uint32_t RW = rec_bytes / 4;
+  const uint64_t waves = (n + 63) / 64;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((waves + 3) / 4, 4096);
+  const uint32_t* rec = reinterpret_cast<const uint32_t*>(recs);
+  count_kernel<false><<<grid, 256, 0, st>>>(hdr, leaves, nullptr, nullptr, rec, n, RW, counts);
+  if (ms) count_kernel<true><<<grid, 256, 0, st>>>(hdr, ms->leaves, ms->M, ms->bound, rec, n, RW, counts);
+  return hipGetLastError();
+}
+
+// One pass of the host tier places buckets lo .. hi-1 in exact regions:
+// caps[j] = counts_all[lo + j], rstart = their exclusive sum, counts zeroed,
+// header set for total records and hi - lo buckets.  One block.
+constexpr uint32_t kExThreads = 1024;
+constexpr uint32_t kExPer = 8;
+
+__global__ __launch_bounds__(kExThreads) void exact_regions_kernel(const uint32_t* __restrict__ counts_all,
+                                                                   uint32_t lo, uint32_t nb, uint64_t total,
+                                                                   uint32_t* __restrict__ caps,
+                                                                   uint32_t* __restrict__ rstart,
+                                                                   uint32_t* __restrict__ counts,
+                                                                   PartHeader* __restrict__ ph) {
+  __shared__ uint64_t sh[kExThreads / 64 + 1];
+  uint64_t carry = 0;
+  for (uint32_t base = 0; base < nb; base += kExThreads * kExPer) {
+    uint32_t c[kExPer];
+    uint64_t sum = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kExPer; ++i) {
+      const uint32_t j = base + threadIdx.x * kExPer + i;
+      c[i] = j < nb ? counts_all[lo + j] : 0u;
+      sum += c[i];
+    }
+    uint64_t tot;
+    uint64_t run = block_exclusive_scan<uint64_t, kExThreads>(sum, sh, &tot) + carry;
+#pragma unroll
+    for (uint32_t i = 0; i < kExPer; ++i) {
+      const uint32_t j = base + threadIdx.x * kExPer + i;
+      if (j < nb) {
+        caps[j] = c[i];
+        rstart[j] = (uint32_t)run;
+        counts[j] = 0;
+      }
+      run += c[i];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    ph->n = total;
+    ph->cap_slots = total;
+    ph->B = nb;
+    ph->spill_count = 0;
+    ph->n_mid = 0;
+    ph->n_big = 0;
+    ph->max_count = 0;
+    ph->mid_records = 0;
+    ph->big_records = 0;
+  }
+}
+
+hipError_t launch_exact_regions(const uint32_t* counts_all, uint32_t lo, uint32_t nb, uint64_t total, uint8_t* part,
+                                const PartLayout& lay, hipStream_t st) {
+  exact_regions_kernel<<<1, kExThreads, 0, st>>>(counts_all, lo, nb, total,
+                                                 reinterpret_cast<uint32_t*>(part + lay.caps),
+                                                 reinterpret_cast<uint32_t*>(part + lay.rstart),
+                                                 reinterpret_cast<uint32_t*>(part + lay.counts),
+                                                 reinterpret_cast<PartHeader*>(part + lay.header));
   return hipGetLastError();
 }
 
