@@ -39,6 +39,10 @@ WORKLOADS = {
                                  "of records on 1000 hot keys, seed 2, 65536 buckets"),
     "uniform-1M": dict(kind="uniform", seed=0, n=1_000_000, buckets=1024,
                        desc="1M x 100B, uniform printable 10-byte keys, seed 0, 1024 buckets"),
+    "host-1B": dict(kind="host", gen="mixed", seed=4, n=1_000_000_000, pass_records=400_000_000,
+                    desc="1.0e9 x 100B (100 GB) in pageable host memory, sorted into pageable host memory; keys per "
+                         "record uniform or skewed-with-hot-keys with p 0.5; seed 4; 4 GB chunks; passes of at "
+                         "most 4e8 records in HBM; MLP root with linear-root fallback"),
     "batch-4096": dict(kind="batch", seed=3, jobs=4096,
                        desc="4096 independent jobs, sizes log-uniform in [1K, 4M] records x 100B, even jobs "
                             "uniform keys, odd jobs Zipf(1.1) first byte; seed 3; in place; one graph launch"),
@@ -51,7 +55,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform-100M", choices=sorted(WORKLOADS))
-    ap.add_argument("--model", default="rmi", choices=["rmi", "mlp", "auto"])
+    ap.add_argument("--model", default=None, choices=["rmi", "mlp", "auto"],
+                    help="CDF root (default: mlp for the host workload, rmi otherwise)")
     ap.add_argument("--leaves", type=int, default=0, help="RMI leaves L (0: buckets / 16)")
     ap.add_argument("--mlp-steps", type=int, default=0, help="Adam steps of the MLP fit (0: library default)")
     ap.add_argument("--accept-ratio", type=float, default=1.5,
@@ -109,6 +114,114 @@ def cpu_baseline(wl, n_cpu):
     return {"value": n_cpu / dt, "unit": "records/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n_cpu} records of the same workload (same generator and seed), "
                       f"single-threaded qsort of record indices by (memcmp key, index), {dt:.1f} s"}
+
+
+def check_host_output(h_in, h_out, n, threads=16, probes=8, seed=0):
+    """Oracle checks of a host-sized output, split over threads (ctypes calls
+    run without the GIL): key order across the whole output, the same multiset
+    of records as the input, and the exact output position of a few input
+    records (their stable rank, counted over the whole input)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+    R = RECORD_BYTES
+    pin, pout = h_in.data_ptr(), h_out.data_ptr()
+    seg = (n + threads - 1) // threads
+    parts = [(k * seg, min(n, (k + 1) * seg + 1)) for k in range(threads) if k * seg < n]  # overlap by one
+    halves = [(a, min(a + seg, n)) for a, _ in parts]
+    with ThreadPoolExecutor(threads) as ex:
+        unsorted = list(ex.map(lambda ab: oracle.first_unsorted_ptr(pout + ab[0] * R, ab[1] - ab[0]), parts))
+        hin = list(ex.map(lambda ab: oracle.multiset_hash_ptr(pin + ab[0] * R, ab[1] - ab[0]), halves))
+        hout = list(ex.map(lambda ab: oracle.multiset_hash_ptr(pout + ab[0] * R, ab[1] - ab[0]), halves))
+        rng = np.random.default_rng(seed)
+        idx = [int(x) for x in rng.integers(0, n, probes)]
+        src = h_in.numpy()
+        keys = [bytes(src[i * R:i * R + 10]) for i in idx]
+        ranks = list(ex.map(lambda q: oracle.rank_of_ptr(pin, n, q[0], q[1]), zip(keys, idx)))
+    ok_sorted = all(u == ab[1] - ab[0] for u, ab in zip(unsorted, parts))
+    mask = (1 << 64) - 1
+    ok_hash = (sum(hin) & mask) == (sum(hout) & mask)
+    dst = h_out.numpy()
+    ok_probe = all(np.array_equal(src[i * R:(i + 1) * R], dst[r * R:(r + 1) * R]) for i, r in zip(idx, ranks))
+    return {"sorted": ok_sorted, "multiset": ok_hash, "probes": probes, "probes_ok": ok_probe}
+
+
+def bench_host(args, wl):
+    """The host tier: records in pinned host memory sorted into pinned host
+    memory; each step is one elsar_sort_host call, timed on the host around
+    the call (it returns when the output is complete)."""
+    import torch
+
+    import datagen
+    import paper_2305_05671_amd as elsar
+
+    n, seed = wl["n"], wl["seed"]
+    args.model = args.model or "mlp"
+    kind = {"rmi": elsar.RMI, "mlp": elsar.MLP, "auto": elsar.AUTO}[args.model]
+    params = elsar.fit_params(seed=seed, kind=kind, accept_ratio=args.accept_ratio, mlp_steps=args.mlp_steps)
+    t0 = time.perf_counter()
+    # pageable host memory: the box pins only a few tens of GB in total
+    h_in = torch.empty(n * RECORD_BYTES, dtype=torch.uint8)
+    h_out = torch.empty(n * RECORD_BYTES, dtype=torch.uint8)
+    # the input, generated on the GPU in slices and copied to host memory
+    sp = datagen.spec(wl["gen"], seed=seed)
+    step = 50_000_000
+    tmp = torch.empty(step * RECORD_BYTES, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    for a in range(0, n, step):
+        c = min(step, n - a)
+        datagen.generate_device(sp, tmp.data_ptr(), a, c, stream)
+        h_in[a * RECORD_BYTES:(a + c) * RECORD_BYTES].copy_(tmp[:c * RECORD_BYTES])
+        if (a // step) % 4 == 3:
+            print(f"bench: generated {(a + c) / 1e9:.2f} G records", file=sys.stderr, flush=True)
+    del tmp
+    torch.cuda.synchronize()
+    ws = torch.empty(elsar.sort_host_workspace_size(n, params, 0, wl["pass_records"]), dtype=torch.uint8,
+                     device="cuda")
+    print(f"bench: {n / 1e9:.2f} G records in pinned host memory, workspace {ws.numel() / 1e9:.1f} GB, "
+          f"set up in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        elsar.sort_host(h_in, h_out, params, workspace=ws)
+    ms = []
+    st = None
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        st = elsar.sort_host(h_in, h_out, params, workspace=ws)
+        ms.append((time.perf_counter() - t1) * 1e3)
+        print(f"bench: step {ms[-1]:.0f} ms (fit {st.fit_ms:.0f}, count {st.count_ms:.0f}, "
+              f"{st.passes} passes {st.passes_ms:.0f})", file=sys.stderr, flush=True)
+    ms_per_step = sum(ms) / len(ms)
+    t2 = time.perf_counter()
+    chk = check_host_output(h_in, h_out, n)
+    print(f"bench: oracle checks {chk} in {time.perf_counter() - t2:.1f} s", file=sys.stderr, flush=True)
+    pcie_bytes = (2 + st.passes) * n * RECORD_BYTES  # counting pass + one read per pass + the output
+    result = {
+        "metric": "sorted records/s (100-byte records, host memory to host memory through one GPU)",
+        "value": n / (ms_per_step * 1e-3),
+        "unit": "records/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "records": n, "record_bytes": RECORD_BYTES,
+                   "model": args.model, "buckets": st.num_buckets, "chunk_records": st.chunk_records,
+                   "pass_records": st.pass_records, "passes": st.passes, "parallelism": "single GPU"},
+        "phases_ms": {"fit": round(st.fit_ms, 1), "count_pass": round(st.count_ms, 1),
+                      "sort_passes": round(st.passes_ms, 1)},
+        "pcie_GBps": round(pcie_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+        "step_ms": [round(x, 1) for x in ms],
+        "oracle_checks": chk,
+    }
+    print(json.dumps(result), flush=True)
+    if not (chk["sorted"] and chk["multiset"] and chk["probes_ok"]):
+        sys.exit(1)
 
 
 def bench_batch(args, wl):
@@ -213,7 +326,10 @@ def main():
     wl = WORKLOADS[args.workload]
     if wl["kind"] == "batch":
         return bench_batch(args, wl)
+    if wl["kind"] == "host":
+        return bench_host(args, wl)
     n = wl["n"]
+    args.model = args.model or "rmi"
     kind = {"rmi": elsar.RMI, "mlp": elsar.MLP, "auto": elsar.AUTO}[args.model]
     params = elsar.fit_params(num_buckets=wl["buckets"], num_leaves=args.leaves, seed=wl["seed"], kind=kind,
                               mlp_steps=args.mlp_steps, accept_ratio=args.accept_ratio)

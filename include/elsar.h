@@ -192,17 +192,18 @@ elsar_status elsar_sort_host_workspace_size(const elsar_fit_params* p, uint64_t 
 
 /*
  * The external tier (the paper's larger-than-memory setting, Section 3, with
- * host memory in the role of the external store): n records in pinned host
- * memory h_in (allocated with hipHostMalloc or another pinned allocator, so
- * that the device can read it) are sorted into host memory h_out, which must
- * not overlap h_in (pinned for full copy speed).  The sample is read by the
- * GPU straight from h_in; a counting pass streams every chunk to HBM and
- * counts its records per bucket; then each pass streams the chunks again and
- * places only a range of consecutive buckets whose records fit the workspace,
- * in regions of exact size, sorts them and copies them to h_out at their
- * offsets -- the concatenation of Section 3.5 at host level.  Copies run on
- * streams of their own, double buffered against the kernels on `stream`.
- * d_ws: workspace; its size bounds the records held in HBM at once (see
+ * host memory in the role of the external store): n records in host memory
+ * h_in are sorted into host memory h_out, which must not overlap h_in.  Either
+ * may be pageable; pinned memory (hipHostMalloc or another pinned allocator)
+ * copies at full link speed.  The sample is drawn from the first chunk (the
+ * paper samples from the first batch that one reader reads, Section 3.1); a
+ * counting pass streams every chunk to HBM and counts its records per bucket;
+ * then each pass streams the chunks again and places only a range of
+ * consecutive buckets whose records fit the workspace, in regions of exact
+ * size, sorts them and copies them to h_out at their offsets -- the
+ * concatenation of Section 3.5 at host level.  Copies run on streams of their
+ * own, double buffered against the kernels on `stream`.  d_ws: workspace; its
+ * size bounds the records held in HBM at once (see
  * elsar_sort_host_workspace_size).  Synchronous: returns when h_out is
  * complete.  n < 2^32.  ELSAR_E_NO_MEMORY when one bucket alone exceeds what
  * a pass can hold.  stats may be NULL.

@@ -271,17 +271,16 @@ def sort_host_workspace_size(n: int, params: FitParams | None = None, chunk_reco
 
 def sort_host(h_in, h_out, params: FitParams | None = None, chunk_records: int = 0, pass_records: int = 0,
               workspace=None, stream=None) -> HostStats:
-    """elsar_sort_host: records in pinned host memory (uint8 CPU tensors made
-    with pin_memory=True) sorted into h_out.  The device workspace is sized
-    for passes of ``pass_records`` records (0: the whole input in one pass)
-    unless one is given.  Synchronous; returns the call's statistics."""
+    """elsar_sort_host: records in host memory (uint8 CPU tensors; pinned ones,
+    made with pin_memory=True, copy fastest) sorted into h_out.  The device
+    workspace is sized for passes of ``pass_records`` records (0: the whole
+    input in one pass) unless one is given.  Synchronous; returns the call's
+    statistics."""
     import torch
     params = params or fit_params()
     for t in (h_in, h_out):
         if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or t.is_cuda or not t.is_contiguous():
             raise TypeError("host records must be contiguous uint8 CPU tensors")
-    if not h_in.is_pinned():
-        raise TypeError("the input must be pinned host memory")
     n = h_in.numel() // params.record_bytes
     if h_in.numel() % params.record_bytes or h_out.numel() != h_in.numel():
         raise ValueError("input and output must hold the same whole number of records")

@@ -807,19 +807,19 @@ elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, const el
   if (P == 0) return ELSAR_E_NO_MEMORY;
   const HostLayout hl = host_layout(q, n, chunk_records, P);
   uint8_t* w = static_cast<uint8_t*>(d_ws);
-  void* d_in_view = nullptr;  // the device's address of the pinned input
-  if (hipHostGetDevicePointer(&d_in_view, const_cast<void*>(h_in), 0) != hipSuccess || !d_in_view)
-    return ELSAR_E_INVALID_ARG;
   Streams ss;
   if (!ss.init()) return ELSAR_E_HIP;
-  // 1. sample (read from host memory by the device) and fit
+  // 1. sample and fit on the first chunk (the paper samples from the first
+  //    batch one reader reads), streamed to HBM like every chunk
   elsar_model m{};
   m.p = q;
   m.B = hl.sh.B;
   m.L = hl.sh.L;
-  m.S = hl.sh.S;
+  const uint64_t c0 = std::min<uint64_t>(hl.C, n);
+  m.S = std::min<uint64_t>(hl.sh.S, c0);
   place_model(&m, w + hl.model);
-  s = do_fit(&m, d_in_view, n, w + hl.fit, fit_ws_bytes(hl.sh.S), stream);
+  HIP_TRY(hipMemcpyAsync(w + hl.chunk[0], in, c0 * R, hipMemcpyHostToDevice, stream));
+  s = do_fit(&m, w + hl.chunk[0], c0, w + hl.fit, fit_ws_bytes(hl.sh.S), stream);
   if (s != ELSAR_OK) return s;
   HIP_TRY(hipStreamSynchronize(stream));
   const double t_fit = ms_since(t0);

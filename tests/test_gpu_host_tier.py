@@ -18,23 +18,26 @@ def env():
     return torch, elsar
 
 
-def _pinned(torch, recs):
-    t = torch.empty(recs.size, dtype=torch.uint8, pin_memory=True)
+def _pinned(torch, recs, pinned=True):
+    t = torch.empty(recs.size, dtype=torch.uint8, pin_memory=pinned)
     t.numpy()[:] = recs.reshape(-1)
     return t
 
 
-@pytest.mark.parametrize("kind,n,chunk,pass_records,B", [
-    ("uniform", 3_000_001, 250_000, 700_000, 0),   # several chunks (ragged last), five passes
-    ("skewed", 2_000_000, 333_333, 900_000, 0),    # hot keys: buckets above the LDS caps inside passes
-    ("zipf", 1_500_000, 0, 0, 1024),               # one chunk, one pass
-    ("mixed", 777_777, 100_000, 250_000, 512),
+@pytest.mark.parametrize("kind,n,chunk,pass_records,B,pinned", [
+    ("uniform", 3_000_001, 250_000, 700_000, 0, True),   # several chunks (ragged last), five passes
+    ("skewed", 2_000_000, 333_333, 900_000, 0, True),    # hot keys: buckets above the LDS caps inside passes
+    ("zipf", 1_500_000, 0, 0, 1024, True),               # one chunk, one pass
+    ("mixed", 777_777, 100_000, 250_000, 512, False),    # pageable host memory
+    ("uniform", 1_000_000, 30_000, 300_000, 0, False),   # sample from a first chunk smaller than S
 ])
-def test_host_tier_matches_oracle(env, kind, n, chunk, pass_records, B):
+def test_host_tier_matches_oracle(env, kind, n, chunk, pass_records, B, pinned):
     torch, elsar = env
     recs = datagen.generate(datagen.spec(kind, seed=41), n)
-    h_in = _pinned(torch, recs)
-    h_out = torch.zeros_like(h_in).pin_memory()
+    h_in = _pinned(torch, recs, pinned)
+    h_out = torch.zeros_like(h_in)
+    if pinned:
+        h_out = h_out.pin_memory()
     st = elsar.sort_host(h_in, h_out, elsar.fit_params(num_buckets=B, seed=41), chunk_records=chunk,
                          pass_records=pass_records)
     if pass_records:
