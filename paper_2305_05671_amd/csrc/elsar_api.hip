@@ -411,8 +411,11 @@ uint32_t ceil_log2(uint64_t n) {
 
 uint32_t tuned_buckets(uint64_t n) {
   const uint32_t r = ceil_log2(n);
-  const uint32_t b = r < kAutotuneRows ? kAutotuneBuckets[r] : 0u;
-  return b ? b : default_buckets(n);
+  const uint32_t per = r < kAutotuneRows ? kAutotuneRecordsPerBucket[r] : 0u;
+  if (per == 0) return default_buckets(n);
+  uint32_t b = 1;
+  while ((uint64_t)b * 2 * per <= n && b < kMaxBuckets) b *= 2;
+  return b;
 }
 
 elsar_fit_params job_params(const elsar_fit_params& p, uint64_t n, uint32_t j) {
