@@ -371,8 +371,13 @@ elsar_status elsar_sort_workspace_size(const elsar_fit_params* p, uint64_t n, si
 namespace {
 
 // One whole sort on device-resident records; q has its defaults filled in.
+// A model fitted ahead of the job (batch): where it lives.
+struct Prefit {
+  uint8_t* base;  // model_dev_bytes(L, B, RMI) bytes, placed as place_model does
+};
+
 elsar_status sort_job(const void* d_in, uint64_t n, void* d_out, const elsar_fit_params& q, void* d_ws,
-                      size_t ws_bytes, hipStream_t stream, bool timed) {
+                      size_t ws_bytes, hipStream_t stream, bool timed, const Prefit* pre = nullptr) {
   Shape sh = resolve(q, n);
   SortLayout sl = sort_layout(q, sh, n);
   if (ws_bytes < sl.bytes) return ELSAR_E_NO_MEMORY;
@@ -387,11 +392,16 @@ elsar_status sort_job(const void* d_in, uint64_t n, void* d_out, const elsar_fit
   m.L = sh.L;
   m.S = sh.S;
   m.dev = nullptr;
-  place_model(&m, w + sl.model);
+  place_model(&m, pre ? pre->base : w + sl.model);
   uint64_t* offsets = reinterpret_cast<uint64_t*>(w + sl.offsets);
   PhaseMarks pm = timed ? begin_marks() : PhaseMarks{};
   mark(pm, 0, stream);
-  elsar_status s = do_fit(&m, d_in, n, w + sl.fit, fit_ws_bytes(sh.S), stream);
+  elsar_status s = ELSAR_OK;
+  if (pre) {
+    m.n = n;  // fitted already, by the batch's fit kernel
+  } else {
+    s = do_fit(&m, d_in, n, w + sl.fit, fit_ws_bytes(sh.S), stream);
+  }
   if (s != ELSAR_OK) return s;
   s = do_partition(&m, d_in, n, w + sl.part, sl.lay.bytes, offsets, stream, &pm);
   if (s != ELSAR_OK) return s;
@@ -427,6 +437,10 @@ elsar_fit_params job_params(const elsar_fit_params& p, uint64_t n, uint32_t j) {
 
 struct BatchLayout {
   std::vector<TinyJob> tiny;
+  std::vector<uint32_t> prefit;       // jobs whose model the batch fit kernel fits
+  std::vector<size_t> prefit_model;   // workspace offset of each such job's model
+  std::vector<int32_t> prefit_of;     // per job: index into prefit, or -1
+  size_t fit_desc = 0;
   std::vector<std::vector<uint32_t>> lanes;  // job indices per lane, largest first
   size_t tiny_desc = 0, tiny_stage = 0, bytes = 0;
   std::vector<size_t> lane_off, lane_bytes;
@@ -453,6 +467,16 @@ elsar_status batch_layout(const elsar_job* jobs, uint32_t njobs, const elsar_fit
       big.push_back(j);
     }
   }
+  // jobs whose sample fits LDS get their model from one batched kernel
+  bl->prefit_of.assign(njobs, -1);
+  if (p.kind == ELSAR_MODEL_RMI)
+    for (uint32_t j : big) {
+      const elsar_fit_params q = job_params(p, jobs[j].n, j);
+      if (resolve(q, jobs[j].n).S <= kBatchFitMaxS) {
+        bl->prefit_of[j] = (int32_t)bl->prefit.size();
+        bl->prefit.push_back(j);
+      }
+    }
   // longest job first to the least loaded lane
   std::stable_sort(big.begin(), big.end(), [&](uint32_t a, uint32_t b) { return jobs[a].n > jobs[b].n; });
   const uint32_t nl = std::min<uint32_t>(kBatchLanes, (uint32_t)big.size());
@@ -470,6 +494,14 @@ elsar_status batch_layout(const elsar_job* jobs, uint32_t njobs, const elsar_fit
   size_t off = 0;
   bl->tiny_desc = off;
   off += align_up(bl->tiny.size() * sizeof(TinyJob));
+  bl->fit_desc = off;
+  off += align_up(bl->prefit.size() * sizeof(FitJob));
+  for (uint32_t j : bl->prefit) {
+    const elsar_fit_params q = job_params(p, jobs[j].n, j);
+    const Shape sh = resolve(q, jobs[j].n);
+    bl->prefit_model.push_back(off);
+    off += align_up(model_dev_bytes(sh.L, sh.B, ELSAR_MODEL_RMI));
+  }
   bl->tiny_stage = off;
   off += align_up(stage_dw * 4);
   bl->lane_off.assign(nl, 0);
@@ -481,9 +513,37 @@ elsar_status batch_layout(const elsar_job* jobs, uint32_t njobs, const elsar_fit
   return ELSAR_OK;
 }
 
+std::vector<FitJob> fit_descriptors(const elsar_job* jobs, const elsar_fit_params& p, const BatchLayout& bl,
+                                    uint8_t* w) {
+  std::vector<FitJob> out;
+  for (size_t k = 0; k < bl.prefit.size(); ++k) {
+    const uint32_t j = bl.prefit[k];
+    const elsar_fit_params q = job_params(p, jobs[j].n, j);
+    const Shape sh = resolve(q, jobs[j].n);
+    elsar_model m{};
+    m.p = q;
+    m.B = sh.B;
+    m.L = sh.L;
+    place_model(&m, w + bl.prefit_model[k]);
+    FitJob f{};
+    f.recs = static_cast<const uint8_t*>(jobs[j].d_in);
+    f.n = jobs[j].n;
+    f.S = sh.S;
+    f.seed = q.seed;
+    f.L = sh.L;
+    f.B = sh.B;
+    f.hdr = m.hdr;
+    f.leaves = m.leaves;
+    f.hist = m.hist;
+    out.push_back(f);
+  }
+  return out;
+}
+
 struct BatchPlan {
   std::vector<uint8_t> key;
-  std::vector<TinyJob> tiny;  // source of the per-launch descriptor upload
+  std::vector<FitJob> fit;    // source of the per-launch descriptor uploads
+  std::vector<TinyJob> tiny;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -512,13 +572,17 @@ elsar_status enqueue_batch(const elsar_job* jobs, const elsar_fit_params& p, con
   if (!bl.tiny.empty())
     HIP_TRY(launch_tiny_jobs(reinterpret_cast<const TinyJob*>(w + bl.tiny_desc), (uint32_t)bl.tiny.size(),
                              p.record_bytes, p.key_bytes, reinterpret_cast<uint32_t*>(w + bl.tiny_stage), cap));
+  if (!bl.prefit.empty())
+    HIP_TRY(launch_batch_fit(reinterpret_cast<const FitJob*>(w + bl.fit_desc), (uint32_t)bl.prefit.size(),
+                             p.record_bytes, cap));
   HIP_TRY(hipEventRecord(fork, cap));
   for (size_t l = 0; l < bl.lanes.size(); ++l) {
     HIP_TRY(hipStreamWaitEvent(lanes[l], fork, 0));
     for (uint32_t j : bl.lanes[l]) {
       const elsar_fit_params q = job_params(p, jobs[j].n, j);
+      Prefit pre{bl.prefit_of[j] >= 0 ? w + bl.prefit_model[bl.prefit_of[j]] : nullptr};
       elsar_status s = sort_job(jobs[j].d_in, jobs[j].n, jobs[j].d_out, q, w + bl.lane_off[l], bl.lane_bytes[l],
-                                lanes[l], false);
+                                lanes[l], false, pre.base ? &pre : nullptr);
       if (s != ELSAR_OK) return s;
     }
     HIP_TRY(hipEventRecord(done[l], lanes[l]));
@@ -620,6 +684,7 @@ elsar_status elsar_sort_batch(const elsar_job* h_jobs, uint32_t njobs, const els
     BatchPlan plan;
     plan.key = std::move(key);
     plan.tiny = bl.tiny;
+    plan.fit = fit_descriptors(h_jobs, *p, bl, w);
     s = build_plan(h_jobs, *p, bl, w, &plan);
     if (s != ELSAR_OK) return s;
     if (g_plans.size() >= kMaxPlans) {  // the oldest plan may still run: wait before freeing it
@@ -639,6 +704,9 @@ elsar_status elsar_sort_batch(const elsar_job* h_jobs, uint32_t njobs, const els
   // caller may have used the workspace for something else in between
   if (!it->tiny.empty())
     HIP_TRY(hipMemcpyAsync(w + bl.tiny_desc, it->tiny.data(), it->tiny.size() * sizeof(TinyJob),
+                           hipMemcpyHostToDevice, stream));
+  if (!it->fit.empty())
+    HIP_TRY(hipMemcpyAsync(w + bl.fit_desc, it->fit.data(), it->fit.size() * sizeof(FitJob),
                            hipMemcpyHostToDevice, stream));
   HIP_TRY(hipGraphLaunch(it->exec, stream));
   return ELSAR_OK;

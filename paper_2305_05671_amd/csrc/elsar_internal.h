@@ -232,6 +232,17 @@ hipError_t launch_fit_rmi(const uint64_t* sorted_codes, uint64_t S, uint64_t n, 
                           ModelHeader* hdr, Leaf* leaves, void* scratch, hipStream_t st);
 hipError_t launch_sample_hist(const ModelHeader* hdr, const Leaf* leaves, const uint64_t* sorted_codes,
                               uint64_t S, uint32_t B, uint32_t* hist, hipStream_t st);
+// batch: one block fits the model of one job whose sample fits LDS
+constexpr uint64_t kBatchFitMaxS = 16384;
+struct FitJob {
+  const uint8_t* recs;   // the job's records (device)
+  uint64_t n, S, seed;
+  uint32_t L, B;
+  ModelHeader* hdr;
+  Leaf* leaves;          // L
+  uint32_t* hist;        // B
+};
+hipError_t launch_batch_fit(const FitJob* d_jobs, uint32_t njobs, uint32_t rec_bytes, hipStream_t st);
 hipError_t launch_capacities(const uint32_t* hist, uint64_t S, uint64_t n, uint32_t B, uint32_t region_pct,
                              uint8_t* part, const PartLayout& lay, hipStream_t st);
 

@@ -10,15 +10,20 @@
 namespace elsar {
 
 // ------------------------------------------------------------- sampling --
+// Record of sample s: uniform (one Philox draw) within the stratum
+// [floor(s n / S), floor((s+1) n / S)).
+__device__ __forceinline__ uint64_t sample_index(uint64_t s, uint64_t n, uint64_t S, uint64_t seed) {
+  const uint64_t lo = s * n / S, hi = (s + 1) * n / S;
+  const uint32_t u = philox_x(s, 0x53414D50u, 0u, seed);
+  return lo + (((uint64_t)u * (hi - lo)) >> 32);
+}
+
 __global__ __launch_bounds__(256) void sample_codes_kernel(const uint8_t* __restrict__ recs, uint64_t n,
                                                            uint32_t rec_bytes, uint64_t S, uint64_t seed,
                                                            uint64_t* __restrict__ codes) {
   uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (s >= S) return;
-  uint64_t lo = s * n / S, hi = (s + 1) * n / S;
-  uint32_t u = philox_x(s, 0x53414D50u, 0u, seed);
-  uint64_t i = lo + (((uint64_t)u * (hi - lo)) >> 32);
-  const uint32_t* r = reinterpret_cast<const uint32_t*>(recs + i * rec_bytes);
+  const uint32_t* r = reinterpret_cast<const uint32_t*>(recs + sample_index(s, n, S, seed) * rec_bytes);
   codes[s] = key_code(r[0], r[1]);
 }
 
@@ -211,6 +216,20 @@ __global__ __launch_bounds__(kFitThreads) void root_moments_kernel(const uint64_
   }
 }
 
+// Least-squares line of t = L*s/S on x (centred sums), slope clamped at 0.
+__device__ __forceinline__ void root_line(double mx, double sxx, double sxt, uint32_t L, uint64_t S, double* a0,
+                                          double* a1) {
+  const double mt = (double)L * (double)(S - 1) / (2.0 * (double)S);
+  double b = sxx > 0 ? sxt / sxx : 0.0;
+  if (b < 0) {
+    *a1 = 0;
+    *a0 = mt;
+  } else {
+    *a1 = b;
+    *a0 = mt - b * mx;
+  }
+}
+
 __global__ __launch_bounds__(kFitThreads) void root_final_kernel(uint64_t S, uint64_t n, uint32_t L, uint32_t B,
                                                                  const double* __restrict__ part_x,
                                                                  const double* __restrict__ part_xx,
@@ -221,15 +240,8 @@ __global__ __launch_bounds__(kFitThreads) void root_final_kernel(uint64_t S, uin
   double sxx = block_sum(part_xx[threadIdx.x], sh);
   double sxt = block_sum(part_xt[threadIdx.x], sh);
   if (threadIdx.x == 0) {
-    double mt = (double)L * (double)(S - 1) / (2.0 * (double)S);
-    double a1 = sxx > 0 ? sxt / sxx : 0.0;
-    double a0;
-    if (a1 < 0) {
-      a1 = 0;
-      a0 = mt;
-    } else {
-      a0 = mt - a1 * mx;
-    }
+    double a0, a1;
+    root_line(mx, sxx, sxt, L, S, &a0, &a1);
     hdr->a0 = (float)a0;
     hdr->a1 = (float)a1;
     hdr->L = L;
@@ -254,15 +266,7 @@ __device__ uint64_t first_in_leaf(const uint64_t* e, uint64_t S, float a0, float
   return lo;
 }
 
-__global__ __launch_bounds__(256) void leaf_fit_kernel(const uint64_t* __restrict__ e, uint64_t S,
-                                                       const ModelHeader* __restrict__ hdr,
-                                                       Leaf* __restrict__ leaves) {
-  uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t L = hdr->L, B = hdr->B;
-  if (j >= L) return;
-  const float a0 = hdr->a0, a1 = hdr->a1;
-  uint64_t f = first_in_leaf(e, S, a0, a1, L, j);
-  uint64_t g = j + 1 < L ? first_in_leaf(e, S, a0, a1, L, j + 1) : S;
+__device__ Leaf spline_leaf(const uint64_t* e, uint64_t S, uint32_t B, uint64_t f, uint64_t g) {
   Leaf lf;
   lf.pad[0] = lf.pad[1] = 0;
   if (f == g) {
@@ -283,7 +287,19 @@ __global__ __launch_bounds__(256) void leaf_fit_kernel(const uint64_t* __restric
     uint64_t h = ((uint64_t)B * (g - 1)) / S;
     lf.hi = (uint32_t)(h < B - 1 ? h : B - 1);
   }
-  leaves[j] = lf;
+  return lf;
+}
+
+__global__ __launch_bounds__(256) void leaf_fit_kernel(const uint64_t* __restrict__ e, uint64_t S,
+                                                       const ModelHeader* __restrict__ hdr,
+                                                       Leaf* __restrict__ leaves) {
+  uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t L = hdr->L, B = hdr->B;
+  if (j >= L) return;
+  const float a0 = hdr->a0, a1 = hdr->a1;
+  uint64_t f = first_in_leaf(e, S, a0, a1, L, j);
+  uint64_t g = j + 1 < L ? first_in_leaf(e, S, a0, a1, L, j + 1) : S;
+  leaves[j] = spline_leaf(e, S, B, f, g);
 }
 
 size_t fit_scratch_bytes(uint64_t /*S*/) { return 3 * kFitBlocks * sizeof(double); }
@@ -335,6 +351,119 @@ hipError_t launch_sample_hist(const ModelHeader* hdr, const Leaf* leaves, const 
   hipError_t err = launch_fill_u32(hist, B, 0u, st);
   if (err != hipSuccess) return err;
   if (S) sample_bucket_hist_kernel<<<(uint32_t)((S + 255) / 256), 256, 0, st>>>(e, S, hdr, leaves, hist);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------- batch: fit per job --
+// One 1024-thread block fits the whole model of one job whose sample fits
+// LDS: its S <= kBatchFitMaxS sample codes are drawn straight from the job's
+// records, sorted in LDS (bitonic network), then the root line, the spline
+// leaves and the sample histogram are computed as by the per-job kernels.
+constexpr uint32_t kBfThreads = 1024;
+
+__device__ double bf_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0;
+  for (uint32_t i = 0; i < kBfThreads / 64; ++i) t += sh[i];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kBfThreads) void batch_fit_kernel(const FitJob* __restrict__ jobs, uint32_t njobs,
+                                                               uint32_t rec_bytes) {
+  __shared__ uint64_t e[kBatchFitMaxS];
+  __shared__ double sh[kBfThreads / 64];
+  __shared__ uint32_t shm[kBfThreads / 64];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
+    const FitJob J = jobs[jb];
+    const uint64_t S = J.S;
+    uint32_t P = 1;
+    while (P < S) P <<= 1;
+    for (uint32_t s = tid; s < P; s += kBfThreads) {
+      uint64_t c = ~0ull;  // padding sorts last
+      if (s < S) {
+        const uint32_t* r = reinterpret_cast<const uint32_t*>(J.recs + sample_index(s, J.n, S, J.seed) * rec_bytes);
+        c = key_code(r[0], r[1]);
+      }
+      e[s] = c;
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1)
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t i = tid; i < P; i += kBfThreads) {
+          const uint32_t ij = i ^ j;
+          if (ij > i) {
+            const uint64_t a = e[i], b = e[ij];
+            if ((a > b) == ((i & k) == 0)) {
+              e[i] = b;
+              e[ij] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    // root line
+    double sx = 0;
+    for (uint32_t s = tid; s < S; s += kBfThreads) sx += (double)code_f32(e[s]);
+    const double mx = bf_sum(sx, sh) / (double)S;
+    const double mt = (double)J.L * (double)(S - 1) / (2.0 * (double)S);
+    double sxx = 0, sxt = 0;
+    for (uint32_t s = tid; s < S; s += kBfThreads) {
+      const double dx = (double)code_f32(e[s]) - mx;
+      const double dt = (double)J.L * (double)s / (double)S - mt;
+      sxx += dx * dx;
+      sxt += dx * dt;
+    }
+    sxx = bf_sum(sxx, sh);
+    sxt = bf_sum(sxt, sh);
+    double a0d, a1d;
+    root_line(mx, sxx, sxt, J.L, S, &a0d, &a1d);
+    const float a0 = (float)a0d, a1 = (float)a1d;
+    // leaves, then the histogram of the sample over the buckets
+    for (uint32_t j = tid; j < J.L; j += kBfThreads) {
+      const uint64_t f = first_in_leaf(e, S, a0, a1, J.L, j);
+      const uint64_t g = j + 1 < J.L ? first_in_leaf(e, S, a0, a1, J.L, j + 1) : S;
+      J.leaves[j] = spline_leaf(e, S, J.B, f, g);
+    }
+    for (uint32_t b = tid; b < J.B; b += kBfThreads) J.hist[b] = 0;
+    __syncthreads();
+    for (uint32_t s = tid; s < S; s += kBfThreads)
+      atomicAdd(&J.hist[leaf_bucket(load_leaf(J.leaves, rmi_leaf(a0, a1, J.L, e[s])), e[s])], 1u);
+    __syncthreads();
+    uint32_t m = 0;
+    for (uint32_t b = tid; b < J.B; b += kBfThreads) m = J.hist[b] > m ? J.hist[b] : m;
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint32_t o = __shfl_xor(m, off);
+      m = o > m ? o : m;
+    }
+    if (lane_id() == 0) shm[tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t mm = 0;
+      for (uint32_t i = 0; i < kBfThreads / 64; ++i) mm = shm[i] > mm ? shm[i] : mm;
+      ModelHeader* h = J.hdr;
+      h->a0 = a0;
+      h->a1 = a1;
+      h->L = J.L;
+      h->B = J.B;
+      h->kind_used = 0;
+      h->mlp_rejected = 0;
+      h->n_fit = J.n;
+      h->S = S;
+      h->max_sample_bucket = mm;
+      h->opt_sample_bucket = (uint32_t)((S + J.B - 1) / J.B);
+      h->max_sample_run = 0;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_batch_fit(const FitJob* d_jobs, uint32_t njobs, uint32_t rec_bytes, hipStream_t st) {
+  if (njobs == 0) return hipSuccess;
+  batch_fit_kernel<<<njobs < 2048 ? njobs : 2048, kBfThreads, 0, st>>>(d_jobs, njobs, rec_bytes);
   return hipGetLastError();
 }
 
