@@ -410,13 +410,35 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
                              [&](uint32_t e) { return digit_of(ent[e], (uint32_t)pbyte); });
       cur ^= 1;
     }
-    // 3. copy records in sorted order to the output
-    const uint32_t total = br.n * RW;
+    // 3. copy records in sorted order to the output: lane q moves 16-byte
+    //    chunk q % LC of the record at sorted position q / LC, kSmGroup loads
+    //    in flight per thread before the stores
+    const uint32_t SC = W / 4, LC = (RW + 1 + 3) / 4;
     uint32_t* o_dw = out + br.out0 * RW;
-    for (uint32_t f = threadIdx.x; f < total; f += THREADS) {
-      uint32_t k = f / RW, d = f - k * RW;
-      uint32_t sl = slot_of(br, perm[cur][k], spill_map, cap_slots);
-      o_dw[f] = slots[(uint64_t)sl * W + d + 1];
+    const uint32_t nq = br.n * LC;
+    const u32x4* s4 = reinterpret_cast<const u32x4*>(slots);
+    for (uint32_t q0 = 0; q0 < nq; q0 += kSmGroup * THREADS) {
+      u32x4 g[kSmGroup];
+#pragma unroll
+      for (uint32_t i = 0; i < kSmGroup; ++i) {
+        const uint32_t q = q0 + threadIdx.x + i * THREADS;
+        const uint32_t qq = q < nq ? q : nq - 1;
+        const uint32_t k = qq / LC, c = qq - k * LC;
+        g[i] = s4[(uint64_t)slot_of(br, perm[cur][k], spill_map, cap_slots) * SC + c];
+      }
+#pragma unroll
+      for (uint32_t i = 0; i < kSmGroup; ++i) {
+        const uint32_t q = q0 + threadIdx.x + i * THREADS;
+        if (q < nq) {
+          const uint32_t k = q / LC, c = q - k * LC;
+          uint32_t* o = o_dw + k * RW;
+#pragma unroll
+          for (uint32_t t = 0; t < 4; ++t) {
+            const uint32_t sd = 4 * c + t;  // slot dword: 0 is the index, 1..RW the record
+            if (sd >= 1 && sd <= RW) o[sd - 1] = g[i][t];
+          }
+        }
+      }
     }
     __syncthreads();
   }

@@ -371,14 +371,9 @@ __device__ double bf_sum(double v, double* sh) {
   return t;
 }
 
-__global__ __launch_bounds__(kBfThreads) void batch_fit_kernel(const FitJob* __restrict__ jobs, uint32_t njobs,
-                                                               uint32_t rec_bytes) {
-  __shared__ uint64_t e[kBatchFitMaxS];
-  __shared__ double sh[kBfThreads / 64];
-  __shared__ uint32_t shm[kBfThreads / 64];
+__device__ void fit_job_block(const FitJob& J, uint32_t rec_bytes, uint64_t* e, double* sh, uint32_t* shm) {
   const uint32_t tid = threadIdx.x;
-  for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
-    const FitJob J = jobs[jb];
+  {
     const uint64_t S = J.S;
     uint32_t P = 1;
     while (P < S) P <<= 1;
@@ -460,6 +455,15 @@ __global__ __launch_bounds__(kBfThreads) void batch_fit_kernel(const FitJob* __r
     __syncthreads();
   }
 }
+
+__global__ __launch_bounds__(kBfThreads) void batch_fit_kernel(const FitJob* __restrict__ jobs, uint32_t njobs,
+                                                               uint32_t rec_bytes) {
+  __shared__ uint64_t e[kBatchFitMaxS];
+  __shared__ double sh[kBfThreads / 64];
+  __shared__ uint32_t shm[kBfThreads / 64];
+  for (uint32_t jb = blockIdx.x; jb < njobs; jb += gridDim.x) fit_job_block(jobs[jb], rec_bytes, e, sh, shm);
+}
+
 
 hipError_t launch_batch_fit(const FitJob* d_jobs, uint32_t njobs, uint32_t rec_bytes, hipStream_t st) {
   if (njobs == 0) return hipSuccess;
