@@ -53,7 +53,9 @@ typedef enum {
 typedef enum {
   ELSAR_MODEL_RMI = 0,  /* two-level RMI: linear root, linear-spline leaves */
   ELSAR_MODEL_MLP = 1,  /* monotone MLP root over the same kind of leaves; RMI if it fails acceptance */
-  ELSAR_MODEL_AUTO = 2  /* MLP if it passes acceptance or has the smaller largest sample bucket, else RMI */
+  ELSAR_MODEL_AUTO = 2, /* MLP if it passes acceptance or has the smaller largest sample bucket, else RMI */
+  ELSAR_MODEL_RADIX = 3 /* no learned model: equi-width buckets of the code, floor(code * B / 95^8), the
+                           radix partitioning the paper compares its model against (Section 3.3) */
 } elsar_model_kind;
 
 /* Fit parameters.  Zero fields take the defaults noted. */

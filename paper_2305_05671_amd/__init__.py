@@ -20,7 +20,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libelsar.so")
 
-RMI, MLP, AUTO = 0, 1, 2
+RMI, MLP, AUTO, RADIX = 0, 1, 2, 3
 MLP_PARAMS = 4801
 MLP_GRAD_ROWS = 128
 OK, E_INVALID_ARG, E_NO_MEMORY, E_HIP, E_UNSUPPORTED, E_MODEL_REJECTED = range(6)

@@ -60,7 +60,7 @@ elsar_status check_params(const elsar_fit_params* p) {
     return ELSAR_E_UNSUPPORTED;
   if (p->num_buckets > kMaxBuckets) return ELSAR_E_INVALID_ARG;
   if (p->num_leaves > (1u << 22)) return ELSAR_E_INVALID_ARG;
-  if (p->kind > ELSAR_MODEL_AUTO) return ELSAR_E_INVALID_ARG;
+  if (p->kind > ELSAR_MODEL_RADIX) return ELSAR_E_INVALID_ARG;
   if (p->sample_size > 10000000ull * 4) return ELSAR_E_INVALID_ARG;
   if (p->region_pct > 1000) return ELSAR_E_INVALID_ARG;
   return ELSAR_OK;
@@ -196,6 +196,13 @@ elsar_status do_fit(elsar_model* m, const void* d_records, uint64_t n, void* d_w
   void* fscr = w + 2 * align_up(S * 8) + align_up(radix_u64_scratch_bytes(S));
   HIP_TRY(launch_sample_codes(static_cast<const uint8_t*>(d_records), n, m->p.record_bytes, S, m->p.seed, codes,
                               st));
+  if (m->p.kind == ELSAR_MODEL_RADIX) {  // equi-width buckets; the sample only sizes the regions
+    HIP_TRY(launch_radix_model(S, n, m->L, m->B, m->hdr, m->leaves, st));
+    HIP_TRY(launch_sample_hist(m->hdr, m->leaves, codes, S, m->B, m->hist, st));
+    HIP_TRY(launch_decide_root(m->hist, nullptr, m->B, S, m->p.accept_ratio, m->p.kind, m->hdr, m->hist, st));
+    m->n = n;
+    return ELSAR_OK;
+  }
   uint64_t* sorted = nullptr;
   // codes < 95^8 < 2^53: bytes 0..6 carry the value
   HIP_TRY(launch_radix_sort_u64(codes, tmp, S, 0, 6, rscr, st, &sorted));

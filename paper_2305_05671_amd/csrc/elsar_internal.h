@@ -243,6 +243,8 @@ struct FitJob {
   uint32_t* hist;        // B
 };
 hipError_t launch_batch_fit(const FitJob* d_jobs, uint32_t njobs, uint32_t rec_bytes, hipStream_t st);
+hipError_t launch_radix_model(uint64_t S, uint64_t n, uint32_t L, uint32_t B, ModelHeader* hdr, Leaf* leaves,
+                              hipStream_t st);
 hipError_t launch_capacities(const uint32_t* hist, uint64_t S, uint64_t n, uint32_t B, uint32_t region_pct,
                              uint8_t* part, const PartLayout& lay, hipStream_t st);
 

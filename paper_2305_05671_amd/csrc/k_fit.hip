@@ -354,6 +354,40 @@ hipError_t launch_sample_hist(const ModelHeader* hdr, const Leaf* leaves, const 
   return hipGetLastError();
 }
 
+// ---------------------------------------------- radix (equi-width) model --
+// No learned model: the root sends every code to leaf 0 (a0 = a1 = 0), whose
+// line maps the whole code range [0, 95^8) linearly onto the B buckets.
+__global__ void radix_model_kernel(uint64_t S, uint64_t n, uint32_t L, uint32_t B, ModelHeader* __restrict__ hdr,
+                                   Leaf* __restrict__ leaves) {
+  for (uint32_t j = threadIdx.x; j < L; j += blockDim.x) {
+    Leaf lf;
+    lf.base = 0;
+    lf.c = (float)((double)B / 6634204312890625.0);  // 95^8
+    lf.b = 0.0f;
+    lf.lo = 0;
+    lf.hi = B - 1;
+    lf.pad[0] = lf.pad[1] = 0;
+    leaves[j] = lf;
+  }
+  if (threadIdx.x == 0) {
+    hdr->a0 = 0.0f;
+    hdr->a1 = 0.0f;
+    hdr->L = L;
+    hdr->B = B;
+    hdr->kind_used = 0;
+    hdr->mlp_rejected = 0;
+    hdr->n_fit = n;
+    hdr->S = S;
+    hdr->max_sample_run = 0;
+  }
+}
+
+hipError_t launch_radix_model(uint64_t S, uint64_t n, uint32_t L, uint32_t B, ModelHeader* hdr, Leaf* leaves,
+                              hipStream_t st) {
+  radix_model_kernel<<<1, 256, 0, st>>>(S, n, L, B, hdr, leaves);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------- batch: fit per job --
 // One 1024-thread block fits the whole model of one job whose sample fits
 // LDS: its S <= kBatchFitMaxS sample codes are drawn straight from the job's

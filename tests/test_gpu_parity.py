@@ -254,3 +254,35 @@ def test_batch_matches_oracle_and_replays(env):
         for j in range(sizes.size):
             _assert_same(fresh[j].cpu().numpy().reshape(-1, R), want[j])
     del junk
+
+
+@pytest.mark.parametrize("kind,n,B", [("uniform", 500_000, 512), ("skewed", 500_000, 512), ("zipf", 400_000, 256)])
+def test_radix_partitioner(env, kind, n, B):
+    """The radix (equi-width) bucket function: counts bit-exact against the
+    oracle's FP32 evaluation of the same one-line model, the sort byte-exact,
+    and -- the paper's model-vs-radix comparison -- the learned RMI's bucket
+    sizes vary less than the radix partitioner's on skewed keys."""
+    torch, elsar = env
+    recs = datagen.generate(datagen.spec(kind, seed=61), n)
+    m, part, offsets, d = _fit_and_partition(env, recs, num_buckets=B, seed=61, kind=elsar.RADIX)
+    info = m.info()
+    ref = oracle.RMI(info.num_leaves, B)
+    ref.root[:] = [0.0, 0.0]
+    ref.base[:] = 0
+    ref.c[:] = np.float32(B / 95.0 ** 8)
+    ref.b[:] = 0
+    ref.lo[:] = 0
+    ref.hi[:] = B - 1
+    _, want = oracle.counts_offsets(ref.buckets(recs), B)
+    got = offsets.cpu().numpy().astype(np.uint64)
+    assert np.array_equal(got, want)
+    out = torch.empty_like(d)
+    m.sort_buckets(part, offsets, n, out)
+    torch.cuda.synchronize()
+    _assert_same(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs))
+    _, _, off_rmi, _ = _fit_and_partition(env, recs, num_buckets=B, seed=61)
+    cv = lambda o: float(np.std(np.diff(o)) / np.mean(np.diff(o)))
+    cv_radix, cv_rmi = cv(got.astype(np.int64)), cv(off_rmi.cpu().numpy())
+    print(f"\n{kind}: CV of bucket sizes, radix {cv_radix:.3f}, learned RMI {cv_rmi:.3f}")
+    if kind != "uniform":
+        assert cv_rmi < cv_radix
