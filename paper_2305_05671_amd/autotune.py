@@ -1,12 +1,18 @@
 """Bucket-count autotuner for batched sorts.
 
-Sweeps whole sorts (elsar_sort, the per-job pipeline of elsar_sort_batch) of
-2^k records for k in 11..22 over candidate bucket sizes (records per bucket),
-on the batch workload's two key laws (uniform, first-byte Zipf), and writes
-the fastest size per k into csrc/autotune_table.h.  Run it on the GPU, then
-rebuild the library:
+Two sweeps, both run on the GPU:
 
-    python -m paper_2305_05671_amd.autotune            # writes the table
+* per size (default): whole sorts (elsar_sort, the per-job pipeline of
+  elsar_sort_batch) of 2^k records, k in 11..22, over candidate bucket sizes
+  (records per bucket), on the batch workload's two key laws (uniform,
+  first-byte Zipf); the fastest size per k goes into csrc/autotune_table.h.
+* --batch: jobs of a batch run four at a time, which changes the trade-off,
+  so this sweep times the batch workload itself (bench.py --workload
+  batch-4096) with one records-per-bucket value for every job of up to 2^20
+  records, rebuilding the library for each candidate, and keeps the fastest.
+
+    python -m paper_2305_05671_amd.autotune            # per-size table
+    python -m paper_2305_05671_amd.autotune --batch    # batch-context table
     python -c "import __graft_entry__ as g; g.build()"
 """
 from __future__ import annotations
@@ -63,9 +69,10 @@ def write_table(best, path=TABLE):
     body = ",\n    ".join(", ".join(str(v) for v in rows[i:i + 11]) for i in range(0, 33, 11))
     text = f"""// Records per bucket for batched sorts, indexed by ceil(log2(n)): a job of n
 // records gets the largest power of two <= n / kAutotuneRecordsPerBucket[r]
-// buckets (at least 1).  Written by paper_2305_05671_amd/autotune.py from a
-// sweep of whole sorts on gfx950 (uniform and first-byte-Zipf keys, the
-// batch workload's two key laws); 0 means the default, 950.
+// buckets (at least 1).  Written by paper_2305_05671_amd/autotune.py on
+// gfx950: the per-size sweep of whole sorts (uniform and first-byte-Zipf keys,
+// the batch workload's two key laws), then the batch-context sweep for jobs of
+// up to 2^20 records; 0 means the default, 950.
 #pragma once
 #include <stdint.h>
 
@@ -79,12 +86,54 @@ constexpr uint32_t kAutotuneRecordsPerBucket[kAutotuneRows] = {{
         f.write(text)
 
 
+def read_table(path=TABLE):
+    import re
+    text = open(path).read()
+    body = text[text.index("kAutotuneRecordsPerBucket[kAutotuneRows] = {") + 45:]
+    vals = [int(v) for v in re.findall(r"\d+", body[:body.index("}")])]
+    return {r: v for r, v in enumerate(vals) if v}
+
+
+def batch_sweep(candidates, jobs=4096, small_rows=range(11, 21), log=sys.stderr):
+    """Time the batch workload with each candidate for the rows in small_rows
+    (the other rows as they are), rebuilding the library each time."""
+    import json
+    import subprocess
+    sys.path.insert(0, os.path.dirname(HERE))
+    from paper_2305_05671_amd import _build
+    base = read_table()
+    best, best_ms = None, float("inf")
+    for c in candidates:
+        t = dict(base)
+        t.update({r: c for r in small_rows})
+        write_table(t)
+        _build.build()
+        r = subprocess.run([sys.executable, os.path.join(os.path.dirname(HERE), "bench.py"), "--workload",
+                            "batch-4096", "--jobs", str(jobs), "--steps", "3", "--warmup", "1", "--verify-jobs", "2"],
+                           capture_output=True, text=True, check=True)
+        ms = json.loads(r.stdout.strip().splitlines()[-1])["ms_per_step"]
+        print(f"batch, {c} records per bucket for 2^{small_rows.start}..2^{small_rows.stop - 1}: {ms:.1f} ms",
+              file=log, flush=True)
+        if ms < best_ms:
+            best, best_ms = c, ms
+    base.update({r: best for r in small_rows})
+    write_table(base)
+    _build.build()
+    return base
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--kmin", type=int, default=11)
     ap.add_argument("--kmax", type=int, default=22)
     ap.add_argument("--out", default=TABLE)
+    ap.add_argument("--batch", action="store_true", help="batch-context sweep (rewrites the table in place)")
+    ap.add_argument("--candidates", default="64,96,128,192,256")
     a = ap.parse_args()
+    if a.batch:
+        batch_sweep([int(c) for c in a.candidates.split(",")])
+        print(open(TABLE).read())
+        return
     write_table(sweep(a.kmin, a.kmax), a.out)
     print(open(a.out).read())
 

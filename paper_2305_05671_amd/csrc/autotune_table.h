@@ -1,8 +1,9 @@
 // Records per bucket for batched sorts, indexed by ceil(log2(n)): a job of n
 // records gets the largest power of two <= n / kAutotuneRecordsPerBucket[r]
-// buckets (at least 1).  Written by paper_2305_05671_amd/autotune.py from a
-// sweep of whole sorts on gfx950 (uniform and first-byte-Zipf keys, the
-// batch workload's two key laws); 0 means the default, 950.
+// buckets (at least 1).  Written by paper_2305_05671_amd/autotune.py on
+// gfx950: the per-size sweep of whole sorts (uniform and first-byte-Zipf keys,
+// the batch workload's two key laws), then the batch-context sweep for jobs of
+// up to 2^20 records; 0 means the default, 950.
 #pragma once
 #include <stdint.h>
 
@@ -10,6 +11,6 @@ namespace elsar {
 constexpr uint32_t kAutotuneRows = 33;
 constexpr uint32_t kAutotuneRecordsPerBucket[kAutotuneRows] = {
     0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0,
-    256, 256, 256, 256, 256, 256, 256, 256, 256, 256, 384,
+    128, 128, 128, 128, 128, 128, 128, 128, 128, 128, 384,
     384, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 }  // namespace elsar

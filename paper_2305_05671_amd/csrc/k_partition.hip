@@ -228,7 +228,10 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const Ml
   const uint32_t RW = rec_bytes / 4;
   const size_t lds = 2 * (size_t)kPartTile * RW * 4;
   uint64_t ntiles = (n + kPartTile - 1) / kPartTile;
+  // at least four tiles per block below 8192 tiles, so that the pipeline has
+  // tiles to overlap (small jobs of a batch run beside others)
   uint32_t grid = (uint32_t)(ntiles < 2048 ? ntiles : 2048);
+  if (ntiles < 8192) grid = (uint32_t)((ntiles + 3) / 4);
   auto* counts = reinterpret_cast<uint32_t*>(part + lay.counts);
   auto* caps = reinterpret_cast<const uint32_t*>(part + lay.caps);
   auto* rstart = reinterpret_cast<const uint32_t*>(part + lay.rstart);
