@@ -167,10 +167,11 @@ elsar_status elsar_sort_batch_workspace_size(const elsar_job* h_jobs, uint32_t n
  * jobs and concurrent lanes).  h_jobs: host array of njobs jobs.  p applies to every job, except
  * that num_buckets / num_leaves of 0 are chosen per job from the tuned table,
  * and job j's sampler seed is p->seed + j.  Jobs of up to 2048 records are
- * sorted whole, one block each, in a single kernel; the others run the full
- * pipeline on four concurrent lanes, each lane reusing one slice of d_ws
- * sized for its largest job (scratch is bounded by four jobs, not by the
- * batch).  The first call with a given (table, parameters, workspace) records
+ * sorted whole, one block each, in a single kernel; the models of jobs whose
+ * sample fits LDS are fitted by one kernel, one block each; the jobs then run
+ * the rest of the pipeline on sixteen concurrent lanes, each lane reusing one
+ * slice of d_ws sized for its largest job (scratch is bounded by sixteen
+ * jobs, not by the batch).  The first call with a given (table, parameters, workspace) records
  * the whole batch as one HIP graph; that call and every later one with the
  * same arguments is a single graph launch on `stream`.  Asynchronous.
  */

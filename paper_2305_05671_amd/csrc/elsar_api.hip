@@ -417,7 +417,7 @@ elsar_status sort_job(const void* d_in, uint64_t n, void* d_out, const elsar_fit
 }
 
 // ------------------------------------------------------------------ batch --
-constexpr uint32_t kBatchLanes = 4;
+constexpr uint32_t kBatchLanes = 16;
 constexpr size_t kMaxPlans = 8;
 
 uint32_t ceil_log2(uint64_t n) {

@@ -96,6 +96,9 @@ __device__ __forceinline__ float mlp_y64(uint64_t code, const MlpHead& M, const 
   float y_own = 0.0f;
 #pragma unroll 1
   for (uint32_t c = 0; c < 4; ++c) {
+    // the layer-1 weights are re-read from LDS for every chunk instead of
+    // being kept in registers across chunks and tiles (which costs occupancy)
+    __asm__ volatile("" ::: "memory");
     const uint64_t cc = shfl_u64(code, (int)(16 * c + r));  // record 16c + r
     float phi[8], h1[16];
     s16x4 a[4];
