@@ -819,7 +819,6 @@ __global__ __launch_bounds__(kSmThreads) void seg_sort_kernel(const uint32_t* __
     const uint32_t* X = (sg.w ? Bf : A) + 5ull * sg.y;
     uint32_t* refs = out + offsets[sg.x] * RW + (uint64_t)(RW - 1) * nb + sg.y;
     uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
-    uint64_t cmin = ~0ull, cmax = 0;
 #pragma unroll
     for (uint32_t i = 0; i < AR; ++i) {
       const uint32_t q = tid + i * kSmThreads;
@@ -828,13 +827,39 @@ __global__ __launch_bounds__(kSmThreads) void seg_sort_kernel(const uint32_t* __
         cw[0][q] = c.x; cw[1][q] = c.y; cw[2][q] = c.z; cw[3][q] = c.w;
         o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
         a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
-        const uint64_t e = key_code(__builtin_bswap32(c.x), __builtin_bswap32(c.y));
-        cmin = e < cmin ? e : cmin;
-        cmax = e > cmax ? e : cmax;
       }
     }
     const uint32_t vary = vary_mask(block_diff<kSmThreads>(o, a, sh_or, sh_and));
+    // the counting digit: the key's base-95 code scaled over its range in the
+    // segment; when the code is the same for the whole segment (one key, or
+    // keys equal in their first 8 bytes), the 8 composite bytes from the first
+    // varying one (key bytes 8.. and the index) instead
+    uint64_t cmin = ~0ull, cmax = 0;
+    for (uint32_t q = tid; q < n; q += kSmThreads) {
+      const uint64_t e = key_code(__builtin_bswap32(cw[0][q]), __builtin_bswap32(cw[1][q]));
+      cmin = e < cmin ? e : cmin;
+      cmax = e > cmax ? e : cmax;
+    }
     block_min_max_u64<kSmThreads>(cmin, cmax, sh_mm);
+    const bool by_code = cmax > cmin;
+    const uint32_t p0 = vary ? (uint32_t)__builtin_ctz(vary) : 0u;
+    auto digit_src = [&](uint32_t q) -> uint64_t {
+      if (by_code) return key_code(__builtin_bswap32(cw[0][q]), __builtin_bswap32(cw[1][q]));
+      const uint32_t wd = p0 >> 2, sh = 8 * (p0 & 3);
+      const uint64_t hi = ((uint64_t)cw[wd][q] << 32) | (wd + 1 < 4 ? cw[wd + 1][q] : 0u);
+      const uint32_t nx = wd + 2 < 4 ? cw[wd + 2][q] : 0u;
+      return sh ? (hi << sh) | (nx >> (32 - sh)) : hi;
+    };
+    if (!by_code) {
+      cmin = ~0ull;
+      cmax = 0;
+      for (uint32_t q = tid; q < n; q += kSmThreads) {
+        const uint64_t wv = digit_src(q);
+        cmin = wv < cmin ? wv : cmin;
+        cmax = wv > cmax ? wv : cmax;
+      }
+      block_min_max_u64<kSmThreads>(cmin, cmax, sh_mm);
+    }
     uint32_t cur = 0;
     if (n == 1) {
       if (tid == 0) perm[0][0] = 0;
@@ -842,8 +867,7 @@ __global__ __launch_bounds__(kSmThreads) void seg_sort_kernel(const uint32_t* __
       const double scale = (double)(1u << kSmBits) / ((double)(cmax - cmin) + 1.0);
       for (uint32_t i = tid; i < (1u << kSmBits); i += kSmThreads) bins[i] = 0;
       for (uint32_t q = tid; q < n; q += kSmThreads) {
-        const uint64_t e = key_code(__builtin_bswap32(cw[0][q]), __builtin_bswap32(cw[1][q]));
-        const uint32_t d = (uint32_t)((double)(e - cmin) * scale);
+        const uint32_t d = (uint32_t)((double)(digit_src(q) - cmin) * scale);
         perm[1][q] = (uint16_t)(d < (1u << kSmBits) ? d : (1u << kSmBits) - 1);
       }
       cur = small_sort_core(n, vary, cw, perm, bins, sh_scan, tot);
@@ -877,14 +901,27 @@ __global__ __launch_bounds__(kMsdThreads) void big_gather_kernel(const uint32_t*
       for (uint32_t i = threadIdx.x; i < m; i += kMsdThreads) chunk_slot[i] = refs[k0 + i];
       __syncthreads();
       const uint32_t nq = m * LC;
-      for (uint32_t q = threadIdx.x; q < nq; q += kMsdThreads) {
-        const uint32_t k = q / LC, c = q - k * LC;
-        const u32x4 g = reinterpret_cast<const u32x4*>(slots)[(uint64_t)chunk_slot[k] * SC + c];
-        uint32_t* o = o_dw + (uint64_t)(k0 + k) * RW;
+      for (uint32_t q0 = 0; q0 < nq; q0 += kSmGroup * kMsdThreads) {
+        u32x4 g[kSmGroup];
 #pragma unroll
-        for (uint32_t t = 0; t < 4; ++t) {
-          const uint32_t sd = 4 * c + t;  // slot dword: 0 is the index, 1..RW the record
-          if (sd >= 1 && sd <= RW) o[sd - 1] = g[t];
+        for (uint32_t i = 0; i < kSmGroup; ++i) {  // kSmGroup loads in flight before the stores
+          const uint32_t q = q0 + threadIdx.x + i * kMsdThreads;
+          const uint32_t qq = q < nq ? q : nq - 1;
+          const uint32_t k = qq / LC, c = qq - k * LC;
+          g[i] = reinterpret_cast<const u32x4*>(slots)[(uint64_t)chunk_slot[k] * SC + c];
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < kSmGroup; ++i) {
+          const uint32_t q = q0 + threadIdx.x + i * kMsdThreads;
+          if (q < nq) {
+            const uint32_t k = q / LC, c = q - k * LC;
+            uint32_t* o = o_dw + (uint64_t)(k0 + k) * RW;
+#pragma unroll
+            for (uint32_t t = 0; t < 4; ++t) {
+              const uint32_t sd = 4 * c + t;  // slot dword: 0 is the index, 1..RW the record
+              if (sd >= 1 && sd <= RW) o[sd - 1] = g[i][t];
+            }
+          }
         }
       }
       __syncthreads();
