@@ -112,13 +112,15 @@ __global__ void mlp_publish_kernel(const float* __restrict__ master, const uint6
 
 // --------------------------------------------------------------- training --
 // One step on kMlpGradRows rows: forward, MSE gradient with targets t, backward
-// into G (flat parameter order).  Block of 256 threads; wave w owns rows
-// 32w .. 32w + 31 in two 16-row chunks.  The 64x64 products (forward, dW2 and
-// dh1) run on the matrix cores in bfloat16 with FP32 accumulation; everything
-// else is FP32.
-constexpr uint32_t kTrainThreads = 256;
+// into G (flat parameter order).  Block of 512 threads; wave w owns rows
+// 16w .. 16w + 15 (one 16-row chunk), and output tiles w, w + 8 of dW2.  The
+// 64x64 products (forward, dW2 and dh1) run on the matrix cores in bfloat16
+// with FP32 accumulation; everything else is FP32.
+constexpr uint32_t kTrainThreads = 512;
+constexpr uint32_t kWaves = kTrainThreads / 64;
 constexpr uint32_t kRows = kMlpGradRows;
-static_assert(kRows == 32 * (kTrainThreads / 64), "two 16-row chunks per wave");
+constexpr uint32_t kChunks = kRows / (16 * kWaves);  // 16-row chunks per wave
+static_assert(kChunks >= 1 && kRows == 16 * kChunks * kWaves, "whole chunks per wave");
 
 struct TrainLds {
   MlpBlock M;
@@ -134,11 +136,11 @@ struct TrainLds {
 __device__ void step_grad(TrainLds& sm) {
   const uint32_t tid = threadIdx.x, w = tid >> 6, l = __lane_id(), r = l & 15u, g = l >> 4;
   const MlpHead& M = sm.M.h;
-  float h2[2][4][4];  // [chunk][ct][e]: row 32w + 16c + 4g + e, column 16ct + r
+  float h2[kChunks][4][4];  // [chunk][ct][e]: row 16 kChunks w + 16c + 4g + e, column 16ct + r
   // forward
 #pragma unroll
-  for (uint32_t c = 0; c < 2; ++c) {
-    const uint32_t r0 = 32 * w + 16 * c;
+  for (uint32_t c = 0; c < kChunks; ++c) {
+    const uint32_t r0 = 16 * kChunks * w + 16 * c;
     float phi[8], h1[16];
     s16x4 a[4];
 #pragma unroll
@@ -189,10 +191,10 @@ __device__ void step_grad(TrainLds& sm) {
       const uint32_t col = 16 * ct + r;
       float gw3 = 0.f, gb2 = 0.f;
 #pragma unroll
-      for (uint32_t c = 0; c < 2; ++c)
+      for (uint32_t c = 0; c < kChunks; ++c)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const uint32_t row = 32 * w + 16 * c + 4 * g + e;
+          const uint32_t row = 16 * kChunks * w + 16 * c + 4 * g + e;
           const float dy = sm.DY[row], v = h2[c][ct][e];
           const float dz2 = dy * M.w3[col] * v * (1.0f - v);
           gw3 = __builtin_fmaf(dy, v, gw3);
@@ -212,24 +214,25 @@ __device__ void step_grad(TrainLds& sm) {
     }
   }
   __syncthreads();
-  // dW2[j][u] = sum_t dz2[t][j] h1q[t][u]; wave w takes j = 16w .. 16w + 15
-#pragma unroll
-  for (uint32_t ct = 0; ct < 4; ++ct) {
+  // dW2[j][u] = sum_t dz2[t][j] h1q[t][u]: 16 output tiles (jt, ct), wave w
+  // takes tiles w, w + kWaves, ...
+  for (uint32_t tile = w; tile < 16; tile += kWaves) {
+    const uint32_t jt = tile & 3u, ct = tile >> 2;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (uint32_t ks = 0; ks < kRows / 16; ++ks) {
-      const s16x4 a = load4_bf16(sm.DZ2T + (16 * w + r) * kRows + 16 * ks + 4 * g);
+      const s16x4 a = load4_bf16(sm.DZ2T + (16 * jt + r) * kRows + 16 * ks + 4 * g);
       const float* h = sm.H1T + (16 * ct + r) * kRows + 16 * ks + 4 * g;
       const s16x4 b = pack4_bf16(h[0], h[1], h[2], h[3]);
       acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) sm.G[kOffW2 + (16 * w + 4 * g + e) * 64 + 16 * ct + r] = acc[e];
+    for (int e = 0; e < 4; ++e) sm.G[kOffW2 + (16 * jt + 4 * g + e) * 64 + 16 * ct + r] = acc[e];
   }
   // dh1[t][u] = sum_j dz2[t][j] W2q[j][u]; dz1 = dh1 h1 (1 - h1); dW1 = dz1^T phi, db1
 #pragma unroll
-  for (uint32_t c = 0; c < 2; ++c) {
-    const uint32_t r0 = 32 * w + 16 * c;
+  for (uint32_t c = 0; c < kChunks; ++c) {
+    const uint32_t r0 = 16 * kChunks * w + 16 * c;
 #pragma unroll
     for (uint32_t ct = 0; ct < 4; ++ct) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -281,7 +284,7 @@ __device__ void clear_grad(TrainLds& sm) {
 // All training steps in one block: per step kRows sample positions drawn with
 // Philox, the gradient, then Adam (beta1 0.9, beta2 0.999, eps 1e-8) with
 // W1, W2, w3 projected onto >= 0, and a fresh evaluation copy.  Thread t owns
-// parameters t, t + 256, ...: their FP32 values and Adam moments stay in its
+// parameters t, t + kTrainThreads, ...: their FP32 values and Adam moments stay in its
 // registers for the whole fit.
 constexpr uint32_t kOwn = (kMlpParams + kTrainThreads - 1) / kTrainThreads;
 
@@ -304,17 +307,27 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(const uint64_t
     a2[k] = ok ? adam[kMlpParams + p] : 0.0f;
   }
   float p1 = 1.0f, p2 = 1.0f;  // beta^step
+  // row tid of each step: the sample position and its code, fetched one step
+  // ahead so that the load's latency overlaps the previous step
+  auto pick = [&](uint32_t step) {
+    const uint64_t ctr = (uint64_t)step * kRows + tid;
+    return ((uint64_t)philox_x(ctr, 0x4D4C5042u /* "MLPB" */, 0u, seed) * S) >> 32;
+  };
+  uint64_t s_cur = tid < kRows ? pick(1) : 0, code_cur = tid < kRows ? e[s_cur] : 0;
   __syncthreads();
   for (uint32_t step = 1; step <= steps; ++step) {
     clear_grad(sm);
+    uint64_t s_next = 0, code_next = 0;
     if (tid < kRows) {
-      const uint64_t ctr = (uint64_t)step * kRows + tid;
-      const uint64_t s = ((uint64_t)philox_x(ctr, 0x4D4C5042u /* "MLPB" */, 0u, seed) * S) >> 32;
-      sm.T[tid] = (float)((double)s / (double)S);
+      sm.T[tid] = (float)((double)s_cur / (double)S);
       float phi[8];
-      mlp_features(e[s], sm.M.h, phi);
+      mlp_features(code_cur, sm.M.h, phi);
 #pragma unroll
       for (int k = 0; k < 8; ++k) sm.PHI[tid * 8 + k] = phi[k];
+      if (step < steps) {
+        s_next = pick(step + 1);
+        code_next = e[s_next];
+      }
     }
     __syncthreads();
     step_grad(sm);
@@ -336,6 +349,8 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(const uint64_t
       }
     }
     __syncthreads();
+    s_cur = s_next;
+    code_cur = code_next;
   }
 #pragma unroll
   for (uint32_t k = 0; k < kOwn; ++k) {
@@ -408,7 +423,12 @@ __global__ __launch_bounds__(256) void mlp_sample_leaves_kernel(const uint64_t* 
   __syncthreads();
   const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const float y = mlp_y64(e[s < S ? s : S - 1], mh, w);
-  if (s < S) atomicMin(&first_exact[mlp_leaf_guess(y, L)], (uint32_t)s);
+  const uint32_t j = mlp_leaf_guess(y, L);
+  // a lane whose left neighbour has the same leaf holds a larger position than
+  // that neighbour, so only the first lane of each run of equal leaves can
+  // hold the minimum (the sample is sorted, so runs are long)
+  const uint32_t jl = __shfl_up(j, 1);
+  if (s < S && (__lane_id() == 0 || jl != j)) atomicMin(&first_exact[j], (uint32_t)s);
 }
 
 // first[j] = min over j' >= j of first_exact[j'] (the running maximum of the
@@ -478,9 +498,9 @@ __global__ __launch_bounds__(256) void mlp_sample_stats_kernel(const uint64_t* _
                                                                uint32_t* __restrict__ hist,
                                                                ModelHeader* __restrict__ hdr) {
   const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  const uint64_t c = e[s];
-  if (s + 1 == S || e[s + 1] != c) {
+  const bool in = s < S;
+  const uint64_t c = e[in ? s : S - 1];
+  if (in && (s + 1 == S || e[s + 1] != c)) {
     uint64_t lo = 0, hi = s;
     while (lo < hi) {
       const uint64_t mid = (lo + hi) >> 1;
@@ -493,7 +513,18 @@ __global__ __launch_bounds__(256) void mlp_sample_stats_kernel(const uint64_t* _
     const uint32_t mid = (lo + hi) >> 1;
     if (first[mid] <= s) lo = mid; else hi = mid;
   }
-  atomicAdd(&hist[leaf_bucket(load_leaf(leaves, lo), c)], 1u);
+  // one add per run of equal buckets within the wave (the sample is sorted)
+  const uint32_t b = leaf_bucket(load_leaf(leaves, lo), c);
+  const uint32_t l = __lane_id();
+  const uint32_t bl = __shfl_up(b, 1), br = __shfl_down(b, 1);
+  const bool start = in && (l == 0 || bl != b);
+  const bool last = in && (l == 63 || br != b || s + 1 == S);
+  const uint64_t starts = __ballot(start);
+  if (last) {
+    const uint64_t below = starts & (l == 63 ? ~0ull : ((2ull << l) - 1));  // starts at lanes <= l
+    const uint32_t first_lane = 63u - (uint32_t)__clzll((long long)below);
+    atomicAdd(&hist[b], l + 1 - first_lane);
+  }
 }
 
 // Choice of the root.  The MLP passes when its largest sample bucket is at
