@@ -176,23 +176,31 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
     if (keep) s = atomicAdd(&counts[b], 1u);
     // 3. the previous tile's slots, while the atomics are in flight
     if (have_prev) write_tile(tprev, buf(cur ^ 1), dst[cur ^ 1]);
-    // 4. this tile's slots
-    if (FILTER && threadIdx.x < cnt && !keep) dst[cur][threadIdx.x] = kNoSlot;
+    // 4. this tile's slots.  Overflowing records take spill positions from one
+    //    shared counter; a wave reserves all of its own with a single atomic
+    //    (skewed inputs overflow in bursts, and same-address atomics serialise).
+    uint32_t slot = kNoSlot, over = 0;
+    bool spill = false;
     if (keep) {
-      uint32_t cap = caps[b];
-      uint32_t slot;
-      if (s < cap) {
-        slot = rstart[b] + s;
-      } else if (FILTER) {  // exact regions leave no room: counted as an error, never placed
-        atomicAdd(&ph->spill_count, 1u);
-        slot = kNoSlot;
-      } else {
-        uint32_t q = atomicAdd(&ph->spill_count, 1u);
-        spill_meta[q] = make_uint2(b, s - cap);
+      const uint32_t cap = caps[b];
+      if (s < cap) slot = rstart[b] + s;
+      else { spill = true; over = s - cap; }
+    }
+    const uint64_t spill_mask = __ballot(spill);
+    if (spill_mask) {
+      const uint32_t leader = (uint32_t)__ffsll((long long)spill_mask) - 1u;
+      uint32_t q0 = 0;
+      if (lane_id() == leader) q0 = atomicAdd(&ph->spill_count, (uint32_t)__popcll(spill_mask));
+      q0 = __shfl(q0, (int)leader);
+      // FILTER: exact regions leave no room, so an overflow is only counted (an
+      // error for the caller) and never placed
+      if (!FILTER && spill) {
+        const uint32_t q = q0 + (uint32_t)__popcll(spill_mask & lanemask_lt());
+        spill_meta[q] = make_uint2(b, over);
         slot = (uint32_t)cap_slots + q;
       }
-      dst[cur][threadIdx.x] = slot;
     }
+    if (threadIdx.x < cnt) dst[cur][threadIdx.x] = slot;
     __syncthreads();
     // 5. the next tile into the buffer the previous tile has left (on the last
     //    iteration a copy of tile t lands there unused; again no branch)
