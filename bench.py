@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform-100M", choices=sorted(WORKLOADS))
-    ap.add_argument("--model", default=None, choices=["rmi", "mlp", "auto", "radix"],
+    ap.add_argument("--model", default=None, choices=["rmi", "mlp", "auto", "radix", "spline"],
                     help="CDF root (default: mlp for the host workload, rmi otherwise)")
     ap.add_argument("--leaves", type=int, default=0, help="RMI leaves L (0: buckets / 16)")
     ap.add_argument("--mlp-steps", type=int, default=0, help="Adam steps of the MLP fit (0: library default)")
@@ -159,7 +159,8 @@ def bench_host(args, wl):
 
     n, seed = wl["n"], wl["seed"]
     args.model = args.model or "mlp"
-    kind = {"rmi": elsar.RMI, "mlp": elsar.MLP, "auto": elsar.AUTO, "radix": elsar.RADIX}[args.model]
+    kind = {"rmi": elsar.RMI, "mlp": elsar.MLP, "auto": elsar.AUTO, "radix": elsar.RADIX,
+            "spline": elsar.SPLINE}[args.model]
     params = elsar.fit_params(seed=seed, kind=kind, accept_ratio=args.accept_ratio, mlp_steps=args.mlp_steps)
     t0 = time.perf_counter()
     # pageable host memory: the box pins only a few tens of GB in total
@@ -330,7 +331,8 @@ def main():
         return bench_host(args, wl)
     n = wl["n"]
     args.model = args.model or "rmi"
-    kind = {"rmi": elsar.RMI, "mlp": elsar.MLP, "auto": elsar.AUTO, "radix": elsar.RADIX}[args.model]
+    kind = {"rmi": elsar.RMI, "mlp": elsar.MLP, "auto": elsar.AUTO, "radix": elsar.RADIX,
+            "spline": elsar.SPLINE}[args.model]
     params = elsar.fit_params(num_buckets=wl["buckets"], num_leaves=args.leaves, seed=wl["seed"], kind=kind,
                               mlp_steps=args.mlp_steps, accept_ratio=args.accept_ratio)
 
@@ -393,7 +395,7 @@ def main():
         "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "records": n, "record_bytes": RECORD_BYTES, "buckets": wl["buckets"],
-                   "model": args.model, "model_used": "radix" if args.model == "radix" else ["rmi", "mlp"][info.kind_used],
+                   "model": args.model, "model_used": "radix" if args.model == "radix" else {0: "rmi", 1: "mlp", 4: "spline"}[info.kind_used],
                    "leaves": info.num_leaves, "sample": info.sample_size,
                    "max_sample_bucket": info.max_sample_bucket, "ideal_sample_bucket": info.opt_sample_bucket,
                    "parallelism": "single GPU"},

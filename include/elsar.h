@@ -52,10 +52,14 @@ typedef enum {
 
 typedef enum {
   ELSAR_MODEL_RMI = 0,  /* two-level RMI: linear root, linear-spline leaves */
-  ELSAR_MODEL_MLP = 1,  /* monotone MLP root over the same kind of leaves; RMI if it fails acceptance */
-  ELSAR_MODEL_AUTO = 2, /* MLP if it passes acceptance or has the smaller largest sample bucket, else RMI */
-  ELSAR_MODEL_RADIX = 3 /* no learned model: equi-width buckets of the code, floor(code * B / 95^8), the
-                           radix partitioning the paper compares its model against (Section 3.3) */
+  ELSAR_MODEL_MLP = 1,  /* monotone MLP root over equi-depth spline leaves; RMI if it fails acceptance */
+  ELSAR_MODEL_AUTO = 2, /* RMI when its largest sample bucket is within accept_ratio of a perfect
+                           model's, lambda + sqrt(2 ln(B) lambda) + 1 with lambda = S/B; else SPLINE */
+  ELSAR_MODEL_RADIX = 3, /* no learned model: equi-width buckets of the code, floor(code * B / 95^8), the
+                            radix partitioning the paper compares its model against (Section 3.3) */
+  ELSAR_MODEL_SPLINE = 4 /* linear-spline CDF: K = L/64 segments between equi-depth sample knots over the
+                            same equi-depth spline leaves as the MLP root; a record is routed exactly by a
+                            binary search among the knots, then among its segment's leaves */
 } elsar_model_kind;
 
 /* Fit parameters.  Zero fields take the defaults noted. */
@@ -63,7 +67,8 @@ typedef struct {
   uint32_t record_bytes;  /* record length R (100) */
   uint32_t key_bytes;     /* key length K (10) */
   uint32_t num_buckets;   /* B, the paper's f; 0: largest power of two <= n/950, in [1, 2^21] */
-  uint32_t num_leaves;    /* L; 0: max(1, B/16) */
+  uint32_t num_leaves;    /* L; 0: max(1, B/16) under the linear root, min(B, 2^20) under the equi-depth
+                             (MLP and spline) roots */
   uint64_t sample_size;   /* S; 0: min(max(ceil(n/100), 1024), 10^7, n) (Section 3.1, Section 6) */
   uint64_t seed;          /* seed of the sampler's Philox4x32-10 draws */
   uint32_t kind;          /* elsar_model_kind */
@@ -97,11 +102,15 @@ elsar_status elsar_fit_workspace_size(const elsar_model* m, uint64_t n, size_t* 
  * d_records: n records on the device.  d_ws: elsar_fit_workspace_size bytes.
  * The model's parameters live on the device; the call is asynchronous.
  *
- * kind MLP or AUTO also fits the monotone MLP root (8 quantile-ramp features
- * of the code -> 64 -> 64 -> 1, sigmoid units, non-negative weights; MSE to
- * rank/S on the sample; Adam), fixes its leaves on the sorted sample (leaf of
- * sample s = running maximum of floor(L*y)), fits the same spline leaves over
- * those ranges, and chooses the root on the device (see elsar_model_kind).
+ * kinds MLP, AUTO and SPLINE also cut equi-depth leaves in the sorted
+ * sample: leaf j starts at the first sample of the run of equal codes that
+ * holds sample floor(j*S/L), and takes the same spline over its ranks.  The
+ * spline root groups them in K = L/64 segments whose first codes (knots) it
+ * searches.  Kind MLP also trains the monotone MLP root (8 quantile-ramp
+ * features of the code -> 64 -> 64 -> 1, sigmoid units, non-negative weights;
+ * MSE to rank/S on the sample; Adam), whose guess floor(L*y) starts an exact
+ * search among the leaves' first codes.  The root is chosen on the device (see
+ * elsar_model_kind).
  * With kind MLP the call then synchronises with `stream` and returns
  * ELSAR_E_MODEL_REJECTED when the linear root was kept (the model stays valid).
  */
@@ -142,8 +151,8 @@ elsar_status elsar_sort_workspace_size(const elsar_fit_params* p, uint64_t n, si
  * The whole method on device-resident records: sample + fit, partition, sort
  * and concatenate.  d_out may equal d_in (in place).  d_ws: at least
  * elsar_sort_workspace_size bytes; it holds the model, the partition buffer and
- * the offsets.  Asynchronous; no host synchronisation inside (the MLP/RMI
- * choice of kind MLP or AUTO is made on the device; a rejected MLP falls back
+ * the offsets.  Asynchronous; no host synchronisation inside (the choice of
+ * root of kinds MLP and AUTO is made on the device; a rejected MLP falls back
  * to the RMI without an error).
  */
 elsar_status elsar_sort(const void* d_in, uint64_t n, void* d_out, const elsar_fit_params* p, void* d_ws,
@@ -217,13 +226,15 @@ elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, const el
 
 /* What a fitted model looks like; synchronises with the device. */
 typedef struct {
-  uint32_t kind_used;        /* elsar_model_kind actually in use (RMI or MLP) */
+  uint32_t kind_used;        /* elsar_model_kind of the root in use (RMI, MLP or SPLINE) */
   uint32_t mlp_rejected;     /* 1 if an MLP was fitted and failed the acceptance test */
   uint32_t num_buckets, num_leaves;
   uint64_t sample_size;
   uint64_t n_fit;
   float root_a0, root_a1;    /* linear root (leaf units): floor(fmaf(a1, x, a0)) */
   uint32_t max_sample_bucket, opt_sample_bucket;  /* acceptance statistics (MLP fits) */
+  uint32_t mlp_leaves;       /* equi-depth leaves of the MLP / spline roots (0 without them) */
+  uint32_t spline_segments;  /* K segments of the spline root (0 without it) */
 } elsar_model_info;
 
 elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info);
@@ -233,10 +244,17 @@ elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info);
 elsar_status elsar_model_leaves(const elsar_model* m, uint64_t* h_base, float* h_slope, float* h_icpt,
                                 uint32_t* h_lo, uint32_t* h_hi);
 
-/* The MLP root of a model created with kind MLP or AUTO (ELSAR_E_INVALID_ARG
+/* The spline root of a model created with kind MLP, AUTO or SPLINE
+ * (ELSAR_E_INVALID_ARG otherwise): h_knots[spline_segments + 1] (segment i
+ * starts at code knots[i] = bound[(i L) / K]; knots[K] is past every code),
+ * h_bound[mlp_leaves + 1] and h_first[mlp_leaves + 1] as below.  Any pointer
+ * may be NULL.  Synchronises. */
+elsar_status elsar_model_spline_get(const elsar_model* m, uint64_t* h_knots, uint64_t* h_bound, uint32_t* h_first);
+
+/* The MLP root of a model created with kind MLP (ELSAR_E_INVALID_ARG
  * otherwise): h_params[ELSAR_MLP_PARAMS] (FP32 master copy), h_knots[9]
- * (q_0..q_8), h_bound[num_leaves + 1] (leaf j takes the codes in
- * [bound[j], bound[j+1])), h_first[num_leaves + 1] (first sample rank of each
+ * (q_0..q_8), h_bound[mlp_leaves + 1] (leaf j takes the codes in
+ * [bound[j], bound[j+1])), h_first[mlp_leaves + 1] (first sample rank of each
  * leaf; first[L] = S).  Any pointer may be NULL.  Synchronises. */
 elsar_status elsar_model_mlp_get(const elsar_model* m, float* h_params, uint64_t* h_knots, uint64_t* h_bound,
                                  uint32_t* h_first);

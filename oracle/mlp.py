@@ -5,7 +5,7 @@ root this build adds is a small monotone MLP fitted to the same target, the
 empirical CDF of the sample (rank / S), and used as the RMI's root.  This module
 is the plain reference of what the GPU computes: features, forward pass, MSE
 loss, backward pass, the Adam step with the non-negativity projection, and the
-leaf assignment of a sorted sample.  Everything is FP64 numpy; ``bf16=True``
+equi-depth leaf ranges of a sorted sample.  Everything is FP64 numpy; ``bf16=True``
 rounds the hidden activations and the 64x64 weights to bfloat16 the way the GPU
 feeds its matrix cores, for parity checks on identical inputs.
 
@@ -129,14 +129,17 @@ def pack(P: dict) -> np.ndarray:
     return np.concatenate([np.asarray(P[k], dtype=np.float64).ravel() for k in PARAM_SHAPES])
 
 
-def first_of_leaves(leaves: np.ndarray, L: int) -> np.ndarray:
-    """first[j] = first sample whose leaf is >= j, for non-decreasing per-sample
-    leaves; first[L] = S."""
-    return np.searchsorted(np.asarray(leaves), np.arange(L + 1), side="left").astype(np.uint64)
+def equi_depth_first(sorted_codes: np.ndarray, L: int) -> np.ndarray:
+    """Leaf ranges under the MLP root: leaf j starts at the first sample of the
+    run of equal codes that holds sample floor(j*S/L) (a run of equal keys is
+    never split between leaves); first[L] = S."""
+    c = np.asarray(sorted_codes, dtype=np.uint64)
+    S = c.size
+    q = (np.arange(L, dtype=np.int64) * S) // L
+    first = np.searchsorted(c, c[q], side="left")
+    return np.append(first, S).astype(np.uint64)
 
 
-def leaves_of_sorted(y: np.ndarray, L: int) -> np.ndarray:
-    """Leaf of each sample of a sorted sample from the root outputs y:
-    floor(L*y) clamped to [0, L-1], made non-decreasing by a running maximum."""
-    lv = np.clip(np.floor(np.asarray(y) * L), 0, L - 1).astype(np.int64)
-    return np.maximum.accumulate(lv)
+def leaf_guess(y: np.ndarray, L: int) -> np.ndarray:
+    """The router's starting leaf floor(L*y), clamped to [0, L-1]."""
+    return np.clip(np.floor(np.asarray(y) * L), 0, L - 1).astype(np.int64)

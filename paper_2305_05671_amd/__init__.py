@@ -20,7 +20,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libelsar.so")
 
-RMI, MLP, AUTO, RADIX = 0, 1, 2, 3
+RMI, MLP, AUTO, RADIX, SPLINE = 0, 1, 2, 3, 4
 MLP_PARAMS = 4801
 MLP_GRAD_ROWS = 128
 OK, E_INVALID_ARG, E_NO_MEMORY, E_HIP, E_UNSUPPORTED, E_MODEL_REJECTED = range(6)
@@ -53,6 +53,8 @@ class ModelInfo(ctypes.Structure):
         ("root_a1", ctypes.c_float),
         ("max_sample_bucket", ctypes.c_uint32),
         ("opt_sample_bucket", ctypes.c_uint32),
+        ("mlp_leaves", ctypes.c_uint32),
+        ("spline_segments", ctypes.c_uint32),
     ]
 
 
@@ -133,6 +135,7 @@ def lib():
             "elsar_model_leaves": ([_P, _P, _P, _P, _P, _P], st),
             "elsar_partition_stats_get": ([_P, _P, _SZ, ctypes.POINTER(PartitionStats)], st),
             "elsar_model_mlp_get": ([_P, _P, _P, _P, _P], st),
+            "elsar_model_spline_get": ([_P, _P, _P, _P], st),
             "elsar_sort_batch_workspace_size": ([ctypes.POINTER(Job), ctypes.c_uint32, ctypes.POINTER(FitParams),
                                                  ctypes.POINTER(_SZ)], st),
             "elsar_sort_batch": ([ctypes.POINTER(Job), ctypes.c_uint32, ctypes.POINTER(FitParams), _P, _SZ, _P], st),
@@ -368,7 +371,7 @@ class Model:
     def mlp(self):
         """(params[4801] f32, knots[9] u64, bound[L+1] u64, first[L+1] u32) of the MLP root."""
         import numpy as np
-        L = self.info().num_leaves
+        L = self.info().mlp_leaves
         params = np.zeros(MLP_PARAMS, np.float32)
         knots = np.zeros(9, np.uint64)
         bound = np.zeros(L + 1, np.uint64)
@@ -376,6 +379,17 @@ class Model:
         _check("elsar_model_mlp_get", lib().elsar_model_mlp_get(self._h, params.ctypes.data, knots.ctypes.data,
                                                                 bound.ctypes.data, first.ctypes.data))
         return params, knots, bound, first
+
+    def spline(self):
+        """(knots[K+1] u64, bound[L+1] u64, first[L+1] u32) of the equi-depth leaves and the spline root."""
+        import numpy as np
+        i = self.info()
+        knots = np.zeros(i.spline_segments + 1, np.uint64)
+        bound = np.zeros(i.mlp_leaves + 1, np.uint64)
+        first = np.zeros(i.mlp_leaves + 1, np.uint32)
+        _check("elsar_model_spline_get", lib().elsar_model_spline_get(self._h, knots.ctypes.data, bound.ctypes.data,
+                                                                      first.ctypes.data))
+        return knots, bound, first
 
     def partition_stats(self, part) -> PartitionStats:
         s = PartitionStats()

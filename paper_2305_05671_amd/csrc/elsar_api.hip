@@ -20,13 +20,14 @@ using namespace elsar;
 
 struct elsar_model {
   elsar_fit_params p;  // resolved parameters
-  uint32_t B, L;
+  uint32_t B, L;       // buckets, leaves under the linear root
+  uint32_t Lm;         // leaves under the MLP root
   uint64_t S, n;
   void* dev;           // owned allocation (null for a model placed in a workspace)
   ModelHeader* hdr;
   Leaf* leaves;
   uint32_t* hist;      // sample keys per bucket (B) under the root in use
-  bool has_mlp;        // kind MLP or AUTO: the MLP state below is placed
+  bool has_mlp;        // kind MLP, AUTO or SPLINE: the equi-depth state below is placed
   MlpState ms;
 };
 
@@ -60,7 +61,7 @@ elsar_status check_params(const elsar_fit_params* p) {
     return ELSAR_E_UNSUPPORTED;
   if (p->num_buckets > kMaxBuckets) return ELSAR_E_INVALID_ARG;
   if (p->num_leaves > (1u << 22)) return ELSAR_E_INVALID_ARG;
-  if (p->kind > ELSAR_MODEL_RADIX) return ELSAR_E_INVALID_ARG;
+  if (p->kind > ELSAR_MODEL_SPLINE) return ELSAR_E_INVALID_ARG;
   if (p->sample_size > 10000000ull * 4) return ELSAR_E_INVALID_ARG;
   if (p->region_pct > 1000) return ELSAR_E_INVALID_ARG;
   return ELSAR_OK;
@@ -68,7 +69,7 @@ elsar_status check_params(const elsar_fit_params* p) {
 
 // Resolved shape of a model for n records.
 struct Shape {
-  uint32_t B, L;
+  uint32_t B, L, Lm;  // buckets, leaves under the linear and under the MLP root
   uint64_t S;
 };
 
@@ -84,16 +85,22 @@ Shape resolve(const elsar_fit_params& p, uint64_t n) {
   Shape s;
   s.B = p.num_buckets ? p.num_buckets : default_buckets(n);
   s.L = p.num_leaves ? p.num_leaves : std::max<uint32_t>(1, s.B / 16);
+  // the MLP root's leaves are equi-depth in the sample: one per bucket by
+  // default (at most 2^20)
+  s.Lm = p.num_leaves ? p.num_leaves : std::min<uint32_t>(s.B, 1u << 20);
   s.S = p.sample_size ? std::min<uint64_t>(p.sample_size, n) : default_sample_size(n);
   if (n > 0 && s.S == 0) s.S = 1;
   return s;
 }
 
-bool wants_mlp(uint32_t kind) { return kind == ELSAR_MODEL_MLP || kind == ELSAR_MODEL_AUTO; }
+// Kinds with equi-depth leaves (the MLP and the spline roots).
+bool wants_mlp(uint32_t kind) {
+  return kind == ELSAR_MODEL_MLP || kind == ELSAR_MODEL_AUTO || kind == ELSAR_MODEL_SPLINE;
+}
 
-size_t model_dev_bytes(uint32_t L, uint32_t B, uint32_t kind) {
-  size_t b = align_up(sizeof(ModelHeader)) + align_up((size_t)L * sizeof(Leaf)) + align_up((size_t)B * 4);
-  if (wants_mlp(kind)) b += align_up(mlp_state_bytes(L, B));
+size_t model_dev_bytes(const Shape& sh, uint32_t kind) {
+  size_t b = align_up(sizeof(ModelHeader)) + align_up((size_t)sh.L * sizeof(Leaf)) + align_up((size_t)sh.B * 4);
+  if (wants_mlp(kind)) b += align_up(mlp_state_bytes(sh.Lm, sh.B));
   return b;
 }
 
@@ -107,7 +114,7 @@ void place_model(elsar_model* m, void* base) {
   b += align_up((size_t)m->B * 4);
   m->has_mlp = wants_mlp(m->p.kind);
   m->ms = MlpState{};
-  if (m->has_mlp) place_mlp_state(&m->ms, b, m->L, m->B);
+  if (m->has_mlp) place_mlp_state(&m->ms, b, m->Lm, m->B);
 }
 
 size_t fit_ws_bytes(uint64_t S) {
@@ -208,8 +215,12 @@ elsar_status do_fit(elsar_model* m, const void* d_records, uint64_t n, void* d_w
   HIP_TRY(launch_radix_sort_u64(codes, tmp, S, 0, 6, rscr, st, &sorted));
   HIP_TRY(launch_fit_rmi(sorted, S, n, m->L, m->B, m->hdr, m->leaves, fscr, st));
   HIP_TRY(launch_sample_hist(m->hdr, m->leaves, sorted, S, m->B, m->hist, st));
-  if (m->has_mlp)
-    HIP_TRY(launch_mlp_fit(sorted, S, m->L, m->B, m->p.seed, m->p.mlp_steps, kMlpLearningRate, m->hdr, m->ms, st));
+  if (m->has_mlp) {
+    HIP_TRY(launch_auto_gate(m->hist, m->B, S, m->p.accept_ratio, m->p.kind, m->hdr, st));
+    if (m->p.kind == ELSAR_MODEL_MLP)
+      HIP_TRY(launch_mlp_train(sorted, S, m->p.seed, m->p.mlp_steps, kMlpLearningRate, m->ms, st));
+    HIP_TRY(launch_equi_depth_leaves(sorted, S, m->Lm, m->B, m->hdr, m->ms, st));
+  }
   HIP_TRY(launch_decide_root(m->hist, m->has_mlp ? &m->ms : nullptr, m->B, S, m->p.accept_ratio, m->p.kind,
                              m->hdr, m->hist, st));
   m->n = n;
@@ -254,7 +265,7 @@ SortLayout sort_layout(const elsar_fit_params& p, const Shape& sh, uint64_t n) {
   SortLayout sl{};
   size_t off = 0;
   sl.model = off;
-  off += align_up(model_dev_bytes(sh.L, sh.B, p.kind));
+  off += align_up(model_dev_bytes(sh, p.kind));
   sl.fit = off;
   off += align_up(fit_ws_bytes(sh.S));
   sl.offsets = off;
@@ -293,9 +304,10 @@ elsar_status elsar_model_create(const elsar_fit_params* p, uint64_t n, elsar_mod
   m->p = with_defaults(*p);
   m->B = sh.B;
   m->L = sh.L;
+  m->Lm = sh.Lm;
   m->S = sh.S;
   m->n = 0;
-  if (hipMalloc(&m->dev, model_dev_bytes(m->L, m->B, m->p.kind)) != hipSuccess) {
+  if (hipMalloc(&m->dev, model_dev_bytes(sh, m->p.kind)) != hipSuccess) {
     delete m;
     return ELSAR_E_NO_MEMORY;
   }
@@ -322,7 +334,7 @@ elsar_status elsar_sample_fit(elsar_model* m, const void* d_records, uint64_t n,
   if (n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;
   if (n && (!d_records || !d_ws || !aligned16(d_records))) return ELSAR_E_INVALID_ARG;
   Shape sh = resolve(m->p, n);
-  if (sh.B != m->B || sh.L != m->L) return ELSAR_E_INVALID_ARG;  // model shaped for another n
+  if (sh.B != m->B || sh.L != m->L || sh.Lm != m->Lm) return ELSAR_E_INVALID_ARG;  // model shaped for another n
   m->S = sh.S;
   if (ws_bytes < fit_ws_bytes(m->S)) return ELSAR_E_NO_MEMORY;
   elsar_status s = do_fit(m, d_records, n, d_ws, ws_bytes, stream);
@@ -380,7 +392,7 @@ namespace {
 // One whole sort on device-resident records; q has its defaults filled in.
 // A model fitted ahead of the job (batch): where it lives.
 struct Prefit {
-  uint8_t* base;  // model_dev_bytes(L, B, RMI) bytes, placed as place_model does
+  uint8_t* base;  // model_dev_bytes(shape, RMI) bytes, placed as place_model does
 };
 
 elsar_status sort_job(const void* d_in, uint64_t n, void* d_out, const elsar_fit_params& q, void* d_ws,
@@ -397,6 +409,7 @@ elsar_status sort_job(const void* d_in, uint64_t n, void* d_out, const elsar_fit
   m.p = q;
   m.B = sh.B;
   m.L = sh.L;
+  m.Lm = sh.Lm;
   m.S = sh.S;
   m.dev = nullptr;
   place_model(&m, pre ? pre->base : w + sl.model);
@@ -507,7 +520,7 @@ elsar_status batch_layout(const elsar_job* jobs, uint32_t njobs, const elsar_fit
     const elsar_fit_params q = job_params(p, jobs[j].n, j);
     const Shape sh = resolve(q, jobs[j].n);
     bl->prefit_model.push_back(off);
-    off += align_up(model_dev_bytes(sh.L, sh.B, ELSAR_MODEL_RMI));
+    off += align_up(model_dev_bytes(sh, ELSAR_MODEL_RMI));
   }
   bl->tiny_stage = off;
   off += align_up(stage_dw * 4);
@@ -773,7 +786,7 @@ HostLayout host_layout(const elsar_fit_params& q, uint64_t n, uint64_t C, uint64
     off += align_up(bytes);
     return o;
   };
-  h.model = take(model_dev_bytes(h.sh.L, h.sh.B, q.kind));
+  h.model = take(model_dev_bytes(h.sh, q.kind));
   h.fit = take(fit_ws_bytes(h.sh.S));
   h.counts = take((size_t)h.sh.B * 4);
   h.offsets = take(((size_t)h.sh.B + 1) * 8);
@@ -893,6 +906,7 @@ elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, const el
   m.p = q;
   m.B = hl.sh.B;
   m.L = hl.sh.L;
+  m.Lm = hl.sh.Lm;
   const uint64_t c0 = std::min<uint64_t>(hl.C, n);
   m.S = std::min<uint64_t>(hl.sh.S, c0);
   place_model(&m, w + hl.model);
@@ -982,10 +996,12 @@ elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info) 
   ModelHeader h;
   HIP_TRY(hipMemcpy(&h, m->hdr, sizeof(h), hipMemcpyDeviceToHost));
   std::memset(info, 0, sizeof(*info));
-  info->kind_used = h.kind_used;
+  info->kind_used = h.kind_used == 2 ? (uint32_t)ELSAR_MODEL_SPLINE : h.kind_used;  // header: 2 = spline root
   info->mlp_rejected = h.mlp_rejected;
   info->num_buckets = m->B;
-  info->num_leaves = m->L;
+  info->num_leaves = (m->has_mlp && h.kind_used != 0) ? m->Lm : m->L;
+  info->mlp_leaves = m->has_mlp ? m->Lm : 0;
+  info->spline_segments = m->has_mlp ? spline_segments(m->Lm) : 0;
   info->sample_size = m->S;
   info->n_fit = m->n;
   info->root_a0 = h.a0;
@@ -1000,10 +1016,11 @@ elsar_status elsar_model_leaves(const elsar_model* m, uint64_t* h_base, float* h
   if (!m) return ELSAR_E_INVALID_ARG;
   ModelHeader h;
   HIP_TRY(hipMemcpy(&h, m->hdr, sizeof(h), hipMemcpyDeviceToHost));
-  const Leaf* src = (m->has_mlp && h.kind_used == 1) ? m->ms.leaves : m->leaves;
-  std::vector<Leaf> lv(m->L);
+  const bool mlp = m->has_mlp && h.kind_used != 0;
+  const Leaf* src = mlp ? m->ms.leaves : m->leaves;
+  std::vector<Leaf> lv(mlp ? m->Lm : m->L);
   HIP_TRY(hipMemcpy(lv.data(), src, lv.size() * sizeof(Leaf), hipMemcpyDeviceToHost));
-  for (uint32_t j = 0; j < m->L; ++j) {
+  for (uint32_t j = 0; j < lv.size(); ++j) {
     if (h_base) h_base[j] = lv[j].base;
     if (h_slope) h_slope[j] = lv[j].c;
     if (h_icpt) h_icpt[j] = lv[j].b;
@@ -1013,13 +1030,22 @@ elsar_status elsar_model_leaves(const elsar_model* m, uint64_t* h_base, float* h
   return ELSAR_OK;
 }
 
+elsar_status elsar_model_spline_get(const elsar_model* m, uint64_t* h_knots, uint64_t* h_bound, uint32_t* h_first) {
+  if (!m || !m->has_mlp) return ELSAR_E_INVALID_ARG;
+  const size_t K = spline_segments(m->Lm);
+  if (h_knots) HIP_TRY(hipMemcpy(h_knots, m->ms.knots, (K + 1) * 8, hipMemcpyDeviceToHost));
+  if (h_bound) HIP_TRY(hipMemcpy(h_bound, m->ms.bound, ((size_t)m->Lm + 1) * 8, hipMemcpyDeviceToHost));
+  if (h_first) HIP_TRY(hipMemcpy(h_first, m->ms.first, ((size_t)m->Lm + 1) * 4, hipMemcpyDeviceToHost));
+  return ELSAR_OK;
+}
+
 elsar_status elsar_model_mlp_get(const elsar_model* m, float* h_params, uint64_t* h_knots, uint64_t* h_bound,
                                  uint32_t* h_first) {
-  if (!m || !m->has_mlp) return ELSAR_E_INVALID_ARG;
+  if (!m || !m->has_mlp || m->p.kind != ELSAR_MODEL_MLP) return ELSAR_E_INVALID_ARG;
   if (h_params) HIP_TRY(hipMemcpy(h_params, m->ms.master, (size_t)kMlpParams * 4, hipMemcpyDeviceToHost));
   if (h_knots) HIP_TRY(hipMemcpy(h_knots, m->ms.M->h.q, 9 * 8, hipMemcpyDeviceToHost));
-  if (h_bound) HIP_TRY(hipMemcpy(h_bound, m->ms.bound, ((size_t)m->L + 1) * 8, hipMemcpyDeviceToHost));
-  if (h_first) HIP_TRY(hipMemcpy(h_first, m->ms.first, ((size_t)m->L + 1) * 4, hipMemcpyDeviceToHost));
+  if (h_bound) HIP_TRY(hipMemcpy(h_bound, m->ms.bound, ((size_t)m->Lm + 1) * 8, hipMemcpyDeviceToHost));
+  if (h_first) HIP_TRY(hipMemcpy(h_first, m->ms.first, ((size_t)m->Lm + 1) * 4, hipMemcpyDeviceToHost));
   return ELSAR_OK;
 }
 

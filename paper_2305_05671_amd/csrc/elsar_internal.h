@@ -32,13 +32,15 @@ static_assert(sizeof(Leaf) == 32, "leaf is two 16-byte vectors");
 struct ModelHeader {   // device-resident root of a fitted model
   float a0, a1;        // linear root in leaf units
   uint32_t L, B;       // leaves, buckets
-  uint32_t kind_used;  // 0 = RMI root, 1 = MLP root
+  uint32_t kind_used;  // root in use: 0 = linear RMI, 1 = MLP, 2 = linear spline
   uint32_t mlp_rejected;
   uint64_t n_fit;      // records the model was fitted for
   uint64_t S;          // sample size
   uint32_t max_sample_bucket, opt_sample_bucket;
   uint32_t max_sample_run;  // longest run of equal codes in the sorted sample
-  uint32_t pad[3];
+  uint32_t mlp_L;           // equi-depth leaves under the MLP or spline root
+  uint32_t mlp_skip;        // automatic choice: the linear root passed the gate
+  uint32_t spline_K;        // segments of the spline root
 };
 
 // Monotone MLP root (8 -> 64 -> 64 -> 1), flat parameter order W1 (64x8),
@@ -151,6 +153,30 @@ __device__ __forceinline__ uint32_t leaf_bucket(const Leaf& lf, uint64_t e) {
   return (uint32_t)y;
 }
 
+// Spline root over equi-depth leaves: K segments of about L / K leaves each;
+// segment i holds leaves (i L) / K .. ((i + 1) L) / K - 1 and starts at the
+// code knots[i] = bound[(i L) / K] (knots[K] past every code).
+__host__ __device__ __forceinline__ uint32_t spline_segments(uint32_t L) { return L >= 64 ? L / 64 : 1; }
+
+// The leaf j with bound[j] <= code < bound[j+1]: a binary search among the K
+// segment knots (a small table that stays in the L1 cache), then among the
+// segment's own leaves.
+__device__ __forceinline__ uint32_t spline_exact_leaf(const uint64_t* __restrict__ knots, uint32_t K,
+                                                      const uint64_t* __restrict__ bound, uint32_t L,
+                                                      uint64_t code) {
+  uint32_t lo = 0, hi = K;  // knots[lo] <= code < knots[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (knots[mid] <= code) lo = mid; else hi = mid;
+  }
+  uint32_t a = (uint32_t)(((uint64_t)lo * L) / K), b = (uint32_t)(((uint64_t)(lo + 1) * L) / K);
+  while (b - a > 1) {  // bound[a] <= code < bound[b]
+    const uint32_t mid = (a + b) >> 1;
+    if (bound[mid] <= code) a = mid; else b = mid;
+  }
+  return a;
+}
+
 __device__ __forceinline__ Leaf load_leaf(const Leaf* __restrict__ leaves, uint32_t j) {
   const uint4* p = reinterpret_cast<const uint4*>(leaves + j);
   uint4 a = p[0], b = p[1];
@@ -248,20 +274,31 @@ hipError_t launch_radix_model(uint64_t S, uint64_t n, uint32_t L, uint32_t B, Mo
 hipError_t launch_capacities(const uint32_t* hist, uint64_t S, uint64_t n, uint32_t B, uint32_t region_pct,
                              uint8_t* part, const PartLayout& lay, hipStream_t st);
 
-// MLP root (k_mlp.hip).  The model state beyond the RMI's.
+// Equi-depth roots (k_mlp.hip): the MLP and the linear spline share leaves
+// cut at sample quantiles; the state beyond the RMI's.
 struct MlpState {
   MlpBlock* M;
-  Leaf* leaves;      // L leaves under the MLP root
+  Leaf* leaves;      // L equi-depth leaves
   uint64_t* bound;   // L + 1 routing boundaries: leaf j takes codes in [bound[j], bound[j+1])
   uint32_t* first;   // L + 1: first sample rank of each leaf
-  uint32_t* hist;    // B: sample keys per bucket under the MLP root
-  float* master;     // kMlpParams FP32 parameters
+  uint32_t* hist;    // B: sample keys per bucket under these leaves
+  uint64_t* knots;   // spline_segments(L) + 1 segment knots of the spline root
+  float* master;     // kMlpParams FP32 parameters of the MLP
   float* adam;       // 2 * kMlpParams moments
 };
 size_t mlp_state_bytes(uint32_t L, uint32_t B);
 void place_mlp_state(MlpState* s, void* base, uint32_t L, uint32_t B);
-hipError_t launch_mlp_fit(const uint64_t* sorted_codes, uint64_t S, uint32_t L, uint32_t B, uint64_t seed,
-                          uint32_t steps, float lr, ModelHeader* hdr, const MlpState& ms, hipStream_t st);
+// MLP training on the sorted sample (initial weights, Adam steps).
+hipError_t launch_mlp_train(const uint64_t* sorted_codes, uint64_t S, uint64_t seed, uint32_t steps, float lr,
+                            const MlpState& ms, hipStream_t st);
+// Equi-depth leaves, their splines and boundaries, the spline root's knots,
+// and the sample histogram under these leaves.
+hipError_t launch_equi_depth_leaves(const uint64_t* sorted_codes, uint64_t S, uint32_t L, uint32_t B,
+                                    ModelHeader* hdr, const MlpState& ms, hipStream_t st);
+// Automatic kind: whether the linear root is kept (ModelHeader::mlp_skip);
+// other kinds clear the flag.
+hipError_t launch_auto_gate(const uint32_t* hist_rmi, uint32_t B, uint64_t S, float accept_ratio, uint32_t kind,
+                            ModelHeader* hdr, hipStream_t st);
 hipError_t launch_decide_root(const uint32_t* hist_rmi, const MlpState* ms, uint32_t B, uint64_t S,
                               float accept_ratio, uint32_t kind, ModelHeader* hdr, uint32_t* hist_used,
                               hipStream_t st);

@@ -250,6 +250,9 @@ __global__ __launch_bounds__(kFitThreads) void root_final_kernel(uint64_t S, uin
     hdr->mlp_rejected = 0;
     hdr->n_fit = n;
     hdr->S = S;
+    hdr->max_sample_run = 0;
+    hdr->mlp_L = 0;
+    hdr->mlp_skip = 0;
   }
 }
 
@@ -379,6 +382,8 @@ __global__ void radix_model_kernel(uint64_t S, uint64_t n, uint32_t L, uint32_t 
     hdr->n_fit = n;
     hdr->S = S;
     hdr->max_sample_run = 0;
+    hdr->mlp_L = 0;
+    hdr->mlp_skip = 0;
   }
 }
 
@@ -485,6 +490,8 @@ __device__ void fit_job_block(const FitJob& J, uint32_t rec_bytes, uint64_t* e, 
       h->max_sample_bucket = mm;
       h->opt_sample_bucket = (uint32_t)((S + J.B - 1) / J.B);
       h->max_sample_run = 0;
+      h->mlp_L = 0;
+      h->mlp_skip = 0;
     }
     __syncthreads();
   }

@@ -28,7 +28,8 @@ inline size_t al(size_t x) { return (x + kA - 1) & ~(kA - 1); }
 
 size_t mlp_state_bytes(uint32_t L, uint32_t B) {
   return al(sizeof(MlpBlock)) + al((size_t)L * sizeof(Leaf)) + al(((size_t)L + 1) * 8) + al(((size_t)L + 1) * 4) +
-         al((size_t)B * 4) + al((size_t)kMlpParams * 4) + al((size_t)kMlpParams * 8);
+         al((size_t)B * 4) + al(((size_t)spline_segments(L) + 1) * 8) + al((size_t)kMlpParams * 4) +
+         al((size_t)kMlpParams * 8);
 }
 
 void place_mlp_state(MlpState* s, void* base, uint32_t L, uint32_t B) {
@@ -43,6 +44,8 @@ void place_mlp_state(MlpState* s, void* base, uint32_t L, uint32_t B) {
   b += al(((size_t)L + 1) * 4);
   s->hist = reinterpret_cast<uint32_t*>(b);
   b += al((size_t)B * 4);
+  s->knots = reinterpret_cast<uint64_t*>(b);
+  b += al(((size_t)spline_segments(L) + 1) * 8);
   s->master = reinterpret_cast<float*>(b);
   b += al((size_t)kMlpParams * 4);
   s->adam = reinterpret_cast<float*>(b);
@@ -64,11 +67,10 @@ __device__ void set_knots(const uint64_t* q9, MlpHead* h) {
 // Knots q_k = e[k S / 8] (k < 8), q_8 = e[S-1]; initial weights from Philox
 // draws u: W1 = u, b1 = -4u, W2 = 0.1u, b2 = -3, w3 = 0.05u, b3 = 0 (small
 // positive weights, hidden units off saturation); Adam moments zero.
-__global__ void mlp_setup_kernel(const uint64_t* __restrict__ e, uint64_t S, uint64_t seed, MlpBlock* __restrict__ M,
-                                 float* __restrict__ master, float* __restrict__ adam, ModelHeader* __restrict__ hdr) {
+__global__ void mlp_setup_kernel(const uint64_t* __restrict__ e, uint64_t S, uint64_t seed,
+                                 MlpBlock* __restrict__ M, float* __restrict__ master, float* __restrict__ adam) {
   __shared__ uint64_t q9[9];
   if (threadIdx.x < 9) q9[threadIdx.x] = e[threadIdx.x < 8 ? (threadIdx.x * S) / 8 : S - 1];
-  if (threadIdx.x == 0) hdr->max_sample_run = 0;
   __syncthreads();
   set_knots(q9, &M->h);
   for (uint32_t p = threadIdx.x; p < kMlpParams; p += blockDim.x) {
@@ -411,49 +413,30 @@ __global__ __launch_bounds__(256) void mlp_eval_kernel(const MlpBlock* __restric
   if (i < n) y[i] = v;
 }
 
-// Raw leaf of every sorted sample, floor(L y) clamped; first_exact[j] gets
-// the smallest sample with raw leaf j (atomic minimum).
-__global__ __launch_bounds__(256) void mlp_sample_leaves_kernel(const uint64_t* __restrict__ e, uint64_t S,
-                                                                uint32_t L, const MlpBlock* __restrict__ Mg,
-                                                                uint32_t* __restrict__ first_exact) {
-  __shared__ MlpHead mh;
-  load_head(Mg, mh);
-  W2Frags w;
-  mlp_load_w2(Mg->W2bf, w);
-  __syncthreads();
-  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const float y = mlp_y64(e[s < S ? s : S - 1], mh, w);
-  const uint32_t j = mlp_leaf_guess(y, L);
-  // a lane whose left neighbour has the same leaf holds a larger position than
-  // that neighbour, so only the first lane of each run of equal leaves can
-  // hold the minimum (the sample is sorted, so runs are long)
-  const uint32_t jl = __shfl_up(j, 1);
-  if (s < S && (__lane_id() == 0 || jl != j)) atomicMin(&first_exact[j], (uint32_t)s);
-}
-
-// first[j] = min over j' >= j of first_exact[j'] (the running maximum of the
-// raw leaves, seen from the leaf side); first[L] = S.  One block.
-__global__ __launch_bounds__(1024) void suffix_min_kernel(uint32_t* __restrict__ v, uint32_t L, uint32_t S) {
-  __shared__ uint32_t sh[1024];
-  const uint32_t per = (L + 1023) / 1024;
-  const uint32_t b = threadIdx.x * per < L ? threadIdx.x * per : L;
-  const uint32_t end = b + per < L ? b + per : L;
-  uint32_t m = S;
-  for (uint32_t i = b; i < end; ++i) m = v[i] < m ? v[i] : m;
-  sh[threadIdx.x] = m;
-  __syncthreads();
-  for (uint32_t off = 1; off < 1024; off <<= 1) {
-    const uint32_t x = threadIdx.x + off < 1024 ? sh[threadIdx.x + off] : S;
-    __syncthreads();
-    if (x < sh[threadIdx.x]) sh[threadIdx.x] = x;
-    __syncthreads();
+// Equi-depth leaves on the sorted sample: leaf j starts at the first sample
+// of the run of equal codes that holds sample floor(j S / L), so a run is
+// never split (its records route to one leaf); first[L] = S.  Leaves that a
+// long run swallows come out empty (first[j] == first[j+1]).
+__global__ __launch_bounds__(256) void quantile_first_kernel(const uint64_t* __restrict__ e, uint64_t S,
+                                                             uint32_t L, uint32_t* __restrict__ first,
+                                                             ModelHeader* __restrict__ hdr) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > L) return;
+  if (j == L) {
+    first[L] = (uint32_t)S;
+    hdr->mlp_L = L;
+    hdr->spline_K = spline_segments(L);
+    hdr->max_sample_run = 0;
+    return;
   }
-  uint32_t run = threadIdx.x + 1 < 1024 ? sh[threadIdx.x + 1] : S;
-  for (uint32_t i = end; i > b; --i) {
-    run = v[i - 1] < run ? v[i - 1] : run;
-    v[i - 1] = run;
+  const uint64_t q = ((uint64_t)j * S) / L;
+  const uint64_t c = e[q];
+  uint64_t lo = 0, hi = q;  // the first position holding c; e[hi] == c
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (e[mid] < c) lo = mid + 1; else hi = mid;
   }
-  if (threadIdx.x == 0) v[L] = S;
+  first[j] = (uint32_t)lo;
 }
 
 // Leaf j covers samples first[j] .. first[j+1]-1: the same two-point spline
@@ -490,7 +473,14 @@ __global__ __launch_bounds__(256) void mlp_leaf_fit_kernel(const uint64_t* __res
   leaves[j] = lf;
 }
 
-// Per sample: its bucket under the MLP root (leaf found from first[]), and
+// Segment knots of the spline root: knots[i] = bound[(i L) / K], i = 0..K.
+__global__ __launch_bounds__(256) void spline_knots_kernel(const uint64_t* __restrict__ bound, uint32_t L,
+                                                           uint32_t K, uint64_t* __restrict__ knots) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= K) knots[i] = bound[((uint64_t)i * L) / K];
+}
+
+// Per sample: its bucket under the equi-depth leaves (leaf found from first[]), and
 // the longest run of equal codes (no monotone bucketing can split a run).
 __global__ __launch_bounds__(256) void mlp_sample_stats_kernel(const uint64_t* __restrict__ e, uint64_t S,
                                                                uint32_t L, const uint32_t* __restrict__ first,
@@ -527,11 +517,36 @@ __global__ __launch_bounds__(256) void mlp_sample_stats_kernel(const uint64_t* _
   }
 }
 
-// Choice of the root.  The MLP passes when its largest sample bucket is at
-// most accept_ratio times the ideal max(ceil(S/B), longest equal-code run).
-// kind 1 (MLP): the MLP if it passes, else the linear root.  kind 2 (automatic):
-// the MLP if it passes or beats the linear root's largest sample bucket.
-// The chosen root's sample histogram is copied to hist_used.
+// Automatic choice: the linear root is kept when its largest sample bucket is
+// within accept_ratio of what a perfect model shows on S sample keys,
+// lambda + sqrt(2 ln(B) lambda) + 1 with lambda = S/B (about the largest of B
+// Poisson(lambda) counts); otherwise the spline root takes over.  One block.
+__global__ __launch_bounds__(256) void auto_gate_kernel(const uint32_t* __restrict__ hist_rmi, uint32_t B,
+                                                        uint64_t S, float accept_ratio, uint32_t kind,
+                                                        ModelHeader* __restrict__ hdr) {
+  __shared__ uint32_t mr[256];
+  uint32_t a = 0;
+  for (uint32_t j = threadIdx.x; j < B; j += 256) a = hist_rmi[j] > a ? hist_rmi[j] : a;
+  mr[threadIdx.x] = a;
+  __syncthreads();
+  for (uint32_t off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off && mr[threadIdx.x + off] > mr[threadIdx.x]) mr[threadIdx.x] = mr[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double lambda = (double)S / (double)B;
+    const double perfect = lambda + sqrt(2.0 * log((double)B) * lambda) + 1.0;
+    hdr->mlp_skip = (kind == 2u && (double)mr[0] <= (double)accept_ratio * perfect) ? 1u : 0u;
+  }
+}
+
+// Choice of the root.  hist_eq: the sample histogram under the equi-depth
+// leaves (MLP and spline roots share them).  kind 1 (MLP): the MLP if its
+// largest sample bucket is at most accept_ratio times the ideal
+// max(ceil(S/B), longest equal-code run), else the linear root.  kind 2
+// (automatic): the linear root if it passed the gate, else the spline root.
+// kind 4 (spline): the spline root.  The chosen root's sample histogram is
+// copied to hist_used.
 __global__ __launch_bounds__(256) void decide_root_kernel(const uint32_t* __restrict__ hist_rmi,
                                                           const uint32_t* __restrict__ hist_mlp, uint32_t B,
                                                           uint64_t S, float accept_ratio, uint32_t kind,
@@ -559,9 +574,15 @@ __global__ __launch_bounds__(256) void decide_root_kernel(const uint32_t* __rest
     if (hist_mlp && hdr->max_sample_run > ideal) ideal = hdr->max_sample_run;
     uint32_t u = 0, rejected = 0;
     if (hist_mlp) {
-      const bool pass = (double)mm[0] <= (double)accept_ratio * (double)ideal;
-      rejected = pass ? 0u : 1u;
-      u = (pass || (kind == 2 && mm[0] < mr[0])) ? 1u : 0u;
+      if (kind == 1u) {
+        const bool pass = (double)mm[0] <= (double)accept_ratio * (double)ideal;
+        rejected = pass ? 0u : 1u;
+        u = pass ? 1u : 0u;
+      } else if (kind == 2u) {
+        u = hdr->mlp_skip ? 0u : 2u;
+      } else if (kind == 4u) {
+        u = 2u;
+      }
     }
     hdr->kind_used = u;
     hdr->mlp_rejected = rejected;
@@ -590,25 +611,35 @@ hipError_t mlp_prepare_kernels() {
   return once;
 }
 
-hipError_t launch_mlp_fit(const uint64_t* e, uint64_t S, uint32_t L, uint32_t B, uint64_t seed, uint32_t steps,
-                          float lr, ModelHeader* hdr, const MlpState& ms, hipStream_t st) {
+hipError_t launch_mlp_train(const uint64_t* e, uint64_t S, uint64_t seed, uint32_t steps, float lr,
+                            const MlpState& ms, hipStream_t st) {
   if (S == 0) return hipSuccess;
-  mlp_setup_kernel<<<1, 256, 0, st>>>(e, S, seed, ms.M, ms.master, ms.adam, hdr);
+  mlp_setup_kernel<<<1, 256, 0, st>>>(e, S, seed, ms.M, ms.master, ms.adam);
   mlp_publish_kernel<<<1, 256, 0, st>>>(ms.master, nullptr, ms.M);
   if (steps) {
     hipError_t err = mlp_prepare_kernels();
     if (err != hipSuccess) return err;
     mlp_train_kernel<<<1, kTrainThreads, sizeof(TrainLds), st>>>(e, S, steps, lr, seed, ms.master, ms.adam, ms.M);
   }
-  hipError_t err = launch_fill_u32(ms.first, (uint64_t)L + 1, 0xFFFFFFFFu, st);
-  if (err != hipSuccess) return err;
-  const uint32_t nb = (uint32_t)((S + 255) / 256);
-  mlp_sample_leaves_kernel<<<nb, 256, 0, st>>>(e, S, L, ms.M, ms.first);
-  suffix_min_kernel<<<1, 1024, 0, st>>>(ms.first, L, (uint32_t)S);
+  return hipGetLastError();
+}
+
+hipError_t launch_equi_depth_leaves(const uint64_t* e, uint64_t S, uint32_t L, uint32_t B, ModelHeader* hdr,
+                                    const MlpState& ms, hipStream_t st) {
+  if (S == 0) return hipSuccess;
+  const uint32_t K = spline_segments(L);
+  quantile_first_kernel<<<(L + 1 + 255) / 256, 256, 0, st>>>(e, S, L, ms.first, hdr);
   mlp_leaf_fit_kernel<<<(L + 255) / 256, 256, 0, st>>>(e, S, L, B, ms.first, ms.leaves, ms.bound);
-  err = launch_fill_u32(ms.hist, B, 0u, st);
+  spline_knots_kernel<<<(K + 1 + 255) / 256, 256, 0, st>>>(ms.bound, L, K, ms.knots);
+  hipError_t err = launch_fill_u32(ms.hist, B, 0u, st);
   if (err != hipSuccess) return err;
-  mlp_sample_stats_kernel<<<nb, 256, 0, st>>>(e, S, L, ms.first, ms.leaves, ms.hist, hdr);
+  mlp_sample_stats_kernel<<<(uint32_t)((S + 255) / 256), 256, 0, st>>>(e, S, L, ms.first, ms.leaves, ms.hist, hdr);
+  return hipGetLastError();
+}
+
+hipError_t launch_auto_gate(const uint32_t* hist_rmi, uint32_t B, uint64_t S, float accept_ratio, uint32_t kind,
+                            ModelHeader* hdr, hipStream_t st) {
+  auto_gate_kernel<<<1, 256, 0, st>>>(hist_rmi, B, S, accept_ratio, kind, hdr);
   return hipGetLastError();
 }
 

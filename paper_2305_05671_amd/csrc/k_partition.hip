@@ -80,18 +80,20 @@ __device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const
 // slots and the slots of tile t-1 are written, so neither the load latency nor
 // the atomic latency stalls the block.  Two LDS tile buffers alternate.
 //
-// MLP: the root is the monotone network (kind_used == 1): its floor(L y) is the
-// guess from which the exact leaf is found among the routing boundaries.  The
-// linear-root and the MLP-root kernels are both launched when a fit may
-// choose either; each returns at once unless the header names its root.
+// ROOT (kind_used of the header): 0 the linear RMI root; 1 the monotone MLP,
+// whose floor(L y) is the guess from which the exact leaf is found among the
+// routing boundaries; 2 the linear spline over equi-depth leaves, routed by a
+// binary search among its segment knots and then the segment's leaves.  A fit
+// that may choose among roots launches a kernel per root; each returns at
+// once unless the header names its own.
 //
 // FILTER (host tier): the records are one chunk of a larger input whose first
 // record has index f.idx_base; only buckets f.lo .. f.hi-1 are placed (bucket
 // b at local bucket b - f.lo), the others are skipped.
-template <int RW_T, bool MLP, bool FILTER>
+template <int RW_T, int ROOT, bool FILTER>
 __global__ __launch_bounds__(kPartThreads) void partition_kernel(
     const ModelHeader* __restrict__ hdr, const Leaf* __restrict__ leaves, const MlpBlock* __restrict__ mlp,
-    const uint64_t* __restrict__ bound, const uint8_t* __restrict__ recs,
+    const uint64_t* __restrict__ bound, const uint64_t* __restrict__ knots, const uint8_t* __restrict__ recs,
     uint64_t n, uint32_t rw_rt, uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps,
     const uint32_t* __restrict__ rstart, PartHeader* __restrict__ ph, uint2* __restrict__ spill_meta,
     uint4* __restrict__ slots, uint64_t cap_slots, PassFilter f) {
@@ -100,10 +102,11 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
   constexpr uint32_t RV = RW_T ? (kPartTile * RW_T / 4 + kPartThreads - 1) / kPartThreads : 8;
   extern __shared__ uint4 lds4[];                      // 2 tiles of kPartTile * RW dwords
   __shared__ uint32_t dst[2][kPartTile];
-  if ((hdr->kind_used == 1u) != MLP) return;
+  constexpr bool MLP = ROOT == 1;
+  if (hdr->kind_used != (uint32_t)ROOT) return;
   const uint32_t tile_dw = kPartTile * RW;
   const float a0 = hdr->a0, a1 = hdr->a1;
-  const uint32_t L = hdr->L;
+  const uint32_t L = ROOT ? hdr->mlp_L : hdr->L, K = hdr->spline_K;
   __shared__ typename std::conditional<MLP, MlpHead, uint32_t>::type mh_;
   W2Frags w2;
   if constexpr (MLP) {
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
     } else if (threadIdx.x < cnt) {
       const uint32_t* r = buf(cur) + threadIdx.x * RW;
       uint64_t e = key_code(r[0], r[1]);
-      uint32_t j = rmi_leaf(a0, a1, L, e);
+      const uint32_t j = ROOT == 2 ? spline_exact_leaf(knots, K, bound, L, e) : rmi_leaf(a0, a1, L, e);
       b = leaf_bucket(load_leaf(leaves, j), e);
     }
     bool keep = threadIdx.x < cnt;
@@ -215,18 +218,20 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
   write_tile(tprev, buf(cur), dst[cur]);
 }
 
-template <bool MLP, bool FILTER>
+template <int ROOT, bool FILTER>
 static void launch_partition_root(uint32_t grid, size_t lds, hipStream_t st, uint32_t RW, const ModelHeader* hdr,
                                   const Leaf* leaves, const MlpBlock* mlp, const uint64_t* bound,
-                                  const uint8_t* recs, uint64_t n, uint32_t* counts, const uint32_t* caps,
-                                  const uint32_t* rstart, PartHeader* ph, uint2* meta, uint4* slots,
-                                  uint64_t cap_slots, PassFilter f) {
+                                  const uint64_t* knots, const uint8_t* recs, uint64_t n, uint32_t* counts,
+                                  const uint32_t* caps, const uint32_t* rstart, PartHeader* ph, uint2* meta,
+                                  uint4* slots, uint64_t cap_slots, PassFilter f) {
   if (RW == 25)
-    partition_kernel<25, MLP, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, recs, n, RW, counts,
-                                                                       caps, rstart, ph, meta, slots, cap_slots, f);
+    partition_kernel<25, ROOT, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, knots, recs, n, RW,
+                                                                        counts, caps, rstart, ph, meta, slots,
+                                                                        cap_slots, f);
   else
-    partition_kernel<0, MLP, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, recs, n, RW, counts,
-                                                                      caps, rstart, ph, meta, slots, cap_slots, f);
+    partition_kernel<0, ROOT, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, knots, recs, n, RW,
+                                                                       counts, caps, rstart, ph, meta, slots,
+                                                                       cap_slots, f);
 }
 
 hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const MlpState* ms, const uint8_t* recs,
@@ -248,17 +253,23 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const Ml
   auto* slots = reinterpret_cast<uint4*>(part + lay.slots);
   const PassFilter f = filter ? *filter : PassFilter{0, 0, 0};
   if (filter) {
-    launch_partition_root<false, true>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, recs, n, counts, caps,
-                                       rstart, ph, meta, slots, lay.cap_slots, f);
-    if (ms)
-      launch_partition_root<true, true>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, recs, n, counts, caps,
-                                        rstart, ph, meta, slots, lay.cap_slots, f);
+    launch_partition_root<0, true>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, nullptr, recs, n, counts, caps,
+                                   rstart, ph, meta, slots, lay.cap_slots, f);
+    if (ms) {
+      launch_partition_root<1, true>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, nullptr, recs, n, counts,
+                                     caps, rstart, ph, meta, slots, lay.cap_slots, f);
+      launch_partition_root<2, true>(grid, lds, st, RW, hdr, ms->leaves, nullptr, ms->bound, ms->knots, recs, n,
+                                     counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
+    }
   } else {
-    launch_partition_root<false, false>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, recs, n, counts, caps,
-                                        rstart, ph, meta, slots, lay.cap_slots, f);
-    if (ms)
-      launch_partition_root<true, false>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, recs, n, counts,
-                                         caps, rstart, ph, meta, slots, lay.cap_slots, f);
+    launch_partition_root<0, false>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, nullptr, recs, n, counts, caps,
+                                    rstart, ph, meta, slots, lay.cap_slots, f);
+    if (ms) {
+      launch_partition_root<1, false>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, nullptr, recs, n, counts,
+                                      caps, rstart, ph, meta, slots, lay.cap_slots, f);
+      launch_partition_root<2, false>(grid, lds, st, RW, hdr, ms->leaves, nullptr, ms->bound, ms->knots, recs, n,
+                                      counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
+    }
   }
   return hipGetLastError();
 }
@@ -266,12 +277,14 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const Ml
 // ------------------------------------------------------------- host tier --
 // Bucket counts of one chunk of records (no placement).  A wave takes 64
 // consecutive records; lanes past the end evaluate a clamped copy and drop it.
-template <bool MLP>
+template <int ROOT>
 __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restrict__ hdr,
                                                     const Leaf* __restrict__ leaves, const MlpBlock* __restrict__ mlp,
-                                                    const uint64_t* __restrict__ bound, const uint32_t* __restrict__ rec,
+                                                    const uint64_t* __restrict__ bound,
+                                                    const uint64_t* __restrict__ knots, const uint32_t* __restrict__ rec,
                                                     uint64_t n, uint32_t RW, uint32_t* __restrict__ counts) {
-  if ((hdr->kind_used == 1u) != MLP) return;
+  constexpr bool MLP = ROOT == 1;
+  if (hdr->kind_used != (uint32_t)ROOT) return;
   __shared__ typename std::conditional<MLP, MlpHead, uint32_t>::type mh_;
   W2Frags w2;
   if constexpr (MLP) {
@@ -281,7 +294,7 @@ __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restric
     __syncthreads();
   }
   const float a0 = hdr->a0, a1 = hdr->a1;
-  const uint32_t L = hdr->L;
+  const uint32_t L = ROOT ? hdr->mlp_L : hdr->L, K = hdr->spline_K;
   const uint64_t wave0 = ((uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u));
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t base = wave0; base < n; base += stride) {  // uniform per wave
@@ -293,7 +306,8 @@ __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restric
       const float y = mlp_y64(e, mh_, w2);
       b = leaf_bucket(load_leaf(leaves, mlp_exact_leaf(bound, L, e, mlp_leaf_guess(y, L))), e);
     } else {
-      b = leaf_bucket(load_leaf(leaves, rmi_leaf(a0, a1, L, e)), e);
+      const uint32_t j = ROOT == 2 ? spline_exact_leaf(knots, K, bound, L, e) : rmi_leaf(a0, a1, L, e);
+      b = leaf_bucket(load_leaf(leaves, j), e);
     }
     if (i < n) atomicAdd(&counts[b], 1u);
   }
@@ -306,8 +320,11 @@ hipError_t launch_count(const ModelHeader* hdr, const Leaf* leaves, const MlpSta
   const uint64_t waves = (n + 63) / 64;
   const uint32_t grid = (uint32_t)std::min<uint64_t>((waves + 3) / 4, 4096);
   const uint32_t* rec = reinterpret_cast<const uint32_t*>(recs);
-  count_kernel<false><<<grid, 256, 0, st>>>(hdr, leaves, nullptr, nullptr, rec, n, RW, counts);
-  if (ms) count_kernel<true><<<grid, 256, 0, st>>>(hdr, ms->leaves, ms->M, ms->bound, rec, n, RW, counts);
+  count_kernel<0><<<grid, 256, 0, st>>>(hdr, leaves, nullptr, nullptr, nullptr, rec, n, RW, counts);
+  if (ms) {
+    count_kernel<1><<<grid, 256, 0, st>>>(hdr, ms->leaves, ms->M, ms->bound, nullptr, rec, n, RW, counts);
+    count_kernel<2><<<grid, 256, 0, st>>>(hdr, ms->leaves, nullptr, ms->bound, ms->knots, rec, n, RW, counts);
+  }
   return hipGetLastError();
 }
 

@@ -8,10 +8,10 @@ bfloat16 ulp, 2^-8 relative, of one hidden unit), which moves y by at most
 Gradients: one training step's backward pass against the FP64 backward with
 the same rounding points; block-relative error <= 1e-2 on the bfloat16 layer
 (W2), <= 1e-4 on the FP32 layers.
-The fitted model: leaves bit-exact against the oracle's spline over the
-GPU's leaf ranges; the per-sample leaves within the tie tolerance of the
-oracle's running maximum of floor(L y); bucket counts bit-exact against the
-oracle's boundary routing; the sort byte-exact.
+The fitted model: leaf ranges equi-depth in the sample, bit-exact against the
+oracle; leaves bit-exact against the oracle's spline over them; the trained
+root close to the empirical CDF; bucket counts bit-exact against the oracle's
+boundary routing; the sort byte-exact.
 """
 import numpy as np
 import pytest
@@ -121,11 +121,14 @@ def test_fitted_mlp_model(env, kind, n, B, seed):
     info = m.info()
     assert info.kind_used == elsar.MLP and not m.rejected
     L = info.num_leaves
+    assert L == info.mlp_leaves == B  # one equi-depth leaf per bucket by default
     codes = oracle.sample_codes(recs, seed=seed)
     S = codes.size
     params, knots, bound, first = m.mlp()
     q, w = mlp.knots(codes)
     assert np.array_equal(knots, q)
+    # leaf ranges: equi-depth in the sorted sample, bit-exact
+    assert np.array_equal(first.astype(np.uint64), mlp.equi_depth_first(codes, L))
     # leaves of the GPU's leaf ranges, bit-exact
     ref = oracle.spline_leaves(codes, first.astype(np.uint64), B)
     base, c, b, lo, hi = m.leaves()
@@ -135,13 +138,12 @@ def test_fitted_mlp_model(env, kind, n, B, seed):
     assert bound[0] == 0 and bound[L] == np.iinfo(np.uint64).max
     has = first[1:L] < S
     assert np.array_equal(bound[1:L][has], codes[first[1:L][has]])
-    # per-sample leaves against the oracle's running maximum of floor(L y)
+    # the trained root tracks the empirical CDF, so its guesses land near the
+    # sample's own leaf
     y = mlp.forward(_P64(params), mlp.features(codes, q, w), bf16_layer2=True)["y"]
-    lv_ref = mlp.leaves_of_sorted(y, L)
-    lv_gpu = np.searchsorted(first[:L], np.arange(S), side="right") - 1
-    assert np.mean(lv_ref != lv_gpu) <= 1e-3
-    # the trained root tracks the empirical CDF
     assert np.sqrt(np.mean((y - np.arange(S) / S) ** 2)) < 0.05
+    lv = np.searchsorted(first[:L], np.arange(S), side="right") - 1
+    assert np.median(np.abs(mlp.leaf_guess(y, L) - lv)) < 0.05 * L
     # counts bit-exact under the GPU's boundaries and leaves
     bk = oracle.routed_buckets(recs, bound, ref)
     _, want = oracle.counts_offsets(bk, B)
@@ -196,3 +198,16 @@ def test_rejection_falls_back_to_rmi(env):
     assert np.array_equal(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs))
     assert np.array_equal(_sort(env, recs, num_buckets=512, kind=elsar.MLP, accept_ratio=1e-6),
                           oracle.sort_records(recs))
+
+
+def test_auto_choice(env):
+    # uniform keys: the linear root's largest sample bucket is within the
+    # acceptance ratio of a perfect model's, so the automatic choice keeps it;
+    # skewed keys: it fails, and the spline root takes over
+    _, elsar = env
+    recs = datagen.generate(datagen.spec("uniform", seed=12), 300_000)
+    m, *_ = _fit(env, recs, num_buckets=1024, seed=12, kind=elsar.AUTO)
+    assert m.info().kind_used == elsar.RMI and m.info().mlp_rejected == 0
+    recs = datagen.generate(datagen.spec("skewed", seed=13), 300_000)
+    m, *_ = _fit(env, recs, num_buckets=1024, seed=13, kind=elsar.AUTO)
+    assert m.info().kind_used == elsar.SPLINE

@@ -1,0 +1,110 @@
+"""GPU parity of the linear-spline root against the oracle.
+
+The spline root's leaves are equi-depth in the sorted sample (oracle/mlp.py,
+equi_depth_first) with the same two-point splines as the RMI's leaves
+(oracle.spline_leaves); its K segment knots are the leaves' first codes at
+every (i L) / K-th leaf.  A record goes to the leaf whose boundary codes
+bracket its code (oracle.routed_buckets), so the bucket counts are bit-exact
+and the sort byte-exact.
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from oracle import mlp
+
+R = 100
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2305_05671_amd as elsar
+    assert torch.cuda.is_available()
+    return torch, elsar
+
+
+def _fit(env, recs, **kw):
+    torch, elsar = env
+    d = torch.from_numpy(np.ascontiguousarray(recs).reshape(-1)).to("cuda")
+    m = elsar.Model(recs.shape[0], elsar.fit_params(**kw))
+    m.sample_fit(d)
+    part, offsets = m.partition(d)
+    torch.cuda.synchronize()
+    return m, part, offsets, d
+
+
+@pytest.mark.parametrize("kind,n,B,leaves,seed", [
+    ("skewed", 400_000, 2048, 0, 2), ("zipf", 300_000, 1024, 0, 3), ("staircase", 300_000, 1024, 1000, 5),
+    ("uniform", 200_000, 256, 40, 4)])
+def test_fitted_spline_model(env, kind, n, B, leaves, seed):
+    torch, elsar = env
+    recs = datagen.generate(datagen.spec(kind, seed=seed), n)
+    m, part, offsets, d = _fit(env, recs, num_buckets=B, num_leaves=leaves, seed=seed, kind=elsar.SPLINE)
+    info = m.info()
+    assert info.kind_used == elsar.SPLINE
+    L = info.num_leaves
+    assert L == info.mlp_leaves == (leaves or B)  # one leaf per bucket by default
+    K = info.spline_segments
+    assert K == (L // 64 if L >= 64 else 1)
+    codes = oracle.sample_codes(recs, seed=seed)
+    knots, bound, first = m.spline()
+    assert np.array_equal(first.astype(np.uint64), mlp.equi_depth_first(codes, L))
+    ref = oracle.spline_leaves(codes, first.astype(np.uint64), B)
+    base, c, b, lo, hi = m.leaves()
+    assert np.array_equal(base, ref.base) and np.array_equal(c, ref.c) and np.array_equal(b, ref.b)
+    assert np.array_equal(lo, ref.lo) and np.array_equal(hi, ref.hi)
+    S = codes.size
+    assert bound[0] == 0 and bound[L] == np.iinfo(np.uint64).max
+    has = first[1:L] < S
+    assert np.array_equal(bound[1:L][has], codes[first[1:L][has]])
+    assert np.array_equal(knots, bound[(np.arange(K + 1, dtype=np.int64) * L) // K])
+    # counts bit-exact under exact routing among the boundaries
+    bk = oracle.routed_buckets(recs, bound, ref)
+    _, want = oracle.counts_offsets(bk, B)
+    assert np.array_equal(offsets.cpu().numpy().astype(np.uint64), want)
+    # Equation 1 along the sorted order
+    order = oracle.sort_order(recs)
+    assert np.all(np.diff(bk[order].astype(np.int64)) >= 0)
+    out = torch.empty_like(d)
+    m.sort_buckets(part, offsets, n, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().reshape(-1, R), recs[order])
+
+
+@pytest.mark.parametrize("kind,n,B,seed", [
+    ("skewed", 300_000, 0, 2), ("zipf", 200_000, 256, 3), ("mixed", 150_000, 4096, 6), ("uniform", 100_000, 0, 7)])
+def test_sort_with_spline_root_matches_oracle(env, kind, n, B, seed):
+    torch, elsar = env
+    recs = datagen.generate(datagen.spec(kind, seed=seed), n)
+    d = torch.from_numpy(np.ascontiguousarray(recs).reshape(-1)).to("cuda")
+    out = elsar.elsar_sort(d, params=elsar.fit_params(num_buckets=B, seed=seed, kind=elsar.SPLINE))
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs))
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 1000, 2049, 65_537])
+def test_spline_edge_sizes(env, n):
+    torch, elsar = env
+    recs = datagen.generate(datagen.spec("skewed", seed=n), n)
+    d = torch.from_numpy(np.ascontiguousarray(recs).reshape(-1)).to("cuda")
+    out = elsar.elsar_sort(d, params=elsar.fit_params(seed=n, kind=elsar.SPLINE))
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs))
+
+
+def test_spline_all_equal_keys(env):
+    # one run of equal codes: every leaf start moves back to sample 0
+    torch, elsar = env
+    recs = datagen.generate(datagen.spec("uniform", seed=9), 50_000)
+    recs[:, :10] = np.frombuffer(b"SAMEKEY123", dtype=np.uint8)
+    m, part, offsets, d = _fit(env, recs, num_buckets=256, seed=9, kind=elsar.SPLINE)
+    knots, bound, first = m.spline()
+    assert np.all(first[:-1] == 0)
+    out = torch.empty_like(d)
+    m.sort_buckets(part, offsets, recs.shape[0], out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs))

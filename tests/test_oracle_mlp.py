@@ -110,7 +110,8 @@ def test_training_reduces_loss_and_leaves_are_monotone():
         mlp.adam_step(P, m, v, g, step, lr=1e-2)
     l1 = mlp.loss_and_grads(P, X, t)[0]
     assert l1 < 0.1 * l0 and l1 < 2e-3
-    lv = mlp.leaves_of_sorted(mlp.forward(P, X)["y"], 256)
+    # the network is monotone, so the router's guesses never decrease along the sorted sample
+    lv = mlp.leaf_guess(mlp.forward(P, X)["y"], 256)
     assert np.all(np.diff(lv) >= 0) and lv.min() >= 0 and lv.max() < 256
 
 
@@ -128,9 +129,32 @@ def test_bf16_backward_close_to_fp64():
         assert np.abs(gq[k] - g[k]).max() <= 3e-2 * scale, k
 
 
-def test_first_of_leaves():
-    lv = np.array([0, 0, 2, 2, 2, 3, 5])
-    assert list(mlp.first_of_leaves(lv, 6)) == [0, 2, 2, 5, 6, 6, 7]
+def test_equi_depth_first_worked_example():
+    # S = 8, L = 4: leaf j would start at sample 2j; the starts at samples 2
+    # (code 1) and 4 (code 3) move back to the first sample of their run, so the
+    # run of three 1s is not split and leaf 1 comes out empty
+    codes = np.array([1, 1, 1, 2, 3, 3, 4, 5], dtype=np.uint64)
+    assert list(mlp.equi_depth_first(codes, 4)) == [0, 0, 4, 6, 8]
+
+
+def test_equi_depth_first_properties():
+    rng = np.random.default_rng(21)
+    for trial in range(20):
+        S = int(rng.integers(1, 400))
+        L = int(rng.integers(1, 70))
+        # distinct codes: the starts are exactly floor(j S / L)
+        codes = np.sort(rng.choice(10**9, size=S, replace=False)).astype(np.uint64)
+        f = mlp.equi_depth_first(codes, L)
+        assert list(f) == [(j * S) // L for j in range(L)] + [S]
+        # many equal codes: every start is a run start, at or before floor(j S / L),
+        # and no run straddles two leaves
+        codes = np.sort(rng.integers(0, 6, size=S)).astype(np.uint64)
+        f = mlp.equi_depth_first(codes, L).astype(np.int64)
+        assert f[-1] == S and np.all(np.diff(f) >= 0)
+        for j in range(L):
+            q = (j * S) // L
+            assert f[j] <= q and codes[f[j]] == codes[q]
+            assert f[j] == 0 or codes[f[j] - 1] != codes[f[j]]
 
 
 def test_spline_leaves_exact_on_linear_codes():
