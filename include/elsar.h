@@ -75,8 +75,8 @@ typedef struct {
   float accept_ratio;     /* MLP accepted if its largest sample bucket <= ratio * ideal, ideal =
                              max(ceil(S/B), longest run of equal codes in the sample); 0: 1.5 */
   uint32_t mlp_steps;     /* Adam steps (128 sample rows each) of the MLP fit; 0: 400 */
-  uint32_t region_pct;    /* bucket j's region holds ceil(region_pct/100 * max(n*h_j/S, n/B)) + 16
-                             records (h_j: sample keys in bucket j), the rest spills; 0: 125 */
+  uint32_t region_pct;    /* bucket j's region holds ceil(region_pct/100 * max(n*(h_j + 2 sqrt(h_j))/S, n/B))
+                             + 16 records (h_j: sample keys in bucket j), the rest spills; 0: 125 */
 } elsar_fit_params;
 
 /* Fills *p with the defaults for 100-byte records with 10-byte keys. */

@@ -189,13 +189,26 @@ constexpr uint32_t kSmWaves = kSmThreads / 64;
 constexpr uint32_t kSmCap = kSmallCap;
 constexpr uint32_t kSmBits = 11;     // counting-sort digit: 2048 bins of the bucket's code range
 constexpr uint32_t kSmGroup = 7;     // gathered chunks in flight per thread
-constexpr uint32_t kRunMax = 32;     // longest bin sorted by insertion
+constexpr uint32_t kRunMax = 16;     // longest bin sorted by insertion
+constexpr uint32_t kWaveSortMax = 256;  // longest bin a wave sorts (bitonic); longer ones: LSD over the bucket
+
+// LDS writes of a wave visible to all its lanes (compiler ordering; one
+// wave's LDS operations complete in order)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+static_assert(kSmWaves * kWaveSortMax == kSmCap, "a private bitonic area per wave in perm[1]");
 
 // Steps after the digits: the digit of entry p is in perm[1][p] (2^kSmBits
 // bins, non-decreasing in the composite).  A counting pass on the digit, then
-// insertion sort by the whole composite inside each bin, or stable LSD passes
-// over every varying composite byte when a bin is longer than kRunMax.
-// Returns the perm buffer that holds the sorted order.
+// the whole composite orders each bin: insertion sort (one thread) up to
+// kRunMax entries, a bitonic network (one wave, in its own quarter-kilobyte
+// of perm[1]) up to kWaveSortMax, and stable LSD passes over every varying
+// composite byte of the bucket when some bin is longer still (keys clustered
+// at a finer scale than the digit resolves).  Returns the perm buffer that
+// holds the sorted order.
 __device__ __forceinline__ uint32_t small_sort_core(uint32_t n, uint32_t vary, uint32_t (*cw)[kSmCap], uint16_t (*perm)[kSmCap],
                                     uint32_t* bins, uint32_t* sh_scan, uint32_t* tot) {
   const uint32_t tid = threadIdx.x;
@@ -223,11 +236,19 @@ __device__ __forceinline__ uint32_t small_sort_core(uint32_t n, uint32_t vary, u
   for (uint32_t p = tid; p < n; p += kSmThreads) perm[0][atomicAdd(&bins[dig[p]], 1u)] = (uint16_t)p;
   __syncthreads();
   // bins[b] is now the end of bin b; the start is the end of bin b-1
+  __shared__ uint16_t wave_bins[kSmCap / (kRunMax + 1) + 1];  // bins for the waves
+  __shared__ uint32_t n_wave_bins;
+  if (tid == 0) n_wave_bins = 0;
+  __syncthreads();
   bool long_bin = false;
   for (uint32_t b = tid; b < (1u << kSmBits); b += kSmThreads) {
     uint32_t s0 = b ? bins[b - 1] : 0u, s1 = bins[b];
     if (s1 - s0 < 2) continue;
-    if (s1 - s0 > kRunMax) { long_bin = true; continue; }
+    if (s1 - s0 > kRunMax) {
+      if (s1 - s0 > kWaveSortMax) long_bin = true;
+      else wave_bins[atomicAdd(&n_wave_bins, 1u)] = (uint16_t)b;
+      continue;
+    }
     for (uint32_t x = s0 + 1; x < s1; ++x) {  // insertion sort by the whole composite
       uint16_t e = perm[0][x];
       uint32_t y = x;
@@ -240,7 +261,40 @@ __device__ __forceinline__ uint32_t small_sort_core(uint32_t n, uint32_t vary, u
   }
   long_bin = __syncthreads_or(long_bin);
   uint32_t cur = 0;
-  if (long_bin) {  // stable LSD over every varying composite byte
+  if (!long_bin) {
+    // one wave per bin of kRunMax+1 .. kWaveSortMax entries: bitonic network
+    // over the next power of two, padded with a sentinel above every entry
+    const uint32_t w = tid >> 6, lane = tid & 63u;
+    uint16_t* sc = perm[1] + w * kWaveSortMax;
+    const uint32_t nw = n_wave_bins;
+    for (uint32_t i = w; i < nw; i += kSmWaves) {
+      const uint32_t b = wave_bins[i];
+      const uint32_t s0 = b ? bins[b - 1] : 0u, m = bins[b] - s0;
+      uint32_t P = 64;
+      while (P < m) P <<= 1;
+      for (uint32_t x = lane; x < P; x += 64) sc[x] = x < m ? perm[0][s0 + x] : (uint16_t)0xFFFFu;
+      wave_lds_sync();
+      for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+          for (uint32_t x = lane; x < P; x += 64) {
+            const uint32_t y = x ^ j;
+            if (y > x) {
+              const uint16_t a = sc[x], c = sc[y];
+              // a > c, with the sentinel above every entry
+              const bool gt = a == 0xFFFFu ? c != 0xFFFFu : (c != 0xFFFFu && less(c, a));
+              if (gt == ((x & k) == 0)) {
+                sc[x] = c;
+                sc[y] = a;
+              }
+            }
+          }
+          wave_lds_sync();
+        }
+      }
+      for (uint32_t x = lane; x < m; x += 64) perm[0][s0 + x] = sc[x];
+      wave_lds_sync();
+    }
+  } else {  // stable LSD over every varying composite byte
     auto wc = reinterpret_cast<uint32_t(*)[256]>(bins);
     for (int pb = 15; pb >= 0; --pb) {
       if (!((vary >> pb) & 1u)) continue;

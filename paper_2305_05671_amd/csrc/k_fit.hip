@@ -321,9 +321,9 @@ hipError_t launch_fit_rmi(const uint64_t* e, uint64_t S, uint64_t n, uint32_t L,
 
 // -------------------------------------------------------- bucket capacity --
 // h_j = sample keys the fitted model puts in bucket j.  The partition reserves
-// ceil(f * max(n * h_j / S, n / B)) + 16 slots for bucket j (f = region_pct/100,
-// default 1.25), rounded up to even (16-byte aligned 104-byte slots); records
-// beyond continue in the spill.
+// ceil(f * max(n * (h_j + 2 sqrt(h_j)) / S, n / B)) + 16 slots for bucket j
+// (f = region_pct/100, default 1.25), rounded up to even; records beyond
+// continue in the spill.
 __global__ __launch_bounds__(256) void sample_bucket_hist_kernel(const uint64_t* __restrict__ e, uint64_t S,
                                                                  const ModelHeader* __restrict__ hdr,
                                                                  const Leaf* __restrict__ leaves,
@@ -534,7 +534,10 @@ __global__ __launch_bounds__(kScanThreads) void capacity_kernel(const uint32_t* 
       uint32_t j = base + threadIdx.x * kScanPer + i;
       c[i] = 0;
       if (j < B) {
-        double expect = (double)hist[j] * (double)n / (double)S;
+        // h sample keys estimate the bucket's mass as h / S with a standard
+        // deviation of about sqrt(h) / S: the region covers two of them
+        const double h = (double)hist[j];
+        double expect = (h + 2.0 * sqrt(h)) * (double)n / (double)S;
         double m = expect > ideal ? expect : ideal;
         c[i] = ((uint32_t)ceil(scale * m) + 16u + 1u) & ~1u;
       }
