@@ -67,7 +67,7 @@ typedef struct {
   uint32_t record_bytes;  /* record length R (100) */
   uint32_t key_bytes;     /* key length K (10) */
   uint32_t num_buckets;   /* B, the paper's f; 0: largest power of two <= n/950, in [1, 2^21] */
-  uint32_t num_leaves;    /* L; 0: max(1, B/16) under the linear root, min(B, 2^20) under the equi-depth
+  uint32_t num_leaves;    /* L; 0: max(1, B/16) under the linear root, min(B, 2^16) under the equi-depth
                              (MLP and spline) roots */
   uint64_t sample_size;   /* S; 0: min(max(ceil(n/100), 1024), 10^7, n) (Section 3.1, Section 6) */
   uint64_t seed;          /* seed of the sampler's Philox4x32-10 draws */

@@ -85,9 +85,10 @@ Shape resolve(const elsar_fit_params& p, uint64_t n) {
   Shape s;
   s.B = p.num_buckets ? p.num_buckets : default_buckets(n);
   s.L = p.num_leaves ? p.num_leaves : std::max<uint32_t>(1, s.B / 16);
-  // the MLP root's leaves are equi-depth in the sample: one per bucket by
-  // default (at most 2^20)
-  s.Lm = p.num_leaves ? p.num_leaves : std::min<uint32_t>(s.B, 1u << 20);
+  // equi-depth leaves (MLP and spline roots): one per bucket by default, at
+  // most 2^16 so that the routing tables (boundaries 512 KB, leaves 2 MB) stay
+  // in the L2 caches
+  s.Lm = p.num_leaves ? p.num_leaves : std::min<uint32_t>(s.B, 1u << 16);
   s.S = p.sample_size ? std::min<uint64_t>(p.sample_size, n) : default_sample_size(n);
   if (n > 0 && s.S == 0) s.S = 1;
   return s;

@@ -420,6 +420,7 @@ __global__ __launch_bounds__(256) void mlp_eval_kernel(const MlpBlock* __restric
 __global__ __launch_bounds__(256) void quantile_first_kernel(const uint64_t* __restrict__ e, uint64_t S,
                                                              uint32_t L, uint32_t* __restrict__ first,
                                                              ModelHeader* __restrict__ hdr) {
+  if (hdr->mlp_skip) return;  // the automatic choice kept the linear root
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j > L) return;
   if (j == L) {
@@ -445,7 +446,9 @@ __global__ __launch_bounds__(256) void quantile_first_kernel(const uint64_t* __r
 // last sample); bound[L] is past every code.
 __global__ __launch_bounds__(256) void mlp_leaf_fit_kernel(const uint64_t* __restrict__ e, uint64_t S, uint32_t L,
                                                            uint32_t B, const uint32_t* __restrict__ first,
-                                                           Leaf* __restrict__ leaves, uint64_t* __restrict__ bound) {
+                                                           Leaf* __restrict__ leaves, uint64_t* __restrict__ bound,
+                                                           const ModelHeader* __restrict__ hdr) {
+  if (hdr->mlp_skip) return;
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j == 0) bound[L] = ~0ull;
   if (j >= L) return;
@@ -475,7 +478,9 @@ __global__ __launch_bounds__(256) void mlp_leaf_fit_kernel(const uint64_t* __res
 
 // Segment knots of the spline root: knots[i] = bound[(i L) / K], i = 0..K.
 __global__ __launch_bounds__(256) void spline_knots_kernel(const uint64_t* __restrict__ bound, uint32_t L,
-                                                           uint32_t K, uint64_t* __restrict__ knots) {
+                                                           uint32_t K, uint64_t* __restrict__ knots,
+                                                           const ModelHeader* __restrict__ hdr) {
+  if (hdr->mlp_skip) return;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i <= K) knots[i] = bound[((uint64_t)i * L) / K];
 }
@@ -487,6 +492,7 @@ __global__ __launch_bounds__(256) void mlp_sample_stats_kernel(const uint64_t* _
                                                                const Leaf* __restrict__ leaves,
                                                                uint32_t* __restrict__ hist,
                                                                ModelHeader* __restrict__ hdr) {
+  if (hdr->mlp_skip) return;
   const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = s < S;
   const uint64_t c = e[in ? s : S - 1];
@@ -629,8 +635,8 @@ hipError_t launch_equi_depth_leaves(const uint64_t* e, uint64_t S, uint32_t L, u
   if (S == 0) return hipSuccess;
   const uint32_t K = spline_segments(L);
   quantile_first_kernel<<<(L + 1 + 255) / 256, 256, 0, st>>>(e, S, L, ms.first, hdr);
-  mlp_leaf_fit_kernel<<<(L + 255) / 256, 256, 0, st>>>(e, S, L, B, ms.first, ms.leaves, ms.bound);
-  spline_knots_kernel<<<(K + 1 + 255) / 256, 256, 0, st>>>(ms.bound, L, K, ms.knots);
+  mlp_leaf_fit_kernel<<<(L + 255) / 256, 256, 0, st>>>(e, S, L, B, ms.first, ms.leaves, ms.bound, hdr);
+  spline_knots_kernel<<<(K + 1 + 255) / 256, 256, 0, st>>>(ms.bound, L, K, ms.knots, hdr);
   hipError_t err = launch_fill_u32(ms.hist, B, 0u, st);
   if (err != hipSuccess) return err;
   mlp_sample_stats_kernel<<<(uint32_t)((S + 255) / 256), 256, 0, st>>>(e, S, L, ms.first, ms.leaves, ms.hist, hdr);
