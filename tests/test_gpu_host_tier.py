@@ -59,6 +59,19 @@ def test_host_tier_mlp_root(env):
     assert np.array_equal(h_out.numpy().reshape(-1, R), oracle.sort_records(recs))
 
 
+@pytest.mark.parametrize("kind_name", ["SPLINE", "AUTO"])
+def test_host_tier_spline_root(env, kind_name):
+    # the equi-depth root through the counting pass and the filtered placement
+    torch, elsar = env
+    recs = datagen.generate(datagen.spec("skewed", seed=44), 1_200_000)
+    h_in = _pinned(torch, recs)
+    h_out = torch.zeros_like(h_in).pin_memory()
+    st = elsar.sort_host(h_in, h_out, elsar.fit_params(kind=getattr(elsar, kind_name), seed=44),
+                         chunk_records=300_000, pass_records=500_000)
+    assert st.passes >= 3
+    assert np.array_equal(h_out.numpy().reshape(-1, R), oracle.sort_records(recs))
+
+
 def test_host_tier_bucket_larger_than_a_pass(env):
     torch, elsar = env
     recs = datagen.generate(datagen.spec("uniform", seed=43), 200_000)

@@ -256,6 +256,28 @@ def test_batch_matches_oracle_and_replays(env):
     del junk
 
 
+@pytest.mark.parametrize("kind_name", ["AUTO", "SPLINE"])
+def test_batch_with_equi_depth_roots(env, kind_name):
+    # jobs whose models are fitted one by one (no batched linear fit): the
+    # automatic choice per job, or the spline root throughout; replayed twice
+    torch, elsar = env
+    rng = np.random.default_rng(33)
+    sizes = np.round(np.exp(rng.uniform(np.log(1000), np.log(200_000), 24))).astype(int)
+    kinds = ["uniform" if j % 3 == 0 else ("skewed" if j % 3 == 1 else "zipf") for j in range(sizes.size)]
+    host, dev = _batch_inputs(torch, rng, sizes, kinds, 100)
+    want = [oracle.sort_records(h) for h in host]
+    outs = [torch.empty_like(d) for d in dev]
+    params = elsar.fit_params(kind=getattr(elsar, kind_name), seed=5)
+    ws = None
+    for rep in range(2):
+        for o in outs:
+            o.zero_()
+        ws = elsar.sort_batch(dev, outs, params=params, workspace=ws)
+        torch.cuda.synchronize()
+        for j in range(sizes.size):
+            _assert_same(outs[j].cpu().numpy().reshape(-1, R), want[j])
+
+
 @pytest.mark.parametrize("kind,n,B", [("uniform", 500_000, 512), ("skewed", 500_000, 512), ("zipf", 400_000, 256)])
 def test_radix_partitioner(env, kind, n, B):
     """The radix (equi-width) bucket function: counts bit-exact against the
