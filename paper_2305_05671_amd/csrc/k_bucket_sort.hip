@@ -199,49 +199,64 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-static_assert(kSmWaves * kWaveSortMax == kSmCap, "a private bitonic area per wave in perm[1]");
 
-// Steps after the digits: the digit of entry p is in perm[1][p] (2^kSmBits
-// bins, non-decreasing in the composite).  A counting pass on the digit, then
-// the whole composite orders each bin: insertion sort (one thread) up to
-// kRunMax entries, a bitonic network (one wave, in its own quarter-kilobyte
-// of perm[1]) up to kWaveSortMax, and stable LSD passes over every varying
-// composite byte of the bucket when some bin is longer still (keys clustered
-// at a finer scale than the digit resolves).  Returns the perm buffer that
-// holds the sorted order.
-__device__ __forceinline__ uint32_t small_sort_core(uint32_t n, uint32_t vary, uint32_t (*cw)[kSmCap], uint16_t (*perm)[kSmCap],
-                                    uint32_t* bins, uint32_t* sh_scan, uint32_t* tot) {
+// Steps after the digits: the digit of entry p is in perm[1][p] (2^BITS bins,
+// non-decreasing in the composite).  A counting pass on the digit, then the
+// whole composite (less) orders each bin: insertion sort (one thread) up to
+// kRunMax entries, a bitonic network (one wave, in its own kWaveSortMax
+// entries of perm[1]) up to kWaveSortMax, and stable LSD passes over every
+// varying composite byte (byte_of(entry, position)) of the bucket when some
+// bin is longer still (keys clustered at a finer scale than the digit
+// resolves).  CROWD_TO_LSD: the LSD passes also when the bins are crowded
+// overall (a sum of squared bin sizes above 4n; spread keys give about 2n).
+// bins: 2^BITS counters, also the LSD passes' per-wave counters.  Returns
+// the perm buffer that holds the sorted order.
+template <uint32_t CAP, uint32_t THREADS, uint32_t BITS, bool CROWD_TO_LSD, typename Less, typename ByteOf>
+__device__ __forceinline__ uint32_t bin_sort_core(uint32_t n, uint32_t vary, uint16_t (*perm)[CAP], uint32_t* bins,
+                                                  uint32_t* sh_scan, uint32_t* tot, Less less, ByteOf byte_of) {
+  constexpr uint32_t WAVES = THREADS / 64, NB = 1u << BITS;
+  static_assert(WAVES * 256 <= NB, "the bins double as the LSD counters");
+  static_assert(WAVES * kWaveSortMax <= CAP, "a private bitonic area per wave in perm[1]");
   const uint32_t tid = threadIdx.x;
   const uint16_t* dig = perm[1];
-  auto less = [&](uint32_t x, uint32_t y) -> bool {
-    if (cw[0][x] != cw[0][y]) return cw[0][x] < cw[0][y];
-    if (cw[1][x] != cw[1][y]) return cw[1][x] < cw[1][y];
-    if (cw[2][x] != cw[2][y]) return cw[2][x] < cw[2][y];
-    return cw[3][x] < cw[3][y];
-  };
   __syncthreads();
-  for (uint32_t p = tid; p < n; p += kSmThreads) atomicAdd(&bins[dig[p]], 1u);
+  for (uint32_t p = tid; p < n; p += THREADS) atomicAdd(&bins[dig[p]], 1u);
   __syncthreads();
   {  // exclusive scan of the bins: PER contiguous per thread
-    constexpr uint32_t PER = (1u << kSmBits) / kSmThreads;
+    constexpr uint32_t PER = NB / THREADS;
     uint32_t c[PER], sum = 0;
 #pragma unroll
     for (uint32_t i = 0; i < PER; ++i) { c[i] = bins[tid * PER + i]; sum += c[i]; }
     uint32_t total;
-    uint32_t run = block_exclusive_scan<uint32_t, kSmThreads>(sum, sh_scan, &total);
+    uint32_t run = block_exclusive_scan<uint32_t, THREADS>(sum, sh_scan, &total);
 #pragma unroll
     for (uint32_t i = 0; i < PER; ++i) { bins[tid * PER + i] = run; run += c[i]; }
   }
   __syncthreads();
-  for (uint32_t p = tid; p < n; p += kSmThreads) perm[0][atomicAdd(&bins[dig[p]], 1u)] = (uint16_t)p;
+  for (uint32_t p = tid; p < n; p += THREADS) perm[0][atomicAdd(&bins[dig[p]], 1u)] = (uint16_t)p;
   __syncthreads();
+  bool crowded = false;
+  if constexpr (CROWD_TO_LSD) {  // bins[b] is the end of bin b
+    __shared__ uint32_t sq_sum;
+    if (tid == 0) sq_sum = 0;
+    __syncthreads();
+    uint32_t sq = 0;
+    for (uint32_t b = tid; b < NB; b += THREADS) {
+      const uint32_t len = bins[b] - (b ? bins[b - 1] : 0u);
+      sq += len * len;
+    }
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+    if ((tid & 63u) == 0) atomicAdd(&sq_sum, sq);
+    __syncthreads();
+    crowded = sq_sum > 4 * n;
+  }
   // bins[b] is now the end of bin b; the start is the end of bin b-1
-  __shared__ uint16_t wave_bins[kSmCap / (kRunMax + 1) + 1];  // bins for the waves
+  __shared__ uint16_t wave_bins[CAP / (kRunMax + 1) + 1];  // bins for the waves
   __shared__ uint32_t n_wave_bins;
   if (tid == 0) n_wave_bins = 0;
   __syncthreads();
-  bool long_bin = false;
-  for (uint32_t b = tid; b < (1u << kSmBits); b += kSmThreads) {
+  bool long_bin = crowded;
+  for (uint32_t b = crowded ? NB : tid; b < NB; b += THREADS) {
     uint32_t s0 = b ? bins[b - 1] : 0u, s1 = bins[b];
     if (s1 - s0 < 2) continue;
     if (s1 - s0 > kRunMax) {
@@ -267,7 +282,7 @@ __device__ __forceinline__ uint32_t small_sort_core(uint32_t n, uint32_t vary, u
     const uint32_t w = tid >> 6, lane = tid & 63u;
     uint16_t* sc = perm[1] + w * kWaveSortMax;
     const uint32_t nw = n_wave_bins;
-    for (uint32_t i = w; i < nw; i += kSmWaves) {
+    for (uint32_t i = w; i < nw; i += WAVES) {
       const uint32_t b = wave_bins[i];
       const uint32_t s0 = b ? bins[b - 1] : 0u, m = bins[b] - s0;
       uint32_t P = 64;
@@ -298,13 +313,25 @@ __device__ __forceinline__ uint32_t small_sort_core(uint32_t n, uint32_t vary, u
     auto wc = reinterpret_cast<uint32_t(*)[256]>(bins);
     for (int pb = 15; pb >= 0; --pb) {
       if (!((vary >> pb) & 1u)) continue;
-      lsd_pass<kSmCap, kSmThreads>(perm, cur, n, wc, tot, [&](uint32_t e) {
-        return (cw[pb >> 2][e] >> (24 - 8 * (pb & 3))) & 0xFFu;
-      });
+      lsd_pass<CAP, THREADS>(perm, cur, n, wc, tot, [&](uint32_t e) { return byte_of(e, (uint32_t)pb); });
       cur ^= 1;
     }
   }
   return cur;
+}
+
+// The small-bucket instance: composites as four word arrays cw[0..3][entry].
+__device__ __forceinline__ uint32_t small_sort_core(uint32_t n, uint32_t vary, uint32_t (*cw)[kSmCap],
+                                                    uint16_t (*perm)[kSmCap], uint32_t* bins, uint32_t* sh_scan,
+                                                    uint32_t* tot) {
+  auto less = [&](uint32_t x, uint32_t y) -> bool {
+    if (cw[0][x] != cw[0][y]) return cw[0][x] < cw[0][y];
+    if (cw[1][x] != cw[1][y]) return cw[1][x] < cw[1][y];
+    if (cw[2][x] != cw[2][y]) return cw[2][x] < cw[2][y];
+    return cw[3][x] < cw[3][y];
+  };
+  auto byte_of = [&](uint32_t e, uint32_t pb) -> uint32_t { return (cw[pb >> 2][e] >> (24 - 8 * (pb & 3))) & 0xFFu; };
+  return bin_sort_core<kSmCap, kSmThreads, kSmBits, false>(n, vary, perm, bins, sh_scan, tot, less, byte_of);
 }
 
 template <uint32_t RW>  // record dwords
@@ -418,6 +445,11 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
 }
 
 // ------------------------------------------- buckets of up to 6144 records --
+// The small-bucket algorithm at a larger scale: one counting pass on a
+// 13-bit digit of the base-95 code over the bucket's code range, then the
+// per-bin orderings of bin_sort_core.
+constexpr uint32_t kMidBits = 13;
+
 template <uint32_t CAP, uint32_t THREADS>
 __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
@@ -429,9 +461,19 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
   static_assert(CAP % THREADS == 0, "cap is whole rounds");
   __shared__ uint4 ent[CAP];
   __shared__ uint16_t perm[2][CAP];
-  __shared__ uint32_t wc[WAVES][256];
+  __shared__ uint32_t bins[1u << kMidBits];
   __shared__ uint4 sh_or[WAVES], sh_and[WAVES];
+  __shared__ uint64_t sh_mm[2 * WAVES];
+  __shared__ uint32_t sh_scan[WAVES + 1];
   __shared__ uint32_t tot[4];
+  auto less = [&](uint32_t x, uint32_t y) -> bool {
+    const uint4 a = ent[x], b = ent[y];
+    if (a.x != b.x) return a.x < b.x;
+    if (a.y != b.y) return a.y < b.y;
+    if (a.z != b.z) return a.z < b.z;
+    return a.w < b.w;
+  };
+  auto byte_of = [&](uint32_t e, uint32_t pb) -> uint32_t { return digit_of(ent[e], pb); };
   const uint32_t W = slot_bytes_for(RW * 4) / 4;  // slot stride in dwords
   const uint32_t nitems = list ? *list_n : B;
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -444,26 +486,35 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
     br.rs = rstart[j];
     br.so = spill_off[j];
     br.out0 = offsets[j];
-    // 1. load the entries
+    // 1. load the entries, and the range of their base-95 codes
     uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
+    uint64_t cmin = ~0ull, cmax = 0;
     for (uint32_t p = threadIdx.x; p < br.n; p += THREADS) {
       uint32_t sl = slot_of(br, p, spill_map, cap_slots);
       uint4 c = composite(slots + (uint64_t)sl * W, RW, K);
       ent[p] = c;
-      perm[0][p] = (uint16_t)p;
       o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
       a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+      const uint64_t e = key_code(__builtin_bswap32(c.x), __builtin_bswap32(c.y));  // composite words are big-endian
+      cmin = e < cmin ? e : cmin;
+      cmax = e > cmax ? e : cmax;
     }
-    uint32_t vary = varying_bytes<THREADS>(o, a, sh_or, sh_and);  // syncs
-    // 2. LSD passes, least significant composite byte first
-    uint32_t cur = 0;
-    const uint32_t nb = K + 4;
-    for (int pbyte = (int)nb - 1; pbyte >= 0; --pbyte) {
-      if (!((vary >> pbyte) & 1u)) continue;
-      lsd_pass<CAP, THREADS>(perm, cur, br.n, wc, tot,
-                             [&](uint32_t e) { return digit_of(ent[e], (uint32_t)pbyte); });
-      cur ^= 1;
+    const uint4 diff = block_diff<THREADS>(o, a, sh_or, sh_and);  // syncs
+    const uint32_t vary = vary_mask(diff);
+    block_min_max_u64<THREADS>(cmin, cmax, sh_mm);
+    // 2. the digit (code - min) * 2^kMidBits / (max - min + 1), non-decreasing
+    //    in the key, then the bin sorts
+    const double scale = (double)(1u << kMidBits) / ((double)(cmax - cmin) + 1.0);
+    for (uint32_t i = threadIdx.x; i < (1u << kMidBits); i += THREADS) bins[i] = 0;
+    for (uint32_t p = threadIdx.x; p < br.n; p += THREADS) {
+      const uint4 c = ent[p];
+      const uint64_t e = key_code(__builtin_bswap32(c.x), __builtin_bswap32(c.y));
+      const uint32_t d = (uint32_t)((double)(e - cmin) * scale);
+      perm[1][p] = (uint16_t)(d < (1u << kMidBits) ? d : (1u << kMidBits) - 1);
     }
+    const uint32_t cur =
+        bin_sort_core<CAP, THREADS, kMidBits, true>(br.n, vary, perm, bins, sh_scan, tot, less, byte_of);
+    __syncthreads();
     // 3. copy records in sorted order to the output: lane q moves 16-byte
     //    chunk q % LC of the record at sorted position q / LC, kSmGroup loads
     //    in flight per thread before the stores
@@ -1030,7 +1081,8 @@ __global__ __launch_bounds__(kSmThreads) void tiny_jobs_kernel(const TinyJob* __
         cmax = e > cmax ? e : cmax;
       }
     }
-    const uint32_t vary = vary_mask(block_diff<kSmThreads>(o, a, sh_or, sh_and));
+    const uint4 diff = block_diff<kSmThreads>(o, a, sh_or, sh_and);
+    const uint32_t vary = vary_mask(diff);
     block_min_max_u64<kSmThreads>(cmin, cmax, sh_mm);
     uint32_t cur = 0;
     if (n == 1) {
