@@ -81,20 +81,25 @@ def test_few_distinct_keys_large_buckets(env):
     _assert_same(_gpu_sort(env, recs, num_buckets=64), oracle.sort_records(recs))
 
 
-def test_arbitrary_key_bytes(env):
+@pytest.mark.parametrize("kind_name", ["RMI", "SPLINE"])
+def test_arbitrary_key_bytes(env, kind_name):
     # bytes outside the printable range, including 0x00 and 0xFF, and keys that
     # differ only in bytes 8..9 (beyond the 8-byte code)
+    _, elsar = env
     rng = np.random.default_rng(7)
     recs = datagen.generate(datagen.spec("uniform", seed=7), 100_000)
     recs[:, :K] = rng.integers(0, 256, size=(recs.shape[0], K), dtype=np.uint8)
     recs[::3, :8] = np.frombuffer(b"PREFIX!!", np.uint8)
-    _assert_same(_gpu_sort(env, recs, num_buckets=512), oracle.sort_records(recs))
+    _assert_same(_gpu_sort(env, recs, num_buckets=512, kind=getattr(elsar, kind_name)), oracle.sort_records(recs))
 
 
-def test_forced_spill(env):
+@pytest.mark.parametrize("kind_name", ["RMI", "SPLINE"])
+def test_forced_spill(env, kind_name):
     # regions of 1% of the expected load: nearly every record goes through the spill path
+    _, elsar = env
     recs = datagen.generate(datagen.spec("skewed", seed=9), 200_000)
-    _assert_same(_gpu_sort(env, recs, num_buckets=128, region_pct=1), oracle.sort_records(recs))
+    _assert_same(_gpu_sort(env, recs, num_buckets=128, region_pct=1, kind=getattr(elsar, kind_name)),
+                 oracle.sort_records(recs))
 
 
 def test_in_place_and_deterministic(env):
@@ -173,14 +178,16 @@ def test_partition_then_sort_buckets(env):
         _assert_same(got[off[j]:off[j + 1]], want[off[j]:off[j + 1]])
 
 
+@pytest.mark.parametrize("kind_name", ["RMI", "SPLINE"])
 @pytest.mark.parametrize("R,K", [(40, 8), (64, 12), (128, 10)])
-def test_other_record_shapes(env, R, K):
+def test_other_record_shapes(env, R, K, kind_name):
     torch, elsar = env
     rng = np.random.default_rng(R)
     recs = rng.integers(0x20, 0x7F, size=(30_000, R), dtype=np.uint8)
     recs[1::2, :K] = recs[0::2, :K]  # every key twice: ties broken by input index
     d = torch.from_numpy(recs.reshape(-1)).to("cuda")
-    out = elsar.elsar_sort(d, params=elsar.fit_params(record_bytes=R, key_bytes=K, num_buckets=64))
+    out = elsar.elsar_sort(d, params=elsar.fit_params(record_bytes=R, key_bytes=K, num_buckets=64,
+                                                      kind=getattr(elsar, kind_name)))
     torch.cuda.synchronize()
     _assert_same(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs, key_bytes=K))
 
