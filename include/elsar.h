@@ -247,8 +247,10 @@ elsar_status elsar_model_leaves(const elsar_model* m, uint64_t* h_base, float* h
 /* The spline root of a model created with kind MLP, AUTO or SPLINE
  * (ELSAR_E_INVALID_ARG otherwise): h_knots[spline_segments + 1] (segment i
  * starts at code knots[i] = bound[(i L) / K]; knots[K] is past every code),
- * h_bound[mlp_leaves + 1] and h_first[mlp_leaves + 1] as below.  Any pointer
- * may be NULL.  Synchronises. */
+ * h_bound[mlp_leaves + 1] and h_first[mlp_leaves + 1] as below.  Under kind
+ * AUTO they are fitted only when the linear root was not kept; otherwise the
+ * model info shows mlp_leaves 0 and this call returns ELSAR_E_INVALID_ARG.
+ * Any pointer may be NULL.  Synchronises. */
 elsar_status elsar_model_spline_get(const elsar_model* m, uint64_t* h_knots, uint64_t* h_bound, uint32_t* h_first);
 
 /* The MLP root of a model created with kind MLP (ELSAR_E_INVALID_ARG

@@ -1001,8 +1001,9 @@ elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info) 
   info->mlp_rejected = h.mlp_rejected;
   info->num_buckets = m->B;
   info->num_leaves = (m->has_mlp && h.kind_used != 0) ? m->Lm : m->L;
-  info->mlp_leaves = m->has_mlp ? m->Lm : 0;
-  info->spline_segments = m->has_mlp ? spline_segments(m->Lm) : 0;
+  const bool eq = m->has_mlp && !h.mlp_skip;  // the equi-depth leaves were fitted
+  info->mlp_leaves = eq ? m->Lm : 0;
+  info->spline_segments = eq ? spline_segments(m->Lm) : 0;
   info->sample_size = m->S;
   info->n_fit = m->n;
   info->root_a0 = h.a0;
@@ -1033,6 +1034,9 @@ elsar_status elsar_model_leaves(const elsar_model* m, uint64_t* h_base, float* h
 
 elsar_status elsar_model_spline_get(const elsar_model* m, uint64_t* h_knots, uint64_t* h_bound, uint32_t* h_first) {
   if (!m || !m->has_mlp) return ELSAR_E_INVALID_ARG;
+  ModelHeader h;
+  HIP_TRY(hipMemcpy(&h, m->hdr, sizeof(h), hipMemcpyDeviceToHost));
+  if (h.mlp_skip) return ELSAR_E_INVALID_ARG;  // automatic choice kept the linear root: nothing fitted
   const size_t K = spline_segments(m->Lm);
   if (h_knots) HIP_TRY(hipMemcpy(h_knots, m->ms.knots, (K + 1) * 8, hipMemcpyDeviceToHost));
   if (h_bound) HIP_TRY(hipMemcpy(h_bound, m->ms.bound, ((size_t)m->Lm + 1) * 8, hipMemcpyDeviceToHost));

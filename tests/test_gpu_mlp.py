@@ -208,6 +208,9 @@ def test_auto_choice(env):
     recs = datagen.generate(datagen.spec("uniform", seed=12), 300_000)
     m, *_ = _fit(env, recs, num_buckets=1024, seed=12, kind=elsar.AUTO)
     assert m.info().kind_used == elsar.RMI and m.info().mlp_rejected == 0
+    assert m.info().mlp_leaves == 0  # the equi-depth leaves were not fitted
+    with pytest.raises(elsar.ElsarError):
+        m.spline()
     recs = datagen.generate(datagen.spec("skewed", seed=13), 300_000)
     m, *_ = _fit(env, recs, num_buckets=1024, seed=13, kind=elsar.AUTO)
-    assert m.info().kind_used == elsar.SPLINE
+    assert m.info().kind_used == elsar.SPLINE and m.info().mlp_leaves == 1024
