@@ -189,7 +189,7 @@ constexpr uint32_t kSmWaves = kSmThreads / 64;
 constexpr uint32_t kSmCap = kSmallCap;
 constexpr uint32_t kSmBits = 11;     // counting-sort digit: 2048 bins of the bucket's code range
 constexpr uint32_t kSmGroup = 7;     // gathered chunks in flight per thread
-constexpr uint32_t kRunMax = 16;     // longest bin sorted by insertion
+constexpr uint32_t kRunMax = 64;     // longest bin ordered by counted ranks
 constexpr uint32_t kWaveSortMax = 256;  // longest bin a wave sorts (bitonic); longer ones: LSD over the bucket
 
 // LDS writes of a wave visible to all its lanes (compiler ordering; one
@@ -202,9 +202,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Steps after the digits: the digit of entry p is in perm[1][p] (2^BITS bins,
 // non-decreasing in the composite).  A counting pass on the digit, then the
-// whole composite (less) orders each bin: insertion sort (one thread) up to
-// kRunMax entries, a bitonic network (one wave, in its own kWaveSortMax
-// entries of perm[1]) up to kWaveSortMax, and stable LSD passes over every
+// whole composite (less) orders each bin: ranks counted in parallel (one
+// thread per entry) up to kRunMax entries, a bitonic network (one wave, in its
+// own kWaveSortMax entries of perm[1]) up to kWaveSortMax, and stable LSD passes over every
 // varying composite byte (byte_of(entry, position)) of the bucket when some
 // bin is longer still (keys clustered at a finer scale than the digit
 // resolves).  CROWD_TO_LSD: the LSD passes also when the bins are crowded
@@ -257,26 +257,31 @@ __device__ __forceinline__ uint32_t bin_sort_core(uint32_t n, uint32_t vary, uin
   __syncthreads();
   bool long_bin = crowded;
   for (uint32_t b = crowded ? NB : tid; b < NB; b += THREADS) {
-    uint32_t s0 = b ? bins[b - 1] : 0u, s1 = bins[b];
-    if (s1 - s0 < 2) continue;
-    if (s1 - s0 > kRunMax) {
-      if (s1 - s0 > kWaveSortMax) long_bin = true;
+    const uint32_t m = bins[b] - (b ? bins[b - 1] : 0u);
+    if (m > kRunMax) {
+      if (m > kWaveSortMax) long_bin = true;
       else wave_bins[atomicAdd(&n_wave_bins, 1u)] = (uint16_t)b;
-      continue;
-    }
-    for (uint32_t x = s0 + 1; x < s1; ++x) {  // insertion sort by the whole composite
-      uint16_t e = perm[0][x];
-      uint32_t y = x;
-      while (y > s0 && less(e, perm[0][y - 1])) {
-        perm[0][y] = perm[0][y - 1];
-        --y;
-      }
-      perm[0][y] = e;
     }
   }
   long_bin = __syncthreads_or(long_bin);
   uint32_t cur = 0;
   if (!long_bin) {
+    // the bin of each of this thread's positions (start, size), read while
+    // the digits are still in perm[1]
+    constexpr uint32_t AR = CAP / THREADS;
+    static_assert(CAP % THREADS == 0, "whole rounds of positions");
+    uint32_t ext[AR];
+#pragma unroll
+    for (uint32_t i = 0; i < AR; ++i) {
+      const uint32_t x = tid + i * THREADS;
+      ext[i] = 0;
+      if (x < n) {
+        const uint32_t d = dig[perm[0][x]];
+        const uint32_t b0 = d ? bins[d - 1] : 0u;
+        ext[i] = (b0 << 16) | (bins[d] - b0);
+      }
+    }
+    __syncthreads();
     // one wave per bin of kRunMax+1 .. kWaveSortMax entries: bitonic network
     // over the next power of two, padded with a sentinel above every entry
     const uint32_t w = tid >> 6, lane = tid & 63u;
@@ -309,6 +314,28 @@ __device__ __forceinline__ uint32_t bin_sort_core(uint32_t n, uint32_t vary, uin
       for (uint32_t x = lane; x < m; x += 64) perm[0][s0 + x] = sc[x];
       wave_lds_sync();
     }
+    __syncthreads();
+    // bins of up to kRunMax entries: every entry's rank is the number of
+    // entries of its bin below it (one thread per entry, all bins at once);
+    // the entries go to perm[1] at bin start + rank, the longer bins (already
+    // in order) to the same positions
+#pragma unroll
+    for (uint32_t i = 0; i < AR; ++i) {
+      const uint32_t x = tid + i * THREADS;
+      if (x < n) {
+        const uint32_t b0 = ext[i] >> 16, m = ext[i] & 0xFFFFu;
+        const uint16_t e = perm[0][x];
+        uint32_t dest = x;
+        if (m <= kRunMax) {
+          uint32_t rank = 0;
+          for (uint32_t y = b0; y < b0 + m; ++y) rank += less(perm[0][y], e) ? 1u : 0u;
+          dest = b0 + rank;
+        }
+        perm[1][dest] = e;
+      }
+    }
+    __syncthreads();
+    cur = 1;
   } else {  // stable LSD over every varying composite byte
     auto wc = reinterpret_cast<uint32_t(*)[256]>(bins);
     for (int pb = 15; pb >= 0; --pb) {
