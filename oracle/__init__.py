@@ -253,6 +253,17 @@ def routed_buckets(recs: np.ndarray, bound: np.ndarray, leaves: RMI) -> np.ndarr
     return out
 
 
+def routed_leaves(recs: np.ndarray, bound: np.ndarray) -> np.ndarray:
+    """Leaf of every record among boundary codes: the last j with
+    bound[j] <= code (leaf j takes codes in [bound[j], bound[j+1]); equal
+    boundaries leave the earlier leaves empty).  With one equi-depth leaf per
+    bucket this is the bucket, floor(B * the linear spline's CDF)."""
+    codes = e8_records(recs)
+    b = np.ascontiguousarray(bound, dtype=np.uint64)
+    L = b.size - 1
+    return (np.searchsorted(b[:L], codes, side="right") - 1).astype(np.uint32)
+
+
 def counts_offsets(buckets: np.ndarray, B: int):
     buckets = np.ascontiguousarray(buckets, dtype=np.uint32)
     counts = np.empty(B, dtype=np.uint64)

@@ -488,7 +488,7 @@ __global__ __launch_bounds__(256) void spline_knots_kernel(const uint64_t* __res
 // Per sample: its bucket under the equi-depth leaves (leaf found from first[]), and
 // the longest run of equal codes (no monotone bucketing can split a run).
 __global__ __launch_bounds__(256) void mlp_sample_stats_kernel(const uint64_t* __restrict__ e, uint64_t S,
-                                                               uint32_t L, const uint32_t* __restrict__ first,
+                                                               uint32_t L, uint32_t B, const uint32_t* __restrict__ first,
                                                                const Leaf* __restrict__ leaves,
                                                                uint32_t* __restrict__ hist,
                                                                ModelHeader* __restrict__ hdr) {
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(256) void mlp_sample_stats_kernel(const uint64_t* _
     if (first[mid] <= s) lo = mid; else hi = mid;
   }
   // one add per run of equal buckets within the wave (the sample is sorted)
-  const uint32_t b = leaf_bucket(load_leaf(leaves, lo), c);
+  const uint32_t b = L == B ? lo : leaf_bucket(load_leaf(leaves, lo), c);  // one leaf per bucket: the leaf
   const uint32_t l = __lane_id();
   const uint32_t bl = __shfl_up(b, 1), br = __shfl_down(b, 1);
   const bool start = in && (l == 0 || bl != b);
@@ -639,7 +639,8 @@ hipError_t launch_equi_depth_leaves(const uint64_t* e, uint64_t S, uint32_t L, u
   spline_knots_kernel<<<(K + 1 + 255) / 256, 256, 0, st>>>(ms.bound, L, K, ms.knots, hdr);
   hipError_t err = launch_fill_u32(ms.hist, B, 0u, st);
   if (err != hipSuccess) return err;
-  mlp_sample_stats_kernel<<<(uint32_t)((S + 255) / 256), 256, 0, st>>>(e, S, L, ms.first, ms.leaves, ms.hist, hdr);
+  mlp_sample_stats_kernel<<<(uint32_t)((S + 255) / 256), 256, 0, st>>>(e, S, L, B, ms.first, ms.leaves, ms.hist,
+                                                                        hdr);
   return hipGetLastError();
 }
 

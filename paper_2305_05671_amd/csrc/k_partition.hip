@@ -107,6 +107,8 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
   const uint32_t tile_dw = kPartTile * RW;
   const float a0 = hdr->a0, a1 = hdr->a1;
   const uint32_t L = ROOT ? hdr->mlp_L : hdr->L, K = hdr->spline_K;
+  // equi-depth leaves, one per bucket: floor(B * the spline's CDF) is the leaf
+  const bool leaf_is_bucket = ROOT != 0 && L == hdr->B;
   __shared__ typename std::conditional<MLP, MlpHead, uint32_t>::type mh_;
   W2Frags w2;
   if constexpr (MLP) {
@@ -163,13 +165,13 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
       const float y = mlp_y64(e, mh_, w2);
       if (threadIdx.x < cnt) {
         const uint32_t j = mlp_exact_leaf(bound, L, e, mlp_leaf_guess(y, L));
-        b = leaf_bucket(load_leaf(leaves, j), e);
+        b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
       }
     } else if (threadIdx.x < cnt) {
       const uint32_t* r = buf(cur) + threadIdx.x * RW;
       uint64_t e = key_code(r[0], r[1]);
       const uint32_t j = ROOT == 2 ? spline_exact_leaf(knots, K, bound, L, e) : rmi_leaf(a0, a1, L, e);
-      b = leaf_bucket(load_leaf(leaves, j), e);
+      b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
     }
     bool keep = threadIdx.x < cnt;
     if (FILTER) {
@@ -295,6 +297,7 @@ __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restric
   }
   const float a0 = hdr->a0, a1 = hdr->a1;
   const uint32_t L = ROOT ? hdr->mlp_L : hdr->L, K = hdr->spline_K;
+  const bool leaf_is_bucket = ROOT != 0 && L == hdr->B;
   const uint64_t wave0 = ((uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u));
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t base = wave0; base < n; base += stride) {  // uniform per wave
@@ -304,10 +307,11 @@ __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restric
     uint32_t b;
     if constexpr (MLP) {
       const float y = mlp_y64(e, mh_, w2);
-      b = leaf_bucket(load_leaf(leaves, mlp_exact_leaf(bound, L, e, mlp_leaf_guess(y, L))), e);
+      const uint32_t j = mlp_exact_leaf(bound, L, e, mlp_leaf_guess(y, L));
+      b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
     } else {
       const uint32_t j = ROOT == 2 ? spline_exact_leaf(knots, K, bound, L, e) : rmi_leaf(a0, a1, L, e);
-      b = leaf_bucket(load_leaf(leaves, j), e);
+      b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
     }
     if (i < n) atomicAdd(&counts[b], 1u);
   }

@@ -144,8 +144,8 @@ def test_fitted_mlp_model(env, kind, n, B, seed):
     assert np.sqrt(np.mean((y - np.arange(S) / S) ** 2)) < 0.05
     lv = np.searchsorted(first[:L], np.arange(S), side="right") - 1
     assert np.median(np.abs(mlp.leaf_guess(y, L) - lv)) < 0.05 * L
-    # counts bit-exact under the GPU's boundaries and leaves
-    bk = oracle.routed_buckets(recs, bound, ref)
+    # counts bit-exact under the GPU's boundaries (one leaf per bucket: the leaf)
+    bk = oracle.routed_leaves(recs, bound)
     _, want = oracle.counts_offsets(bk, B)
     assert np.array_equal(offsets.cpu().numpy().astype(np.uint64), want)
     # Equation 1: bucket ids non-decreasing along the sorted order

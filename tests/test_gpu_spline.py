@@ -4,8 +4,10 @@ The spline root's leaves are equi-depth in the sorted sample (oracle/mlp.py,
 equi_depth_first) with the same two-point splines as the RMI's leaves
 (oracle.spline_leaves); its K segment knots are the leaves' first codes at
 every (i L) / K-th leaf.  A record goes to the leaf whose boundary codes
-bracket its code (oracle.routed_buckets), so the bucket counts are bit-exact
-and the sort byte-exact.
+bracket its code; with one leaf per bucket that leaf is its bucket
+(oracle.routed_leaves), otherwise the leaf's line gives the bucket
+(oracle.routed_buckets).  The bucket counts are bit-exact and the sort
+byte-exact.
 """
 import numpy as np
 import pytest
@@ -62,8 +64,9 @@ def test_fitted_spline_model(env, kind, n, B, leaves, seed):
     has = first[1:L] < S
     assert np.array_equal(bound[1:L][has], codes[first[1:L][has]])
     assert np.array_equal(knots, bound[(np.arange(K + 1, dtype=np.int64) * L) // K])
-    # counts bit-exact under exact routing among the boundaries
-    bk = oracle.routed_buckets(recs, bound, ref)
+    # counts bit-exact under exact routing among the boundaries: with one leaf
+    # per bucket the leaf is the bucket, otherwise the leaf's line gives it
+    bk = oracle.routed_leaves(recs, bound) if L == B else oracle.routed_buckets(recs, bound, ref)
     _, want = oracle.counts_offsets(bk, B)
     assert np.array_equal(offsets.cpu().numpy().astype(np.uint64), want)
     # Equation 1 along the sorted order

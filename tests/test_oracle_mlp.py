@@ -187,3 +187,35 @@ def test_routed_buckets_equal_root_routing():
         bound[j] = sel.min() if sel.size else bound[j + 1]
     bound[0] = 0
     assert np.array_equal(oracle.routed_buckets(recs, bound, m), m.buckets(recs))
+
+
+def test_routed_leaves_worked_example():
+    # three leaves from boundaries [0, code("C..."), code("C...")] (leaf 1 empty):
+    # keys before "C" go to leaf 0, "C" and after to leaf 2
+    def rec(key):
+        r = np.full(100, ord(" "), dtype=np.uint8)
+        r[:len(key)] = np.frombuffer(key, dtype=np.uint8)
+        return r
+    recs = np.stack([rec(b"A"), rec(b"BZZZZZZZZZ"), rec(b"C"), rec(b"D"), rec(b"~~~~~~~~~~")])
+    c = oracle.e8_records(recs[2:3])[0]
+    bound = np.array([0, c, c, np.iinfo(np.uint64).max], dtype=np.uint64)
+    assert list(oracle.routed_leaves(recs, bound)) == [0, 0, 2, 2, 2]
+
+
+def test_routed_leaves_equal_single_bucket_leaves():
+    # leaves that each map to their own bucket (constant lines) route the same
+    recs = datagen.generate(datagen.spec("skewed", seed=17), 20_000)
+    codes = oracle.sample_codes(recs, seed=17)
+    L = 64
+    first = mlp.equi_depth_first(codes, L)
+    bound = np.full(L + 1, np.iinfo(np.uint64).max, dtype=np.uint64)
+    bound[0] = 0
+    has = first[1:L] < codes.size
+    bound[1:L][has] = codes[first[1:L][has].astype(np.int64)]
+    m = oracle.RMI(L, L)
+    m.base[:] = 0
+    m.c[:] = 0
+    m.b[:] = np.arange(L, dtype=np.float32)
+    m.lo[:] = np.arange(L, dtype=np.uint32)
+    m.hi[:] = np.arange(L, dtype=np.uint32)
+    assert np.array_equal(oracle.routed_leaves(recs, bound), oracle.routed_buckets(recs, bound, m))
