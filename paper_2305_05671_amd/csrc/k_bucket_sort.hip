@@ -207,11 +207,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // own kWaveSortMax entries of perm[1]) up to kWaveSortMax, and stable LSD passes over every
 // varying composite byte (byte_of(entry, position)) of the bucket when some
 // bin is longer still (keys clustered at a finer scale than the digit
-// resolves).  CROWD_TO_LSD: the LSD passes also when the bins are crowded
-// overall (a sum of squared bin sizes above 4n; spread keys give about 2n).
-// bins: 2^BITS counters, also the LSD passes' per-wave counters.  Returns
-// the perm buffer that holds the sorted order.
-template <uint32_t CAP, uint32_t THREADS, uint32_t BITS, bool CROWD_TO_LSD, typename Less, typename ByteOf>
+// resolves).  bins: 2^BITS counters, also the LSD passes' per-wave counters.
+// Returns the perm buffer that holds the sorted order.
+template <uint32_t CAP, uint32_t THREADS, uint32_t BITS, typename Less, typename ByteOf>
 __device__ __forceinline__ uint32_t bin_sort_core(uint32_t n, uint32_t vary, uint16_t (*perm)[CAP], uint32_t* bins,
                                                   uint32_t* sh_scan, uint32_t* tot, Less less, ByteOf byte_of) {
   constexpr uint32_t WAVES = THREADS / 64, NB = 1u << BITS;
@@ -235,28 +233,13 @@ __device__ __forceinline__ uint32_t bin_sort_core(uint32_t n, uint32_t vary, uin
   __syncthreads();
   for (uint32_t p = tid; p < n; p += THREADS) perm[0][atomicAdd(&bins[dig[p]], 1u)] = (uint16_t)p;
   __syncthreads();
-  bool crowded = false;
-  if constexpr (CROWD_TO_LSD) {  // bins[b] is the end of bin b
-    __shared__ uint32_t sq_sum;
-    if (tid == 0) sq_sum = 0;
-    __syncthreads();
-    uint32_t sq = 0;
-    for (uint32_t b = tid; b < NB; b += THREADS) {
-      const uint32_t len = bins[b] - (b ? bins[b - 1] : 0u);
-      sq += len * len;
-    }
-    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
-    if ((tid & 63u) == 0) atomicAdd(&sq_sum, sq);
-    __syncthreads();
-    crowded = sq_sum > 4 * n;
-  }
   // bins[b] is now the end of bin b; the start is the end of bin b-1
   __shared__ uint16_t wave_bins[CAP / (kRunMax + 1) + 1];  // bins for the waves
   __shared__ uint32_t n_wave_bins;
   if (tid == 0) n_wave_bins = 0;
   __syncthreads();
-  bool long_bin = crowded;
-  for (uint32_t b = crowded ? NB : tid; b < NB; b += THREADS) {
+  bool long_bin = false;
+  for (uint32_t b = tid; b < NB; b += THREADS) {  // bins[b] is the end of bin b
     const uint32_t m = bins[b] - (b ? bins[b - 1] : 0u);
     if (m > kRunMax) {
       if (m > kWaveSortMax) long_bin = true;
@@ -358,7 +341,7 @@ __device__ __forceinline__ uint32_t small_sort_core(uint32_t n, uint32_t vary, u
     return cw[3][x] < cw[3][y];
   };
   auto byte_of = [&](uint32_t e, uint32_t pb) -> uint32_t { return (cw[pb >> 2][e] >> (24 - 8 * (pb & 3))) & 0xFFu; };
-  return bin_sort_core<kSmCap, kSmThreads, kSmBits, false>(n, vary, perm, bins, sh_scan, tot, less, byte_of);
+  return bin_sort_core<kSmCap, kSmThreads, kSmBits>(n, vary, perm, bins, sh_scan, tot, less, byte_of);
 }
 
 template <uint32_t RW>  // record dwords
@@ -540,7 +523,7 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
       perm[1][p] = (uint16_t)(d < (1u << kMidBits) ? d : (1u << kMidBits) - 1);
     }
     const uint32_t cur =
-        bin_sort_core<CAP, THREADS, kMidBits, true>(br.n, vary, perm, bins, sh_scan, tot, less, byte_of);
+        bin_sort_core<CAP, THREADS, kMidBits>(br.n, vary, perm, bins, sh_scan, tot, less, byte_of);
     __syncthreads();
     // 3. copy records in sorted order to the output: lane q moves 16-byte
     //    chunk q % LC of the record at sorted position q / LC, kSmGroup loads
