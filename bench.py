@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform-100M", choices=sorted(WORKLOADS))
     ap.add_argument("--model", default=None, choices=["rmi", "mlp", "auto", "radix", "spline"],
-                    help="CDF root (default: mlp for the host workload, rmi otherwise)")
+                    help="CDF root (default: mlp for the host workload, rmi for uniform keys, auto otherwise)")
     ap.add_argument("--leaves", type=int, default=0, help="RMI leaves L (0: buckets / 16)")
     ap.add_argument("--mlp-steps", type=int, default=0, help="Adam steps of the MLP fit (0: library default)")
     ap.add_argument("--accept-ratio", type=float, default=1.5,
