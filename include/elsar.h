@@ -74,7 +74,7 @@ typedef struct {
   uint32_t kind;          /* elsar_model_kind */
   float accept_ratio;     /* MLP accepted if its largest sample bucket <= ratio * ideal, ideal =
                              max(ceil(S/B), longest run of equal codes in the sample); 0: 1.5 */
-  uint32_t mlp_steps;     /* Adam steps (128 sample rows each) of the MLP fit; 0: 400 */
+  uint32_t mlp_steps;     /* Adam steps (128 sample rows each) of the MLP fit; 0: 16 */
   uint32_t region_pct;    /* bucket j's region holds ceil(region_pct/100 * max(n*(h_j + 2 sqrt(h_j))/S, n/B))
                              + 16 records (h_j: sample keys in bucket j), the rest spills; 0: 125 */
 } elsar_fit_params;
@@ -108,9 +108,12 @@ elsar_status elsar_fit_workspace_size(const elsar_model* m, uint64_t n, size_t* 
  * spline root groups them in K = L/64 segments whose first codes (knots) it
  * searches.  Kind MLP also trains the monotone MLP root (8 quantile-ramp
  * features of the code -> 64 -> 64 -> 1, sigmoid units, non-negative weights;
- * MSE to rank/S on the sample; Adam), whose guess floor(L*y) starts an exact
- * search among the leaves' first codes.  The root is chosen on the device (see
- * elsar_model_kind).
+ * MSE to rank/S on the sample; Adam).  After training, a cell table over the
+ * network's output gives, for each of L cells of y, the bracket of leaves
+ * whose first codes map there; a record's leaf is then searched exactly among
+ * the first codes inside that bracket (after a check that it holds, else from
+ * the guess floor(L*y) over all of them).  The root is chosen on the device
+ * (see elsar_model_kind).
  * With kind MLP the call then synchronises with `stream` and returns
  * ELSAR_E_MODEL_REJECTED when the linear root was kept (the model stays valid).
  */

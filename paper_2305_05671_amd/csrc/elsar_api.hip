@@ -34,7 +34,7 @@ struct elsar_model {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr uint32_t kDefaultMlpSteps = 400;
+constexpr uint32_t kDefaultMlpSteps = 16;
 constexpr float kMlpLearningRate = 0.01f;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -221,6 +221,7 @@ elsar_status do_fit(elsar_model* m, const void* d_records, uint64_t n, void* d_w
     if (m->p.kind == ELSAR_MODEL_MLP)
       HIP_TRY(launch_mlp_train(sorted, S, m->p.seed, m->p.mlp_steps, kMlpLearningRate, m->ms, st));
     HIP_TRY(launch_equi_depth_leaves(sorted, S, m->Lm, m->B, m->hdr, m->ms, st));
+    if (m->p.kind == ELSAR_MODEL_MLP) HIP_TRY(launch_mlp_cell_table(m->ms, m->Lm, st));
   }
   HIP_TRY(launch_decide_root(m->hist, m->has_mlp ? &m->ms : nullptr, m->B, S, m->p.accept_ratio, m->p.kind,
                              m->hdr, m->hist, st));

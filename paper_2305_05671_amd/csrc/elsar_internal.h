@@ -283,6 +283,7 @@ struct MlpState {
   uint32_t* first;   // L + 1: first sample rank of each leaf
   uint32_t* hist;    // B: sample keys per bucket under these leaves
   uint64_t* knots;   // spline_segments(L) + 1 segment knots of the spline root
+  uint32_t* cells;   // L + 1: cells[c] = leaves whose MLP cell floor(L y(bound[j])) is below c
   float* master;     // kMlpParams FP32 parameters of the MLP
   float* adam;       // 2 * kMlpParams moments
 };
@@ -295,6 +296,8 @@ hipError_t launch_mlp_train(const uint64_t* sorted_codes, uint64_t S, uint64_t s
 // and the sample histogram under these leaves.
 hipError_t launch_equi_depth_leaves(const uint64_t* sorted_codes, uint64_t S, uint32_t L, uint32_t B,
                                     ModelHeader* hdr, const MlpState& ms, hipStream_t st);
+// The MLP root's cell table over its L leaves (after training and the leaves).
+hipError_t launch_mlp_cell_table(const MlpState& ms, uint32_t L, hipStream_t st);
 // Automatic kind: whether the linear root is kept (ModelHeader::mlp_skip);
 // other kinds clear the flag.
 hipError_t launch_auto_gate(const uint32_t* hist_rmi, uint32_t B, uint64_t S, float accept_ratio, uint32_t kind,

@@ -28,8 +28,8 @@ inline size_t al(size_t x) { return (x + kA - 1) & ~(kA - 1); }
 
 size_t mlp_state_bytes(uint32_t L, uint32_t B) {
   return al(sizeof(MlpBlock)) + al((size_t)L * sizeof(Leaf)) + al(((size_t)L + 1) * 8) + al(((size_t)L + 1) * 4) +
-         al((size_t)B * 4) + al(((size_t)spline_segments(L) + 1) * 8) + al((size_t)kMlpParams * 4) +
-         al((size_t)kMlpParams * 8);
+         al((size_t)B * 4) + al(((size_t)spline_segments(L) + 1) * 8) + al(((size_t)L + 1) * 4) +
+         al((size_t)kMlpParams * 4) + al((size_t)kMlpParams * 8);
 }
 
 void place_mlp_state(MlpState* s, void* base, uint32_t L, uint32_t B) {
@@ -46,6 +46,8 @@ void place_mlp_state(MlpState* s, void* base, uint32_t L, uint32_t B) {
   b += al((size_t)B * 4);
   s->knots = reinterpret_cast<uint64_t*>(b);
   b += al(((size_t)spline_segments(L) + 1) * 8);
+  s->cells = reinterpret_cast<uint32_t*>(b);
+  b += al(((size_t)L + 1) * 4);
   s->master = reinterpret_cast<float*>(b);
   b += al((size_t)kMlpParams * 4);
   s->adam = reinterpret_cast<float*>(b);
@@ -405,8 +407,8 @@ __global__ __launch_bounds__(256) void mlp_eval_kernel(const MlpBlock* __restric
                                                        float* __restrict__ y) {
   __shared__ MlpHead mh;
   load_head(Mg, mh);
-  W2Frags w;
-  mlp_load_w2(Mg->W2bf, w);
+  MlpFrags w;
+  mlp_load_frags(Mg, w);
   __syncthreads();
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const float v = mlp_y64(codes[i < n ? i : n - 1], mh, w);
@@ -483,6 +485,38 @@ __global__ __launch_bounds__(256) void spline_knots_kernel(const uint64_t* __res
   if (hdr->mlp_skip) return;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i <= K) knots[i] = bound[((uint64_t)i * L) / K];
+}
+
+// Cell table of the MLP root.  Cell c of the network's output is [c/L,
+// (c+1)/L); cells[c] counts the leaves j whose boundary code bound[j] lands in
+// a cell below c, found by a binary search over j that evaluates the network
+// at each probe (a wave-collective evaluation: every lane takes part in every
+// probe, lanes past the table repeat the last entry's search).  With y
+// non-decreasing in the code, a record in leaf j* with cell c satisfies
+// cells[c] - 1 <= j* < cells[c + 1], so the leaf search starts from that
+// bracket; the router checks the bracket against the boundaries and falls back
+// to the unbracketed search if rounding ever broke the order.
+__global__ __launch_bounds__(256) void mlp_cell_table_kernel(const MlpBlock* __restrict__ Mg,
+                                                             const uint64_t* __restrict__ bound, uint32_t L,
+                                                             uint32_t* __restrict__ cells) {
+  __shared__ MlpHead mh;
+  load_head(Mg, mh);
+  MlpFrags w;
+  mlp_load_frags(Mg, w);
+  __syncthreads();
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t c = i < L ? i : L;  // cells[L] = L: no cell reaches L
+  uint32_t lo = 0, hi = L;           // first j in [0, L] with cell(j) >= c; j = L counts as true
+  uint32_t iters = 0;
+  while ((1ull << iters) < (uint64_t)L + 1) ++iters;
+  for (uint32_t it = 0; it < iters; ++it) {
+    const uint32_t mid = (lo + hi) >> 1;  // < L while lo < hi
+    const float y = mlp_y64(bound[mid < L ? mid : L - 1], mh, w);
+    if (lo < hi) {
+      if (mlp_leaf_guess(y, L) >= c) hi = mid; else lo = mid + 1;
+    }
+  }
+  if (i <= L) cells[i] = lo;
 }
 
 // Per sample: its bucket under the equi-depth leaves (leaf found from first[]), and
@@ -641,6 +675,12 @@ hipError_t launch_equi_depth_leaves(const uint64_t* e, uint64_t S, uint32_t L, u
   if (err != hipSuccess) return err;
   mlp_sample_stats_kernel<<<(uint32_t)((S + 255) / 256), 256, 0, st>>>(e, S, L, B, ms.first, ms.leaves, ms.hist,
                                                                         hdr);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_cell_table(const MlpState& ms, uint32_t L, hipStream_t st) {
+  if (L == 0) return hipSuccess;
+  mlp_cell_table_kernel<<<(L + 1 + 255) / 256, 256, 0, st>>>(ms.M, ms.bound, L, ms.cells);
   return hipGetLastError();
 }
 

@@ -81,8 +81,8 @@ __device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const
 // the atomic latency stalls the block.  Two LDS tile buffers alternate.
 //
 // ROOT (kind_used of the header): 0 the linear RMI root; 1 the monotone MLP,
-// whose floor(L y) is the guess from which the exact leaf is found among the
-// routing boundaries; 2 the linear spline over equi-depth leaves, routed by a
+// whose output cell floor(L y) names, through the fit's cell table, a bracket
+// of leaves searched among the routing boundaries; 2 the linear spline over equi-depth leaves, routed by a
 // binary search among its segment knots and then the segment's leaves.  A fit
 // that may choose among roots launches a kernel per root; each returns at
 // once unless the header names its own.
@@ -93,8 +93,8 @@ __device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const
 template <int RW_T, int ROOT, bool FILTER>
 __global__ __launch_bounds__(kPartThreads) void partition_kernel(
     const ModelHeader* __restrict__ hdr, const Leaf* __restrict__ leaves, const MlpBlock* __restrict__ mlp,
-    const uint64_t* __restrict__ bound, const uint64_t* __restrict__ knots, const uint8_t* __restrict__ recs,
-    uint64_t n, uint32_t rw_rt, uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps,
+    const uint64_t* __restrict__ bound, const uint64_t* __restrict__ knots, const uint32_t* __restrict__ cells,
+    const uint8_t* __restrict__ recs, uint64_t n, uint32_t rw_rt, uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps,
     const uint32_t* __restrict__ rstart, PartHeader* __restrict__ ph, uint2* __restrict__ spill_meta,
     uint4* __restrict__ slots, uint64_t cap_slots, PassFilter f) {
   const uint32_t RW = RW_T ? (uint32_t)RW_T : rw_rt;  // record dwords
@@ -110,11 +110,11 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
   // equi-depth leaves, one per bucket: floor(B * the spline's CDF) is the leaf
   const bool leaf_is_bucket = ROOT != 0 && L == hdr->B;
   __shared__ typename std::conditional<MLP, MlpHead, uint32_t>::type mh_;
-  W2Frags w2;
+  MlpFrags w2;
   if constexpr (MLP) {
     for (uint32_t i = threadIdx.x; i < sizeof(MlpHead) / 4; i += kPartThreads)
       reinterpret_cast<uint32_t*>(&mh_)[i] = reinterpret_cast<const uint32_t*>(&mlp->h)[i];
-    mlp_load_w2(mlp->W2bf, w2);
+    mlp_load_frags(mlp, w2);
   }
   const uint64_t ntiles = (n + kPartTile - 1) / kPartTile;
   const uint32_t* rec_dw = reinterpret_cast<const uint32_t*>(recs);
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
       const uint64_t e = key_code(r[0], r[1]);
       const float y = mlp_y64(e, mh_, w2);
       if (threadIdx.x < cnt) {
-        const uint32_t j = mlp_exact_leaf(bound, L, e, mlp_leaf_guess(y, L));
+        const uint32_t j = mlp_bracket_leaf(bound, cells, L, e, y);
         b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
       }
     } else if (threadIdx.x < cnt) {
@@ -223,15 +223,16 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
 template <int ROOT, bool FILTER>
 static void launch_partition_root(uint32_t grid, size_t lds, hipStream_t st, uint32_t RW, const ModelHeader* hdr,
                                   const Leaf* leaves, const MlpBlock* mlp, const uint64_t* bound,
-                                  const uint64_t* knots, const uint8_t* recs, uint64_t n, uint32_t* counts,
+                                  const uint64_t* knots, const uint32_t* cells, const uint8_t* recs, uint64_t n,
+                                  uint32_t* counts,
                                   const uint32_t* caps, const uint32_t* rstart, PartHeader* ph, uint2* meta,
                                   uint4* slots, uint64_t cap_slots, PassFilter f) {
   if (RW == 25)
-    partition_kernel<25, ROOT, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, knots, recs, n, RW,
+    partition_kernel<25, ROOT, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, knots, cells, recs, n, RW,
                                                                         counts, caps, rstart, ph, meta, slots,
                                                                         cap_slots, f);
   else
-    partition_kernel<0, ROOT, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, knots, recs, n, RW,
+    partition_kernel<0, ROOT, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, knots, cells, recs, n, RW,
                                                                        counts, caps, rstart, ph, meta, slots,
                                                                        cap_slots, f);
 }
@@ -255,22 +256,22 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const Ml
   auto* slots = reinterpret_cast<uint4*>(part + lay.slots);
   const PassFilter f = filter ? *filter : PassFilter{0, 0, 0};
   if (filter) {
-    launch_partition_root<0, true>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, nullptr, recs, n, counts, caps,
-                                   rstart, ph, meta, slots, lay.cap_slots, f);
+    launch_partition_root<0, true>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, nullptr, nullptr, recs, n,
+                                   counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
     if (ms) {
-      launch_partition_root<1, true>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, nullptr, recs, n, counts,
-                                     caps, rstart, ph, meta, slots, lay.cap_slots, f);
-      launch_partition_root<2, true>(grid, lds, st, RW, hdr, ms->leaves, nullptr, ms->bound, ms->knots, recs, n,
-                                     counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
+      launch_partition_root<1, true>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, nullptr, ms->cells, recs,
+                                     n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
+      launch_partition_root<2, true>(grid, lds, st, RW, hdr, ms->leaves, nullptr, ms->bound, ms->knots, nullptr, recs,
+                                     n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
     }
   } else {
-    launch_partition_root<0, false>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, nullptr, recs, n, counts, caps,
-                                    rstart, ph, meta, slots, lay.cap_slots, f);
+    launch_partition_root<0, false>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, nullptr, nullptr, recs, n,
+                                    counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
     if (ms) {
-      launch_partition_root<1, false>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, nullptr, recs, n, counts,
-                                      caps, rstart, ph, meta, slots, lay.cap_slots, f);
-      launch_partition_root<2, false>(grid, lds, st, RW, hdr, ms->leaves, nullptr, ms->bound, ms->knots, recs, n,
-                                      counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
+      launch_partition_root<1, false>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, nullptr, ms->cells, recs,
+                                      n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
+      launch_partition_root<2, false>(grid, lds, st, RW, hdr, ms->leaves, nullptr, ms->bound, ms->knots, nullptr,
+                                      recs, n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
     }
   }
   return hipGetLastError();
@@ -283,16 +284,17 @@ template <int ROOT>
 __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restrict__ hdr,
                                                     const Leaf* __restrict__ leaves, const MlpBlock* __restrict__ mlp,
                                                     const uint64_t* __restrict__ bound,
-                                                    const uint64_t* __restrict__ knots, const uint32_t* __restrict__ rec,
+                                                    const uint64_t* __restrict__ knots,
+                                                    const uint32_t* __restrict__ cells, const uint32_t* __restrict__ rec,
                                                     uint64_t n, uint32_t RW, uint32_t* __restrict__ counts) {
   constexpr bool MLP = ROOT == 1;
   if (hdr->kind_used != (uint32_t)ROOT) return;
   __shared__ typename std::conditional<MLP, MlpHead, uint32_t>::type mh_;
-  W2Frags w2;
+  MlpFrags w2;
   if constexpr (MLP) {
     for (uint32_t i = threadIdx.x; i < sizeof(MlpHead) / 4; i += blockDim.x)
       reinterpret_cast<uint32_t*>(&mh_)[i] = reinterpret_cast<const uint32_t*>(&mlp->h)[i];
-    mlp_load_w2(mlp->W2bf, w2);
+    mlp_load_frags(mlp, w2);
     __syncthreads();
   }
   const float a0 = hdr->a0, a1 = hdr->a1;
@@ -307,7 +309,7 @@ __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restric
     uint32_t b;
     if constexpr (MLP) {
       const float y = mlp_y64(e, mh_, w2);
-      const uint32_t j = mlp_exact_leaf(bound, L, e, mlp_leaf_guess(y, L));
+      const uint32_t j = mlp_bracket_leaf(bound, cells, L, e, y);
       b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
     } else {
       const uint32_t j = ROOT == 2 ? spline_exact_leaf(knots, K, bound, L, e) : rmi_leaf(a0, a1, L, e);
@@ -324,10 +326,11 @@ hipError_t launch_count(const ModelHeader* hdr, const Leaf* leaves, const MlpSta
   const uint64_t waves = (n + 63) / 64;
   const uint32_t grid = (uint32_t)std::min<uint64_t>((waves + 3) / 4, 4096);
   const uint32_t* rec = reinterpret_cast<const uint32_t*>(recs);
-  count_kernel<0><<<grid, 256, 0, st>>>(hdr, leaves, nullptr, nullptr, nullptr, rec, n, RW, counts);
+  count_kernel<0><<<grid, 256, 0, st>>>(hdr, leaves, nullptr, nullptr, nullptr, nullptr, rec, n, RW, counts);
   if (ms) {
-    count_kernel<1><<<grid, 256, 0, st>>>(hdr, ms->leaves, ms->M, ms->bound, nullptr, rec, n, RW, counts);
-    count_kernel<2><<<grid, 256, 0, st>>>(hdr, ms->leaves, nullptr, ms->bound, ms->knots, rec, n, RW, counts);
+    count_kernel<1><<<grid, 256, 0, st>>>(hdr, ms->leaves, ms->M, ms->bound, nullptr, ms->cells, rec, n, RW, counts);
+    count_kernel<2><<<grid, 256, 0, st>>>(hdr, ms->leaves, nullptr, ms->bound, ms->knots, nullptr, rec, n, RW,
+                                          counts);
   }
   return hipGetLastError();
 }

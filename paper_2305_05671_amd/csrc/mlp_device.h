@@ -71,17 +71,27 @@ __device__ __forceinline__ void mlp_layer1_frags(const float phi[8], const MlpHe
   }
 }
 
-// B fragments of W2 for the 4 column tiles x 4 K-steps, held for a whole kernel.
-struct W2Frags {
-  s16x4 f[16];  // [ct * 4 + ks]
+// Matrix-core operands of the evaluation, held for a whole kernel:
+// f[4ct + ks] = W2[16ct + l%16][16ks + 4(l/16) + e] (e = 0..3, bfloat16), the
+// A fragments of layer 2 computed as W2 . H1^T; w1[2ks + h] = W1[16ks +
+// l%16][4h + l/16], the A operands of layer 1 computed as W1 . Phi^T in FP32
+// (v_mfma_f32_16x16x4_f32: lane l gives A[l%16][l/16] and B[l/16][l%16]).
+struct MlpFrags {
+  s16x4 f[16];
+  float w1[8];
 };
 
-__device__ __forceinline__ void mlp_load_w2(const uint16_t* __restrict__ W2bf, W2Frags& w) {
+__device__ __forceinline__ void mlp_load_frags(const MlpBlock* __restrict__ Mg, MlpFrags& w) {
   const uint32_t l = __lane_id(), r = l & 15u, g = l >> 4;
 #pragma unroll
   for (uint32_t ct = 0; ct < 4; ++ct)
 #pragma unroll
-    for (uint32_t ks = 0; ks < 4; ++ks) w.f[ct * 4 + ks] = load4_bf16(W2bf + (16 * ct + r) * 64 + 16 * ks + 4 * g);
+    for (uint32_t ks = 0; ks < 4; ++ks)
+      w.f[ct * 4 + ks] = load4_bf16(Mg->W2bf + (16 * ct + r) * 64 + 16 * ks + 4 * g);
+#pragma unroll
+  for (uint32_t ks = 0; ks < 4; ++ks)
+#pragma unroll
+    for (uint32_t h = 0; h < 2; ++h) w.w1[2 * ks + h] = Mg->h.W1[(16 * ks + r) * 8 + 4 * h + g];
 }
 
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
@@ -89,43 +99,68 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Feature k of one code (as in mlp_features).
+__device__ __forceinline__ float mlp_feature(uint64_t code, const MlpHead& M, uint32_t k) {
+  const uint64_t d = code >= M.q[k] ? code - M.q[k] : 0ull;
+  return fminf(1.0f, (float)d * M.inv_w[k]);
+}
+
+// Four values rounded to bfloat16 (nearest, ties to even) by the converter.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ s16x4 pack4_bf16_cvt(float a, float b, float c, float d) {
+  const bf16x2 lo = __builtin_convertvector((f32x2){a, b}, bf16x2);
+  const bf16x2 hi = __builtin_convertvector((f32x2){c, d}, bf16x2);
+  const uint32_t u0 = __builtin_bit_cast(uint32_t, lo), u1 = __builtin_bit_cast(uint32_t, hi);
+  s16x4 v;
+  v[0] = (short)(u0 & 0xFFFFu);
+  v[1] = (short)(u0 >> 16);
+  v[2] = (short)(u1 & 0xFFFFu);
+  v[3] = (short)(u1 >> 16);
+  return v;
+}
+
 // Root output y of the record whose code this lane holds; all 64 lanes of the
-// wave must take part (64 records per call).
-__device__ __forceinline__ float mlp_y64(uint64_t code, const MlpHead& M, const W2Frags& w) {
+// wave must take part (64 records per call, in four chunks of 16).  Both
+// hidden layers run transposed, units x records, on the matrix cores: layer 1
+// in FP32 from two features per lane, layer 2 in bfloat16 with FP32
+// accumulation.  Lane l then holds units 16t + 4(l/16) + e of record l%16 of
+// the chunk, so layer 1's output is already layer 2's B fragment, and the
+// output unit is an in-lane sum over 16 units plus a sum over the four lane
+// groups.
+__device__ __forceinline__ float mlp_y64(uint64_t code, const MlpHead& M, const MlpFrags& w) {
   const uint32_t l = __lane_id(), r = l & 15u, g = l >> 4;
   float y_own = 0.0f;
 #pragma unroll 1
   for (uint32_t c = 0; c < 4; ++c) {
-    // the layer-1 weights are re-read from LDS for every chunk instead of
-    // being kept in registers across chunks and tiles (which costs occupancy)
+    // biases are re-read from LDS for every chunk rather than held in registers
     __asm__ volatile("" ::: "memory");
     const uint64_t cc = shfl_u64(code, (int)(16 * c + r));  // record 16c + r
-    float phi[8], h1[16];
-    s16x4 a[4];
-    mlp_features(cc, M, phi);
-    mlp_layer1_frags(phi, M, g, a, h1);
-    float part[4] = {0.f, 0.f, 0.f, 0.f};
+    const float p0 = mlp_feature(cc, M, g), p1 = mlp_feature(cc, M, g + 4);
+    s16x4 h1[4];  // units 16ks + 4g + e of record r
+#pragma unroll
+    for (uint32_t ks = 0; ks < 4; ++ks) {
+      const uint32_t u = 16 * ks + 4 * g;
+      f32x4 z = {M.b1[u], M.b1[u + 1], M.b1[u + 2], M.b1[u + 3]};
+      z = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w1[2 * ks], p0, z, 0, 0, 0);
+      z = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w1[2 * ks + 1], p1, z, 0, 0, 0);
+      h1[ks] = pack4_bf16_cvt(sigm(z[0]), sigm(z[1]), sigm(z[2]), sigm(z[3]));
+    }
+    float part = 0.0f;
 #pragma unroll
     for (uint32_t ct = 0; ct < 4; ++ct) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (uint32_t ks = 0; ks < 4; ++ks)
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ks], w.f[ct * 4 + ks], acc, 0, 0, 0);
-      const uint32_t col = 16 * ct + r;
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w.f[ct * 4 + ks], h1[ks], acc, 0, 0, 0);
+      const uint32_t u = 16 * ct + 4 * g;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) part[e] = __builtin_fmaf(M.w3[col], sigm(acc[e] + M.b2[col]), part[e]);
+      for (int e = 0; e < 4; ++e) part = __builtin_fmaf(M.w3[u + e], sigm(acc[e] + M.b2[u + e]), part);
     }
-    // sum over the 16 columns a lane group holds: rows 4g + e of this chunk
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int off = 1; off < 16; off <<= 1) part[e] += __shfl_xor(part[e], off);
-    // lane l's own record is row l%16 of chunk l/16: lane group r/4, slot r%4
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const float v = __shfl(part[e], (int)(16 * (r >> 2)));
-      if (g == c && (r & 3u) == (uint32_t)e) y_own = v;
-    }
+    // the four lane groups of record r (every lane ends with the same sum)
+    part += __shfl_xor(part, 16);
+    part += __shfl_xor(part, 32);
+    if (g == c) y_own = part;  // lane l's own record is record l%16 of chunk l/16
   }
   return y_own + M.b3;
 }
@@ -163,6 +198,25 @@ __device__ __forceinline__ uint32_t mlp_exact_leaf(const uint64_t* __restrict__ 
       step <<= 1;
     }
   }
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (bound[mid] <= code) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// The same leaf, searched inside the bracket that the cell table gives for
+// the network's output y: cells[c] - 1 <= j < cells[c + 1] for c = floor(L y).
+// The bracket is checked against the boundaries first; a bracket that does not
+// hold (only possible if rounding made y decrease somewhere) falls back to the
+// search from the guess, so the leaf is exact either way.
+__device__ __forceinline__ uint32_t mlp_bracket_leaf(const uint64_t* __restrict__ bound,
+                                                     const uint32_t* __restrict__ cells, uint32_t L, uint64_t code,
+                                                     float y) {
+  const uint32_t c = mlp_leaf_guess(y, L);
+  const uint32_t t0 = cells[c], t1 = cells[c + 1];
+  uint32_t lo = t0 ? t0 - 1u : 0u, hi = t1;  // bound[lo] <= code < bound[hi] (hi == L: past every code)
+  if (hi <= lo || bound[lo] > code || (hi < L && bound[hi] <= code)) return mlp_exact_leaf(bound, L, code, c);
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
     if (bound[mid] <= code) lo = mid; else hi = mid;

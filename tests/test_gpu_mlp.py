@@ -117,7 +117,9 @@ def _fit(env, recs, **kw):
 def test_fitted_mlp_model(env, kind, n, B, seed):
     _, elsar = env
     recs = datagen.generate(datagen.spec(kind, seed=seed), n)
-    m, part, offsets, _ = _fit(env, recs, num_buckets=B, seed=seed, kind=elsar.MLP, accept_ratio=1e9)
+    # 100 Adam steps: this test also checks how closely training follows the CDF
+    m, part, offsets, _ = _fit(env, recs, num_buckets=B, seed=seed, kind=elsar.MLP, accept_ratio=1e9,
+                               mlp_steps=100)
     info = m.info()
     assert info.kind_used == elsar.MLP and not m.rejected
     L = info.num_leaves
