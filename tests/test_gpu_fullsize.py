@@ -1,0 +1,85 @@
+"""GPU parity at the full 100M-record size, in the launch configuration the
+benchmark times (one elsar_sort call with a caller workspace, 65536 buckets).
+
+The oracle cannot sort 10^8 records within a test, so it checks what it can
+compute at this size: every adjacent pair of output records is in key order
+(the output is sorted), the output holds the same multiset of records as the
+input (an order-independent hash), and sampled input records sit at exactly
+the output position the oracle computes for them one by one: their stable
+rank, the number of input records whose (key, input index) is smaller.
+Together these pin a byte-exact stable sort on the sampled records and the
+sorted permutation property everywhere.
+"""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+R, KEY = 100, 10
+N, B = 100_000_000, 65536
+THREADS, PROBES = 16, 16
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2305_05671_amd as elsar
+    assert torch.cuda.is_available()
+    return torch, elsar
+
+
+def _oracle_checks(h_in, h_out, n, seed):
+    pin, pout = h_in.data_ptr(), h_out.data_ptr()
+    seg = (n + THREADS - 1) // THREADS
+    # sortedness per segment, segments overlapping by one record so that every
+    # adjacent pair is checked; the hash per disjoint segment (sums commute)
+    pairs = [(a, min(n, a + seg + 1)) for a in range(0, n, seg)]
+    parts = [(a, min(n, a + seg)) for a in range(0, n, seg)]
+    rng = np.random.default_rng(seed)
+    idx = [int(i) for i in rng.integers(0, n, PROBES)] + [0, n - 1]
+    src, dst = h_in.numpy(), h_out.numpy()
+    keys = [bytes(src[i * R:i * R + KEY]) for i in idx]
+    with ThreadPoolExecutor(THREADS) as ex:
+        unsorted = list(ex.map(lambda ab: oracle.first_unsorted_ptr(pout + ab[0] * R, ab[1] - ab[0]), pairs))
+        h_a = list(ex.map(lambda ab: oracle.multiset_hash_ptr(pin + ab[0] * R, ab[1] - ab[0]), parts))
+        h_b = list(ex.map(lambda ab: oracle.multiset_hash_ptr(pout + ab[0] * R, ab[1] - ab[0]), parts))
+        ranks = list(ex.map(lambda q: oracle.rank_of_ptr(pin, n, q[0], q[1]), zip(keys, idx)))
+    for (a, b), u in zip(pairs, unsorted):
+        assert u == b - a, f"output out of key order at position {a + u}"
+    mask = (1 << 64) - 1
+    assert (sum(h_a) & mask) == (sum(h_b) & mask), "output is not a permutation of the input"
+    for i, r in zip(idx, ranks):
+        assert 0 <= r < n
+        assert np.array_equal(src[i * R:(i + 1) * R], dst[r * R:(r + 1) * R]), (
+            f"input record {i} is not at its stable rank {r}")
+
+
+@pytest.mark.parametrize("law,seed,kind_name", [
+    ("uniform", 1, "RMI"),    # the 100M-record uniform workload the benchmark times
+    ("skewed", 2, "AUTO"),    # the skewed workload with hot keys, automatic root (the spline)
+    ("skewed", 2, "MLP"),     # the same under the MLP root
+])
+def test_full_size_sort(env, law, seed, kind_name):
+    torch, elsar = env
+    print(f"full-size case: {law} seed {seed} root {kind_name}, {N} records", flush=True)
+    kind = getattr(elsar, kind_name)
+    p = elsar.fit_params(num_buckets=B, seed=seed, kind=kind)
+    d_in = torch.empty(N * R, dtype=torch.uint8, device="cuda")
+    datagen.generate_device(datagen.spec(law, seed=seed), d_in.data_ptr(), 0, N,
+                            torch.cuda.current_stream().cuda_stream)
+    h_in = d_in.cpu()
+    d_out = torch.empty_like(d_in)
+    ws = torch.empty(elsar.sort_workspace_size(N, p), dtype=torch.uint8, device="cuda")
+    elsar.elsar_sort(d_in, d_out, p, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(d_in[:R * 1000], h_in[:R * 1000].to("cuda")), "the input was modified"
+    del ws
+    h_out = d_out.cpu()
+    del d_in, d_out
+    torch.cuda.empty_cache()
+    _oracle_checks(h_in, h_out, N, seed)
