@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--model", default=None, choices=["rmi", "mlp", "auto", "radix", "spline"],
                     help="CDF root (default: mlp for the host workload, rmi for uniform keys, auto otherwise)")
     ap.add_argument("--leaves", type=int, default=0, help="RMI leaves L (0: buckets / 16)")
+    ap.add_argument("--key-bytes", type=int, default=10,
+                    help="key length of the in-HBM workloads (10; 13..28 adds the long-key run pass)")
     ap.add_argument("--mlp-steps", type=int, default=0, help="Adam steps of the MLP fit (0: library default)")
     ap.add_argument("--accept-ratio", type=float, default=1.5,
                     help="MLP acceptance: largest sample bucket <= ratio * ideal")
@@ -99,16 +101,16 @@ def measured_traffic(workload: str, kernel: str):
     return None
 
 
-def cpu_baseline(wl, n_cpu):
+def cpu_baseline(wl, n_cpu, key_bytes=10):
     import numpy as np
 
     import datagen
     import oracle
 
-    recs = datagen.generate(datagen.spec(wl["kind"], seed=wl["seed"]), n_cpu)
+    recs = datagen.generate(datagen.spec(wl["kind"], seed=wl["seed"], key_bytes=key_bytes), n_cpu)
     oracle.lib()
     t0 = time.perf_counter()
-    perm = oracle.sort_order(recs)
+    perm = oracle.sort_order(recs, key_bytes=key_bytes)
     dt = time.perf_counter() - t0
     del perm
     return {"value": n_cpu / dt, "unit": "records/s", "cores": 1, "kind": "oracle",
@@ -339,13 +341,13 @@ def main():
     kind = {"rmi": elsar.RMI, "mlp": elsar.MLP, "auto": elsar.AUTO, "radix": elsar.RADIX,
             "spline": elsar.SPLINE}[args.model]
     params = elsar.fit_params(num_buckets=wl["buckets"], num_leaves=args.leaves, seed=wl["seed"], kind=kind,
-                              mlp_steps=args.mlp_steps, accept_ratio=args.accept_ratio)
+                              mlp_steps=args.mlp_steps, accept_ratio=args.accept_ratio, key_bytes=args.key_bytes)
 
     def buffers():
         # the records straight into HBM by the GPU generator (byte-identical to
         # the host generator), the output and the workspace
         d_in = torch.empty(n * RECORD_BYTES, dtype=torch.uint8, device="cuda")
-        datagen.generate_device(datagen.spec(wl["kind"], seed=wl["seed"]), d_in.data_ptr(), 0, n,
+        datagen.generate_device(datagen.spec(wl["kind"], seed=wl["seed"], key_bytes=args.key_bytes), d_in.data_ptr(), 0, n,
                                 torch.cuda.current_stream().cuda_stream)
         d_out = torch.empty_like(d_in)
         ws = torch.empty(elsar.sort_workspace_size(n, params), dtype=torch.uint8, device="cuda")
@@ -399,7 +401,8 @@ def main():
     achieved = alg_bytes / (dur_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.workload, dom), "alg_bytes": alg_bytes,
+                "traffic": measured_traffic(args.workload, dom) if args.key_bytes == 10 else None,
+                "alg_bytes": alg_bytes,
                 "duration_ms": round(dur_ms, 4)}
 
     result = {
@@ -415,7 +418,8 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": wl["desc"], "records": n, "record_bytes": RECORD_BYTES, "buckets": wl["buckets"],
+        "config": {"workload": wl["desc"] + ("" if args.key_bytes == 10 else f"; {args.key_bytes}-byte keys"),
+                   "records": n, "record_bytes": RECORD_BYTES, "key_bytes": args.key_bytes, "buckets": wl["buckets"],
                    "model": args.model, "model_used": "radix" if args.model == "radix" else {0: "rmi", 1: "mlp", 4: "spline"}[info.kind_used],
                    "leaves": info.num_leaves, "sample": info.sample_size,
                    "max_sample_bucket": info.max_sample_bucket, "ideal_sample_bucket": info.opt_sample_bucket,
@@ -439,7 +443,7 @@ def main():
     del d_in, d_out, ws
     torch.cuda.empty_cache()
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_records, n))
+        result["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_records, n), args.key_bytes)
     print(json.dumps(result), flush=True)
 
 

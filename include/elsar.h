@@ -16,7 +16,12 @@
  *    the library owns only elsar_model objects (and their device storage).
  *  - Record buffers are n * record_bytes bytes, 16-byte aligned; record i is at
  *    byte i * record_bytes.  record_bytes is a multiple of 4 in [40, 128];
- *    8 <= key_bytes <= 12 (the tuned shape is 100-byte records, 10-byte keys).
+ *    8 <= key_bytes <= 28 (the tuned shape is 100-byte records, 10-byte keys).
+ *    The bucket sorts order key bytes 0..11 and the input index; with a
+ *    longer key, each run of records with equal 12-byte prefixes is then
+ *    sorted stably by the remaining key bytes in a fix-up pass over the
+ *    output (elsar_sort, elsar_sort_buckets, elsar_sort_host).
+ *    elsar_sort_batch takes keys of at most 12 bytes (ELSAR_E_UNSUPPORTED).
  *  - n < 2^32 for every call that takes records on the device, and at most
  *    ELSAR_MAX_DEVICE_RECORDS for one in-HBM sort.
  *  - Work is enqueued on `stream` and runs asynchronously unless a call says

@@ -122,7 +122,7 @@ size_t fit_ws_bytes(uint64_t S) {
   return 2 * align_up((size_t)S * 8) + align_up(radix_u64_scratch_bytes(S)) + align_up(fit_scratch_bytes(S));
 }
 
-PartLayout part_layout(uint64_t n, uint32_t B, uint32_t R, uint32_t region_pct) {
+PartLayout part_layout(uint64_t n, uint32_t B, uint32_t R, uint32_t region_pct, uint32_t K) {
   PartLayout lay{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -147,7 +147,10 @@ PartLayout part_layout(uint64_t n, uint32_t B, uint32_t R, uint32_t region_pct) 
   lay.cap_slots = (n * 2 * region_pct + 99) / 100 + 18ull * B + 16;
   lay.total_slots = lay.cap_slots + n;
   lay.slot_bytes = slot_bytes_for(R);
-  lay.slots = take((size_t)lay.total_slots * lay.slot_bytes);
+  // after the bucket sorts the slot area is the scratch of the long-key fix-up
+  size_t slot_area = (size_t)lay.total_slots * lay.slot_bytes;
+  if (K > kSortKeyBytes) slot_area = std::max(slot_area, long_key_scratch_bytes(n, R));
+  lay.slots = take(slot_area);
   lay.bytes = off;
   return lay;
 }
@@ -231,7 +234,7 @@ elsar_status do_fit(elsar_model* m, const void* d_records, uint64_t n, void* d_w
 
 elsar_status do_partition(const elsar_model* m, const void* d_records, uint64_t n, void* d_part,
                           size_t part_bytes, uint64_t* d_offsets, hipStream_t st, PhaseMarks* pm) {
-  PartLayout lay = part_layout(n, m->B, m->p.record_bytes, m->p.region_pct);
+  PartLayout lay = part_layout(n, m->B, m->p.record_bytes, m->p.region_pct, m->p.key_bytes);
   if (lay.total_slots >= (1ull << 32)) return ELSAR_E_UNSUPPORTED;  // slot indices are 32-bit
   if (part_bytes < lay.bytes) return ELSAR_E_NO_MEMORY;
   uint8_t* part = static_cast<uint8_t*>(d_part);
@@ -247,13 +250,15 @@ elsar_status do_partition(const elsar_model* m, const void* d_records, uint64_t 
 
 elsar_status do_sort_buckets(const elsar_model* m, void* d_part, size_t part_bytes, uint64_t n,
                              const uint64_t* d_offsets, void* d_out, hipStream_t st, PhaseMarks* pm) {
-  PartLayout lay = part_layout(n, m->B, m->p.record_bytes, m->p.region_pct);
+  PartLayout lay = part_layout(n, m->B, m->p.record_bytes, m->p.region_pct, m->p.key_bytes);
   if (part_bytes < lay.bytes) return ELSAR_E_NO_MEMORY;
   uint8_t* part = static_cast<uint8_t*>(d_part);
   uint8_t* out = static_cast<uint8_t*>(d_out);
-  HIP_TRY(launch_bucket_sort_small(part, lay, m->B, d_offsets, m->p.record_bytes, m->p.key_bytes, out, st));
+  const uint32_t K = m->p.key_bytes, Ks = sort_key_bytes(K);
+  HIP_TRY(launch_bucket_sort_small(part, lay, m->B, d_offsets, m->p.record_bytes, Ks, out, st));
   if (pm) mark(*pm, 4, st);
-  HIP_TRY(launch_bucket_sort_large(part, lay, m->B, d_offsets, m->p.record_bytes, m->p.key_bytes, out, st));
+  HIP_TRY(launch_bucket_sort_large(part, lay, m->B, d_offsets, m->p.record_bytes, Ks, out, st));
+  HIP_TRY(launch_long_key_fixup(out, n, m->p.record_bytes, K, part + lay.slots, st));
   if (pm) mark(*pm, 5, st);
   return ELSAR_OK;
 }
@@ -272,7 +277,7 @@ SortLayout sort_layout(const elsar_fit_params& p, const Shape& sh, uint64_t n) {
   off += align_up(fit_ws_bytes(sh.S));
   sl.offsets = off;
   off += align_up(((size_t)sh.B + 1) * 8);
-  sl.lay = part_layout(n, sh.B, p.record_bytes, p.region_pct);
+  sl.lay = part_layout(n, sh.B, p.record_bytes, p.region_pct, p.key_bytes);
   sl.part = off;
   off += align_up(sl.lay.bytes);
   sl.bytes = off;
@@ -350,7 +355,7 @@ elsar_status elsar_sample_fit(elsar_model* m, const void* d_records, uint64_t n,
 elsar_status elsar_partition_size(const elsar_model* m, uint64_t n, size_t* part_bytes) {
   if (!m || !part_bytes) return ELSAR_E_INVALID_ARG;
   if (n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;
-  *part_bytes = part_layout(n, m->B, m->p.record_bytes, m->p.region_pct).bytes;
+  *part_bytes = part_layout(n, m->B, m->p.record_bytes, m->p.region_pct, m->p.key_bytes).bytes;
   return ELSAR_OK;
 }
 
@@ -680,6 +685,7 @@ elsar_status elsar_sort_batch_workspace_size(const elsar_job* h_jobs, uint32_t n
   if (!bytes || (njobs && !h_jobs)) return ELSAR_E_INVALID_ARG;
   elsar_status s = check_params(p);
   if (s != ELSAR_OK) return s;
+  if (p->key_bytes > kSortKeyBytes) return ELSAR_E_UNSUPPORTED;  // the small-job kernel sorts 12 key bytes
   BatchLayout bl;
   s = batch_layout(h_jobs, njobs, *p, &bl);
   if (s != ELSAR_OK) return s;
@@ -692,6 +698,7 @@ elsar_status elsar_sort_batch(const elsar_job* h_jobs, uint32_t njobs, const els
   if (njobs && !h_jobs) return ELSAR_E_INVALID_ARG;
   elsar_status s = check_params(p);
   if (s != ELSAR_OK) return s;
+  if (p->key_bytes > kSortKeyBytes) return ELSAR_E_UNSUPPORTED;  // the small-job kernel sorts 12 key bytes
   if (njobs == 0) return ELSAR_OK;
   if (!d_ws || !aligned16(d_ws)) return ELSAR_E_INVALID_ARG;
   BatchLayout bl;
@@ -743,7 +750,7 @@ constexpr uint64_t kDefaultChunkRecords = 40000000ull;  // 4 GB of 100-byte reco
 
 // Partition buffer of one pass: P records in exact regions for up to B
 // buckets, no spill area.
-PartLayout pass_layout(uint64_t P, uint32_t B, uint32_t R) {
+PartLayout pass_layout(uint64_t P, uint32_t B, uint32_t R, uint32_t K) {
   PartLayout lay{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -765,7 +772,9 @@ PartLayout pass_layout(uint64_t P, uint32_t B, uint32_t R) {
   lay.cap_slots = P;
   lay.total_slots = P;
   lay.slot_bytes = slot_bytes_for(R);
-  lay.slots = take((size_t)P * lay.slot_bytes);
+  size_t slot_area = (size_t)P * lay.slot_bytes;
+  if (K > kSortKeyBytes) slot_area = std::max(slot_area, long_key_scratch_bytes(P, R));
+  lay.slots = take(slot_area);
   lay.bytes = off;
   return lay;
 }
@@ -794,7 +803,7 @@ HostLayout host_layout(const elsar_fit_params& q, uint64_t n, uint64_t C, uint64
   h.offsets = take(((size_t)h.sh.B + 1) * 8);
   h.chunk[0] = take((size_t)h.C * q.record_bytes);
   h.chunk[1] = take((size_t)h.C * q.record_bytes);
-  h.lay = pass_layout(h.P, h.sh.B, q.record_bytes);
+  h.lay = pass_layout(h.P, h.sh.B, q.record_bytes, q.key_bytes);
   h.part = take(h.lay.bytes);
   h.stage = take((size_t)h.P * q.record_bytes);
   h.bytes = off;
@@ -970,8 +979,9 @@ elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, const el
     if (ph.spill_count != 0) return ELSAR_E_HIP;
     HIP_TRY(launch_scan_counts(part, hl.lay, nb, offsets, stream));
     if (stage_busy) HIP_TRY(hipStreamWaitEvent(stream, ss.copied, 0));  // the previous pass's output is out
-    HIP_TRY(launch_bucket_sort_small(part, hl.lay, nb, offsets, R, q.key_bytes, stage, stream));
-    HIP_TRY(launch_bucket_sort_large(part, hl.lay, nb, offsets, R, q.key_bytes, stage, stream));
+    HIP_TRY(launch_bucket_sort_small(part, hl.lay, nb, offsets, R, sort_key_bytes(q.key_bytes), stage, stream));
+    HIP_TRY(launch_bucket_sort_large(part, hl.lay, nb, offsets, R, sort_key_bytes(q.key_bytes), stage, stream));
+    HIP_TRY(launch_long_key_fixup(stage, ps.total, R, q.key_bytes, part + hl.lay.slots, stream));
     HIP_TRY(hipEventRecord(ss.sorted, stream));
     HIP_TRY(hipStreamWaitEvent(ss.d2h, ss.sorted, 0));
     HIP_TRY(hipMemcpyAsync(out + ps.first * R, stage, ps.total * R, hipMemcpyDeviceToHost, ss.d2h));

@@ -15,7 +15,8 @@ namespace elsar {
 // the first 12 record bytes, so one load gives the whole sort key.  The index
 // makes the in-bucket order independent of the order in which the atomics
 // handed out slots.
-constexpr uint32_t kMaxKeyBytes = 12;   // the LDS sort entry holds key + 4-byte index
+constexpr uint32_t kMaxKeyBytes = 28;   // bytes 12.. of a longer key order runs of equal 12-byte prefixes
+constexpr uint32_t kSortKeyBytes = 12;  // the bucket sorts' entry holds key bytes 0..11 + the 4-byte index
 constexpr uint32_t kMinKeyBytes = 8;    // the code reads the first 8 key bytes
 constexpr uint32_t kSmallCap = 2048;    // largest bucket sorted by the small LDS kernel
 constexpr uint32_t kMidCap = 6144;      // largest bucket sorted by the large LDS kernel
@@ -292,6 +293,13 @@ void place_mlp_state(MlpState* s, void* base, uint32_t L, uint32_t B);
 // MLP training on the sorted sample (initial weights, Adam steps).
 hipError_t launch_mlp_train(const uint64_t* sorted_codes, uint64_t S, uint64_t seed, uint32_t steps, float lr,
                             const MlpState& ms, hipStream_t st);
+// Key bytes the bucket sorts order by; a longer key is finished by the run fix-up.
+inline uint32_t sort_key_bytes(uint32_t K) { return K < kSortKeyBytes ? K : kSortKeyBytes; }
+// Keys longer than kSortKeyBytes: device scratch of the run fix-up for n
+// records, and the fix-up itself on n sorted records at `out` (in place).
+size_t long_key_scratch_bytes(uint64_t n, uint32_t rec_bytes);
+hipError_t launch_long_key_fixup(uint8_t* out, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint8_t* scratch,
+                                 hipStream_t st);
 // Equi-depth leaves, their splines and boundaries, the spline root's knots,
 // and the sample histogram under these leaves.
 hipError_t launch_equi_depth_leaves(const uint64_t* sorted_codes, uint64_t S, uint32_t L, uint32_t B,

@@ -575,19 +575,102 @@ __device__ __forceinline__ uint4 get_key(const uint32_t* buf, uint32_t k) {
   return make_uint4(p[0], p[1], p[2], p[3]);
 }
 
+// LDS of the stable LSD passes over 20-byte entries.
+struct LsdShared {
+  uint32_t wc[kBigWaves][256];  // per wave and digit: count, then output offset
+  uint32_t run[256];            // per digit: output position of the tile's first entry
+  uint32_t hist[256];
+  uint32_t tot[4];
+};
+
+// Stable LSD radix passes, least significant byte first, over the composite
+// bytes set in `vary` (positions below nb) of n 20-byte entries (4 big-endian
+// key words + a payload word), alternating between cur and nxt; one block of
+// kBigThreads.  Returns the buffer that holds the sorted entries.
+__device__ uint32_t* lsd_entries(uint32_t* cur, uint32_t* nxt, uint32_t n, uint32_t vary, uint32_t nb,
+                                 LsdShared& sh) {
+  const uint32_t w = threadIdx.x >> 6;
+  for (int pbyte = (int)nb - 1; pbyte >= 0; --pbyte) {
+    if (!((vary >> pbyte) & 1u)) continue;
+    if (threadIdx.x < 256) sh.hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < n; p += kBigThreads) atomicAdd(&sh.hist[digit_of(get_key(cur, p), pbyte)], 1u);
+    __syncthreads();
+    if (threadIdx.x < 256) {  // exclusive scan of hist -> run
+      uint32_t v = sh.hist[threadIdx.x], x = v;
+      for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off);
+        if (lane_id() >= (uint32_t)off) x += y;
+      }
+      if (lane_id() == 63) sh.tot[threadIdx.x >> 6] = x;
+      __syncthreads();
+      uint32_t add = 0;
+      for (uint32_t i = 0; i < (threadIdx.x >> 6); ++i) add += sh.tot[i];
+      sh.run[threadIdx.x] = x - v + add;
+    } else {
+      __syncthreads();
+    }
+    __syncthreads();
+    for (uint32_t t0 = 0; t0 < n; t0 += kBigTile) {
+      for (uint32_t i = threadIdx.x; i < kBigWaves * 256; i += kBigThreads) (&sh.wc[0][0])[i] = 0;
+      __syncthreads();
+      uint32_t dg[kBigRounds], lc[kBigRounds];
+#pragma unroll
+      for (uint32_t r = 0; r < kBigRounds; ++r) {
+        uint32_t i = t0 + w * (kBigRounds * 64) + r * 64 + lane_id();
+        bool valid = i < n;
+        uint32_t d = valid ? digit_of(get_key(cur, i), pbyte) : 0u;
+        uint64_t peers = match_digit8(d, valid);
+        uint32_t rank = __popcll(peers & lanemask_lt());
+        uint32_t prev = valid ? sh.wc[w][d] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0) sh.wc[w][d] = prev + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        dg[r] = d;
+        lc[r] = prev + rank;
+      }
+      __syncthreads();
+      // per digit: tile count and wave offsets; then global position = run + offset
+      if (threadIdx.x < 256) {
+        uint32_t d = threadIdx.x, s = 0;
+        for (uint32_t ww = 0; ww < kBigWaves; ++ww) {
+          uint32_t c = sh.wc[ww][d];
+          sh.wc[ww][d] = s + sh.run[d];
+          s += c;
+        }
+        sh.hist[d] = s;  // this tile's count of digit d
+      }
+      __syncthreads();
+#pragma unroll
+      for (uint32_t r = 0; r < kBigRounds; ++r) {
+        uint32_t i = t0 + w * (kBigRounds * 64) + r * 64 + lane_id();
+        if (i < n) {
+          const uint32_t* src = cur + 5ull * i;
+          uint32_t dpos = sh.wc[w][dg[r]] + lc[r];
+          uint32_t* dst = nxt + 5ull * dpos;
+          dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2]; dst[3] = src[3]; dst[4] = src[4];
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x < 256) sh.run[threadIdx.x] += sh.hist[threadIdx.x];
+      __syncthreads();
+    }
+    uint32_t* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  return cur;
+}
+
 __global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
     const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
     uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n) {
-  __shared__ uint32_t wc[kBigWaves][256];
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t hist[256];
+  __shared__ LsdShared lsd;
   __shared__ uint4 sh_or[kBigWaves], sh_and[kBigWaves];
-  __shared__ uint32_t tot[4];
   __shared__ uint32_t chunk_slot[kBigTile];
   const uint32_t W = slot_bytes_for(RW * 4) / 4;  // slot stride in dwords
-  const uint32_t w = threadIdx.x >> 6;
   const uint32_t nitems = *list_n;
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const uint32_t j = list[it];
@@ -620,75 +703,7 @@ __global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
     }
     __syncthreads();
     // 2. stable LSD passes through global memory
-    for (int pbyte = (int)nb - 1; pbyte >= 0; --pbyte) {
-      if (!((vary >> pbyte) & 1u)) continue;
-      if (threadIdx.x < 256) hist[threadIdx.x] = 0;
-      __syncthreads();
-      for (uint32_t p = threadIdx.x; p < br.n; p += kBigThreads) atomicAdd(&hist[digit_of(get_key(cur, p), pbyte)], 1u);
-      __syncthreads();
-      if (threadIdx.x < 256) {  // exclusive scan of hist -> run
-        uint32_t v = hist[threadIdx.x], x = v;
-        for (int off = 1; off < 64; off <<= 1) {
-          uint32_t y = __shfl_up(x, off);
-          if (lane_id() >= (uint32_t)off) x += y;
-        }
-        if (lane_id() == 63) tot[threadIdx.x >> 6] = x;
-        __syncthreads();
-        uint32_t add = 0;
-        for (uint32_t i = 0; i < (threadIdx.x >> 6); ++i) add += tot[i];
-        run[threadIdx.x] = x - v + add;
-      } else {
-        __syncthreads();
-      }
-      __syncthreads();
-      for (uint32_t t0 = 0; t0 < br.n; t0 += kBigTile) {
-        for (uint32_t i = threadIdx.x; i < kBigWaves * 256; i += kBigThreads) (&wc[0][0])[i] = 0;
-        __syncthreads();
-        uint32_t dg[kBigRounds], lc[kBigRounds];
-#pragma unroll
-        for (uint32_t r = 0; r < kBigRounds; ++r) {
-          uint32_t i = t0 + w * (kBigRounds * 64) + r * 64 + lane_id();
-          bool valid = i < br.n;
-          uint32_t d = valid ? digit_of(get_key(cur, i), pbyte) : 0u;
-          uint64_t peers = match_digit8(d, valid);
-          uint32_t rank = __popcll(peers & lanemask_lt());
-          uint32_t prev = valid ? wc[w][d] : 0u;
-          __builtin_amdgcn_wave_barrier();
-          if (valid && rank == 0) wc[w][d] = prev + (uint32_t)__popcll(peers);
-          __builtin_amdgcn_wave_barrier();
-          dg[r] = d;
-          lc[r] = prev + rank;
-        }
-        __syncthreads();
-        // per digit: tile count and wave offsets; then global position = run + offset
-        if (threadIdx.x < 256) {
-          uint32_t d = threadIdx.x, s = 0;
-          for (uint32_t ww = 0; ww < kBigWaves; ++ww) {
-            uint32_t c = wc[ww][d];
-            wc[ww][d] = s + run[d];
-            s += c;
-          }
-          hist[d] = s;  // this tile's count of digit d
-        }
-        __syncthreads();
-#pragma unroll
-        for (uint32_t r = 0; r < kBigRounds; ++r) {
-          uint32_t i = t0 + w * (kBigRounds * 64) + r * 64 + lane_id();
-          if (i < br.n) {
-            const uint32_t* src = cur + 5ull * i;
-            uint32_t dpos = wc[w][dg[r]] + lc[r];
-            uint32_t* dst = nxt + 5ull * dpos;
-            dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2]; dst[3] = src[3]; dst[4] = src[4];
-          }
-        }
-        __syncthreads();
-        if (threadIdx.x < 256) run[threadIdx.x] += hist[threadIdx.x];
-        __syncthreads();
-      }
-      uint32_t* t = cur;
-      cur = nxt;
-      nxt = t;
-    }
+    cur = lsd_entries(cur, nxt, br.n, vary, nb, lsd);
     // 3. copy records in sorted order; entry k sits at or after byte R*(k+1)
     //    of the range, so a chunk's entries are read before its records land.
     for (uint32_t k0 = 0; k0 < br.n; k0 += kBigTile) {
@@ -1122,6 +1137,141 @@ hipError_t launch_tiny_jobs(const TinyJob* d_jobs, uint32_t njobs, uint32_t rec_
   if (njobs == 0) return hipSuccess;
   tiny_jobs_kernel<<<njobs < 4096 ? njobs : 4096, kSmThreads, 0, st>>>(d_jobs, njobs, rec_bytes / 4, key_bytes,
                                                                        staging);
+  return hipGetLastError();
+}
+
+// ------------------------------------------- keys longer than 12 bytes --
+// The bucket sorts order records by (key bytes 0..11, input index).  With a
+// longer key, records whose first 12 key bytes agree therefore sit next to
+// each other in input order, and each such run only needs a stable sort by
+// key bytes 12..K-1.  Equal 12-byte prefixes have equal 8-byte codes, so a run
+// never crosses a bucket.
+
+__device__ __forceinline__ bool same_prefix12(const uint32_t* a, const uint32_t* b) {
+  return a[0] == b[0] && a[1] == b[1] && a[2] == b[2];
+}
+
+// Key bytes 12..K-1 of a record as four big-endian words, zero past the key
+// (the record is dword-aligned and at least K bytes long, so every dword
+// read holds a key byte and lies inside the record).
+__device__ __forceinline__ uint4 key_suffix(const uint32_t* rec, uint32_t K) {
+  uint32_t w[4];
+#pragma unroll
+  for (uint32_t q = 0; q < 4; ++q) {
+    const uint32_t b0 = 12 + 4 * q;
+    uint32_t v = b0 < K ? __builtin_bswap32(rec[3 + q]) : 0u;
+    if (b0 < K && K < b0 + 4) v &= ~0u << (8 * (b0 + 4 - K));
+    w[q] = v;
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__device__ __forceinline__ bool suffix_less(const uint4& a, const uint4& b) {
+  if (a.x != b.x) return a.x < b.x;
+  if (a.y != b.y) return a.y < b.y;
+  if (a.z != b.z) return a.z < b.z;
+  return a.w < b.w;
+}
+
+// The first record of every run of two or more equal 12-byte prefixes.
+__global__ __launch_bounds__(256) void long_runs_kernel(const uint32_t* __restrict__ out, uint64_t n, uint32_t RW,
+                                                        uint32_t* __restrict__ list, uint32_t* __restrict__ list_n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i + 1 >= n) return;
+  const uint32_t* r = out + i * RW;
+  if (!same_prefix12(r, r + RW)) return;
+  if (i > 0 && same_prefix12(r - RW, r)) return;
+  list[atomicAdd(list_n, 1u)] = (uint32_t)i;
+}
+
+// One block per run: find its end, leave it if it is already in suffix order
+// (duplicates of one key are), else sort {suffix, position} entries stably by
+// the varying suffix bytes and rewrite the run's records from a staged copy.
+// ea, eb: 20-byte entries of run positions [s, s+len); stage: records.
+__global__ __launch_bounds__(kBigThreads) void long_run_sort_kernel(
+    uint32_t* __restrict__ out, uint64_t n, uint32_t RW, uint32_t K, const uint32_t* __restrict__ list,
+    const uint32_t* __restrict__ list_n, uint32_t* __restrict__ ea, uint32_t* __restrict__ eb,
+    uint32_t* __restrict__ stage) {
+  __shared__ LsdShared lsd;
+  __shared__ uint4 sh_or[kBigWaves], sh_and[kBigWaves];
+  __shared__ uint32_t sh_len, sh_unsorted;
+  const uint32_t nruns = *list_n;
+  for (uint32_t it = blockIdx.x; it < nruns; it += gridDim.x) {
+    const uint64_t s = list[it];
+    uint32_t* rs = out + s * RW;
+    // 1. the run's length: the first later record with another prefix
+    if (threadIdx.x == 0) sh_len = 0xFFFFFFFFu;
+    __syncthreads();
+    for (uint64_t c0 = s + 1;; c0 += kBigThreads) {
+      const uint64_t i = c0 + threadIdx.x;
+      if (i < n && !same_prefix12(rs, out + i * RW)) atomicMin(&sh_len, (uint32_t)(i - s));
+      __syncthreads();
+      const uint32_t found = sh_len;
+      __syncthreads();
+      if (found != 0xFFFFFFFFu || c0 + kBigThreads >= n) break;
+    }
+    const uint32_t len = sh_len != 0xFFFFFFFFu ? sh_len : (uint32_t)(n - s);
+    // 2. already in order?
+    if (threadIdx.x == 0) sh_unsorted = 0;
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k + 1 < len; k += kBigThreads)
+      if (suffix_less(key_suffix(rs + (uint64_t)(k + 1) * RW, K), key_suffix(rs + (uint64_t)k * RW, K)))
+        sh_unsorted = 1;
+    __syncthreads();
+    const bool unsorted = sh_unsorted != 0;
+    __syncthreads();
+    if (!unsorted) continue;
+    // 3. entries and the suffix bytes that vary
+    uint32_t* A = ea + 5 * s;
+    uint32_t* Bf = eb + 5 * s;
+    uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
+    for (uint32_t k = threadIdx.x; k < len; k += kBigThreads) {
+      const uint4 c = key_suffix(rs + (uint64_t)k * RW, K);
+      put_entry(A, k, c, k);
+      o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
+      a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+    }
+    const uint32_t vary = varying_bytes<kBigThreads>(o, a, sh_or, sh_and);  // syncs
+    // 4. stable LSD over them: equal suffixes keep their (input) order
+    const uint32_t* res = lsd_entries(A, Bf, len, vary, K - kSortKeyBytes, lsd);
+    // 5. the run's records in suffix order, through the stage
+    uint32_t* st = stage + s * RW;
+    const uint64_t total = (uint64_t)len * RW;
+    for (uint64_t f = threadIdx.x; f < total; f += kBigThreads) st[f] = rs[f];
+    __syncthreads();
+    for (uint64_t f = threadIdx.x; f < total; f += kBigThreads) {
+      const uint64_t k = f / RW, d = f - k * RW;
+      rs[f] = st[(uint64_t)res[5 * k + 4] * RW + d];
+    }
+    __syncthreads();
+  }
+}
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t long_key_scratch_bytes(uint64_t n, uint32_t rec_bytes) {
+  return al256(4) + al256((n / 2 + 1) * 4) + 2 * al256((size_t)n * 20) + al256((size_t)n * rec_bytes);
+}
+
+hipError_t launch_long_key_fixup(uint8_t* out, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint8_t* scratch,
+                                 hipStream_t st) {
+  if (key_bytes <= kSortKeyBytes || n < 2) return hipSuccess;
+  uint8_t* p = scratch;
+  uint32_t* list_n = reinterpret_cast<uint32_t*>(p);
+  p += al256(4);
+  uint32_t* list = reinterpret_cast<uint32_t*>(p);
+  p += al256((n / 2 + 1) * 4);
+  uint32_t* ea = reinterpret_cast<uint32_t*>(p);
+  p += al256((size_t)n * 20);
+  uint32_t* eb = reinterpret_cast<uint32_t*>(p);
+  p += al256((size_t)n * 20);
+  uint32_t* stage = reinterpret_cast<uint32_t*>(p);
+  hipError_t err = launch_fill_u32(list_n, 1, 0u, st);
+  if (err != hipSuccess) return err;
+  const uint32_t RW = rec_bytes / 4;
+  uint32_t* o = reinterpret_cast<uint32_t*>(out);
+  long_runs_kernel<<<(uint32_t)((n + 255) / 256), 256, 0, st>>>(o, n, RW, list, list_n);
+  long_run_sort_kernel<<<256, kBigThreads, 0, st>>>(o, n, RW, key_bytes, list, list_n, ea, eb, stage);
   return hipGetLastError();
 }
 

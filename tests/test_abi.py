@@ -49,8 +49,20 @@ def test_argument_checks_return_before_any_work(elsar):
     assert lib.elsar_sort_workspace_size(ctypes.byref(p), 1000, ctypes.byref(sz)) == elsar.OK and sz.value > 0
     bad = elsar.fit_params(record_bytes=102)
     assert lib.elsar_sort_workspace_size(ctypes.byref(bad), 10, ctypes.byref(sz)) == elsar.E_UNSUPPORTED
-    bad = elsar.fit_params(key_bytes=13)
+    bad = elsar.fit_params(key_bytes=29)
     assert lib.elsar_sort_workspace_size(ctypes.byref(bad), 10, ctypes.byref(sz)) == elsar.E_UNSUPPORTED
+    bad = elsar.fit_params(key_bytes=7)
+    assert lib.elsar_sort_workspace_size(ctypes.byref(bad), 10, ctypes.byref(sz)) == elsar.E_UNSUPPORTED
+    # keys of 13..28 bytes take the run fix-up, whose scratch the workspace includes
+    long_k = elsar.fit_params(key_bytes=28, region_pct=1)
+    assert lib.elsar_sort_workspace_size(ctypes.byref(long_k), 1000, ctypes.byref(sz)) == elsar.OK
+    assert sz.value >= 1000 * (100 + 40)
+    # the batch's small-job kernel sorts at most 12 key bytes
+    job = elsar.Job()
+    job.n = 10
+    long16 = elsar.fit_params(key_bytes=16)
+    assert lib.elsar_sort_batch_workspace_size(ctypes.byref(job), 1, ctypes.byref(long16),
+                                               ctypes.byref(sz)) == elsar.E_UNSUPPORTED
     bad = elsar.fit_params(record_bytes=36, key_bytes=10)
     assert lib.elsar_sort_workspace_size(ctypes.byref(bad), 10, ctypes.byref(sz)) == elsar.E_UNSUPPORTED
     bad = elsar.fit_params(num_buckets=(1 << 21) + 1)
