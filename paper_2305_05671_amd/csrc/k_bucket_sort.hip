@@ -1141,7 +1141,8 @@ hipError_t launch_tiny_jobs(const TinyJob* d_jobs, uint32_t njobs, uint32_t rec_
 }
 
 // ------------------------------------------- keys longer than 12 bytes --
-// The bucket sorts order records by (key bytes 0..11, input index).  With a
+// Section 4: key bytes past the encoded prefix are ordered by a last-mile
+// step.  The bucket sorts order records by (key bytes 0..11, input index).  With a
 // longer key, records whose first 12 key bytes agree therefore sit next to
 // each other in input order, and each such run only needs a stable sort by
 // key bytes 12..K-1.  Equal 12-byte prefixes have equal 8-byte codes, so a run
