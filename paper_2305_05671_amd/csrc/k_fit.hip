@@ -324,15 +324,26 @@ hipError_t launch_fit_rmi(const uint64_t* e, uint64_t S, uint64_t n, uint32_t L,
 // ceil(f * max(n * (h_j + 2 sqrt(h_j)) / S, n / B)) + 16 slots for bucket j
 // (f = region_pct/100, default 1.25), rounded up to even; records beyond
 // continue in the spill.
+// Sample keys per bucket.  The sample is usually sorted, so neighbouring lanes
+// share buckets: one atomic per run of equal buckets within the wave.
 __global__ __launch_bounds__(256) void sample_bucket_hist_kernel(const uint64_t* __restrict__ e, uint64_t S,
                                                                  const ModelHeader* __restrict__ hdr,
                                                                  const Leaf* __restrict__ leaves,
                                                                  uint32_t* __restrict__ hist) {
-  uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  uint64_t c = e[s];
-  uint32_t j = rmi_leaf(hdr->a0, hdr->a1, hdr->L, c);
-  atomicAdd(&hist[leaf_bucket(load_leaf(leaves, j), c)], 1u);
+  const uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const bool in = s < S;
+  const uint64_t c = e[in ? s : S - 1];
+  const uint32_t b = leaf_bucket(load_leaf(leaves, rmi_leaf(hdr->a0, hdr->a1, hdr->L, c)), c);
+  const uint32_t l = __lane_id();
+  const uint32_t bl = __shfl_up(b, 1), br = __shfl_down(b, 1);
+  const bool start = in && (l == 0 || bl != b);
+  const bool last = in && (l == 63 || br != b || s + 1 == S);
+  const uint64_t starts = __ballot(start);
+  if (last) {
+    const uint64_t below = starts & (l == 63 ? ~0ull : ((2ull << l) - 1));  // starts at lanes <= l
+    const uint32_t first_lane = 63u - (uint32_t)__clzll((long long)below);
+    atomicAdd(&hist[b], l + 1 - first_lane);
+  }
 }
 
 // A plain fill: it records as a kernel node under graph capture, which a
@@ -512,11 +523,15 @@ hipError_t launch_batch_fit(const FitJob* d_jobs, uint32_t njobs, uint32_t rec_b
   return hipGetLastError();
 }
 
-// One block; rounds of 1024 x 8 buckets, each thread 8 consecutive buckets
-// (coalesced loads, no dependent chains).
 constexpr uint32_t kScanThreads = 1024;
-constexpr uint32_t kScanPer = 8;
 
+// Region sizes and starts, in one block: each thread a contiguous segment of
+// P buckets (P a multiple of 16), read in chunks of 16 with all their 16-byte
+// loads issued before any is used.  Pass 1 sums the segment's sizes, one block
+// scan gives the segment's start, pass 2 recomputes the sizes and writes
+// sizes, starts and cleared fill counters.  A region past the reserved slot
+// count cannot happen by construction; such a bucket would get no region and
+// all its records would spill.
 __global__ __launch_bounds__(kScanThreads) void capacity_kernel(const uint32_t* __restrict__ hist, uint64_t S,
                                                                 uint64_t n, uint32_t B, double scale,
                                                                 uint32_t* __restrict__ caps,
@@ -525,40 +540,53 @@ __global__ __launch_bounds__(kScanThreads) void capacity_kernel(const uint32_t* 
                                                                 PartHeader* __restrict__ ph, uint64_t cap_slots) {
   __shared__ uint64_t sh[kScanThreads / 64 + 1];
   const double ideal = (double)n / (double)B;
-  uint64_t carry = 0;
-  for (uint32_t base = 0; base < B; base += kScanThreads * kScanPer) {
-    uint32_t c[kScanPer];
-    uint64_t s = 0;
+  const uint32_t P = ((B + kScanThreads - 1) / kScanThreads + 15) & ~15u;
+  const uint32_t j0 = threadIdx.x * P, j1 = j0 + P < B ? j0 + P : B;
+  // sizes of the chunk at j (zero past the segment)
+  auto sizes16 = [&](uint32_t j, uint32_t c[16]) {
+    uint32_t h[16];
+    if (j + 16 <= j1) {
 #pragma unroll
-    for (uint32_t i = 0; i < kScanPer; ++i) {
-      uint32_t j = base + threadIdx.x * kScanPer + i;
-      c[i] = 0;
-      if (j < B) {
-        // h sample keys estimate the bucket's mass as h / S with a standard
-        // deviation of about sqrt(h) / S: the region covers two of them
-        const double h = (double)hist[j];
-        double expect = (h + 2.0 * sqrt(h)) * (double)n / (double)S;
-        double m = expect > ideal ? expect : ideal;
-        c[i] = ((uint32_t)ceil(scale * m) + 16u + 1u) & ~1u;
+      for (uint32_t q = 0; q < 4; ++q) {
+        const uint4 x = *reinterpret_cast<const uint4*>(hist + j + 4 * q);
+        h[4 * q] = x.x; h[4 * q + 1] = x.y; h[4 * q + 2] = x.z; h[4 * q + 3] = x.w;
       }
-      s += c[i];
-    }
-    uint64_t tot;
-    uint64_t run = carry + block_exclusive_scan<uint64_t, kScanThreads>(s, sh, &tot);
+    } else {
 #pragma unroll
-    for (uint32_t i = 0; i < kScanPer; ++i) {
-      uint32_t j = base + threadIdx.x * kScanPer + i;
-      if (j < B) {
-        // regions past the reserved slot count cannot happen by construction; such a
-        // bucket gets no region and its records all spill
-        bool fits = run + c[i] <= cap_slots;
-        caps[j] = fits ? c[i] : 0u;
-        rstart[j] = fits ? (uint32_t)run : 0u;
-        counts[j] = 0;
-      }
-      run += c[i];
+      for (uint32_t q = 0; q < 16; ++q) h[q] = j + q < j1 ? hist[j + q] : 0u;
     }
-    carry += tot;
+#pragma unroll
+    for (uint32_t q = 0; q < 16; ++q) {
+      // h sample keys estimate the bucket's mass as h / S with a standard
+      // deviation of about sqrt(h) / S: the region covers two of them
+      const double hd = (double)h[q];
+      const double expect = (hd + 2.0 * sqrt(hd)) * (double)n / (double)S;
+      const double m = expect > ideal ? expect : ideal;
+      c[q] = j + q < j1 ? ((uint32_t)ceil(scale * m) + 16u + 1u) & ~1u : 0u;
+    }
+  };
+  uint64_t s = 0;
+  for (uint32_t j = j0; j < j1; j += 16) {
+    uint32_t c[16];
+    sizes16(j, c);
+#pragma unroll
+    for (uint32_t q = 0; q < 16; ++q) s += c[q];
+  }
+  uint64_t tot;
+  uint64_t run = block_exclusive_scan<uint64_t, kScanThreads>(s, sh, &tot);
+  for (uint32_t j = j0; j < j1; j += 16) {
+    uint32_t c[16];
+    sizes16(j, c);
+#pragma unroll
+    for (uint32_t q = 0; q < 16; ++q) {
+      if (j + q < j1) {
+        const bool fits = run + c[q] <= cap_slots;
+        caps[j + q] = fits ? c[q] : 0u;
+        rstart[j + q] = fits ? (uint32_t)run : 0u;
+        counts[j + q] = 0;
+      }
+      run += c[q];
+    }
   }
   if (threadIdx.x == 0) {
     ph->n = n;
@@ -575,10 +603,11 @@ __global__ __launch_bounds__(kScanThreads) void capacity_kernel(const uint32_t* 
 
 hipError_t launch_capacities(const uint32_t* hist, uint64_t S, uint64_t n, uint32_t B, uint32_t region_pct,
                              uint8_t* part, const PartLayout& lay, hipStream_t st) {
-  capacity_kernel<<<1, kScanThreads, 0, st>>>(hist, S, n, B, region_pct / 100.0, reinterpret_cast<uint32_t*>(part + lay.caps),
-                                      reinterpret_cast<uint32_t*>(part + lay.rstart),
-                                      reinterpret_cast<uint32_t*>(part + lay.counts),
-                                      reinterpret_cast<PartHeader*>(part + lay.header), lay.cap_slots);
+  capacity_kernel<<<1, kScanThreads, 0, st>>>(hist, S, n, B, region_pct / 100.0,
+                                              reinterpret_cast<uint32_t*>(part + lay.caps),
+                                              reinterpret_cast<uint32_t*>(part + lay.rstart),
+                                              reinterpret_cast<uint32_t*>(part + lay.counts),
+                                              reinterpret_cast<PartHeader*>(part + lay.header), lay.cap_slots);
   return hipGetLastError();
 }
 

@@ -587,28 +587,38 @@ __global__ __launch_bounds__(256) void auto_gate_kernel(const uint32_t* __restri
 // (automatic): the linear root if it passed the gate, else the spline root.
 // kind 4 (spline): the spline root.  The chosen root's sample histogram is
 // copied to hist_used.
-__global__ __launch_bounds__(256) void decide_root_kernel(const uint32_t* __restrict__ hist_rmi,
-                                                          const uint32_t* __restrict__ hist_mlp, uint32_t B,
-                                                          uint64_t S, float accept_ratio, uint32_t kind,
-                                                          ModelHeader* __restrict__ hdr,
-                                                          uint32_t* __restrict__ hist_used) {
-  __shared__ uint32_t mr[256], mm[256];
+constexpr uint32_t kDecideThreads = 1024;
+
+__global__ __launch_bounds__(kDecideThreads) void decide_root_kernel(const uint32_t* __restrict__ hist_rmi,
+                                                                     const uint32_t* __restrict__ hist_mlp, uint32_t B,
+                                                                     uint64_t S, float accept_ratio, uint32_t kind,
+                                                                     ModelHeader* __restrict__ hdr,
+                                                                     uint32_t* __restrict__ hist_used) {
+  __shared__ uint32_t mr[kDecideThreads / 64], mm[kDecideThreads / 64];
   __shared__ uint32_t use_mlp;
   uint32_t a = 0, b = 0;
-  for (uint32_t j = threadIdx.x; j < B; j += 256) {
+#pragma unroll 4
+  for (uint32_t j = threadIdx.x; j < B; j += kDecideThreads) {
     a = hist_rmi[j] > a ? hist_rmi[j] : a;
     if (hist_mlp) b = hist_mlp[j] > b ? hist_mlp[j] : b;
   }
-  mr[threadIdx.x] = a;
-  mm[threadIdx.x] = b;
-  __syncthreads();
-  for (uint32_t off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) {
-      if (mr[threadIdx.x + off] > mr[threadIdx.x]) mr[threadIdx.x] = mr[threadIdx.x + off];
-      if (mm[threadIdx.x + off] > mm[threadIdx.x]) mm[threadIdx.x] = mm[threadIdx.x + off];
-    }
-    __syncthreads();
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t x = __shfl_xor(a, off), y = __shfl_xor(b, off);
+    a = x > a ? x : a;
+    b = y > b ? y : b;
   }
+  if (__lane_id() == 0) {
+    mr[threadIdx.x >> 6] = a;
+    mm[threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t w = 1; w < kDecideThreads / 64; ++w) {
+      mr[0] = mr[w] > mr[0] ? mr[w] : mr[0];
+      mm[0] = mm[w] > mm[0] ? mm[w] : mm[0];
+    }
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t ideal = (uint32_t)((S + B - 1) / B);
     if (hist_mlp && hdr->max_sample_run > ideal) ideal = hdr->max_sample_run;
@@ -632,7 +642,7 @@ __global__ __launch_bounds__(256) void decide_root_kernel(const uint32_t* __rest
   }
   __syncthreads();
   if (use_mlp)
-    for (uint32_t j = threadIdx.x; j < B; j += 256) hist_used[j] = hist_mlp[j];
+    for (uint32_t j = threadIdx.x; j < B; j += kDecideThreads) hist_used[j] = hist_mlp[j];
 }
 
 // ------------------------------------------------------------------- host --
@@ -693,7 +703,7 @@ hipError_t launch_auto_gate(const uint32_t* hist_rmi, uint32_t B, uint64_t S, fl
 hipError_t launch_decide_root(const uint32_t* hist_rmi, const MlpState* ms, uint32_t B, uint64_t S,
                               float accept_ratio, uint32_t kind, ModelHeader* hdr, uint32_t* hist_used,
                               hipStream_t st) {
-  decide_root_kernel<<<1, 256, 0, st>>>(hist_rmi, ms ? ms->hist : nullptr, B, S, accept_ratio, kind, hdr,
+  decide_root_kernel<<<1, kDecideThreads, 0, st>>>(hist_rmi, ms ? ms->hist : nullptr, B, S, accept_ratio, kind, hdr,
                                         hist_used);
   return hipGetLastError();
 }

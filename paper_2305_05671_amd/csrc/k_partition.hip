@@ -398,7 +398,6 @@ hipError_t launch_exact_regions(const uint32_t* counts_all, uint32_t lo, uint32_
 // offsets[j] = sum_{k<j} counts[k] (u64), offsets[B] = n; spill_off[j] = sum_{k<j}
 // max(counts[k] - caps[k], 0); buckets above the small LDS cap go to lists.
 constexpr uint32_t kScanThreads = 1024;
-constexpr uint32_t kScanPer = 8;
 
 __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_t* __restrict__ counts,
                                                                    const uint32_t* __restrict__ caps, uint32_t B,
@@ -409,56 +408,69 @@ __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_
                                                                    PartHeader* __restrict__ ph) {
   __shared__ uint64_t shc[kScanThreads / 64 + 1];
   __shared__ uint32_t shs[kScanThreads / 64 + 1];
-  uint64_t carry_c = 0;
-  uint32_t carry_s = 0, m = 0, mr = 0, br = 0;
-  for (uint32_t base = 0; base < B; base += kScanThreads * kScanPer) {
-    uint32_t c[kScanPer], sp[kScanPer];
-    uint64_t sc = 0;
-    uint32_t ss = 0;
+  // each thread a contiguous segment of P buckets, P a multiple of 16: chunks
+  // of 16 with all their 16-byte loads issued before any is used
+  const uint32_t P = ((B + kScanThreads - 1) / kScanThreads + 15) & ~15u;
+  const uint32_t j0 = threadIdx.x * P, j1 = j0 + P < B ? j0 + P : B;
+  auto load16 = [&](const uint32_t* src, uint32_t j, uint32_t v[16]) {
+    if (j + 16 <= j1) {
 #pragma unroll
-    for (uint32_t i = 0; i < kScanPer; ++i) {
-      uint32_t j = base + threadIdx.x * kScanPer + i;
-      c[i] = 0;
-      sp[i] = 0;
-      if (j < B) {
-        uint32_t cap = caps[j];
-        c[i] = counts[j];
-        sp[i] = c[i] > cap ? c[i] - cap : 0u;
-        m = c[i] > m ? c[i] : m;
-        if (c[i] > kSmallCap) {
-          if (c[i] <= kMidCap) {
-            mid_list[atomicAdd(&ph->n_mid, 1u)] = j;
-            mr += c[i];
-          } else {
-            big_list[atomicAdd(&ph->n_big, 1u)] = j;
-            br += c[i];
-          }
+      for (uint32_t q = 0; q < 4; ++q) {
+        const uint4 x = *reinterpret_cast<const uint4*>(src + j + 4 * q);
+        v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+      }
+    } else {
+#pragma unroll
+      for (uint32_t q = 0; q < 16; ++q) v[q] = j + q < j1 ? src[j + q] : 0u;
+    }
+  };
+  uint64_t sc = 0;
+  uint32_t ss = 0, m = 0, mr = 0, br = 0;
+  for (uint32_t j = j0; j < j1; j += 16) {
+    uint32_t c[16], k[16];
+    load16(counts, j, c);
+    load16(caps, j, k);
+#pragma unroll
+    for (uint32_t q = 0; q < 16; ++q) {
+      sc += c[q];
+      ss += c[q] > k[q] ? c[q] - k[q] : 0u;
+      m = c[q] > m ? c[q] : m;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < 16; ++q) {
+      if (c[q] > kSmallCap) {  // zero past the segment
+        if (c[q] <= kMidCap) {
+          mid_list[atomicAdd(&ph->n_mid, 1u)] = j + q;
+          mr += c[q];
+        } else {
+          big_list[atomicAdd(&ph->n_big, 1u)] = j + q;
+          br += c[q];
         }
       }
-      sc += c[i];
-      ss += sp[i];
     }
-    uint64_t tc;
-    uint32_t ts;
-    uint64_t rc = carry_c + block_exclusive_scan<uint64_t, kScanThreads>(sc, shc, &tc);
-    uint32_t rs = carry_s + block_exclusive_scan<uint32_t, kScanThreads>(ss, shs, &ts);
+  }
+  uint64_t tc;
+  uint32_t ts;
+  uint64_t rc = block_exclusive_scan<uint64_t, kScanThreads>(sc, shc, &tc);
+  uint32_t rs = block_exclusive_scan<uint32_t, kScanThreads>(ss, shs, &ts);
+  for (uint32_t j = j0; j < j1; j += 16) {
+    uint32_t c[16], k[16];
+    load16(counts, j, c);
+    load16(caps, j, k);
 #pragma unroll
-    for (uint32_t i = 0; i < kScanPer; ++i) {
-      uint32_t j = base + threadIdx.x * kScanPer + i;
-      if (j < B) {
-        offsets[j] = rc;
-        spill_off[j] = rs;
+    for (uint32_t q = 0; q < 16; ++q) {
+      if (j + q < j1) {
+        offsets[j + q] = rc;
+        spill_off[j + q] = rs;
       }
-      rc += c[i];
-      rs += sp[i];
+      rc += c[q];
+      rs += c[q] > k[q] ? c[q] - k[q] : 0u;
     }
-    carry_c += tc;
-    carry_s += ts;
   }
   if (mr) atomicAdd(&ph->mid_records, mr);
   if (br) atomicAdd(&ph->big_records, br);
   if (m) atomicMax(&ph->max_count, m);
-  if (threadIdx.x == 0) offsets[B] = carry_c;
+  if (threadIdx.x == 0) offsets[B] = tc;
 }
 
 hipError_t launch_scan_counts(uint8_t* part, const PartLayout& lay, uint32_t B, uint64_t* offsets,
