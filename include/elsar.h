@@ -145,9 +145,11 @@ elsar_status elsar_partition(const elsar_model* m, const void* d_records, uint64
  * Sections 3.4-3.5: sorts every bucket of d_part by (key in memcmp order, input
  * index) and writes it to d_out + record_bytes * d_bucket_offsets[j].
  * d_out: n records on the device; it may be the input of elsar_partition (the
- * sort is then in place) but must not overlap d_part.  The records in d_part
- * are left as they are; the call uses d_part's bookkeeping area as scratch.
- * Asynchronous.
+ * sort is then in place) but must not overlap d_part.  The call uses d_part's
+ * bookkeeping area as scratch; the records in d_part are left as they are,
+ * except with keys longer than 12 bytes, whose run pass (Section 4's
+ * last-mile ordering of the bytes past the encoded prefix) then reuses the
+ * record area as scratch.  Asynchronous.
  */
 elsar_status elsar_sort_buckets(const elsar_model* m, void* d_part, size_t part_bytes, uint64_t n,
                                 const uint64_t* d_bucket_offsets, void* d_out, hipStream_t stream);

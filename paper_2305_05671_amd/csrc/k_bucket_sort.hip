@@ -3,25 +3,31 @@
 // coalescing the records in sorted order).
 //
 // A bucket's records sit in its region (and possibly the spill area) as
-// 128-byte slots: record, 32-bit input index, padding.  Each record gives a
-// composite sort key: the key bytes and then the index, big-endian, so the
+// 128-byte slots: 32-bit input index, record, padding.  Each record gives a
+// composite sort key: key bytes 0..11 and then the index, big-endian, so the
 // composite order is the key's memcmp order with ties broken by input
-// position, and all composites of a bucket differ.  Sorting uses stable LSD
-// radix passes with 8-bit digits over composite bytes; a byte that is equal
-// across the whole bucket needs no pass (an all-equal-key bucket only sorts
-// its index bytes -- early termination on duplicates).
+// position, and all composites of a bucket differ.  A byte that is equal
+// across the whole bucket is never sorted on: every kernel first ORs and ANDs
+// the bucket's composites, so an all-equal-key bucket orders its index bytes
+// only (early termination on duplicates).
 //
 //  * bucket_sort_small: buckets of up to 2048 records, one 512-thread block
-//    each.  The first 16 bytes of every slot (index and key) go to LDS; one
-//    counting pass on the key's base-95 code scaled over the bucket's code
-//    range into 2048 bins, then an insertion sort by the whole composite
-//    inside each bin (a full LSD sort if a bin is long), orders them.  The records are then gathered in
-//    sorted order, each slot read once, straight into the output.
-//  * bucket_sort_lds: buckets of up to 6144 records (all varying composite
-//    bytes, entries and permutation in LDS, records gathered from the slots).
-//  * bucket_sort_global: larger buckets, one block each; the ping-pong entry
-//    buffers live in the bucket's own output range, which holds R*n bytes and
-//    is not written yet (R >= 40 leaves room for 2 * 20n bytes).
+//    each.  The first 16 bytes of every slot go to LDS; one counting pass on
+//    the key's base-95 code, scaled over the bucket's code range into 2048
+//    bins, then each bin is ordered by the whole composite: ranks counted in
+//    parallel up to 64 entries, a one-wave bitonic network up to 256, a
+//    whole-bucket LSD radix beyond.  The records are then gathered in sorted
+//    order straight into the output (each slot line is read twice: for the
+//    key, then for the record).
+//  * bucket_sort_lds: buckets of up to 6144 records, the same algorithm with
+//    a 13-bit counting digit in one 512-thread block.
+//  * msd_split + seg_sort + big_gather: larger buckets, split by their most
+//    significant varying composite byte into pieces the small-bucket sort
+//    finishes, then copied out in order (records of at least 64 bytes).
+//  * bucket_sort_global: larger buckets of shorter records, stable LSD passes
+//    over the varying composite bytes through the bucket's own output range.
+//  * long_runs + long_run_sort: keys of 13 to 28 bytes, runs of equal 12-byte
+//    prefixes ordered by the rest of the key after the kernels above.
 #include "elsar_internal.h"
 
 namespace elsar {

@@ -1,21 +1,25 @@
 // The learned root (gfx950): a monotone MLP CDF trained on the sample by this
-// file's own forward and backward kernels, used as the root of the RMI.
+// file's own forward and backward kernels, used as the root of the RMI; and
+// the equi-depth leaves that the MLP and the linear-spline roots share.
 //
 // The paper's CDF model is an RMI of linear models fitted to a sample of the
 // keys (Section 3.1).  Here the root may instead be a small monotone network
 // fitted to the same target, the sample's empirical CDF rank/S:
 //   phi_k = min(1, max(code - q_k, 0) / w_k)   k = 0..7, quantile knots q_k
-//   h1 = sigmoid(W1 phi + b1)    8 -> 64, FP32 vector ALUs, W1 >= 0
-//   h2 = sigmoid(W2 h1 + b2)     64 -> 64, bfloat16 matrix cores, FP32 accumulate, W2 >= 0
-//   y  = w3 . h2 + b3            64 -> 1, w3 >= 0
-// Non-negative weights and increasing activations make y non-decreasing in
-// the key.  The leaves are fixed on the sorted sample: the leaf of sample s is
-// the running maximum of floor(L y) up to s, and the first sample code of each
-// leaf becomes a routing boundary.  A record's leaf is the number of
-// boundaries at or below its code; the network's own floor(L y) is only the
-// starting point of that search.  Routing is therefore exactly monotone
-// whatever the rounding inside the matrix cores, and each leaf's linear model
-// is the same two-point spline as under the linear root.
+//   h1 = sigmoid(W1 phi + b1)    8 -> 64, FP32 (vector ALUs in training, FP32 matrix cores in evaluation)
+//   h2 = sigmoid(W2 h1 + b2)     64 -> 64, bfloat16 matrix cores, FP32 accumulate
+//   y  = w3 . h2 + b3            64 -> 1
+// with W1, W2, w3 >= 0, so y is non-decreasing in the key.  The leaves are
+// equi-depth in the sorted sample: leaf j starts at the first sample of the
+// run of equal codes that holds sample floor(j S / L), and that sample's code
+// is a routing boundary.  A record's leaf is the number of boundaries at or
+// below its code.  The network narrows the search: a cell table over its
+// output (cell floor(L y)) gives the bracket of leaves a record of that cell
+// can fall in, and the router checks the bracket before searching it, so the
+// leaf is exact whatever the rounding inside the matrix cores.  Each leaf's
+// linear model is the same two-point spline as under the linear root.  The
+// linear-spline root routes among the same boundaries through its segment
+// knots instead.
 #include "mlp_device.h"
 
 namespace elsar {

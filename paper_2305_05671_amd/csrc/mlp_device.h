@@ -1,12 +1,14 @@
-// Device-side evaluation of the monotone MLP root, shared by the fit kernels
-// and the partition kernel.
+// Device-side code of the monotone MLP root: the training kernels' layer-1
+// helper and the evaluation shared by the cell-table, forward and partition
+// kernels, plus the leaf routers.
 //
-// Matrix core layout of v_mfma_f32_16x16x16bf16_1k (one wave, 16x16x16):
-// lane l holds A[l%16][4(l/16)+e], B[4(l/16)+e][l%16] and D[4(l/16)+e][l%16]
-// for e = 0..3.  A wave evaluates 16 records per product: lane l computes the
-// layer-1 units 16ks + 4(l/16) + e (ks, e = 0..3) of record l%16, which are
-// exactly the A fragments it feeds to the four K-steps, so h1 never leaves
-// registers.
+// Matrix-core layouts (one wave, 16x16 outputs): for
+// v_mfma_f32_16x16x16bf16_1k lane l holds A[l%16][4(l/16)+e],
+// B[4(l/16)+e][l%16] and D[4(l/16)+e][l%16] for e = 0..3; for
+// v_mfma_f32_16x16x4_f32 lane l holds A[l%16][l/16] and B[l/16][l%16], and D
+// as above.  Training computes records x units (layer-1 units of record l%16
+// become the A fragments of the layer-2 product); evaluation computes units x
+// records (mlp_y64).
 #pragma once
 #include "elsar_internal.h"
 
