@@ -257,7 +257,7 @@ elsar_status do_sort_buckets(const elsar_model* m, void* d_part, size_t part_byt
   const uint32_t K = m->p.key_bytes, Ks = sort_key_bytes(K);
   HIP_TRY(launch_bucket_sort_small(part, lay, m->B, d_offsets, m->p.record_bytes, Ks, out, st));
   if (pm) mark(*pm, 4, st);
-  HIP_TRY(launch_bucket_sort_large(part, lay, m->B, d_offsets, m->p.record_bytes, Ks, out, st));
+  HIP_TRY(launch_bucket_sort_large(part, lay, m->B, n, d_offsets, m->p.record_bytes, Ks, out, st));
   HIP_TRY(launch_long_key_fixup(out, n, m->p.record_bytes, K, part + lay.slots, st));
   if (pm) mark(*pm, 5, st);
   return ELSAR_OK;
@@ -980,7 +980,8 @@ elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, const el
     HIP_TRY(launch_scan_counts(part, hl.lay, nb, offsets, stream));
     if (stage_busy) HIP_TRY(hipStreamWaitEvent(stream, ss.copied, 0));  // the previous pass's output is out
     HIP_TRY(launch_bucket_sort_small(part, hl.lay, nb, offsets, R, sort_key_bytes(q.key_bytes), stage, stream));
-    HIP_TRY(launch_bucket_sort_large(part, hl.lay, nb, offsets, R, sort_key_bytes(q.key_bytes), stage, stream));
+    HIP_TRY(launch_bucket_sort_large(part, hl.lay, nb, ps.total, offsets, R, sort_key_bytes(q.key_bytes), stage,
+                                     stream));
     HIP_TRY(launch_long_key_fixup(stage, ps.total, R, q.key_bytes, part + hl.lay.slots, stream));
     HIP_TRY(hipEventRecord(ss.sorted, stream));
     HIP_TRY(hipStreamWaitEvent(ss.d2h, ss.sorted, 0));

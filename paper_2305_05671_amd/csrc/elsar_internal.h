@@ -349,7 +349,7 @@ struct TinyJob {
 };
 hipError_t launch_tiny_jobs(const TinyJob* d_jobs, uint32_t njobs, uint32_t rec_bytes, uint32_t key_bytes,
                             uint32_t* staging, hipStream_t st);
-hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
+hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32_t B, uint64_t n, const uint64_t* offsets,
                                     uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st);
 
 }  // namespace elsar

@@ -354,7 +354,9 @@ template <uint32_t RW>  // record dwords
 __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map, const uint4* __restrict__ slots,
-    uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t K, uint32_t* __restrict__ out, uint32_t B) {
+    uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t K, uint32_t* __restrict__ out, uint32_t B,
+    uint32_t* __restrict__ seg_n) {
+  if (seg_n && blockIdx.x == 0 && threadIdx.x < 4) seg_n[threadIdx.x] = 0;  // the big-bucket split's counters
   constexpr uint32_t SC = slot_bytes_for(RW * 4) / 16;  // 16-byte chunks per slot
   constexpr uint32_t LC = (RW + 1 + 3) / 4;             // chunks holding the index or record bytes
   constexpr uint32_t AR = kSmCap / kSmThreads;          // entries per thread
@@ -472,7 +474,8 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
     const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
     uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
-    uint32_t B) {
+    uint32_t B, uint32_t* __restrict__ seg_n) {
+  if (seg_n && blockIdx.x == 0 && threadIdx.x < 4) seg_n[threadIdx.x] = 0;  // the big-bucket split's counters
   constexpr uint32_t WAVES = THREADS / 64;
   static_assert(CAP % THREADS == 0, "cap is whole rounds");
   __shared__ uint4 ent[CAP];
@@ -1065,9 +1068,6 @@ __global__ __launch_bounds__(kMsdThreads) void big_gather_kernel(const uint32_t*
   }
 }
 
-__global__ void msd_reset_kernel(PartHeader* __restrict__ ph) {
-  if (threadIdx.x < 4) ph->seg_n[threadIdx.x] = 0;
-}
 
 
 
@@ -1309,39 +1309,52 @@ hipError_t launch_bucket_sort_small(uint8_t* part, const PartLayout& lay, uint32
   if (rec_bytes == 100) {
     bucket_sort_small_kernel<25><<<B, kSmThreads, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap,
                                                            reinterpret_cast<const uint4*>(a.slots), lay.cap_slots,
-                                                           offsets, key_bytes, a.out, B);
+                                                           offsets, key_bytes, a.out, B,
+                                                           reinterpret_cast<PartHeader*>(part + lay.header)->seg_n);
   } else {
     bucket_sort_lds_kernel<kSmallCap, 256><<<B, 256, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots,
                                                                lay.cap_slots, offsets, a.RW, key_bytes, a.out,
-                                                               nullptr, nullptr, B);
+                                                               nullptr, nullptr, B,
+                                                               reinterpret_cast<PartHeader*>(part + lay.header)->seg_n);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
-                                    uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st) {
+// The kernels below walk device-side lists with persistent blocks; their grids
+// are sized from what n records can hold (at most n / 2049 mid buckets, n /
+// 6145 big ones, about n / 1024 segments), so that the small jobs of a batch
+// do not dispatch thousands of blocks that find nothing to do.
+static uint32_t grid_for(uint64_t n, uint64_t per_block, uint32_t most) {
+  const uint64_t g = n / per_block + 1;
+  return (uint32_t)(g < most ? g : most);
+}
+
+hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32_t B, uint64_t n,
+                                    const uint64_t* offsets, uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out,
+                                    hipStream_t st) {
   SortArgs a = sort_args(part, lay, rec_bytes, out);
-  bucket_sort_lds_kernel<kMidCap, 512><<<256, 512, 0, st>>>(
+  bucket_sort_lds_kernel<kMidCap, 512><<<grid_for(n, kSmallCap + 1, 256), 512, 0, st>>>(
       a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
-      reinterpret_cast<const uint32_t*>(part + lay.mid_list), &a.ph->n_mid, B);
+      reinterpret_cast<const uint32_t*>(part + lay.mid_list), &a.ph->n_mid, B, nullptr);
   const uint32_t* big_list = reinterpret_cast<const uint32_t*>(part + lay.big_list);
   if (rec_bytes < 64) {  // too little room for the split's buffers, stack and reference list
-    bucket_sort_global_kernel<<<256, kBigThreads, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots,
-                                                           lay.cap_slots, offsets, a.RW, key_bytes, a.out, big_list,
-                                                           &a.ph->n_big);
+    bucket_sort_global_kernel<<<grid_for(n, kMidCap + 1, 256), kBigThreads, 0, st>>>(
+        a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
+        big_list, &a.ph->n_big);
     return hipGetLastError();
   }
   PartHeader* ph = reinterpret_cast<PartHeader*>(part + lay.header);
   uint4* leaf = reinterpret_cast<uint4*>(part + lay.seg_leaf);
   uint32_t* leaf_n = &ph->seg_n[0];
   const uint32_t leaf_cap = lay.seg_leaf_cap;
-  msd_reset_kernel<<<1, 64, 0, st>>>(ph);
-  msd_split_kernel<<<512, kMsdThreads, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots,
-                                                offsets, a.RW, key_bytes, a.out, big_list, &a.ph->n_big, leaf,
-                                                leaf_n, leaf_cap, &ph->seg_n[1]);
-  seg_sort_kernel<<<2048, kSmThreads, 0, st>>>(a.counts, offsets, a.RW, a.out, leaf, leaf_n, leaf_cap);
-  big_gather_kernel<<<512, kMsdThreads, 0, st>>>(a.counts, offsets, a.RW, reinterpret_cast<const uint4*>(a.slots),
-                                                 a.out, big_list, &a.ph->n_big);
+  // the split's counters (ph->seg_n) were cleared by the small-bucket kernel
+  msd_split_kernel<<<grid_for(n, kMidCap + 1, 512), kMsdThreads, 0, st>>>(
+      a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out, big_list,
+      &a.ph->n_big, leaf, leaf_n, leaf_cap, &ph->seg_n[1]);
+  seg_sort_kernel<<<grid_for(n, 1024, 2048), kSmThreads, 0, st>>>(a.counts, offsets, a.RW, a.out, leaf, leaf_n,
+                                                                   leaf_cap);
+  big_gather_kernel<<<grid_for(n, kMidCap + 1, 512), kMsdThreads, 0, st>>>(
+      a.counts, offsets, a.RW, reinterpret_cast<const uint4*>(a.slots), a.out, big_list, &a.ph->n_big);
   return hipGetLastError();
 }
 
