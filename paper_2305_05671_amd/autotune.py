@@ -6,7 +6,7 @@ Two sweeps, both run on the GPU:
   elsar_sort_batch) of 2^k records, k in 11..22, over candidate bucket sizes
   (records per bucket), on the batch workload's two key laws (uniform,
   first-byte Zipf); the fastest size per k goes into csrc/autotune_table.h.
-* --batch: jobs of a batch run four at a time, which changes the trade-off,
+* --batch: jobs of a batch run sixteen at a time, which changes the trade-off,
   so this sweep times the batch workload itself (bench.py --workload
   batch-4096) with one records-per-bucket value for every job of up to 2^20
   records, rebuilding the library for each candidate, and keeps the fastest.
