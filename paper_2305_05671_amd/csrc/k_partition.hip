@@ -21,14 +21,14 @@ constexpr int kPartTile = 256;  // records per tile (one per thread for the mode
 
 // Chunk c (16 bytes) of the slot of tile record k: the index, the record
 // dwords, then zeros.
-__device__ __forceinline__ uint4 slot_chunk(const uint32_t* tile, uint32_t RW, uint32_t k, uint32_t c, uint32_t idx) {
-  uint32_t v[4];
+__device__ __forceinline__ u32x4 slot_chunk(const uint32_t* tile, uint32_t RW, uint32_t k, uint32_t c, uint32_t idx) {
+  u32x4 v;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     uint32_t d = 4 * c + i;  // slot dword
     v[i] = d == 0 ? idx : (d <= RW ? tile[k * RW + d - 1] : 0u);
   }
-  return make_uint4(v[0], v[1], v[2], v[3]);
+  return v;
 }
 
 // Tile t of records held in registers as RV <= 8 named 16-byte vectors per
@@ -51,7 +51,7 @@ __device__ __forceinline__ void load_tile_regs(const uint32_t* __restrict__ rec_
 #define ELSAR_LD(I)                                              \
   if constexpr (I < RV) {                                        \
     uint32_t v = threadIdx.x + (I) * kPartThreads;               \
-    R.v##I = src4[v < nvec ? v : nvec - 1];                      \
+    R.v##I = __builtin_nontemporal_load(src4 + (v < nvec ? v : nvec - 1)); \
   }
   ELSAR_FOR8(ELSAR_LD)
 #undef ELSAR_LD
@@ -75,6 +75,13 @@ __device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const
   if (d < ndw) b[d] = R.tail;
 }
 
+// The records are read and the slots written with nontemporal loads and
+// stores: they stream through once, and marking them so keeps the routing
+// tables (leaves, boundaries, knots; a few hundred KB) resident in L2, where
+// every record's bucket search reads them (the spline root's partition went
+// from 8.6 to 8.0 ms at 100M skewed records, the linear root's from 5.7 to
+// 5.4 ms at 100M uniform ones).
+//
 // Software pipeline per block over its tiles t = blockIdx.x, + gridDim.x, ...:
 // the loads of tile t+1 are in flight while the atomics of tile t reserve
 // slots and the slots of tile t-1 are written, so neither the load latency nor
@@ -130,7 +137,8 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
     for (uint32_t q = threadIdx.x; q < total; q += kPartThreads) {
       uint32_t k = q / SC, c = q - k * SC;
       if (FILTER && dslot[k] == kNoSlot) continue;
-      slots[(uint64_t)dslot[k] * SC + c] = slot_chunk(b, RW, k, c, r0 + k);
+      __builtin_nontemporal_store(slot_chunk(b, RW, k, c, r0 + k),
+                                  reinterpret_cast<u32x4*>(slots) + (uint64_t)dslot[k] * SC + c);
     }
   };
 
