@@ -444,7 +444,10 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
       uint32_t q = q0 + tid + i * kSmThreads;
       uint32_t qq = q < nq ? q : nq - 1;  // clamped: no branch around the loads
       uint32_t k = qq / LC, c = qq - k * LC;
-      g[i] = reinterpret_cast<const u32x4*>(slots)[(uint64_t)slot_of(br, perm[cur][k], spill_map, cap_slots) * SC + c];
+      // last read of the slot line: nontemporal, so that lines other blocks
+      // have fetched for their keys stay in L2 until their own gather
+      g[i] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(slots) +
+                                        (uint64_t)slot_of(br, perm[cur][k], spill_map, cap_slots) * SC + c);
     }
 #pragma unroll
     for (uint32_t i = 0; i < kSmGroup; ++i) {
@@ -548,7 +551,7 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
         const uint32_t q = q0 + threadIdx.x + i * THREADS;
         const uint32_t qq = q < nq ? q : nq - 1;
         const uint32_t k = qq / LC, c = qq - k * LC;
-        g[i] = s4[(uint64_t)slot_of(br, perm[cur][k], spill_map, cap_slots) * SC + c];
+        g[i] = __builtin_nontemporal_load(s4 + (uint64_t)slot_of(br, perm[cur][k], spill_map, cap_slots) * SC + c);
       }
 #pragma unroll
       for (uint32_t i = 0; i < kSmGroup; ++i) {
@@ -1047,7 +1050,7 @@ __global__ __launch_bounds__(kMsdThreads) void big_gather_kernel(const uint32_t*
           const uint32_t q = q0 + threadIdx.x + i * kMsdThreads;
           const uint32_t qq = q < nq ? q : nq - 1;
           const uint32_t k = qq / LC, c = qq - k * LC;
-          g[i] = reinterpret_cast<const u32x4*>(slots)[(uint64_t)chunk_slot[k] * SC + c];
+          g[i] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(slots) + (uint64_t)chunk_slot[k] * SC + c);
         }
 #pragma unroll
         for (uint32_t i = 0; i < kSmGroup; ++i) {
