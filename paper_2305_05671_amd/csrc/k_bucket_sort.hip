@@ -431,37 +431,60 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
     cur = small_sort_core(n, vary, cw, perm, bins, sh_scan, tot);
   }
   __syncthreads();
-  // 3. gather the records in sorted order straight into the output: lane q
-  //    moves 16-byte chunk q % LC of the record at sorted position q / LC, so
-  //    the lanes of a wave cover a contiguous stretch of the output.  Loads go
-  //    out kSmGroup per thread before any store waits on them.
-  uint32_t* o_dw = out + br.out0 * RW;
-  const uint32_t nq = n * LC;
-  for (uint32_t q0 = 0; q0 < nq; q0 += kSmGroup * kSmThreads) {
-    u32x4 g[kSmGroup];
+  // 3. gather through LDS: the records of sorted positions [r0, r0 + kStage)
+  //    are assembled in the composite area (free once the order is known),
+  //    then that stretch of the output goes out as whole 128-byte lines of
+  //    16-byte nontemporal stores, its partial lines at both ends as dword
+  //    stores.  The output is never read back here; whole-line nontemporal
+  //    writes keep it from displacing, in L2, the slot lines that other
+  //    blocks have fetched for their keys and are about to gather.  The slot
+  //    loads are nontemporal too: this is the line's last use.
+  uint32_t* stage = &cw[0][0];
+  constexpr uint32_t kStage = (4 * kSmCap) / RW;  // records per round
+  for (uint32_t r0 = 0; r0 < n; r0 += kStage) {
+    const uint32_t m = n - r0 < kStage ? n - r0 : kStage;
+    const uint32_t nq = m * LC;
+    __syncthreads();  // the composites, or the previous round's stretch, are read
+    for (uint32_t q0 = 0; q0 < nq; q0 += kSmGroup * kSmThreads) {
+      u32x4 g[kSmGroup];
 #pragma unroll
-    for (uint32_t i = 0; i < kSmGroup; ++i) {
-      uint32_t q = q0 + tid + i * kSmThreads;
-      uint32_t qq = q < nq ? q : nq - 1;  // clamped: no branch around the loads
-      uint32_t k = qq / LC, c = qq - k * LC;
-      // last read of the slot line: nontemporal, so that lines other blocks
-      // have fetched for their keys stay in L2 until their own gather
-      g[i] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(slots) +
-                                        (uint64_t)slot_of(br, perm[cur][k], spill_map, cap_slots) * SC + c);
-    }
+      for (uint32_t i = 0; i < kSmGroup; ++i) {  // kSmGroup loads in flight per thread
+        uint32_t q = q0 + tid + i * kSmThreads;
+        uint32_t qq = q < nq ? q : nq - 1;  // clamped: no branch around the loads
+        uint32_t k = qq / LC, c = qq - k * LC;
+        g[i] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(slots) +
+                                          (uint64_t)slot_of(br, perm[cur][r0 + k], spill_map, cap_slots) * SC + c);
+      }
 #pragma unroll
-    for (uint32_t i = 0; i < kSmGroup; ++i) {
-      uint32_t q = q0 + tid + i * kSmThreads;
-      if (q < nq) {
-        uint32_t k = q / LC, c = q - k * LC;
-        uint32_t* o = o_dw + k * RW;
+      for (uint32_t i = 0; i < kSmGroup; ++i) {
+        uint32_t q = q0 + tid + i * kSmThreads;
+        if (q < nq) {
+          uint32_t k = q / LC, c = q - k * LC;
 #pragma unroll
-        for (uint32_t t = 0; t < 4; ++t) {
-          uint32_t sd = 4 * c + t;  // slot dword: 0 is the index, 1..RW the record
-          if (sd >= 1 && sd <= RW) o[sd - 1] = g[i][t];
+          for (uint32_t t = 0; t < 4; ++t) {
+            uint32_t sd = 4 * c + t;  // slot dword: 0 is the index, 1..RW the record
+            if (sd >= 1 && sd <= RW) stage[k * RW + sd - 1] = g[i][t];
+          }
         }
       }
     }
+    __syncthreads();
+    const uint64_t gb = (br.out0 + r0) * RW;  // first output dword of the stretch
+    const uint32_t total = m * RW;
+    uint32_t head = (uint32_t)((32u - (uint32_t)(gb & 31u)) & 31u);  // dwords up to a 128-byte boundary
+    if (head > total) head = total;
+    const uint32_t lines = (total - head) / 32;
+    if (tid < head) out[gb + tid] = stage[tid];
+    for (uint32_t v = tid; v < lines * 8; v += kSmThreads) {
+      const uint32_t s0 = head + 4 * v;
+      u32x4 x;
+      x[0] = stage[s0];
+      x[1] = stage[s0 + 1];
+      x[2] = stage[s0 + 2];
+      x[3] = stage[s0 + 3];
+      __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(out + gb + head) + v);
+    }
+    for (uint32_t t = head + lines * 32 + tid; t < total; t += kSmThreads) out[gb + t] = stage[t];
   }
 }
 
@@ -537,35 +560,58 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
     const uint32_t cur =
         bin_sort_core<CAP, THREADS, kMidBits>(br.n, vary, perm, bins, sh_scan, tot, less, byte_of);
     __syncthreads();
-    // 3. copy records in sorted order to the output: lane q moves 16-byte
-    //    chunk q % LC of the record at sorted position q / LC, kSmGroup loads
-    //    in flight per thread before the stores
+    // 3. copy records in sorted order to the output through LDS, as in the
+    //    small-bucket kernel: a stretch of records assembled in the entry
+    //    area (free once the order is known), then whole 128-byte lines of
+    //    nontemporal 16-byte stores, dword stores at the stretch's ends
     const uint32_t SC = W / 4, LC = (RW + 1 + 3) / 4;
-    uint32_t* o_dw = out + br.out0 * RW;
-    const uint32_t nq = br.n * LC;
     const u32x4* s4 = reinterpret_cast<const u32x4*>(slots);
-    for (uint32_t q0 = 0; q0 < nq; q0 += kSmGroup * THREADS) {
-      u32x4 g[kSmGroup];
+    uint32_t* stage = reinterpret_cast<uint32_t*>(ent);
+    const uint32_t kStage = (4 * CAP) / RW;  // records per round
+    for (uint32_t r0 = 0; r0 < br.n; r0 += kStage) {
+      const uint32_t m = br.n - r0 < kStage ? br.n - r0 : kStage;
+      const uint32_t nq = m * LC;
+      __syncthreads();  // the entries, or the previous round's stretch, are read
+      for (uint32_t q0 = 0; q0 < nq; q0 += kSmGroup * THREADS) {
+        u32x4 g[kSmGroup];
 #pragma unroll
-      for (uint32_t i = 0; i < kSmGroup; ++i) {
-        const uint32_t q = q0 + threadIdx.x + i * THREADS;
-        const uint32_t qq = q < nq ? q : nq - 1;
-        const uint32_t k = qq / LC, c = qq - k * LC;
-        g[i] = __builtin_nontemporal_load(s4 + (uint64_t)slot_of(br, perm[cur][k], spill_map, cap_slots) * SC + c);
-      }
+        for (uint32_t i = 0; i < kSmGroup; ++i) {
+          const uint32_t q = q0 + threadIdx.x + i * THREADS;
+          const uint32_t qq = q < nq ? q : nq - 1;
+          const uint32_t k = qq / LC, c = qq - k * LC;
+          g[i] = __builtin_nontemporal_load(s4 + (uint64_t)slot_of(br, perm[cur][r0 + k], spill_map, cap_slots) * SC +
+                                            c);
+        }
 #pragma unroll
-      for (uint32_t i = 0; i < kSmGroup; ++i) {
-        const uint32_t q = q0 + threadIdx.x + i * THREADS;
-        if (q < nq) {
-          const uint32_t k = q / LC, c = q - k * LC;
-          uint32_t* o = o_dw + k * RW;
+        for (uint32_t i = 0; i < kSmGroup; ++i) {
+          const uint32_t q = q0 + threadIdx.x + i * THREADS;
+          if (q < nq) {
+            const uint32_t k = q / LC, c = q - k * LC;
 #pragma unroll
-          for (uint32_t t = 0; t < 4; ++t) {
-            const uint32_t sd = 4 * c + t;  // slot dword: 0 is the index, 1..RW the record
-            if (sd >= 1 && sd <= RW) o[sd - 1] = g[i][t];
+            for (uint32_t t = 0; t < 4; ++t) {
+              const uint32_t sd = 4 * c + t;  // slot dword: 0 is the index, 1..RW the record
+              if (sd >= 1 && sd <= RW) stage[k * RW + sd - 1] = g[i][t];
+            }
           }
         }
       }
+      __syncthreads();
+      const uint64_t gb = (br.out0 + r0) * RW;  // first output dword of the stretch
+      const uint32_t total = m * RW;
+      uint32_t head = (uint32_t)((32u - (uint32_t)(gb & 31u)) & 31u);
+      if (head > total) head = total;
+      const uint32_t lines = (total - head) / 32;
+      if (threadIdx.x < head) out[gb + threadIdx.x] = stage[threadIdx.x];
+      for (uint32_t v = threadIdx.x; v < lines * 8; v += THREADS) {
+        const uint32_t s0 = head + 4 * v;
+        u32x4 x;
+        x[0] = stage[s0];
+        x[1] = stage[s0 + 1];
+        x[2] = stage[s0 + 2];
+        x[3] = stage[s0 + 3];
+        __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(out + gb + head) + v);
+      }
+      for (uint32_t t = head + lines * 32 + threadIdx.x; t < total; t += THREADS) out[gb + t] = stage[t];
     }
     __syncthreads();
   }
