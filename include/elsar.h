@@ -134,9 +134,10 @@ elsar_status elsar_partition_size(const elsar_model* m, uint64_t n, size_t* part
  * <= every key of bucket j+1), counts the bucket sizes S_p and writes
  * d_bucket_offsets[j] = sum_{k<j} S_k for j = 0..B (u64; d_bucket_offsets[B] = n),
  * the output offsets of Section 3.5.
- * d_part: elsar_partition_size bytes, opaque; it holds each record with its
- * input index, grouped by bucket (in no order within a bucket).
- * d_bucket_offsets: B + 1 u64 on the device.  Asynchronous.
+ * d_part: elsar_partition_size bytes, 16-byte aligned, opaque; it holds each
+ * record with its input index, grouped by bucket (in no order within a bucket).
+ * d_bucket_offsets: B + 1 u64 on the device, 8-byte aligned.  A misaligned
+ * d_part or d_bucket_offsets is ELSAR_E_INVALID_ARG.  Asynchronous.
  */
 elsar_status elsar_partition(const elsar_model* m, const void* d_records, uint64_t n, void* d_part,
                              size_t part_bytes, uint64_t* d_bucket_offsets, hipStream_t stream);
@@ -145,7 +146,8 @@ elsar_status elsar_partition(const elsar_model* m, const void* d_records, uint64
  * Sections 3.4-3.5: sorts every bucket of d_part by (key in memcmp order, input
  * index) and writes it to d_out + record_bytes * d_bucket_offsets[j].
  * d_out: n records on the device; it may be the input of elsar_partition (the
- * sort is then in place) but must not overlap d_part.  The call uses d_part's
+ * sort is then in place) but must not overlap d_part.  d_part and
+ * d_bucket_offsets are those elsar_partition took (same alignment checks).  The call uses d_part's
  * bookkeeping area as scratch; the records in d_part are left as they are,
  * except with keys longer than 12 bytes, whose run pass (Section 4's
  * last-mile ordering of the bytes past the encoded prefix) then reuses the

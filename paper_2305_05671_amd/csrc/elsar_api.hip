@@ -39,6 +39,7 @@ constexpr float kMlpLearningRate = 0.01f;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+inline bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 uint64_t default_sample_size(uint64_t n) {
   uint64_t s = (n + 99) / 100;
@@ -362,6 +363,7 @@ elsar_status elsar_partition_size(const elsar_model* m, uint64_t n, size_t* part
 elsar_status elsar_partition(const elsar_model* m, const void* d_records, uint64_t n, void* d_part,
                              size_t part_bytes, uint64_t* d_bucket_offsets, hipStream_t stream) {
   if (!m || !d_part || !d_bucket_offsets) return ELSAR_E_INVALID_ARG;
+  if (!aligned16(d_part) || !aligned8(d_bucket_offsets)) return ELSAR_E_INVALID_ARG;
   if (n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;
   if (n && (!d_records || !aligned16(d_records))) return ELSAR_E_INVALID_ARG;
   if (m->n == 0 && n > 0) return ELSAR_E_INVALID_ARG;  // not fitted
@@ -375,6 +377,7 @@ elsar_status elsar_partition(const elsar_model* m, const void* d_records, uint64
 elsar_status elsar_sort_buckets(const elsar_model* m, void* d_part, size_t part_bytes, uint64_t n,
                                 const uint64_t* d_bucket_offsets, void* d_out, hipStream_t stream) {
   if (!m || !d_part || !d_bucket_offsets) return ELSAR_E_INVALID_ARG;
+  if (!aligned16(d_part) || !aligned8(d_bucket_offsets)) return ELSAR_E_INVALID_ARG;
   if (n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;
   if (n && (!d_out || !aligned16(d_out))) return ELSAR_E_INVALID_ARG;
   PhaseMarks pm = begin_marks();

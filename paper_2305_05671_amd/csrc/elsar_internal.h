@@ -216,6 +216,24 @@ __device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int off) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  uint32_t lo = __shfl((uint32_t)v, src), hi = __shfl((uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive scan of one value per lane across a whole (converged) wave.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  T x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    T y;
+    if constexpr (sizeof(T) == 8) y = (T)shfl_up_u64((uint64_t)x, off);
+    else y = (T)__shfl_up((uint32_t)x, off);
+    if (lane_id() >= (uint32_t)off) x += y;
+  }
+  return x;
+}
+
 // Exclusive scan of one value per thread across a block of NT threads (NT a
 // multiple of 64, at most 1024).  *total gets the block's sum.  sh: NT/64 slots.
 template <typename T, uint32_t NT>

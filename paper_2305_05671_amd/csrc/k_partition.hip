@@ -405,7 +405,13 @@ hipError_t launch_exact_regions(const uint32_t* counts_all, uint32_t lo, uint32_
 
 // offsets[j] = sum_{k<j} counts[k] (u64), offsets[B] = n; spill_off[j] = sum_{k<j}
 // max(counts[k] - caps[k], 0); buckets above the small LDS cap go to lists.
+// One block.  Wave w owns a contiguous segment of WS buckets (WS a multiple of
+// 256) and walks it 256 buckets a step, lane l taking buckets 4l .. 4l+3 of
+// the step, so that every load and store of the wave covers whole lines.
+// Pass 1 sums the wave's counts and overflows; the waves' sums are scanned in
+// order; pass 2 scans each step across the wave and writes the offsets.
 constexpr uint32_t kScanThreads = 1024;
+constexpr uint32_t kScanWaves = kScanThreads / 64;
 
 __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_t* __restrict__ counts,
                                                                    const uint32_t* __restrict__ caps, uint32_t B,
@@ -414,39 +420,35 @@ __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_
                                                                    uint32_t* __restrict__ mid_list,
                                                                    uint32_t* __restrict__ big_list,
                                                                    PartHeader* __restrict__ ph) {
-  __shared__ uint64_t shc[kScanThreads / 64 + 1];
-  __shared__ uint32_t shs[kScanThreads / 64 + 1];
-  // each thread a contiguous segment of P buckets, P a multiple of 16: chunks
-  // of 16 with all their 16-byte loads issued before any is used
-  const uint32_t P = ((B + kScanThreads - 1) / kScanThreads + 15) & ~15u;
-  const uint32_t j0 = threadIdx.x * P, j1 = j0 + P < B ? j0 + P : B;
-  auto load16 = [&](const uint32_t* src, uint32_t j, uint32_t v[16]) {
-    if (j + 16 <= j1) {
-#pragma unroll
-      for (uint32_t q = 0; q < 4; ++q) {
-        const uint4 x = *reinterpret_cast<const uint4*>(src + j + 4 * q);
-        v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
-      }
+  __shared__ uint64_t shc[kScanWaves + 1];
+  __shared__ uint32_t shs[kScanWaves];
+  const uint32_t WS = ((B + kScanWaves - 1) / kScanWaves + 255) & ~255u;
+  const uint32_t w = threadIdx.x >> 6, l = lane_id();
+  const uint32_t s0 = w * WS, s1 = s0 + WS < B ? s0 + WS : B;  // empty when s0 >= B
+  // values of buckets j .. j+3 (zero past B)
+  auto load4 = [&](const uint32_t* src, uint32_t j, uint32_t v[4]) {
+    if (j + 4 <= B) {
+      const uint4 x = *reinterpret_cast<const uint4*>(src + j);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
     } else {
 #pragma unroll
-      for (uint32_t q = 0; q < 16; ++q) v[q] = j + q < j1 ? src[j + q] : 0u;
+      for (uint32_t q = 0; q < 4; ++q) v[q] = j + q < B ? src[j + q] : 0u;
     }
   };
+  auto over = [](uint32_t c, uint32_t k) { return c > k ? c - k : 0u; };
   uint64_t sc = 0;
   uint32_t ss = 0, m = 0, mr = 0, br = 0;
-  for (uint32_t j = j0; j < j1; j += 16) {
-    uint32_t c[16], k[16];
-    load16(counts, j, c);
-    load16(caps, j, k);
+  for (uint32_t jb = s0; jb < s1; jb += 256) {
+    const uint32_t j = jb + 4 * l;
+    uint32_t c[4], k[4];
+    load4(counts, j, c);
+    load4(caps, j, k);
 #pragma unroll
-    for (uint32_t q = 0; q < 16; ++q) {
+    for (uint32_t q = 0; q < 4; ++q) {
       sc += c[q];
-      ss += c[q] > k[q] ? c[q] - k[q] : 0u;
+      ss += over(c[q], k[q]);
       m = c[q] > m ? c[q] : m;
-    }
-#pragma unroll
-    for (uint32_t q = 0; q < 16; ++q) {
-      if (c[q] > kSmallCap) {  // zero past the segment
+      if (c[q] > kSmallCap) {  // zero past B
         if (c[q] <= kMidCap) {
           mid_list[atomicAdd(&ph->n_mid, 1u)] = j + q;
           mr += c[q];
@@ -457,28 +459,68 @@ __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_
       }
     }
   }
-  uint64_t tc;
-  uint32_t ts;
-  uint64_t rc = block_exclusive_scan<uint64_t, kScanThreads>(sc, shc, &tc);
-  uint32_t rs = block_exclusive_scan<uint32_t, kScanThreads>(ss, shs, &ts);
-  for (uint32_t j = j0; j < j1; j += 16) {
-    uint32_t c[16], k[16];
-    load16(counts, j, c);
-    load16(caps, j, k);
-#pragma unroll
-    for (uint32_t q = 0; q < 16; ++q) {
-      if (j + q < j1) {
-        offsets[j + q] = rc;
-        spill_off[j + q] = rs;
-      }
-      rc += c[q];
-      rs += c[q] > k[q] ? c[q] - k[q] : 0u;
-    }
+  for (int off = 32; off >= 1; off >>= 1) {
+    sc += shfl_xor_u64(sc, off);
+    ss += __shfl_xor(ss, off);
+    mr += __shfl_xor(mr, off);
+    br += __shfl_xor(br, off);
+    const uint32_t mo = __shfl_xor(m, off);
+    m = mo > m ? mo : m;
   }
-  if (mr) atomicAdd(&ph->mid_records, mr);
-  if (br) atomicAdd(&ph->big_records, br);
-  if (m) atomicMax(&ph->max_count, m);
-  if (threadIdx.x == 0) offsets[B] = tc;
+  if (l == 0) {
+    shc[w] = sc;
+    shs[w] = ss;
+    if (mr) atomicAdd(&ph->mid_records, mr);
+    if (br) atomicAdd(&ph->big_records, br);
+    if (m) atomicMax(&ph->max_count, m);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t rc = 0;
+    uint32_t rs = 0;
+    for (uint32_t i = 0; i < kScanWaves; ++i) {
+      const uint64_t c = shc[i];
+      const uint32_t x = shs[i];
+      shc[i] = rc;
+      shs[i] = rs;
+      rc += c;
+      rs += x;
+    }
+    shc[kScanWaves] = rc;
+  }
+  __syncthreads();
+  uint64_t rc = shc[w];
+  uint32_t rs = shs[w];
+  for (uint32_t jb = s0; jb < s1; jb += 256) {
+    const uint32_t j = jb + 4 * l;
+    uint32_t c[4], k[4];
+    load4(counts, j, c);
+    load4(caps, j, k);
+    const uint64_t oc = (uint64_t)c[0] + c[1] + c[2] + c[3];
+    const uint32_t os = over(c[0], k[0]) + over(c[1], k[1]) + over(c[2], k[2]) + over(c[3], k[3]);
+    const uint64_t xc = wave_inclusive_scan<uint64_t>(oc);
+    const uint32_t xs = wave_inclusive_scan<uint32_t>(os);
+    uint64_t r = rc + xc - oc;
+    uint32_t t = rs + xs - os;
+    uint32_t so[4];
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      if (j + q < B) offsets[j + q] = r;
+      so[q] = t;
+      r += c[q];
+      t += over(c[q], k[q]);
+    }
+    if (j + 4 <= B) {
+      *reinterpret_cast<uint4*>(spill_off + j) = make_uint4(so[0], so[1], so[2], so[3]);
+    } else {
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q)
+        if (j + q < B) spill_off[j + q] = so[q];
+    }
+    rc += shfl_u64(xc, 63);  // the step's sums
+    rs += __shfl(xs, 63);
+  }
+  if (threadIdx.x == 0) offsets[B] = shc[kScanWaves];
 }
 
 hipError_t launch_scan_counts(uint8_t* part, const PartLayout& lay, uint32_t B, uint64_t* offsets,

@@ -96,11 +96,6 @@ __device__ __forceinline__ void mlp_load_frags(const MlpBlock* __restrict__ Mg, 
     for (uint32_t h = 0; h < 2; ++h) w.w1[2 * ks + h] = Mg->h.W1[(16 * ks + r) * 8 + 4 * h + g];
 }
 
-__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
-  uint32_t lo = __shfl((uint32_t)v, src), hi = __shfl((uint32_t)(v >> 32), src);
-  return ((uint64_t)hi << 32) | lo;
-}
-
 // Feature k of one code (as in mlp_features).
 __device__ __forceinline__ float mlp_feature(uint64_t code, const MlpHead& M, uint32_t k) {
   const uint64_t d = code >= M.q[k] ? code - M.q[k] : 0ull;

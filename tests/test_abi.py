@@ -75,6 +75,12 @@ def test_argument_checks_return_before_any_work(elsar):
     assert lib.elsar_sort(16, 5, 32, ctypes.byref(p), 64, 10, None) == elsar.E_NO_MEMORY
     assert lib.elsar_sort(17, 5, 32, ctypes.byref(p), 64, 10 ** 12, None) == elsar.E_INVALID_ARG
     assert lib.elsar_partition(None, None, 0, None, 0, None, None) == elsar.E_INVALID_ARG
+    # a misaligned partition buffer or offsets array is refused before the
+    # model or any device memory is touched (the pointers are never dereferenced)
+    assert lib.elsar_partition(64, None, 0, 32 + 8, 1 << 20, 64, None) == elsar.E_INVALID_ARG
+    assert lib.elsar_partition(64, None, 0, 32, 1 << 20, 64 + 4, None) == elsar.E_INVALID_ARG
+    assert lib.elsar_sort_buckets(64, 32 + 8, 1 << 20, 0, 64, None, None) == elsar.E_INVALID_ARG
+    assert lib.elsar_sort_buckets(64, 32, 1 << 20, 0, 64 + 4, None, None) == elsar.E_INVALID_ARG
 
 
 def test_workspace_grows_linearly(elsar):
