@@ -526,16 +526,18 @@ hipError_t launch_batch_fit(const FitJob* d_jobs, uint32_t njobs, uint32_t rec_b
 constexpr uint32_t kScanThreads = 1024;
 
 // Region sizes and starts, in one block.  Wave w owns a contiguous segment of
-// WS buckets (WS a multiple of 256) and walks it 256 buckets a step, lane l
+// WS buckets (WS a multiple of 1024) and walks it 256 buckets a step, lane l
 // taking buckets 4l .. 4l+3 of the step with 16-byte loads and stores, so
 // that every access of a wave covers whole lines (one segment per thread made
-// each access touch 64 lines, all through the one CU).  Pass 1 sums the
-// wave's sizes; the waves' sums are scanned in order; pass 2 recomputes the
-// sizes, scans them across the wave step by step and writes sizes, starts and
-// cleared fill counters.  A region past the reserved slot count cannot happen
-// by construction; such a bucket would get no region and all its records
-// would spill.
+// each access touch 64 lines, all through the one CU).  The loads of four
+// steps are issued before any is used.  Pass 1 sums the wave's sizes; the
+// waves' sums are scanned in order; pass 2 recomputes the sizes, scans them
+// across the wave step by step and writes sizes, starts and cleared fill
+// counters.  A region past the reserved slot count cannot happen by
+// construction; such a bucket would get no region and all its records would
+// spill.
 constexpr uint32_t kScanWaves = kScanThreads / 64;
+constexpr uint32_t kScanSteps = 4;  // steps of 256 buckets whose loads are in flight together
 
 __global__ __launch_bounds__(kScanThreads) void capacity_kernel(const uint32_t* __restrict__ hist, uint64_t S,
                                                                 uint64_t n, uint32_t B, double scale,
@@ -543,36 +545,39 @@ __global__ __launch_bounds__(kScanThreads) void capacity_kernel(const uint32_t* 
                                                                 uint32_t* __restrict__ rstart,
                                                                 uint32_t* __restrict__ counts,
                                                                 PartHeader* __restrict__ ph, uint64_t cap_slots) {
-  __shared__ uint64_t sh[kScanWaves + 1];
+  __shared__ uint64_t sh[kScanWaves];
   const double ideal = (double)n / (double)B;
-  const uint32_t WS = ((B + kScanWaves - 1) / kScanWaves + 255) & ~255u;
+  const uint32_t WS = ((B + kScanWaves - 1) / kScanWaves + 1023) & ~1023u;
   const uint32_t w = threadIdx.x >> 6, l = lane_id();
   const uint32_t s0 = w * WS, s1 = s0 + WS < B ? s0 + WS : B;  // empty when s0 >= B
-  // sizes of buckets j .. j+3 (zero past B)
-  auto sizes4 = [&](uint32_t j, uint32_t c[4]) {
-    uint32_t h[4];
-    if (j + 4 <= B) {
+  // sample counts of buckets j .. j+3 (zero past the segment)
+  auto load4 = [&](uint32_t j, uint32_t h[4]) {
+    if (j + 4 <= s1) {
       const uint4 x = *reinterpret_cast<const uint4*>(hist + j);
       h[0] = x.x; h[1] = x.y; h[2] = x.z; h[3] = x.w;
     } else {
 #pragma unroll
-      for (uint32_t q = 0; q < 4; ++q) h[q] = j + q < B ? hist[j + q] : 0u;
-    }
-#pragma unroll
-    for (uint32_t q = 0; q < 4; ++q) {
-      // h sample keys estimate the bucket's mass as h / S with a standard
-      // deviation of about sqrt(h) / S: the region covers two of them
-      const double hd = (double)h[q];
-      const double expect = (hd + 2.0 * sqrt(hd)) * (double)n / (double)S;
-      const double m = expect > ideal ? expect : ideal;
-      c[q] = j + q < B ? ((uint32_t)ceil(scale * m) + 16u + 1u) & ~1u : 0u;
+      for (uint32_t q = 0; q < 4; ++q) h[q] = j + q < s1 ? hist[j + q] : 0u;
     }
   };
+  // region size of bucket j from its sample count h: h sample keys estimate
+  // the bucket's mass as h / S with a standard deviation of about sqrt(h) / S,
+  // and the region covers two of them
+  auto size_of = [&](uint32_t j, uint32_t h) {
+    const double hd = (double)h;
+    const double expect = (hd + 2.0 * sqrt(hd)) * (double)n / (double)S;
+    const double m = expect > ideal ? expect : ideal;
+    return j < s1 ? ((uint32_t)ceil(scale * m) + 16u + 1u) & ~1u : 0u;
+  };
   uint64_t s = 0;
-  for (uint32_t jb = s0; jb < s1; jb += 256) {
-    uint32_t c[4];
-    sizes4(jb + 4 * l, c);
-    s += (uint64_t)c[0] + c[1] + c[2] + c[3];
+  for (uint32_t jb = s0; jb < s1; jb += 256 * kScanSteps) {
+    uint32_t h[kScanSteps][4];
+#pragma unroll
+    for (uint32_t u = 0; u < kScanSteps; ++u) load4(jb + 256 * u + 4 * l, h[u]);
+#pragma unroll
+    for (uint32_t u = 0; u < kScanSteps; ++u)
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) s += size_of(jb + 256 * u + 4 * l + q, h[u][q]);
   }
   for (int off = 32; off >= 1; off >>= 1) s += shfl_xor_u64(s, off);
   if (l == 0) sh[w] = s;
@@ -587,36 +592,43 @@ __global__ __launch_bounds__(kScanThreads) void capacity_kernel(const uint32_t* 
   }
   __syncthreads();
   uint64_t run = sh[w];
-  for (uint32_t jb = s0; jb < s1; jb += 256) {
-    const uint32_t j = jb + 4 * l;
-    uint32_t c[4];
-    sizes4(j, c);
-    const uint64_t own = (uint64_t)c[0] + c[1] + c[2] + c[3];
-    const uint64_t x = wave_inclusive_scan<uint64_t>(own);
-    uint64_t r = run + x - own;
-    uint32_t cp[4], rp[4];
+  for (uint32_t jb = s0; jb < s1; jb += 256 * kScanSteps) {
+    uint32_t h[kScanSteps][4];
 #pragma unroll
-    for (uint32_t q = 0; q < 4; ++q) {
-      const bool fits = r + c[q] <= cap_slots;
-      cp[q] = fits ? c[q] : 0u;
-      rp[q] = fits ? (uint32_t)r : 0u;
-      r += c[q];
-    }
-    if (j + 4 <= B) {
-      *reinterpret_cast<uint4*>(caps + j) = make_uint4(cp[0], cp[1], cp[2], cp[3]);
-      *reinterpret_cast<uint4*>(rstart + j) = make_uint4(rp[0], rp[1], rp[2], rp[3]);
-      *reinterpret_cast<uint4*>(counts + j) = make_uint4(0, 0, 0, 0);
-    } else {
+    for (uint32_t u = 0; u < kScanSteps; ++u) load4(jb + 256 * u + 4 * l, h[u]);
+#pragma unroll
+    for (uint32_t u = 0; u < kScanSteps; ++u) {
+      const uint32_t j = jb + 256 * u + 4 * l;
+      uint32_t c[4];
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) c[q] = size_of(j + q, h[u][q]);
+      const uint64_t own = (uint64_t)c[0] + c[1] + c[2] + c[3];
+      const uint64_t x = wave_inclusive_scan<uint64_t>(own);
+      uint64_t r = run + x - own;
+      uint32_t cp[4], rp[4];
 #pragma unroll
       for (uint32_t q = 0; q < 4; ++q) {
-        if (j + q < B) {
-          caps[j + q] = cp[q];
-          rstart[j + q] = rp[q];
-          counts[j + q] = 0;
+        const bool fits = r + c[q] <= cap_slots;
+        cp[q] = fits ? c[q] : 0u;
+        rp[q] = fits ? (uint32_t)r : 0u;
+        r += c[q];
+      }
+      if (j + 4 <= s1) {
+        *reinterpret_cast<uint4*>(caps + j) = make_uint4(cp[0], cp[1], cp[2], cp[3]);
+        *reinterpret_cast<uint4*>(rstart + j) = make_uint4(rp[0], rp[1], rp[2], rp[3]);
+        *reinterpret_cast<uint4*>(counts + j) = make_uint4(0, 0, 0, 0);
+      } else {
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+          if (j + q < s1) {
+            caps[j + q] = cp[q];
+            rstart[j + q] = rp[q];
+            counts[j + q] = 0;
+          }
         }
       }
+      run += shfl_u64(x, 63);  // the step's sum
     }
-    run += shfl_u64(x, 63);  // the step's sum
   }
   if (threadIdx.x == 0) {
     ph->n = n;

@@ -406,12 +406,14 @@ hipError_t launch_exact_regions(const uint32_t* counts_all, uint32_t lo, uint32_
 // offsets[j] = sum_{k<j} counts[k] (u64), offsets[B] = n; spill_off[j] = sum_{k<j}
 // max(counts[k] - caps[k], 0); buckets above the small LDS cap go to lists.
 // One block.  Wave w owns a contiguous segment of WS buckets (WS a multiple of
-// 256) and walks it 256 buckets a step, lane l taking buckets 4l .. 4l+3 of
-// the step, so that every load and store of the wave covers whole lines.
-// Pass 1 sums the wave's counts and overflows; the waves' sums are scanned in
-// order; pass 2 scans each step across the wave and writes the offsets.
+// 1024) and walks it 256 buckets a step, lane l taking buckets 4l .. 4l+3 of
+// the step, so that every load and store of the wave covers whole lines; the
+// loads of four steps are issued before any is used.  Pass 1 sums the wave's
+// counts and overflows; the waves' sums are scanned in order; pass 2 scans
+// each step across the wave and writes the offsets.
 constexpr uint32_t kScanThreads = 1024;
 constexpr uint32_t kScanWaves = kScanThreads / 64;
+constexpr uint32_t kScanSteps = 4;  // steps of 256 buckets whose loads are in flight together
 
 __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_t* __restrict__ counts,
                                                                    const uint32_t* __restrict__ caps, uint32_t B,
@@ -422,39 +424,46 @@ __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_
                                                                    PartHeader* __restrict__ ph) {
   __shared__ uint64_t shc[kScanWaves + 1];
   __shared__ uint32_t shs[kScanWaves];
-  const uint32_t WS = ((B + kScanWaves - 1) / kScanWaves + 255) & ~255u;
+  const uint32_t WS = ((B + kScanWaves - 1) / kScanWaves + 1023) & ~1023u;
   const uint32_t w = threadIdx.x >> 6, l = lane_id();
   const uint32_t s0 = w * WS, s1 = s0 + WS < B ? s0 + WS : B;  // empty when s0 >= B
-  // values of buckets j .. j+3 (zero past B)
+  // values of buckets j .. j+3 (zero past the segment)
   auto load4 = [&](const uint32_t* src, uint32_t j, uint32_t v[4]) {
-    if (j + 4 <= B) {
+    if (j + 4 <= s1) {
       const uint4 x = *reinterpret_cast<const uint4*>(src + j);
       v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
     } else {
 #pragma unroll
-      for (uint32_t q = 0; q < 4; ++q) v[q] = j + q < B ? src[j + q] : 0u;
+      for (uint32_t q = 0; q < 4; ++q) v[q] = j + q < s1 ? src[j + q] : 0u;
     }
   };
   auto over = [](uint32_t c, uint32_t k) { return c > k ? c - k : 0u; };
   uint64_t sc = 0;
   uint32_t ss = 0, m = 0, mr = 0, br = 0;
-  for (uint32_t jb = s0; jb < s1; jb += 256) {
-    const uint32_t j = jb + 4 * l;
-    uint32_t c[4], k[4];
-    load4(counts, j, c);
-    load4(caps, j, k);
+  for (uint32_t jb = s0; jb < s1; jb += 256 * kScanSteps) {
+    uint32_t c[kScanSteps][4], k[kScanSteps][4];
 #pragma unroll
-    for (uint32_t q = 0; q < 4; ++q) {
-      sc += c[q];
-      ss += over(c[q], k[q]);
-      m = c[q] > m ? c[q] : m;
-      if (c[q] > kSmallCap) {  // zero past B
-        if (c[q] <= kMidCap) {
-          mid_list[atomicAdd(&ph->n_mid, 1u)] = j + q;
-          mr += c[q];
-        } else {
-          big_list[atomicAdd(&ph->n_big, 1u)] = j + q;
-          br += c[q];
+    for (uint32_t u = 0; u < kScanSteps; ++u) {
+      load4(counts, jb + 256 * u + 4 * l, c[u]);
+      load4(caps, jb + 256 * u + 4 * l, k[u]);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kScanSteps; ++u) {
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) {
+        const uint32_t cq = c[u][q];
+        sc += cq;
+        ss += over(cq, k[u][q]);
+        m = cq > m ? cq : m;
+        if (cq > kSmallCap) {  // zero past the segment
+          const uint32_t j = jb + 256 * u + 4 * l + q;
+          if (cq <= kMidCap) {
+            mid_list[atomicAdd(&ph->n_mid, 1u)] = j;
+            mr += cq;
+          } else {
+            big_list[atomicAdd(&ph->n_big, 1u)] = j;
+            br += cq;
+          }
         }
       }
     }
@@ -491,34 +500,41 @@ __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_
   __syncthreads();
   uint64_t rc = shc[w];
   uint32_t rs = shs[w];
-  for (uint32_t jb = s0; jb < s1; jb += 256) {
-    const uint32_t j = jb + 4 * l;
-    uint32_t c[4], k[4];
-    load4(counts, j, c);
-    load4(caps, j, k);
-    const uint64_t oc = (uint64_t)c[0] + c[1] + c[2] + c[3];
-    const uint32_t os = over(c[0], k[0]) + over(c[1], k[1]) + over(c[2], k[2]) + over(c[3], k[3]);
-    const uint64_t xc = wave_inclusive_scan<uint64_t>(oc);
-    const uint32_t xs = wave_inclusive_scan<uint32_t>(os);
-    uint64_t r = rc + xc - oc;
-    uint32_t t = rs + xs - os;
-    uint32_t so[4];
+  for (uint32_t jb = s0; jb < s1; jb += 256 * kScanSteps) {
+    uint32_t c[kScanSteps][4], k[kScanSteps][4];
 #pragma unroll
-    for (uint32_t q = 0; q < 4; ++q) {
-      if (j + q < B) offsets[j + q] = r;
-      so[q] = t;
-      r += c[q];
-      t += over(c[q], k[q]);
+    for (uint32_t u = 0; u < kScanSteps; ++u) {
+      load4(counts, jb + 256 * u + 4 * l, c[u]);
+      load4(caps, jb + 256 * u + 4 * l, k[u]);
     }
-    if (j + 4 <= B) {
-      *reinterpret_cast<uint4*>(spill_off + j) = make_uint4(so[0], so[1], so[2], so[3]);
-    } else {
 #pragma unroll
-      for (uint32_t q = 0; q < 4; ++q)
-        if (j + q < B) spill_off[j + q] = so[q];
+    for (uint32_t u = 0; u < kScanSteps; ++u) {
+      const uint32_t j = jb + 256 * u + 4 * l;
+      const uint64_t oc = (uint64_t)c[u][0] + c[u][1] + c[u][2] + c[u][3];
+      const uint32_t os = over(c[u][0], k[u][0]) + over(c[u][1], k[u][1]) + over(c[u][2], k[u][2]) +
+                          over(c[u][3], k[u][3]);
+      const uint64_t xc = wave_inclusive_scan<uint64_t>(oc);
+      const uint32_t xs = wave_inclusive_scan<uint32_t>(os);
+      uint64_t r = rc + xc - oc;
+      uint32_t t = rs + xs - os;
+      uint32_t so[4];
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) {
+        if (j + q < s1) offsets[j + q] = r;
+        so[q] = t;
+        r += c[u][q];
+        t += over(c[u][q], k[u][q]);
+      }
+      if (j + 4 <= s1) {
+        *reinterpret_cast<uint4*>(spill_off + j) = make_uint4(so[0], so[1], so[2], so[3]);
+      } else {
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q)
+          if (j + q < s1) spill_off[j + q] = so[q];
+      }
+      rc += shfl_u64(xc, 63);  // the step's sums
+      rs += __shfl(xs, 63);
     }
-    rc += shfl_u64(xc, 63);  // the step's sums
-    rs += __shfl(xs, 63);
   }
   if (threadIdx.x == 0) offsets[B] = shc[kScanWaves];
 }
