@@ -38,11 +38,14 @@ hipError_t launch_sample_codes(const uint8_t* recs, uint64_t n, uint32_t rec_byt
 // ---------------------------------------------- LSD radix sort of u64 keys --
 // Per pass (one byte): per-tile digit histograms (digit-major), one exclusive
 // scan over them, then a stable scatter where each wave ranks its own items in
-// order with ballot-matched digits.
+// order with ballot-matched digits.  With few tiles (a sample of up to 64K
+// codes) the scatter blocks scan the counts themselves and the scan kernel's
+// launch is saved: at 10^4 codes a pass costs launches, not bandwidth.
 constexpr int kRadixThreads = 256;
 constexpr int kRadixRounds = 16;  // rounds of 64 items per wave
 constexpr int kRadixWaves = kRadixThreads / 64;
 constexpr int kRadixTile = kRadixThreads * kRadixRounds;  // 4096
+constexpr uint32_t kRadixFuseTiles = 16;  // up to this many tiles the scatter scans the tile counts itself
 
 __global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const uint64_t* __restrict__ keys, uint64_t n,
                                                                    int shift, uint32_t ntiles,
@@ -87,11 +90,15 @@ __global__ __launch_bounds__(256) void radix_digit_scan_kernel(uint32_t* __restr
   if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
+// fused (few tiles): tile_off holds the raw per-tile counts and digit_tot is
+// unused; each block sums, per digit, all tiles and the tiles before its own,
+// which replaces the digit-scan launch.
 __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(const uint64_t* __restrict__ in,
                                                                       uint64_t* __restrict__ out, uint64_t n,
                                                                       int shift, uint32_t ntiles,
                                                                       const uint32_t* __restrict__ tile_off,
-                                                                      const uint32_t* __restrict__ digit_tot) {
+                                                                      const uint32_t* __restrict__ digit_tot,
+                                                                      bool fused) {
   __shared__ uint32_t wc[kRadixWaves][256];
   __shared__ uint32_t gbase[256];
   __shared__ uint32_t sh[kRadixThreads / 64 + 1];
@@ -116,8 +123,19 @@ __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(const uint
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  uint32_t dtot;
-  uint32_t dbase = block_exclusive_scan<uint32_t, kRadixThreads>(digit_tot[threadIdx.x], sh, &dtot);
+  uint32_t dtot, before = 0, total = 0;
+  if (fused) {
+    const uint32_t* h = tile_off + (uint64_t)threadIdx.x * ntiles;
+    for (uint32_t t = 0; t < ntiles; ++t) {
+      const uint32_t c = h[t];
+      before += t < blockIdx.x ? c : 0u;
+      total += c;
+    }
+  } else {
+    before = tile_off[(uint64_t)threadIdx.x * ntiles + blockIdx.x];
+    total = digit_tot[threadIdx.x];
+  }
+  uint32_t dbase = block_exclusive_scan<uint32_t, kRadixThreads>(total, sh, &dtot);
   {
     uint32_t d = threadIdx.x, run = 0;
     for (int ww = 0; ww < kRadixWaves; ++ww) {
@@ -125,7 +143,7 @@ __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(const uint
       wc[ww][d] = run;
       run += c;
     }
-    gbase[d] = dbase + tile_off[(uint64_t)d * ntiles + blockIdx.x];
+    gbase[d] = dbase + before;
   }
   __syncthreads();
 #pragma unroll
@@ -154,9 +172,10 @@ hipError_t launch_radix_sort_u64(uint64_t* keys, uint64_t* tmp, uint64_t n, int 
   uint64_t *a = keys, *b = tmp;
   for (int byte = lo_byte; byte <= hi_byte; ++byte) {
     int shift = 8 * byte;
+    const bool fused = ntiles <= kRadixFuseTiles;
     radix_hist_kernel<<<ntiles, kRadixThreads, 0, st>>>(a, n, shift, ntiles, th);
-    radix_digit_scan_kernel<<<256, 256, 0, st>>>(th, ntiles, dtot);
-    radix_scatter_kernel<<<ntiles, kRadixThreads, 0, st>>>(a, b, n, shift, ntiles, th, dtot);
+    if (!fused) radix_digit_scan_kernel<<<256, 256, 0, st>>>(th, ntiles, dtot);
+    radix_scatter_kernel<<<ntiles, kRadixThreads, 0, st>>>(a, b, n, shift, ntiles, th, dtot, fused);
     uint64_t* t = a;
     a = b;
     b = t;
