@@ -13,6 +13,13 @@ The JSON line carries:
                  from HIP events the library records on its launch stream
   cpu_baseline   the oracle (single-threaded qsort of the stable memcmp order)
                  timed on a bounded sample of the same workload on host cores
+  cpu_parallel_baseline
+                 a parallel stable sort (libstdc++ parallel mode) on every host
+                 thread, over the whole workload
+  skewed_root_comparison
+                 (default run) the skewed workload with hot keys sorted under
+                 the linear RMI root, the automatic choice, and the MLP root
+                 with and without its acceptance test
 """
 from __future__ import annotations
 
@@ -71,6 +78,9 @@ def parse():
                     help="batch workload: jobs checked against the oracle after the timed steps")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy kernel of known size (counter calibration)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the skewed-workload comparison of roots (linear, automatic, MLP)")
+    ap.add_argument("--compare-steps", type=int, default=5, help="timed sorts per root of the comparison")
     return ap.parse_args()
 
 
@@ -318,6 +328,115 @@ def bench_batch(args, wl):
         sys.exit(1)
 
 
+def _kind(elsar, name):
+    return {"rmi": elsar.RMI, "mlp": elsar.MLP, "auto": elsar.AUTO, "radix": elsar.RADIX,
+            "spline": elsar.SPLINE}[name]
+
+
+def _model_name(info, model):
+    if model == "radix":
+        return "radix"
+    return {0: "rmi", 1: "mlp", 4: "spline"}[info.kind_used]
+
+
+def time_sorts(elsar, torch, n, params, d_in, d_out, ws, warmup, steps):
+    """warmup untimed sorts, then `steps` sorts timed on the host around the
+    whole loop (synchronised on both sides); the library's per-phase HIP
+    events over the same calls."""
+    for _ in range(warmup):
+        elsar.elsar_sort(d_in, d_out, params, ws)
+    torch.cuda.synchronize()
+    elsar.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        elsar.elsar_sort(d_in, d_out, params, ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = elsar.timings()
+    elsar.set_timing(False)
+    return wall / steps * 1e3, tm
+
+
+def fit_stats(elsar, n, params, d_in):
+    """Model and partition statistics of one more fit on the same input
+    (outside any timed region)."""
+    m = elsar.Model(n, params)
+    m.sample_fit(d_in)
+    part, _ = m.partition(d_in)
+    st = m.partition_stats(part)
+    info = m.info()
+    del part, m
+    return st, info
+
+
+def phases(tm):
+    return {"sample_fit": round(tm.sample_fit_ms, 3), "partition": round(tm.partition_ms, 3),
+            "scan": round(tm.scan_ms, 3), "bucket_sort_lds": round(tm.bucket_sort_lds_ms, 3),
+            "bucket_sort_rest": round(tm.bucket_sort_rest_ms, 3), "total": round(tm.total_ms, 3)}
+
+
+def compare_roots(args, elsar, torch):
+    """The learned part against the plain model on the skewed workload with
+    hot keys: the same input sorted under the linear RMI root, the automatic
+    choice (the plain model: linear root or linear spline), the MLP root with
+    its acceptance test, and the MLP root accepted whatever its statistic."""
+    import datagen
+    wl = WORKLOADS["skewed-hot-100M"]
+    n = wl["n"]
+    roots = [("rmi", "rmi", 1.5), ("auto", "auto", 1.5), ("mlp", "mlp", 1.5), ("mlp_forced", "mlp", 1e9)]
+    plist = [(name, elsar.fit_params(num_buckets=wl["buckets"], seed=wl["seed"], kind=_kind(elsar, model),
+                                     accept_ratio=ratio), model) for name, model, ratio in roots]
+    d_in = torch.empty(n * RECORD_BYTES, dtype=torch.uint8, device="cuda")
+    datagen.generate_device(datagen.spec(wl["kind"], seed=wl["seed"]), d_in.data_ptr(), 0, n,
+                            torch.cuda.current_stream().cuda_stream)
+    d_out = torch.empty_like(d_in)
+    ws = torch.empty(max(elsar.sort_workspace_size(n, p) for _, p, _ in plist), dtype=torch.uint8, device="cuda")
+    out = {"workload": wl["desc"], "steps": args.compare_steps, "warmup": 2}
+    for name, params, model in plist:
+        ms, tm = time_sorts(elsar, torch, n, params, d_in, d_out, ws, 2, args.compare_steps)
+        st, info = fit_stats(elsar, n, params, d_in)
+        out[name] = {
+            "accept_ratio": params.accept_ratio, "model_used": _model_name(info, model),
+            "mlp_rejected": bool(info.mlp_rejected), "ms_per_step": round(ms, 3),
+            "records_per_s": round(n / (ms * 1e-3)), "phases_ms": phases(tm),
+            "max_bucket": st.max_bucket, "records_in_buckets_above_6144": st.big_records,
+            "max_sample_bucket": info.max_sample_bucket, "ideal_sample_bucket": info.opt_sample_bucket,
+            "rmi_max_sample_bucket": info.rmi_max_sample_bucket,
+            "network_max_sample_bucket": info.net_max_sample_bucket if model == "mlp" else None,
+        }
+        print(f"bench: skewed-hot-100M {name}: {ms:.2f} ms ({out[name]['model_used']})", file=sys.stderr, flush=True)
+    del d_in, d_out, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_parallel_baseline(wl, key_bytes=10):
+    """The all-core CPU baseline on the whole workload: libstdc++'s parallel
+    stable sort of record indices (memcmp key, ties in input order)."""
+    import datagen
+    import oracle
+    n = wl["n"]
+    recs = datagen.generate(datagen.spec(wl["kind"], seed=wl["seed"], key_bytes=key_bytes), n)
+    perm, used = oracle.parallel_sort_order(recs.ctypes.data, n, key_bytes=key_bytes)  # loads the library
+    del perm
+    t0 = time.perf_counter()
+    perm, used = oracle.parallel_sort_order(recs.ctypes.data, n, key_bytes=key_bytes)
+    dt = time.perf_counter() - t0
+    del perm, recs
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": n / dt, "unit": "records/s", "cores": used, "kind": "libstdc++ parallel-mode stable_sort",
+            "sample": f"all {n} records of the same workload, record indices sorted by (memcmp key, index) on "
+                      f"{used} threads, {dt:.1f} s", "cpu_model": model, "nproc": os.cpu_count()}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -338,10 +457,9 @@ def main():
     # the library's automatic choice unless a root is named: on uniform keys it
     # keeps the linear RMI, on the skewed law it takes the spline root
     args.model = args.model or ("rmi" if wl["kind"] == "uniform" else "auto")
-    kind = {"rmi": elsar.RMI, "mlp": elsar.MLP, "auto": elsar.AUTO, "radix": elsar.RADIX,
-            "spline": elsar.SPLINE}[args.model]
-    params = elsar.fit_params(num_buckets=wl["buckets"], num_leaves=args.leaves, seed=wl["seed"], kind=kind,
-                              mlp_steps=args.mlp_steps, accept_ratio=args.accept_ratio, key_bytes=args.key_bytes)
+    params = elsar.fit_params(num_buckets=wl["buckets"], num_leaves=args.leaves, seed=wl["seed"],
+                              kind=_kind(elsar, args.model), mlp_steps=args.mlp_steps,
+                              accept_ratio=args.accept_ratio, key_bytes=args.key_bytes)
 
     def buffers():
         # the records straight into HBM by the GPU generator (byte-identical to
@@ -368,28 +486,8 @@ def main():
     print(f"bench: {args.workload} resident in HBM ({n * RECORD_BYTES / 1e9:.1f} GB), "
           f"workspace {ws.numel() / 1e9:.1f} GB", file=sys.stderr, flush=True)
 
-    for _ in range(args.warmup):
-        elsar.elsar_sort(d_in, d_out, params, ws)
-    torch.cuda.synchronize()
-
-    elsar.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        elsar.elsar_sort(d_in, d_out, params, ws)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    tm = elsar.timings()
-    elsar.set_timing(False)
-    ms_per_step = wall / args.steps * 1e3
-
-    # model / partition statistics of one more fit on the same input (outside the timed region)
-    m = elsar.Model(n, params)
-    m.sample_fit(d_in)
-    part, _ = m.partition(d_in)
-    st = m.partition_stats(part)
-    info = m.info()
-    del part, m
+    ms_per_step, tm = time_sorts(elsar, torch, n, params, d_in, d_out, ws, args.warmup, args.steps)
+    st, info = fit_stats(elsar, n, params, d_in)
 
     small_records = n - st.mid_records - st.big_records  # records the small-bucket LDS kernel sorts
     kernels = {  # name in the profiles, phase time, algorithmic bytes per launch
@@ -420,15 +518,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"] + ("" if args.key_bytes == 10 else f"; {args.key_bytes}-byte keys"),
                    "records": n, "record_bytes": RECORD_BYTES, "key_bytes": args.key_bytes, "buckets": wl["buckets"],
-                   "model": args.model, "model_used": "radix" if args.model == "radix" else {0: "rmi", 1: "mlp", 4: "spline"}[info.kind_used],
+                   "model": args.model, "model_used": _model_name(info, args.model),
                    "leaves": info.num_leaves, "sample": info.sample_size,
                    "max_sample_bucket": info.max_sample_bucket, "ideal_sample_bucket": info.opt_sample_bucket,
                    "parallelism": "single GPU"},
         "algorithmic_GBps": round(2 * PASS_BYTES * n / (ms_per_step * 1e-3) / 1e9, 1),
         "hbm_frac_whole_path": round(2 * PASS_BYTES * n / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "phases_ms": {"sample_fit": round(tm.sample_fit_ms, 3), "partition": round(tm.partition_ms, 3),
-                      "scan": round(tm.scan_ms, 3), "bucket_sort_lds": round(tm.bucket_sort_lds_ms, 3),
-                      "bucket_sort_rest": round(tm.bucket_sort_rest_ms, 3), "total": round(tm.total_ms, 3)},
+        "phases_ms": phases(tm),
         "buckets": {"max": st.max_bucket, "ideal": round(n / st.num_buckets, 1), "spill": st.spill_count,
                     "mid": st.mid_buckets, "big": st.big_buckets, "mid_records": st.mid_records,
                     "big_records": st.big_records},
@@ -442,8 +538,11 @@ def main():
         del a, b
     del d_in, d_out, ws
     torch.cuda.empty_cache()
+    if args.workload == "uniform-100M" and args.model == "rmi" and args.key_bytes == 10 and not args.no_compare:
+        result["skewed_root_comparison"] = compare_roots(args, elsar, torch)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_records, n), args.key_bytes)
+        result["cpu_parallel_baseline"] = cpu_parallel_baseline(wl, args.key_bytes)
     print(json.dumps(result), flush=True)
 
 

@@ -45,6 +45,7 @@ extern "C" {
 #define ELSAR_MAX_DEVICE_RECORDS 1000000000ull
 #define ELSAR_MLP_PARAMS 4801      /* W1 (64x8), b1 (64), W2 (64x64), b2 (64), w3 (64), b3, row-major */
 #define ELSAR_MLP_GRAD_ROWS 128    /* rows of one MLP training step */
+#define ELSAR_MLP_STEPS_NONE 0xFFFFFFFFu  /* mlp_steps: no training, the initial network (for comparisons) */
 
 typedef enum {
   ELSAR_OK = 0,
@@ -52,12 +53,13 @@ typedef enum {
   ELSAR_E_NO_MEMORY = 2,       /* workspace or partition buffer too small, or allocation failed */
   ELSAR_E_HIP = 3,             /* a HIP runtime call or kernel launch failed */
   ELSAR_E_UNSUPPORTED = 4,     /* shape outside the supported range (e.g. n too large) */
-  ELSAR_E_MODEL_REJECTED = 5   /* the learned model failed its acceptance test (RMI kept) */
+  ELSAR_E_MODEL_REJECTED = 5   /* the learned model failed its acceptance test (the plain model kept) */
 } elsar_status;
 
 typedef enum {
   ELSAR_MODEL_RMI = 0,  /* two-level RMI: linear root, linear-spline leaves */
-  ELSAR_MODEL_MLP = 1,  /* monotone MLP root over equi-depth spline leaves; RMI if it fails acceptance */
+  ELSAR_MODEL_MLP = 1,  /* monotone MLP root over equi-depth spline leaves if the network passes its
+                           acceptance test, else the plain model the automatic choice would take */
   ELSAR_MODEL_AUTO = 2, /* RMI when its largest sample bucket is within accept_ratio of a perfect
                            model's, lambda + sqrt(2 ln(B) lambda) + 1 with lambda = S/B; else SPLINE */
   ELSAR_MODEL_RADIX = 3, /* no learned model: equi-width buckets of the code, floor(code * B / 95^8), the
@@ -77,9 +79,12 @@ typedef struct {
   uint64_t sample_size;   /* S; 0: min(max(ceil(n/100), 1024), 10^7, n) (Section 3.1, Section 6) */
   uint64_t seed;          /* seed of the sampler's Philox4x32-10 draws */
   uint32_t kind;          /* elsar_model_kind */
-  float accept_ratio;     /* MLP accepted if its largest sample bucket <= ratio * ideal, ideal =
-                             max(ceil(S/B), longest run of equal codes in the sample); 0: 1.5 */
-  uint32_t mlp_steps;     /* Adam steps (128 sample rows each) of the MLP fit; 0: 16 */
+  float accept_ratio;     /* MLP accepted if the largest bucket of the network's own output,
+                             clamp(floor(B y), 0, B-1), over the sample is <= ratio * ideal, ideal =
+                             max(ceil(S/B), longest run of equal codes in the sample); the linear root's
+                             gate (ELSAR_MODEL_AUTO) takes the same ratio; 0: 1.5 */
+  uint32_t mlp_steps;     /* Adam steps (128 sample rows each) of the MLP fit; 0: 16;
+                             ELSAR_MLP_STEPS_NONE: none */
   uint32_t region_pct;    /* bucket j's region holds ceil(region_pct/100 * max(n*(h_j + 2 sqrt(h_j))/S, n/B))
                              + 16 records (h_j: sample keys in bucket j), the rest spills; 0: 125 */
 } elsar_fit_params;
@@ -117,10 +122,15 @@ elsar_status elsar_fit_workspace_size(const elsar_model* m, uint64_t n, size_t* 
  * network's output gives, for each of L cells of y, the bracket of leaves
  * whose first codes map there; a record's leaf is then searched exactly among
  * the first codes inside that bracket (after a check that it holds, else from
- * the guess floor(L*y) over all of them).  The root is chosen on the device
- * (see elsar_model_kind).
+ * the guess floor(L*y) over all of them).  The bucket of a record under the
+ * MLP root is therefore that of its equi-depth leaf; the network decides the
+ * cost of finding it.  Acceptance judges the network itself: the histogram of
+ * its own buckets clamp(floor(B y), 0, B-1) over the sorted sample must peak
+ * at most accept_ratio times the ideal (see elsar_fit_params).  The root is
+ * chosen on the device (see elsar_model_kind).
  * With kind MLP the call then synchronises with `stream` and returns
- * ELSAR_E_MODEL_REJECTED when the linear root was kept (the model stays valid).
+ * ELSAR_E_MODEL_REJECTED when the network was rejected; the model stays valid
+ * with the plain root (linear or spline) in use.
  */
 elsar_status elsar_sample_fit(elsar_model* m, const void* d_records, uint64_t n, void* d_ws, size_t ws_bytes,
                               hipStream_t stream);
@@ -247,6 +257,13 @@ typedef struct {
   uint32_t max_sample_bucket, opt_sample_bucket;  /* acceptance statistics (MLP fits) */
   uint32_t mlp_leaves;       /* equi-depth leaves of the MLP / spline roots (0 without them) */
   uint32_t spline_segments;  /* K segments of the spline root (0 without it) */
+  /* acceptance statistics on the sample (0 where not computed): largest sample
+   * bucket under the linear root, under the equi-depth leaves, under the
+   * network's own buckets clamp(floor(B y), 0, B-1); whether the linear root
+   * passed its gate (largest sample bucket <= accept_ratio * perfect); and
+   * perfect = lambda + sqrt(2 ln(B) lambda) + 1, lambda = S/B */
+  uint32_t rmi_max_sample_bucket, eq_max_sample_bucket, net_max_sample_bucket, rmi_gate_passed;
+  float perfect_sample_bucket;
 } elsar_model_info;
 
 elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info);
@@ -283,6 +300,16 @@ elsar_status elsar_mlp_forward(const float* h_params, const uint64_t* h_knots, c
                                float* h_y);
 elsar_status elsar_mlp_gradient(const float* h_params, const uint64_t* h_knots, const uint64_t* h_codes,
                                 const float* h_targets, float* h_grad, float* h_loss);
+/* One training step as the fit runs it: the gradient of elsar_mlp_gradient on
+ * the ELSAR_MLP_GRAD_ROWS rows, then the Adam update of step `step` (>= 1;
+ * beta1 0.9, beta2 0.999, eps 1e-8, bias corrections 1/(1 - beta^step)) with
+ * learning rate lr, W1, W2 and w3 projected onto >= 0.  h_adam: the first and
+ * then the second moments (2 * ELSAR_MLP_PARAMS).  The updated parameters and
+ * moments go to h_params_out / h_adam_out; h_grad (ELSAR_MLP_PARAMS) and
+ * h_loss may be NULL.  ELSAR_E_INVALID_ARG for step 0 or a negative lr. */
+elsar_status elsar_mlp_train_step(const float* h_params, const float* h_adam, const uint64_t* h_knots,
+                                  const uint64_t* h_codes, const float* h_targets, uint32_t step, float lr,
+                                  float* h_params_out, float* h_adam_out, float* h_grad, float* h_loss);
 
 /* Statistics of the last partition in d_part; synchronises. */
 typedef struct {

@@ -39,6 +39,39 @@ def build(quiet: bool = True) -> str:
     return _LIB_PATH
 
 
+_PAR_PATH = os.path.join(_HERE, "libelsar_oracle_par.so")
+
+
+def build_parallel(quiet: bool = True) -> str:
+    """Compile the all-core CPU baseline (libstdc++ parallel mode, OpenMP)."""
+    src = os.path.join(_HERE, "parallel_sort.cpp")
+    tmp = _PAR_PATH + ".tmp"
+    cmd = ["g++", "-O2", "-fPIC", "-shared", "-fopenmp", "-std=c++17", "-Wall", "-o", tmp, src]
+    subprocess.run(cmd, check=True, capture_output=quiet)
+    os.replace(tmp, _PAR_PATH)
+    return _PAR_PATH
+
+
+_par = None
+
+
+def parallel_sort_order(recs_ptr: int, n: int, record_bytes: int = 100, key_bytes: int = 10, threads: int = 0):
+    """All-core baseline: the stable memcmp-key order by libstdc++'s parallel
+    stable sort.  Returns (perm, threads used)."""
+    global _par
+    if _par is None:
+        if not os.path.exists(_PAR_PATH):
+            build_parallel()
+        _par = ctypes.CDLL(_PAR_PATH)
+        _par.oracle_parallel_sort_order.argtypes = [_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _u64p,
+                                                    ctypes.c_int]
+        _par.oracle_parallel_sort_order.restype = ctypes.c_int
+    perm = np.empty(n, dtype=np.uint64)
+    used = _par.oracle_parallel_sort_order(ctypes.cast(recs_ptr, _u8p), n, record_bytes, key_bytes,
+                                           _p(perm, _u64p), threads)
+    return perm, int(used)
+
+
 _lib = None
 
 
@@ -52,6 +85,7 @@ def lib():
             "oracle_sort_order": ([_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _u64p], ctypes.c_int),
             "oracle_sort_records": ([_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _u8p], ctypes.c_int),
             "oracle_first_unsorted": ([_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_uint64),
+            "oracle_first_unstable": ([_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_uint64),
             "oracle_multiset_hash": ([_u8p, ctypes.c_uint64, ctypes.c_uint32], ctypes.c_uint64),
             "oracle_rank_of": ([_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _u8p, ctypes.c_uint64],
                                ctypes.c_uint64),
@@ -73,6 +107,10 @@ def lib():
                                       _f32p, _f32p, _u32p, _u32p], None),
             "oracle_routed_buckets": ([_u8p, ctypes.c_uint64, ctypes.c_uint32, _u64p, ctypes.c_uint32, _u64p,
                                        _f32p, _f32p, _u32p, _u32p, _u32p], None),
+            "oracle_rmi_buckets_codes": ([_u64p, ctypes.c_uint64, _f32p, ctypes.c_uint32, _u64p, _f32p, _f32p,
+                                          _u32p, _u32p, _u32p], None),
+            "oracle_leaves_under_root": ([_u64p, ctypes.c_uint64, ctypes.c_float, ctypes.c_float, ctypes.c_uint32,
+                                          ctypes.c_uint32, _u64p, _f32p, _f32p, _u32p, _u32p], None),
             "oracle_counts_offsets": ([_u32p, ctypes.c_uint64, ctypes.c_uint32, _u64p, _u64p], ctypes.c_int),
             "oracle_opt_max_bucket": ([_u64p, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_uint64),
         }
@@ -124,6 +162,18 @@ def first_unsorted(recs: np.ndarray, key_bytes: int = 10) -> int:
 
 def first_unsorted_ptr(ptr: int, n: int, record_bytes: int = 100, key_bytes: int = 10) -> int:
     return int(lib().oracle_first_unsorted(ctypes.cast(ptr, _u8p), n, record_bytes, key_bytes))
+
+
+def first_unstable_ptr(ptr: int, n: int, record_bytes: int = 100, key_bytes: int = 10) -> int:
+    """Records carrying their input index as 10 decimal digits after the key:
+    first position whose (key, index) is not strictly below the next one's,
+    or n."""
+    return int(lib().oracle_first_unstable(ctypes.cast(ptr, _u8p), n, record_bytes, key_bytes))
+
+
+def first_unstable(recs: np.ndarray, key_bytes: int = 10) -> int:
+    recs = _records(recs)
+    return first_unstable_ptr(recs.ctypes.data, recs.shape[0], recs.shape[1], key_bytes)
 
 
 def multiset_hash(recs: np.ndarray) -> int:
@@ -207,6 +257,14 @@ class RMI:
         return int(lib().oracle_leaf_bucket(int(self.base[j]), float(self.c[j]), float(self.b[j]),
                                             int(self.lo[j]), int(self.hi[j]), int(code)))
 
+    def buckets_of_codes(self, codes: np.ndarray) -> np.ndarray:
+        codes = np.ascontiguousarray(codes, dtype=np.uint64)
+        out = np.empty(codes.size, dtype=np.uint32)
+        lib().oracle_rmi_buckets_codes(_p(codes, _u64p), codes.size, _p(self.root, _f32p), self.L,
+                                       _p(self.base, _u64p), _p(self.c, _f32p), _p(self.b, _f32p),
+                                       _p(self.lo, _u32p), _p(self.hi, _u32p), _p(out, _u32p))
+        return out
+
     def buckets(self, recs: np.ndarray) -> np.ndarray:
         recs = _records(recs)
         out = np.empty(recs.shape[0], dtype=np.uint32)
@@ -223,6 +281,19 @@ def fit_rmi(codes: np.ndarray, L: int, B: int) -> RMI:
                               _p(m.c, _f32p), _p(m.b, _f32p), _p(m.lo, _u32p), _p(m.hi, _u32p))
     if rc != 0:
         raise ValueError("fit_rmi: codes must be sorted and S, L, B > 0")
+    return m
+
+
+def leaves_under_root(codes: np.ndarray, a0: float, a1: float, L: int, B: int) -> RMI:
+    """The RMI whose root is the given (a0, a1) and whose leaves are fitted
+    over the sorted sample as routed by that root (the leaf step of
+    fit_rmi)."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint64)
+    m = RMI(L, B)
+    m.root[:] = [a0, a1]
+    lib().oracle_leaves_under_root(_p(codes, _u64p), codes.size, float(m.root[0]), float(m.root[1]), L, B,
+                                   _p(m.base, _u64p), _p(m.c, _f32p), _p(m.b, _f32p), _p(m.lo, _u32p),
+                                   _p(m.hi, _u32p))
     return m
 
 
@@ -277,3 +348,24 @@ def counts_offsets(buckets: np.ndarray, B: int):
 def opt_max_bucket(codes: np.ndarray, B: int) -> int:
     codes = np.ascontiguousarray(codes, dtype=np.uint64)
     return int(lib().oracle_opt_max_bucket(_p(codes, _u64p), codes.size, B))
+
+
+def sample_gate(max_bucket: int, S: int, B: int, ratio: float):
+    """The linear root's gate: the largest sample bucket against what a
+    perfect model shows on S sample keys, lambda + sqrt(2 ln B lambda) + 1
+    with lambda = S / B (about the largest of B Poisson(lambda) counts).
+    Returns (passed, perfect)."""
+    import math
+    lam = S / B
+    perfect = lam + math.sqrt(2.0 * math.log(B) * lam) + 1.0
+    return max_bucket <= ratio * perfect, perfect
+
+
+def sample_ideal(codes: np.ndarray, B: int) -> int:
+    """The acceptance test's ideal on a sorted sample: max(ceil(S/B), the
+    longest run of equal codes), a lower bound of the best largest bucket
+    (opt_max_bucket computes that optimum itself)."""
+    c = np.asarray(codes, dtype=np.uint64)
+    S = c.size
+    starts = np.flatnonzero(np.concatenate([[True], c[1:] != c[:-1], [True]]))
+    return max(-(-S // B), int(np.diff(starts).max()))

@@ -93,6 +93,23 @@ int oracle_sort_records(const uint8_t* in, uint64_t n, uint32_t rec, uint32_t ke
 
 /* -------------------------------------------------------------- checkers -- */
 
+/* For records whose input index is written as 10 decimal digits right after
+ * the key (bytes [key, key+10)): the index of the first k where (key, index)
+ * of record k is not strictly below that of record k+1, or n when none.  With
+ * fixed-width digits the pair compares as the bytes [0, key+10) in memcmp
+ * order.  Strictly increasing (key, index) plus the input's multiset of
+ * records is the definition of the stable sort, so the two checks together
+ * pin the whole output. */
+uint64_t oracle_first_unstable(const uint8_t* recs, uint64_t n, uint32_t rec, uint32_t key) {
+  uint64_t bad = n;
+  int64_t last = (int64_t)n - 1;
+#pragma omp parallel for reduction(min : bad)
+  for (int64_t k = 0; k < last; ++k)
+    if (memcmp(recs + (uint64_t)k * rec, recs + (uint64_t)(k + 1) * rec, key + 10) >= 0 && (uint64_t)k < bad)
+      bad = (uint64_t)k;
+  return bad;
+}
+
 /* Index of the first k with key(k) > key(k+1), or n when keys never decrease. */
 uint64_t oracle_first_unsorted(const uint8_t* recs, uint64_t n, uint32_t rec, uint32_t key) {
   uint64_t bad = n;
@@ -353,6 +370,32 @@ void oracle_rmi_buckets(const uint8_t* recs, uint64_t n, uint32_t rec, const flo
     uint32_t j = oracle_rmi_leaf(root[0], root[1], L, e);
     out[i] = oracle_leaf_bucket(base[j], c[j], b[j], lo[j], hi[j], e);
   }
+}
+
+/* Bucket of every code under an RMI (codes instead of records: the sample). */
+void oracle_rmi_buckets_codes(const uint64_t* e, uint64_t n, const float* root, uint32_t L, const uint64_t* base,
+                              const float* c, const float* b, const uint32_t* lo, const uint32_t* hi,
+                              uint32_t* out) {
+  for (uint64_t i = 0; i < n; ++i) {
+    uint32_t j = oracle_rmi_leaf(root[0], root[1], L, e[i]);
+    out[i] = oracle_leaf_bucket(base[j], c[j], b[j], lo[j], hi[j], e[i]);
+  }
+}
+
+/* Leaves under a given root (a0, a1): the sorted sample is routed by that
+ * root and each leaf takes the spline over the ranks routed to it, as
+ * oracle_fit_rmi does after its own least-squares root. */
+void oracle_leaves_under_root(const uint64_t* e, uint64_t S, float a0, float a1, uint32_t L, uint32_t B,
+                              uint64_t* base, float* c, float* b, uint32_t* lo, uint32_t* hi) {
+  uint64_t* first = (uint64_t*)malloc(((uint64_t)L + 1) * sizeof(uint64_t));
+  uint64_t s = 0;
+  for (uint32_t j = 0; j <= L; ++j) {
+    while (s < S && oracle_rmi_leaf(a0, a1, L, e[s]) < j) ++s;
+    first[j] = s;
+  }
+  first[L] = S;
+  oracle_spline_leaves(e, S, first, L, B, base, c, b, lo, hi);
+  free(first);
 }
 
 /* counts[j] = #records with bucket j; offsets[j] = sum_{k<j} counts[k], offsets[B] = n. */

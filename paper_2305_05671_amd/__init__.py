@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libelsar.so")
 RMI, MLP, AUTO, RADIX, SPLINE = 0, 1, 2, 3, 4
 MLP_PARAMS = 4801
 MLP_GRAD_ROWS = 128
+MLP_STEPS_NONE = 0xFFFFFFFF
 OK, E_INVALID_ARG, E_NO_MEMORY, E_HIP, E_UNSUPPORTED, E_MODEL_REJECTED = range(6)
 
 
@@ -55,6 +56,11 @@ class ModelInfo(ctypes.Structure):
         ("opt_sample_bucket", ctypes.c_uint32),
         ("mlp_leaves", ctypes.c_uint32),
         ("spline_segments", ctypes.c_uint32),
+        ("rmi_max_sample_bucket", ctypes.c_uint32),
+        ("eq_max_sample_bucket", ctypes.c_uint32),
+        ("net_max_sample_bucket", ctypes.c_uint32),
+        ("rmi_gate_passed", ctypes.c_uint32),
+        ("perfect_sample_bucket", ctypes.c_float),
     ]
 
 
@@ -145,6 +151,7 @@ def lib():
                                  ctypes.POINTER(HostStats)], st),
             "elsar_mlp_forward": ([_P, _P, _P, _U64, _P], st),
             "elsar_mlp_gradient": ([_P, _P, _P, _P, _P, _P], st),
+            "elsar_mlp_train_step": ([_P, _P, _P, _P, _P, ctypes.c_uint32, ctypes.c_float, _P, _P, _P, _P], st),
             "elsar_set_timing": ([ctypes.c_int], st),
             "elsar_timings_get": ([ctypes.POINTER(Timings)], st),
             "elsar_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -436,3 +443,27 @@ def mlp_gradient(params, knots, codes, targets):
     _check("elsar_mlp_gradient", lib().elsar_mlp_gradient(params.ctypes.data, knots.ctypes.data, codes.ctypes.data,
                                                           targets.ctypes.data, g.ctypes.data, loss.ctypes.data))
     return float(loss[0]), g
+
+
+def mlp_train_step(params, adam, knots, codes, targets, step: int, lr: float):
+    """elsar_mlp_train_step: one training step (gradient, then the Adam update
+    of step ``step``).  adam holds the first then the second moments.  Returns
+    (params, adam, grad, loss) after the step."""
+    import numpy as np
+    params = np.ascontiguousarray(params, np.float32)
+    adam = np.ascontiguousarray(adam, np.float32)
+    knots = np.ascontiguousarray(knots, np.uint64)
+    codes = np.ascontiguousarray(codes, np.uint64)
+    targets = np.ascontiguousarray(targets, np.float32)
+    if (params.size != MLP_PARAMS or adam.size != 2 * MLP_PARAMS or knots.size != 9
+            or codes.size != MLP_GRAD_ROWS or targets.size != MLP_GRAD_ROWS):
+        raise ValueError("params 4801, adam 9602, knots 9, codes and targets MLP_GRAD_ROWS each")
+    p_out = np.zeros(MLP_PARAMS, np.float32)
+    a_out = np.zeros(2 * MLP_PARAMS, np.float32)
+    g = np.zeros(MLP_PARAMS, np.float32)
+    loss = np.zeros(1, np.float32)
+    _check("elsar_mlp_train_step",
+           lib().elsar_mlp_train_step(params.ctypes.data, adam.ctypes.data, knots.ctypes.data, codes.ctypes.data,
+                                      targets.ctypes.data, step, lr, p_out.ctypes.data, a_out.ctypes.data,
+                                      g.ctypes.data, loss.ctypes.data))
+    return p_out, a_out, g, float(loss[0])

@@ -222,10 +222,15 @@ elsar_status do_fit(elsar_model* m, const void* d_records, uint64_t n, void* d_w
   HIP_TRY(launch_sample_hist(m->hdr, m->leaves, sorted, S, m->B, m->hist, st));
   if (m->has_mlp) {
     HIP_TRY(launch_auto_gate(m->hist, m->B, S, m->p.accept_ratio, m->p.kind, m->hdr, st));
-    if (m->p.kind == ELSAR_MODEL_MLP)
-      HIP_TRY(launch_mlp_train(sorted, S, m->p.seed, m->p.mlp_steps, kMlpLearningRate, m->ms, st));
+    if (m->p.kind == ELSAR_MODEL_MLP) {
+      const uint32_t steps = m->p.mlp_steps == ELSAR_MLP_STEPS_NONE ? 0u : m->p.mlp_steps;
+      HIP_TRY(launch_mlp_train(sorted, S, m->p.seed, steps, kMlpLearningRate, m->ms, st));
+    }
     HIP_TRY(launch_equi_depth_leaves(sorted, S, m->Lm, m->B, m->hdr, m->ms, st));
-    if (m->p.kind == ELSAR_MODEL_MLP) HIP_TRY(launch_mlp_cell_table(m->ms, m->Lm, st));
+    if (m->p.kind == ELSAR_MODEL_MLP) {
+      HIP_TRY(launch_mlp_cell_table(m->ms, m->Lm, st));
+      HIP_TRY(launch_mlp_net_hist(m->ms, sorted, S, m->B, st));
+    }
   }
   HIP_TRY(launch_decide_root(m->hist, m->has_mlp ? &m->ms : nullptr, m->B, S, m->p.accept_ratio, m->p.kind,
                              m->hdr, m->hist, st));
@@ -1025,6 +1030,11 @@ elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info) 
   info->root_a1 = h.a1;
   info->max_sample_bucket = h.max_sample_bucket;
   info->opt_sample_bucket = h.opt_sample_bucket;
+  info->rmi_max_sample_bucket = h.max_rmi;
+  info->eq_max_sample_bucket = h.max_eq;
+  info->net_max_sample_bucket = h.max_net;
+  info->rmi_gate_passed = h.rmi_ok;
+  info->perfect_sample_bucket = h.perfect;
   return ELSAR_OK;
 }
 
@@ -1132,6 +1142,44 @@ elsar_status elsar_mlp_gradient(const float* h_params, const uint64_t* h_knots, 
   HIP_TRY(hipMemcpy(d_t, h_targets, rows * 4, hipMemcpyHostToDevice));
   HIP_TRY(launch_mlp_grad(M, d_codes, d_t, d_g, d_loss, nullptr));
   HIP_TRY(hipMemcpy(h_grad, d_g, (size_t)kMlpParams * 4, hipMemcpyDeviceToHost));
+  if (h_loss) HIP_TRY(hipMemcpy(h_loss, d_loss, 4, hipMemcpyDeviceToHost));
+  return ELSAR_OK;
+}
+
+elsar_status elsar_mlp_train_step(const float* h_params, const float* h_adam, const uint64_t* h_knots,
+                                  const uint64_t* h_codes, const float* h_targets, uint32_t step, float lr,
+                                  float* h_params_out, float* h_adam_out, float* h_grad, float* h_loss) {
+  if (!h_params || !h_adam || !h_knots || !h_codes || !h_targets || !h_params_out || !h_adam_out)
+    return ELSAR_E_INVALID_ARG;
+  if (step == 0 || !(lr >= 0.0f)) return ELSAR_E_INVALID_ARG;
+  const size_t rows = kMlpGradRows, P = kMlpParams;
+  DevBuf buf;
+  MlpBlock* M = nullptr;
+  uint8_t* rest = nullptr;
+  elsar_status s = mlp_block_from_host(h_params, h_knots, buf,
+                                       align_up(rows * 8) + align_up(rows * 4) + align_up(P * 4) + align_up(P * 8) +
+                                           align_up(P * 4) + 256,
+                                       &M, &rest);
+  if (s != ELSAR_OK) return s;
+  uint64_t* d_codes = reinterpret_cast<uint64_t*>(rest);
+  rest += align_up(rows * 8);
+  float* d_t = reinterpret_cast<float*>(rest);
+  rest += align_up(rows * 4);
+  float* d_p = reinterpret_cast<float*>(rest);
+  rest += align_up(P * 4);
+  float* d_a = reinterpret_cast<float*>(rest);
+  rest += align_up(P * 8);
+  float* d_g = reinterpret_cast<float*>(rest);
+  rest += align_up(P * 4);
+  float* d_loss = reinterpret_cast<float*>(rest);
+  HIP_TRY(hipMemcpy(d_codes, h_codes, rows * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d_t, h_targets, rows * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d_p, h_params, P * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d_a, h_adam, P * 8, hipMemcpyHostToDevice));
+  HIP_TRY(launch_mlp_step(M, d_p, d_a, d_codes, d_t, step, lr, d_g, d_loss, nullptr));
+  HIP_TRY(hipMemcpy(h_params_out, d_p, P * 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(h_adam_out, d_a, P * 8, hipMemcpyDeviceToHost));
+  if (h_grad) HIP_TRY(hipMemcpy(h_grad, d_g, P * 4, hipMemcpyDeviceToHost));
   if (h_loss) HIP_TRY(hipMemcpy(h_loss, d_loss, 4, hipMemcpyDeviceToHost));
   return ELSAR_OK;
 }

@@ -42,6 +42,13 @@ struct ModelHeader {   // device-resident root of a fitted model
   uint32_t mlp_L;           // equi-depth leaves under the MLP or spline root
   uint32_t mlp_skip;        // automatic choice: the linear root passed the gate
   uint32_t spline_K;        // segments of the spline root
+  // acceptance statistics: largest sample bucket under the linear root, under
+  // the equi-depth leaves, and under the network's own buckets
+  // clamp(floor(B y), 0, B-1); whether the linear root passed its gate; the
+  // gate's bound lambda + sqrt(2 ln(B) lambda) + 1, lambda = S/B
+  uint32_t max_rmi, max_eq, max_net, rmi_ok;
+  float perfect;
+  uint32_t pad_[3];
 };
 
 // Monotone MLP root (8 -> 64 -> 64 -> 1), flat parameter order W1 (64x8),
@@ -301,6 +308,7 @@ struct MlpState {
   uint64_t* bound;   // L + 1 routing boundaries: leaf j takes codes in [bound[j], bound[j+1])
   uint32_t* first;   // L + 1: first sample rank of each leaf
   uint32_t* hist;    // B: sample keys per bucket under these leaves
+  uint32_t* hist_net;  // B: sample keys per bucket of the network's own output, floor(B y)
   uint64_t* knots;   // spline_segments(L) + 1 segment knots of the spline root
   uint32_t* cells;   // L + 1: cells[c] = leaves whose MLP cell floor(L y(bound[j])) is below c
   float* master;     // kMlpParams FP32 parameters of the MLP
@@ -311,6 +319,10 @@ void place_mlp_state(MlpState* s, void* base, uint32_t L, uint32_t B);
 // MLP training on the sorted sample (initial weights, Adam steps).
 hipError_t launch_mlp_train(const uint64_t* sorted_codes, uint64_t S, uint64_t seed, uint32_t steps, float lr,
                             const MlpState& ms, hipStream_t st);
+// Histogram of the trained network's own buckets clamp(floor(B y), 0, B-1)
+// over the sorted sample (the MLP's acceptance statistic).
+hipError_t launch_mlp_net_hist(const MlpState& ms, const uint64_t* sorted_codes, uint64_t S, uint32_t B,
+                               hipStream_t st);
 // Key bytes the bucket sorts order by; a longer key is finished by the run fix-up.
 inline uint32_t sort_key_bytes(uint32_t K) { return K < kSortKeyBytes ? K : kSortKeyBytes; }
 // Keys longer than kSortKeyBytes: device scratch of the run fix-up for n
@@ -331,6 +343,10 @@ hipError_t launch_auto_gate(const uint32_t* hist_rmi, uint32_t B, uint64_t S, fl
 hipError_t launch_decide_root(const uint32_t* hist_rmi, const MlpState* ms, uint32_t B, uint64_t S,
                               float accept_ratio, uint32_t kind, ModelHeader* hdr, uint32_t* hist_used,
                               hipStream_t st);
+// One training step on caller rows (verification): gradient, then the Adam
+// update at step `step` (>= 1) of the FP32 parameters and moments, in place.
+hipError_t launch_mlp_step(const MlpBlock* M, float* params, float* adam, const uint64_t* codes,
+                           const float* targets, uint32_t step, float lr, float* grad, float* loss, hipStream_t st);
 hipError_t mlp_prepare_kernels();
 hipError_t launch_mlp_params_to_block(const float* d_params, const uint64_t* d_q9, MlpBlock* M, hipStream_t st);
 hipError_t launch_mlp_eval(const MlpBlock* M, const uint64_t* codes, uint64_t n, float* y, hipStream_t st);

@@ -272,6 +272,8 @@ __global__ __launch_bounds__(kFitThreads) void root_final_kernel(uint64_t S, uin
     hdr->max_sample_run = 0;
     hdr->mlp_L = 0;
     hdr->mlp_skip = 0;
+    hdr->max_rmi = hdr->max_eq = hdr->max_net = hdr->rmi_ok = 0;
+    hdr->perfect = 0.0f;
   }
 }
 
@@ -414,6 +416,8 @@ __global__ void radix_model_kernel(uint64_t S, uint64_t n, uint32_t L, uint32_t 
     hdr->max_sample_run = 0;
     hdr->mlp_L = 0;
     hdr->mlp_skip = 0;
+    hdr->max_rmi = hdr->max_eq = hdr->max_net = hdr->rmi_ok = 0;
+    hdr->perfect = 0.0f;
   }
 }
 
@@ -522,6 +526,9 @@ __device__ void fit_job_block(const FitJob& J, uint32_t rec_bytes, uint64_t* e, 
       h->max_sample_run = 0;
       h->mlp_L = 0;
       h->mlp_skip = 0;
+      h->max_rmi = mm;
+      h->max_eq = h->max_net = h->rmi_ok = 0;
+      h->perfect = 0.0f;
     }
     __syncthreads();
   }

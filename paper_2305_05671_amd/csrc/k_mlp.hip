@@ -32,7 +32,7 @@ inline size_t al(size_t x) { return (x + kA - 1) & ~(kA - 1); }
 
 size_t mlp_state_bytes(uint32_t L, uint32_t B) {
   return al(sizeof(MlpBlock)) + al((size_t)L * sizeof(Leaf)) + al(((size_t)L + 1) * 8) + al(((size_t)L + 1) * 4) +
-         al((size_t)B * 4) + al(((size_t)spline_segments(L) + 1) * 8) + al(((size_t)L + 1) * 4) +
+         2 * al((size_t)B * 4) + al(((size_t)spline_segments(L) + 1) * 8) + al(((size_t)L + 1) * 4) +
          al((size_t)kMlpParams * 4) + al((size_t)kMlpParams * 8);
 }
 
@@ -47,6 +47,8 @@ void place_mlp_state(MlpState* s, void* base, uint32_t L, uint32_t B) {
   s->first = reinterpret_cast<uint32_t*>(b);
   b += al(((size_t)L + 1) * 4);
   s->hist = reinterpret_cast<uint32_t*>(b);
+  b += al((size_t)B * 4);
+  s->hist_net = reinterpret_cast<uint32_t*>(b);
   b += al((size_t)B * 4);
   s->knots = reinterpret_cast<uint64_t*>(b);
   b += al(((size_t)spline_segments(L) + 1) * 8);
@@ -296,6 +298,23 @@ __device__ void clear_grad(TrainLds& sm) {
 // registers for the whole fit.
 constexpr uint32_t kOwn = (kMlpParams + kTrainThreads - 1) / kTrainThreads;
 
+__device__ __forceinline__ bool mlp_nonneg(uint32_t p) {  // W1, W2 and w3 stay >= 0
+  return p < kOffB1 || (p >= kOffW2 && p < kOffB2) || (p >= kOffW3 && p < kOffB3);
+}
+
+// Adam on parameter p with gradient gr: moments m1 <- 0.9 m1 + 0.1 gr and
+// m2 <- 0.999 m2 + 0.001 gr^2, then v - lr (m1 c1) / (sqrt(m2 c2) + 1e-8)
+// with the bias corrections c1 = 1 / (1 - 0.9^t), c2 = 1 / (1 - 0.999^t),
+// projected onto >= 0 for the weights.
+__device__ __forceinline__ float adam_update(uint32_t p, float v, float gr, float& m1, float& m2, float c1, float c2,
+                                             float lr) {
+  m1 = 0.9f * m1 + 0.1f * gr;
+  m2 = 0.999f * m2 + 0.001f * gr * gr;
+  float r = v - lr * (m1 * c1) / (sqrtf(m2 * c2) + 1e-8f);
+  if (mlp_nonneg(p)) r = fmaxf(r, 0.0f);
+  return r;
+}
+
 __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(const uint64_t* __restrict__ e, uint64_t S,
                                                                   uint32_t steps, float lr, uint64_t seed,
                                                                   float* __restrict__ master,
@@ -346,14 +365,8 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(const uint64_t
     for (uint32_t k = 0; k < kOwn; ++k) {
       const uint32_t p = tid + k * kTrainThreads;
       if (p < kMlpParams) {
-        const float gr = sm.G[p];
-        a1[k] = 0.9f * a1[k] + 0.1f * gr;
-        a2[k] = 0.999f * a2[k] + 0.001f * gr * gr;
-        float v = pv[k] - lr * (a1[k] * c1) / (sqrtf(a2[k] * c2) + 1e-8f);
-        const bool nonneg = p < kOffB1 || (p >= kOffW2 && p < kOffB2) || (p >= kOffW3 && p < kOffB3);
-        if (nonneg) v = fmaxf(v, 0.0f);
-        pv[k] = v;
-        publish_one(p, v, &sm.M);
+        pv[k] = adam_update(p, pv[k], sm.G[p], a1[k], a2[k], c1, c2, lr);
+        publish_one(p, pv[k], &sm.M);
       }
     }
     __syncthreads();
@@ -396,6 +409,47 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_grad_kernel(const MlpBlock*
   __syncthreads();
   step_grad(sm);
   for (uint32_t p = tid; p < kMlpParams; p += kTrainThreads) grad[p] = sm.G[p];
+  if (tid == 0) *loss = sm.loss;
+}
+
+// One training step on caller-supplied rows, for verification: the gradient
+// of mlp_grad_kernel, then the training kernel's Adam update at step `step`
+// (the bias corrections from beta^step accumulated the way training does)
+// applied to params and adam (moments m then v) in place.
+__global__ __launch_bounds__(kTrainThreads) void mlp_step_kernel(const MlpBlock* __restrict__ Mg,
+                                                                 float* __restrict__ params, float* __restrict__ adam,
+                                                                 const uint64_t* __restrict__ codes,
+                                                                 const float* __restrict__ targets, uint32_t step,
+                                                                 float lr, float* __restrict__ grad,
+                                                                 float* __restrict__ loss) {
+  extern __shared__ uint4 lds_raw[];
+  TrainLds& sm = *reinterpret_cast<TrainLds*>(lds_raw);
+  const uint32_t tid = threadIdx.x;
+  load_block(Mg, sm.M);
+  clear_grad(sm);
+  __syncthreads();
+  if (tid < kRows) {
+    sm.T[tid] = targets[tid];
+    float phi[8];
+    mlp_features(codes[tid], sm.M.h, phi);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sm.PHI[tid * 8 + k] = phi[k];
+  }
+  __syncthreads();
+  step_grad(sm);
+  float p1 = 1.0f, p2 = 1.0f;
+  for (uint32_t t = 0; t < step; ++t) {
+    p1 *= 0.9f;
+    p2 *= 0.999f;
+  }
+  const float c1 = 1.0f / (1.0f - p1), c2 = 1.0f / (1.0f - p2);
+  for (uint32_t p = tid; p < kMlpParams; p += kTrainThreads) {
+    float m1 = adam[p], m2 = adam[kMlpParams + p];
+    params[p] = adam_update(p, params[p], sm.G[p], m1, m2, c1, c2, lr);
+    adam[p] = m1;
+    adam[kMlpParams + p] = m2;
+    grad[p] = sm.G[p];
+  }
   if (tid == 0) *loss = sm.loss;
 }
 
@@ -561,10 +615,42 @@ __global__ __launch_bounds__(256) void mlp_sample_stats_kernel(const uint64_t* _
   }
 }
 
-// Automatic choice: the linear root is kept when its largest sample bucket is
-// within accept_ratio of what a perfect model shows on S sample keys,
-// lambda + sqrt(2 ln(B) lambda) + 1 with lambda = S/B (about the largest of B
-// Poisson(lambda) counts); otherwise the spline root takes over.  One block.
+// The network's own buckets on the sorted sample: b = clamp(floor(B y), 0,
+// B-1) of every sample code, counted per bucket (one add per run of equal
+// buckets within a wave).  This is the MLP's acceptance statistic: it judges
+// the network itself, independently of the equi-depth leaves that route the
+// records once the network is accepted.  Every lane takes part in the
+// evaluation; lanes past the sample repeat the last code and add nothing.
+__global__ __launch_bounds__(256) void mlp_net_hist_kernel(const MlpBlock* __restrict__ Mg,
+                                                           const uint64_t* __restrict__ e, uint64_t S, uint32_t B,
+                                                           uint32_t* __restrict__ hist_net) {
+  __shared__ MlpHead mh;
+  load_head(Mg, mh);
+  MlpFrags w;
+  mlp_load_frags(Mg, w);
+  __syncthreads();
+  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = s < S;
+  const float y = mlp_y64(e[in ? s : S - 1], mh, w);
+  const uint32_t b = mlp_leaf_guess(y, B);
+  const uint32_t l = __lane_id();
+  const uint32_t bl = __shfl_up(b, 1), br = __shfl_down(b, 1);
+  const bool start = in && (l == 0 || bl != b);
+  const bool last = in && (l == 63 || br != b || s + 1 == S);
+  const uint64_t starts = __ballot(start);
+  if (last) {
+    const uint64_t below = starts & (l == 63 ? ~0ull : ((2ull << l) - 1));  // starts at lanes <= l
+    const uint32_t first_lane = 63u - (uint32_t)__clzll((long long)below);
+    atomicAdd(&hist_net[b], l + 1 - first_lane);
+  }
+}
+
+// Gate of the linear root, for every kind with equi-depth leaves: the linear
+// root passes when its largest sample bucket is within accept_ratio of what a
+// perfect model shows on S sample keys, lambda + sqrt(2 ln(B) lambda) + 1 with
+// lambda = S/B (about the largest of B Poisson(lambda) counts).  Under the
+// automatic choice a passing linear root is kept and the equi-depth leaves are
+// not fitted (mlp_skip).  One block.
 __global__ __launch_bounds__(256) void auto_gate_kernel(const uint32_t* __restrict__ hist_rmi, uint32_t B,
                                                         uint64_t S, float accept_ratio, uint32_t kind,
                                                         ModelHeader* __restrict__ hdr) {
@@ -580,58 +666,70 @@ __global__ __launch_bounds__(256) void auto_gate_kernel(const uint32_t* __restri
   if (threadIdx.x == 0) {
     const double lambda = (double)S / (double)B;
     const double perfect = lambda + sqrt(2.0 * log((double)B) * lambda) + 1.0;
-    hdr->mlp_skip = (kind == 2u && (double)mr[0] <= (double)accept_ratio * perfect) ? 1u : 0u;
+    const bool ok = (double)mr[0] <= (double)accept_ratio * perfect;
+    hdr->max_rmi = mr[0];
+    hdr->perfect = (float)perfect;
+    hdr->rmi_ok = ok ? 1u : 0u;
+    hdr->mlp_skip = (kind == 2u && ok) ? 1u : 0u;
   }
 }
 
 // Choice of the root.  hist_eq: the sample histogram under the equi-depth
-// leaves (MLP and spline roots share them).  kind 1 (MLP): the MLP if its
-// largest sample bucket is at most accept_ratio times the ideal
-// max(ceil(S/B), longest equal-code run), else the linear root.  kind 2
-// (automatic): the linear root if it passed the gate, else the spline root.
-// kind 4 (spline): the spline root.  The chosen root's sample histogram is
-// copied to hist_used.
+// leaves (MLP and spline roots share them); hist_net: the network's own
+// buckets (kind MLP).  The ideal is max(ceil(S/B), longest equal-code run).
+//  kind 1 (MLP): the network is accepted if its own largest sample bucket is
+//    at most accept_ratio times the ideal; records are then routed by the
+//    network into the equi-depth leaves.  Otherwise the plain model takes
+//    over, as the automatic choice picks it: the linear root if it passed its
+//    gate, else the spline root.
+//  kind 2 (automatic): the linear root if it passed its gate, else the spline.
+//  kind 4 (spline): the spline root.  Kinds 0 and 3: the linear root.
+// The chosen root's sample histogram is copied to hist_used; the three
+// largest sample buckets are recorded.
 constexpr uint32_t kDecideThreads = 1024;
 
 __global__ __launch_bounds__(kDecideThreads) void decide_root_kernel(const uint32_t* __restrict__ hist_rmi,
-                                                                     const uint32_t* __restrict__ hist_mlp, uint32_t B,
+                                                                     const uint32_t* __restrict__ hist_eq,
+                                                                     const uint32_t* __restrict__ hist_net, uint32_t B,
                                                                      uint64_t S, float accept_ratio, uint32_t kind,
                                                                      ModelHeader* __restrict__ hdr,
                                                                      uint32_t* __restrict__ hist_used) {
-  __shared__ uint32_t mr[kDecideThreads / 64], mm[kDecideThreads / 64];
-  __shared__ uint32_t use_mlp;
-  uint32_t a = 0, b = 0;
+  constexpr uint32_t W = kDecideThreads / 64;
+  __shared__ uint32_t mr[W], me[W], mn[W];
+  __shared__ uint32_t use_eq;
+  uint32_t a = 0, b = 0, c = 0;
 #pragma unroll 4
   for (uint32_t j = threadIdx.x; j < B; j += kDecideThreads) {
     a = hist_rmi[j] > a ? hist_rmi[j] : a;
-    if (hist_mlp) b = hist_mlp[j] > b ? hist_mlp[j] : b;
+    if (hist_eq) b = hist_eq[j] > b ? hist_eq[j] : b;
+    if (hist_net) c = hist_net[j] > c ? hist_net[j] : c;
   }
   for (int off = 32; off > 0; off >>= 1) {
-    const uint32_t x = __shfl_xor(a, off), y = __shfl_xor(b, off);
+    const uint32_t x = __shfl_xor(a, off), y = __shfl_xor(b, off), z = __shfl_xor(c, off);
     a = x > a ? x : a;
     b = y > b ? y : b;
+    c = z > c ? z : c;
   }
   if (__lane_id() == 0) {
     mr[threadIdx.x >> 6] = a;
-    mm[threadIdx.x >> 6] = b;
+    me[threadIdx.x >> 6] = b;
+    mn[threadIdx.x >> 6] = c;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (uint32_t w = 1; w < kDecideThreads / 64; ++w) {
+    for (uint32_t w = 1; w < W; ++w) {
       mr[0] = mr[w] > mr[0] ? mr[w] : mr[0];
-      mm[0] = mm[w] > mm[0] ? mm[w] : mm[0];
+      me[0] = me[w] > me[0] ? me[w] : me[0];
+      mn[0] = mn[w] > mn[0] ? mn[w] : mn[0];
     }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
     uint32_t ideal = (uint32_t)((S + B - 1) / B);
-    if (hist_mlp && hdr->max_sample_run > ideal) ideal = hdr->max_sample_run;
+    if (hist_eq && hdr->max_sample_run > ideal) ideal = hdr->max_sample_run;
     uint32_t u = 0, rejected = 0;
-    if (hist_mlp) {
+    if (hist_eq) {
       if (kind == 1u) {
-        const bool pass = (double)mm[0] <= (double)accept_ratio * (double)ideal;
+        const bool pass = hist_net && (double)mn[0] <= (double)accept_ratio * (double)ideal;
         rejected = pass ? 0u : 1u;
-        u = pass ? 1u : 0u;
+        u = pass ? 1u : (hdr->rmi_ok ? 0u : 2u);
       } else if (kind == 2u) {
         u = hdr->mlp_skip ? 0u : 2u;
       } else if (kind == 4u) {
@@ -640,13 +738,16 @@ __global__ __launch_bounds__(kDecideThreads) void decide_root_kernel(const uint3
     }
     hdr->kind_used = u;
     hdr->mlp_rejected = rejected;
-    hdr->max_sample_bucket = u ? mm[0] : mr[0];
+    hdr->max_rmi = mr[0];
+    hdr->max_eq = hist_eq ? me[0] : 0u;
+    hdr->max_net = hist_net ? mn[0] : 0u;
+    hdr->max_sample_bucket = u ? me[0] : mr[0];
     hdr->opt_sample_bucket = ideal;
-    use_mlp = u;
+    use_eq = u;
   }
   __syncthreads();
-  if (use_mlp)
-    for (uint32_t j = threadIdx.x; j < B; j += kDecideThreads) hist_used[j] = hist_mlp[j];
+  if (use_eq)
+    for (uint32_t j = threadIdx.x; j < B; j += kDecideThreads) hist_used[j] = hist_eq[j];
 }
 
 // ------------------------------------------------------------------- host --
@@ -660,6 +761,7 @@ hipError_t mlp_prepare_kernels() {
   static hipError_t once = [] {
     hipError_t e = allow_big_lds(reinterpret_cast<const void*>(mlp_train_kernel));
     if (e == hipSuccess) e = allow_big_lds(reinterpret_cast<const void*>(mlp_grad_kernel));
+    if (e == hipSuccess) e = allow_big_lds(reinterpret_cast<const void*>(mlp_step_kernel));
     return e;
   }();
   return once;
@@ -707,8 +809,24 @@ hipError_t launch_auto_gate(const uint32_t* hist_rmi, uint32_t B, uint64_t S, fl
 hipError_t launch_decide_root(const uint32_t* hist_rmi, const MlpState* ms, uint32_t B, uint64_t S,
                               float accept_ratio, uint32_t kind, ModelHeader* hdr, uint32_t* hist_used,
                               hipStream_t st) {
-  decide_root_kernel<<<1, kDecideThreads, 0, st>>>(hist_rmi, ms ? ms->hist : nullptr, B, S, accept_ratio, kind, hdr,
-                                        hist_used);
+  const uint32_t* hist_net = (ms && kind == 1u) ? ms->hist_net : nullptr;
+  decide_root_kernel<<<1, kDecideThreads, 0, st>>>(hist_rmi, ms ? ms->hist : nullptr, hist_net, B, S, accept_ratio,
+                                                   kind, hdr, hist_used);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_net_hist(const MlpState& ms, const uint64_t* e, uint64_t S, uint32_t B, hipStream_t st) {
+  hipError_t err = launch_fill_u32(ms.hist_net, B, 0u, st);
+  if (err != hipSuccess || S == 0) return err;
+  mlp_net_hist_kernel<<<(uint32_t)((S + 255) / 256), 256, 0, st>>>(ms.M, e, S, B, ms.hist_net);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_step(const MlpBlock* M, float* params, float* adam, const uint64_t* codes,
+                           const float* targets, uint32_t step, float lr, float* grad, float* loss, hipStream_t st) {
+  hipError_t err = mlp_prepare_kernels();
+  if (err != hipSuccess) return err;
+  mlp_step_kernel<<<1, kTrainThreads, sizeof(TrainLds), st>>>(M, params, adam, codes, targets, step, lr, grad, loss);
   return hipGetLastError();
 }
 

@@ -1,23 +1,88 @@
 """What the trained network gains over the method without it.
 
-Skewed keys with hot keys (the c3 law), same seed, same B and L: the
-partition under the MLP root against the partition under the linear root.
-The gain measured is balance: the largest bucket and the largest sample
-bucket.  Both partitions are exact (the sort is checked elsewhere); this test
-records what the learned root changes."""
+Three comparisons on the same input, seed, B and L:
+
+* trained against untrained network (mlp_steps 16 and 100 against
+  ELSAR_MLP_STEPS_NONE): the network's fit to the sample's empirical CDF (its
+  MSE), the distance of its leaf guess floor(L y) from the record's exact
+  leaf (what the router must search), and the largest bucket of its own
+  output floor(B y) (the acceptance statistic);
+* the MLP root against the spline root: both route into the same
+  equi-depth leaves, so their bucket counts are identical -- the network
+  decides how a record's leaf is found, not which leaf it is;
+* the MLP root (forced past its acceptance test) against the linear root on
+  the skewed law with hot keys: the balance gained by the equi-depth leaves
+  the learned root routes into.
+"""
 import numpy as np
 import pytest
 
 import datagen
+import oracle
+from oracle import mlp
 
 pytestmark = pytest.mark.gpu
 
 
-def _stats(torch, elsar, d, n, **kw):
+def _fit(torch, elsar, d, n, **kw):
     m = elsar.Model(n, elsar.fit_params(**kw))
     m.sample_fit(d)
     part, offsets = m.partition(d)
     torch.cuda.synchronize()
+    return m, part, offsets
+
+
+def _network_quality(elsar, m, codes):
+    params, knots, bound, first = m.mlp()
+    q, w = mlp.knots(codes)
+    P = mlp.unpack(params.astype(np.float64))
+    y = mlp.forward(P, mlp.features(codes, q, w), bf16_layer2=True)["y"]
+    S = codes.size
+    L = m.info().mlp_leaves
+    mse = float(np.mean((y - np.arange(S) / S) ** 2))
+    leaf = np.searchsorted(first[:L], np.arange(S), side="right") - 1
+    miss = float(np.median(np.abs(mlp.leaf_guess(y, L) - leaf)))
+    return mse, miss, m.info().net_max_sample_bucket
+
+
+@pytest.mark.parametrize("kind,n,B", [("skewed", 2_000_000, 1024), ("uniform", 1_000_000, 1024)])
+def test_trained_network_against_untrained(kind, n, B):
+    import torch
+    import paper_2305_05671_amd as elsar
+    recs = datagen.generate(datagen.spec(kind, seed=2), n)
+    d = torch.from_numpy(recs.reshape(-1)).to("cuda")
+    codes = oracle.sample_codes(recs, seed=2)
+    res = {}
+    for steps in (elsar.MLP_STEPS_NONE, 16, 100):
+        m, _, offsets = _fit(torch, elsar, d, n, num_buckets=B, seed=2, kind=elsar.MLP, accept_ratio=1e9,
+                             mlp_steps=steps)
+        assert m.info().kind_used == elsar.MLP
+        res[steps] = _network_quality(elsar, m, codes) + (offsets.cpu().numpy(),)
+    none, s16, s100 = res[elsar.MLP_STEPS_NONE], res[16], res[100]
+    print(f"\n{kind} n={n} B={B}: MSE to rank/S untrained {none[0]:.2e}, 16 steps {s16[0]:.2e}, "
+          f"100 steps {s100[0]:.2e}; median leaf miss {none[1]:.0f} / {s16[1]:.0f} / {s100[1]:.0f} of {B}; "
+          f"network's own largest bucket {none[2]} / {s16[2]} / {s100[2]} (ideal {-(-codes.size // B)})")
+    # training fits the CDF and narrows the router's search
+    assert s16[0] < 0.5 * none[0] and s100[0] < s16[0]
+    assert s100[1] < none[1]
+    # the buckets themselves are the equi-depth leaves' whatever the network
+    assert np.array_equal(none[3], s16[3]) and np.array_equal(s16[3], s100[3])
+
+
+def test_mlp_root_and_spline_root_share_buckets():
+    import torch
+    import paper_2305_05671_amd as elsar
+    n, B = 1_000_000, 2048
+    recs = datagen.generate(datagen.spec("skewed", seed=5), n)
+    d = torch.from_numpy(recs.reshape(-1)).to("cuda")
+    m_m, _, off_m = _fit(torch, elsar, d, n, num_buckets=B, seed=5, kind=elsar.MLP, accept_ratio=1e9)
+    m_s, _, off_s = _fit(torch, elsar, d, n, num_buckets=B, seed=5, kind=elsar.SPLINE)
+    assert m_m.info().kind_used == elsar.MLP and m_s.info().kind_used == elsar.SPLINE
+    assert np.array_equal(off_m.cpu().numpy(), off_s.cpu().numpy())
+
+
+def _stats(torch, elsar, d, n, **kw):
+    m, part, offsets = _fit(torch, elsar, d, n, **kw)
     st = m.partition_stats(part)
     info = m.info()
     counts = np.diff(offsets.cpu().numpy())
@@ -35,7 +100,7 @@ def test_mlp_root_balances_skewed_buckets(n, B):
     assert info_r.kind_used == elsar.RMI and info_m.kind_used == elsar.MLP
     ideal = n / B
     cv = lambda c: float(np.std(c) / np.mean(c))
-    print(f"\\nn={n} B={B}: largest bucket RMI {st_r.max_bucket} ({st_r.max_bucket / ideal:.1f}x ideal), "
+    print(f"\nn={n} B={B}: largest bucket RMI {st_r.max_bucket} ({st_r.max_bucket / ideal:.1f}x ideal), "
           f"MLP {st_m.max_bucket} ({st_m.max_bucket / ideal:.1f}x); largest sample bucket RMI "
           f"{info_r.max_sample_bucket}, MLP {info_m.max_sample_bucket} (ideal {info_m.opt_sample_bucket}); "
           f"CV RMI {cv(c_r):.2f}, MLP {cv(c_m):.2f}; records in buckets > 6144: RMI {st_r.big_records}, "

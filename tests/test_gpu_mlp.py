@@ -182,17 +182,16 @@ def test_mlp_edge_sizes(env, n):
         assert np.array_equal(got, oracle.sort_records(recs)), kind
 
 
-def test_rejection_falls_back_to_rmi(env):
+def test_rejection_falls_back_to_plain_model(env):
     torch, elsar = env
+    # a ratio no model can meet, on skewed keys: the network is rejected, the
+    # linear root fails its gate too, and the spline root takes over
     recs = datagen.generate(datagen.spec("skewed", seed=8), 200_000)
-    # a ratio no model can meet: the linear root is kept
     m, part, offsets, d = _fit(env, recs, num_buckets=512, kind=elsar.MLP, accept_ratio=1e-6)
     info = m.info()
-    assert m.rejected and info.kind_used == elsar.RMI and info.mlp_rejected == 1
-    ref = oracle.RMI(info.num_leaves, 512)
-    ref.root[:] = [info.root_a0, info.root_a1]
-    ref.base[:], ref.c[:], ref.b[:], ref.lo[:], ref.hi[:] = m.leaves()
-    _, want = oracle.counts_offsets(ref.buckets(recs), 512)
+    assert m.rejected and info.kind_used == elsar.SPLINE and info.mlp_rejected == 1
+    _, bound, _ = m.spline()
+    _, want = oracle.counts_offsets(oracle.routed_leaves(recs, bound), 512)
     assert np.array_equal(offsets.cpu().numpy().astype(np.uint64), want)
     out = torch.empty_like(d)
     m.sort_buckets(part, offsets, recs.shape[0], out)
@@ -200,6 +199,132 @@ def test_rejection_falls_back_to_rmi(env):
     assert np.array_equal(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs))
     assert np.array_equal(_sort(env, recs, num_buckets=512, kind=elsar.MLP, accept_ratio=1e-6),
                           oracle.sort_records(recs))
+    # uniform keys with the default ratio: the untrained network is rejected,
+    # the linear root passes its gate and is kept
+    recs = datagen.generate(datagen.spec("uniform", seed=9), 200_000)
+    m, part, offsets, d = _fit(env, recs, num_buckets=512, kind=elsar.MLP, mlp_steps=elsar.MLP_STEPS_NONE)
+    info = m.info()
+    assert m.rejected and info.kind_used == elsar.RMI and info.rmi_gate_passed == 1
+    ref = oracle.RMI(info.num_leaves, 512)
+    ref.root[:] = [info.root_a0, info.root_a1]
+    ref.base[:], ref.c[:], ref.b[:], ref.lo[:], ref.hi[:] = m.leaves()
+    _, want = oracle.counts_offsets(ref.buckets(recs), 512)
+    assert np.array_equal(offsets.cpu().numpy().astype(np.uint64), want)
+    assert np.array_equal(_sort(env, recs, num_buckets=512, kind=elsar.MLP, mlp_steps=elsar.MLP_STEPS_NONE),
+                          oracle.sort_records(recs))
+
+
+def test_train_step_matches_oracle(env):
+    # One training step through the C ABI against the oracle.  (a) The Adam
+    # arithmetic: the oracle's adam_step applied to the GPU's own gradient
+    # reproduces the GPU's parameters and moments to FP32 rounding, at steps
+    # 1, 2, 3 and 10 (bias corrections, moments, projection).  (b) The whole
+    # step: the oracle's gradient (same bfloat16 rounding points) and Adam give
+    # the GPU's parameters within 1e-4 relative at step 1, for every parameter
+    # whose gradient is clear of zero (the step is lr * sign(g) there).
+    _, elsar = env
+    _, codes = _codes("skewed", 200_000, 4)
+    q, w = mlp.knots(codes)
+    rng = np.random.default_rng(9)
+    N = mlp.N_PARAMS
+    flat = _params32(mlp.initial_params(rng.uniform(0, 1, N)))
+    adam = np.zeros(2 * N, np.float32)
+    lr = 0.01
+    for step in (1, 2, 3, 10):
+        idx = rng.integers(0, codes.size, elsar.MLP_GRAD_ROWS)
+        x, t = codes[idx], (idx / codes.size).astype(np.float32)
+        p_out, a_out, g, loss = elsar.mlp_train_step(flat, adam, q, x, t, step, lr)
+        P, M, V = _P64(flat), mlp.unpack(adam[:N].astype(np.float64)), mlp.unpack(adam[N:].astype(np.float64))
+        mlp.adam_step(P, M, V, mlp.unpack(g.astype(np.float64)), step, lr)
+        want_p, want_m, want_v = mlp.pack(P), mlp.pack(M), mlp.pack(V)
+        assert np.allclose(p_out, want_p, rtol=1e-5, atol=1e-7), step
+        assert np.allclose(a_out[:N], want_m, rtol=1e-5, atol=1e-6 * np.abs(want_m).max()), step
+        assert np.allclose(a_out[N:], want_v, rtol=1e-5, atol=1e-6 * np.abs(want_v).max()), step
+        if step == 1:
+            Pd = _P64(flat)
+            _, go = mlp.loss_and_grads(Pd, mlp.features(x, q, w), t.astype(np.float64), bf16_layer2=True,
+                                       bf16_dz2=True)
+            Z = {k: np.zeros_like(v) for k, v in Pd.items()}
+            mlp.adam_step(Pd, Z, {k: np.zeros_like(v) for k, v in Pd.items()}, go, 1, lr)
+            gof = mlp.pack(go)
+            clear = np.zeros(N, bool)
+            o = 0
+            for k, shp in mlp.PARAM_SHAPES.items():
+                n_k = int(np.prod(shp))
+                blk = np.abs(gof[o:o + n_k])
+                clear[o:o + n_k] = blk > 0.05 * blk.max()
+                o += n_k
+            full = mlp.pack(Pd)
+            rel = np.abs(p_out[clear] - full[clear]) / np.maximum(np.abs(full[clear]), lr)
+            assert clear.sum() > N // 2 and rel.max() <= 1e-4, rel.max()
+        flat, adam = p_out, a_out
+
+
+def _oracle_stats(elsar, m, recs, seed, B):
+    """What the oracle computes on its own sample for the GPU's fitted model:
+    the largest sample bucket under the linear root (leaves refitted under the
+    GPU's root), under the equi-depth leaves (the GPU's boundaries), and under
+    the network's own buckets (the GPU's trained parameters, FP64 forward with
+    the kernels' bfloat16 rounding points); the ideal and the perfect bound."""
+    codes = oracle.sample_codes(recs, seed=seed)
+    S = codes.size
+    info = m.info()
+    rmi = oracle.leaves_under_root(codes, info.root_a0, info.root_a1, max(1, B // 16), B)
+    h_rmi = np.bincount(rmi.buckets_of_codes(codes), minlength=B)
+    params, knots, bound, first = m.mlp()
+    L = info.mlp_leaves
+    h_eq = np.bincount(np.searchsorted(bound[:L], codes, side="right") - 1, minlength=B)
+    q, w = mlp.knots(codes)
+    y = mlp.forward(_P64(params), mlp.features(codes, q, w), bf16_layer2=True)["y"]
+    h_net = np.bincount(np.clip(np.floor(y * B), 0, B - 1).astype(np.int64), minlength=B)
+    _, perfect = oracle.sample_gate(0, S, B, 1.0)
+    return dict(rmi=int(h_rmi.max()), eq=int(h_eq.max()), net=int(h_net.max()),
+                ideal=oracle.sample_ideal(codes, B), perfect=perfect, codes=codes)
+
+
+@pytest.mark.parametrize("kind,sigma,n,B,seed", [("skewed", 6.0, 1_000_000, 1024, 2),
+                                                 ("skewed", 16.0, 400_000, 1024, 3),
+                                                 ("uniform", 6.0, 500_000, 512, 4)])
+def test_acceptance_statistics_and_decisions(env, kind, sigma, n, B, seed):
+    # The device's acceptance statistics against the oracle's on the oracle's
+    # sample, then the decisions with the threshold placed 5% either side of
+    # each statistic: the network's own largest bucket over the ideal (kind
+    # MLP), and the linear root's largest bucket over the perfect bound (the
+    # automatic choice, and kind MLP's fallback).
+    _, elsar = env
+    recs = datagen.generate(datagen.spec(kind, seed=seed, sigma=sigma), n)
+    m, *_ = _fit(env, recs, num_buckets=B, seed=seed, kind=elsar.MLP)
+    info = m.info()
+    o = _oracle_stats(elsar, m, recs, seed, B)
+    assert info.sample_size == o["codes"].size
+    assert info.opt_sample_bucket == o["ideal"]
+    assert info.perfect_sample_bucket == pytest.approx(o["perfect"], rel=1e-6)
+    assert info.rmi_max_sample_bucket == o["rmi"]
+    assert info.eq_max_sample_bucket == o["eq"]
+    # the network's buckets may differ where B*y lies within FP32-vs-FP64
+    # evaluation error of an integer; its largest bucket moves by a few at most
+    assert abs(int(info.net_max_sample_bucket) - o["net"]) <= max(2, o["net"] // 100)
+    # default ratio: decision as the oracle's statistics give it
+    net_pass = o["net"] <= 1.5 * o["ideal"]
+    rmi_pass = o["rmi"] <= 1.5 * o["perfect"]
+    want = elsar.MLP if net_pass else (elsar.RMI if rmi_pass else elsar.SPLINE)
+    assert info.kind_used == want and info.mlp_rejected == (0 if net_pass else 1)
+    assert info.rmi_gate_passed == (1 if rmi_pass else 0)
+    # kind MLP at 5% either side of the network's statistic
+    r = info.net_max_sample_bucket / o["ideal"]
+    m_hi, *_ = _fit(env, recs, num_buckets=B, seed=seed, kind=elsar.MLP, accept_ratio=1.05 * r)
+    m_lo, *_ = _fit(env, recs, num_buckets=B, seed=seed, kind=elsar.MLP, accept_ratio=0.95 * r)
+    assert m_hi.info().kind_used == elsar.MLP and not m_hi.rejected
+    assert m_lo.rejected and m_lo.info().kind_used in (elsar.RMI, elsar.SPLINE)
+    # the automatic choice at 5% either side of the linear root's statistic
+    r = o["rmi"] / o["perfect"]
+    a_hi, *_ = _fit(env, recs, num_buckets=B, seed=seed, kind=elsar.AUTO, accept_ratio=1.05 * r)
+    a_lo, *_ = _fit(env, recs, num_buckets=B, seed=seed, kind=elsar.AUTO, accept_ratio=0.95 * r)
+    assert a_hi.info().kind_used == elsar.RMI and a_hi.info().rmi_gate_passed == 1
+    assert a_lo.info().kind_used == elsar.SPLINE and a_lo.info().rmi_gate_passed == 0
+    print(f"\n{kind} sigma={sigma} n={n} B={B}: network {info.net_max_sample_bucket} / ideal {o['ideal']} "
+          f"(oracle {o['net']}), linear root {o['rmi']} / perfect {o['perfect']:.1f}, "
+          f"equi-depth {o['eq']}; kind MLP -> {info.kind_used}")
 
 
 def test_auto_choice(env):

@@ -2,7 +2,8 @@
 
 Final output: byte-exact against the oracle's stable memcmp sort.  Model fit:
 root parameters within 1e-6 relative of the oracle's FP64 fit (the two sum in
-different orders), leaves bit-exact when the roots agree.  Bucket ids: the
+different orders), leaves bit-exact against the oracle's leaves fitted under
+the GPU's own root.  Bucket ids: the
 oracle's FP32 evaluation of the GPU's own parameters gives exactly the GPU's
 bucket counts.
 """
@@ -136,10 +137,13 @@ def test_fit_matches_oracle(env, kind, n, B, seed):
     assert info.sample_size == oracle.sample_size(n)
     assert info.root_a1 == pytest.approx(float(ref.root[1]), rel=1e-6)
     assert info.root_a0 == pytest.approx(float(ref.root[0]), rel=1e-6, abs=1e-6)
+    # the leaves bit-exact against the oracle's leaf fit under the GPU's own
+    # root (the roots themselves may differ in the last bit: FP64 sums in
+    # another order)
     base, c, b, lo, hi = m.leaves()
-    if info.root_a0 == ref.root[0] and info.root_a1 == ref.root[1]:
-        assert np.array_equal(base, ref.base) and np.array_equal(lo, ref.lo) and np.array_equal(hi, ref.hi)
-        assert np.array_equal(c, ref.c) and np.array_equal(b, ref.b)
+    own = oracle.leaves_under_root(oracle.sample_codes(recs, seed=seed), info.root_a0, info.root_a1, L, B)
+    assert np.array_equal(base, own.base) and np.array_equal(lo, own.lo) and np.array_equal(hi, own.hi)
+    assert np.array_equal(c, own.c) and np.array_equal(b, own.b)
 
 
 @pytest.mark.parametrize("kind,n,B,seed", [("uniform", 1_000_000, 1024, 0), ("skewed", 400_000, 2048, 2),

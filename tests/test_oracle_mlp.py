@@ -93,6 +93,56 @@ def test_adam_projection_keeps_weights_nonnegative():
         assert P[k].min() >= 0
 
 
+def test_adam_step_closed_form():
+    # Step 1 from zero moments: m = 0.1 g and v = 0.001 g^2, and the bias
+    # corrections 1/(1 - 0.9) and 1/(1 - 0.999) give back g and g^2, so every
+    # parameter moves by -lr g / (|g| + eps).  Step 2 with gradient h:
+    # m = 0.09 g + 0.1 h, v = 0.000999 g^2 + 0.001 h^2, corrected by
+    # 1/(1 - 0.81) and 1/(1 - 0.998001).  W1, W2, w3 are then clipped at 0,
+    # the biases are not.
+    lr, eps = 0.05, 1e-8
+    P = {k: np.full(s, 0.02) for k, s in mlp.PARAM_SHAPES.items()}
+    P["b1"][:] = -0.02
+    m = {k: np.zeros(s) for k, s in mlp.PARAM_SHAPES.items()}
+    v = {k: np.zeros(s) for k, s in mlp.PARAM_SHAPES.items()}
+    g = {k: np.full(s, 3.0) for k, s in mlp.PARAM_SHAPES.items()}
+    g["b2"][:] = -2.0
+    g["w3"][:] = 1e-9  # comparable to eps: the step shrinks to lr * g / (g + eps) = lr / 11
+    mlp.adam_step(P, m, v, g, 1, lr)
+    assert np.allclose(P["W2"], 0.0)                        # 0.02 - 0.05 < 0: clipped
+    assert np.allclose(P["b1"], -0.02 - lr * 3 / (3 + eps))  # bias: not clipped
+    assert np.allclose(P["b2"], 0.02 + lr * 2 / (2 + eps))
+    assert np.allclose(P["w3"], 0.02 - lr * 1e-9 / (1e-9 + eps), rtol=1e-12)
+    assert np.allclose(m["W1"], 0.3) and np.allclose(v["W1"], 0.009)
+    h = {k: np.full(s, -1.0) for k, s in mlp.PARAM_SHAPES.items()}
+    before = {k: x.copy() for k, x in P.items()}
+    mlp.adam_step(P, m, v, h, 2, lr)
+    m2 = 0.09 * 3 + 0.1 * -1.0
+    v2 = 0.000999 * 9 + 0.001 * 1.0
+    step = lr * (m2 / (1 - 0.9 ** 2)) / (np.sqrt(v2 / (1 - 0.999 ** 2)) + eps)
+    assert np.allclose(m["b1"], m2) and np.allclose(v["b1"], v2)
+    assert np.allclose(P["b1"], before["b1"] - step, rtol=1e-12, atol=0)
+    assert np.allclose(P["W1"], np.maximum(before["W1"] - step, 0.0), rtol=1e-12, atol=0)
+
+
+def test_gate_helpers():
+    # the perfect-model bound: lambda + sqrt(2 ln B lambda) + 1, lambda = S/B
+    ok, perf = oracle.sample_gate(30, 16384, 1024, 1.5)
+    assert perf == pytest.approx(16 + np.sqrt(2 * np.log(1024) * 16) + 1)
+    assert ok == (30 <= 1.5 * perf)
+    assert oracle.sample_gate(int(1.5 * perf), 16384, 1024, 1.5)[0]
+    assert not oracle.sample_gate(int(1.5 * perf) + 1, 16384, 1024, 1.5)[0]
+    # the ideal: ceil(S/B), or a longer run of equal codes; it never exceeds the
+    # optimum that brute-force packing finds
+    c = np.array([1, 2, 2, 2, 2, 3, 4, 5, 6, 7], np.uint64)
+    assert oracle.sample_ideal(c, 5) == 4 and oracle.sample_ideal(c, 2) == 5
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        c = np.sort(rng.integers(0, 30, rng.integers(1, 200))).astype(np.uint64)
+        B = int(rng.integers(1, 40))
+        assert oracle.sample_ideal(c, B) <= oracle.opt_max_bucket(c, B)
+
+
 def test_training_reduces_loss_and_leaves_are_monotone():
     recs = datagen.generate(datagen.spec("skewed", seed=5), 100_000)
     codes = oracle.sample_codes(recs, seed=1, S=20_000)

@@ -145,6 +145,19 @@ def test_fit_root_is_library_least_squares_and_leaves_are_splines():
         assert m.bucket_of(int(codes[f])) == m.lo[j]
         assert abs(int(m.bucket_of(int(codes[g]))) - int(m.hi[j])) <= 1
     assert checked > 10
+    # the leaves refitted under that root reproduce the fit's own leaves, and
+    # under another root they follow that root's routing (closed forms above)
+    r = oracle.leaves_under_root(codes, float(m.root[0]), float(m.root[1]), L, B)
+    for a, b in ((r.base, m.base), (r.c, m.c), (r.b, m.b), (r.lo, m.lo), (r.hi, m.hi)):
+        assert np.array_equal(a, b)
+    a0, a1 = np.float32(0.5), np.float32(m.root[1] * 0.75)
+    r = oracle.leaves_under_root(codes, float(a0), float(a1), L, B)
+    lv = np.array([oracle.lib().oracle_rmi_leaf(a0, a1, L, int(c)) for c in codes])
+    for j in np.unique(lv):
+        sel = np.nonzero(lv == j)[0]
+        f, g = sel[0], sel[-1]
+        assert r.base[j] == codes[f] and r.b[j] == _f32(B * f / S)
+        assert r.lo[j] == (B * f) // S and r.hi[j] == min((B * g) // S, B - 1)
 
 
 @pytest.mark.parametrize("kind", ["uniform", "skewed", "zipf", "staircase"])

@@ -101,9 +101,37 @@ def test_checkers_fire_on_planted_mistakes():
     assert oracle.multiset_hash(bad) != oracle.multiset_hash(recs)
 
 
+def test_stable_order_checker():
+    # on records carrying their input index, "strictly increasing (key, index)"
+    # holds for the oracle's output and fails exactly where a tie is swapped
+    recs = datagen.generate(datagen.spec("skewed", seed=12, embed_idx=True), 200_000)
+    out = oracle.sort_records(recs)
+    assert oracle.first_unstable(out) == out.shape[0]
+    keys = out[:, :K]
+    tie = int(np.nonzero(np.all(keys[1:] == keys[:-1], axis=1))[0][0])
+    bad = out.copy()
+    bad[[tie, tie + 1]] = bad[[tie + 1, tie]]
+    assert oracle.first_unsorted(bad) == bad.shape[0]  # the keys alone cannot see it
+    assert oracle.first_unstable(bad) == tie
+    bad = out.copy()
+    bad[[10, 11]] = bad[[11, 10]]
+    assert oracle.first_unstable(bad) == 10
+    bad = out.copy()
+    bad[50] = bad[49]  # a duplicated record: (key, index) repeats
+    assert oracle.first_unstable(bad) == 49
+
+
 def test_rank_of_matches_sorted_position():
     recs = datagen.generate(datagen.spec("skewed", seed=9), 30_000)
     order = oracle.sort_order(recs)
     for pos in [0, 1, 17, 4999, 29_999]:
         i = int(order[pos])
         assert oracle.rank_of_ptr(recs.ctypes.data, recs.shape[0], bytes(recs[i, :K]), i) == pos
+
+
+def test_parallel_baseline_matches_oracle():
+    # the all-core CPU baseline computes the same permutation as the oracle
+    recs = datagen.generate(datagen.spec("skewed", seed=13), 100_000)
+    perm, used = oracle.parallel_sort_order(recs.ctypes.data, recs.shape[0])
+    assert used >= 1
+    assert np.array_equal(perm, oracle.sort_order(recs))
