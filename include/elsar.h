@@ -180,6 +180,26 @@ elsar_status elsar_sort_workspace_size(const elsar_fit_params* p, uint64_t n, si
 elsar_status elsar_sort(const void* d_in, uint64_t n, void* d_out, const elsar_fit_params* p, void* d_ws,
                         size_t ws_bytes, hipStream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): elsar_sort
+ * with its workspace in a fixed array that the library holds on every device
+ * it runs on, ELSAR_NOALLOC_SCRATCH_BYTES bytes, from the first call on that
+ * device until the process ends.  The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine); the caller passes the records and
+ * the output as for elsar_sort.  n must satisfy
+ * elsar_sort_workspace_size(p, n) <= ELSAR_NOALLOC_SCRATCH_BYTES (about
+ * 5.5e5 100-byte records with the default parameters); a larger n returns
+ * ELSAR_E_NO_MEMORY before anything is enqueued.  Every call on a device
+ * shares that device's array, which keeps the last call's contents: calls
+ * that overlap on one device (on different streams, or from different host
+ * threads without ordering) race and give undefined output; calls ordered on
+ * one stream are safe.  Asynchronous on `stream`.
+ */
+#define ELSAR_NOALLOC_SCRATCH_BYTES (256ull << 20)
+elsar_status elsar_sort_noalloc(const void* d_in, uint64_t n, void* d_out, const elsar_fit_params* p,
+                                hipStream_t stream);
+
 /* One job of a batch: n records at d_in, sorted into d_out (may equal d_in). */
 typedef struct {
   const void* d_in;

@@ -137,6 +137,7 @@ def lib():
             "elsar_sort_buckets": ([_P, _P, _SZ, _U64, _P, _P, _P], st),
             "elsar_sort_workspace_size": ([ctypes.POINTER(FitParams), _U64, ctypes.POINTER(_SZ)], st),
             "elsar_sort": ([_P, _U64, _P, ctypes.POINTER(FitParams), _P, _SZ, _P], st),
+            "elsar_sort_noalloc": ([_P, _U64, _P, ctypes.POINTER(FitParams), _P], st),
             "elsar_model_info_get": ([_P, ctypes.POINTER(ModelInfo)], st),
             "elsar_model_leaves": ([_P, _P, _P, _P, _P, _P], st),
             "elsar_partition_stats_get": ([_P, _P, _SZ, ctypes.POINTER(PartitionStats)], st),
@@ -226,6 +227,22 @@ def elsar_sort(records, out=None, params: FitParams | None = None, workspace=Non
         workspace = _dev_bytes(need, records.device)
     _check("elsar_sort", lib().elsar_sort(records.data_ptr(), n, out.data_ptr(), ctypes.byref(params),
                                           workspace.data_ptr(), workspace.numel(), _stream(stream)))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
+def elsar_sort_noalloc(records, out, params: FitParams | None = None, stream=None):
+    """elsar_sort_noalloc: the sort with the library's own fixed device scratch
+    as workspace (no device allocation in the call).  ``out`` must be given
+    (may be ``records``)."""
+    params = params or fit_params()
+    n = _check_records(records, params.record_bytes)
+    if _check_records(out, params.record_bytes) != n:
+        raise ValueError("out must hold n records")
+    _check("elsar_sort_noalloc", lib().elsar_sort_noalloc(records.data_ptr(), n, out.data_ptr(),
+                                                          ctypes.byref(params), _stream(stream)))
     return out
 
 

@@ -688,6 +688,52 @@ elsar_status elsar_sort(const void* d_in, uint64_t n, void* d_out, const elsar_f
   return sort_job(d_in, n, d_out, with_defaults(*p), d_ws, ws_bytes, stream, true);
 }
 
+}  // extern "C"
+
+// --------------------------------------------------- no-allocation entry --
+// The workspace of elsar_sort_noalloc: one array per device, in the code
+// object, held until the process ends.  Host code never uses the name as an
+// address: the device address comes from hipGetSymbolAddress, once per device
+// with that device current, and only that pointer reaches the kernels.
+static __device__ __align__(256) uint8_t scratch[ELSAR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+elsar_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return ELSAR_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return ELSAR_E_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return ELSAR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+elsar_status elsar_sort_noalloc(const void* d_in, uint64_t n, void* d_out, const elsar_fit_params* p,
+                                hipStream_t stream) {
+  elsar_status s = check_params(p);
+  if (s != ELSAR_OK) return s;
+  if (n > ELSAR_MAX_DEVICE_RECORDS) return ELSAR_E_UNSUPPORTED;
+  if (n == 0) return ELSAR_OK;
+  if (!d_in || !d_out || !aligned16(d_in) || !aligned16(d_out)) return ELSAR_E_INVALID_ARG;
+  const elsar_fit_params q = with_defaults(*p);
+  if (sort_layout(q, resolve(q, n), n).bytes > (size_t)ELSAR_NOALLOC_SCRATCH_BYTES) return ELSAR_E_NO_MEMORY;
+  void* ws = nullptr;
+  s = scratch_of_current_device(&ws);
+  if (s != ELSAR_OK) return s;
+  return sort_job(d_in, n, d_out, q, ws, (size_t)ELSAR_NOALLOC_SCRATCH_BYTES, stream, false);
+}
+
 elsar_status elsar_sort_batch_workspace_size(const elsar_job* h_jobs, uint32_t njobs, const elsar_fit_params* p,
                                              size_t* bytes) {
   if (!bytes || (njobs && !h_jobs)) return ELSAR_E_INVALID_ARG;

@@ -83,6 +83,18 @@ def test_argument_checks_return_before_any_work(elsar):
     assert lib.elsar_sort_buckets(64, 32, 1 << 20, 0, 64 + 4, None, None) == elsar.E_INVALID_ARG
 
 
+def test_noalloc_argument_checks(elsar):
+    # the no-allocation entry refuses null buffers and sizes whose workspace
+    # exceeds its fixed scratch before it touches the device
+    lib = elsar.lib()
+    p = elsar.fit_params()
+    assert lib.elsar_sort_noalloc(None, 0, None, ctypes.byref(p), None) == elsar.OK
+    assert lib.elsar_sort_noalloc(None, 5, None, ctypes.byref(p), None) == elsar.E_INVALID_ARG
+    assert lib.elsar_sort_noalloc(16, 10 ** 7, 32, ctypes.byref(p), None) == elsar.E_NO_MEMORY
+    assert lib.elsar_sort_noalloc(16, 5, 32, None, None) == elsar.E_INVALID_ARG
+    assert elsar.sort_workspace_size(500_000, p) <= elsar.NOALLOC_SCRATCH_BYTES
+
+
 def test_workspace_grows_linearly(elsar):
     lib = elsar.lib()
     p = elsar.fit_params()
