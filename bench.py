@@ -48,8 +48,9 @@ WORKLOADS = {
                        desc="1M x 100B, uniform printable 10-byte keys, seed 0, 1024 buckets"),
     "host-1B": dict(kind="host", gen="mixed", seed=4, n=1_000_000_000, pass_records=400_000_000,
                     desc="1.0e9 x 100B (100 GB) in pageable host memory, sorted into pageable host memory; keys per "
-                         "record uniform or skewed-with-hot-keys with p 0.5; seed 4; 4 GB chunks; passes of at "
-                         "most 4e8 records in HBM; MLP root with linear-root fallback"),
+                         "record uniform or skewed-with-hot-keys with p 0.5; seed 4; 4 GB chunks sorted into runs "
+                         "written over the input; group passes of at most 4e8 records in HBM; MLP root with "
+                         "plain-model fallback"),
     "batch-4096": dict(kind="batch", seed=3, jobs=4096,
                        desc="4096 independent jobs, sizes log-uniform in [1K, 4M] records x 100B, even jobs "
                             "uniform keys, odd jobs Zipf(1.1) first byte; seed 3; in place; one graph launch"),
@@ -163,7 +164,10 @@ def check_host_output(h_in, h_out, n, threads=16, probes=8, seed=0):
 def bench_host(args, wl):
     """The host tier: records in pageable host memory sorted into pageable host
     memory; each step is one elsar_sort_host call, timed on the host around
-    the call (it returns when the output is complete)."""
+    the call (it returns when the output is complete).  The sorted runs are
+    written over the input (two 100 GB buffers fit the machine's host memory,
+    three do not), so the input is generated again before every step, outside
+    the timed region."""
     import torch
 
     import datagen
@@ -171,25 +175,25 @@ def bench_host(args, wl):
 
     n, seed = wl["n"], wl["seed"]
     args.model = args.model or "mlp"
-    kind = {"rmi": elsar.RMI, "mlp": elsar.MLP, "auto": elsar.AUTO, "radix": elsar.RADIX,
-            "spline": elsar.SPLINE}[args.model]
-    params = elsar.fit_params(seed=seed, kind=kind, accept_ratio=args.accept_ratio, mlp_steps=args.mlp_steps)
+    params = elsar.fit_params(seed=seed, kind=_kind(elsar, args.model), accept_ratio=args.accept_ratio,
+                              mlp_steps=args.mlp_steps)
     t0 = time.perf_counter()
-    # pageable host memory: the box pins only a few tens of GB in total
     h_in = torch.empty(n * RECORD_BYTES, dtype=torch.uint8)
     h_out = torch.empty(n * RECORD_BYTES, dtype=torch.uint8)
-    # the input, generated on the GPU in slices and copied to host memory
     sp = datagen.spec(wl["gen"], seed=seed)
     step = 50_000_000
     tmp = torch.empty(step * RECORD_BYTES, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
-    for a in range(0, n, step):
-        c = min(step, n - a)
-        datagen.generate_device(sp, tmp.data_ptr(), a, c, stream)
-        h_in[a * RECORD_BYTES:(a + c) * RECORD_BYTES].copy_(tmp[:c * RECORD_BYTES])
-        if (a // step) % 4 == 3:
-            print(f"bench: generated {(a + c) / 1e9:.2f} G records", file=sys.stderr, flush=True)
-    del tmp
+
+    def generate():
+        # the input, generated on the GPU in slices and copied to host memory
+        for a in range(0, n, step):
+            c = min(step, n - a)
+            datagen.generate_device(sp, tmp.data_ptr(), a, c, stream)
+            h_in[a * RECORD_BYTES:(a + c) * RECORD_BYTES].copy_(tmp[:c * RECORD_BYTES])
+        torch.cuda.synchronize()
+
+    generate()
     # the output's pages are touched once here, so that the timed call does
     # not pay the operating system's first-touch faults on 100 GB
     h_out.fill_(0)
@@ -198,21 +202,26 @@ def bench_host(args, wl):
                      device="cuda")
     print(f"bench: {n / 1e9:.2f} G records in pageable host memory, workspace {ws.numel() / 1e9:.1f} GB, "
           f"set up in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        elsar.sort_host(h_in, h_out, params, workspace=ws)
     ms = []
     st = None
-    for _ in range(args.steps):
+    for k in range(args.warmup + args.steps):
+        if k:
+            generate()
         t1 = time.perf_counter()
-        st = elsar.sort_host(h_in, h_out, params, workspace=ws)
-        ms.append((time.perf_counter() - t1) * 1e3)
-        print(f"bench: step {ms[-1]:.0f} ms (fit {st.fit_ms:.0f}, count {st.count_ms:.0f}, "
-              f"{st.passes} passes {st.passes_ms:.0f})", file=sys.stderr, flush=True)
+        st = elsar.sort_host(h_in, h_out, params, workspace=ws, h_frag=h_in, pass_records=wl["pass_records"])
+        dt = (time.perf_counter() - t1) * 1e3
+        if k >= args.warmup:
+            ms.append(dt)
+        print(f"bench: step {dt:.0f} ms (fit {st.fit_ms:.0f}, {st.runs} runs {st.count_ms:.0f}, "
+              f"{st.passes} group passes {st.passes_ms:.0f})", file=sys.stderr, flush=True)
+    del tmp
     ms_per_step = sum(ms) / len(ms)
+    # the oracle checks need the input: generate it once more (the runs
+    # overwrote it) and check the last output against it
+    generate()
     t2 = time.perf_counter()
     chk = check_host_output(h_in, h_out, n)
     print(f"bench: oracle checks {chk} in {time.perf_counter() - t2:.1f} s", file=sys.stderr, flush=True)
-    pcie_bytes = (2 + st.passes) * n * RECORD_BYTES  # counting pass + one read per pass + the output
     result = {
         "metric": "sorted records/s (100-byte records, host memory to host memory through one GPU)",
         "value": n / (ms_per_step * 1e-3),
@@ -228,10 +237,12 @@ def bench_host(args, wl):
         "data": "synthetic",
         "config": {"workload": wl["desc"], "records": n, "record_bytes": RECORD_BYTES,
                    "model": args.model, "buckets": st.num_buckets, "chunk_records": st.chunk_records,
-                   "pass_records": st.pass_records, "passes": st.passes, "parallelism": "single GPU"},
-        "phases_ms": {"fit": round(st.fit_ms, 1), "count_pass": round(st.count_ms, 1),
-                      "sort_passes": round(st.passes_ms, 1)},
-        "pcie_GBps": round(pcie_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+                   "pass_records": st.pass_records, "passes": st.passes, "runs": st.runs,
+                   "parallelism": "single GPU"},
+        "phases_ms": {"fit": round(st.fit_ms, 1), "runs": round(st.count_ms, 1),
+                      "group_passes": round(st.passes_ms, 1)},
+        "link_bytes": st.link_bytes,
+        "pcie_GBps": round(st.link_bytes / (ms_per_step * 1e-3) / 1e9, 1),
         "step_ms": [round(x, 1) for x in ms],
         "oracle_checks": chk,
     }

@@ -231,40 +231,59 @@ elsar_status elsar_sort_batch(const elsar_job* h_jobs, uint32_t njobs, const els
 
 /* Host tier. */
 typedef struct {
-  uint64_t chunk_records;     /* records per streamed chunk */
-  uint64_t pass_records;      /* most records one pass can hold in HBM */
-  uint32_t passes;            /* passes over the input after the counting pass */
-  uint32_t num_buckets;
-  float fit_ms, count_ms, passes_ms, total_ms;  /* host wall time of each part */
+  uint64_t chunk_records;     /* records per streamed chunk (one sorted run each) */
+  uint64_t pass_records;      /* most records one group pass holds in HBM */
+  uint32_t passes;            /* group passes (consecutive buckets fitting a pass) */
+  uint32_t num_buckets;       /* B of the global model */
+  uint32_t runs;              /* sorted runs written to the fragment store */
+  uint32_t copy_passes;       /* groups of one all-equal-key bucket larger than a pass, copied through */
+  uint64_t link_bytes;        /* bytes moved over the host link, both directions */
+  float fit_ms, count_ms, passes_ms, total_ms;  /* host wall time: global model, runs, group passes, all */
 } elsar_host_stats;
 
+#define ELSAR_HOST_SAMPLE_FIRST_CHUNK 1u  /* fit the global model on the first chunk only */
+
 /* Device workspace of elsar_sort_host for n records streamed in chunks of
- * chunk_records (0: 40M, 4 GB of 100-byte records), when one pass may hold
- * up to pass_records records in HBM (0: n, a single pass). */
+ * chunk_records (0: 40M, 4 GB of 100-byte records), when one group pass may
+ * hold up to pass_records records in HBM (0: n, a single pass). */
 elsar_status elsar_sort_host_workspace_size(const elsar_fit_params* p, uint64_t n, uint64_t chunk_records,
                                             uint64_t pass_records, size_t* bytes);
 
 /*
  * The external tier (the paper's larger-than-memory setting, Section 3, with
- * host memory in the role of the external store): n records in host memory
- * h_in are sorted into host memory h_out, which must not overlap h_in.  Either
- * may be pageable; pinned memory (hipHostMalloc or another pinned allocator)
- * copies at full link speed.  The sample is drawn from the first chunk (the
- * paper samples from the first batch that one reader reads, Section 3.1); a
- * counting pass streams every chunk to HBM and counts its records per bucket;
- * then each pass streams the chunks again and places only a range of
- * consecutive buckets whose records fit the workspace, in regions of exact
- * size, sorts them and copies them to h_out at their offsets -- the
- * concatenation of Section 3.5 at host level.  Copies run on streams of their
- * own, double buffered against the kernels on `stream`.  d_ws: workspace; its
- * size bounds the records held in HBM at once (see
- * elsar_sort_host_workspace_size).  Synchronous: returns when h_out is
- * complete.  n < 2^32.  ELSAR_E_NO_MEMORY when one bucket alone exceeds what
- * a pass can hold.  stats may be NULL.
+ * host memory as the external store): n records in host memory h_in are
+ * sorted into host memory h_out.  Either may be pageable; pinned memory copies
+ * at full link speed.
+ *  1. The global model (Section 3.1) is fitted on a sample of 1% of the input
+ *     (at most 10^7 records) gathered as evenly spaced blocks over the whole
+ *     input by one strided copy; with ELSAR_HOST_SAMPLE_FIRST_CHUNK, on the
+ *     first chunk only, as the paper samples the first batch one reader reads.
+ *  2. Runs (Section 3.3, fragments written once): every chunk of
+ *     chunk_records records is streamed to HBM, sorted there by the in-HBM
+ *     method, and copied back to h_frag at the chunk's own position as a
+ *     sorted run; the global model's bucket counts of the run are kept.
+ *  3. Group passes (Section 3.4): consecutive buckets whose records fit one
+ *     pass are read back, one slice per run, placed in exact regions, sorted
+ *     and copied to h_out at their offset (Section 3.5's concatenation).
+ *  Every record crosses the link four times (plus the sample), whatever the
+ *  number of passes.  Copies run on streams of their own, double buffered
+ *  against the kernels on `stream`.
+ * h_frag: n * record_bytes bytes of host memory for the runs; it may be h_in
+ * itself (the input is then overwritten with the runs) and must not overlap
+ * h_out; h_in must not overlap h_out.  d_ws: workspace; its size bounds the
+ * records of one group pass (elsar_sort_host_workspace_size); pass_records,
+ * if nonzero, bounds them further.  chunk_records: as for the workspace size
+ * (0: 40M).  flags: 0 or ELSAR_HOST_SAMPLE_FIRST_CHUNK.  A bucket
+ * larger than a pass is copied through in run order when all its keys are
+ * equal (the order of equal keys is the input order); if its keys differ the
+ * call returns ELSAR_E_UNSUPPORTED (the output is then unspecified): this
+ * needs more records than a pass sharing the first 8 key bytes, or a model
+ * fitted on an unrepresentative first chunk.  Synchronous: returns when h_out
+ * is complete.  n < 2^32.  stats may be NULL.
  */
-elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, const elsar_fit_params* p,
-                             uint64_t chunk_records, void* d_ws, size_t ws_bytes, hipStream_t stream,
-                             elsar_host_stats* stats);
+elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, void* h_frag, const elsar_fit_params* p,
+                             uint64_t chunk_records, uint64_t pass_records, uint32_t flags, void* d_ws,
+                             size_t ws_bytes, hipStream_t stream, elsar_host_stats* stats);
 
 /* What a fitted model looks like; synchronises with the device. */
 typedef struct {

@@ -93,12 +93,18 @@ class Job(ctypes.Structure):
     _fields_ = [("d_in", ctypes.c_void_p), ("d_out", ctypes.c_void_p), ("n", ctypes.c_uint64)]
 
 
+HOST_SAMPLE_FIRST_CHUNK = 1
+
+
 class HostStats(ctypes.Structure):
     _fields_ = [
         ("chunk_records", ctypes.c_uint64),
         ("pass_records", ctypes.c_uint64),
         ("passes", ctypes.c_uint32),
         ("num_buckets", ctypes.c_uint32),
+        ("runs", ctypes.c_uint32),
+        ("copy_passes", ctypes.c_uint32),
+        ("link_bytes", ctypes.c_uint64),
         ("fit_ms", ctypes.c_float),
         ("count_ms", ctypes.c_float),
         ("passes_ms", ctypes.c_float),
@@ -148,8 +154,8 @@ def lib():
             "elsar_sort_batch": ([ctypes.POINTER(Job), ctypes.c_uint32, ctypes.POINTER(FitParams), _P, _SZ, _P], st),
             "elsar_sort_host_workspace_size": ([ctypes.POINTER(FitParams), _U64, _U64, _U64, ctypes.POINTER(_SZ)],
                                                st),
-            "elsar_sort_host": ([_P, _U64, _P, ctypes.POINTER(FitParams), _U64, _P, _SZ, _P,
-                                 ctypes.POINTER(HostStats)], st),
+            "elsar_sort_host": ([_P, _U64, _P, _P, ctypes.POINTER(FitParams), _U64, _U64, ctypes.c_uint32, _P, _SZ,
+                                 _P, ctypes.POINTER(HostStats)], st),
             "elsar_mlp_forward": ([_P, _P, _P, _U64, _P], st),
             "elsar_mlp_gradient": ([_P, _P, _P, _P, _P, _P], st),
             "elsar_mlp_train_step": ([_P, _P, _P, _P, _P, ctypes.c_uint32, ctypes.c_float, _P, _P, _P, _P], st),
@@ -297,26 +303,33 @@ def sort_host_workspace_size(n: int, params: FitParams | None = None, chunk_reco
 
 
 def sort_host(h_in, h_out, params: FitParams | None = None, chunk_records: int = 0, pass_records: int = 0,
-              workspace=None, stream=None) -> HostStats:
+              workspace=None, stream=None, h_frag=None, first_chunk_sample: bool = False) -> HostStats:
     """elsar_sort_host: records in host memory (uint8 CPU tensors; pinned ones,
-    made with pin_memory=True, copy fastest) sorted into h_out.  The device
-    workspace is sized for passes of ``pass_records`` records (0: the whole
-    input in one pass) unless one is given.  Synchronous; returns the call's
-    statistics."""
+    made with pin_memory=True, copy fastest) sorted into h_out.  h_frag holds
+    the sorted runs: a host tensor of the same size, ``h_in`` itself (the input
+    is then overwritten), or None for a new one (pinned when h_in is).  The
+    device workspace is sized for group passes of ``pass_records`` records (0:
+    the whole input in one pass) unless one is given; ``pass_records`` also
+    bounds the group passes of a given workspace.  Synchronous; returns the
+    call's statistics."""
     import torch
     params = params or fit_params()
-    for t in (h_in, h_out):
+    if h_frag is None:
+        h_frag = torch.empty(h_in.numel(), dtype=torch.uint8, pin_memory=bool(h_in.is_pinned()))
+    for t in (h_in, h_out, h_frag):
         if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or t.is_cuda or not t.is_contiguous():
             raise TypeError("host records must be contiguous uint8 CPU tensors")
     n = h_in.numel() // params.record_bytes
-    if h_in.numel() % params.record_bytes or h_out.numel() != h_in.numel():
-        raise ValueError("input and output must hold the same whole number of records")
+    if h_in.numel() % params.record_bytes or h_out.numel() != h_in.numel() or h_frag.numel() != h_in.numel():
+        raise ValueError("input, output and fragment store must hold the same whole number of records")
     if workspace is None:
         workspace = _dev_bytes(sort_host_workspace_size(n, params, chunk_records, pass_records), "cuda")
     st = HostStats()
-    _check("elsar_sort_host", lib().elsar_sort_host(h_in.data_ptr(), n, h_out.data_ptr(), ctypes.byref(params),
-                                                    chunk_records, workspace.data_ptr(), workspace.numel(),
-                                                    _stream(stream), ctypes.byref(st)))
+    flags = HOST_SAMPLE_FIRST_CHUNK if first_chunk_sample else 0
+    _check("elsar_sort_host", lib().elsar_sort_host(h_in.data_ptr(), n, h_out.data_ptr(), h_frag.data_ptr(),
+                                                    ctypes.byref(params), chunk_records, pass_records, flags,
+                                                    workspace.data_ptr(), workspace.numel(), _stream(stream),
+                                                    ctypes.byref(st)))
     return st
 
 

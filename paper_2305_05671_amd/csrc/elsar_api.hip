@@ -800,9 +800,23 @@ elsar_status elsar_sort_batch(const elsar_job* h_jobs, uint32_t njobs, const els
 namespace {
 
 // ------------------------------------------------------------- host tier --
+// The paper's larger-than-memory setting (Section 3) with host memory as the
+// external store.  Two passes over the data, each record crossing the link
+// four times in all:
+//  * runs (Section 3.3's partitioning pass, written once): every chunk is
+//    streamed to HBM, sorted there by the in-HBM method, and written back to
+//    the fragment store as a sorted run; the global model's bucket counts of
+//    the run are kept (its buckets are contiguous ranges of the sorted run);
+//  * groups (Section 3.4): consecutive buckets whose records fit one pass are
+//    read back, one slice per run, sorted in HBM and written to the output at
+//    their offset (Section 3.5's concatenation at host level).
+// A bucket alone larger than a pass whose keys are all equal is already in
+// order across the runs (each run is stable, runs are in input order) and is
+// copied through; one with different keys is refused.
 constexpr uint64_t kDefaultChunkRecords = 40000000ull;  // 4 GB of 100-byte records
+constexpr uint32_t kSampleBlocks = 4096;                  // strided blocks of the whole-input sample
 
-// Partition buffer of one pass: P records in exact regions for up to B
+// Partition buffer of one group pass: P records in exact regions for up to B
 // buckets, no spill area.
 PartLayout pass_layout(uint64_t P, uint32_t B, uint32_t R, uint32_t K) {
   PartLayout lay{};
@@ -833,10 +847,25 @@ PartLayout pass_layout(uint64_t P, uint32_t B, uint32_t R, uint32_t K) {
   return lay;
 }
 
+// Parameters of the in-HBM sort of one chunk (its own sample and model).
+elsar_fit_params chunk_params(const elsar_fit_params& q) {
+  elsar_fit_params c = q;
+  c.num_buckets = 0;
+  c.num_leaves = 0;
+  c.sample_size = 0;
+  return c;
+}
+
 struct HostLayout {
-  Shape sh;
-  uint64_t C = 0, P = 0;
-  size_t model = 0, fit = 0, counts = 0, offsets = 0, chunk[2] = {0, 0}, part = 0, stage = 0, bytes = 0;
+  Shape sh;                // the global model
+  uint64_t C = 0, P = 0;   // chunk records, group-pass records
+  size_t model = 0, fit = 0, counts = 0, ccount[2] = {0, 0}, offsets = 0, flag = 0;
+  size_t region = 0;       // shared by the fit sample, the run pass and the group passes
+  // run pass (offsets from region)
+  size_t chunk[2] = {0, 0}, sorted[2] = {0, 0}, sort_ws = 0, sort_ws_bytes = 0;
+  // group passes (offsets from region)
+  size_t group = 0, part = 0, stage = 0;
+  size_t bytes = 0;
   PartLayout lay;
 };
 
@@ -845,6 +874,7 @@ HostLayout host_layout(const elsar_fit_params& q, uint64_t n, uint64_t C, uint64
   h.sh = resolve(q, n);
   h.C = std::max<uint64_t>(1, std::min<uint64_t>(C ? C : kDefaultChunkRecords, n));
   h.P = std::max<uint64_t>(1, P);
+  const uint32_t R = q.record_bytes;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -854,17 +884,40 @@ HostLayout host_layout(const elsar_fit_params& q, uint64_t n, uint64_t C, uint64
   h.model = take(model_dev_bytes(h.sh, q.kind));
   h.fit = take(fit_ws_bytes(h.sh.S));
   h.counts = take((size_t)h.sh.B * 4);
+  h.ccount[0] = take((size_t)h.sh.B * 4);
+  h.ccount[1] = take((size_t)h.sh.B * 4);
   h.offsets = take(((size_t)h.sh.B + 1) * 8);
-  h.chunk[0] = take((size_t)h.C * q.record_bytes);
-  h.chunk[1] = take((size_t)h.C * q.record_bytes);
-  h.lay = pass_layout(h.P, h.sh.B, q.record_bytes, q.key_bytes);
-  h.part = take(h.lay.bytes);
-  h.stage = take((size_t)h.P * q.record_bytes);
-  h.bytes = off;
+  h.flag = take(256);
+  h.region = off;
+  // the sample of the global model
+  size_t r_fit = align_up((size_t)h.sh.S * R);
+  // run pass: two input chunks, two sorted chunks, one chunk sort's workspace
+  const elsar_fit_params cq = chunk_params(q);
+  size_t r = 0;
+  auto take_r = [&](size_t bytes) {
+    size_t o = r;
+    r += align_up(bytes);
+    return o;
+  };
+  h.chunk[0] = take_r((size_t)h.C * R);
+  h.chunk[1] = take_r((size_t)h.C * R);
+  h.sorted[0] = take_r((size_t)h.C * R);
+  h.sorted[1] = take_r((size_t)h.C * R);
+  h.sort_ws_bytes = sort_layout(cq, resolve(cq, h.C), h.C).bytes;
+  h.sort_ws = take_r(h.sort_ws_bytes);
+  const size_t r_runs = r;
+  // group passes: the gathered slices, the partition buffer, the output stage
+  r = 0;
+  h.group = take_r((size_t)h.P * R);
+  h.lay = pass_layout(h.P, h.sh.B, R, q.key_bytes);
+  h.part = take_r(h.lay.bytes);
+  h.stage = take_r((size_t)h.P * R);
+  const size_t r_groups = r;
+  h.bytes = h.region + std::max(r_fit, std::max(r_runs, r_groups));
   return h;
 }
 
-// Largest pass that fits ws_bytes (0 if not even one record does).
+// Largest group pass that fits ws_bytes (0 if not even one record does).
 uint64_t pass_capacity(const elsar_fit_params& q, uint64_t n, uint64_t C, size_t ws_bytes) {
   uint64_t lo = 0, hi = n;
   while (lo < hi) {
@@ -876,26 +929,21 @@ uint64_t pass_capacity(const elsar_fit_params& q, uint64_t n, uint64_t C, size_t
 
 struct Streams {  // two copy streams and their events, released on every path
   hipStream_t h2d = nullptr, d2h = nullptr;
-  hipEvent_t loaded[2] = {}, freed[2] = {}, sorted = nullptr, copied = nullptr;
+  hipEvent_t loaded[2] = {}, freed[2] = {}, sorted[2] = {}, copied[2] = {}, counted[2] = {};
   ~Streams() {
     if (h2d) (void)hipStreamDestroy(h2d);
     if (d2h) (void)hipStreamDestroy(d2h);
-    for (auto e : loaded)
-      if (e) (void)hipEventDestroy(e);
-    for (auto e : freed)
-      if (e) (void)hipEventDestroy(e);
-    if (sorted) (void)hipEventDestroy(sorted);
-    if (copied) (void)hipEventDestroy(copied);
+    for (auto* arr : {loaded, freed, sorted, copied, counted})
+      for (int i = 0; i < 2; ++i)
+        if (arr[i]) (void)hipEventDestroy(arr[i]);
   }
   bool init() {
     if (hipStreamCreateWithFlags(&h2d, hipStreamNonBlocking) != hipSuccess) return false;
     if (hipStreamCreateWithFlags(&d2h, hipStreamNonBlocking) != hipSuccess) return false;
-    for (int i = 0; i < 2; ++i)
-      if (hipEventCreateWithFlags(&loaded[i], hipEventDisableTiming) != hipSuccess ||
-          hipEventCreateWithFlags(&freed[i], hipEventDisableTiming) != hipSuccess)
-        return false;
-    return hipEventCreateWithFlags(&sorted, hipEventDisableTiming) == hipSuccess &&
-           hipEventCreateWithFlags(&copied, hipEventDisableTiming) == hipSuccess;
+    for (auto* arr : {loaded, freed, sorted, copied, counted})
+      for (int i = 0; i < 2; ++i)
+        if (hipEventCreateWithFlags(&arr[i], hipEventDisableTiming) != hipSuccess) return false;
+    return true;
   }
 };
 
@@ -903,28 +951,21 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// Every chunk of the input through HBM: copy chunk c into buffer c % 2 on the
-// copy stream once the kernels that used the buffer are done, then run
-// body(buffer, first record, records) on the compute stream.
-template <typename Body>
-elsar_status stream_chunks(const uint8_t* h_in, uint64_t n, uint32_t R, const HostLayout& hl, uint8_t* w,
-                           Streams& ss, hipStream_t st, Body body) {
-  const uint64_t nchunks = (n + hl.C - 1) / hl.C;
-  for (uint64_t c = 0; c < nchunks; ++c) {
-    const int k = (int)(c & 1u);
-    const uint64_t first = c * hl.C, cnt = std::min<uint64_t>(hl.C, n - first);
-    uint8_t* buf = w + hl.chunk[k];
-    if (c >= 2) HIP_TRY(hipStreamWaitEvent(ss.h2d, ss.freed[k], 0));
-    HIP_TRY(hipMemcpyAsync(buf, h_in + first * R, cnt * R, hipMemcpyHostToDevice, ss.h2d));
-    HIP_TRY(hipEventRecord(ss.loaded[k], ss.h2d));
-    HIP_TRY(hipStreamWaitEvent(st, ss.loaded[k], 0));
-    elsar_status s = body(buf, first, cnt);
-    if (s != ELSAR_OK) return s;
-    HIP_TRY(hipEventRecord(ss.freed[k], st));
-  }
-  // the next user of the buffers is ordered after the last kernels
-  HIP_TRY(hipStreamWaitEvent(ss.h2d, ss.freed[0], 0));
-  if (nchunks > 1) HIP_TRY(hipStreamWaitEvent(ss.h2d, ss.freed[1], 0));
+// The whole-input sample for the global model: nb evenly spaced blocks of bs
+// consecutive records (systematic sampling with one random start), gathered
+// by one strided copy.  Returns the records copied.
+elsar_status gather_sample(const uint8_t* in, uint64_t n, uint32_t R, uint64_t S, uint64_t seed, uint8_t* dst,
+                           hipStream_t st, uint64_t* got) {
+  const uint64_t nb = std::min<uint64_t>(S, kSampleBlocks);
+  const uint64_t bs = S / nb, pitch = n / nb;  // bs <= pitch since S <= n
+  // a start in [0, pitch - bs] from the seed (SplitMix64 output function)
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const uint64_t start = (pitch > bs) ? z % (pitch - bs + 1) : 0;
+  HIP_TRY(hipMemcpy2DAsync(dst, bs * R, in + start * R, pitch * R, bs * R, nb, hipMemcpyHostToDevice, st));
+  *got = nb * bs;
   return ELSAR_OK;
 }
 
@@ -943,117 +984,247 @@ elsar_status elsar_sort_host_workspace_size(const elsar_fit_params* p, uint64_t 
   return ELSAR_OK;
 }
 
-elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, const elsar_fit_params* p,
-                             uint64_t chunk_records, void* d_ws, size_t ws_bytes, hipStream_t stream,
-                             elsar_host_stats* stats) {
+elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, void* h_frag, const elsar_fit_params* p,
+                             uint64_t chunk_records, uint64_t pass_records, uint32_t flags, void* d_ws,
+                             size_t ws_bytes, hipStream_t stream, elsar_host_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
   elsar_status s = check_params(p);
   if (s != ELSAR_OK) return s;
-  if (n > 0xFFFFFFFFull) return ELSAR_E_UNSUPPORTED;  // input indices are 32-bit
+  if (n > 0xFFFFFFFFull) return ELSAR_E_UNSUPPORTED;  // chunk and group positions are 32-bit
+  if (flags & ~(uint32_t)ELSAR_HOST_SAMPLE_FIRST_CHUNK) return ELSAR_E_INVALID_ARG;
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (n == 0) return ELSAR_OK;
-  if (!h_in || !h_out || !d_ws || !aligned16(d_ws) || !aligned16(h_in) || !aligned16(h_out))
+  if (!h_in || !h_out || !h_frag || !d_ws || !aligned16(d_ws) || !aligned16(h_in) || !aligned16(h_out) ||
+      !aligned16(h_frag))
     return ELSAR_E_INVALID_ARG;
   const elsar_fit_params q = with_defaults(*p);
   const uint32_t R = q.record_bytes;
   const uint8_t* in = static_cast<const uint8_t*>(h_in);
   uint8_t* out = static_cast<uint8_t*>(h_out);
-  if (in < out + n * R && out < in + n * R) return ELSAR_E_INVALID_ARG;  // overlapping
-  const uint64_t P = pass_capacity(q, n, chunk_records, ws_bytes);
+  uint8_t* frag = static_cast<uint8_t*>(h_frag);
+  auto overlap = [&](const uint8_t* a, const uint8_t* b) { return a < b + n * R && b < a + n * R; };
+  if (overlap(in, out) || overlap(frag, out)) return ELSAR_E_INVALID_ARG;
+  if (frag != in && overlap(frag, in)) return ELSAR_E_INVALID_ARG;
+  uint64_t P = pass_capacity(q, n, chunk_records, ws_bytes);
   if (P == 0) return ELSAR_E_NO_MEMORY;
+  if (pass_records) P = std::min(P, pass_records);
   const HostLayout hl = host_layout(q, n, chunk_records, P);
   uint8_t* w = static_cast<uint8_t*>(d_ws);
+  uint8_t* region = w + hl.region;
   Streams ss;
   if (!ss.init()) return ELSAR_E_HIP;
-  // 1. sample and fit on the first chunk (the paper samples from the first
-  //    batch one reader reads), streamed to HBM like every chunk
+  uint64_t link = 0;
+
+  // 1. the global model: on a sample spread over the whole input, or (flag) on
+  //    the first chunk only, as the paper samples the first batch that one
+  //    reader reads (Section 3.1)
   elsar_model m{};
   m.p = q;
   m.B = hl.sh.B;
   m.L = hl.sh.L;
   m.Lm = hl.sh.Lm;
-  const uint64_t c0 = std::min<uint64_t>(hl.C, n);
-  m.S = std::min<uint64_t>(hl.sh.S, c0);
   place_model(&m, w + hl.model);
-  HIP_TRY(hipMemcpyAsync(w + hl.chunk[0], in, c0 * R, hipMemcpyHostToDevice, stream));
-  s = do_fit(&m, w + hl.chunk[0], c0, w + hl.fit, fit_ws_bytes(hl.sh.S), stream);
-  if (s != ELSAR_OK) return s;
+  {
+    uint64_t ns = 0;
+    if (flags & ELSAR_HOST_SAMPLE_FIRST_CHUNK) {
+      ns = std::min<uint64_t>(hl.C, n);
+      HIP_TRY(hipMemcpyAsync(region, in, ns * R, hipMemcpyHostToDevice, stream));
+    } else {
+      s = gather_sample(in, n, R, hl.sh.S, q.seed, region, stream, &ns);
+      if (s != ELSAR_OK) return s;
+    }
+    link += ns * R;
+    m.S = std::min<uint64_t>(hl.sh.S, ns);
+    s = do_fit(&m, region, ns, w + hl.fit, fit_ws_bytes(hl.sh.S), stream);
+    if (s != ELSAR_OK) return s;
+  }
   HIP_TRY(hipStreamSynchronize(stream));
   const double t_fit = ms_since(t0);
-  // 2. counting pass
-  uint32_t* counts_all = reinterpret_cast<uint32_t*>(w + hl.counts);
-  HIP_TRY(launch_fill_u32(counts_all, m.B, 0u, stream));
   const MlpState* ms = m.has_mlp ? &m.ms : nullptr;
-  s = stream_chunks(in, n, R, hl, w, ss, stream, [&](uint8_t* buf, uint64_t, uint64_t cnt) {
-    return launch_count(m.hdr, m.leaves, ms, buf, cnt, R, counts_all, stream) == hipSuccess ? ELSAR_OK
-                                                                                         : ELSAR_E_HIP;
-  });
-  if (s != ELSAR_OK) return s;
-  std::vector<uint32_t> counts(m.B);
-  HIP_TRY(hipMemcpyAsync(counts.data(), counts_all, (size_t)m.B * 4, hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipStreamSynchronize(stream));
-  const double t_count = ms_since(t0);
-  // 3. passes: consecutive bucket ranges whose records fit one pass
-  struct Pass {
-    uint32_t lo, hi;
-    uint64_t first, total;
-  };
-  std::vector<Pass> passes;
-  uint64_t done = 0;
-  for (uint32_t b = 0; b < m.B;) {
-    Pass ps{b, b, done, 0};
-    while (ps.hi < m.B && ps.total + counts[ps.hi] <= hl.P) ps.total += counts[ps.hi++];
-    if (ps.hi == ps.lo) return ELSAR_E_NO_MEMORY;  // one bucket is larger than a pass
-    passes.push_back(ps);
-    done += ps.total;
-    b = ps.hi;
-  }
-  if (done != n) return ELSAR_E_HIP;  // the counts must cover every record
-  uint8_t* part = w + hl.part;
-  uint8_t* stage = w + hl.stage;
-  uint64_t* offsets = reinterpret_cast<uint64_t*>(w + hl.offsets);
-  bool stage_busy = false;
-  for (const Pass& ps : passes) {
-    if (ps.total == 0) continue;
-    const uint32_t nb = ps.hi - ps.lo;
-    HIP_TRY(launch_exact_regions(counts_all, ps.lo, nb, ps.total, part, hl.lay, stream));
-    s = stream_chunks(in, n, R, hl, w, ss, stream, [&](uint8_t* buf, uint64_t first, uint64_t cnt) {
-      PassFilter f{first, ps.lo, ps.hi};
-      return launch_partition(m.hdr, m.leaves, ms, buf, cnt, R, q.key_bytes, part, hl.lay, stream, &f) ==
-                     hipSuccess
-                 ? ELSAR_OK
-                 : ELSAR_E_HIP;
-    });
+
+  // 2. runs: each chunk sorted in HBM and written to the fragment store at its
+  //    own place; its counts per global bucket kept for the group passes
+  const uint64_t nchunks = (n + hl.C - 1) / hl.C;
+  std::vector<std::vector<uint32_t>> ccounts(nchunks, std::vector<uint32_t>(m.B));
+  const elsar_fit_params cq = chunk_params(q);
+  for (uint64_t c = 0; c < nchunks; ++c) {
+    const int k = (int)(c & 1u);
+    const uint64_t first = c * hl.C, cnt = std::min<uint64_t>(hl.C, n - first);
+    uint8_t* buf = region + hl.chunk[k];
+    uint8_t* srt = region + hl.sorted[k];
+    uint32_t* cc = reinterpret_cast<uint32_t*>(w + hl.ccount[k]);
+    if (c >= 2) HIP_TRY(hipStreamWaitEvent(ss.h2d, ss.freed[k], 0));
+    HIP_TRY(hipMemcpyAsync(buf, in + first * R, cnt * R, hipMemcpyHostToDevice, ss.h2d));
+    HIP_TRY(hipEventRecord(ss.loaded[k], ss.h2d));
+    HIP_TRY(hipStreamWaitEvent(stream, ss.loaded[k], 0));
+    if (c >= 2) HIP_TRY(hipStreamWaitEvent(stream, ss.copied[k], 0));  // sorted[k] and cc[k] are out
+    s = sort_job(buf, cnt, srt, cq, region + hl.sort_ws, hl.sort_ws_bytes, stream, false);
     if (s != ELSAR_OK) return s;
-    // the regions are exact: a record that found its region full means the
-    // counting and placing passes disagree; stop before anything reads it
-    PartHeader ph;
-    HIP_TRY(hipMemcpyAsync(&ph, part + hl.lay.header, sizeof(ph), hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
-    if (ph.spill_count != 0) return ELSAR_E_HIP;
-    HIP_TRY(launch_scan_counts(part, hl.lay, nb, offsets, stream));
-    if (stage_busy) HIP_TRY(hipStreamWaitEvent(stream, ss.copied, 0));  // the previous pass's output is out
-    HIP_TRY(launch_bucket_sort_small(part, hl.lay, nb, offsets, R, sort_key_bytes(q.key_bytes), stage, stream));
-    HIP_TRY(launch_bucket_sort_large(part, hl.lay, nb, ps.total, offsets, R, sort_key_bytes(q.key_bytes), stage,
-                                     stream));
-    HIP_TRY(launch_long_key_fixup(stage, ps.total, R, q.key_bytes, part + hl.lay.slots, stream));
-    HIP_TRY(hipEventRecord(ss.sorted, stream));
-    HIP_TRY(hipStreamWaitEvent(ss.d2h, ss.sorted, 0));
-    HIP_TRY(hipMemcpyAsync(out + ps.first * R, stage, ps.total * R, hipMemcpyDeviceToHost, ss.d2h));
-    HIP_TRY(hipEventRecord(ss.copied, ss.d2h));
-    stage_busy = true;
+    HIP_TRY(hipEventRecord(ss.freed[k], stream));
+    HIP_TRY(launch_fill_u32(cc, m.B, 0u, stream));
+    HIP_TRY(launch_count(m.hdr, m.leaves, ms, srt, cnt, R, cc, stream));
+    HIP_TRY(hipEventRecord(ss.sorted[k], stream));
+    HIP_TRY(hipStreamWaitEvent(ss.d2h, ss.sorted[k], 0));
+    HIP_TRY(hipMemcpyAsync(frag + first * R, srt, cnt * R, hipMemcpyDeviceToHost, ss.d2h));
+    HIP_TRY(hipMemcpyAsync(ccounts[c].data(), cc, (size_t)m.B * 4, hipMemcpyDeviceToHost, ss.d2h));
+    HIP_TRY(hipEventRecord(ss.copied[k], ss.d2h));
+    link += 2 * cnt * R;
   }
   HIP_TRY(hipStreamSynchronize(ss.d2h));
   HIP_TRY(hipStreamSynchronize(stream));
+  const double t_runs = ms_since(t0);
+
+  // 3. group passes over consecutive buckets whose records fit one pass
+  std::vector<uint64_t> counts(m.B, 0);
+  for (uint64_t c = 0; c < nchunks; ++c)
+    for (uint32_t b = 0; b < m.B; ++b) counts[b] += ccounts[c][b];
+  // run c's bucket b starts at pre[c][b] in the run (exclusive sums)
+  std::vector<std::vector<uint32_t>> pre(nchunks, std::vector<uint32_t>(m.B + 1));
+  for (uint64_t c = 0; c < nchunks; ++c) {
+    uint32_t acc = 0;
+    for (uint32_t b = 0; b < m.B; ++b) {
+      pre[c][b] = acc;
+      acc += ccounts[c][b];
+    }
+    pre[c][m.B] = acc;
+    if (acc != std::min<uint64_t>(hl.C, n - c * hl.C)) return ELSAR_E_HIP;  // counts must cover the run
+  }
+  ccounts.clear();
+  struct Group {
+    uint32_t lo, hi;  // buckets lo .. hi-1
+    uint64_t first, total;
+    bool copy;        // one bucket above a pass: all keys equal, copied through in run order
+  };
+  std::vector<Group> groups;
+  uint64_t done = 0;
+  for (uint32_t b = 0; b < m.B;) {
+    Group g{b, b, done, 0, false};
+    while (g.hi < m.B && g.total + counts[g.hi] <= hl.P) g.total += counts[g.hi++];
+    if (g.hi == g.lo) {
+      g.hi = b + 1;
+      g.total = counts[b];
+      g.copy = true;
+    }
+    groups.push_back(g);
+    done += g.total;
+    b = g.hi;
+  }
+  if (done != n) return ELSAR_E_HIP;  // the counts must cover every record
+  uint32_t* counts_dev = reinterpret_cast<uint32_t*>(w + hl.counts);
+  {
+    std::vector<uint32_t> c32(m.B);
+    for (uint32_t b = 0; b < m.B; ++b) c32[b] = (uint32_t)counts[b];
+    HIP_TRY(hipMemcpyAsync(counts_dev, c32.data(), (size_t)m.B * 4, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+  }
+  uint8_t* gbuf = region + hl.group;
+  uint8_t* part = region + hl.part;
+  uint8_t* stage = region + hl.stage;
+  uint64_t* offsets = reinterpret_cast<uint64_t*>(w + hl.offsets);
+  uint32_t* flag = reinterpret_cast<uint32_t*>(w + hl.flag);
+  HIP_TRY(launch_fill_u32(flag, 1, 0u, stream));
+  bool stage_busy = false, gbuf_busy = false;
+  uint32_t copy_groups = 0;
+  for (const Group& g : groups) {
+    if (g.total == 0) continue;
+    if (g.copy) {
+      // a bucket above a pass: its slices in run order, piece by piece through
+      // the stage; a kernel checks that every key equals the bucket's first
+      ++copy_groups;
+      uint64_t put = 0;
+      bool have_ref = false;
+      uint64_t c = 0, pos = pre[0][g.lo];
+      while (put < g.total) {
+        if (stage_busy) HIP_TRY(hipStreamWaitEvent(ss.h2d, ss.copied[0], 0));
+        uint64_t got = 0;
+        while (got < hl.P && c < nchunks) {
+          const uint64_t end = pre[c][g.hi];
+          const uint64_t take = std::min<uint64_t>(end - pos, hl.P - got);
+          if (take)
+            HIP_TRY(hipMemcpyAsync(stage + got * R, frag + (c * hl.C + pos) * R, take * R, hipMemcpyHostToDevice,
+                                   ss.h2d));
+          got += take;
+          pos += take;
+          if (pos == end && ++c < nchunks) pos = pre[c][g.lo];
+        }
+        HIP_TRY(hipEventRecord(ss.loaded[0], ss.h2d));
+        HIP_TRY(hipStreamWaitEvent(stream, ss.loaded[0], 0));
+        if (!have_ref) {
+          HIP_TRY(hipMemcpyAsync(flag + 32, stage, q.key_bytes, hipMemcpyDeviceToDevice, stream));
+          have_ref = true;
+        }
+        HIP_TRY(launch_keys_differ(stage, got, R, q.key_bytes, reinterpret_cast<const uint8_t*>(flag + 32), flag,
+                                   stream));
+        HIP_TRY(hipEventRecord(ss.sorted[0], stream));
+        HIP_TRY(hipStreamWaitEvent(ss.d2h, ss.sorted[0], 0));
+        HIP_TRY(hipMemcpyAsync(out + (g.first + put) * R, stage, got * R, hipMemcpyDeviceToHost, ss.d2h));
+        HIP_TRY(hipEventRecord(ss.copied[0], ss.d2h));
+        stage_busy = true;
+        put += got;
+        link += 2 * got * R;
+      }
+      continue;
+    }
+    // gather the group's slice of every run into gbuf (after the previous
+    // group's partition has read it)
+    if (gbuf_busy) HIP_TRY(hipStreamWaitEvent(ss.h2d, ss.freed[0], 0));
+    uint64_t got = 0;
+    for (uint64_t c = 0; c < nchunks; ++c) {
+      const uint64_t a = pre[c][g.lo], e = pre[c][g.hi];
+      if (e > a)
+        HIP_TRY(hipMemcpyAsync(gbuf + got * R, frag + (c * hl.C + a) * R, (e - a) * R, hipMemcpyHostToDevice,
+                               ss.h2d));
+      got += e - a;
+    }
+    if (got != g.total) return ELSAR_E_HIP;
+    link += 2 * got * R;
+    HIP_TRY(hipEventRecord(ss.loaded[0], ss.h2d));
+    HIP_TRY(hipStreamWaitEvent(stream, ss.loaded[0], 0));
+    const uint32_t nb = g.hi - g.lo;
+    HIP_TRY(launch_exact_regions(counts_dev, g.lo, nb, g.total, part, hl.lay, stream));
+    PassFilter f{0, g.lo, g.hi};  // every record of gbuf is in the group; its position breaks ties
+    HIP_TRY(launch_partition(m.hdr, m.leaves, ms, gbuf, g.total, R, q.key_bytes, part, hl.lay, stream, &f));
+    HIP_TRY(hipEventRecord(ss.freed[0], stream));
+    gbuf_busy = true;
+    // the regions are exact: a record that found its region full would mean
+    // the run counts and the placement disagree; stop before a sort reads it
+    {
+      PartHeader ph;
+      HIP_TRY(hipMemcpyAsync(&ph, part + hl.lay.header, sizeof(ph), hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      if (ph.spill_count != 0) return ELSAR_E_HIP;
+    }
+    HIP_TRY(launch_scan_counts(part, hl.lay, nb, offsets, stream));
+    if (stage_busy) HIP_TRY(hipStreamWaitEvent(stream, ss.copied[0], 0));  // the previous output is out
+    HIP_TRY(launch_bucket_sort_small(part, hl.lay, nb, offsets, R, sort_key_bytes(q.key_bytes), stage, stream));
+    HIP_TRY(launch_bucket_sort_large(part, hl.lay, nb, g.total, offsets, R, sort_key_bytes(q.key_bytes), stage,
+                                     stream));
+    HIP_TRY(launch_long_key_fixup(stage, g.total, R, q.key_bytes, part + hl.lay.slots, stream));
+    HIP_TRY(hipEventRecord(ss.sorted[0], stream));
+    HIP_TRY(hipStreamWaitEvent(ss.d2h, ss.sorted[0], 0));
+    HIP_TRY(hipMemcpyAsync(out + g.first * R, stage, g.total * R, hipMemcpyDeviceToHost, ss.d2h));
+    HIP_TRY(hipEventRecord(ss.copied[0], ss.d2h));
+    stage_busy = true;
+  }
+  HIP_TRY(hipStreamSynchronize(ss.d2h));
+  HIP_TRY(hipStreamSynchronize(ss.h2d));
+  HIP_TRY(hipStreamSynchronize(stream));
+  // every bucket copied through held one key only
+  uint32_t bad = 0;
+  HIP_TRY(hipMemcpy(&bad, flag, 4, hipMemcpyDeviceToHost));
+  if (bad) return ELSAR_E_UNSUPPORTED;  // a bucket above a pass whose keys differ
   if (stats) {
     stats->chunk_records = hl.C;
     stats->pass_records = hl.P;
-    stats->passes = (uint32_t)passes.size();
+    stats->passes = (uint32_t)groups.size();
     stats->num_buckets = m.B;
+    stats->runs = (uint32_t)nchunks;
+    stats->copy_passes = copy_groups;
+    stats->link_bytes = link;
     stats->fit_ms = (float)t_fit;
-    stats->count_ms = (float)(t_count - t_fit);
+    stats->count_ms = (float)(t_runs - t_fit);
     stats->total_ms = (float)ms_since(t0);
-    stats->passes_ms = stats->total_ms - (float)t_count;
+    stats->passes_ms = stats->total_ms - (float)t_runs;
   }
   return ELSAR_OK;
 }

@@ -365,6 +365,8 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const Ml
                             const PartLayout& lay, hipStream_t st, const PassFilter* filter = nullptr);
 hipError_t launch_count(const ModelHeader* hdr, const Leaf* leaves, const MlpState* ms, const uint8_t* recs,
                         uint64_t n, uint32_t rec_bytes, uint32_t* counts, hipStream_t st);
+hipError_t launch_keys_differ(const uint8_t* recs, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
+                              const uint8_t* ref, uint32_t* flag, hipStream_t st);
 hipError_t launch_exact_regions(const uint32_t* counts_all, uint32_t lo, uint32_t nb, uint64_t total, uint8_t* part,
                                 const PartLayout& lay, hipStream_t st);
 hipError_t launch_scan_counts(uint8_t* part, const PartLayout& lay, uint32_t B, uint64_t* offsets,

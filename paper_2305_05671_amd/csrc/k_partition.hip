@@ -343,6 +343,27 @@ hipError_t launch_count(const ModelHeader* hdr, const Leaf* leaves, const MlpSta
   return hipGetLastError();
 }
 
+// flag[0] = 1 if the first K bytes of any of n records differ from ref (the
+// host tier's check of a bucket that it copies through without sorting).
+__global__ __launch_bounds__(256) void keys_differ_kernel(const uint8_t* __restrict__ recs, uint64_t n, uint32_t R,
+                                                          uint32_t K, const uint8_t* __restrict__ ref,
+                                                          uint32_t* __restrict__ flag) {
+  bool diff = false;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint8_t* r = recs + i * R;
+    for (uint32_t b = 0; b < K; ++b) diff |= r[b] != ref[b];
+  }
+  if (__ballot(diff) && lane_id() == 0) flag[0] = 1u;
+}
+
+hipError_t launch_keys_differ(const uint8_t* recs, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
+                              const uint8_t* ref, uint32_t* flag, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 4096);
+  keys_differ_kernel<<<grid, 256, 0, st>>>(recs, n, rec_bytes, key_bytes, ref, flag);
+  return hipGetLastError();
+}
+
 // One pass of the host tier places buckets lo .. hi-1 in exact regions:
 // caps[j] = counts_all[lo + j], rstart = their exclusive sum, counts zeroed,
 // header set for total records and hi - lo buckets.  One block.
