@@ -214,11 +214,11 @@ def bench_host(args, wl):
             ms.append(dt)
         print(f"bench: step {dt:.0f} ms (fit {st.fit_ms:.0f}, {st.runs} runs {st.count_ms:.0f}, "
               f"{st.passes} group passes {st.passes_ms:.0f})", file=sys.stderr, flush=True)
-    del tmp
     ms_per_step = sum(ms) / len(ms)
     # the oracle checks need the input: generate it once more (the runs
     # overwrote it) and check the last output against it
     generate()
+    del tmp
     t2 = time.perf_counter()
     chk = check_host_output(h_in, h_out, n)
     print(f"bench: oracle checks {chk} in {time.perf_counter() - t2:.1f} s", file=sys.stderr, flush=True)

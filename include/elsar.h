@@ -42,7 +42,10 @@
 extern "C" {
 #endif
 
-#define ELSAR_MAX_DEVICE_RECORDS 1000000000ull
+/* In-HBM sorts: n records in, n out and the workspace (about 463 bytes per
+ * 100-byte record: regions of up to 2.5 n slots, a spill area of n slots,
+ * 128 bytes each) fit the 288 GB of one MI355X up to this many records. */
+#define ELSAR_MAX_DEVICE_RECORDS 400000000ull
 #define ELSAR_MLP_PARAMS 4801      /* W1 (64x8), b1 (64), W2 (64x64), b2 (64), w3 (64), b3, row-major */
 #define ELSAR_MLP_GRAD_ROWS 128    /* rows of one MLP training step */
 #define ELSAR_MLP_STEPS_NONE 0xFFFFFFFFu  /* mlp_steps: no training, the initial network (for comparisons) */
@@ -87,6 +90,14 @@ typedef struct {
                              ELSAR_MLP_STEPS_NONE: none */
   uint32_t region_pct;    /* bucket j's region holds ceil(region_pct/100 * max(n*(h_j + 2 sqrt(h_j))/S, n/B))
                              + 16 records (h_j: sample keys in bucket j), the rest spills; 0: 125 */
+  uint32_t key_len_offset; /* 0: fixed-length keys.  Otherwise variable-length keys (Section 4's padding
+                              rule): record byte key_len_offset holds the key's length len (values above
+                              key_bytes count as key_bytes); the key is the first len bytes of the key field
+                              [0, key_bytes), the field's later bytes are padding and ignored.  Keys order as
+                              byte strings: the padding reads as 0x00, below every byte value, and a key sorts
+                              before the longer keys it is a prefix of; equal keys keep input order.  Needs
+                              key_bytes <= key_len_offset <= 11 (so key_bytes <= 11); not in elsar_sort_batch
+                              (ELSAR_E_UNSUPPORTED). */
 } elsar_fit_params;
 
 /* Fills *p with the defaults for 100-byte records with 10-byte keys. */
@@ -360,6 +371,11 @@ typedef struct {
   uint32_t max_bucket;       /* largest bucket */
   uint32_t mid_records;      /* records in the mid_buckets */
   uint32_t big_records;      /* records in the big_buckets */
+  /* after elsar_sort_buckets: the split of the big buckets into segments --
+   * segments listed, the list's capacity, and 1 if a piece stack overflowed.
+   * A count above the capacity or an overflow means some segment was not
+   * sorted (the bounds make neither expected for any input). */
+  uint32_t split_segments, split_segment_cap, split_overflow;
 } elsar_partition_stats;
 
 elsar_status elsar_partition_stats_get(const elsar_model* m, const void* d_part, size_t part_bytes,

@@ -84,6 +84,8 @@ def lib():
         sig = {
             "oracle_sort_order": ([_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _u64p], ctypes.c_int),
             "oracle_sort_records": ([_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _u8p], ctypes.c_int),
+            "oracle_sort_order_varlen": ([_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                          _u64p], ctypes.c_int),
             "oracle_first_unsorted": ([_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_uint64),
             "oracle_first_unstable": ([_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_uint64),
             "oracle_multiset_hash": ([_u8p, ctypes.c_uint64, ctypes.c_uint32], ctypes.c_uint64),
@@ -153,6 +155,23 @@ def sort_records(recs: np.ndarray, key_bytes: int = 10) -> np.ndarray:
     if lib().oracle_sort_records(_p(recs, _u8p), n, R, key_bytes, _p(out, _u8p)) != 0:
         raise ValueError("bad arguments")
     return out
+
+
+def sort_order_varlen(recs: np.ndarray, key_bytes: int, len_offset: int) -> np.ndarray:
+    """Variable-length keys: input index of each output position when the key
+    of a record is the first min(record[len_offset], key_bytes) bytes of its
+    key field, ordered as byte strings (a prefix first), ties by input index."""
+    recs = _records(recs)
+    n, R = recs.shape
+    perm = np.empty(n, dtype=np.uint64)
+    if lib().oracle_sort_order_varlen(_p(recs, _u8p), n, R, key_bytes, len_offset, _p(perm, _u64p)) != 0:
+        raise ValueError("bad arguments")
+    return perm
+
+
+def sort_records_varlen(recs: np.ndarray, key_bytes: int, len_offset: int) -> np.ndarray:
+    recs = _records(recs)
+    return recs[sort_order_varlen(recs, key_bytes, len_offset).astype(np.int64)]
 
 
 def first_unsorted(recs: np.ndarray, key_bytes: int = 10) -> int:

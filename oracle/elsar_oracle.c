@@ -110,6 +110,42 @@ uint64_t oracle_first_unstable(const uint8_t* recs, uint64_t n, uint32_t rec, ui
   return bad;
 }
 
+/* Variable-length keys (Section 4's padding rule, read as: a key shorter
+ * than the key field is padded with bytes below every byte value).  Record
+ * byte len_off holds the length (at most key); the key is the first len bytes
+ * of the field.  Keys compare as byte strings: memcmp over the shorter length,
+ * then the shorter key first; equal keys by input index. */
+typedef struct {
+  const uint8_t* base;
+  uint32_t rec, key, len_off;
+} varlen_ctx;
+static varlen_ctx g_vctx;
+
+static int cmp_varlen_then_index(const void* pa, const void* pb) {
+  uint64_t a = *(const uint64_t*)pa, b = *(const uint64_t*)pb;
+  const uint8_t* ra = g_vctx.base + a * g_vctx.rec;
+  const uint8_t* rb = g_vctx.base + b * g_vctx.rec;
+  uint32_t la = ra[g_vctx.len_off], lb = rb[g_vctx.len_off];
+  if (la > g_vctx.key) la = g_vctx.key;
+  if (lb > g_vctx.key) lb = g_vctx.key;
+  int c = memcmp(ra, rb, la < lb ? la : lb);
+  if (c) return c;
+  if (la != lb) return la < lb ? -1 : 1;
+  return (a > b) - (a < b);
+}
+
+int oracle_sort_order_varlen(const uint8_t* in, uint64_t n, uint32_t rec, uint32_t key, uint32_t len_off,
+                             uint64_t* perm) {
+  if (!in || !perm || key == 0 || len_off >= rec) return 1;
+  for (uint64_t i = 0; i < n; ++i) perm[i] = i;
+  g_vctx.base = in;
+  g_vctx.rec = rec;
+  g_vctx.key = key;
+  g_vctx.len_off = len_off;
+  qsort(perm, n, sizeof(uint64_t), cmp_varlen_then_index);
+  return 0;
+}
+
 /* Index of the first k with key(k) > key(k+1), or n when keys never decrease. */
 uint64_t oracle_first_unsorted(const uint8_t* recs, uint64_t n, uint32_t rec, uint32_t key) {
   uint64_t bad = n;

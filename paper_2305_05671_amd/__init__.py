@@ -39,6 +39,7 @@ class FitParams(ctypes.Structure):
         ("accept_ratio", ctypes.c_float),
         ("mlp_steps", ctypes.c_uint32),
         ("region_pct", ctypes.c_uint32),
+        ("key_len_offset", ctypes.c_uint32),
     ]
 
 
@@ -74,6 +75,9 @@ class PartitionStats(ctypes.Structure):
         ("max_bucket", ctypes.c_uint32),
         ("mid_records", ctypes.c_uint32),
         ("big_records", ctypes.c_uint32),
+        ("split_segments", ctypes.c_uint32),
+        ("split_segment_cap", ctypes.c_uint32),
+        ("split_overflow", ctypes.c_uint32),
     ]
 
 
@@ -181,7 +185,7 @@ def _check(fn: str, s: int):
 
 
 def fit_params(record_bytes=100, key_bytes=10, num_buckets=0, num_leaves=0, sample_size=0, seed=0,
-               kind=RMI, accept_ratio=1.5, mlp_steps=0, region_pct=0) -> FitParams:
+               kind=RMI, accept_ratio=1.5, mlp_steps=0, region_pct=0, key_len_offset=0) -> FitParams:
     p = FitParams()
     _check("elsar_fit_params_default", lib().elsar_fit_params_default(ctypes.byref(p)))
     p.record_bytes, p.key_bytes = record_bytes, key_bytes
@@ -189,6 +193,7 @@ def fit_params(record_bytes=100, key_bytes=10, num_buckets=0, num_leaves=0, samp
     p.sample_size, p.seed, p.kind = sample_size, seed, kind
     p.accept_ratio, p.mlp_steps = accept_ratio, mlp_steps
     p.region_pct = region_pct
+    p.key_len_offset = key_len_offset
     return p
 
 

@@ -65,7 +65,19 @@ elsar_status check_params(const elsar_fit_params* p) {
   if (p->kind > ELSAR_MODEL_SPLINE) return ELSAR_E_INVALID_ARG;
   if (p->sample_size > 10000000ull * 4) return ELSAR_E_INVALID_ARG;
   if (p->region_pct > 1000) return ELSAR_E_INVALID_ARG;
+  if (p->key_len_offset) {  // variable-length keys: the length byte sits after the key, in the first 12 bytes
+    if (p->key_bytes > 11 || p->key_len_offset < p->key_bytes || p->key_len_offset > 11) return ELSAR_E_UNSUPPORTED;
+  }
   return ELSAR_OK;
+}
+
+// Variable-length keys (virtual_key): the kernels' vk, and the key bytes the
+// bucket sorts order (the virtual key counts its length byte).
+inline uint32_t vkey(const elsar_fit_params& p) {
+  return p.key_len_offset ? (p.key_len_offset << 8) | p.key_bytes : 0u;
+}
+inline uint32_t sort_bytes(const elsar_fit_params& p) {
+  return sort_key_bytes(p.key_bytes + (p.key_len_offset ? 1u : 0u));
 }
 
 // Resolved shape of a model for n records.
@@ -207,7 +219,7 @@ elsar_status do_fit(elsar_model* m, const void* d_records, uint64_t n, void* d_w
   void* rscr = w + 2 * align_up(S * 8);
   void* fscr = w + 2 * align_up(S * 8) + align_up(radix_u64_scratch_bytes(S));
   HIP_TRY(launch_sample_codes(static_cast<const uint8_t*>(d_records), n, m->p.record_bytes, S, m->p.seed, codes,
-                              st));
+                              st, vkey(m->p)));
   if (m->p.kind == ELSAR_MODEL_RADIX) {  // equi-width buckets; the sample only sizes the regions
     HIP_TRY(launch_radix_model(S, n, m->L, m->B, m->hdr, m->leaves, st));
     HIP_TRY(launch_sample_hist(m->hdr, m->leaves, codes, S, m->B, m->hist, st));
@@ -247,7 +259,7 @@ elsar_status do_partition(const elsar_model* m, const void* d_records, uint64_t 
   HIP_TRY(launch_capacities(m->hist, m->S, n, m->B, m->p.region_pct, part, lay, st));
   if (pm) mark(*pm, 1, st);
   HIP_TRY(launch_partition(m->hdr, m->leaves, m->has_mlp ? &m->ms : nullptr, static_cast<const uint8_t*>(d_records),
-                           n, m->p.record_bytes, m->p.key_bytes, part, lay, st));
+                           n, m->p.record_bytes, vkey(m->p), part, lay, st));
   if (pm) mark(*pm, 2, st);
   HIP_TRY(launch_scan_counts(part, lay, m->B, d_offsets, st));
   HIP_TRY(launch_spill_fixup(part, lay, n, st));
@@ -260,10 +272,10 @@ elsar_status do_sort_buckets(const elsar_model* m, void* d_part, size_t part_byt
   if (part_bytes < lay.bytes) return ELSAR_E_NO_MEMORY;
   uint8_t* part = static_cast<uint8_t*>(d_part);
   uint8_t* out = static_cast<uint8_t*>(d_out);
-  const uint32_t K = m->p.key_bytes, Ks = sort_key_bytes(K);
-  HIP_TRY(launch_bucket_sort_small(part, lay, m->B, d_offsets, m->p.record_bytes, Ks, out, st));
+  const uint32_t K = m->p.key_bytes, Ks = sort_bytes(m->p), vk = vkey(m->p);
+  HIP_TRY(launch_bucket_sort_small(part, lay, m->B, d_offsets, m->p.record_bytes, Ks, out, st, vk));
   if (pm) mark(*pm, 4, st);
-  HIP_TRY(launch_bucket_sort_large(part, lay, m->B, n, d_offsets, m->p.record_bytes, Ks, out, st));
+  HIP_TRY(launch_bucket_sort_large(part, lay, m->B, n, d_offsets, m->p.record_bytes, Ks, out, st, vk));
   HIP_TRY(launch_long_key_fixup(out, n, m->p.record_bytes, K, part + lay.slots, st));
   if (pm) mark(*pm, 5, st);
   return ELSAR_OK;
@@ -740,6 +752,7 @@ elsar_status elsar_sort_batch_workspace_size(const elsar_job* h_jobs, uint32_t n
   elsar_status s = check_params(p);
   if (s != ELSAR_OK) return s;
   if (p->key_bytes > kSortKeyBytes) return ELSAR_E_UNSUPPORTED;  // the small-job kernel sorts 12 key bytes
+  if (p->key_len_offset) return ELSAR_E_UNSUPPORTED;             // fixed-length keys only
   BatchLayout bl;
   s = batch_layout(h_jobs, njobs, *p, &bl);
   if (s != ELSAR_OK) return s;
@@ -753,6 +766,7 @@ elsar_status elsar_sort_batch(const elsar_job* h_jobs, uint32_t njobs, const els
   elsar_status s = check_params(p);
   if (s != ELSAR_OK) return s;
   if (p->key_bytes > kSortKeyBytes) return ELSAR_E_UNSUPPORTED;  // the small-job kernel sorts 12 key bytes
+  if (p->key_len_offset) return ELSAR_E_UNSUPPORTED;             // fixed-length keys only
   if (njobs == 0) return ELSAR_OK;
   if (!d_ws || !aligned16(d_ws)) return ELSAR_E_INVALID_ARG;
   BatchLayout bl;
@@ -845,6 +859,12 @@ PartLayout pass_layout(uint64_t P, uint32_t B, uint32_t R, uint32_t K) {
   lay.slots = take(slot_area);
   lay.bytes = off;
   return lay;
+}
+
+// The big-bucket split stayed within its bounds: segments listed (seg_n[0])
+// within the list's capacity, and no piece stack overflowed (seg_n[1]).
+bool split_ok(const PartHeader& ph, const PartLayout& lay) {
+  return ph.seg_n[1] == 0 && ph.seg_n[0] <= lay.seg_leaf_cap;
 }
 
 // Parameters of the in-HBM sort of one chunk (its own sample and model).
@@ -1062,7 +1082,7 @@ elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, void* h_
     if (s != ELSAR_OK) return s;
     HIP_TRY(hipEventRecord(ss.freed[k], stream));
     HIP_TRY(launch_fill_u32(cc, m.B, 0u, stream));
-    HIP_TRY(launch_count(m.hdr, m.leaves, ms, srt, cnt, R, cc, stream));
+    HIP_TRY(launch_count(m.hdr, m.leaves, ms, srt, cnt, R, cc, stream, vkey(q)));
     HIP_TRY(hipEventRecord(ss.sorted[k], stream));
     HIP_TRY(hipStreamWaitEvent(ss.d2h, ss.sorted[k], 0));
     HIP_TRY(hipMemcpyAsync(frag + first * R, srt, cnt * R, hipMemcpyDeviceToHost, ss.d2h));
@@ -1124,7 +1144,11 @@ elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, void* h_
   uint32_t* flag = reinterpret_cast<uint32_t*>(w + hl.flag);
   HIP_TRY(launch_fill_u32(flag, 1, 0u, stream));
   bool stage_busy = false, gbuf_busy = false;
+  bool sorted_once = false;  // the pass buffer's split bookkeeping is valid once a group was sorted
   uint32_t copy_groups = 0;
+  // bytes compared by the copy pass: the key, and with variable-length keys
+  // every byte up to the length byte (equal bytes there mean equal keys)
+  const uint32_t cmp_bytes = q.key_len_offset ? q.key_len_offset + 1 : q.key_bytes;
   for (const Group& g : groups) {
     if (g.total == 0) continue;
     if (g.copy) {
@@ -1150,10 +1174,10 @@ elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, void* h_
         HIP_TRY(hipEventRecord(ss.loaded[0], ss.h2d));
         HIP_TRY(hipStreamWaitEvent(stream, ss.loaded[0], 0));
         if (!have_ref) {
-          HIP_TRY(hipMemcpyAsync(flag + 32, stage, q.key_bytes, hipMemcpyDeviceToDevice, stream));
+          HIP_TRY(hipMemcpyAsync(flag + 32, stage, cmp_bytes, hipMemcpyDeviceToDevice, stream));
           have_ref = true;
         }
-        HIP_TRY(launch_keys_differ(stage, got, R, q.key_bytes, reinterpret_cast<const uint8_t*>(flag + 32), flag,
+        HIP_TRY(launch_keys_differ(stage, got, R, cmp_bytes, reinterpret_cast<const uint8_t*>(flag + 32), flag,
                                    stream));
         HIP_TRY(hipEventRecord(ss.sorted[0], stream));
         HIP_TRY(hipStreamWaitEvent(ss.d2h, ss.sorted[0], 0));
@@ -1183,23 +1207,26 @@ elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, void* h_
     const uint32_t nb = g.hi - g.lo;
     HIP_TRY(launch_exact_regions(counts_dev, g.lo, nb, g.total, part, hl.lay, stream));
     PassFilter f{0, g.lo, g.hi};  // every record of gbuf is in the group; its position breaks ties
-    HIP_TRY(launch_partition(m.hdr, m.leaves, ms, gbuf, g.total, R, q.key_bytes, part, hl.lay, stream, &f));
+    HIP_TRY(launch_partition(m.hdr, m.leaves, ms, gbuf, g.total, R, vkey(q), part, hl.lay, stream, &f));
     HIP_TRY(hipEventRecord(ss.freed[0], stream));
     gbuf_busy = true;
     // the regions are exact: a record that found its region full would mean
-    // the run counts and the placement disagree; stop before a sort reads it
+    // the run counts and the placement disagree; stop before a sort reads it.
+    // The header still holds the previous group's split bookkeeping (the
+    // bucket sorts clear it), checked here too.
     {
       PartHeader ph;
       HIP_TRY(hipMemcpyAsync(&ph, part + hl.lay.header, sizeof(ph), hipMemcpyDeviceToHost, stream));
       HIP_TRY(hipStreamSynchronize(stream));
-      if (ph.spill_count != 0) return ELSAR_E_HIP;
+      if (ph.spill_count != 0 || (sorted_once && !split_ok(ph, hl.lay))) return ELSAR_E_HIP;
     }
     HIP_TRY(launch_scan_counts(part, hl.lay, nb, offsets, stream));
     if (stage_busy) HIP_TRY(hipStreamWaitEvent(stream, ss.copied[0], 0));  // the previous output is out
-    HIP_TRY(launch_bucket_sort_small(part, hl.lay, nb, offsets, R, sort_key_bytes(q.key_bytes), stage, stream));
-    HIP_TRY(launch_bucket_sort_large(part, hl.lay, nb, g.total, offsets, R, sort_key_bytes(q.key_bytes), stage,
-                                     stream));
+    HIP_TRY(launch_bucket_sort_small(part, hl.lay, nb, offsets, R, sort_bytes(q), stage, stream, vkey(q)));
+    HIP_TRY(launch_bucket_sort_large(part, hl.lay, nb, g.total, offsets, R, sort_bytes(q), stage, stream,
+                                     vkey(q)));
     HIP_TRY(launch_long_key_fixup(stage, g.total, R, q.key_bytes, part + hl.lay.slots, stream));
+    sorted_once = true;
     HIP_TRY(hipEventRecord(ss.sorted[0], stream));
     HIP_TRY(hipStreamWaitEvent(ss.d2h, ss.sorted[0], 0));
     HIP_TRY(hipMemcpyAsync(out + g.first * R, stage, g.total * R, hipMemcpyDeviceToHost, ss.d2h));
@@ -1209,10 +1236,16 @@ elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, void* h_
   HIP_TRY(hipStreamSynchronize(ss.d2h));
   HIP_TRY(hipStreamSynchronize(ss.h2d));
   HIP_TRY(hipStreamSynchronize(stream));
-  // every bucket copied through held one key only
+  // every bucket copied through held one key only; the last group's split
+  // stayed within its bounds
   uint32_t bad = 0;
   HIP_TRY(hipMemcpy(&bad, flag, 4, hipMemcpyDeviceToHost));
   if (bad) return ELSAR_E_UNSUPPORTED;  // a bucket above a pass whose keys differ
+  if (sorted_once) {
+    PartHeader ph;
+    HIP_TRY(hipMemcpy(&ph, part + hl.lay.header, sizeof(ph), hipMemcpyDeviceToHost));
+    if (!split_ok(ph, hl.lay)) return ELSAR_E_HIP;
+  }
   if (stats) {
     stats->chunk_records = hl.C;
     stats->pass_records = hl.P;
@@ -1417,6 +1450,10 @@ elsar_status elsar_partition_stats_get(const elsar_model* m, const void* d_part,
   st->max_bucket = h.max_count;
   st->mid_records = h.mid_records;
   st->big_records = h.big_records;
+  st->split_segments = h.seg_n[0];
+  st->split_segment_cap =
+      part_layout(h.n, m->B, m->p.record_bytes, m->p.region_pct, m->p.key_bytes).seg_leaf_cap;
+  st->split_overflow = h.seg_n[1];
   return ELSAR_OK;
 }
 

@@ -144,6 +144,32 @@ __device__ __forceinline__ uint64_t key_code(uint32_t w0, uint32_t w1) {
   return (uint64_t)h * 81450625ull + l;  // 95^4
 }
 
+// Variable-length keys.  vk = 0: fixed-length keys.  Otherwise vk = (lo << 8)
+// | K: the key field is record bytes [0, K) (K <= 11), the key proper is its
+// first len bytes, len = min(record byte lo, K) with K <= lo < 12, and the
+// field's bytes from len on are padding, whatever they hold.  Order: the
+// padded key with the padding read as 0x00 (below every byte value), then
+// len, so that a key sorts before the keys it is a proper prefix of.  The
+// record's first 12 bytes (little-endian dwords r0..r2) become that sort key
+// as a fixed key of K + 1 bytes: bytes [0, len) kept, [len, K) zero, byte K =
+// len, the rest zero.  Every kernel that reads a key applies this first, so
+// the code, the bucket and the composite all see the same key.
+__device__ __forceinline__ void virtual_key(uint32_t& r0, uint32_t& r1, uint32_t& r2, uint32_t vk) {
+  if (!vk) return;
+  const uint32_t K = vk & 0xFFu, lo = vk >> 8;
+  const uint32_t w = lo < 4 ? r0 : (lo < 8 ? r1 : r2);
+  uint32_t len = (w >> (8 * (lo & 3u))) & 0xFFu;
+  len = len < K ? len : K;
+  auto keep = [&](uint32_t x, uint32_t base) -> uint32_t {  // bytes base..base+3 of the window
+    if (len >= base + 4) return x;
+    if (len <= base) return 0u;
+    return x & ((1u << (8 * (len - base))) - 1u);
+  };
+  r0 = keep(r0, 0);
+  r1 = keep(r1, 4);
+  r2 = keep(r2, 8) | (len << (8 * (K - 8)));  // K in 8..11: byte K sits in r2
+}
+
 __device__ __forceinline__ float code_f32(uint64_t e) { return (float)(double)e; }
 
 __device__ __forceinline__ uint32_t rmi_leaf(float a0, float a1, uint32_t L, uint64_t e) {
@@ -275,7 +301,7 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T* total) {
 // sample / fit (k_fit.hip)
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_sample_codes(const uint8_t* recs, uint64_t n, uint32_t rec_bytes, uint64_t S, uint64_t seed,
-                               uint64_t* codes, hipStream_t st);
+                               uint64_t* codes, hipStream_t st, uint32_t vk = 0);
 size_t radix_u64_scratch_bytes(uint64_t n);
 hipError_t launch_radix_sort_u64(uint64_t* keys, uint64_t* tmp, uint64_t n, int lo_byte, int hi_byte,
                                  void* scratch, hipStream_t st, uint64_t** sorted);
@@ -361,10 +387,10 @@ struct PassFilter {     // host tier: a chunk at input index idx_base, buckets l
 };
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const MlpState* ms, const uint8_t* recs,
-                            uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint8_t* part,
+                            uint64_t n, uint32_t rec_bytes, uint32_t vk, uint8_t* part,
                             const PartLayout& lay, hipStream_t st, const PassFilter* filter = nullptr);
 hipError_t launch_count(const ModelHeader* hdr, const Leaf* leaves, const MlpState* ms, const uint8_t* recs,
-                        uint64_t n, uint32_t rec_bytes, uint32_t* counts, hipStream_t st);
+                        uint64_t n, uint32_t rec_bytes, uint32_t* counts, hipStream_t st, uint32_t vk = 0);
 hipError_t launch_keys_differ(const uint8_t* recs, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
                               const uint8_t* ref, uint32_t* flag, hipStream_t st);
 hipError_t launch_exact_regions(const uint32_t* counts_all, uint32_t lo, uint32_t nb, uint64_t total, uint8_t* part,
@@ -374,8 +400,11 @@ hipError_t launch_scan_counts(uint8_t* part, const PartLayout& lay, uint32_t B, 
 hipError_t launch_spill_fixup(uint8_t* part, const PartLayout& lay, uint64_t n, hipStream_t st);
 
 // bucket sort (k_bucket_sort.hip)
+// key_bytes: bytes of the (virtual) key the composite holds, at most 12; vk
+// as for virtual_key.
 hipError_t launch_bucket_sort_small(uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
-                                    uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st);
+                                    uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st,
+                                    uint32_t vk = 0);
 // whole jobs of up to kSmallCap records, one block each (batch)
 struct TinyJob {
   const uint32_t* in;   // n records
@@ -386,6 +415,7 @@ struct TinyJob {
 hipError_t launch_tiny_jobs(const TinyJob* d_jobs, uint32_t njobs, uint32_t rec_bytes, uint32_t key_bytes,
                             uint32_t* staging, hipStream_t st);
 hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32_t B, uint64_t n, const uint64_t* offsets,
-                                    uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st);
+                                    uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st,
+                                    uint32_t vk = 0);
 
 }  // namespace elsar

@@ -58,8 +58,12 @@ __device__ __forceinline__ uint4 composite_words(uint32_t idx, uint32_t r0, uint
   return make_uint4(__builtin_bswap32(r0), __builtin_bswap32(r1), (uint32_t)(low >> 32), (uint32_t)low);
 }
 
-__device__ __forceinline__ uint4 composite(const uint32_t* __restrict__ s, uint32_t /*RW*/, uint32_t K) {
-  return composite_words(s[0], s[1], s[2], s[3], K);
+// The composite of a slot; with variable-length keys (vk != 0) of the
+// record's virtual key (virtual_key), K then counting its length byte.
+__device__ __forceinline__ uint4 composite(const uint32_t* __restrict__ s, uint32_t K, uint32_t vk) {
+  uint32_t r0 = s[1], r1 = s[2], r2 = s[3];
+  virtual_key(r0, r1, r2, vk);
+  return composite_words(s[0], r0, r1, r2, K);
 }
 
 __device__ __forceinline__ uint32_t digit_of(const uint4& c, uint32_t p) {
@@ -355,7 +359,7 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map, const uint4* __restrict__ slots,
     uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t K, uint32_t* __restrict__ out, uint32_t B,
-    uint32_t* __restrict__ seg_n) {
+    uint32_t* __restrict__ seg_n, uint32_t vk) {
   if (seg_n && blockIdx.x == 0 && threadIdx.x < 4) seg_n[threadIdx.x] = 0;  // the big-bucket split's counters
   constexpr uint32_t SC = slot_bytes_for(RW * 4) / 16;  // 16-byte chunks per slot
   constexpr uint32_t LC = (RW + 1 + 3) / 4;             // chunks holding the index or record bytes
@@ -387,6 +391,10 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
   for (uint32_t i = 0; i < AR; ++i) {
     uint32_t p = tid + i * kSmThreads;
     if (p < n) v[i] = slots[(uint64_t)slot_of(br, p, spill_map, cap_slots) * SC];
+  }
+  if (vk) {
+#pragma unroll
+    for (uint32_t i = 0; i < AR; ++i) virtual_key(v[i].y, v[i].z, v[i].w, vk);
   }
   uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
   uint64_t cmin = ~0ull, cmax = 0;  // base-95 codes of the first 8 key bytes
@@ -500,7 +508,7 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
     const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
     uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
-    uint32_t B, uint32_t* __restrict__ seg_n) {
+    uint32_t B, uint32_t* __restrict__ seg_n, uint32_t vk) {
   if (seg_n && blockIdx.x == 0 && threadIdx.x < 4) seg_n[threadIdx.x] = 0;  // the big-bucket split's counters
   constexpr uint32_t WAVES = THREADS / 64;
   static_assert(CAP % THREADS == 0, "cap is whole rounds");
@@ -536,7 +544,7 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
     uint64_t cmin = ~0ull, cmax = 0;
     for (uint32_t p = threadIdx.x; p < br.n; p += THREADS) {
       uint32_t sl = slot_of(br, p, spill_map, cap_slots);
-      uint4 c = composite(slots + (uint64_t)sl * W, RW, K);
+      uint4 c = composite(slots + (uint64_t)sl * W, K, vk);
       ent[p] = c;
       o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
       a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
@@ -724,7 +732,8 @@ __global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
     const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
-    uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n) {
+    uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
+    uint32_t vk) {
   __shared__ LsdShared lsd;
   __shared__ uint4 sh_or[kBigWaves], sh_and[kBigWaves];
   __shared__ uint32_t chunk_slot[kBigTile];
@@ -745,7 +754,7 @@ __global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
     // 1. which composite bytes vary
     uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
     for (uint32_t p = threadIdx.x; p < br.n; p += kBigThreads) {
-      uint4 c = composite(slots + (uint64_t)slot_of(br, p, spill_map, cap_slots) * W, RW, K);
+      uint4 c = composite(slots + (uint64_t)slot_of(br, p, spill_map, cap_slots) * W, K, vk);
       o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
       a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
     }
@@ -757,7 +766,7 @@ __global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
     uint32_t* nxt = (passes & 1u) ? buf1 : buf0;
     for (uint32_t p = threadIdx.x; p < br.n; p += kBigThreads) {
       uint32_t sl = slot_of(br, p, spill_map, cap_slots);
-      put_entry(cur, p, composite(slots + (uint64_t)sl * W, RW, K), sl);
+      put_entry(cur, p, composite(slots + (uint64_t)sl * W, K, vk), sl);
     }
     __syncthreads();
     // 2. stable LSD passes through global memory
@@ -919,7 +928,8 @@ __global__ __launch_bounds__(kMsdThreads) void msd_split_kernel(
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
     const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
     uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
-    uint4* __restrict__ leaf, uint32_t* __restrict__ leaf_n, uint32_t leaf_cap, uint32_t* __restrict__ error) {
+    uint4* __restrict__ leaf, uint32_t* __restrict__ leaf_n, uint32_t leaf_cap, uint32_t* __restrict__ error,
+    uint32_t vk) {
   __shared__ MsdShared sh;
   const uint32_t W = slot_bytes_for(RW * 4) / 4;
   const uint32_t nitems = *list_n;
@@ -943,7 +953,7 @@ __global__ __launch_bounds__(kMsdThreads) void msd_split_kernel(
     uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
     for (uint32_t q = threadIdx.x; q < br.n; q += kMsdThreads) {
       const uint32_t sl = slot_of(br, q, spill_map, cap_slots);
-      const uint4 c = composite(slots + (uint64_t)sl * W, RW, K);
+      const uint4 c = composite(slots + (uint64_t)sl * W, K, vk);
       put_entry(Bf, q, c, sl);
       o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
       a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
@@ -1353,18 +1363,21 @@ static SortArgs sort_args(const uint8_t* part, const PartLayout& lay, uint32_t r
 }
 
 hipError_t launch_bucket_sort_small(uint8_t* part, const PartLayout& lay, uint32_t B, const uint64_t* offsets,
-                                    uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st) {
+                                    uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st,
+                                    uint32_t vk) {
   SortArgs a = sort_args(part, lay, rec_bytes, out);
   if (rec_bytes == 100) {
     bucket_sort_small_kernel<25><<<B, kSmThreads, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap,
                                                            reinterpret_cast<const uint4*>(a.slots), lay.cap_slots,
                                                            offsets, key_bytes, a.out, B,
-                                                           reinterpret_cast<PartHeader*>(part + lay.header)->seg_n);
+                                                           reinterpret_cast<PartHeader*>(part + lay.header)->seg_n,
+                                                           vk);
   } else {
     bucket_sort_lds_kernel<kSmallCap, 256><<<B, 256, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots,
                                                                lay.cap_slots, offsets, a.RW, key_bytes, a.out,
                                                                nullptr, nullptr, B,
-                                                               reinterpret_cast<PartHeader*>(part + lay.header)->seg_n);
+                                                               reinterpret_cast<PartHeader*>(part + lay.header)->seg_n,
+                                                               vk);
   }
   return hipGetLastError();
 }
@@ -1380,16 +1393,16 @@ static uint32_t grid_for(uint64_t n, uint64_t per_block, uint32_t most) {
 
 hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32_t B, uint64_t n,
                                     const uint64_t* offsets, uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out,
-                                    hipStream_t st) {
+                                    hipStream_t st, uint32_t vk) {
   SortArgs a = sort_args(part, lay, rec_bytes, out);
   bucket_sort_lds_kernel<kMidCap, 512><<<grid_for(n, kSmallCap + 1, 256), 512, 0, st>>>(
       a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
-      reinterpret_cast<const uint32_t*>(part + lay.mid_list), &a.ph->n_mid, B, nullptr);
+      reinterpret_cast<const uint32_t*>(part + lay.mid_list), &a.ph->n_mid, B, nullptr, vk);
   const uint32_t* big_list = reinterpret_cast<const uint32_t*>(part + lay.big_list);
   if (rec_bytes < 64) {  // too little room for the split's buffers, stack and reference list
     bucket_sort_global_kernel<<<grid_for(n, kMidCap + 1, 256), kBigThreads, 0, st>>>(
         a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
-        big_list, &a.ph->n_big);
+        big_list, &a.ph->n_big, vk);
     return hipGetLastError();
   }
   PartHeader* ph = reinterpret_cast<PartHeader*>(part + lay.header);
@@ -1399,7 +1412,7 @@ hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32
   // the split's counters (ph->seg_n) were cleared by the small-bucket kernel
   msd_split_kernel<<<grid_for(n, kMidCap + 1, 512), kMsdThreads, 0, st>>>(
       a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out, big_list,
-      &a.ph->n_big, leaf, leaf_n, leaf_cap, &ph->seg_n[1]);
+      &a.ph->n_big, leaf, leaf_n, leaf_cap, &ph->seg_n[1], vk);
   seg_sort_kernel<<<grid_for(n, 1024, 2048), kSmThreads, 0, st>>>(a.counts, offsets, a.RW, a.out, leaf, leaf_n,
                                                                    leaf_cap);
   big_gather_kernel<<<grid_for(n, kMidCap + 1, 512), kMsdThreads, 0, st>>>(

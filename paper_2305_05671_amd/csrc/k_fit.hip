@@ -20,18 +20,20 @@ __device__ __forceinline__ uint64_t sample_index(uint64_t s, uint64_t n, uint64_
 
 __global__ __launch_bounds__(256) void sample_codes_kernel(const uint8_t* __restrict__ recs, uint64_t n,
                                                            uint32_t rec_bytes, uint64_t S, uint64_t seed,
-                                                           uint64_t* __restrict__ codes) {
+                                                           uint64_t* __restrict__ codes, uint32_t vk) {
   uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (s >= S) return;
   const uint32_t* r = reinterpret_cast<const uint32_t*>(recs + sample_index(s, n, S, seed) * rec_bytes);
-  codes[s] = key_code(r[0], r[1]);
+  uint32_t r0 = r[0], r1 = r[1], r2 = vk ? r[2] : 0u;
+  virtual_key(r0, r1, r2, vk);
+  codes[s] = key_code(r0, r1);
 }
 
 hipError_t launch_sample_codes(const uint8_t* recs, uint64_t n, uint32_t rec_bytes, uint64_t S, uint64_t seed,
-                               uint64_t* codes, hipStream_t st) {
+                               uint64_t* codes, hipStream_t st, uint32_t vk) {
   if (S == 0) return hipSuccess;
   uint32_t grid = (uint32_t)((S + 255) / 256);
-  sample_codes_kernel<<<grid, 256, 0, st>>>(recs, n, rec_bytes, S, seed, codes);
+  sample_codes_kernel<<<grid, 256, 0, st>>>(recs, n, rec_bytes, S, seed, codes, vk);
   return hipGetLastError();
 }
 

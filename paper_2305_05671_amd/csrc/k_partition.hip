@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
     const uint64_t* __restrict__ bound, const uint64_t* __restrict__ knots, const uint32_t* __restrict__ cells,
     const uint8_t* __restrict__ recs, uint64_t n, uint32_t rw_rt, uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps,
     const uint32_t* __restrict__ rstart, PartHeader* __restrict__ ph, uint2* __restrict__ spill_meta,
-    uint4* __restrict__ slots, uint64_t cap_slots, PassFilter f) {
+    uint4* __restrict__ slots, uint64_t cap_slots, PassFilter f, uint32_t vk) {
   const uint32_t RW = RW_T ? (uint32_t)RW_T : rw_rt;  // record dwords
   const uint32_t SC = slot_bytes_for(RW * 4) / 16;     // 16-byte chunks per slot
   constexpr uint32_t RV = RW_T ? (kPartTile * RW_T / 4 + kPartThreads - 1) / kPartThreads : 8;
@@ -169,7 +169,9 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
       // every lane takes part in the matrix products; lanes past the tile's
       // end read stale tile bytes and discard the result
       const uint32_t* r = buf(cur) + threadIdx.x * RW;
-      const uint64_t e = key_code(r[0], r[1]);
+      uint32_t r0 = r[0], r1 = r[1], r2 = vk ? r[2] : 0u;
+      virtual_key(r0, r1, r2, vk);
+      const uint64_t e = key_code(r0, r1);
       const float y = mlp_y64(e, mh_, w2);
       if (threadIdx.x < cnt) {
         const uint32_t j = mlp_bracket_leaf(bound, cells, L, e, y);
@@ -177,7 +179,9 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
       }
     } else if (threadIdx.x < cnt) {
       const uint32_t* r = buf(cur) + threadIdx.x * RW;
-      uint64_t e = key_code(r[0], r[1]);
+      uint32_t r0 = r[0], r1 = r[1], r2 = vk ? r[2] : 0u;
+      virtual_key(r0, r1, r2, vk);
+      uint64_t e = key_code(r0, r1);
       const uint32_t j = ROOT == 2 ? spline_exact_leaf(knots, K, bound, L, e) : rmi_leaf(a0, a1, L, e);
       b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
     }
@@ -234,19 +238,19 @@ static void launch_partition_root(uint32_t grid, size_t lds, hipStream_t st, uin
                                   const uint64_t* knots, const uint32_t* cells, const uint8_t* recs, uint64_t n,
                                   uint32_t* counts,
                                   const uint32_t* caps, const uint32_t* rstart, PartHeader* ph, uint2* meta,
-                                  uint4* slots, uint64_t cap_slots, PassFilter f) {
+                                  uint4* slots, uint64_t cap_slots, PassFilter f, uint32_t vk) {
   if (RW == 25)
     partition_kernel<25, ROOT, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, knots, cells, recs, n, RW,
                                                                         counts, caps, rstart, ph, meta, slots,
-                                                                        cap_slots, f);
+                                                                        cap_slots, f, vk);
   else
     partition_kernel<0, ROOT, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, knots, cells, recs, n, RW,
                                                                        counts, caps, rstart, ph, meta, slots,
-                                                                       cap_slots, f);
+                                                                       cap_slots, f, vk);
 }
 
 hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const MlpState* ms, const uint8_t* recs,
-                            uint64_t n, uint32_t rec_bytes, uint32_t /*key_bytes*/, uint8_t* part,
+                            uint64_t n, uint32_t rec_bytes, uint32_t vk, uint8_t* part,
                             const PartLayout& lay, hipStream_t st, const PassFilter* filter) {
   if (n == 0) return hipSuccess;
   const uint32_t RW = rec_bytes / 4;
@@ -265,21 +269,21 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const Ml
   const PassFilter f = filter ? *filter : PassFilter{0, 0, 0};
   if (filter) {
     launch_partition_root<0, true>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, nullptr, nullptr, recs, n,
-                                   counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
+                                   counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk);
     if (ms) {
       launch_partition_root<1, true>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, nullptr, ms->cells, recs,
-                                     n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
+                                     n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk);
       launch_partition_root<2, true>(grid, lds, st, RW, hdr, ms->leaves, nullptr, ms->bound, ms->knots, nullptr, recs,
-                                     n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
+                                     n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk);
     }
   } else {
     launch_partition_root<0, false>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, nullptr, nullptr, recs, n,
-                                    counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
+                                    counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk);
     if (ms) {
       launch_partition_root<1, false>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, nullptr, ms->cells, recs,
-                                      n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
+                                      n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk);
       launch_partition_root<2, false>(grid, lds, st, RW, hdr, ms->leaves, nullptr, ms->bound, ms->knots, nullptr,
-                                      recs, n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f);
+                                      recs, n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk);
     }
   }
   return hipGetLastError();
@@ -294,7 +298,8 @@ __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restric
                                                     const uint64_t* __restrict__ bound,
                                                     const uint64_t* __restrict__ knots,
                                                     const uint32_t* __restrict__ cells, const uint32_t* __restrict__ rec,
-                                                    uint64_t n, uint32_t RW, uint32_t* __restrict__ counts) {
+                                                    uint64_t n, uint32_t RW, uint32_t* __restrict__ counts,
+                                                    uint32_t vk) {
   constexpr bool MLP = ROOT == 1;
   if (hdr->kind_used != (uint32_t)ROOT) return;
   __shared__ typename std::conditional<MLP, MlpHead, uint32_t>::type mh_;
@@ -313,7 +318,9 @@ __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restric
   for (uint64_t base = wave0; base < n; base += stride) {  // uniform per wave
     const uint64_t i = base + lane_id();
     const uint32_t* r = rec + (i < n ? i : n - 1) * RW;
-    const uint64_t e = key_code(r[0], r[1]);
+    uint32_t r0 = r[0], r1 = r[1], r2 = vk ? r[2] : 0u;
+    virtual_key(r0, r1, r2, vk);
+    const uint64_t e = key_code(r0, r1);
     uint32_t b;
     if constexpr (MLP) {
       const float y = mlp_y64(e, mh_, w2);
@@ -328,17 +335,17 @@ __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restric
 }
 
 hipError_t launch_count(const ModelHeader* hdr, const Leaf* leaves, const MlpState* ms, const uint8_t* recs,
-                        uint64_t n, uint32_t rec_bytes, uint32_t* counts, hipStream_t st) {
+                        uint64_t n, uint32_t rec_bytes, uint32_t* counts, hipStream_t st, uint32_t vk) {
   if (n == 0) return hipSuccess;
   const uint32_t RW = rec_bytes / 4;
   const uint64_t waves = (n + 63) / 64;
   const uint32_t grid = (uint32_t)std::min<uint64_t>((waves + 3) / 4, 4096);
   const uint32_t* rec = reinterpret_cast<const uint32_t*>(recs);
-  count_kernel<0><<<grid, 256, 0, st>>>(hdr, leaves, nullptr, nullptr, nullptr, nullptr, rec, n, RW, counts);
+  count_kernel<0><<<grid, 256, 0, st>>>(hdr, leaves, nullptr, nullptr, nullptr, nullptr, rec, n, RW, counts, vk);
   if (ms) {
-    count_kernel<1><<<grid, 256, 0, st>>>(hdr, ms->leaves, ms->M, ms->bound, nullptr, ms->cells, rec, n, RW, counts);
+    count_kernel<1><<<grid, 256, 0, st>>>(hdr, ms->leaves, ms->M, ms->bound, nullptr, ms->cells, rec, n, RW, counts, vk);
     count_kernel<2><<<grid, 256, 0, st>>>(hdr, ms->leaves, nullptr, ms->bound, ms->knots, nullptr, rec, n, RW,
-                                          counts);
+                                          counts, vk);
   }
   return hipGetLastError();
 }

@@ -68,6 +68,13 @@ def test_argument_checks_return_before_any_work(elsar):
     bad = elsar.fit_params(num_buckets=(1 << 21) + 1)
     assert lib.elsar_sort_workspace_size(ctypes.byref(bad), 10, ctypes.byref(sz)) == elsar.E_INVALID_ARG
     assert lib.elsar_sort_workspace_size(ctypes.byref(p), 2 * 10 ** 9, ctypes.byref(sz)) == elsar.E_UNSUPPORTED
+    # the in-HBM ceiling: input, output and workspace of the largest sort fit
+    # one MI355X's 288 GB; one record more is refused before any work
+    top = 400_000_000
+    assert lib.elsar_sort_workspace_size(ctypes.byref(p), top, ctypes.byref(sz)) == elsar.OK
+    assert sz.value + 2 * 100 * top <= 288 * 10 ** 9
+    assert lib.elsar_sort_workspace_size(ctypes.byref(p), top + 1, ctypes.byref(sz)) == elsar.E_UNSUPPORTED
+    assert lib.elsar_sort(16, top + 1, 32, ctypes.byref(p), 64, 10 ** 12, None) == elsar.E_UNSUPPORTED
     assert lib.elsar_sort_workspace_size(None, 10, ctypes.byref(sz)) == elsar.E_INVALID_ARG
     # n == 0 is a no-op; null buffers with n > 0 are rejected before anything is enqueued
     assert lib.elsar_sort(None, 0, None, ctypes.byref(p), None, 0, None) == elsar.OK

@@ -202,8 +202,18 @@ def test_other_record_shapes(env, R, K, kind_name):
     ("uniform", 400_000, 8, 23, 1),        # huge buckets mostly in the spill area
 ])
 def test_big_buckets_split(env, kind, n, B, seed, region):
+    torch, elsar = env
     recs = datagen.generate(datagen.spec(kind, seed=seed), n)
     _assert_same(_gpu_sort(env, recs, num_buckets=B, seed=seed, region_pct=region), oracle.sort_records(recs))
+    # the split's own bookkeeping: every segment listed, no stack overflow
+    m, part, offsets, d = _fit_and_partition(env, recs, num_buckets=B, seed=seed, region_pct=region)
+    out = torch.empty_like(d)
+    m.sort_buckets(part, offsets, n, out)
+    torch.cuda.synchronize()
+    st = m.partition_stats(part)
+    assert st.big_buckets > 0 and st.split_segments > 0
+    assert st.split_segments <= st.split_segment_cap and st.split_overflow == 0
+    _assert_same(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs))
 
 
 def test_big_bucket_equal_keys_and_prefixes(env):

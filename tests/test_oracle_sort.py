@@ -135,3 +135,35 @@ def test_parallel_baseline_matches_oracle():
     perm, used = oracle.parallel_sort_order(recs.ctypes.data, recs.shape[0])
     assert used >= 1
     assert np.array_equal(perm, oracle.sort_order(recs))
+
+
+def _varlen_records(n, K, lo, seed, alphabet=b"ab\x00\xff"):
+    rng = np.random.default_rng(seed)
+    recs = rng.integers(0, 256, size=(n, 32), dtype=np.uint8)  # garbage everywhere first
+    a = np.frombuffer(alphabet, np.uint8)
+    recs[:, :K] = a[rng.integers(0, a.size, size=(n, K))]
+    recs[:, lo] = rng.integers(0, K + 3, size=n)  # lengths above K count as K
+    return recs
+
+
+def test_varlen_worked_example():
+    # the key is the first len bytes; the rest of the field is ignored padding;
+    # a proper prefix sorts first, a 0x00 byte is a byte like any other
+    K, lo = 4, 4
+    rows = [(b"abXX", 2), (b"ab\x00Y", 3), (b"abc\x00", 3), (b"abZZ", 2), (b"a\xff\xff\xff", 4),
+            (b"\x00\x00\x00\x00", 0), (b"ab\x01Q", 3), (b"zzzz", 9)]
+    recs = np.zeros((len(rows), 8), np.uint8)
+    for i, (k, ln) in enumerate(rows):
+        recs[i, :4] = np.frombuffer(k, np.uint8)
+        recs[i, lo] = ln
+    order = [int(i) for i in oracle.sort_order_varlen(recs, K, lo)]
+    # "" < "ab" (twice, input order) < "ab\x00" < "ab\x01" < "abc" < "a\xff\xff\xff" < "zzzz"
+    assert order == [5, 0, 3, 1, 6, 2, 4, 7]
+
+
+@pytest.mark.parametrize("K,lo", [(8, 8), (10, 10), (11, 11), (8, 11)])
+def test_varlen_matches_python_bytes_order(K, lo):
+    recs = _varlen_records(20_000, K, lo, seed=K + lo)
+    lens = np.minimum(recs[:, lo], K)
+    want = sorted(range(recs.shape[0]), key=lambda i: (bytes(recs[i, :lens[i]]), i))
+    assert [int(x) for x in oracle.sort_order_varlen(recs, K, lo)] == want
