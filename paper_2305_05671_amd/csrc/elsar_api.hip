@@ -145,6 +145,8 @@ PartLayout part_layout(uint64_t n, uint32_t B, uint32_t R, uint32_t region_pct, 
   };
   lay.header = take(sizeof(PartHeader));
   lay.counts = take((size_t)B * 4);
+  lay.cstride = counter_stride(B);
+  lay.pcounts = lay.cstride > 1 ? take((size_t)B * lay.cstride * 4) : lay.counts;
   lay.caps = take((size_t)B * 4);
   lay.rstart = take((size_t)B * 4);
   lay.spill_off = take((size_t)B * 4);
@@ -842,6 +844,8 @@ PartLayout pass_layout(uint64_t P, uint32_t B, uint32_t R, uint32_t K) {
   };
   lay.header = take(sizeof(PartHeader));
   lay.counts = take((size_t)B * 4);
+  lay.cstride = counter_stride(B);
+  lay.pcounts = lay.cstride > 1 ? take((size_t)B * lay.cstride * 4) : lay.counts;
   lay.caps = take((size_t)B * 4);
   lay.rstart = take((size_t)B * 4);
   lay.spill_off = take((size_t)B * 4);

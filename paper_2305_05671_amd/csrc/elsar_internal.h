@@ -89,6 +89,14 @@ struct PartHeader {    // device-resident state of one partition pass
 // Byte offsets of the partition buffer's parts for n records and B buckets.
 struct PartLayout {
   size_t header, counts, caps, rstart, spill_off, mid_list, big_list;
+  // The partition's slot counters: bucket j's at pcounts + 4 * j * cstride.
+  // Returning atomics on counters packed 32 to a 128-byte line serialise per
+  // line (10^6 of them on 1024 packed counters took 5x as long as on the same
+  // counters one per line), so with fewer than 65536 buckets the counters are
+  // spread over at least 2048 lines; the scan then writes the dense counts
+  // the bucket sorts read.  With cstride 1, pcounts == counts.
+  size_t pcounts;
+  uint32_t cstride;
   size_t spill_meta, spill_map, slots;
   size_t seg_leaf;               // segment list of the big-bucket split
   uint32_t seg_leaf_cap;
@@ -99,6 +107,18 @@ struct PartLayout {
 };
 
 __host__ __device__ constexpr uint32_t slot_bytes_for(uint32_t rec_bytes) { return (rec_bytes + 4 + 127) / 128 * 128; }
+
+// Spacing (in u32) of the partition's slot counters for B buckets.  Every
+// record is one atomic on its bucket's counter, and atomics to one 128-byte
+// line serialise in L2, so with few buckets the counters are spread over at
+// least 2048 lines (at most one per line).  From 65536 buckets up they stay
+// dense: the counters are already spread over enough lines, and padding
+// them only adds L2 footprint.
+inline uint32_t counter_stride(uint32_t B) {
+  if (B >= 65536) return 1;
+  const uint32_t s = 65536 / B;
+  return s < 32 ? s : 32;
+}
 
 // ----------------------------------------------------------- device code --
 // Native 4 x u32 vector for register-held data: HIP's uint4 struct copies go

@@ -571,7 +571,7 @@ __global__ __launch_bounds__(kScanThreads) void capacity_kernel(const uint32_t* 
                                                                 uint64_t n, uint32_t B, double scale,
                                                                 uint32_t* __restrict__ caps,
                                                                 uint32_t* __restrict__ rstart,
-                                                                uint32_t* __restrict__ counts,
+                                                                uint32_t* __restrict__ counts, uint32_t cstride,
                                                                 PartHeader* __restrict__ ph, uint64_t cap_slots) {
   __shared__ uint64_t sh[kScanWaves];
   const double ideal = (double)n / (double)B;
@@ -644,14 +644,19 @@ __global__ __launch_bounds__(kScanThreads) void capacity_kernel(const uint32_t* 
       if (j + 4 <= s1) {
         *reinterpret_cast<uint4*>(caps + j) = make_uint4(cp[0], cp[1], cp[2], cp[3]);
         *reinterpret_cast<uint4*>(rstart + j) = make_uint4(rp[0], rp[1], rp[2], rp[3]);
-        *reinterpret_cast<uint4*>(counts + j) = make_uint4(0, 0, 0, 0);
+        if (cstride == 1) {
+          *reinterpret_cast<uint4*>(counts + j) = make_uint4(0, 0, 0, 0);
+        } else {
+#pragma unroll
+          for (uint32_t q = 0; q < 4; ++q) counts[(uint64_t)(j + q) * cstride] = 0;
+        }
       } else {
 #pragma unroll
         for (uint32_t q = 0; q < 4; ++q) {
           if (j + q < s1) {
             caps[j + q] = cp[q];
             rstart[j + q] = rp[q];
-            counts[j + q] = 0;
+            counts[(uint64_t)(j + q) * cstride] = 0;
           }
         }
       }
@@ -676,7 +681,7 @@ hipError_t launch_capacities(const uint32_t* hist, uint64_t S, uint64_t n, uint3
   capacity_kernel<<<1, kScanThreads, 0, st>>>(hist, S, n, B, region_pct / 100.0,
                                               reinterpret_cast<uint32_t*>(part + lay.caps),
                                               reinterpret_cast<uint32_t*>(part + lay.rstart),
-                                              reinterpret_cast<uint32_t*>(part + lay.counts),
+                                              reinterpret_cast<uint32_t*>(part + lay.pcounts), lay.cstride,
                                               reinterpret_cast<PartHeader*>(part + lay.header), lay.cap_slots);
   return hipGetLastError();
 }

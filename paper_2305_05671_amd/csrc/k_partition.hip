@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
     const uint64_t* __restrict__ bound, const uint64_t* __restrict__ knots, const uint32_t* __restrict__ cells,
     const uint8_t* __restrict__ recs, uint64_t n, uint32_t rw_rt, uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps,
     const uint32_t* __restrict__ rstart, PartHeader* __restrict__ ph, uint2* __restrict__ spill_meta,
-    uint4* __restrict__ slots, uint64_t cap_slots, PassFilter f, uint32_t vk) {
+    uint4* __restrict__ slots, uint64_t cap_slots, PassFilter f, uint32_t vk, uint32_t cstride) {
   const uint32_t RW = RW_T ? (uint32_t)RW_T : rw_rt;  // record dwords
   const uint32_t SC = slot_bytes_for(RW * 4) / 16;     // 16-byte chunks per slot
   constexpr uint32_t RV = RW_T ? (kPartTile * RW_T / 4 + kPartThreads - 1) / kPartThreads : 8;
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
       keep = keep && b >= f.lo && b < f.hi;
       b -= f.lo;
     }
-    if (keep) s = atomicAdd(&counts[b], 1u);
+    if (keep) s = atomicAdd(&counts[(uint64_t)b * cstride], 1u);
     // 3. the previous tile's slots, while the atomics are in flight
     if (have_prev) write_tile(tprev, buf(cur ^ 1), dst[cur ^ 1]);
     // 4. this tile's slots.  Overflowing records take spill positions from one
@@ -238,15 +238,15 @@ static void launch_partition_root(uint32_t grid, size_t lds, hipStream_t st, uin
                                   const uint64_t* knots, const uint32_t* cells, const uint8_t* recs, uint64_t n,
                                   uint32_t* counts,
                                   const uint32_t* caps, const uint32_t* rstart, PartHeader* ph, uint2* meta,
-                                  uint4* slots, uint64_t cap_slots, PassFilter f, uint32_t vk) {
+                                  uint4* slots, uint64_t cap_slots, PassFilter f, uint32_t vk, uint32_t cstride) {
   if (RW == 25)
     partition_kernel<25, ROOT, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, knots, cells, recs, n, RW,
                                                                         counts, caps, rstart, ph, meta, slots,
-                                                                        cap_slots, f, vk);
+                                                                        cap_slots, f, vk, cstride);
   else
     partition_kernel<0, ROOT, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, knots, cells, recs, n, RW,
                                                                        counts, caps, rstart, ph, meta, slots,
-                                                                       cap_slots, f, vk);
+                                                                       cap_slots, f, vk, cstride);
 }
 
 hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const MlpState* ms, const uint8_t* recs,
@@ -260,7 +260,8 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const Ml
   // tiles to overlap (small jobs of a batch run beside others)
   uint32_t grid = (uint32_t)(ntiles < 2048 ? ntiles : 2048);
   if (ntiles < 8192) grid = (uint32_t)((ntiles + 3) / 4);
-  auto* counts = reinterpret_cast<uint32_t*>(part + lay.counts);
+  auto* counts = reinterpret_cast<uint32_t*>(part + lay.pcounts);  // the partition's slot counters
+  const uint32_t cstride = lay.cstride;
   auto* caps = reinterpret_cast<const uint32_t*>(part + lay.caps);
   auto* rstart = reinterpret_cast<const uint32_t*>(part + lay.rstart);
   auto* ph = reinterpret_cast<PartHeader*>(part + lay.header);
@@ -269,21 +270,21 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const Ml
   const PassFilter f = filter ? *filter : PassFilter{0, 0, 0};
   if (filter) {
     launch_partition_root<0, true>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, nullptr, nullptr, recs, n,
-                                   counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk);
+                                   counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk, cstride);
     if (ms) {
       launch_partition_root<1, true>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, nullptr, ms->cells, recs,
-                                     n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk);
+                                     n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk, cstride);
       launch_partition_root<2, true>(grid, lds, st, RW, hdr, ms->leaves, nullptr, ms->bound, ms->knots, nullptr, recs,
-                                     n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk);
+                                     n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk, cstride);
     }
   } else {
     launch_partition_root<0, false>(grid, lds, st, RW, hdr, leaves, nullptr, nullptr, nullptr, nullptr, recs, n,
-                                    counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk);
+                                    counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk, cstride);
     if (ms) {
       launch_partition_root<1, false>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, nullptr, ms->cells, recs,
-                                      n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk);
+                                      n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk, cstride);
       launch_partition_root<2, false>(grid, lds, st, RW, hdr, ms->leaves, nullptr, ms->bound, ms->knots, nullptr,
-                                      recs, n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk);
+                                      recs, n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk, cstride);
     }
   }
   return hipGetLastError();
@@ -381,7 +382,7 @@ __global__ __launch_bounds__(kExThreads) void exact_regions_kernel(const uint32_
                                                                    uint32_t lo, uint32_t nb, uint64_t total,
                                                                    uint32_t* __restrict__ caps,
                                                                    uint32_t* __restrict__ rstart,
-                                                                   uint32_t* __restrict__ counts,
+                                                                   uint32_t* __restrict__ counts, uint32_t cstride,
                                                                    PartHeader* __restrict__ ph) {
   __shared__ uint64_t sh[kExThreads / 64 + 1];
   uint64_t carry = 0;
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(kExThreads) void exact_regions_kernel(const uint32_
       if (j < nb) {
         caps[j] = c[i];
         rstart[j] = (uint32_t)run;
-        counts[j] = 0;
+        counts[(uint64_t)j * cstride] = 0;
       }
       run += c[i];
     }
@@ -426,7 +427,7 @@ hipError_t launch_exact_regions(const uint32_t* counts_all, uint32_t lo, uint32_
   exact_regions_kernel<<<1, kExThreads, 0, st>>>(counts_all, lo, nb, total,
                                                  reinterpret_cast<uint32_t*>(part + lay.caps),
                                                  reinterpret_cast<uint32_t*>(part + lay.rstart),
-                                                 reinterpret_cast<uint32_t*>(part + lay.counts),
+                                                 reinterpret_cast<uint32_t*>(part + lay.pcounts), lay.cstride,
                                                  reinterpret_cast<PartHeader*>(part + lay.header));
   return hipGetLastError();
 }
@@ -443,7 +444,10 @@ constexpr uint32_t kScanThreads = 1024;
 constexpr uint32_t kScanWaves = kScanThreads / 64;
 constexpr uint32_t kScanSteps = 4;  // steps of 256 buckets whose loads are in flight together
 
+// counts: the partition's slot counters, cstride apart; with cstride > 1 the
+// dense counts the bucket sorts read go to dense.
 __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_t* __restrict__ counts,
+                                                                   uint32_t cstride, uint32_t* __restrict__ dense,
                                                                    const uint32_t* __restrict__ caps, uint32_t B,
                                                                    uint64_t* __restrict__ offsets,
                                                                    uint32_t* __restrict__ spill_off,
@@ -465,6 +469,15 @@ __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_
       for (uint32_t q = 0; q < 4; ++q) v[q] = j + q < s1 ? src[j + q] : 0u;
     }
   };
+  // counts of buckets j .. j+3 (zero past the segment), wherever the counters sit
+  auto loadc = [&](uint32_t j, uint32_t v[4]) {
+    if (cstride == 1) {
+      load4(counts, j, v);
+    } else {
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) v[q] = j + q < s1 ? counts[(uint64_t)(j + q) * cstride] : 0u;
+    }
+  };
   auto over = [](uint32_t c, uint32_t k) { return c > k ? c - k : 0u; };
   uint64_t sc = 0;
   uint32_t ss = 0, m = 0, mr = 0, br = 0;
@@ -472,7 +485,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_
     uint32_t c[kScanSteps][4], k[kScanSteps][4];
 #pragma unroll
     for (uint32_t u = 0; u < kScanSteps; ++u) {
-      load4(counts, jb + 256 * u + 4 * l, c[u]);
+      loadc(jb + 256 * u + 4 * l, c[u]);
       load4(caps, jb + 256 * u + 4 * l, k[u]);
     }
 #pragma unroll
@@ -532,7 +545,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_
     uint32_t c[kScanSteps][4], k[kScanSteps][4];
 #pragma unroll
     for (uint32_t u = 0; u < kScanSteps; ++u) {
-      load4(counts, jb + 256 * u + 4 * l, c[u]);
+      loadc(jb + 256 * u + 4 * l, c[u]);
       load4(caps, jb + 256 * u + 4 * l, k[u]);
     }
 #pragma unroll
@@ -555,10 +568,14 @@ __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_
       }
       if (j + 4 <= s1) {
         *reinterpret_cast<uint4*>(spill_off + j) = make_uint4(so[0], so[1], so[2], so[3]);
+        if (cstride > 1) *reinterpret_cast<uint4*>(dense + j) = make_uint4(c[u][0], c[u][1], c[u][2], c[u][3]);
       } else {
 #pragma unroll
         for (uint32_t q = 0; q < 4; ++q)
-          if (j + q < s1) spill_off[j + q] = so[q];
+          if (j + q < s1) {
+            spill_off[j + q] = so[q];
+            if (cstride > 1) dense[j + q] = c[u][q];
+          }
       }
       rc += shfl_u64(xc, 63);  // the step's sums
       rs += __shfl(xs, 63);
@@ -570,7 +587,8 @@ __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_
 hipError_t launch_scan_counts(uint8_t* part, const PartLayout& lay, uint32_t B, uint64_t* offsets,
                               hipStream_t st) {
   scan_counts_kernel<<<1, kScanThreads, 0, st>>>(
-      reinterpret_cast<const uint32_t*>(part + lay.counts), reinterpret_cast<const uint32_t*>(part + lay.caps), B,
+      reinterpret_cast<const uint32_t*>(part + lay.pcounts), lay.cstride, reinterpret_cast<uint32_t*>(part + lay.counts),
+      reinterpret_cast<const uint32_t*>(part + lay.caps), B,
       offsets, reinterpret_cast<uint32_t*>(part + lay.spill_off), reinterpret_cast<uint32_t*>(part + lay.mid_list),
       reinterpret_cast<uint32_t*>(part + lay.big_list), reinterpret_cast<PartHeader*>(part + lay.header));
   return hipGetLastError();
