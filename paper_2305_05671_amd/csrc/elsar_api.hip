@@ -419,13 +419,8 @@ elsar_status elsar_sort_workspace_size(const elsar_fit_params* p, uint64_t n, si
 namespace {
 
 // One whole sort on device-resident records; q has its defaults filled in.
-// A model fitted ahead of the job (batch): where it lives.
-struct Prefit {
-  uint8_t* base;  // model_dev_bytes(shape, RMI) bytes, placed as place_model does
-};
-
 elsar_status sort_job(const void* d_in, uint64_t n, void* d_out, const elsar_fit_params& q, void* d_ws,
-                      size_t ws_bytes, hipStream_t stream, bool timed, const Prefit* pre = nullptr) {
+                      size_t ws_bytes, hipStream_t stream, bool timed) {
   Shape sh = resolve(q, n);
   SortLayout sl = sort_layout(q, sh, n);
   if (ws_bytes < sl.bytes) return ELSAR_E_NO_MEMORY;
@@ -441,16 +436,11 @@ elsar_status sort_job(const void* d_in, uint64_t n, void* d_out, const elsar_fit
   m.Lm = sh.Lm;
   m.S = sh.S;
   m.dev = nullptr;
-  place_model(&m, pre ? pre->base : w + sl.model);
+  place_model(&m, w + sl.model);
   uint64_t* offsets = reinterpret_cast<uint64_t*>(w + sl.offsets);
   PhaseMarks pm = timed ? begin_marks() : PhaseMarks{};
   mark(pm, 0, stream);
-  elsar_status s = ELSAR_OK;
-  if (pre) {
-    m.n = n;  // fitted already, by the batch's fit kernel
-  } else {
-    s = do_fit(&m, d_in, n, w + sl.fit, fit_ws_bytes(sh.S), stream);
-  }
+  elsar_status s = do_fit(&m, d_in, n, w + sl.fit, fit_ws_bytes(sh.S), stream);
   if (s != ELSAR_OK) return s;
   s = do_partition(&m, d_in, n, w + sl.part, sl.lay.bytes, offsets, stream, &pm);
   if (s != ELSAR_OK) return s;
@@ -484,16 +474,36 @@ elsar_fit_params job_params(const elsar_fit_params& p, uint64_t n, uint32_t j) {
   return with_defaults(q);
 }
 
+// A window: jobs whose sizes differ by at most 2x and whose partition buffers
+// fit the window area together, sorted by one launch per phase.
+struct BatchWindow {
+  std::vector<uint32_t> jobs;  // job indices, largest first
+  uint64_t nmax = 0;           // records of its largest job
+  uint32_t Bmax = 0;           // buckets of its job with the most
+  bool prefit_only = true;     // every model comes from the batched fit kernel
+  size_t desc = 0;             // workspace offset of its WinJob array
+};
+
 struct BatchLayout {
   std::vector<TinyJob> tiny;
-  std::vector<uint32_t> prefit;       // jobs whose model the batch fit kernel fits
-  std::vector<size_t> prefit_model;   // workspace offset of each such job's model
-  std::vector<int32_t> prefit_of;     // per job: index into prefit, or -1
-  size_t fit_desc = 0;
-  std::vector<std::vector<uint32_t>> lanes;  // job indices per lane, largest first
-  size_t tiny_desc = 0, tiny_stage = 0, bytes = 0;
-  std::vector<size_t> lane_off, lane_bytes;
+  std::vector<uint32_t> prefit;                  // jobs whose model the batch fit kernel fits
+  std::vector<size_t> model;                     // per job above kSmallCap: workspace offset of its model
+  std::vector<std::vector<uint32_t>> fit_lanes;  // the other jobs, fitted one by one, per lane
+  std::vector<size_t> fit_off, fit_bytes;        // per lane: its fit scratch
+  std::vector<BatchWindow> windows;              // smallest jobs first
+  size_t fit_desc = 0, tiny_desc = 0, tiny_stage = 0, win_desc = 0, area = 0, area_bytes = 0, bytes = 0;
 };
+
+// Records per window, unless one job alone is larger: about the 100M-record
+// sort's working set (a window of this many records needs about 30 GB of
+// partition buffers), large enough that every phase kernel fills the GPU.
+constexpr uint64_t kWindowRecords = 64ull << 20;
+
+// Window-area bytes of one job: its B + 1 output offsets, then its partition buffer.
+size_t window_job_bytes(const elsar_fit_params& q, const Shape& sh, uint64_t n) {
+  return align_up(((size_t)sh.B + 1) * 8) +
+         align_up(part_layout(n, sh.B, q.record_bytes, q.region_pct, q.key_bytes).bytes);
+}
 
 elsar_status batch_layout(const elsar_job* jobs, uint32_t njobs, const elsar_fit_params& p, BatchLayout* bl) {
   const uint32_t RW = p.record_bytes / 4;
@@ -513,74 +523,124 @@ elsar_status batch_layout(const elsar_job* jobs, uint32_t njobs, const elsar_fit
       if (J.d_in == J.d_out) stage_dw += (J.n * RW + 3) & ~3ull;
       bl->tiny.push_back(t);
     } else {
+      const elsar_fit_params q = job_params(p, J.n, j);
+      if (part_layout(J.n, resolve(q, J.n).B, q.record_bytes, q.region_pct, q.key_bytes).total_slots >= (1ull << 32))
+        return ELSAR_E_UNSUPPORTED;  // slot indices are 32-bit
       big.push_back(j);
     }
   }
-  // jobs whose sample fits LDS get their model from one batched kernel
-  bl->prefit_of.assign(njobs, -1);
-  if (p.kind == ELSAR_MODEL_RMI)
-    for (uint32_t j : big) {
-      const elsar_fit_params q = job_params(p, jobs[j].n, j);
-      if (resolve(q, jobs[j].n).S <= kBatchFitMaxS) {
-        bl->prefit_of[j] = (int32_t)bl->prefit.size();
-        bl->prefit.push_back(j);
-      }
-    }
-  // longest job first to the least loaded lane
   std::stable_sort(big.begin(), big.end(), [&](uint32_t a, uint32_t b) { return jobs[a].n > jobs[b].n; });
-  const uint32_t nl = std::min<uint32_t>(kBatchLanes, (uint32_t)big.size());
-  bl->lanes.assign(nl, {});
-  std::vector<uint64_t> load(nl, 0);
-  bl->lane_bytes.assign(nl, 0);
+  // models: one batched kernel for the linear root of jobs whose sample fits
+  // LDS; the others one by one, longest sample first to the least loaded lane
+  std::vector<uint8_t> is_prefit(njobs, 0);
+  std::vector<uint32_t> lone;
   for (uint32_t j : big) {
-    const uint32_t l = (uint32_t)(std::min_element(load.begin(), load.end()) - load.begin());
-    bl->lanes[l].push_back(j);
-    load[l] += jobs[j].n;
     const elsar_fit_params q = job_params(p, jobs[j].n, j);
-    const size_t need = sort_layout(q, resolve(q, jobs[j].n), jobs[j].n).bytes;
-    bl->lane_bytes[l] = std::max(bl->lane_bytes[l], need);
+    if (p.kind == ELSAR_MODEL_RMI && resolve(q, jobs[j].n).S <= kBatchFitMaxS) {
+      bl->prefit.push_back(j);
+      is_prefit[j] = 1;
+    } else {
+      lone.push_back(j);
+    }
   }
+  const uint32_t nl = std::min<uint32_t>(kBatchLanes, (uint32_t)lone.size());
+  bl->fit_lanes.assign(nl, {});
+  bl->fit_bytes.assign(nl, 0);
+  std::vector<uint64_t> load(nl, 0);
+  for (uint32_t j : lone) {
+    const uint32_t l = (uint32_t)(std::min_element(load.begin(), load.end()) - load.begin());
+    const uint64_t S = resolve(job_params(p, jobs[j].n, j), jobs[j].n).S;
+    bl->fit_lanes[l].push_back(j);
+    load[l] += S;
+    bl->fit_bytes[l] = std::max(bl->fit_bytes[l], fit_ws_bytes(S));
+  }
+  // windows over the jobs in decreasing size: a window takes jobs while they
+  // are at least half its largest and fit its record budget
+  for (size_t i = 0; i < big.size();) {
+    BatchWindow w;
+    w.nmax = jobs[big[i]].n;
+    const uint64_t budget = std::max<uint64_t>(kWindowRecords, w.nmax);
+    uint64_t sum = 0;
+    while (i < big.size()) {
+      const uint32_t j = big[i];
+      const uint64_t n = jobs[j].n;
+      const uint32_t B = resolve(job_params(p, n, j), n).B;
+      const uint64_t most = std::max<uint64_t>(std::max(B, w.Bmax), 2048);  // largest per-job grid
+      if (!w.jobs.empty() && (2 * n < w.nmax || sum + n > budget || (w.jobs.size() + 1) * most > 0x7FFFFFFFull))
+        break;
+      w.jobs.push_back(j);
+      w.Bmax = std::max(w.Bmax, B);
+      w.prefit_only = w.prefit_only && is_prefit[j];
+      sum += n;
+      ++i;
+    }
+    bl->windows.push_back(std::move(w));
+  }
+  std::reverse(bl->windows.begin(), bl->windows.end());
   size_t off = 0;
   bl->tiny_desc = off;
   off += align_up(bl->tiny.size() * sizeof(TinyJob));
   bl->fit_desc = off;
   off += align_up(bl->prefit.size() * sizeof(FitJob));
-  for (uint32_t j : bl->prefit) {
+  bl->model.assign(njobs, 0);
+  for (uint32_t j : big) {
     const elsar_fit_params q = job_params(p, jobs[j].n, j);
-    const Shape sh = resolve(q, jobs[j].n);
-    bl->prefit_model.push_back(off);
-    off += align_up(model_dev_bytes(sh, ELSAR_MODEL_RMI));
+    bl->model[j] = off;
+    off += align_up(model_dev_bytes(resolve(q, jobs[j].n), q.kind));
   }
   bl->tiny_stage = off;
   off += align_up(stage_dw * 4);
-  bl->lane_off.assign(nl, 0);
+  bl->fit_off.assign(nl, 0);
   for (uint32_t l = 0; l < nl; ++l) {
-    bl->lane_off[l] = off;
-    off += align_up(bl->lane_bytes[l]);
+    bl->fit_off[l] = off;
+    off += align_up(bl->fit_bytes[l]);
   }
+  bl->win_desc = off;  // every window's WinJob array, one after another
+  off += align_up(big.size() * sizeof(WinJob));
+  size_t k = 0;
+  for (BatchWindow& w : bl->windows) {
+    w.desc = bl->win_desc + k * sizeof(WinJob);
+    k += w.jobs.size();
+    size_t a = 0;
+    for (uint32_t j : w.jobs) {
+      const elsar_fit_params q = job_params(p, jobs[j].n, j);
+      a += window_job_bytes(q, resolve(q, jobs[j].n), jobs[j].n);
+    }
+    bl->area_bytes = std::max(bl->area_bytes, a);
+  }
+  bl->area = off;
+  off += bl->area_bytes;
   bl->bytes = std::max<size_t>(off, 256);
   return ELSAR_OK;
+}
+
+// A job's model, placed where the layout keeps it.
+elsar_model job_model(const elsar_job* jobs, const elsar_fit_params& p, const BatchLayout& bl, uint8_t* w,
+                      uint32_t j) {
+  const elsar_fit_params q = job_params(p, jobs[j].n, j);
+  const Shape sh = resolve(q, jobs[j].n);
+  elsar_model m{};
+  m.p = q;
+  m.B = sh.B;
+  m.L = sh.L;
+  m.Lm = sh.Lm;
+  m.S = sh.S;
+  place_model(&m, w + bl.model[j]);
+  return m;
 }
 
 std::vector<FitJob> fit_descriptors(const elsar_job* jobs, const elsar_fit_params& p, const BatchLayout& bl,
                                     uint8_t* w) {
   std::vector<FitJob> out;
-  for (size_t k = 0; k < bl.prefit.size(); ++k) {
-    const uint32_t j = bl.prefit[k];
-    const elsar_fit_params q = job_params(p, jobs[j].n, j);
-    const Shape sh = resolve(q, jobs[j].n);
-    elsar_model m{};
-    m.p = q;
-    m.B = sh.B;
-    m.L = sh.L;
-    place_model(&m, w + bl.prefit_model[k]);
+  for (uint32_t j : bl.prefit) {
+    const elsar_model m = job_model(jobs, p, bl, w, j);
     FitJob f{};
     f.recs = static_cast<const uint8_t*>(jobs[j].d_in);
     f.n = jobs[j].n;
-    f.S = sh.S;
-    f.seed = q.seed;
-    f.L = sh.L;
-    f.B = sh.B;
+    f.S = m.S;
+    f.seed = m.p.seed;
+    f.L = m.L;
+    f.B = m.B;
     f.hdr = m.hdr;
     f.leaves = m.leaves;
     f.hist = m.hist;
@@ -589,10 +649,45 @@ std::vector<FitJob> fit_descriptors(const elsar_job* jobs, const elsar_fit_param
   return out;
 }
 
+// The WinJob arrays of every window, in window order.
+std::vector<WinJob> window_descriptors(const elsar_job* jobs, const elsar_fit_params& p, const BatchLayout& bl,
+                                       uint8_t* w) {
+  std::vector<WinJob> out;
+  for (const BatchWindow& win : bl.windows) {
+    size_t a = bl.area;
+    for (uint32_t j : win.jobs) {
+      const elsar_model m = job_model(jobs, p, bl, w, j);
+      WinJob J{};
+      J.recs = static_cast<const uint8_t*>(jobs[j].d_in);
+      J.out = static_cast<uint8_t*>(jobs[j].d_out);
+      J.n = jobs[j].n;
+      J.S = m.S;
+      J.hdr = m.hdr;
+      J.leaves = m.leaves;
+      J.hist = m.hist;
+      if (m.has_mlp) {
+        J.mlp = m.ms.M;
+        J.eq_leaves = m.ms.leaves;
+        J.bound = m.ms.bound;
+        J.knots = m.ms.knots;
+        J.cells = m.ms.cells;
+      }
+      J.offsets = reinterpret_cast<uint64_t*>(w + a);
+      J.lay = part_layout(J.n, m.B, m.p.record_bytes, m.p.region_pct, m.p.key_bytes);
+      J.part = w + a + align_up(((size_t)m.B + 1) * 8);
+      J.B = m.B;
+      a += window_job_bytes(m.p, resolve(m.p, J.n), J.n);
+      out.push_back(J);
+    }
+  }
+  return out;
+}
+
 struct BatchPlan {
   std::vector<uint8_t> key;
-  std::vector<FitJob> fit;    // source of the per-launch descriptor uploads
+  std::vector<FitJob> fit;    // sources of the per-launch descriptor uploads
   std::vector<TinyJob> tiny;
+  std::vector<WinJob> win;    // every window's jobs, in window order
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -614,30 +709,61 @@ std::vector<uint8_t> plan_key(const elsar_job* jobs, uint32_t njobs, const elsar
   return k;
 }
 
-// Every kernel of the batch on `cap` (small jobs) and on lane streams forked
-// from it and joined back.
+// One window: each phase one launch over all its jobs.
+elsar_status enqueue_window(const BatchWindow& win, const elsar_fit_params& p, uint8_t* w, hipStream_t st) {
+  const WinJob* d = reinterpret_cast<const WinJob*>(w + win.desc);
+  const uint32_t nj = (uint32_t)win.jobs.size();
+  const WinGrids g = window_grids(win.nmax, win.Bmax);
+  const elsar_fit_params q = with_defaults(p);
+  HIP_TRY(launch_capacities_win(d, nj, q.region_pct, st));
+  HIP_TRY(launch_partition_win(d, nj, g.part, q.record_bytes, wants_mlp(q.kind), st));
+  HIP_TRY(launch_scan_counts_win(d, nj, st));
+  HIP_TRY(launch_spill_fixup_win(d, nj, g.fixup, st));
+  HIP_TRY(launch_bucket_sort_small_win(d, nj, g.small, q.record_bytes, sort_bytes(q), st));
+  HIP_TRY(launch_bucket_sort_large_win(d, nj, g, q.record_bytes, sort_bytes(q), st));
+  return ELSAR_OK;
+}
+
+// Every kernel of the batch: the small jobs, the batched fit and the windows
+// on `cap`; the models fitted one by one on lane streams forked from it, beside
+// the windows whose models the batched fit provides, and joined back before the
+// first window that needs them.
 elsar_status enqueue_batch(const elsar_job* jobs, const elsar_fit_params& p, const BatchLayout& bl, uint8_t* w,
                            hipStream_t cap, hipStream_t* lanes, hipEvent_t fork, hipEvent_t* done) {
+  const size_t nl = bl.fit_lanes.size();
+  if (nl) {
+    HIP_TRY(hipEventRecord(fork, cap));
+    for (size_t l = 0; l < nl; ++l) {
+      HIP_TRY(hipStreamWaitEvent(lanes[l], fork, 0));
+      for (uint32_t j : bl.fit_lanes[l]) {
+        elsar_model m = job_model(jobs, p, bl, w, j);
+        elsar_status s = do_fit(&m, jobs[j].d_in, jobs[j].n, w + bl.fit_off[l], bl.fit_bytes[l], lanes[l]);
+        if (s != ELSAR_OK) return s;
+      }
+      HIP_TRY(hipEventRecord(done[l], lanes[l]));
+    }
+  }
   if (!bl.tiny.empty())
     HIP_TRY(launch_tiny_jobs(reinterpret_cast<const TinyJob*>(w + bl.tiny_desc), (uint32_t)bl.tiny.size(),
                              p.record_bytes, p.key_bytes, reinterpret_cast<uint32_t*>(w + bl.tiny_stage), cap));
   if (!bl.prefit.empty())
     HIP_TRY(launch_batch_fit(reinterpret_cast<const FitJob*>(w + bl.fit_desc), (uint32_t)bl.prefit.size(),
                              p.record_bytes, cap));
-  HIP_TRY(hipEventRecord(fork, cap));
-  for (size_t l = 0; l < bl.lanes.size(); ++l) {
-    HIP_TRY(hipStreamWaitEvent(lanes[l], fork, 0));
-    for (uint32_t j : bl.lanes[l]) {
-      const elsar_fit_params q = job_params(p, jobs[j].n, j);
-      Prefit pre{bl.prefit_of[j] >= 0 ? w + bl.prefit_model[bl.prefit_of[j]] : nullptr};
-      elsar_status s = sort_job(jobs[j].d_in, jobs[j].n, jobs[j].d_out, q, w + bl.lane_off[l], bl.lane_bytes[l],
-                                lanes[l], false, pre.base ? &pre : nullptr);
+  bool joined = nl == 0;
+  auto join = [&]() -> elsar_status {
+    for (size_t l = 0; l < nl; ++l) HIP_TRY(hipStreamWaitEvent(cap, done[l], 0));
+    joined = true;
+    return ELSAR_OK;
+  };
+  for (const BatchWindow& win : bl.windows) {
+    if (!joined && !win.prefit_only) {
+      elsar_status s = join();
       if (s != ELSAR_OK) return s;
     }
-    HIP_TRY(hipEventRecord(done[l], lanes[l]));
-    HIP_TRY(hipStreamWaitEvent(cap, done[l], 0));
+    elsar_status s = enqueue_window(win, p, w, cap);
+    if (s != ELSAR_OK) return s;
   }
-  return ELSAR_OK;
+  return joined ? ELSAR_OK : join();
 }
 
 elsar_status build_plan(const elsar_job* jobs, const elsar_fit_params& p, const BatchLayout& bl, uint8_t* w,
@@ -784,6 +910,7 @@ elsar_status elsar_sort_batch(const elsar_job* h_jobs, uint32_t njobs, const els
     plan.key = std::move(key);
     plan.tiny = bl.tiny;
     plan.fit = fit_descriptors(h_jobs, *p, bl, w);
+    plan.win = window_descriptors(h_jobs, *p, bl, w);
     s = build_plan(h_jobs, *p, bl, w, &plan);
     if (s != ELSAR_OK) return s;
     if (g_plans.size() >= kMaxPlans) {  // the oldest plan may still run: wait before freeing it
@@ -806,6 +933,9 @@ elsar_status elsar_sort_batch(const elsar_job* h_jobs, uint32_t njobs, const els
                            hipMemcpyHostToDevice, stream));
   if (!it->fit.empty())
     HIP_TRY(hipMemcpyAsync(w + bl.fit_desc, it->fit.data(), it->fit.size() * sizeof(FitJob),
+                           hipMemcpyHostToDevice, stream));
+  if (!it->win.empty())
+    HIP_TRY(hipMemcpyAsync(w + bl.win_desc, it->win.data(), it->win.size() * sizeof(WinJob),
                            hipMemcpyHostToDevice, stream));
   HIP_TRY(hipGraphLaunch(it->exec, stream));
   return ELSAR_OK;

@@ -438,4 +438,45 @@ hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32
                                     uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out, hipStream_t st,
                                     uint32_t vk = 0);
 
+// ---------------------------------------------------------- batch windows --
+// A window of a batch: jobs whose sizes differ by at most 2x, whose partition
+// buffers fit the window's workspace together, sorted by one launch per phase
+// (capacities, partition, scan, spill fix-up, bucket sorts) instead of one
+// launch per phase and job.  Every job of a window gets the same number G of
+// blocks in a phase's grid: block b of the launch works for job b / G as its
+// block b % G of G, so the mapping costs one division and no table.
+struct WinJob {
+  const uint8_t* recs;      // the job's records (device)
+  uint8_t* out;             // its output, may equal recs
+  uint64_t n, S;
+  const ModelHeader* hdr;   // the job's fitted model
+  const Leaf* leaves;       // RMI leaves
+  const uint32_t* hist;     // sample keys per bucket under the root in use
+  const MlpBlock* mlp;      // equi-depth roots only (else null): the network,
+  const Leaf* eq_leaves;    // the equi-depth leaves and their routing tables
+  const uint64_t* bound;
+  const uint64_t* knots;
+  const uint32_t* cells;
+  uint8_t* part;            // partition buffer laid out as lay
+  uint64_t* offsets;        // B + 1 output offsets
+  PartLayout lay;
+  uint32_t B, pad_;
+};
+struct WinGrids {           // blocks per job of each phase's launch
+  uint32_t part, fixup, small, mid, split, seg, gather;
+};
+// The grids of a window whose largest job has nmax records and B buckets at most.
+WinGrids window_grids(uint64_t nmax, uint32_t Bmax);
+uint32_t partition_grid(uint64_t n);    // blocks of the partition of n records
+uint32_t spill_fixup_grid(uint64_t n);  // blocks of the spill fix-up of n records
+hipError_t launch_capacities_win(const WinJob* jobs, uint32_t njobs, uint32_t region_pct, hipStream_t st);
+hipError_t launch_partition_win(const WinJob* jobs, uint32_t njobs, uint32_t G, uint32_t rec_bytes, bool equi_depth,
+                                hipStream_t st);
+hipError_t launch_scan_counts_win(const WinJob* jobs, uint32_t njobs, hipStream_t st);
+hipError_t launch_spill_fixup_win(const WinJob* jobs, uint32_t njobs, uint32_t G, hipStream_t st);
+hipError_t launch_bucket_sort_small_win(const WinJob* jobs, uint32_t njobs, uint32_t G, uint32_t rec_bytes,
+                                        uint32_t key_bytes, hipStream_t st);
+hipError_t launch_bucket_sort_large_win(const WinJob* jobs, uint32_t njobs, const WinGrids& g, uint32_t rec_bytes,
+                                        uint32_t key_bytes, hipStream_t st);
+
 }  // namespace elsar

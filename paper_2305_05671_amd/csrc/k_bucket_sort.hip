@@ -355,12 +355,13 @@ __device__ __forceinline__ uint32_t small_sort_core(uint32_t n, uint32_t vary, u
 }
 
 template <uint32_t RW>  // record dwords
-__global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
+__device__ __forceinline__ void bucket_sort_small_body(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map, const uint4* __restrict__ slots,
     uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t K, uint32_t* __restrict__ out, uint32_t B,
-    uint32_t* __restrict__ seg_n, uint32_t vk) {
-  if (seg_n && blockIdx.x == 0 && threadIdx.x < 4) seg_n[threadIdx.x] = 0;  // the big-bucket split's counters
+    uint32_t* __restrict__ seg_n, uint32_t vk, uint32_t bid,
+    uint32_t nblk) {
+  if (seg_n && bid == 0 && threadIdx.x < 4) seg_n[threadIdx.x] = 0;  // the big-bucket split's counters
   constexpr uint32_t SC = slot_bytes_for(RW * 4) / 16;  // 16-byte chunks per slot
   constexpr uint32_t LC = (RW + 1 + 3) / 4;             // chunks holding the index or record bytes
   constexpr uint32_t AR = kSmCap / kSmThreads;          // entries per thread
@@ -373,7 +374,7 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
   __shared__ uint32_t tot[4];
   static_assert((1u << kSmBits) == kSmWaves * 256, "bins double as the LSD counters");
   const uint32_t tid = threadIdx.x;
-  const uint32_t j = blockIdx.x;
+  const uint32_t j = bid;
   if (j >= B) return;
   BucketRef br;
   br.n = counts[j];
@@ -496,6 +497,15 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
   }
 }
 
+template <uint32_t RW>
+__global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
+    const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map, const uint4* __restrict__ slots,
+    uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t K, uint32_t* __restrict__ out, uint32_t B,
+    uint32_t* __restrict__ seg_n, uint32_t vk) {
+  bucket_sort_small_body<RW>(counts, caps, rstart, spill_off, spill_map, slots, cap_slots, offsets, K, out, B, seg_n, vk, blockIdx.x, gridDim.x);
+}
+
 // ------------------------------------------- buckets of up to 6144 records --
 // The small-bucket algorithm at a larger scale: one counting pass on a
 // 13-bit digit of the base-95 code over the bucket's code range, then the
@@ -503,13 +513,14 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
 constexpr uint32_t kMidBits = 13;
 
 template <uint32_t CAP, uint32_t THREADS>
-__global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
+__device__ __forceinline__ void bucket_sort_lds_body(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
     const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
     uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
-    uint32_t B, uint32_t* __restrict__ seg_n, uint32_t vk) {
-  if (seg_n && blockIdx.x == 0 && threadIdx.x < 4) seg_n[threadIdx.x] = 0;  // the big-bucket split's counters
+    uint32_t B, uint32_t* __restrict__ seg_n, uint32_t vk, uint32_t bid,
+    uint32_t nblk) {
+  if (seg_n && bid == 0 && threadIdx.x < 4) seg_n[threadIdx.x] = 0;  // the big-bucket split's counters
   constexpr uint32_t WAVES = THREADS / 64;
   static_assert(CAP % THREADS == 0, "cap is whole rounds");
   __shared__ uint4 ent[CAP];
@@ -529,7 +540,7 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
   auto byte_of = [&](uint32_t e, uint32_t pb) -> uint32_t { return digit_of(ent[e], pb); };
   const uint32_t W = slot_bytes_for(RW * 4) / 4;  // slot stride in dwords
   const uint32_t nitems = list ? *list_n : B;
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+  for (uint32_t it = bid; it < nitems; it += nblk) {
     const uint32_t j = list ? list[it] : it;
     BucketRef br;
     br.n = counts[j];
@@ -623,6 +634,16 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
     }
     __syncthreads();
   }
+}
+
+template <uint32_t CAP, uint32_t THREADS>
+__global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
+    const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
+    const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
+    uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
+    uint32_t B, uint32_t* __restrict__ seg_n, uint32_t vk) {
+  bucket_sort_lds_body<CAP, THREADS>(counts, caps, rstart, spill_off, spill_map, slots, cap_slots, offsets, RW, K, out, list, list_n, B, seg_n, vk, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------ buckets above the LDS cap --
@@ -728,18 +749,19 @@ __device__ uint32_t* lsd_entries(uint32_t* cur, uint32_t* nxt, uint32_t n, uint3
   return cur;
 }
 
-__global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
+__device__ __forceinline__ void bucket_sort_global_body(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
     const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
     uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
-    uint32_t vk) {
+    uint32_t vk, uint32_t bid,
+    uint32_t nblk) {
   __shared__ LsdShared lsd;
   __shared__ uint4 sh_or[kBigWaves], sh_and[kBigWaves];
   __shared__ uint32_t chunk_slot[kBigTile];
   const uint32_t W = slot_bytes_for(RW * 4) / 4;  // slot stride in dwords
   const uint32_t nitems = *list_n;
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+  for (uint32_t it = bid; it < nitems; it += nblk) {
     const uint32_t j = list[it];
     BucketRef br;
     br.n = counts[j];
@@ -785,6 +807,15 @@ __global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
       __syncthreads();
     }
   }
+}
+
+__global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
+    const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
+    const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
+    uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
+    uint32_t vk) {
+  bucket_sort_global_body(counts, caps, rstart, spill_off, spill_map, slots, cap_slots, offsets, RW, K, out, list, list_n, vk, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------- buckets above the LDS caps: MSD split --
@@ -923,17 +954,18 @@ __device__ __forceinline__ void bucket_bufs(uint32_t* out, uint64_t out0, uint32
   *B = o_dw + 5ull * n;
 }
 
-__global__ __launch_bounds__(kMsdThreads) void msd_split_kernel(
+__device__ __forceinline__ void msd_split_body(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
     const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
     uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
     uint4* __restrict__ leaf, uint32_t* __restrict__ leaf_n, uint32_t leaf_cap, uint32_t* __restrict__ error,
-    uint32_t vk) {
+    uint32_t vk, uint32_t bid,
+    uint32_t nblk) {
   __shared__ MsdShared sh;
   const uint32_t W = slot_bytes_for(RW * 4) / 4;
   const uint32_t nitems = *list_n;
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+  for (uint32_t it = bid; it < nitems; it += nblk) {
     const uint32_t j = list[it];
     BucketRef br;
     br.n = counts[j];
@@ -992,13 +1024,24 @@ __global__ __launch_bounds__(kMsdThreads) void msd_split_kernel(
   }
 }
 
+__global__ __launch_bounds__(kMsdThreads) void msd_split_kernel(
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
+    const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
+    const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
+    uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
+    uint4* __restrict__ leaf, uint32_t* __restrict__ leaf_n, uint32_t leaf_cap, uint32_t* __restrict__ error,
+    uint32_t vk) {
+  msd_split_body(counts, caps, rstart, spill_off, spill_map, slots, cap_slots, offsets, RW, K, out, list, list_n, leaf, leaf_n, leaf_cap, error, vk, blockIdx.x, gridDim.x);
+}
+
 // One segment per block: the small-bucket sort on entries from the buffer;
 // the sorted slot numbers go to the bucket's reference list.
-__global__ __launch_bounds__(kSmThreads) void seg_sort_kernel(const uint32_t* __restrict__ counts,
+__device__ __forceinline__ void seg_sort_body(const uint32_t* __restrict__ counts,
                                                               const uint64_t* __restrict__ offsets, uint32_t RW,
                                                               uint32_t* __restrict__ out,
                                                               const uint4* __restrict__ segs,
-                                                              const uint32_t* __restrict__ segs_n, uint32_t segs_cap) {
+                                                              const uint32_t* __restrict__ segs_n, uint32_t segs_cap, uint32_t bid,
+    uint32_t nblk) {
   constexpr uint32_t AR = kSmCap / kSmThreads;
   __shared__ uint32_t cw[4][kSmCap];
   __shared__ uint16_t perm[2][kSmCap];
@@ -1009,7 +1052,7 @@ __global__ __launch_bounds__(kSmThreads) void seg_sort_kernel(const uint32_t* __
   __shared__ uint32_t tot[4];
   const uint32_t tid = threadIdx.x;
   const uint32_t nseg = *segs_n < segs_cap ? *segs_n : segs_cap;
-  for (uint32_t it = blockIdx.x; it < nseg; it += gridDim.x) {
+  for (uint32_t it = bid; it < nseg; it += nblk) {
     const uint4 sg = segs[it];
     const uint32_t nb = counts[sg.x], n = sg.z;
     uint32_t *A, *Bf;
@@ -1076,21 +1119,30 @@ __global__ __launch_bounds__(kSmThreads) void seg_sort_kernel(const uint32_t* __
   }
 }
 
+__global__ __launch_bounds__(kSmThreads) void seg_sort_kernel(const uint32_t* __restrict__ counts,
+                                                              const uint64_t* __restrict__ offsets, uint32_t RW,
+                                                              uint32_t* __restrict__ out,
+                                                              const uint4* __restrict__ segs,
+                                                              const uint32_t* __restrict__ segs_n, uint32_t segs_cap) {
+  seg_sort_body(counts, offsets, RW, out, segs, segs_n, segs_cap, blockIdx.x, gridDim.x);
+}
+
 // Each bucket's records in the order of its reference list: lane q moves
 // 16-byte chunk q % LC of record q / LC (one slot line per record).
 constexpr uint32_t kGatherChunk = 4096;
 
-__global__ __launch_bounds__(kMsdThreads) void big_gather_kernel(const uint32_t* __restrict__ counts,
+__device__ __forceinline__ void big_gather_body(const uint32_t* __restrict__ counts,
                                                                  const uint64_t* __restrict__ offsets, uint32_t RW,
                                                                  const uint4* __restrict__ slots,
                                                                  uint32_t* __restrict__ out,
                                                                  const uint32_t* __restrict__ list,
-                                                                 const uint32_t* __restrict__ list_n) {
+                                                                 const uint32_t* __restrict__ list_n, uint32_t bid,
+    uint32_t nblk) {
   __shared__ uint32_t chunk_slot[kGatherChunk];
   const uint32_t SC = slot_bytes_for(RW * 4) / 16;
   const uint32_t LC = (RW + 1 + 3) / 4;
   const uint32_t nitems = *list_n;
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+  for (uint32_t it = bid; it < nitems; it += nblk) {
     const uint32_t j = list[it], n = counts[j];
     uint32_t* o_dw = out + offsets[j] * RW;
     const uint32_t* refs = o_dw + (uint64_t)(RW - 1) * n;
@@ -1125,6 +1177,15 @@ __global__ __launch_bounds__(kMsdThreads) void big_gather_kernel(const uint32_t*
       __syncthreads();
     }
   }
+}
+
+__global__ __launch_bounds__(kMsdThreads) void big_gather_kernel(const uint32_t* __restrict__ counts,
+                                                                 const uint64_t* __restrict__ offsets, uint32_t RW,
+                                                                 const uint4* __restrict__ slots,
+                                                                 uint32_t* __restrict__ out,
+                                                                 const uint32_t* __restrict__ list,
+                                                                 const uint32_t* __restrict__ list_n) {
+  big_gather_body(counts, offsets, RW, slots, out, list, list_n, blockIdx.x, gridDim.x);
 }
 
 
@@ -1417,6 +1478,127 @@ hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32
                                                                    leaf_cap);
   big_gather_kernel<<<grid_for(n, kMidCap + 1, 512), kMsdThreads, 0, st>>>(
       a.counts, offsets, a.RW, reinterpret_cast<const uint4*>(a.slots), a.out, big_list, &a.ph->n_big);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- batch windows --
+// The bucket sorts of a window of a batch: G blocks per job, block b working
+// for job b / G as its block b % G of G.  Each kernel body is the one the
+// single-job launches above run.
+WinGrids window_grids(uint64_t nmax, uint32_t Bmax) {
+  WinGrids g;
+  g.part = partition_grid(nmax);
+  g.fixup = spill_fixup_grid(nmax);
+  g.small = Bmax;
+  g.mid = grid_for(nmax, kSmallCap + 1, 256);
+  g.split = grid_for(nmax, kMidCap + 1, 512);
+  g.seg = grid_for(nmax, 1024, 2048);
+  g.gather = grid_for(nmax, kMidCap + 1, 512);
+  return g;
+}
+
+struct WinRefs {  // a job's partition buffer as the bucket sorts read it
+  const uint32_t *counts, *caps, *rstart, *soff, *smap, *slots;
+  PartHeader* ph;
+};
+
+__device__ __forceinline__ WinRefs win_refs(const WinJob& J) {
+  uint8_t* p = J.part;
+  WinRefs r;
+  r.counts = reinterpret_cast<const uint32_t*>(p + J.lay.counts);
+  r.caps = reinterpret_cast<const uint32_t*>(p + J.lay.caps);
+  r.rstart = reinterpret_cast<const uint32_t*>(p + J.lay.rstart);
+  r.soff = reinterpret_cast<const uint32_t*>(p + J.lay.spill_off);
+  r.smap = reinterpret_cast<const uint32_t*>(p + J.lay.spill_map);
+  r.slots = reinterpret_cast<const uint32_t*>(p + J.lay.slots);
+  r.ph = reinterpret_cast<PartHeader*>(p + J.lay.header);
+  return r;
+}
+
+template <uint32_t RW>
+__global__ __launch_bounds__(kSmThreads) void bucket_sort_small_win_kernel(const WinJob* __restrict__ jobs,
+                                                                           uint32_t G, uint32_t K) {
+  const WinJob& J = jobs[blockIdx.x / G];
+  const WinRefs r = win_refs(J);
+  bucket_sort_small_body<RW>(r.counts, r.caps, r.rstart, r.soff, r.smap, reinterpret_cast<const uint4*>(r.slots),
+                             J.lay.cap_slots, J.offsets, K, reinterpret_cast<uint32_t*>(J.out), J.B, r.ph->seg_n, 0u,
+                             blockIdx.x % G, G);
+}
+
+// MID: the buckets of the mid list (kSmallCap < count <= kMidCap); otherwise
+// every bucket up to kSmallCap records (records other than 100 bytes).
+template <uint32_t CAP, uint32_t THREADS, bool MID>
+__global__ __launch_bounds__(THREADS) void bucket_sort_lds_win_kernel(const WinJob* __restrict__ jobs, uint32_t G,
+                                                                      uint32_t RW, uint32_t K) {
+  const WinJob& J = jobs[blockIdx.x / G];
+  const WinRefs r = win_refs(J);
+  bucket_sort_lds_body<CAP, THREADS>(r.counts, r.caps, r.rstart, r.soff, r.smap, r.slots, J.lay.cap_slots, J.offsets,
+                                     RW, K, reinterpret_cast<uint32_t*>(J.out),
+                                     MID ? reinterpret_cast<const uint32_t*>(J.part + J.lay.mid_list) : nullptr,
+                                     MID ? &r.ph->n_mid : nullptr, J.B, MID ? nullptr : r.ph->seg_n, 0u,
+                                     blockIdx.x % G, G);
+}
+
+__global__ __launch_bounds__(kBigThreads) void bucket_sort_global_win_kernel(const WinJob* __restrict__ jobs,
+                                                                             uint32_t G, uint32_t RW, uint32_t K) {
+  const WinJob& J = jobs[blockIdx.x / G];
+  const WinRefs r = win_refs(J);
+  bucket_sort_global_body(r.counts, r.caps, r.rstart, r.soff, r.smap, r.slots, J.lay.cap_slots, J.offsets, RW, K,
+                          reinterpret_cast<uint32_t*>(J.out), reinterpret_cast<const uint32_t*>(J.part + J.lay.big_list),
+                          &r.ph->n_big, 0u, blockIdx.x % G, G);
+}
+
+__global__ __launch_bounds__(kMsdThreads) void msd_split_win_kernel(const WinJob* __restrict__ jobs, uint32_t G,
+                                                                    uint32_t RW, uint32_t K) {
+  const WinJob& J = jobs[blockIdx.x / G];
+  const WinRefs r = win_refs(J);
+  msd_split_body(r.counts, r.caps, r.rstart, r.soff, r.smap, r.slots, J.lay.cap_slots, J.offsets, RW, K,
+                 reinterpret_cast<uint32_t*>(J.out), reinterpret_cast<const uint32_t*>(J.part + J.lay.big_list),
+                 &r.ph->n_big, reinterpret_cast<uint4*>(J.part + J.lay.seg_leaf), &r.ph->seg_n[0], J.lay.seg_leaf_cap,
+                 &r.ph->seg_n[1], 0u, blockIdx.x % G, G);
+}
+
+__global__ __launch_bounds__(kSmThreads) void seg_sort_win_kernel(const WinJob* __restrict__ jobs, uint32_t G,
+                                                                  uint32_t RW) {
+  const WinJob& J = jobs[blockIdx.x / G];
+  const WinRefs r = win_refs(J);
+  seg_sort_body(r.counts, J.offsets, RW, reinterpret_cast<uint32_t*>(J.out),
+                reinterpret_cast<const uint4*>(J.part + J.lay.seg_leaf), &r.ph->seg_n[0], J.lay.seg_leaf_cap,
+                blockIdx.x % G, G);
+}
+
+__global__ __launch_bounds__(kMsdThreads) void big_gather_win_kernel(const WinJob* __restrict__ jobs, uint32_t G,
+                                                                     uint32_t RW) {
+  const WinJob& J = jobs[blockIdx.x / G];
+  const WinRefs r = win_refs(J);
+  big_gather_body(r.counts, J.offsets, RW, reinterpret_cast<const uint4*>(r.slots), reinterpret_cast<uint32_t*>(J.out),
+                  reinterpret_cast<const uint32_t*>(J.part + J.lay.big_list), &r.ph->n_big, blockIdx.x % G, G);
+}
+
+hipError_t launch_bucket_sort_small_win(const WinJob* jobs, uint32_t njobs, uint32_t G, uint32_t rec_bytes,
+                                        uint32_t key_bytes, hipStream_t st) {
+  if (njobs == 0 || G == 0) return hipSuccess;
+  if (rec_bytes == 100)
+    bucket_sort_small_win_kernel<25><<<njobs * G, kSmThreads, 0, st>>>(jobs, G, key_bytes);
+  else
+    bucket_sort_lds_win_kernel<kSmallCap, 256, false><<<njobs * G, 256, 0, st>>>(jobs, G, rec_bytes / 4, key_bytes);
+  return hipGetLastError();
+}
+
+hipError_t launch_bucket_sort_large_win(const WinJob* jobs, uint32_t njobs, const WinGrids& g, uint32_t rec_bytes,
+                                        uint32_t key_bytes, hipStream_t st) {
+  if (njobs == 0) return hipSuccess;
+  const uint32_t RW = rec_bytes / 4;
+  bucket_sort_lds_win_kernel<kMidCap, 512, true><<<njobs * g.mid, 512, 0, st>>>(jobs, g.mid, RW, key_bytes);
+  if (rec_bytes < 64) {  // too little room for the split's buffers, stack and reference list
+    const uint32_t G = g.split < 256 ? g.split : 256;
+    bucket_sort_global_win_kernel<<<njobs * G, kBigThreads, 0, st>>>(jobs, G, RW, key_bytes);
+    return hipGetLastError();
+  }
+  // the split's counters (seg_n) were cleared by the small-bucket kernel
+  msd_split_win_kernel<<<njobs * g.split, kMsdThreads, 0, st>>>(jobs, g.split, RW, key_bytes);
+  seg_sort_win_kernel<<<njobs * g.seg, kSmThreads, 0, st>>>(jobs, g.seg, RW);
+  big_gather_win_kernel<<<njobs * g.gather, kMsdThreads, 0, st>>>(jobs, g.gather, RW);
   return hipGetLastError();
 }
 

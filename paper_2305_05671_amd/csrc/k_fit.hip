@@ -567,12 +567,10 @@ constexpr uint32_t kScanThreads = 1024;
 constexpr uint32_t kScanWaves = kScanThreads / 64;
 constexpr uint32_t kScanSteps = 4;  // steps of 256 buckets whose loads are in flight together
 
-__global__ __launch_bounds__(kScanThreads) void capacity_kernel(const uint32_t* __restrict__ hist, uint64_t S,
-                                                                uint64_t n, uint32_t B, double scale,
-                                                                uint32_t* __restrict__ caps,
-                                                                uint32_t* __restrict__ rstart,
-                                                                uint32_t* __restrict__ counts, uint32_t cstride,
-                                                                PartHeader* __restrict__ ph, uint64_t cap_slots) {
+__device__ __forceinline__ void capacity_body(const uint32_t* __restrict__ hist, uint64_t S, uint64_t n, uint32_t B,
+                                              double scale, uint32_t* __restrict__ caps,
+                                              uint32_t* __restrict__ rstart, uint32_t* __restrict__ counts,
+                                              uint32_t cstride, PartHeader* __restrict__ ph, uint64_t cap_slots) {
   __shared__ uint64_t sh[kScanWaves];
   const double ideal = (double)n / (double)B;
   const uint32_t WS = ((B + kScanWaves - 1) / kScanWaves + 1023) & ~1023u;
@@ -674,6 +672,30 @@ __global__ __launch_bounds__(kScanThreads) void capacity_kernel(const uint32_t* 
     ph->mid_records = 0;
     ph->big_records = 0;
   }
+}
+
+__global__ __launch_bounds__(kScanThreads) void capacity_kernel(const uint32_t* __restrict__ hist, uint64_t S,
+                                                                uint64_t n, uint32_t B, double scale,
+                                                                uint32_t* __restrict__ caps,
+                                                                uint32_t* __restrict__ rstart,
+                                                                uint32_t* __restrict__ counts, uint32_t cstride,
+                                                                PartHeader* __restrict__ ph, uint64_t cap_slots) {
+  capacity_body(hist, S, n, B, scale, caps, rstart, counts, cstride, ph, cap_slots);
+}
+
+// A window of a batch: one block per job.
+__global__ __launch_bounds__(kScanThreads) void capacity_win_kernel(const WinJob* __restrict__ jobs, double scale) {
+  const WinJob& J = jobs[blockIdx.x];
+  uint8_t* part = J.part;
+  capacity_body(J.hist, J.S, J.n, J.B, scale, reinterpret_cast<uint32_t*>(part + J.lay.caps),
+                reinterpret_cast<uint32_t*>(part + J.lay.rstart), reinterpret_cast<uint32_t*>(part + J.lay.pcounts),
+                J.lay.cstride, reinterpret_cast<PartHeader*>(part + J.lay.header), J.lay.cap_slots);
+}
+
+hipError_t launch_capacities_win(const WinJob* jobs, uint32_t njobs, uint32_t region_pct, hipStream_t st) {
+  if (njobs == 0) return hipSuccess;
+  capacity_win_kernel<<<njobs, kScanThreads, 0, st>>>(jobs, region_pct / 100.0);
+  return hipGetLastError();
 }
 
 hipError_t launch_capacities(const uint32_t* hist, uint64_t S, uint64_t n, uint32_t B, uint32_t region_pct,

@@ -82,7 +82,8 @@ __device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const
 // from 8.6 to 8.0 ms at 100M skewed records, the linear root's from 5.7 to
 // 5.4 ms at 100M uniform ones).
 //
-// Software pipeline per block over its tiles t = blockIdx.x, + gridDim.x, ...:
+// Software pipeline per block over its tiles t = bid, bid + nblk, ... (bid
+// and nblk: the block's index and the number of blocks working for the job):
 // the loads of tile t+1 are in flight while the atomics of tile t reserve
 // slots and the slots of tile t-1 are written, so neither the load latency nor
 // the atomic latency stalls the block.  Two LDS tile buffers alternate.
@@ -98,12 +99,13 @@ __device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const
 // record has index f.idx_base; only buckets f.lo .. f.hi-1 are placed (bucket
 // b at local bucket b - f.lo), the others are skipped.
 template <int RW_T, int ROOT, bool FILTER>
-__global__ __launch_bounds__(kPartThreads) void partition_kernel(
+__device__ __forceinline__ void partition_body(
     const ModelHeader* __restrict__ hdr, const Leaf* __restrict__ leaves, const MlpBlock* __restrict__ mlp,
     const uint64_t* __restrict__ bound, const uint64_t* __restrict__ knots, const uint32_t* __restrict__ cells,
     const uint8_t* __restrict__ recs, uint64_t n, uint32_t rw_rt, uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps,
     const uint32_t* __restrict__ rstart, PartHeader* __restrict__ ph, uint2* __restrict__ spill_meta,
-    uint4* __restrict__ slots, uint64_t cap_slots, PassFilter f, uint32_t vk, uint32_t cstride) {
+    uint4* __restrict__ slots, uint64_t cap_slots, PassFilter f, uint32_t vk, uint32_t cstride, uint32_t bid,
+    uint32_t nblk) {
   const uint32_t RW = RW_T ? (uint32_t)RW_T : rw_rt;  // record dwords
   const uint32_t SC = slot_bytes_for(RW * 4) / 16;     // 16-byte chunks per slot
   constexpr uint32_t RV = RW_T ? (kPartTile * RW_T / 4 + kPartThreads - 1) / kPartThreads : 8;
@@ -142,7 +144,7 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
     }
   };
 
-  uint64_t t = blockIdx.x;
+  uint64_t t = bid;
   if (t >= ntiles) return;
   // tile t is copied through registers: RV 16-byte vectors per thread plus a dword tail
   {
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
   bool have_prev = false;
   uint64_t tprev = 0;
   for (;;) {
-    const uint64_t tn = t + gridDim.x;
+    const uint64_t tn = t + nblk;
     const bool have_next = tn < ntiles;
     // 1. loads of the next tile
     // (the last iteration reloads its own tile instead: no branch around the loads)
@@ -232,6 +234,39 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
   write_tile(tprev, buf(cur), dst[cur]);
 }
 
+template <int RW_T, int ROOT, bool FILTER>
+__global__ __launch_bounds__(kPartThreads) void partition_kernel(
+    const ModelHeader* __restrict__ hdr, const Leaf* __restrict__ leaves, const MlpBlock* __restrict__ mlp,
+    const uint64_t* __restrict__ bound, const uint64_t* __restrict__ knots, const uint32_t* __restrict__ cells,
+    const uint8_t* __restrict__ recs, uint64_t n, uint32_t rw_rt, uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps,
+    const uint32_t* __restrict__ rstart, PartHeader* __restrict__ ph, uint2* __restrict__ spill_meta,
+    uint4* __restrict__ slots, uint64_t cap_slots, PassFilter f, uint32_t vk, uint32_t cstride) {
+  partition_body<RW_T, ROOT, FILTER>(hdr, leaves, mlp, bound, knots, cells, recs, n, rw_rt, counts, caps, rstart, ph,
+                                     spill_meta, slots, cap_slots, f, vk, cstride, blockIdx.x, gridDim.x);
+}
+
+// A window of a batch: G blocks per job.
+template <int RW_T, int ROOT>
+__global__ __launch_bounds__(kPartThreads) void partition_win_kernel(const WinJob* __restrict__ jobs, uint32_t G,
+                                                                     uint32_t rw_rt) {
+  const WinJob& J = jobs[blockIdx.x / G];
+  uint8_t* part = J.part;
+  partition_body<RW_T, ROOT, false>(
+      J.hdr, ROOT ? J.eq_leaves : J.leaves, J.mlp, J.bound, J.knots, J.cells, J.recs, J.n, rw_rt,
+      reinterpret_cast<uint32_t*>(part + J.lay.pcounts), reinterpret_cast<const uint32_t*>(part + J.lay.caps),
+      reinterpret_cast<const uint32_t*>(part + J.lay.rstart), reinterpret_cast<PartHeader*>(part + J.lay.header),
+      reinterpret_cast<uint2*>(part + J.lay.spill_meta), reinterpret_cast<uint4*>(part + J.lay.slots),
+      J.lay.cap_slots, PassFilter{0, 0, 0}, 0u, J.lay.cstride, blockIdx.x % G, G);
+}
+
+// Blocks of the partition of n records: at least four tiles per block below
+// 8192 tiles, so that the pipeline has tiles to overlap (small jobs of a
+// batch run beside others), at most 2048 blocks.
+uint32_t partition_grid(uint64_t n) {
+  const uint64_t ntiles = (n + kPartTile - 1) / kPartTile;
+  return ntiles < 8192 ? (uint32_t)((ntiles + 3) / 4) : 2048u;
+}
+
 template <int ROOT, bool FILTER>
 static void launch_partition_root(uint32_t grid, size_t lds, hipStream_t st, uint32_t RW, const ModelHeader* hdr,
                                   const Leaf* leaves, const MlpBlock* mlp, const uint64_t* bound,
@@ -255,11 +290,7 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const Ml
   if (n == 0) return hipSuccess;
   const uint32_t RW = rec_bytes / 4;
   const size_t lds = 2 * (size_t)kPartTile * RW * 4;
-  uint64_t ntiles = (n + kPartTile - 1) / kPartTile;
-  // at least four tiles per block below 8192 tiles, so that the pipeline has
-  // tiles to overlap (small jobs of a batch run beside others)
-  uint32_t grid = (uint32_t)(ntiles < 2048 ? ntiles : 2048);
-  if (ntiles < 8192) grid = (uint32_t)((ntiles + 3) / 4);
+  const uint32_t grid = partition_grid(n);
   auto* counts = reinterpret_cast<uint32_t*>(part + lay.pcounts);  // the partition's slot counters
   const uint32_t cstride = lay.cstride;
   auto* caps = reinterpret_cast<const uint32_t*>(part + lay.caps);
@@ -287,6 +318,28 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const Ml
                                       recs, n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk, cstride);
     }
   }
+  return hipGetLastError();
+}
+
+template <int RW_T>
+static void launch_partition_win_rw(const WinJob* jobs, uint32_t njobs, uint32_t G, uint32_t RW, bool equi_depth,
+                                    hipStream_t st) {
+  const size_t lds = 2 * (size_t)kPartTile * RW * 4;
+  partition_win_kernel<RW_T, 0><<<njobs * G, kPartThreads, lds, st>>>(jobs, G, RW);
+  if (equi_depth) {
+    partition_win_kernel<RW_T, 1><<<njobs * G, kPartThreads, lds, st>>>(jobs, G, RW);
+    partition_win_kernel<RW_T, 2><<<njobs * G, kPartThreads, lds, st>>>(jobs, G, RW);
+  }
+}
+
+hipError_t launch_partition_win(const WinJob* jobs, uint32_t njobs, uint32_t G, uint32_t rec_bytes, bool equi_depth,
+                                hipStream_t st) {
+  if (njobs == 0 || G == 0) return hipSuccess;
+  const uint32_t RW = rec_bytes / 4;
+  if (RW == 25)
+    launch_partition_win_rw<25>(jobs, njobs, G, RW, equi_depth, st);
+  else
+    launch_partition_win_rw<0>(jobs, njobs, G, RW, equi_depth, st);
   return hipGetLastError();
 }
 
@@ -446,14 +499,11 @@ constexpr uint32_t kScanSteps = 4;  // steps of 256 buckets whose loads are in f
 
 // counts: the partition's slot counters, cstride apart; with cstride > 1 the
 // dense counts the bucket sorts read go to dense.
-__global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_t* __restrict__ counts,
-                                                                   uint32_t cstride, uint32_t* __restrict__ dense,
-                                                                   const uint32_t* __restrict__ caps, uint32_t B,
-                                                                   uint64_t* __restrict__ offsets,
-                                                                   uint32_t* __restrict__ spill_off,
-                                                                   uint32_t* __restrict__ mid_list,
-                                                                   uint32_t* __restrict__ big_list,
-                                                                   PartHeader* __restrict__ ph) {
+__device__ __forceinline__ void scan_counts_body(const uint32_t* __restrict__ counts, uint32_t cstride,
+                                                 uint32_t* __restrict__ dense, const uint32_t* __restrict__ caps,
+                                                 uint32_t B, uint64_t* __restrict__ offsets,
+                                                 uint32_t* __restrict__ spill_off, uint32_t* __restrict__ mid_list,
+                                                 uint32_t* __restrict__ big_list, PartHeader* __restrict__ ph) {
   __shared__ uint64_t shc[kScanWaves + 1];
   __shared__ uint32_t shs[kScanWaves];
   const uint32_t WS = ((B + kScanWaves - 1) / kScanWaves + 1023) & ~1023u;
@@ -584,6 +634,34 @@ __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_
   if (threadIdx.x == 0) offsets[B] = shc[kScanWaves];
 }
 
+__global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(const uint32_t* __restrict__ counts,
+                                                                   uint32_t cstride, uint32_t* __restrict__ dense,
+                                                                   const uint32_t* __restrict__ caps, uint32_t B,
+                                                                   uint64_t* __restrict__ offsets,
+                                                                   uint32_t* __restrict__ spill_off,
+                                                                   uint32_t* __restrict__ mid_list,
+                                                                   uint32_t* __restrict__ big_list,
+                                                                   PartHeader* __restrict__ ph) {
+  scan_counts_body(counts, cstride, dense, caps, B, offsets, spill_off, mid_list, big_list, ph);
+}
+
+// A window of a batch: one block per job.
+__global__ __launch_bounds__(kScanThreads) void scan_counts_win_kernel(const WinJob* __restrict__ jobs) {
+  const WinJob& J = jobs[blockIdx.x];
+  uint8_t* part = J.part;
+  scan_counts_body(reinterpret_cast<const uint32_t*>(part + J.lay.pcounts), J.lay.cstride,
+                   reinterpret_cast<uint32_t*>(part + J.lay.counts), reinterpret_cast<const uint32_t*>(part + J.lay.caps),
+                   J.B, J.offsets, reinterpret_cast<uint32_t*>(part + J.lay.spill_off),
+                   reinterpret_cast<uint32_t*>(part + J.lay.mid_list), reinterpret_cast<uint32_t*>(part + J.lay.big_list),
+                   reinterpret_cast<PartHeader*>(part + J.lay.header));
+}
+
+hipError_t launch_scan_counts_win(const WinJob* jobs, uint32_t njobs, hipStream_t st) {
+  if (njobs == 0) return hipSuccess;
+  scan_counts_win_kernel<<<njobs, kScanThreads, 0, st>>>(jobs);
+  return hipGetLastError();
+}
+
 hipError_t launch_scan_counts(uint8_t* part, const PartLayout& lay, uint32_t B, uint64_t* offsets,
                               hipStream_t st) {
   scan_counts_kernel<<<1, kScanThreads, 0, st>>>(
@@ -595,22 +673,47 @@ hipError_t launch_scan_counts(uint8_t* part, const PartLayout& lay, uint32_t B, 
 }
 
 // spill_map[spill_off[b] + k] = spill slot of the k-th overflow record of bucket b.
-__global__ __launch_bounds__(256) void spill_fixup_kernel(const PartHeader* __restrict__ ph,
-                                                          const uint2* __restrict__ meta,
-                                                          const uint32_t* __restrict__ spill_off,
-                                                          uint32_t* __restrict__ spill_map) {
+__device__ __forceinline__ void spill_fixup_body(const PartHeader* __restrict__ ph, const uint2* __restrict__ meta,
+                                                 const uint32_t* __restrict__ spill_off,
+                                                 uint32_t* __restrict__ spill_map, uint32_t bid, uint32_t nblk) {
   const uint32_t m = ph->spill_count;
-  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < m; q += gridDim.x * blockDim.x) {
+  for (uint32_t q = bid * 256u + threadIdx.x; q < m; q += nblk * 256u) {
     uint2 bm = meta[q];
     spill_map[spill_off[bm.x] + bm.y] = q;
   }
 }
 
+__global__ __launch_bounds__(256) void spill_fixup_kernel(const PartHeader* __restrict__ ph,
+                                                          const uint2* __restrict__ meta,
+                                                          const uint32_t* __restrict__ spill_off,
+                                                          uint32_t* __restrict__ spill_map) {
+  spill_fixup_body(ph, meta, spill_off, spill_map, blockIdx.x, gridDim.x);
+}
+
+// A window of a batch: G blocks per job.
+__global__ __launch_bounds__(256) void spill_fixup_win_kernel(const WinJob* __restrict__ jobs, uint32_t G) {
+  const WinJob& J = jobs[blockIdx.x / G];
+  const uint8_t* part = J.part;
+  spill_fixup_body(reinterpret_cast<const PartHeader*>(part + J.lay.header),
+                   reinterpret_cast<const uint2*>(part + J.lay.spill_meta),
+                   reinterpret_cast<const uint32_t*>(part + J.lay.spill_off),
+                   reinterpret_cast<uint32_t*>(J.part + J.lay.spill_map), blockIdx.x % G, G);
+}
+
+hipError_t launch_spill_fixup_win(const WinJob* jobs, uint32_t njobs, uint32_t G, hipStream_t st) {
+  if (njobs == 0 || G == 0) return hipSuccess;
+  spill_fixup_win_kernel<<<njobs * G, 256, 0, st>>>(jobs, G);
+  return hipGetLastError();
+}
+
+// Grid of the spill fix-up for n records.
+uint32_t spill_fixup_grid(uint64_t n) {
+  uint64_t g = (n + 255) / 256;
+  return (uint32_t)(g > 1024 ? 1024 : (g == 0 ? 1 : g));
+}
+
 hipError_t launch_spill_fixup(uint8_t* part, const PartLayout& lay, uint64_t n, hipStream_t st) {
-  uint32_t grid = (uint32_t)((n + 255) / 256);
-  if (grid > 1024) grid = 1024;
-  if (grid == 0) grid = 1;
-  spill_fixup_kernel<<<grid, 256, 0, st>>>(reinterpret_cast<const PartHeader*>(part + lay.header),
+  spill_fixup_kernel<<<spill_fixup_grid(n), 256, 0, st>>>(reinterpret_cast<const PartHeader*>(part + lay.header),
                                            reinterpret_cast<const uint2*>(part + lay.spill_meta),
                                            reinterpret_cast<const uint32_t*>(part + lay.spill_off),
                                            reinterpret_cast<uint32_t*>(part + lay.spill_map));

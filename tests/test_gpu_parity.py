@@ -277,6 +277,52 @@ def test_batch_matches_oracle_and_replays(env):
     del junk
 
 
+def test_batch_windows_large_jobs_and_big_buckets(env):
+    """Jobs whose samples are too large for the batched one-block fit (fitted
+    one by one beside the first windows) in the same batch as jobs the batched
+    fit takes; hot keys that make buckets above the LDS caps (the split and
+    gather kernels inside a window); sizes that put several jobs in one window
+    and leave others alone in theirs.  Out of place, then in place."""
+    torch, elsar = env
+    rng = np.random.default_rng(35)
+    sizes = [2_100_000, 1_700_000, 1_000_000, 900_000, 600_000, 520_000, 300_000, 120_000, 90_000, 7_000, 4_100,
+             2_049]
+    kinds = ["uniform", "skewed", "skewed", "zipf", "uniform", "skewed", "zipf", "skewed", "uniform", "zipf",
+             "skewed", "uniform"]
+    host, dev = _batch_inputs(torch, rng, sizes, kinds, 300)
+    want = [oracle.sort_records(h) for h in host]
+    outs = [torch.empty_like(d) for d in dev]
+    ws = elsar.sort_batch(dev, outs)
+    torch.cuda.synchronize()
+    for j in range(len(sizes)):
+        _assert_same(outs[j].cpu().numpy().reshape(-1, R), want[j])
+    ws = elsar.sort_batch(dev, None, workspace=ws)  # in place: a new job table, a new recorded graph
+    torch.cuda.synchronize()
+    for j in range(len(sizes)):
+        _assert_same(dev[j].cpu().numpy().reshape(-1, R), want[j])
+
+
+@pytest.mark.parametrize("rec_bytes", [48, 64])
+def test_batch_windows_other_record_sizes(env, rec_bytes):
+    """Records other than 100 bytes: the general LDS kernel sorts every small
+    bucket, and below 64 bytes the global kernel the big ones."""
+    torch, elsar = env
+    rng = np.random.default_rng(37)
+    sizes = [400_000, 350_000, 250_000, 60_000, 3_000]
+    kinds = ["skewed", "uniform", "skewed", "zipf", "skewed"]
+    host, dev = [], []
+    for j, (n, kind) in enumerate(zip(sizes, kinds)):
+        r = datagen.generate(datagen.spec(kind, seed=400 + j, record_bytes=rec_bytes), n)
+        host.append(r)
+        dev.append(torch.from_numpy(np.ascontiguousarray(r).reshape(-1)).to("cuda"))
+    want = [oracle.sort_records(h) for h in host]
+    outs = [torch.empty_like(d) for d in dev]
+    elsar.sort_batch(dev, outs, params=elsar.fit_params(record_bytes=rec_bytes))
+    torch.cuda.synchronize()
+    for j in range(len(sizes)):
+        _assert_same(outs[j].cpu().numpy().reshape(-1, rec_bytes), want[j])
+
+
 @pytest.mark.parametrize("kind_name", ["AUTO", "SPLINE"])
 def test_batch_with_equi_depth_roots(env, kind_name):
     # jobs whose models are fitted one by one (no batched linear fit): the
