@@ -225,17 +225,22 @@ elsar_status elsar_sort_batch_workspace_size(const elsar_job* h_jobs, uint32_t n
 /*
  * Independent sorts of many jobs of uneven sizes in one launch (the method
  * applied per job; uneven work is balanced the way the paper balances uneven
- * partitions over threads with dynamic scheduling, Section 7.3, here over
- * jobs and concurrent lanes).  h_jobs: host array of njobs jobs.  p applies to every job, except
- * that num_buckets / num_leaves of 0 are chosen per job from the tuned table,
- * and job j's sampler seed is p->seed + j.  Jobs of up to 2048 records are
- * sorted whole, one block each, in a single kernel; the models of jobs whose
- * sample fits LDS are fitted by one kernel, one block each; the jobs then run
- * the rest of the pipeline on sixteen concurrent lanes, each lane reusing one
- * slice of d_ws sized for its largest job (scratch is bounded by sixteen
- * jobs, not by the batch).  The first call with a given (table, parameters, workspace) records
- * the whole batch as one HIP graph; that call and every later one with the
- * same arguments is a single graph launch on `stream`.  Asynchronous.
+ * partitions over threads, Section 7.3, here by giving every phase kernel the
+ * work of many jobs at once).  h_jobs: host array of njobs jobs; jobs must
+ * not overlap one another (a job's output may be its input).  p applies to
+ * every job, except that num_buckets / num_leaves of 0 are chosen per job
+ * from the tuned table, and job j's sampler seed is p->seed + j.
+ *  - Jobs of up to 2048 records are sorted whole, one block each, in one kernel.
+ *  - Models: under kind RMI one kernel fits the jobs whose sample has at most
+ *    3 * 16384 codes, one block each; other jobs are fitted one by one.
+ *  - The jobs are grouped into windows: jobs within a factor 2 in size, about
+ *    64M records per window (more for one larger job).  A window's jobs share
+ *    one launch per phase (capacities, partition, scan, spill fix-up, bucket
+ *    sorts); the windows run one after another in one area of d_ws, so the
+ *    scratch is bounded by one window, not by the batch.
+ * The first call with a given (table, parameters, workspace) records the whole
+ * batch as one HIP graph; that call and every later one with the same
+ * arguments is a single graph launch on `stream`.  Asynchronous.
  */
 elsar_status elsar_sort_batch(const elsar_job* h_jobs, uint32_t njobs, const elsar_fit_params* p, void* d_ws,
                               size_t ws_bytes, hipStream_t stream);
@@ -317,6 +322,16 @@ typedef struct {
 } elsar_model_info;
 
 elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info);
+
+/* The model of job `job` as the last elsar_sort_batch call with this job
+ * table, parameters and workspace fitted it, read back from d_ws once that
+ * call has completed (synchronises with the device); the fields are those of
+ * elsar_model_info_get.  For checking the batched fit against elsar_sample_fit
+ * with the job's parameters (num_buckets and num_leaves as reported, seed
+ * p->seed + job).  ELSAR_E_INVALID_ARG for a job out of range or one sorted
+ * whole (2048 records or fewer, no model). */
+elsar_status elsar_sort_batch_model_info(const elsar_job* h_jobs, uint32_t njobs, const elsar_fit_params* p,
+                                         const void* d_ws, size_t ws_bytes, uint32_t job, elsar_model_info* info);
 
 /* Copies the leaf table of the root in use to host arrays of num_leaves
  * entries each (any may be NULL).  Synchronises. */

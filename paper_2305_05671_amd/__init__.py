@@ -149,6 +149,8 @@ def lib():
             "elsar_sort": ([_P, _U64, _P, ctypes.POINTER(FitParams), _P, _SZ, _P], st),
             "elsar_sort_noalloc": ([_P, _U64, _P, ctypes.POINTER(FitParams), _P], st),
             "elsar_model_info_get": ([_P, ctypes.POINTER(ModelInfo)], st),
+            "elsar_sort_batch_model_info": ([ctypes.POINTER(Job), ctypes.c_uint32, ctypes.POINTER(FitParams), _P, _SZ,
+                                             ctypes.c_uint32, ctypes.POINTER(ModelInfo)], st),
             "elsar_model_leaves": ([_P, _P, _P, _P, _P, _P], st),
             "elsar_partition_stats_get": ([_P, _P, _SZ, ctypes.POINTER(PartitionStats)], st),
             "elsar_model_mlp_get": ([_P, _P, _P, _P, _P], st),
@@ -295,6 +297,18 @@ def sort_batch(inputs, outputs=None, params: FitParams | None = None, workspace=
     _check("elsar_sort_batch", lib().elsar_sort_batch(table, len(inputs), ctypes.byref(params),
                                                       workspace.data_ptr(), workspace.numel(), _stream(stream)))
     return workspace
+
+
+def sort_batch_model_info(inputs, job: int, workspace, outputs=None, params: FitParams | None = None) -> ModelInfo:
+    """elsar_sort_batch_model_info: the model the last sort_batch call with
+    these tensors, parameters and workspace fitted for job ``job``."""
+    params = params or fit_params()
+    table = _job_table(inputs, outputs, params.record_bytes)
+    i = ModelInfo()
+    _check("elsar_sort_batch_model_info",
+           lib().elsar_sort_batch_model_info(table, len(inputs), ctypes.byref(params), workspace.data_ptr(),
+                                             workspace.numel(), job, ctypes.byref(i)))
+    return i
 
 
 def sort_host_workspace_size(n: int, params: FitParams | None = None, chunk_records: int = 0,

@@ -6,13 +6,14 @@ Two sweeps, both run on the GPU:
   elsar_sort_batch) of 2^k records, k in 11..22, over candidate bucket sizes
   (records per bucket), on the batch workload's two key laws (uniform,
   first-byte Zipf); the fastest size per k goes into csrc/autotune_table.h.
-* --batch: jobs of a batch run sixteen at a time, which changes the trade-off,
-  so this sweep times the batch workload itself (bench.py --workload
-  batch-4096) with one records-per-bucket value for every job of up to 2^20
-  records, rebuilding the library for each candidate, and keeps the fastest.
+* --batch: a batch sorts its jobs window by window (many jobs per launch),
+  which changes the trade-off, so this sweep times the batch workload itself
+  (bench.py --workload batch-4096) with one records-per-bucket value for
+  every job whose ceil(log2 n) is in --rows, rebuilding the library for each
+  candidate, and keeps the fastest (0: the default rule).
 
-    python -m paper_2305_05671_amd.autotune            # per-size table
-    python -m paper_2305_05671_amd.autotune --batch    # batch-context table
+    python -m paper_2305_05671_amd.autotune                          # per-size table
+    python -m paper_2305_05671_amd.autotune --batch --rows 11-22     # batch-context table
     python -c "import __graft_entry__ as g; g.build()"
 """
 from __future__ import annotations
@@ -71,8 +72,9 @@ def write_table(best, path=TABLE):
 // records gets the largest power of two <= n / kAutotuneRecordsPerBucket[r]
 // buckets (at least 1).  Written by paper_2305_05671_amd/autotune.py on
 // gfx950: the per-size sweep of whole sorts (uniform and first-byte-Zipf keys,
-// the batch workload's two key laws), then the batch-context sweep for jobs of
-// up to 2^20 records; 0 means the default, 950.
+// the batch workload's two key laws), then the batch-context sweep (the batch
+// workload, sorted window by window) over the rows it names; 0 means the
+// default, 950.
 #pragma once
 #include <stdint.h>
 
@@ -128,10 +130,12 @@ def main():
     ap.add_argument("--kmax", type=int, default=22)
     ap.add_argument("--out", default=TABLE)
     ap.add_argument("--batch", action="store_true", help="batch-context sweep (rewrites the table in place)")
-    ap.add_argument("--candidates", default="64,96,128,192,256")
+    ap.add_argument("--candidates", default="0,256,512,768,1200")
+    ap.add_argument("--rows", default="11-20", help="table rows (ceil(log2 n)) the batch sweep sets, lo-hi")
     a = ap.parse_args()
     if a.batch:
-        batch_sweep([int(c) for c in a.candidates.split(",")])
+        lo, hi = (int(x) for x in a.rows.split("-"))
+        batch_sweep([int(c) for c in a.candidates.split(",")], small_rows=range(lo, hi + 1))
         print(open(TABLE).read())
         return
     write_table(sweep(a.kmin, a.kmax), a.out)

@@ -2,8 +2,9 @@
 // records gets the largest power of two <= n / kAutotuneRecordsPerBucket[r]
 // buckets (at least 1).  Written by paper_2305_05671_amd/autotune.py on
 // gfx950: the per-size sweep of whole sorts (uniform and first-byte-Zipf keys,
-// the batch workload's two key laws), then the batch-context sweep for jobs of
-// up to 2^20 records; 0 means the default, 950.
+// the batch workload's two key laws), then the batch-context sweep (the batch
+// workload, sorted window by window) over the rows it names; 0 means the
+// default, 950.
 #pragma once
 #include <stdint.h>
 
@@ -11,6 +12,6 @@ namespace elsar {
 constexpr uint32_t kAutotuneRows = 33;
 constexpr uint32_t kAutotuneRecordsPerBucket[kAutotuneRows] = {
     0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0,
-    128, 128, 128, 128, 128, 128, 128, 128, 128, 128, 384,
-    384, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    512, 512, 512, 512, 512, 512, 512, 512, 512, 512, 512,
+    512, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 }  // namespace elsar

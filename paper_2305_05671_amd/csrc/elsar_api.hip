@@ -487,6 +487,7 @@ struct BatchWindow {
 struct BatchLayout {
   std::vector<TinyJob> tiny;
   std::vector<uint32_t> prefit;                  // jobs whose model the batch fit kernel fits
+  std::vector<size_t> prefit_scratch;            // per such job: offset of its sample scratch (larger samples)
   std::vector<size_t> model;                     // per job above kSmallCap: workspace offset of its model
   std::vector<std::vector<uint32_t>> fit_lanes;  // the other jobs, fitted one by one, per lane
   std::vector<size_t> fit_off, fit_bytes;        // per lane: its fit scratch
@@ -530,13 +531,14 @@ elsar_status batch_layout(const elsar_job* jobs, uint32_t njobs, const elsar_fit
     }
   }
   std::stable_sort(big.begin(), big.end(), [&](uint32_t a, uint32_t b) { return jobs[a].n > jobs[b].n; });
-  // models: one batched kernel for the linear root of jobs whose sample fits
-  // LDS; the others one by one, longest sample first to the least loaded lane
+  // models: one batched kernel for the linear root of jobs whose sample it
+  // can sort; the others one by one, longest sample first to the least loaded
+  // lane
   std::vector<uint8_t> is_prefit(njobs, 0);
   std::vector<uint32_t> lone;
   for (uint32_t j : big) {
     const elsar_fit_params q = job_params(p, jobs[j].n, j);
-    if (p.kind == ELSAR_MODEL_RMI && resolve(q, jobs[j].n).S <= kBatchFitMaxS) {
+    if (p.kind == ELSAR_MODEL_RMI && resolve(q, jobs[j].n).S <= kBatchFitMaxS * kBatchFitChunks) {
       bl->prefit.push_back(j);
       is_prefit[j] = 1;
     } else {
@@ -588,6 +590,11 @@ elsar_status batch_layout(const elsar_job* jobs, uint32_t njobs, const elsar_fit
     bl->model[j] = off;
     off += align_up(model_dev_bytes(resolve(q, jobs[j].n), q.kind));
   }
+  for (uint32_t j : bl->prefit) {
+    const uint64_t S = resolve(job_params(p, jobs[j].n, j), jobs[j].n).S;
+    bl->prefit_scratch.push_back(S > kBatchFitMaxS ? off : 0);
+    if (S > kBatchFitMaxS) off += align_up((size_t)S * 16);
+  }
   bl->tiny_stage = off;
   off += align_up(stage_dw * 4);
   bl->fit_off.assign(nl, 0);
@@ -632,9 +639,11 @@ elsar_model job_model(const elsar_job* jobs, const elsar_fit_params& p, const Ba
 std::vector<FitJob> fit_descriptors(const elsar_job* jobs, const elsar_fit_params& p, const BatchLayout& bl,
                                     uint8_t* w) {
   std::vector<FitJob> out;
-  for (uint32_t j : bl.prefit) {
+  for (size_t k = 0; k < bl.prefit.size(); ++k) {
+    const uint32_t j = bl.prefit[k];
     const elsar_model m = job_model(jobs, p, bl, w, j);
     FitJob f{};
+    f.scratch = bl.prefit_scratch[k] ? reinterpret_cast<uint64_t*>(w + bl.prefit_scratch[k]) : nullptr;
     f.recs = static_cast<const uint8_t*>(jobs[j].d_in);
     f.n = jobs[j].n;
     f.S = m.S;
@@ -1396,10 +1405,10 @@ elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, void* h_
   return ELSAR_OK;
 }
 
-elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info) {
-  if (!m || !info) return ELSAR_E_INVALID_ARG;
-  ModelHeader h;
-  HIP_TRY(hipMemcpy(&h, m->hdr, sizeof(h), hipMemcpyDeviceToHost));
+}  // extern "C"
+
+namespace {
+void fill_model_info(const elsar_model* m, const ModelHeader& h, uint64_t n_fit, elsar_model_info* info) {
   std::memset(info, 0, sizeof(*info));
   info->kind_used = h.kind_used == 2 ? (uint32_t)ELSAR_MODEL_SPLINE : h.kind_used;  // header: 2 = spline root
   info->mlp_rejected = h.mlp_rejected;
@@ -1409,7 +1418,7 @@ elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info) 
   info->mlp_leaves = eq ? m->Lm : 0;
   info->spline_segments = eq ? spline_segments(m->Lm) : 0;
   info->sample_size = m->S;
-  info->n_fit = m->n;
+  info->n_fit = n_fit;
   info->root_a0 = h.a0;
   info->root_a1 = h.a1;
   info->max_sample_bucket = h.max_sample_bucket;
@@ -1419,6 +1428,34 @@ elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info) 
   info->net_max_sample_bucket = h.max_net;
   info->rmi_gate_passed = h.rmi_ok;
   info->perfect_sample_bucket = h.perfect;
+}
+}  // namespace
+
+extern "C" {
+
+elsar_status elsar_model_info_get(const elsar_model* m, elsar_model_info* info) {
+  if (!m || !info) return ELSAR_E_INVALID_ARG;
+  ModelHeader h;
+  HIP_TRY(hipMemcpy(&h, m->hdr, sizeof(h), hipMemcpyDeviceToHost));
+  fill_model_info(m, h, m->n, info);
+  return ELSAR_OK;
+}
+
+elsar_status elsar_sort_batch_model_info(const elsar_job* h_jobs, uint32_t njobs, const elsar_fit_params* p,
+                                         const void* d_ws, size_t ws_bytes, uint32_t job, elsar_model_info* info) {
+  if (!h_jobs || !info || !d_ws || job >= njobs) return ELSAR_E_INVALID_ARG;
+  elsar_status s = check_params(p);
+  if (s != ELSAR_OK) return s;
+  if (h_jobs[job].n <= kSmallCap) return ELSAR_E_INVALID_ARG;
+  BatchLayout bl;
+  s = batch_layout(h_jobs, njobs, *p, &bl);
+  if (s != ELSAR_OK) return s;
+  if (ws_bytes < bl.bytes) return ELSAR_E_NO_MEMORY;
+  const elsar_model m = job_model(h_jobs, *p, bl, static_cast<uint8_t*>(const_cast<void*>(d_ws)), job);
+  ModelHeader h;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(&h, m.hdr, sizeof(h), hipMemcpyDeviceToHost));
+  fill_model_info(&m, h, h.n_fit, info);
   return ELSAR_OK;
 }
 

@@ -330,8 +330,11 @@ hipError_t launch_fit_rmi(const uint64_t* sorted_codes, uint64_t S, uint64_t n, 
                           ModelHeader* hdr, Leaf* leaves, void* scratch, hipStream_t st);
 hipError_t launch_sample_hist(const ModelHeader* hdr, const Leaf* leaves, const uint64_t* sorted_codes,
                               uint64_t S, uint32_t B, uint32_t* hist, hipStream_t st);
-// batch: one block fits the model of one job whose sample fits LDS
+// batch: one block fits the linear model of one job; a sample of up to
+// kBatchFitMaxS codes is sorted in LDS, one of up to kBatchFitChunks times
+// that in chunks through 2 S codes of global scratch
 constexpr uint64_t kBatchFitMaxS = 16384;
+constexpr uint64_t kBatchFitChunks = 3;
 struct FitJob {
   const uint8_t* recs;   // the job's records (device)
   uint64_t n, S, seed;
@@ -339,6 +342,7 @@ struct FitJob {
   ModelHeader* hdr;
   Leaf* leaves;          // L
   uint32_t* hist;        // B
+  uint64_t* scratch;     // 2 S codes when S > kBatchFitMaxS, else unused
 };
 hipError_t launch_batch_fit(const FitJob* d_jobs, uint32_t njobs, uint32_t rec_bytes, hipStream_t st);
 hipError_t launch_radix_model(uint64_t S, uint64_t n, uint32_t L, uint32_t B, ModelHeader* hdr, Leaf* leaves,

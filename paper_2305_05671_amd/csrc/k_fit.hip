@@ -430,10 +430,14 @@ hipError_t launch_radix_model(uint64_t S, uint64_t n, uint32_t L, uint32_t B, Mo
 }
 
 // ---------------------------------------------------- batch: fit per job --
-// One 1024-thread block fits the whole model of one job whose sample fits
-// LDS: its S <= kBatchFitMaxS sample codes are drawn straight from the job's
-// records, sorted in LDS (bitonic network), then the root line, the spline
-// leaves and the sample histogram are computed as by the per-job kernels.
+// One 1024-thread block fits the whole model of one job: its S sample codes
+// are drawn straight from the job's records and sorted, then the root line,
+// the spline leaves and the sample histogram are computed as by the per-job
+// kernels.  A sample of up to kBatchFitMaxS codes is sorted in LDS (bitonic
+// network) and read there; a larger one (up to kBatchFitChunks chunks of
+// kBatchFitMaxS) is sorted chunk by chunk in LDS into the job's global
+// scratch, the sorted chunks are merged by rank into its second half, and the
+// fit reads that (a few hundred KB, held in L2).
 constexpr uint32_t kBfThreads = 1024;
 
 __device__ double bf_sum(double v, double* sh) {
@@ -446,35 +450,57 @@ __device__ double bf_sum(double v, double* sh) {
   return t;
 }
 
-__device__ void fit_job_block(const FitJob& J, uint32_t rec_bytes, uint64_t* e, double* sh, uint32_t* shm) {
+// Sample codes c0 .. c0+m-1 of job J sorted into e[0 .. m) (LDS); the
+// bitonic network runs over the next power of two, padded with codes that
+// sort last.
+__device__ __forceinline__ void bf_sort_chunk(const FitJob& J, uint32_t rec_bytes, uint64_t c0, uint32_t m,
+                                              uint64_t* e) {
+  const uint32_t tid = threadIdx.x;
+  uint32_t P = 1;
+  while (P < m) P <<= 1;
+  for (uint32_t s = tid; s < P; s += kBfThreads) {
+    uint64_t c = ~0ull;
+    if (s < m) {
+      const uint32_t* r =
+          reinterpret_cast<const uint32_t*>(J.recs + sample_index(c0 + s, J.n, J.S, J.seed) * rec_bytes);
+      c = key_code(r[0], r[1]);
+    }
+    e[s] = c;
+  }
+  __syncthreads();
+  for (uint32_t k = 2; k <= P; k <<= 1)
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = tid; i < P; i += kBfThreads) {
+        const uint32_t ij = i ^ j;
+        if (ij > i) {
+          const uint64_t a = e[i], b = e[ij];
+          if ((a > b) == ((i & k) == 0)) {
+            e[i] = b;
+            e[ij] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+// Codes of the sorted run g[0 .. len) below x (or, with upper, not above x).
+__device__ __forceinline__ uint32_t bf_rank(const uint64_t* g, uint32_t len, uint64_t x, bool upper) {
+  uint32_t lo = 0, hi = len;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    const uint64_t v = g[mid];
+    if (v < x || (upper && v == x)) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// The model from the sorted sample e[0 .. S) (LDS or global).
+__device__ __forceinline__ void bf_fit_sorted(const FitJob& J, const uint64_t* e, double* sh, uint32_t* shm) {
   const uint32_t tid = threadIdx.x;
   {
     const uint64_t S = J.S;
-    uint32_t P = 1;
-    while (P < S) P <<= 1;
-    for (uint32_t s = tid; s < P; s += kBfThreads) {
-      uint64_t c = ~0ull;  // padding sorts last
-      if (s < S) {
-        const uint32_t* r = reinterpret_cast<const uint32_t*>(J.recs + sample_index(s, J.n, S, J.seed) * rec_bytes);
-        c = key_code(r[0], r[1]);
-      }
-      e[s] = c;
-    }
-    __syncthreads();
-    for (uint32_t k = 2; k <= P; k <<= 1)
-      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        for (uint32_t i = tid; i < P; i += kBfThreads) {
-          const uint32_t ij = i ^ j;
-          if (ij > i) {
-            const uint64_t a = e[i], b = e[ij];
-            if ((a > b) == ((i & k) == 0)) {
-              e[i] = b;
-              e[ij] = a;
-            }
-          }
-        }
-        __syncthreads();
-      }
     // root line
     double sx = 0;
     for (uint32_t s = tid; s < S; s += kBfThreads) sx += (double)code_f32(e[s]);
@@ -534,6 +560,42 @@ __device__ void fit_job_block(const FitJob& J, uint32_t rec_bytes, uint64_t* e, 
     }
     __syncthreads();
   }
+}
+
+__device__ void fit_job_block(const FitJob& J, uint32_t rec_bytes, uint64_t* e, double* sh, uint32_t* shm) {
+  const uint64_t S = J.S;
+  if (S <= kBatchFitMaxS) {
+    bf_sort_chunk(J, rec_bytes, 0, (uint32_t)S, e);
+    bf_fit_sorted(J, e, sh, shm);
+    return;
+  }
+  // chunks sorted in LDS into g, merged by rank into g2: a code at index i of
+  // chunk a goes to i + (codes not above it in earlier chunks) + (codes below
+  // it in later chunks), a permutation that orders the whole sample
+  uint64_t* g = J.scratch;
+  uint64_t* g2 = J.scratch + S;
+  const uint32_t nc = (uint32_t)((S + kBatchFitMaxS - 1) / kBatchFitMaxS);
+  for (uint32_t a = 0; a < nc; ++a) {
+    const uint64_t c0 = (uint64_t)a * kBatchFitMaxS;
+    const uint32_t m = (uint32_t)(S - c0 < kBatchFitMaxS ? S - c0 : kBatchFitMaxS);
+    bf_sort_chunk(J, rec_bytes, c0, m, e);
+    for (uint32_t i = threadIdx.x; i < m; i += kBfThreads) g[c0 + i] = e[i];
+    __syncthreads();
+  }
+  for (uint32_t s = threadIdx.x; s < S; s += kBfThreads) {
+    const uint32_t a = s / kBatchFitMaxS;
+    const uint64_t x = g[s];
+    uint64_t pos = s - (uint64_t)a * kBatchFitMaxS;
+    for (uint32_t b = 0; b < nc; ++b) {
+      if (b == a) continue;
+      const uint64_t b0 = (uint64_t)b * kBatchFitMaxS;
+      const uint32_t len = (uint32_t)(S - b0 < kBatchFitMaxS ? S - b0 : kBatchFitMaxS);
+      pos += bf_rank(g + b0, len, x, b < a);
+    }
+    g2[pos] = x;
+  }
+  __syncthreads();
+  bf_fit_sorted(J, g2, sh, shm);
 }
 
 __global__ __launch_bounds__(kBfThreads) void batch_fit_kernel(const FitJob* __restrict__ jobs, uint32_t njobs,

@@ -278,17 +278,20 @@ def test_batch_matches_oracle_and_replays(env):
 
 
 def test_batch_windows_large_jobs_and_big_buckets(env):
-    """Jobs whose samples are too large for the batched one-block fit (fitted
-    one by one beside the first windows) in the same batch as jobs the batched
-    fit takes; hot keys that make buckets above the LDS caps (the split and
-    gather kernels inside a window); sizes that put several jobs in one window
-    and leave others alone in theirs.  Out of place, then in place."""
+    """Every way a batch fits its models, in one batch: samples sorted in LDS
+    (up to 16384 codes), in two and three LDS chunks merged through global
+    scratch (up to 49152), and a job too large for the batched fit (fitted on
+    its own beside the first windows); hot keys that make buckets above the
+    LDS caps (the split and gather kernels inside a window); sizes that put
+    several jobs in one window and leave others alone in theirs.  Out of place,
+    then in place.  The batched fit's models are those of the per-job fit of
+    the same jobs (same sample draws, same root and leaf formulas)."""
     torch, elsar = env
     rng = np.random.default_rng(35)
-    sizes = [2_100_000, 1_700_000, 1_000_000, 900_000, 600_000, 520_000, 300_000, 120_000, 90_000, 7_000, 4_100,
-             2_049]
-    kinds = ["uniform", "skewed", "skewed", "zipf", "uniform", "skewed", "zipf", "skewed", "uniform", "zipf",
-             "skewed", "uniform"]
+    sizes = [5_200_000, 4_500_000, 2_100_000, 1_700_000, 1_000_000, 900_000, 600_000, 520_000, 300_000, 120_000,
+             90_000, 7_000, 4_100, 2_049]
+    kinds = ["skewed", "zipf", "uniform", "skewed", "skewed", "zipf", "uniform", "skewed", "zipf", "skewed",
+             "uniform", "zipf", "skewed", "uniform"]
     host, dev = _batch_inputs(torch, rng, sizes, kinds, 300)
     want = [oracle.sort_records(h) for h in host]
     outs = [torch.empty_like(d) for d in dev]
@@ -296,6 +299,19 @@ def test_batch_windows_large_jobs_and_big_buckets(env):
     torch.cuda.synchronize()
     for j in range(len(sizes)):
         _assert_same(outs[j].cpu().numpy().reshape(-1, R), want[j])
+    p = elsar.fit_params()
+    for j in (0, 1, 2, 3, 4, 8):
+        bi = elsar.sort_batch_model_info(dev, j, ws, outputs=outs)
+        m = elsar.Model(sizes[j], elsar.fit_params(num_buckets=bi.num_buckets, num_leaves=bi.num_leaves,
+                                                   seed=p.seed + j))
+        m.sample_fit(dev[j])
+        mi = m.info()
+        assert (bi.sample_size, bi.n_fit, bi.kind_used) == (mi.sample_size, sizes[j], 0), j
+        assert abs(bi.root_a1 - mi.root_a1) <= 1e-6 * abs(mi.root_a1), (j, bi.root_a1, mi.root_a1)
+        assert abs(bi.root_a0 - mi.root_a0) <= 1e-6 * max(1.0, abs(mi.root_a0)), (j, bi.root_a0, mi.root_a0)
+        if (bi.root_a0, bi.root_a1) == (mi.root_a0, mi.root_a1):
+            assert bi.max_sample_bucket == mi.max_sample_bucket, j
+        del m
     ws = elsar.sort_batch(dev, None, workspace=ws)  # in place: a new job table, a new recorded graph
     torch.cuda.synchronize()
     for j in range(len(sizes)):
