@@ -678,7 +678,7 @@ std::vector<WinJob> window_descriptors(const elsar_job* jobs, const elsar_fit_pa
         J.mlp = m.ms.M;
         J.eq_leaves = m.ms.leaves;
         J.bound = m.ms.bound;
-        J.knots = m.ms.knots;
+        J.ccells = m.ms.ccells;
         J.cells = m.ms.cells;
       }
       J.offsets = reinterpret_cast<uint64_t*>(w + a);

@@ -48,7 +48,8 @@ struct ModelHeader {   // device-resident root of a fitted model
   // gate's bound lambda + sqrt(2 ln(B) lambda) + 1, lambda = S/B
   uint32_t max_rmi, max_eq, max_net, rmi_ok;
   float perfect;
-  uint32_t pad_[3];
+  uint32_t cell_shift;  // equi-depth leaves: code-cell width 2^cell_shift (code_cell)
+  uint32_t pad_[2];
 };
 
 // Monotone MLP root (8 -> 64 -> 64 -> 1), flat parameter order W1 (64x8),
@@ -212,19 +213,29 @@ __device__ __forceinline__ uint32_t leaf_bucket(const Leaf& lf, uint64_t e) {
 // code knots[i] = bound[(i L) / K] (knots[K] past every code).
 __host__ __device__ __forceinline__ uint32_t spline_segments(uint32_t L) { return L >= 64 ? L / 64 : 1; }
 
-// The leaf j with bound[j] <= code < bound[j+1]: a binary search among the K
-// segment knots (a small table that stays in the L1 cache), then among the
-// segment's own leaves.
-__device__ __forceinline__ uint32_t spline_exact_leaf(const uint64_t* __restrict__ knots, uint32_t K,
-                                                      const uint64_t* __restrict__ bound, uint32_t L,
-                                                      uint64_t code) {
-  uint32_t lo = 0, hi = K;  // knots[lo] <= code < knots[hi]
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (knots[mid] <= code) lo = mid; else hi = mid;
-  }
-  uint32_t a = (uint32_t)(((uint64_t)lo * L) / K), b = (uint32_t)(((uint64_t)(lo + 1) * L) / K);
-  while (b - a > 1) {  // bound[a] <= code < bound[b]
+// Routing to an equi-depth leaf: the last leaf j with bound[j] <= code (leaf
+// 0 below bound[1]).  A table over the code range narrows the search: cell c
+// holds the codes e with (e - bound[1]) >> cell_shift == c (codes at or below
+// bound[1] in cell 0, codes past the last cell in the last), cell_shift the
+// smallest with (bound[L-1] - bound[1]) >> cell_shift < kCodeCells, and
+// ccells[c] counts the boundaries bound[1 .. L-1] in cells below c.  Cells are
+// monotone in the code, so a code of cell c lies in a leaf j with
+// ccells[c] <= j <= ccells[c + 1]: the search covers the leaves whose
+// boundary shares the code's cell (two or three probes on the skewed laws,
+// against about 16 for a search over segment knots then leaves).
+constexpr uint32_t kCodeCells = 1u << 16;
+
+__host__ __device__ __forceinline__ uint32_t code_cell(uint64_t e, uint64_t e0, uint32_t shift) {
+  const uint64_t d = e > e0 ? (e - e0) >> shift : 0ull;
+  return d < kCodeCells ? (uint32_t)d : kCodeCells - 1;
+}
+
+__device__ __forceinline__ uint32_t cell_exact_leaf(const uint32_t* __restrict__ ccells, uint32_t shift,
+                                                    uint64_t e0, const uint64_t* __restrict__ bound,
+                                                    uint64_t code) {
+  const uint32_t c = code_cell(code, e0, shift);
+  uint32_t a = ccells[c], b = ccells[c + 1] + 1;  // bound[a] <= code < bound[b] (bound[L] never read)
+  while (b - a > 1) {
     const uint32_t mid = (a + b) >> 1;
     if (bound[mid] <= code) a = mid; else b = mid;
   }
@@ -360,6 +371,7 @@ struct MlpState {
   uint32_t* hist;    // B: sample keys per bucket under these leaves
   uint32_t* hist_net;  // B: sample keys per bucket of the network's own output, floor(B y)
   uint64_t* knots;   // spline_segments(L) + 1 segment knots of the spline root
+  uint32_t* ccells;  // kCodeCells + 1: the code-cell table that brackets the leaf search
   uint32_t* cells;   // L + 1: cells[c] = leaves whose MLP cell floor(L y(bound[j])) is below c
   float* master;     // kMlpParams FP32 parameters of the MLP
   float* adam;       // 2 * kMlpParams moments
@@ -459,7 +471,7 @@ struct WinJob {
   const MlpBlock* mlp;      // equi-depth roots only (else null): the network,
   const Leaf* eq_leaves;    // the equi-depth leaves and their routing tables
   const uint64_t* bound;
-  const uint64_t* knots;
+  const uint32_t* ccells;   // the spline root's code-cell table
   const uint32_t* cells;
   uint8_t* part;            // partition buffer laid out as lay
   uint64_t* offsets;        // B + 1 output offsets

@@ -77,7 +77,7 @@ __device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const
 
 // The records are read and the slots written with nontemporal loads and
 // stores: they stream through once, and marking them so keeps the routing
-// tables (leaves, boundaries, knots; a few hundred KB) resident in L2, where
+// tables (leaves, boundaries, cell tables; a few hundred KB) resident in L2, where
 // every record's bucket search reads them (the spline root's partition went
 // from 8.6 to 8.0 ms at 100M skewed records, the linear root's from 5.7 to
 // 5.4 ms at 100M uniform ones).
@@ -90,8 +90,9 @@ __device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const
 //
 // ROOT (kind_used of the header): 0 the linear RMI root; 1 the monotone MLP,
 // whose output cell floor(L y) names, through the fit's cell table, a bracket
-// of leaves searched among the routing boundaries; 2 the linear spline over equi-depth leaves, routed by a
-// binary search among its segment knots and then the segment's leaves.  A fit
+// of leaves searched among the routing boundaries; 2 the linear spline over
+// equi-depth leaves, whose leaf is found among the routing boundaries in the
+// bracket of the code's cell (cell_exact_leaf).  A fit
 // that may choose among roots launches a kernel per root; each returns at
 // once unless the header names its own.
 //
@@ -101,7 +102,7 @@ __device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const
 template <int RW_T, int ROOT, bool FILTER>
 __device__ __forceinline__ void partition_body(
     const ModelHeader* __restrict__ hdr, const Leaf* __restrict__ leaves, const MlpBlock* __restrict__ mlp,
-    const uint64_t* __restrict__ bound, const uint64_t* __restrict__ knots, const uint32_t* __restrict__ cells,
+    const uint64_t* __restrict__ bound, const uint32_t* __restrict__ ccells, const uint32_t* __restrict__ cells,
     const uint8_t* __restrict__ recs, uint64_t n, uint32_t rw_rt, uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps,
     const uint32_t* __restrict__ rstart, PartHeader* __restrict__ ph, uint2* __restrict__ spill_meta,
     uint4* __restrict__ slots, uint64_t cap_slots, PassFilter f, uint32_t vk, uint32_t cstride, uint32_t bid,
@@ -115,9 +116,11 @@ __device__ __forceinline__ void partition_body(
   if (hdr->kind_used != (uint32_t)ROOT) return;
   const uint32_t tile_dw = kPartTile * RW;
   const float a0 = hdr->a0, a1 = hdr->a1;
-  const uint32_t L = ROOT ? hdr->mlp_L : hdr->L, K = hdr->spline_K;
+  const uint32_t L = ROOT ? hdr->mlp_L : hdr->L;
   // equi-depth leaves, one per bucket: floor(B * the spline's CDF) is the leaf
   const bool leaf_is_bucket = ROOT != 0 && L == hdr->B;
+  const uint32_t csh = ROOT == 2 ? hdr->cell_shift : 0u;  // the code-cell table of the spline root
+  const uint64_t ce0 = ROOT == 2 && L >= 2 ? bound[1] : 0ull;
   __shared__ typename std::conditional<MLP, MlpHead, uint32_t>::type mh_;
   MlpFrags w2;
   if constexpr (MLP) {
@@ -184,7 +187,7 @@ __device__ __forceinline__ void partition_body(
       uint32_t r0 = r[0], r1 = r[1], r2 = vk ? r[2] : 0u;
       virtual_key(r0, r1, r2, vk);
       uint64_t e = key_code(r0, r1);
-      const uint32_t j = ROOT == 2 ? spline_exact_leaf(knots, K, bound, L, e) : rmi_leaf(a0, a1, L, e);
+      const uint32_t j = ROOT == 2 ? cell_exact_leaf(ccells, csh, ce0, bound, e) : rmi_leaf(a0, a1, L, e);
       b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
     }
     bool keep = threadIdx.x < cnt;
@@ -237,11 +240,11 @@ __device__ __forceinline__ void partition_body(
 template <int RW_T, int ROOT, bool FILTER>
 __global__ __launch_bounds__(kPartThreads) void partition_kernel(
     const ModelHeader* __restrict__ hdr, const Leaf* __restrict__ leaves, const MlpBlock* __restrict__ mlp,
-    const uint64_t* __restrict__ bound, const uint64_t* __restrict__ knots, const uint32_t* __restrict__ cells,
+    const uint64_t* __restrict__ bound, const uint32_t* __restrict__ ccells, const uint32_t* __restrict__ cells,
     const uint8_t* __restrict__ recs, uint64_t n, uint32_t rw_rt, uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps,
     const uint32_t* __restrict__ rstart, PartHeader* __restrict__ ph, uint2* __restrict__ spill_meta,
     uint4* __restrict__ slots, uint64_t cap_slots, PassFilter f, uint32_t vk, uint32_t cstride) {
-  partition_body<RW_T, ROOT, FILTER>(hdr, leaves, mlp, bound, knots, cells, recs, n, rw_rt, counts, caps, rstart, ph,
+  partition_body<RW_T, ROOT, FILTER>(hdr, leaves, mlp, bound, ccells, cells, recs, n, rw_rt, counts, caps, rstart, ph,
                                      spill_meta, slots, cap_slots, f, vk, cstride, blockIdx.x, gridDim.x);
 }
 
@@ -252,7 +255,7 @@ __global__ __launch_bounds__(kPartThreads) void partition_win_kernel(const WinJo
   const WinJob& J = jobs[blockIdx.x / G];
   uint8_t* part = J.part;
   partition_body<RW_T, ROOT, false>(
-      J.hdr, ROOT ? J.eq_leaves : J.leaves, J.mlp, J.bound, J.knots, J.cells, J.recs, J.n, rw_rt,
+      J.hdr, ROOT ? J.eq_leaves : J.leaves, J.mlp, J.bound, J.ccells, J.cells, J.recs, J.n, rw_rt,
       reinterpret_cast<uint32_t*>(part + J.lay.pcounts), reinterpret_cast<const uint32_t*>(part + J.lay.caps),
       reinterpret_cast<const uint32_t*>(part + J.lay.rstart), reinterpret_cast<PartHeader*>(part + J.lay.header),
       reinterpret_cast<uint2*>(part + J.lay.spill_meta), reinterpret_cast<uint4*>(part + J.lay.slots),
@@ -270,16 +273,16 @@ uint32_t partition_grid(uint64_t n) {
 template <int ROOT, bool FILTER>
 static void launch_partition_root(uint32_t grid, size_t lds, hipStream_t st, uint32_t RW, const ModelHeader* hdr,
                                   const Leaf* leaves, const MlpBlock* mlp, const uint64_t* bound,
-                                  const uint64_t* knots, const uint32_t* cells, const uint8_t* recs, uint64_t n,
+                                  const uint32_t* ccells, const uint32_t* cells, const uint8_t* recs, uint64_t n,
                                   uint32_t* counts,
                                   const uint32_t* caps, const uint32_t* rstart, PartHeader* ph, uint2* meta,
                                   uint4* slots, uint64_t cap_slots, PassFilter f, uint32_t vk, uint32_t cstride) {
   if (RW == 25)
-    partition_kernel<25, ROOT, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, knots, cells, recs, n, RW,
+    partition_kernel<25, ROOT, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, ccells, cells, recs, n, RW,
                                                                         counts, caps, rstart, ph, meta, slots,
                                                                         cap_slots, f, vk, cstride);
   else
-    partition_kernel<0, ROOT, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, knots, cells, recs, n, RW,
+    partition_kernel<0, ROOT, FILTER><<<grid, kPartThreads, lds, st>>>(hdr, leaves, mlp, bound, ccells, cells, recs, n, RW,
                                                                        counts, caps, rstart, ph, meta, slots,
                                                                        cap_slots, f, vk, cstride);
 }
@@ -305,7 +308,7 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const Ml
     if (ms) {
       launch_partition_root<1, true>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, nullptr, ms->cells, recs,
                                      n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk, cstride);
-      launch_partition_root<2, true>(grid, lds, st, RW, hdr, ms->leaves, nullptr, ms->bound, ms->knots, nullptr, recs,
+      launch_partition_root<2, true>(grid, lds, st, RW, hdr, ms->leaves, nullptr, ms->bound, ms->ccells, nullptr, recs,
                                      n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk, cstride);
     }
   } else {
@@ -314,7 +317,7 @@ hipError_t launch_partition(const ModelHeader* hdr, const Leaf* leaves, const Ml
     if (ms) {
       launch_partition_root<1, false>(grid, lds, st, RW, hdr, ms->leaves, ms->M, ms->bound, nullptr, ms->cells, recs,
                                       n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk, cstride);
-      launch_partition_root<2, false>(grid, lds, st, RW, hdr, ms->leaves, nullptr, ms->bound, ms->knots, nullptr,
+      launch_partition_root<2, false>(grid, lds, st, RW, hdr, ms->leaves, nullptr, ms->bound, ms->ccells, nullptr,
                                       recs, n, counts, caps, rstart, ph, meta, slots, lay.cap_slots, f, vk, cstride);
     }
   }
@@ -350,7 +353,7 @@ template <int ROOT>
 __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restrict__ hdr,
                                                     const Leaf* __restrict__ leaves, const MlpBlock* __restrict__ mlp,
                                                     const uint64_t* __restrict__ bound,
-                                                    const uint64_t* __restrict__ knots,
+                                                    const uint32_t* __restrict__ ccells,
                                                     const uint32_t* __restrict__ cells, const uint32_t* __restrict__ rec,
                                                     uint64_t n, uint32_t RW, uint32_t* __restrict__ counts,
                                                     uint32_t vk) {
@@ -365,7 +368,9 @@ __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restric
     __syncthreads();
   }
   const float a0 = hdr->a0, a1 = hdr->a1;
-  const uint32_t L = ROOT ? hdr->mlp_L : hdr->L, K = hdr->spline_K;
+  const uint32_t L = ROOT ? hdr->mlp_L : hdr->L;
+  const uint32_t csh = ROOT == 2 ? hdr->cell_shift : 0u;
+  const uint64_t ce0 = ROOT == 2 && L >= 2 ? bound[1] : 0ull;
   const bool leaf_is_bucket = ROOT != 0 && L == hdr->B;
   const uint64_t wave0 = ((uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u));
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -381,7 +386,7 @@ __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restric
       const uint32_t j = mlp_bracket_leaf(bound, cells, L, e, y);
       b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
     } else {
-      const uint32_t j = ROOT == 2 ? spline_exact_leaf(knots, K, bound, L, e) : rmi_leaf(a0, a1, L, e);
+      const uint32_t j = ROOT == 2 ? cell_exact_leaf(ccells, csh, ce0, bound, e) : rmi_leaf(a0, a1, L, e);
       b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
     }
     if (i < n) atomicAdd(&counts[b], 1u);
@@ -398,7 +403,7 @@ hipError_t launch_count(const ModelHeader* hdr, const Leaf* leaves, const MlpSta
   count_kernel<0><<<grid, 256, 0, st>>>(hdr, leaves, nullptr, nullptr, nullptr, nullptr, rec, n, RW, counts, vk);
   if (ms) {
     count_kernel<1><<<grid, 256, 0, st>>>(hdr, ms->leaves, ms->M, ms->bound, nullptr, ms->cells, rec, n, RW, counts, vk);
-    count_kernel<2><<<grid, 256, 0, st>>>(hdr, ms->leaves, nullptr, ms->bound, ms->knots, nullptr, rec, n, RW,
+    count_kernel<2><<<grid, 256, 0, st>>>(hdr, ms->leaves, nullptr, ms->bound, ms->ccells, nullptr, rec, n, RW,
                                           counts, vk);
   }
   return hipGetLastError();
