@@ -125,9 +125,13 @@ elsar_status elsar_fit_workspace_size(const elsar_model* m, uint64_t n, size_t* 
  *
  * kinds MLP, AUTO and SPLINE also cut equi-depth leaves in the sorted
  * sample: leaf j starts at the first sample of the run of equal codes that
- * holds sample floor(j*S/L), and takes the same spline over its ranks.  The
- * spline root groups them in K = L/64 segments whose first codes (knots) it
- * searches.  Kind MLP also trains the monotone MLP root (8 quantile-ramp
+ * holds sample floor(j*S/L), and takes the same spline over its ranks; a run
+ * holding the start samples of several leaves is a leaf of its own (the
+ * first of them covers exactly the run's code, the next starts at that code
+ * + 1), so that a heavily repeated key gets a bucket whose keys are all
+ * equal.  The spline root groups the leaves in K = L/64 segments (knots: the
+ * segments' first boundaries); a record's leaf is found exactly among the
+ * boundaries, in the bracket a table of 65536 code cells gives.  Kind MLP also trains the monotone MLP root (8 quantile-ramp
  * features of the code -> 64 -> 64 -> 1, sigmoid units, non-negative weights;
  * MSE to rank/S on the sample; Adam).  After training, a cell table over the
  * network's output gives, for each of L cells of y, the bracket of leaves

@@ -129,15 +129,51 @@ def pack(P: dict) -> np.ndarray:
     return np.concatenate([np.asarray(P[k], dtype=np.float64).ravel() for k in PARAM_SHAPES])
 
 
+def _after_run(c: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """Leaves whose start sample q[j] lies in the same run of equal codes as
+    the previous leaf's start sample."""
+    a = np.zeros(q.size, dtype=bool)
+    a[1:] = c[q[1:]] == c[q[:-1]]
+    return a
+
+
 def equi_depth_first(sorted_codes: np.ndarray, L: int) -> np.ndarray:
-    """Leaf ranges under the MLP root: leaf j starts at the first sample of the
-    run of equal codes that holds sample floor(j*S/L) (a run of equal keys is
-    never split between leaves); first[L] = S."""
+    """Leaf ranges under the equi-depth roots (MLP and spline): leaf j starts
+    at the first sample of the run of equal codes that holds sample
+    floor(j*S/L), so a run of equal keys is never split between leaves --
+    except that a run holding the start samples of several leaves becomes a
+    leaf of its own: the first of those leaves covers exactly the run, and the
+    others start after it (the run's code then has a bucket to itself, whose
+    keys are all equal).  first[L] = S."""
     c = np.asarray(sorted_codes, dtype=np.uint64)
     S = c.size
     q = (np.arange(L, dtype=np.int64) * S) // L
     first = np.searchsorted(c, c[q], side="left")
+    after = _after_run(c, q)
+    first[after] = np.searchsorted(c, c[q[after]], side="right")
     return np.append(first, S).astype(np.uint64)
+
+
+def equi_depth_bound(sorted_codes: np.ndarray, L: int) -> np.ndarray:
+    """Routing boundaries of those leaves (leaf j takes the codes in
+    [bound[j], bound[j+1])): 0 for leaf 0; the code of the leaf's first sample;
+    for a leaf that starts after a run of code v, v + 1 (so the run's own leaf
+    holds that one code); past every code for a leaf with no samples after
+    it, and for bound[L]."""
+    c = np.asarray(sorted_codes, dtype=np.uint64)
+    S = c.size
+    first = equi_depth_first(c, L).astype(np.int64)
+    q = (np.arange(L, dtype=np.int64) * S) // L
+    after = _after_run(c, q)
+    top = np.iinfo(np.uint64).max
+    bound = np.full(L + 1, top, dtype=np.uint64)
+    for j in range(1, L):
+        if after[j]:
+            bound[j] = c[q[j]] + np.uint64(1)
+        elif first[j] < S:
+            bound[j] = c[first[j]]
+    bound[0] = 0
+    return bound
 
 
 def leaf_guess(y: np.ndarray, L: int) -> np.ndarray:

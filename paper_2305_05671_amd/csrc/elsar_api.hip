@@ -152,6 +152,7 @@ PartLayout part_layout(uint64_t n, uint32_t B, uint32_t R, uint32_t region_pct, 
   lay.spill_off = take((size_t)B * 4);
   lay.mid_list = take((size_t)B * 4);
   lay.big_list = take((size_t)B * 4);
+  lay.big2_list = take((size_t)B * 4);
   lay.spill_meta = take((size_t)n * 8);
   lay.spill_map = take((size_t)n * 4);
   // split of buckets above the LDS caps: every split of c entries gives at most
@@ -990,6 +991,7 @@ PartLayout pass_layout(uint64_t P, uint32_t B, uint32_t R, uint32_t K) {
   lay.spill_off = take((size_t)B * 4);
   lay.mid_list = take((size_t)B * 4);
   lay.big_list = take((size_t)B * 4);
+  lay.big2_list = take((size_t)B * 4);
   lay.spill_meta = take(0);
   lay.spill_map = take(0);
   lay.seg_leaf_cap = (uint32_t)std::min<uint64_t>(P / 32 + 4096, 0xFFFFFFFFull);

@@ -84,12 +84,14 @@ struct PartHeader {    // device-resident state of one partition pass
   uint32_t mid_records;  // records in the n_mid buckets
   uint32_t big_records;  // records in the n_big buckets
   uint32_t seg_n[4];     // split of the n_big buckets: segments, stack overflow flag, spare (2)
-  uint32_t pad[3];
+  uint32_t n_big2;       // of the n_big buckets, those the equal-key kernel leaves to the split
+  uint32_t pad[2];
 };
 
 // Byte offsets of the partition buffer's parts for n records and B buckets.
 struct PartLayout {
   size_t header, counts, caps, rstart, spill_off, mid_list, big_list;
+  size_t big2_list;  // the big buckets left to the split (keys not all equal, or above the equal-key cap)
   // The partition's slot counters: bucket j's at pcounts + 4 * j * cstride.
   // Returning atomics on counters packed 32 to a 128-byte line serialise per
   // line (10^6 of them on 1024 packed counters took 5x as long as on the same

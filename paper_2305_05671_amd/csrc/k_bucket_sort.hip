@@ -646,6 +646,171 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
   bucket_sort_lds_body<CAP, THREADS>(counts, caps, rstart, spill_off, spill_map, slots, cap_slots, offsets, RW, K, out, list, list_n, B, seg_n, vk, blockIdx.x, gridDim.x);
 }
 
+// ------------------------------------------ big buckets of one repeated key --
+// A bucket above the mid cap whose keys are all equal -- a heavily repeated
+// key, which the equi-depth roots give a bucket of its own -- is in order
+// once its records are in input order.  One block per bucket:
+//  1. a probe: the keys of 64 records spread over the bucket, so that a
+//     bucket of different keys is handed on after 64 reads, not n;
+//  2. the 16-byte head of every slot: the key words (checked equal across
+//     the bucket) and the input index, kept in LDS;
+//  3. the positions ordered by index: a counting pass on a digit of the index
+//     scaled over the bucket's index range, then bin_sort_core's per-bin
+//     orderings (the indices of a hot key are spread over the input, so the
+//     bins hold a few entries each);
+//  4. the records copied in that order through an LDS stage, as in the other
+//     bucket sorts.
+// A bucket whose keys differ, or one above kEqCap records, goes on the list
+// the general split takes (list2).
+constexpr uint32_t kEqCap = 16384;
+constexpr uint32_t kEqThreads = 1024;
+constexpr uint32_t kEqBits = 12;  // counting digit: 4096 bins of the index range
+
+__device__ __forceinline__ void equal_keys_body(
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
+    const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
+    const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
+    uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
+    uint32_t* __restrict__ list2, uint32_t* __restrict__ list2_n, uint32_t vk, uint32_t bid, uint32_t nblk) {
+  constexpr uint32_t WAVES = kEqThreads / 64;
+  __shared__ uint32_t idx[kEqCap];  // input index of each position; after the sort, the stage
+  __shared__ uint16_t perm[2][kEqCap];
+  __shared__ uint32_t bins[1u << kEqBits];
+  __shared__ uint4 sh_or[WAVES], sh_and[WAVES];
+  __shared__ uint32_t sh_scan[WAVES + 1];
+  __shared__ uint64_t sh_mm[2 * WAVES];
+  __shared__ uint32_t tot[4];
+  __shared__ uint32_t probe_vary;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t W = slot_bytes_for(RW * 4) / 4;  // slot stride in dwords
+  const uint32_t SC = W / 4, LC = (RW + 1 + 3) / 4;
+  const uint32_t key_mask = (1u << K) - 1u;        // composite bytes of the key
+  const uint32_t nitems = *list_n;
+  for (uint32_t it = bid; it < nitems; it += nblk) {
+    const uint32_t j = list[it];
+    BucketRef br;
+    br.n = counts[j];
+    const uint32_t n = br.n;
+    const uint32_t cap = caps[j];
+    br.nr = n < cap ? n : cap;
+    br.rs = rstart[j];
+    br.so = spill_off[j];
+    br.out0 = offsets[j];
+    // 1. the probe (wave 0)
+    if (tid < 64) {
+      const uint32_t p = (uint32_t)(((uint64_t)tid * n) / 64);
+      uint4 c = composite(slots + (uint64_t)slot_of(br, p, spill_map, cap_slots) * W, K, vk), o = c, a = c;
+      for (int off = 32; off > 0; off >>= 1) {
+        o.x |= __shfl_xor(o.x, off); o.y |= __shfl_xor(o.y, off);
+        o.z |= __shfl_xor(o.z, off); o.w |= __shfl_xor(o.w, off);
+        a.x &= __shfl_xor(a.x, off); a.y &= __shfl_xor(a.y, off);
+        a.z &= __shfl_xor(a.z, off); a.w &= __shfl_xor(a.w, off);
+      }
+      if (tid == 0) probe_vary = vary_mask(make_uint4(o.x ^ a.x, o.y ^ a.y, o.z ^ a.z, o.w ^ a.w)) & key_mask;
+    }
+    __syncthreads();
+    const bool probe_differs = probe_vary != 0;
+    __syncthreads();  // probe_vary is read before the next bucket's probe writes it
+    if (probe_differs || n > kEqCap) {
+      if (tid == 0) list2[atomicAdd(list2_n, 1u)] = j;
+      continue;
+    }
+    // 2. heads: the key words (OR / AND across the bucket), the indices and their range
+    uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
+    uint64_t imin = ~0ull, imax = 0;
+    for (uint32_t p = tid; p < n; p += kEqThreads) {
+      const uint32_t* sl = slots + (uint64_t)slot_of(br, p, spill_map, cap_slots) * W;
+      const uint4 c = composite(sl, K, vk);
+      o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
+      a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+      const uint32_t x = sl[0];
+      idx[p] = x;
+      imin = x < imin ? x : imin;
+      imax = x > imax ? x : imax;
+    }
+    const uint32_t vary = vary_mask(block_diff<kEqThreads>(o, a, sh_or, sh_and));  // syncs
+    if (vary & key_mask) {  // the keys differ after all: the general split takes the bucket
+      if (tid == 0) list2[atomicAdd(list2_n, 1u)] = j;
+      continue;
+    }
+    block_min_max_u64<kEqThreads>(imin, imax, sh_mm);
+    // 3. positions in index order: the digit (index - min) * 2^kEqBits / (max - min + 1)
+    const double scale = (double)(1u << kEqBits) / ((double)(imax - imin) + 1.0);
+    for (uint32_t i = tid; i < (1u << kEqBits); i += kEqThreads) bins[i] = 0;
+    for (uint32_t p = tid; p < n; p += kEqThreads) {
+      const uint32_t d = (uint32_t)((double)(idx[p] - (uint32_t)imin) * scale);
+      perm[1][p] = (uint16_t)(d < (1u << kEqBits) ? d : (1u << kEqBits) - 1);
+    }
+    const uint32_t span = (uint32_t)(imax ^ imin);  // index bytes that can differ (big-endian positions 0..3)
+    uint32_t ivary = 0;
+    for (uint32_t pb = 0; pb < 4; ++pb) ivary |= (uint32_t)((span >> (24 - 8 * pb)) != 0) << pb;
+    auto less = [&](uint32_t x, uint32_t y) -> bool { return idx[x] < idx[y]; };
+    auto byte_of = [&](uint32_t e, uint32_t pb) -> uint32_t { return (idx[e] >> (24 - 8 * pb)) & 0xFFu; };
+    const uint32_t cur = bin_sort_core<kEqCap, kEqThreads, kEqBits>(n, ivary, perm, bins, sh_scan, tot, less, byte_of);
+    __syncthreads();
+    // 4. the records in that order, through the stage (the index area, free now)
+    uint32_t* stage = idx;
+    const uint32_t kStage = kEqCap / RW;  // records per round
+    const u32x4* s4 = reinterpret_cast<const u32x4*>(slots);
+    for (uint32_t r0 = 0; r0 < n; r0 += kStage) {
+      const uint32_t m = n - r0 < kStage ? n - r0 : kStage;
+      const uint32_t nq = m * LC;
+      __syncthreads();  // the previous round's stretch is read
+      for (uint32_t q0 = 0; q0 < nq; q0 += kSmGroup * kEqThreads) {
+        u32x4 g[kSmGroup];
+#pragma unroll
+        for (uint32_t i = 0; i < kSmGroup; ++i) {
+          const uint32_t q = q0 + tid + i * kEqThreads;
+          const uint32_t qq = q < nq ? q : nq - 1;
+          const uint32_t k = qq / LC, c = qq - k * LC;
+          g[i] = __builtin_nontemporal_load(s4 + (uint64_t)slot_of(br, perm[cur][r0 + k], spill_map, cap_slots) * SC +
+                                            c);
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < kSmGroup; ++i) {
+          const uint32_t q = q0 + tid + i * kEqThreads;
+          if (q < nq) {
+            const uint32_t k = q / LC, c = q - k * LC;
+#pragma unroll
+            for (uint32_t t = 0; t < 4; ++t) {
+              const uint32_t sd = 4 * c + t;  // slot dword: 0 is the index, 1..RW the record
+              if (sd >= 1 && sd <= RW) stage[k * RW + sd - 1] = g[i][t];
+            }
+          }
+        }
+      }
+      __syncthreads();
+      const uint64_t gb = (br.out0 + r0) * RW;  // first output dword of the stretch
+      const uint32_t total = m * RW;
+      uint32_t head = (uint32_t)((32u - (uint32_t)(gb & 31u)) & 31u);
+      if (head > total) head = total;
+      const uint32_t lines = (total - head) / 32;
+      if (tid < head) out[gb + tid] = stage[tid];
+      for (uint32_t v = tid; v < lines * 8; v += kEqThreads) {
+        const uint32_t s0 = head + 4 * v;
+        u32x4 x;
+        x[0] = stage[s0];
+        x[1] = stage[s0 + 1];
+        x[2] = stage[s0 + 2];
+        x[3] = stage[s0 + 3];
+        __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(out + gb + head) + v);
+      }
+      for (uint32_t t = head + lines * 32 + tid; t < total; t += kEqThreads) out[gb + t] = stage[t];
+    }
+    __syncthreads();  // the stage is read before the next bucket's indices overwrite it
+  }
+}
+
+__global__ __launch_bounds__(kEqThreads) void equal_keys_kernel(
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
+    const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
+    const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
+    uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
+    uint32_t* __restrict__ list2, uint32_t* __restrict__ list2_n, uint32_t vk) {
+  equal_keys_body(counts, caps, rstart, spill_off, spill_map, slots, cap_slots, offsets, RW, K, out, list, list_n,
+                  list2, list2_n, vk, blockIdx.x, gridDim.x);
+}
+
 // ------------------------------------------------ buckets above the LDS cap --
 constexpr uint32_t kBigThreads = 1024;
 constexpr uint32_t kBigWaves = kBigThreads / 64;
@@ -1459,25 +1624,29 @@ hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32
   bucket_sort_lds_kernel<kMidCap, 512><<<grid_for(n, kSmallCap + 1, 256), 512, 0, st>>>(
       a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
       reinterpret_cast<const uint32_t*>(part + lay.mid_list), &a.ph->n_mid, B, nullptr, vk);
-  const uint32_t* big_list = reinterpret_cast<const uint32_t*>(part + lay.big_list);
+  PartHeader* ph = reinterpret_cast<PartHeader*>(part + lay.header);
+  // buckets of one repeated key first; the others go on to big2
+  uint32_t* big2 = reinterpret_cast<uint32_t*>(part + lay.big2_list);
+  equal_keys_kernel<<<grid_for(n, kMidCap + 1, 256), kEqThreads, 0, st>>>(
+      a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
+      reinterpret_cast<const uint32_t*>(part + lay.big_list), &a.ph->n_big, big2, &ph->n_big2, vk);
   if (rec_bytes < 64) {  // too little room for the split's buffers, stack and reference list
     bucket_sort_global_kernel<<<grid_for(n, kMidCap + 1, 256), kBigThreads, 0, st>>>(
         a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
-        big_list, &a.ph->n_big, vk);
+        big2, &ph->n_big2, vk);
     return hipGetLastError();
   }
-  PartHeader* ph = reinterpret_cast<PartHeader*>(part + lay.header);
   uint4* leaf = reinterpret_cast<uint4*>(part + lay.seg_leaf);
   uint32_t* leaf_n = &ph->seg_n[0];
   const uint32_t leaf_cap = lay.seg_leaf_cap;
   // the split's counters (ph->seg_n) were cleared by the small-bucket kernel
   msd_split_kernel<<<grid_for(n, kMidCap + 1, 512), kMsdThreads, 0, st>>>(
-      a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out, big_list,
-      &a.ph->n_big, leaf, leaf_n, leaf_cap, &ph->seg_n[1], vk);
+      a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out, big2,
+      &ph->n_big2, leaf, leaf_n, leaf_cap, &ph->seg_n[1], vk);
   seg_sort_kernel<<<grid_for(n, 1024, 2048), kSmThreads, 0, st>>>(a.counts, offsets, a.RW, a.out, leaf, leaf_n,
                                                                    leaf_cap);
   big_gather_kernel<<<grid_for(n, kMidCap + 1, 512), kMsdThreads, 0, st>>>(
-      a.counts, offsets, a.RW, reinterpret_cast<const uint4*>(a.slots), a.out, big_list, &a.ph->n_big);
+      a.counts, offsets, a.RW, reinterpret_cast<const uint4*>(a.slots), a.out, big2, &ph->n_big2);
   return hipGetLastError();
 }
 
@@ -1539,13 +1708,23 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_win_kernel(const WinJ
                                      blockIdx.x % G, G);
 }
 
+__global__ __launch_bounds__(kEqThreads) void equal_keys_win_kernel(const WinJob* __restrict__ jobs, uint32_t G,
+                                                                    uint32_t RW, uint32_t K) {
+  const WinJob& J = jobs[blockIdx.x / G];
+  const WinRefs r = win_refs(J);
+  equal_keys_body(r.counts, r.caps, r.rstart, r.soff, r.smap, r.slots, J.lay.cap_slots, J.offsets, RW, K,
+                  reinterpret_cast<uint32_t*>(J.out), reinterpret_cast<const uint32_t*>(J.part + J.lay.big_list),
+                  &r.ph->n_big, reinterpret_cast<uint32_t*>(J.part + J.lay.big2_list), &r.ph->n_big2, 0u,
+                  blockIdx.x % G, G);
+}
+
 __global__ __launch_bounds__(kBigThreads) void bucket_sort_global_win_kernel(const WinJob* __restrict__ jobs,
                                                                              uint32_t G, uint32_t RW, uint32_t K) {
   const WinJob& J = jobs[blockIdx.x / G];
   const WinRefs r = win_refs(J);
   bucket_sort_global_body(r.counts, r.caps, r.rstart, r.soff, r.smap, r.slots, J.lay.cap_slots, J.offsets, RW, K,
-                          reinterpret_cast<uint32_t*>(J.out), reinterpret_cast<const uint32_t*>(J.part + J.lay.big_list),
-                          &r.ph->n_big, 0u, blockIdx.x % G, G);
+                          reinterpret_cast<uint32_t*>(J.out), reinterpret_cast<const uint32_t*>(J.part + J.lay.big2_list),
+                          &r.ph->n_big2, 0u, blockIdx.x % G, G);
 }
 
 __global__ __launch_bounds__(kMsdThreads) void msd_split_win_kernel(const WinJob* __restrict__ jobs, uint32_t G,
@@ -1553,8 +1732,8 @@ __global__ __launch_bounds__(kMsdThreads) void msd_split_win_kernel(const WinJob
   const WinJob& J = jobs[blockIdx.x / G];
   const WinRefs r = win_refs(J);
   msd_split_body(r.counts, r.caps, r.rstart, r.soff, r.smap, r.slots, J.lay.cap_slots, J.offsets, RW, K,
-                 reinterpret_cast<uint32_t*>(J.out), reinterpret_cast<const uint32_t*>(J.part + J.lay.big_list),
-                 &r.ph->n_big, reinterpret_cast<uint4*>(J.part + J.lay.seg_leaf), &r.ph->seg_n[0], J.lay.seg_leaf_cap,
+                 reinterpret_cast<uint32_t*>(J.out), reinterpret_cast<const uint32_t*>(J.part + J.lay.big2_list),
+                 &r.ph->n_big2, reinterpret_cast<uint4*>(J.part + J.lay.seg_leaf), &r.ph->seg_n[0], J.lay.seg_leaf_cap,
                  &r.ph->seg_n[1], 0u, blockIdx.x % G, G);
 }
 
@@ -1572,7 +1751,7 @@ __global__ __launch_bounds__(kMsdThreads) void big_gather_win_kernel(const WinJo
   const WinJob& J = jobs[blockIdx.x / G];
   const WinRefs r = win_refs(J);
   big_gather_body(r.counts, J.offsets, RW, reinterpret_cast<const uint4*>(r.slots), reinterpret_cast<uint32_t*>(J.out),
-                  reinterpret_cast<const uint32_t*>(J.part + J.lay.big_list), &r.ph->n_big, blockIdx.x % G, G);
+                  reinterpret_cast<const uint32_t*>(J.part + J.lay.big2_list), &r.ph->n_big2, blockIdx.x % G, G);
 }
 
 hipError_t launch_bucket_sort_small_win(const WinJob* jobs, uint32_t njobs, uint32_t G, uint32_t rec_bytes,
@@ -1590,6 +1769,8 @@ hipError_t launch_bucket_sort_large_win(const WinJob* jobs, uint32_t njobs, cons
   if (njobs == 0) return hipSuccess;
   const uint32_t RW = rec_bytes / 4;
   bucket_sort_lds_win_kernel<kMidCap, 512, true><<<njobs * g.mid, 512, 0, st>>>(jobs, g.mid, RW, key_bytes);
+  // buckets of one repeated key first (as many blocks per job as the mid sort)
+  equal_keys_win_kernel<<<njobs * g.mid, kEqThreads, 0, st>>>(jobs, g.mid, RW, key_bytes);
   if (rec_bytes < 64) {  // too little room for the split's buffers, stack and reference list
     const uint32_t G = g.split < 256 ? g.split : 256;
     bucket_sort_global_win_kernel<<<njobs * G, kBigThreads, 0, st>>>(jobs, G, RW, key_bytes);

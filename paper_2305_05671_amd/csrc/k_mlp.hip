@@ -495,6 +495,17 @@ __global__ __launch_bounds__(256) void quantile_first_kernel(const uint64_t* __r
   }
   const uint64_t q = ((uint64_t)j * S) / L;
   const uint64_t c = e[q];
+  if (j > 0 && e[((uint64_t)(j - 1) * S) / L] == c) {
+    // the previous leaf's start lies in the same run: that leaf takes the
+    // run alone, this one starts after it (the first position past c)
+    uint64_t lo = q + 1, hi = S;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (e[mid] <= c) lo = mid + 1; else hi = mid;
+    }
+    first[j] = (uint32_t)lo;
+    return;
+  }
   uint64_t lo = 0, hi = q;  // the first position holding c; e[hi] == c
   while (lo < hi) {
     const uint64_t mid = (lo + hi) >> 1;
@@ -506,7 +517,9 @@ __global__ __launch_bounds__(256) void quantile_first_kernel(const uint64_t* __r
 // Leaf j covers samples first[j] .. first[j+1]-1: the same two-point spline
 // and bucket range as a leaf of the linear root.  bound[j] = code of the
 // leaf's first sample (0 for leaf 0; past every code for leaves after the
-// last sample); bound[L] is past every code.
+// last sample); for a leaf that starts after a run of equal codes v (its
+// start sample shares the previous leaf's run), v + 1, so that the run's own
+// leaf holds exactly the code v; bound[L] is past every code.
 __global__ __launch_bounds__(256) void mlp_leaf_fit_kernel(const uint64_t* __restrict__ e, uint64_t S, uint32_t L,
                                                            uint32_t B, const uint32_t* __restrict__ first,
                                                            Leaf* __restrict__ leaves, uint64_t* __restrict__ bound,
@@ -516,7 +529,9 @@ __global__ __launch_bounds__(256) void mlp_leaf_fit_kernel(const uint64_t* __res
   if (j == 0) bound[L] = ~0ull;
   if (j >= L) return;
   const uint64_t f = first[j], gg = first[j + 1];
-  bound[j] = j == 0 ? 0ull : (f < S ? e[f] : ~0ull);
+  const uint64_t cq = e[((uint64_t)j * S) / L];
+  const bool after_run = j > 0 && e[((uint64_t)(j - 1) * S) / L] == cq;
+  bound[j] = j == 0 ? 0ull : (after_run ? cq + 1 : (f < S ? e[f] : ~0ull));
   Leaf lf;
   lf.pad[0] = lf.pad[1] = 0;
   if (f >= gg) {

@@ -474,6 +474,7 @@ __global__ __launch_bounds__(kExThreads) void exact_regions_kernel(const uint32_
     ph->spill_count = 0;
     ph->n_mid = 0;
     ph->n_big = 0;
+    ph->n_big2 = 0;
     ph->max_count = 0;
     ph->mid_records = 0;
     ph->big_records = 0;

@@ -136,10 +136,9 @@ def test_fitted_mlp_model(env, kind, n, B, seed):
     base, c, b, lo, hi = m.leaves()
     assert np.array_equal(base, ref.base) and np.array_equal(c, ref.c) and np.array_equal(b, ref.b)
     assert np.array_equal(lo, ref.lo) and np.array_equal(hi, ref.hi)
-    # boundaries: the code of each leaf's first sample
-    assert bound[0] == 0 and bound[L] == np.iinfo(np.uint64).max
-    has = first[1:L] < S
-    assert np.array_equal(bound[1:L][has], codes[first[1:L][has]])
+    # boundaries: the code of each leaf's first sample, one past a run's code
+    # for a leaf that starts after it
+    assert np.array_equal(bound, mlp.equi_depth_bound(codes, L))
     # the trained root tracks the empirical CDF, so its guesses land near the
     # sample's own leaf
     y = mlp.forward(_P64(params), mlp.features(codes, q, w), bf16_layer2=True)["y"]

@@ -60,9 +60,7 @@ def test_fitted_spline_model(env, kind, n, B, leaves, seed):
     assert np.array_equal(base, ref.base) and np.array_equal(c, ref.c) and np.array_equal(b, ref.b)
     assert np.array_equal(lo, ref.lo) and np.array_equal(hi, ref.hi)
     S = codes.size
-    assert bound[0] == 0 and bound[L] == np.iinfo(np.uint64).max
-    has = first[1:L] < S
-    assert np.array_equal(bound[1:L][has], codes[first[1:L][has]])
+    assert np.array_equal(bound, mlp.equi_depth_bound(codes, L))
     assert np.array_equal(knots, bound[(np.arange(K + 1, dtype=np.int64) * L) // K])
     # counts bit-exact under exact routing among the boundaries: with one leaf
     # per bucket the leaf is the bucket, otherwise the leaf's line gives it
@@ -100,14 +98,49 @@ def test_spline_edge_sizes(env, n):
 
 
 def test_spline_all_equal_keys(env):
-    # one run of equal codes: every leaf start moves back to sample 0
+    # one run of equal codes holding every leaf start: leaf 0 takes the whole
+    # run, every other leaf starts after it (empty), at the code + 1
     torch, elsar = env
     recs = datagen.generate(datagen.spec("uniform", seed=9), 50_000)
     recs[:, :10] = np.frombuffer(b"SAMEKEY123", dtype=np.uint8)
     m, part, offsets, d = _fit(env, recs, num_buckets=256, seed=9, kind=elsar.SPLINE)
     knots, bound, first = m.spline()
-    assert np.all(first[:-1] == 0)
+    codes = oracle.sample_codes(recs, seed=9)
+    L = first.size - 1
+    assert first[0] == 0 and np.all(first[1:] == codes.size)
+    assert np.array_equal(first.astype(np.uint64), mlp.equi_depth_first(codes, L))
+    assert np.array_equal(bound, mlp.equi_depth_bound(codes, L))
     out = torch.empty_like(d)
     m.sort_buckets(part, offsets, recs.shape[0], out)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs))
+
+
+@pytest.mark.parametrize("n_hot,kind_name,key_bytes", [
+    (10, "SPLINE", 10),   # ten hot keys of about 10^4 records: buckets of one key, sorted by input index
+    (2, "SPLINE", 10),    # two of about 5 * 10^4: above that kernel's cap, the general split takes them
+    (10, "RMI", 10),      # the linear root: big buckets of different keys, handed on after the probe
+    (10, "SPLINE", 16),   # keys past 12 bytes: runs of equal 12-byte prefixes finished by the fix-up
+])
+def test_hot_key_buckets(env, n_hot, kind_name, key_bytes):
+    """Heavily repeated keys: under the equi-depth roots each hot key's run of
+    sample codes is a leaf (and a bucket) of its own, so its bucket holds that
+    one key; the sort is byte-exact whichever kernel takes a big bucket."""
+    torch, elsar = env
+    n = 1_000_000
+    recs = datagen.generate(datagen.spec("skewed", seed=40 + n_hot, n_hot=n_hot, key_bytes=key_bytes), n)
+    m, part, offsets, d = _fit(env, recs, num_buckets=1024, seed=41, kind=getattr(elsar, kind_name),
+                               key_bytes=key_bytes)
+    st = m.partition_stats(part)
+    assert st.big_buckets >= n_hot
+    if kind_name == "SPLINE":
+        # one bucket per hot key holds exactly that key's records
+        hot = oracle.e8_records(recs)
+        vals, cnt = np.unique(hot, return_counts=True)
+        top = np.sort(cnt)[::-1][:n_hot]
+        assert st.max_bucket == top[0]
+    out = torch.empty_like(d)
+    m.sort_buckets(part, offsets, n, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs, key_bytes))
+

@@ -180,11 +180,45 @@ def test_bf16_backward_close_to_fp64():
 
 
 def test_equi_depth_first_worked_example():
-    # S = 8, L = 4: leaf j would start at sample 2j; the starts at samples 2
-    # (code 1) and 4 (code 3) move back to the first sample of their run, so the
-    # run of three 1s is not split and leaf 1 comes out empty
+    # S = 8, L = 4: leaf j would start at sample 2j.  Samples 0 and 2 lie in
+    # the same run (three 1s): leaf 0 takes exactly that run and leaf 1 starts
+    # after it, at the 2 (boundary 1 + 1 = 2); the start at sample 4 (code 3)
+    # moves back to the first sample of its run
     codes = np.array([1, 1, 1, 2, 3, 3, 4, 5], dtype=np.uint64)
-    assert list(mlp.equi_depth_first(codes, 4)) == [0, 0, 4, 6, 8]
+    assert list(mlp.equi_depth_first(codes, 4)) == [0, 3, 4, 6, 8]
+    top = np.iinfo(np.uint64).max
+    assert list(mlp.equi_depth_bound(codes, 4)) == [0, 2, 3, 4, top]
+    # a run holding three starts: its first leaf takes it, the next one is empty
+    codes = np.array([7, 9, 9, 9, 9, 9, 9, 12], dtype=np.uint64)
+    assert list(mlp.equi_depth_first(codes, 4)) == [0, 1, 7, 7, 8]
+    assert list(mlp.equi_depth_bound(codes, 4)) == [0, 9, 10, 10, top]
+
+
+def test_equi_depth_samples_route_to_their_own_leaf():
+    # through the boundaries (last j with bound[j] <= code), every sample
+    # reaches the leaf whose range holds it; a run that holds several leaf
+    # starts is a leaf of its own
+    rng = np.random.default_rng(23)
+    for trial in range(40):
+        S = int(rng.integers(1, 500))
+        L = int(rng.integers(1, 80))
+        hi = int(rng.choice([4, 30, 10**9]))
+        codes = np.sort(rng.integers(0, hi, size=S)).astype(np.uint64)
+        f = mlp.equi_depth_first(codes, L).astype(np.int64)
+        bound = mlp.equi_depth_bound(codes, L)
+        assert f[0] == 0 and f[-1] == S and np.all(np.diff(f) >= 0)
+        routed = np.searchsorted(bound[:L], codes, side="right") - 1
+        own = np.searchsorted(f[:L], np.arange(S), side="right") - 1
+        assert np.array_equal(routed, own)
+        q = (np.arange(L) * S) // L
+        for j in range(1, L):
+            if codes[q[j]] == codes[q[j - 1]]:
+                k = j - 1
+                while k > 0 and codes[q[k - 1]] == codes[q[j]]:
+                    k -= 1
+                rs = int(np.searchsorted(codes, codes[q[j]], side="left"))
+                re = int(np.searchsorted(codes, codes[q[j]], side="right"))
+                assert f[k] == (rs if k > 0 else 0) and f[k + 1] == re  # the run's own leaf
 
 
 def test_equi_depth_first_properties():
@@ -192,19 +226,25 @@ def test_equi_depth_first_properties():
     for trial in range(20):
         S = int(rng.integers(1, 400))
         L = int(rng.integers(1, 70))
-        # distinct codes: the starts are exactly floor(j S / L)
+        # distinct codes: the starts are exactly floor(j S / L), one past it
+        # where two leaves would start at the same sample (S < L)
         codes = np.sort(rng.choice(10**9, size=S, replace=False)).astype(np.uint64)
         f = mlp.equi_depth_first(codes, L)
-        assert list(f) == [(j * S) // L for j in range(L)] + [S]
-        # many equal codes: every start is a run start, at or before floor(j S / L),
-        # and no run straddles two leaves
+        q = [(j * S) // L for j in range(L)]
+        assert list(f) == [q[j] + (1 if j and q[j] == q[j - 1] else 0) for j in range(L)] + [S]
+        # many equal codes: every start is a run start (at or before
+        # floor(j S / L), or the end of the previous leaf's run), and no run
+        # straddles two leaves
         codes = np.sort(rng.integers(0, 6, size=S)).astype(np.uint64)
         f = mlp.equi_depth_first(codes, L).astype(np.int64)
         assert f[-1] == S and np.all(np.diff(f) >= 0)
         for j in range(L):
             q = (j * S) // L
-            assert f[j] <= q and codes[f[j]] == codes[q]
-            assert f[j] == 0 or codes[f[j] - 1] != codes[f[j]]
+            if j and codes[(j - 1) * S // L] == codes[q]:
+                assert f[j] == np.searchsorted(codes, codes[q], side="right")
+            else:
+                assert f[j] <= q and codes[f[j]] == codes[q]
+            assert f[j] == 0 or f[j] == S or codes[f[j] - 1] != codes[f[j]]
 
 
 def test_spline_leaves_exact_on_linear_codes():
