@@ -216,26 +216,32 @@ __device__ __forceinline__ uint32_t leaf_bucket(const Leaf& lf, uint64_t e) {
 __host__ __device__ __forceinline__ uint32_t spline_segments(uint32_t L) { return L >= 64 ? L / 64 : 1; }
 
 // Routing to an equi-depth leaf: the last leaf j with bound[j] <= code (leaf
-// 0 below bound[1]).  A table over the code range narrows the search: cell c
-// holds the codes e with (e - bound[1]) >> cell_shift == c (codes at or below
-// bound[1] in cell 0, codes past the last cell in the last), cell_shift the
-// smallest with (bound[L-1] - bound[1]) >> cell_shift < kCodeCells, and
-// ccells[c] counts the boundaries bound[1 .. L-1] in cells below c.  Cells are
-// monotone in the code, so a code of cell c lies in a leaf j with
-// ccells[c] <= j <= ccells[c + 1]: the search covers the leaves whose
-// boundary shares the code's cell (two or three probes on the skewed laws,
-// against about 16 for a search over segment knots then leaves).
-constexpr uint32_t kCodeCells = 1u << 16;
+// 0 below bound[1]).  A table over the code range narrows the search: with NC
+// cells (code_cells_for(L)), cell c holds the codes e with
+// (e - bound[1]) >> cell_shift == c (codes at or below bound[1] in cell 0,
+// codes past the last cell in the last), cell_shift the smallest with
+// (bound[L-1] - bound[1]) >> cell_shift < NC, and ccells[c] counts the
+// boundaries bound[1 .. L-1] in cells below c.  Cells are monotone in the
+// code, so a code of cell c lies in a leaf j with ccells[c] <= j <=
+// ccells[c + 1]: the search covers the boundaries that share the code's cell.
+// With about four cells per leaf most cells hold no boundary and the table
+// read alone names the leaf (against about 16 probes for a search over
+// segment knots then leaves).
+__host__ __device__ __forceinline__ uint32_t code_cells_for(uint32_t L) {
+  uint32_t nc = 1024;
+  while (nc < 4u * L && nc < (1u << 18)) nc <<= 1;
+  return nc;
+}
 
-__host__ __device__ __forceinline__ uint32_t code_cell(uint64_t e, uint64_t e0, uint32_t shift) {
+__host__ __device__ __forceinline__ uint32_t code_cell(uint64_t e, uint64_t e0, uint32_t shift, uint32_t nc) {
   const uint64_t d = e > e0 ? (e - e0) >> shift : 0ull;
-  return d < kCodeCells ? (uint32_t)d : kCodeCells - 1;
+  return d < nc ? (uint32_t)d : nc - 1;
 }
 
 __device__ __forceinline__ uint32_t cell_exact_leaf(const uint32_t* __restrict__ ccells, uint32_t shift,
-                                                    uint64_t e0, const uint64_t* __restrict__ bound,
+                                                    uint32_t nc, uint64_t e0, const uint64_t* __restrict__ bound,
                                                     uint64_t code) {
-  const uint32_t c = code_cell(code, e0, shift);
+  const uint32_t c = code_cell(code, e0, shift, nc);
   uint32_t a = ccells[c], b = ccells[c + 1] + 1;  // bound[a] <= code < bound[b] (bound[L] never read)
   while (b - a > 1) {
     const uint32_t mid = (a + b) >> 1;
@@ -373,7 +379,7 @@ struct MlpState {
   uint32_t* hist;    // B: sample keys per bucket under these leaves
   uint32_t* hist_net;  // B: sample keys per bucket of the network's own output, floor(B y)
   uint64_t* knots;   // spline_segments(L) + 1 segment knots of the spline root
-  uint32_t* ccells;  // kCodeCells + 1: the code-cell table that brackets the leaf search
+  uint32_t* ccells;  // code_cells_for(L) + 1: the code-cell table that brackets the leaf search
   uint32_t* cells;   // L + 1: cells[c] = leaves whose MLP cell floor(L y(bound[j])) is below c
   float* master;     // kMlpParams FP32 parameters of the MLP
   float* adam;       // 2 * kMlpParams moments

@@ -32,7 +32,7 @@ inline size_t al(size_t x) { return (x + kA - 1) & ~(kA - 1); }
 
 size_t mlp_state_bytes(uint32_t L, uint32_t B) {
   return al(sizeof(MlpBlock)) + al((size_t)L * sizeof(Leaf)) + al(((size_t)L + 1) * 8) + al(((size_t)L + 1) * 4) +
-         2 * al((size_t)B * 4) + al(((size_t)spline_segments(L) + 1) * 8) + al(((size_t)kCodeCells + 1) * 4) +
+         2 * al((size_t)B * 4) + al(((size_t)spline_segments(L) + 1) * 8) + al(((size_t)code_cells_for(L) + 1) * 4) +
          al(((size_t)L + 1) * 4) +
          al((size_t)kMlpParams * 4) + al((size_t)kMlpParams * 8);
 }
@@ -54,7 +54,7 @@ void place_mlp_state(MlpState* s, void* base, uint32_t L, uint32_t B) {
   s->knots = reinterpret_cast<uint64_t*>(b);
   b += al(((size_t)spline_segments(L) + 1) * 8);
   s->ccells = reinterpret_cast<uint32_t*>(b);
-  b += al(((size_t)kCodeCells + 1) * 4);
+  b += al(((size_t)code_cells_for(L) + 1) * 4);
   s->cells = reinterpret_cast<uint32_t*>(b);
   b += al(((size_t)L + 1) * 4);
   s->master = reinterpret_cast<float*>(b);
@@ -571,14 +571,15 @@ __global__ __launch_bounds__(256) void code_cell_kernel(const uint64_t* __restri
   if (hdr->mlp_skip) return;
   const uint64_t e0 = L >= 2 ? bound[1] : 0ull, range = L >= 2 ? bound[L - 1] - e0 : 0ull;
   uint32_t shift = 0;
-  while ((range >> shift) >= kCodeCells) ++shift;
+  const uint32_t nc = code_cells_for(L);
+  while ((range >> shift) >= nc) ++shift;
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c == 0) hdr->cell_shift = shift;
-  if (c > kCodeCells) return;
+  if (c > nc) return;
   uint32_t lo = 1, hi = L > 0 ? L : 1;  // first j in [1, L) whose cell is >= c (hi if none)
   while (lo < hi) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (code_cell(bound[mid], e0, shift) < c) lo = mid + 1;
+    if (code_cell(bound[mid], e0, shift, nc) < c) lo = mid + 1;
     else hi = mid;
   }
   ccells[c] = lo - 1;
@@ -826,7 +827,7 @@ hipError_t launch_equi_depth_leaves(const uint64_t* e, uint64_t S, uint32_t L, u
   quantile_first_kernel<<<(L + 1 + 255) / 256, 256, 0, st>>>(e, S, L, ms.first, hdr);
   mlp_leaf_fit_kernel<<<(L + 255) / 256, 256, 0, st>>>(e, S, L, B, ms.first, ms.leaves, ms.bound, hdr);
   spline_knots_kernel<<<(K + 1 + 255) / 256, 256, 0, st>>>(ms.bound, L, K, ms.knots, hdr);
-  code_cell_kernel<<<(kCodeCells + 1 + 255) / 256, 256, 0, st>>>(ms.bound, L, ms.ccells, hdr);
+  code_cell_kernel<<<(code_cells_for(L) + 1 + 255) / 256, 256, 0, st>>>(ms.bound, L, ms.ccells, hdr);
   hipError_t err = launch_fill_u32(ms.hist, B, 0u, st);
   if (err != hipSuccess) return err;
   mlp_sample_stats_kernel<<<(uint32_t)((S + 255) / 256), 256, 0, st>>>(e, S, L, B, ms.first, ms.leaves, ms.hist,

@@ -120,6 +120,7 @@ __device__ __forceinline__ void partition_body(
   // equi-depth leaves, one per bucket: floor(B * the spline's CDF) is the leaf
   const bool leaf_is_bucket = ROOT != 0 && L == hdr->B;
   const uint32_t csh = ROOT == 2 ? hdr->cell_shift : 0u;  // the code-cell table of the spline root
+  const uint32_t cnc = ROOT == 2 ? code_cells_for(L) : 1u;
   const uint64_t ce0 = ROOT == 2 && L >= 2 ? bound[1] : 0ull;
   __shared__ typename std::conditional<MLP, MlpHead, uint32_t>::type mh_;
   MlpFrags w2;
@@ -187,7 +188,7 @@ __device__ __forceinline__ void partition_body(
       uint32_t r0 = r[0], r1 = r[1], r2 = vk ? r[2] : 0u;
       virtual_key(r0, r1, r2, vk);
       uint64_t e = key_code(r0, r1);
-      const uint32_t j = ROOT == 2 ? cell_exact_leaf(ccells, csh, ce0, bound, e) : rmi_leaf(a0, a1, L, e);
+      const uint32_t j = ROOT == 2 ? cell_exact_leaf(ccells, csh, cnc, ce0, bound, e) : rmi_leaf(a0, a1, L, e);
       b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
     }
     bool keep = threadIdx.x < cnt;
@@ -370,6 +371,7 @@ __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restric
   const float a0 = hdr->a0, a1 = hdr->a1;
   const uint32_t L = ROOT ? hdr->mlp_L : hdr->L;
   const uint32_t csh = ROOT == 2 ? hdr->cell_shift : 0u;
+  const uint32_t cnc = ROOT == 2 ? code_cells_for(L) : 1u;
   const uint64_t ce0 = ROOT == 2 && L >= 2 ? bound[1] : 0ull;
   const bool leaf_is_bucket = ROOT != 0 && L == hdr->B;
   const uint64_t wave0 = ((uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u));
@@ -386,7 +388,7 @@ __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restric
       const uint32_t j = mlp_bracket_leaf(bound, cells, L, e, y);
       b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
     } else {
-      const uint32_t j = ROOT == 2 ? cell_exact_leaf(ccells, csh, ce0, bound, e) : rmi_leaf(a0, a1, L, e);
+      const uint32_t j = ROOT == 2 ? cell_exact_leaf(ccells, csh, cnc, ce0, bound, e) : rmi_leaf(a0, a1, L, e);
       b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
     }
     if (i < n) atomicAdd(&counts[b], 1u);
