@@ -339,6 +339,32 @@ def test_batch_windows_other_record_sizes(env, rec_bytes):
         _assert_same(outs[j].cpu().numpy().reshape(-1, rec_bytes), want[j])
 
 
+def test_batch_windows_hot_keys(env):
+    """Jobs with a few heavily repeated keys under the spline root: each hot
+    key's bucket holds only that key, so the windows' one-key bucket kernel
+    orders them (about 10^4 copies each), and the remaining big buckets go to
+    the split."""
+    torch, elsar = env
+    rng = np.random.default_rng(39)
+    sizes = [700_000, 600_000, 520_000, 450_000, 90_000]
+    host, dev = [], []
+    for j, n in enumerate(sizes):
+        r = datagen.generate(datagen.spec("skewed", seed=500 + j, n_hot=6), n)
+        host.append(r)
+        dev.append(torch.from_numpy(np.ascontiguousarray(r).reshape(-1)).to("cuda"))
+    want = [oracle.sort_records(h) for h in host]
+    params = elsar.fit_params(kind=elsar.SPLINE, seed=9)
+    # out of place; then in place (a new job table, its own graph); then the
+    # in-place graph replayed on its own output (sorted input, same result)
+    for rep in range(3):
+        outs = [torch.empty_like(d) for d in dev] if rep == 0 else None
+        elsar.sort_batch(dev, outs, params=params)
+        torch.cuda.synchronize()
+        for j in range(len(sizes)):
+            got = (outs[j] if rep == 0 else dev[j]).cpu().numpy().reshape(-1, R)
+            _assert_same(got, want[j])
+
+
 @pytest.mark.parametrize("kind_name", ["AUTO", "SPLINE"])
 def test_batch_with_equi_depth_roots(env, kind_name):
     # jobs whose models are fitted one by one (no batched linear fit): the

@@ -144,3 +144,23 @@ def test_hot_key_buckets(env, n_hot, kind_name, key_bytes):
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs, key_bytes))
 
+
+@pytest.mark.parametrize("rec_bytes,region_pct", [(48, 0), (100, 1)])
+def test_hot_key_buckets_small_records_and_spill(env, rec_bytes, region_pct):
+    """The one-key bucket kernel with records below 64 bytes, and with regions
+    so small (region_pct 1) that most of each hot key's records sit in the
+    spill area."""
+    torch, elsar = env
+    n = 600_000
+    recs = datagen.generate(datagen.spec("skewed", seed=50, n_hot=8, record_bytes=rec_bytes), n)
+    m, part, offsets, d = _fit(env, recs, num_buckets=512, seed=51, kind=elsar.SPLINE, record_bytes=rec_bytes,
+                               region_pct=region_pct)
+    st = m.partition_stats(part)
+    assert st.big_buckets >= 8
+    if region_pct:
+        assert st.spill_count > n // 2
+    out = torch.empty_like(d)
+    m.sort_buckets(part, offsets, n, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().reshape(-1, rec_bytes), oracle.sort_records(recs))
+
