@@ -272,8 +272,10 @@ elsar_status elsar_sort_host_workspace_size(const elsar_fit_params* p, uint64_t 
 /*
  * The external tier (the paper's larger-than-memory setting, Section 3, with
  * host memory as the external store): n records in host memory h_in are
- * sorted into host memory h_out.  Either may be pageable; pinned memory copies
- * at full link speed.
+ * sorted into host memory h_out.  Either may be pageable: pageable memory is
+ * copied through about 4.5 GB of page-locked slots the call allocates, by
+ * CPU threads (8 per direction) overlapped with the DMA; page-locked memory
+ * is copied directly.
  *  1. The global model (Section 3.1) is fitted on a sample of 1% of the input
  *     (at most 10^7 records) gathered as evenly spaced blocks over the whole
  *     input by one strided copy; with ELSAR_HOST_SAMPLE_FIRST_CHUNK, on the
@@ -286,8 +288,9 @@ elsar_status elsar_sort_host_workspace_size(const elsar_fit_params* p, uint64_t 
  *     pass are read back, one slice per run, placed in exact regions, sorted
  *     and copied to h_out at their offset (Section 3.5's concatenation).
  *  Every record crosses the link four times (plus the sample), whatever the
- *  number of passes.  Copies run on streams of their own, double buffered
- *  against the kernels on `stream`.
+ *  number of passes.  Copies run on streams of their own (device-to-host
+ *  copies from a worker thread), double buffered against the kernels on
+ *  `stream`.
  * h_frag: n * record_bytes bytes of host memory for the runs; it may be h_in
  * itself (the input is then overwritten with the runs) and must not overlap
  * h_out; h_in must not overlap h_out.  d_ws: workspace; its size bounds the
