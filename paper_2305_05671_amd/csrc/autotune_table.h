@@ -12,6 +12,13 @@ namespace elsar {
 constexpr uint32_t kAutotuneRows = 33;
 constexpr uint32_t kAutotuneRecordsPerBucket[kAutotuneRows] = {
     0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0,
-    512, 512, 512, 512, 512, 512, 512, 512, 512, 512, 512,
-    512, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    384, 384, 384, 384, 384, 384, 384, 384, 384, 384, 640,
+    640, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+// Partition tiles (256 records) per block in a batch window whose largest job
+// has ceil(log2 n) = row; 0 means the default rule (four below 8192 tiles,
+// else 2048 blocks).
+constexpr uint32_t kAutotunePartTilesPerBlock[kAutotuneRows] = {
+    0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0,
+    16, 16, 16, 16, 16, 16, 16, 16, 16, 16, 16,
+    16, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 }  // namespace elsar

@@ -726,7 +726,8 @@ std::vector<uint8_t> plan_key(const elsar_job* jobs, uint32_t njobs, const elsar
 elsar_status enqueue_window(const BatchWindow& win, const elsar_fit_params& p, uint8_t* w, hipStream_t st) {
   const WinJob* d = reinterpret_cast<const WinJob*>(w + win.desc);
   const uint32_t nj = (uint32_t)win.jobs.size();
-  const WinGrids g = window_grids(win.nmax, win.Bmax);
+  const uint32_t row = ceil_log2(win.nmax);
+  const WinGrids g = window_grids(win.nmax, win.Bmax, row < kAutotuneRows ? kAutotunePartTilesPerBlock[row] : 0u);
   const elsar_fit_params q = with_defaults(p);
   HIP_TRY(launch_capacities_win(d, nj, q.region_pct, st));
   HIP_TRY(launch_partition_win(d, nj, g.part, q.record_bytes, wants_mlp(q.kind), st));

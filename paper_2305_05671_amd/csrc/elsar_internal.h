@@ -489,8 +489,9 @@ struct WinJob {
 struct WinGrids {           // blocks per job of each phase's launch
   uint32_t part, fixup, small, mid, split, seg, gather;
 };
-// The grids of a window whose largest job has nmax records and B buckets at most.
-WinGrids window_grids(uint64_t nmax, uint32_t Bmax);
+// The grids of a window whose largest job has nmax records and B buckets at
+// most; tiles_per_block: partition tiles per block (0: partition_grid's rule).
+WinGrids window_grids(uint64_t nmax, uint32_t Bmax, uint32_t tiles_per_block);
 uint32_t partition_grid(uint64_t n);    // blocks of the partition of n records
 uint32_t spill_fixup_grid(uint64_t n);  // blocks of the spill fix-up of n records
 hipError_t launch_capacities_win(const WinJob* jobs, uint32_t njobs, uint32_t region_pct, hipStream_t st);

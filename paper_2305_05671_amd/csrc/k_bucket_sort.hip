@@ -1654,9 +1654,11 @@ hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32
 // The bucket sorts of a window of a batch: G blocks per job, block b working
 // for job b / G as its block b % G of G.  Each kernel body is the one the
 // single-job launches above run.
-WinGrids window_grids(uint64_t nmax, uint32_t Bmax) {
+WinGrids window_grids(uint64_t nmax, uint32_t Bmax, uint32_t tiles_per_block) {
   WinGrids g;
-  g.part = partition_grid(nmax);
+  const uint64_t ntiles = (nmax + 255) / 256;  // partition tiles of the largest job
+  g.part = tiles_per_block ? (uint32_t)std::min<uint64_t>((ntiles + tiles_per_block - 1) / tiles_per_block, 1u << 16)
+                           : partition_grid(nmax);
   g.fixup = spill_fixup_grid(nmax);
   g.small = Bmax;
   g.mid = grid_for(nmax, kSmallCap + 1, 256);
