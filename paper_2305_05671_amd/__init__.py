@@ -244,6 +244,7 @@ def elsar_sort(records, out=None, params: FitParams | None = None, workspace=Non
 
 
 NOALLOC_SCRATCH_BYTES = 256 << 20
+MAX_DEVICE_RECORDS = 400_000_000  # ELSAR_MAX_DEVICE_RECORDS: the largest in-HBM sort
 
 
 def elsar_sort_noalloc(records, out, params: FitParams | None = None, stream=None):

@@ -71,6 +71,7 @@ def test_argument_checks_return_before_any_work(elsar):
     # the in-HBM ceiling: input, output and workspace of the largest sort fit
     # one MI355X's 288 GB; one record more is refused before any work
     top = 400_000_000
+    assert elsar.MAX_DEVICE_RECORDS == top
     assert lib.elsar_sort_workspace_size(ctypes.byref(p), top, ctypes.byref(sz)) == elsar.OK
     assert sz.value + 2 * 100 * top <= 288 * 10 ** 9
     assert lib.elsar_sort_workspace_size(ctypes.byref(p), top + 1, ctypes.byref(sz)) == elsar.E_UNSUPPORTED

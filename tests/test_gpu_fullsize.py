@@ -86,3 +86,30 @@ def test_full_size_sort(env, law, seed, kind_name, ratio):
     del d_in, d_out
     torch.cuda.empty_cache()
     _oracle_checks(h_in, h_out, N, seed)
+
+
+def test_max_size_sort(env):
+    """The largest in-HBM sort the library accepts (ELSAR_MAX_DEVICE_RECORDS,
+    4 * 10^8 records): input, output and workspace take about 265 GB of HBM;
+    the default bucket count is 2^18.  Checked over the whole output as
+    above (key and input index strictly increasing, multiset, probes)."""
+    torch, elsar = env
+    n = elsar.MAX_DEVICE_RECORDS
+    seed = 7
+    print(f"max-size case: uniform seed {seed}, {n} records", flush=True)
+    p = elsar.fit_params(seed=seed)
+    d_in = torch.empty(n * R, dtype=torch.uint8, device="cuda")
+    datagen.generate_device(datagen.spec("uniform", seed=seed, embed_idx=True), d_in.data_ptr(), 0, n,
+                            torch.cuda.current_stream().cuda_stream)
+    d_out = torch.empty_like(d_in)
+    ws = torch.empty(elsar.sort_workspace_size(n, p), dtype=torch.uint8, device="cuda")
+    elsar.elsar_sort(d_in, d_out, p, ws)
+    torch.cuda.synchronize()
+    del ws
+    h_in = d_in.cpu()
+    del d_in
+    h_out = d_out.cpu()
+    del d_out
+    torch.cuda.empty_cache()
+    _oracle_checks(h_in, h_out, n, seed)
+
