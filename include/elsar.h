@@ -273,9 +273,9 @@ elsar_status elsar_sort_host_workspace_size(const elsar_fit_params* p, uint64_t 
  * The external tier (the paper's larger-than-memory setting, Section 3, with
  * host memory as the external store): n records in host memory h_in are
  * sorted into host memory h_out.  Either may be pageable: pageable memory is
- * copied through about 4.5 GB of page-locked slots the call allocates, by
- * CPU threads (8 per direction) overlapped with the DMA; page-locked memory
- * is copied directly.
+ * copied through page-locked slots the call allocates (sized from the chunk,
+ * at most about 4.5 GB), by CPU threads (8 per direction) overlapped with
+ * the DMA; page-locked memory is copied directly.
  *  1. The global model (Section 3.1) is fitted on a sample of 1% of the input
  *     (at most 10^7 records) gathered as evenly spaced blocks over the whole
  *     input by one strided copy; with ELSAR_HOST_SAMPLE_FIRST_CHUNK, on the

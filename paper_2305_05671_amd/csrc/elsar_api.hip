@@ -1131,8 +1131,8 @@ struct Streams {  // the upload stream and the events, released on every path (t
 //    at its destination.
 class Stager {
  public:
-  static constexpr size_t kSlotBytes = 128ull << 20;
-  static constexpr int kInSlots = 4, kOutSlots = 32;
+  static constexpr size_t kMaxSlotBytes = 128ull << 20;
+  static constexpr int kInSlots = 4, kMaxOutSlots = 32;
 
   ~Stager() {
     if (worker_.joinable()) {
@@ -1146,29 +1146,34 @@ class Stager {
     }
     if (wst_) (void)hipStreamDestroy(wst_);
     for (Slot* arr : {in_, out_})
-      for (int i = 0; i < (arr == in_ ? kInSlots : kOutSlots); ++i) {
+      for (int i = 0; i < (arr == in_ ? kInSlots : kMaxOutSlots); ++i) {
         if (arr[i].ev) (void)hipEventDestroy(arr[i].ev);
         if (arr[i].p) (void)hipHostFree(arr[i].p);
       }
   }
 
-  // false: the worker or its stream could not be started (nothing can be
-  // copied to the host then); without pinned slots the pageable copies go
-  // the runtime's way, from the worker
-  bool init() {
+  // slots: whether any host buffer is pageable; bytes: the largest single
+  // transfer to expect (a chunk).  Slots are at most 128 MB and about an
+  // eighth of that transfer (at least 1 MB); enough out-slots for one such
+  // transfer (4 to 32), four in-slots.  False: the worker or its stream could
+  // not be started (nothing can be copied to the host then); without pinned
+  // slots the pageable copies go the runtime's way, from the worker.
+  bool init(bool slots, size_t bytes) {
     const unsigned hc = std::thread::hardware_concurrency();
     threads_ = hc ? std::min(8u, std::max(1u, hc / 2)) : 4u;
     if (hipStreamCreateWithFlags(&wst_, hipStreamNonBlocking) != hipSuccess) return false;
-    slots_ok_ = true;
+    slot_bytes_ = std::min(kMaxSlotBytes, std::max<size_t>(1u << 20, (bytes / 8 + 4095) & ~size_t(4095)));
+    nout_ = (int)std::min<size_t>(kMaxOutSlots, std::max<size_t>(4, (bytes + slot_bytes_ - 1) / slot_bytes_));
+    slots_ok_ = slots;
     for (Slot* arr : {in_, out_})
-      for (int i = 0; i < (arr == in_ ? kInSlots : kOutSlots); ++i) {
-        if (hipHostMalloc(reinterpret_cast<void**>(&arr[i].p), kSlotBytes, hipHostMallocDefault) != hipSuccess ||
+      for (int i = 0; slots && i < (arr == in_ ? kInSlots : nout_); ++i) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&arr[i].p), slot_bytes_, hipHostMallocDefault) != hipSuccess ||
             hipEventCreateWithFlags(&arr[i].ev, hipEventDisableTiming) != hipSuccess) {
           (void)hipGetLastError();
           slots_ok_ = false;
         }
       }
-    for (int k = 0; k < kOutSlots; ++k) free_.push_back(k);
+    for (int k = 0; k < nout_; ++k) free_.push_back(k);
     try {
       worker_ = std::thread([this] { work(); });
     } catch (...) {
@@ -1192,8 +1197,8 @@ class Stager {
       HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
       return ELSAR_OK;
     }
-    for (size_t off = 0; off < bytes; off += kSlotBytes) {
-      const size_t len = std::min(kSlotBytes, bytes - off);
+    for (size_t off = 0; off < bytes; off += slot_bytes_) {
+      const size_t len = std::min(slot_bytes_, bytes - off);
       Slot& sl = in_[next_in_];
       next_in_ = (next_in_ + 1) % kInSlots;
       HIP_TRY(hipEventSynchronize(sl.ev));  // its previous DMA has read it
@@ -1304,7 +1309,7 @@ class Stager {
         } else if (ok) {
           const int k = free_.back();
           free_.pop_back();
-          const size_t len = std::min(kSlotBytes, r.bytes - r.issued);
+          const size_t len = std::min(slot_bytes_, r.bytes - r.issued);
           Slot& sl = out_[k];
           sl.dst = r.dst + r.issued;
           sl.len = len;
@@ -1351,8 +1356,9 @@ class Stager {
     }
   }
 
-  Slot in_[kInSlots], out_[kOutSlots];
-  int next_in_ = 0;
+  Slot in_[kInSlots], out_[kMaxOutSlots];
+  int next_in_ = 0, nout_ = 4;
+  size_t slot_bytes_ = kMaxSlotBytes;
   unsigned threads_ = 4;
   bool slots_ok_ = false;
   hipStream_t wst_ = nullptr;
@@ -1434,9 +1440,9 @@ elsar_status elsar_sort_host(const void* h_in, uint64_t n, void* h_out, void* h_
   if (!ss.init()) return ELSAR_E_HIP;
   uint64_t link = 0;
   // buffers that are not page-locked go through the stager's pinned slots
-  Stager stg;
-  if (!stg.init()) return ELSAR_E_HIP;
   const bool in_pinned = Stager::pinned(in), out_pinned = Stager::pinned(out), frag_pinned = Stager::pinned(frag);
+  Stager stg;
+  if (!stg.init(!(in_pinned && out_pinned && frag_pinned), (size_t)std::min<uint64_t>(hl.C, n) * R)) return ELSAR_E_HIP;
 
   // 1. the global model: on a sample spread over the whole input, or (flag) on
   //    the first chunk only, as the paper samples the first batch that one
