@@ -4,9 +4,10 @@
 //
 // Matrix-core layouts (one wave, 16x16 outputs): for
 // v_mfma_f32_16x16x16bf16_1k lane l holds A[l%16][4(l/16)+e],
-// B[4(l/16)+e][l%16] and D[4(l/16)+e][l%16] for e = 0..3; for
-// v_mfma_f32_16x16x4_f32 lane l holds A[l%16][l/16] and B[l/16][l%16], and D
-// as above.  Training computes records x units (layer-1 units of record l%16
+// B[4(l/16)+e][l%16] and D[4(l/16)+e][l%16] for e = 0..3; for gfx950's
+// v_mfma_f32_16x16x32_bf16 lane l holds A[l%16][8(l/16)+e] and
+// B[8(l/16)+e][l%16] for e = 0..7, D as above; for v_mfma_f32_16x16x4_f32
+// lane l holds A[l%16][l/16] and B[l/16][l%16], and D as above.  Training computes records x units (layer-1 units of record l%16
 // become the A fragments of the layer-2 product); evaluation computes units x
 // records (mlp_y64).
 #pragma once
@@ -15,7 +16,16 @@
 namespace elsar {
 
 typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Two 4-element bfloat16 fragments as the 8 elements one lane gives a
+// 16x16x32 product.
+__device__ __forceinline__ bf16x8 cat8_bf16(s16x4 a, s16x4 b) {
+  const s16x8 v = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+  return __builtin_bit_cast(bf16x8, v);
+}
 
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {  // round to nearest, ties to even (finite f)
   uint32_t u = __float_as_uint(f);
@@ -124,7 +134,11 @@ __device__ __forceinline__ s16x4 pack4_bf16_cvt(float a, float b, float c, float
 // accumulation.  Lane l then holds units 16t + 4(l/16) + e of record l%16 of
 // the chunk, so layer 1's output is already layer 2's B fragment, and the
 // output unit is an in-lane sum over 16 units plus a sum over the four lane
-// groups.
+// groups.  Layer 2 runs as 16x16x32 products: K-step s contracts units
+// 32s .. 32s+31, lane group g giving units 32s + 4g + e and 32s + 16 + 4g +
+// e (e = 0..3) -- the h1 tiles 2s and 2s+1 it holds, and the W2 fragments of
+// the same units; the contraction does not depend on the order of its terms
+// across lane slots, only on A and B agreeing on it.
 __device__ __forceinline__ float mlp_y64(uint64_t code, const MlpHead& M, const MlpFrags& w) {
   const uint32_t l = __lane_id(), r = l & 15u, g = l >> 4;
   float y_own = 0.0f;
@@ -148,8 +162,9 @@ __device__ __forceinline__ float mlp_y64(uint64_t code, const MlpHead& M, const 
     for (uint32_t ct = 0; ct < 4; ++ct) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (uint32_t ks = 0; ks < 4; ++ks)
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w.f[ct * 4 + ks], h1[ks], acc, 0, 0, 0);
+      for (uint32_t s = 0; s < 2; ++s)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cat8_bf16(w.f[ct * 4 + 2 * s], w.f[ct * 4 + 2 * s + 1]),
+                                                      cat8_bf16(h1[2 * s], h1[2 * s + 1]), acc, 0, 0, 0);
       const uint32_t u = 16 * ct + 4 * g;
 #pragma unroll
       for (int e = 0; e < 4; ++e) part = __builtin_fmaf(M.w3[u + e], sigm(acc[e] + M.b2[u + e]), part);
