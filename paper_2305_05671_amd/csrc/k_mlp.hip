@@ -168,9 +168,10 @@ __device__ void step_grad(TrainLds& sm) {
     for (uint32_t ct = 0; ct < 4; ++ct) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (uint32_t ks = 0; ks < 4; ++ks) {
-        const s16x4 b = load4_bf16(sm.M.W2bf + (16 * ct + r) * 64 + 16 * ks + 4 * g);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ks], b, acc, 0, 0, 0);
+      for (uint32_t s2 = 0; s2 < 2; ++s2) {  // K-steps 2s2 and 2s2+1 as one 16x16x32 product
+        const uint16_t* wr = sm.M.W2bf + (16 * ct + r) * 64 + 32 * s2 + 4 * g;
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cat8_bf16(a[2 * s2], a[2 * s2 + 1]),
+                                                      cat8_bf16(load4_bf16(wr), load4_bf16(wr + 16)), acc, 0, 0, 0);
       }
       const uint32_t col = 16 * ct + r;
 #pragma unroll
@@ -233,11 +234,13 @@ __device__ void step_grad(TrainLds& sm) {
     const uint32_t jt = tile & 3u, ct = tile >> 2;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (uint32_t ks = 0; ks < kRows / 16; ++ks) {
-      const s16x4 a = load4_bf16(sm.DZ2T + (16 * jt + r) * kRows + 16 * ks + 4 * g);
-      const float* h = sm.H1T + (16 * ct + r) * kRows + 16 * ks + 4 * g;
-      const s16x4 b = pack4_bf16(h[0], h[1], h[2], h[3]);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    for (uint32_t s2 = 0; s2 < kRows / 32; ++s2) {  // rows 32s2 + 4g + e and 32s2 + 16 + 4g + e
+      const uint16_t* dz = sm.DZ2T + (16 * jt + r) * kRows + 32 * s2 + 4 * g;
+      const float* h = sm.H1T + (16 * ct + r) * kRows + 32 * s2 + 4 * g;
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cat8_bf16(load4_bf16(dz), load4_bf16(dz + 16)),
+                                                    cat8_bf16(pack4_bf16(h[0], h[1], h[2], h[3]),
+                                                              pack4_bf16(h[16], h[17], h[18], h[19])),
+                                                    acc, 0, 0, 0);
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) sm.G[kOffW2 + (16 * jt + 4 * g + e) * 64 + 16 * ct + r] = acc[e];
@@ -250,10 +253,11 @@ __device__ void step_grad(TrainLds& sm) {
     for (uint32_t ct = 0; ct < 4; ++ct) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (uint32_t ks = 0; ks < 4; ++ks) {
-        const s16x4 a = load4_bf16(sm.DZ2 + (r0 + r) * 64 + 16 * ks + 4 * g);
-        const s16x4 b = load4_bf16(sm.M.W2bfT + (16 * ct + r) * 64 + 16 * ks + 4 * g);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+      for (uint32_t s2 = 0; s2 < 2; ++s2) {
+        const uint16_t* dz = sm.DZ2 + (r0 + r) * 64 + 32 * s2 + 4 * g;
+        const uint16_t* wt = sm.M.W2bfT + (16 * ct + r) * 64 + 32 * s2 + 4 * g;
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cat8_bf16(load4_bf16(dz), load4_bf16(dz + 16)),
+                                                      cat8_bf16(load4_bf16(wt), load4_bf16(wt + 16)), acc, 0, 0, 0);
       }
       const uint32_t u = 16 * ct + r;
       float gw[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, gb = 0.f;
