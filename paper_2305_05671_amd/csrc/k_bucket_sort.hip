@@ -359,9 +359,7 @@ __device__ __forceinline__ void bucket_sort_small_body(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map, const uint4* __restrict__ slots,
     uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t K, uint32_t* __restrict__ out, uint32_t B,
-    uint32_t* __restrict__ seg_n, uint32_t vk, uint32_t bid,
-    uint32_t nblk) {
-  if (seg_n && bid == 0 && threadIdx.x < 4) seg_n[threadIdx.x] = 0;  // the big-bucket split's counters
+    uint32_t vk, uint32_t bid, uint32_t nblk) {
   constexpr uint32_t SC = slot_bytes_for(RW * 4) / 16;  // 16-byte chunks per slot
   constexpr uint32_t LC = (RW + 1 + 3) / 4;             // chunks holding the index or record bytes
   constexpr uint32_t AR = kSmCap / kSmThreads;          // entries per thread
@@ -502,8 +500,8 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map, const uint4* __restrict__ slots,
     uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t K, uint32_t* __restrict__ out, uint32_t B,
-    uint32_t* __restrict__ seg_n, uint32_t vk) {
-  bucket_sort_small_body<RW>(counts, caps, rstart, spill_off, spill_map, slots, cap_slots, offsets, K, out, B, seg_n, vk, blockIdx.x, gridDim.x);
+    uint32_t vk) {
+  bucket_sort_small_body<RW>(counts, caps, rstart, spill_off, spill_map, slots, cap_slots, offsets, K, out, B, vk, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------- buckets of up to 6144 records --
@@ -518,9 +516,15 @@ __device__ __forceinline__ void bucket_sort_lds_body(
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
     const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
     uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
-    uint32_t B, uint32_t* __restrict__ seg_n, uint32_t vk, uint32_t bid,
+    uint32_t B, PartHeader* __restrict__ reset, uint32_t vk, uint32_t bid,
     uint32_t nblk) {
-  if (seg_n && bid == 0 && threadIdx.x < 4) seg_n[threadIdx.x] = 0;  // the big-bucket split's counters
+  // the first kernel of the larger buckets' chain starts the split's counters
+  // and the equal-key kernel's hand-on list afresh (every call of the chain
+  // on a partition is then the same)
+  if (reset && bid == 0 && threadIdx.x < 5) {
+    if (threadIdx.x < 4) reset->seg_n[threadIdx.x] = 0;
+    else reset->n_big2 = 0;
+  }
   constexpr uint32_t WAVES = THREADS / 64;
   static_assert(CAP % THREADS == 0, "cap is whole rounds");
   __shared__ uint4 ent[CAP];
@@ -642,8 +646,8 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
     const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
     uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
-    uint32_t B, uint32_t* __restrict__ seg_n, uint32_t vk) {
-  bucket_sort_lds_body<CAP, THREADS>(counts, caps, rstart, spill_off, spill_map, slots, cap_slots, offsets, RW, K, out, list, list_n, B, seg_n, vk, blockIdx.x, gridDim.x);
+    uint32_t B, PartHeader* __restrict__ reset, uint32_t vk) {
+  bucket_sort_lds_body<CAP, THREADS>(counts, caps, rstart, spill_off, spill_map, slots, cap_slots, offsets, RW, K, out, list, list_n, B, reset, vk, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------ big buckets of one repeated key --
@@ -1595,15 +1599,11 @@ hipError_t launch_bucket_sort_small(uint8_t* part, const PartLayout& lay, uint32
   if (rec_bytes == 100) {
     bucket_sort_small_kernel<25><<<B, kSmThreads, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap,
                                                            reinterpret_cast<const uint4*>(a.slots), lay.cap_slots,
-                                                           offsets, key_bytes, a.out, B,
-                                                           reinterpret_cast<PartHeader*>(part + lay.header)->seg_n,
-                                                           vk);
+                                                           offsets, key_bytes, a.out, B, vk);
   } else {
     bucket_sort_lds_kernel<kSmallCap, 256><<<B, 256, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots,
                                                                lay.cap_slots, offsets, a.RW, key_bytes, a.out,
-                                                               nullptr, nullptr, B,
-                                                               reinterpret_cast<PartHeader*>(part + lay.header)->seg_n,
-                                                               vk);
+                                                               nullptr, nullptr, B, nullptr, vk);
   }
   return hipGetLastError();
 }
@@ -1623,7 +1623,8 @@ hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32
   SortArgs a = sort_args(part, lay, rec_bytes, out);
   bucket_sort_lds_kernel<kMidCap, 512><<<grid_for(n, kSmallCap + 1, 256), 512, 0, st>>>(
       a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
-      reinterpret_cast<const uint32_t*>(part + lay.mid_list), &a.ph->n_mid, B, nullptr, vk);
+      reinterpret_cast<const uint32_t*>(part + lay.mid_list), &a.ph->n_mid, B,
+      reinterpret_cast<PartHeader*>(part + lay.header), vk);
   PartHeader* ph = reinterpret_cast<PartHeader*>(part + lay.header);
   // buckets of one repeated key first; the others go on to big2
   uint32_t* big2 = reinterpret_cast<uint32_t*>(part + lay.big2_list);
@@ -1639,7 +1640,7 @@ hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32
   uint4* leaf = reinterpret_cast<uint4*>(part + lay.seg_leaf);
   uint32_t* leaf_n = &ph->seg_n[0];
   const uint32_t leaf_cap = lay.seg_leaf_cap;
-  // the split's counters (ph->seg_n) were cleared by the small-bucket kernel
+  // the split's counters (ph->seg_n) were cleared by the mid-bucket kernel
   msd_split_kernel<<<grid_for(n, kMidCap + 1, 512), kMsdThreads, 0, st>>>(
       a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out, big2,
       &ph->n_big2, leaf, leaf_n, leaf_cap, &ph->seg_n[1], vk);
@@ -1692,7 +1693,7 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_win_kernel(const
   const WinJob& J = jobs[blockIdx.x / G];
   const WinRefs r = win_refs(J);
   bucket_sort_small_body<RW>(r.counts, r.caps, r.rstart, r.soff, r.smap, reinterpret_cast<const uint4*>(r.slots),
-                             J.lay.cap_slots, J.offsets, K, reinterpret_cast<uint32_t*>(J.out), J.B, r.ph->seg_n, 0u,
+                             J.lay.cap_slots, J.offsets, K, reinterpret_cast<uint32_t*>(J.out), J.B, 0u,
                              blockIdx.x % G, G);
 }
 
@@ -1706,7 +1707,7 @@ __global__ __launch_bounds__(THREADS) void bucket_sort_lds_win_kernel(const WinJ
   bucket_sort_lds_body<CAP, THREADS>(r.counts, r.caps, r.rstart, r.soff, r.smap, r.slots, J.lay.cap_slots, J.offsets,
                                      RW, K, reinterpret_cast<uint32_t*>(J.out),
                                      MID ? reinterpret_cast<const uint32_t*>(J.part + J.lay.mid_list) : nullptr,
-                                     MID ? &r.ph->n_mid : nullptr, J.B, MID ? nullptr : r.ph->seg_n, 0u,
+                                     MID ? &r.ph->n_mid : nullptr, J.B, MID ? r.ph : nullptr, 0u,
                                      blockIdx.x % G, G);
 }
 
@@ -1778,7 +1779,7 @@ hipError_t launch_bucket_sort_large_win(const WinJob* jobs, uint32_t njobs, cons
     bucket_sort_global_win_kernel<<<njobs * G, kBigThreads, 0, st>>>(jobs, G, RW, key_bytes);
     return hipGetLastError();
   }
-  // the split's counters (seg_n) were cleared by the small-bucket kernel
+  // the split's counters (seg_n) were cleared by the mid-bucket kernel
   msd_split_win_kernel<<<njobs * g.split, kMsdThreads, 0, st>>>(jobs, g.split, RW, key_bytes);
   seg_sort_win_kernel<<<njobs * g.seg, kSmThreads, 0, st>>>(jobs, g.seg, RW);
   big_gather_win_kernel<<<njobs * g.gather, kMsdThreads, 0, st>>>(jobs, g.gather, RW);

@@ -213,7 +213,16 @@ def test_big_buckets_split(env, kind, n, B, seed, region):
     st = m.partition_stats(part)
     assert st.big_buckets > 0 and st.split_segments > 0
     assert st.split_segments <= st.split_segment_cap and st.split_overflow == 0
-    _assert_same(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs))
+    want = oracle.sort_records(recs)
+    _assert_same(out.cpu().numpy().reshape(-1, R), want)
+    # the bucket sort again on the same partition: its lists and counters
+    # start afresh, so the second output and bookkeeping are the first's
+    out2 = torch.full_like(d, 0x55)
+    m.sort_buckets(part, offsets, n, out2)
+    torch.cuda.synchronize()
+    st2 = m.partition_stats(part)
+    assert (st2.split_segments, st2.split_overflow) == (st.split_segments, st.split_overflow)
+    _assert_same(out2.cpu().numpy().reshape(-1, R), want)
 
 
 def test_big_bucket_equal_keys_and_prefixes(env):
