@@ -14,9 +14,10 @@
 //  * bucket_sort_small: buckets of up to 2048 records, one 512-thread block
 //    each.  The first 16 bytes of every slot go to LDS; one counting pass on
 //    the key's base-95 code, scaled over the bucket's code range into 2048
-//    bins, then each bin is ordered by the whole composite: ranks counted in
-//    parallel up to 64 entries, a one-wave bitonic network up to 256, a
-//    whole-bucket LSD radix beyond.  The records are then gathered in sorted
+//    bins (a second, finer one when a bin holds more than 12 entries), then
+//    each bin is ordered by the whole composite: ranks counted in parallel up
+//    to 64 entries, a one-wave bitonic network up to 256, a whole-bucket LSD
+//    radix beyond.  The records are then gathered in sorted
 //    order straight into the output (each slot line is read twice: for the
 //    key, then for the record).
 //  * bucket_sort_lds: buckets of up to 6144 records, the same algorithm with
@@ -219,30 +220,80 @@ __device__ __forceinline__ void wave_lds_sync() {
 // bin is longer still (keys clustered at a finer scale than the digit
 // resolves).  bins: 2^BITS counters, also the LSD passes' per-wave counters.
 // Returns the perm buffer that holds the sorted order.
-template <uint32_t CAP, uint32_t THREADS, uint32_t BITS, typename Less, typename ByteOf>
+//
+// With a position function (pos(entry): the scaled value whose floor is the
+// entry's digit, non-decreasing in the key), a bucket with a bin of more than
+// kRefineMin entries is counted a second time on a finer digit: bin b's m
+// entries, at [s, s + m) after the first pass, get the sub-bins s +
+// floor(m * (pos - b)), by where each lies within the bin's own stretch of
+// the scale.  The sub-bins refine the bins, so their order stays the key's;
+// keys clustered within a bin (the skewed law's per-byte peaks) then meet far
+// fewer others of their sub-bin in the rank counting below.
+struct NoPos {
+  static constexpr bool enabled = false;
+  __device__ double operator()(uint32_t) const { return 0.0; }
+};
+constexpr uint32_t kRefineMin = 12;
+
+template <uint32_t CAP, uint32_t THREADS, uint32_t BITS, typename Less, typename ByteOf, typename Pos = NoPos>
 __device__ __forceinline__ uint32_t bin_sort_core(uint32_t n, uint32_t vary, uint16_t (*perm)[CAP], uint32_t* bins,
-                                                  uint32_t* sh_scan, uint32_t* tot, Less less, ByteOf byte_of) {
+                                                  uint32_t* sh_scan, uint32_t* tot, Less less, ByteOf byte_of,
+                                                  Pos pos = Pos()) {
   constexpr uint32_t WAVES = THREADS / 64, NB = 1u << BITS;
   static_assert(WAVES * 256 <= NB, "the bins double as the LSD counters");
   static_assert(WAVES * kWaveSortMax <= CAP, "a private bitonic area per wave in perm[1]");
+  static_assert(!Pos::enabled || CAP <= NB, "the sub-bins of a refined count are positions below n");
   const uint32_t tid = threadIdx.x;
-  const uint16_t* dig = perm[1];
-  __syncthreads();
-  for (uint32_t p = tid; p < n; p += THREADS) atomicAdd(&bins[dig[p]], 1u);
-  __syncthreads();
-  {  // exclusive scan of the bins: PER contiguous per thread
-    constexpr uint32_t PER = NB / THREADS;
-    uint32_t c[PER], sum = 0;
+  uint16_t* dig = perm[1];
+  auto counting_pass = [&]() {  // bins zeroed: entries to perm[0] by digit; bins[b] is then the end of bin b
+    __syncthreads();
+    for (uint32_t p = tid; p < n; p += THREADS) atomicAdd(&bins[dig[p]], 1u);
+    __syncthreads();
+    {  // exclusive scan of the bins: PER contiguous per thread
+      constexpr uint32_t PER = NB / THREADS;
+      uint32_t c[PER], sum = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < PER; ++i) { c[i] = bins[tid * PER + i]; sum += c[i]; }
-    uint32_t total;
-    uint32_t run = block_exclusive_scan<uint32_t, THREADS>(sum, sh_scan, &total);
+      for (uint32_t i = 0; i < PER; ++i) { c[i] = bins[tid * PER + i]; sum += c[i]; }
+      uint32_t total;
+      uint32_t run = block_exclusive_scan<uint32_t, THREADS>(sum, sh_scan, &total);
 #pragma unroll
-    for (uint32_t i = 0; i < PER; ++i) { bins[tid * PER + i] = run; run += c[i]; }
+      for (uint32_t i = 0; i < PER; ++i) { bins[tid * PER + i] = run; run += c[i]; }
+    }
+    __syncthreads();
+    for (uint32_t p = tid; p < n; p += THREADS) perm[0][atomicAdd(&bins[dig[p]], 1u)] = (uint16_t)p;
+    __syncthreads();
+  };
+  counting_pass();
+  if constexpr (Pos::enabled) {
+    bool crowded = false;
+    for (uint32_t b = tid; b < NB; b += THREADS) crowded |= bins[b] - (b ? bins[b - 1] : 0u) > kRefineMin;
+    if (__syncthreads_or(crowded)) {
+      constexpr uint32_t AR = CAP / THREADS;
+      static_assert(CAP % THREADS == 0, "whole rounds of entries");
+      uint16_t sub[AR];
+#pragma unroll
+      for (uint32_t i = 0; i < AR; ++i) {
+        const uint32_t e = tid + i * THREADS;
+        sub[i] = 0;
+        if (e < n) {
+          const uint32_t b = dig[e];
+          const uint32_t s0 = b ? bins[b - 1] : 0u, m = bins[b] - s0;
+          double f = pos(e) - (double)b;
+          f = f < 0.0 ? 0.0 : f;
+          uint32_t k = (uint32_t)(f * (double)m);
+          sub[i] = (uint16_t)(s0 + (k < m ? k : m - 1));
+        }
+      }
+      __syncthreads();  // every bin bound is read
+#pragma unroll
+      for (uint32_t i = 0; i < AR; ++i) {
+        const uint32_t e = tid + i * THREADS;
+        if (e < n) dig[e] = sub[i];
+      }
+      for (uint32_t b = tid; b < NB; b += THREADS) bins[b] = 0;
+      counting_pass();
+    }
   }
-  __syncthreads();
-  for (uint32_t p = tid; p < n; p += THREADS) perm[0][atomicAdd(&bins[dig[p]], 1u)] = (uint16_t)p;
-  __syncthreads();
   // bins[b] is now the end of bin b; the start is the end of bin b-1
   __shared__ uint16_t wave_bins[CAP / (kRunMax + 1) + 1];  // bins for the waves
   __shared__ uint32_t n_wave_bins;
@@ -340,10 +391,26 @@ __device__ __forceinline__ uint32_t bin_sort_core(uint32_t n, uint32_t vary, uin
   return cur;
 }
 
+// The position of a digit taken from a 64-bit source value scaled over the
+// bucket's range: (src(entry) - min) * scale.
+template <typename Src>
+struct ScaledPos {
+  static constexpr bool enabled = true;
+  Src src;
+  uint64_t lo;
+  double scale;
+  __device__ double operator()(uint32_t e) const { return (double)(src(e) - lo) * scale; }
+};
+template <typename Src>
+__device__ __forceinline__ ScaledPos<Src> scaled_pos(Src src, uint64_t lo, double scale) {
+  return ScaledPos<Src>{src, lo, scale};
+}
+
 // The small-bucket instance: composites as four word arrays cw[0..3][entry].
+template <typename Pos = NoPos>
 __device__ __forceinline__ uint32_t small_sort_core(uint32_t n, uint32_t vary, uint32_t (*cw)[kSmCap],
                                                     uint16_t (*perm)[kSmCap], uint32_t* bins, uint32_t* sh_scan,
-                                                    uint32_t* tot) {
+                                                    uint32_t* tot, Pos pos = Pos()) {
   auto less = [&](uint32_t x, uint32_t y) -> bool {
     if (cw[0][x] != cw[0][y]) return cw[0][x] < cw[0][y];
     if (cw[1][x] != cw[1][y]) return cw[1][x] < cw[1][y];
@@ -351,7 +418,7 @@ __device__ __forceinline__ uint32_t small_sort_core(uint32_t n, uint32_t vary, u
     return cw[3][x] < cw[3][y];
   };
   auto byte_of = [&](uint32_t e, uint32_t pb) -> uint32_t { return (cw[pb >> 2][e] >> (24 - 8 * (pb & 3))) & 0xFFu; };
-  return bin_sort_core<kSmCap, kSmThreads, kSmBits>(n, vary, perm, bins, sh_scan, tot, less, byte_of);
+  return bin_sort_core<kSmCap, kSmThreads, kSmBits>(n, vary, perm, bins, sh_scan, tot, less, byte_of, pos);
 }
 
 template <uint32_t RW>  // record dwords
@@ -435,7 +502,10 @@ __device__ __forceinline__ void bucket_sort_small_body(
         dig[p] = (uint16_t)(d < (1u << kSmBits) ? d : (1u << kSmBits) - 1);
       }
     }
-    cur = small_sort_core(n, vary, cw, perm, bins, sh_scan, tot);
+    auto code_of = [&](uint32_t e) -> uint64_t {
+      return key_code(__builtin_bswap32(cw[0][e]), __builtin_bswap32(cw[1][e]));
+    };
+    cur = small_sort_core(n, vary, cw, perm, bins, sh_scan, tot, scaled_pos(code_of, cmin, scale));
   }
   __syncthreads();
   // 3. gather through LDS: the records of sorted positions [r0, r0 + kStage)
@@ -580,8 +650,11 @@ __device__ __forceinline__ void bucket_sort_lds_body(
       const uint32_t d = (uint32_t)((double)(e - cmin) * scale);
       perm[1][p] = (uint16_t)(d < (1u << kMidBits) ? d : (1u << kMidBits) - 1);
     }
-    const uint32_t cur =
-        bin_sort_core<CAP, THREADS, kMidBits>(br.n, vary, perm, bins, sh_scan, tot, less, byte_of);
+    auto code_of = [&](uint32_t e) -> uint64_t {
+      return key_code(__builtin_bswap32(ent[e].x), __builtin_bswap32(ent[e].y));
+    };
+    const uint32_t cur = bin_sort_core<CAP, THREADS, kMidBits>(br.n, vary, perm, bins, sh_scan, tot, less, byte_of,
+                                                               scaled_pos(code_of, cmin, scale));
     __syncthreads();
     // 3. copy records in sorted order to the output through LDS, as in the
     //    small-bucket kernel: a stretch of records assembled in the entry
@@ -1280,7 +1353,7 @@ __device__ __forceinline__ void seg_sort_body(const uint32_t* __restrict__ count
         const uint32_t d = (uint32_t)((double)(digit_src(q) - cmin) * scale);
         perm[1][q] = (uint16_t)(d < (1u << kSmBits) ? d : (1u << kSmBits) - 1);
       }
-      cur = small_sort_core(n, vary, cw, perm, bins, sh_scan, tot);
+      cur = small_sort_core(n, vary, cw, perm, bins, sh_scan, tot, scaled_pos(digit_src, cmin, scale));
     }
     __syncthreads();
     for (uint32_t k = tid; k < n; k += kSmThreads) refs[k] = X[5ull * perm[cur][k] + 4];
@@ -1416,7 +1489,11 @@ __global__ __launch_bounds__(kSmThreads) void tiny_jobs_kernel(const TinyJob* __
         const uint32_t d = (uint32_t)((double)(e - cmin) * scale);
         perm[1][q] = (uint16_t)(d < (1u << kSmBits) ? d : (1u << kSmBits) - 1);
       }
-      cur = small_sort_core(n, vary, cw, perm, bins, sh_scan, tot);
+      auto code_of = [&](uint32_t q) -> uint64_t {
+        const uint32_t* r = src + (uint64_t)q * RW;
+        return key_code(r[0], r[1]);
+      };
+      cur = small_sort_core(n, vary, cw, perm, bins, sh_scan, tot, scaled_pos(code_of, cmin, scale));
     }
     __syncthreads();
     for (uint32_t f = tid; f < n * RW; f += kSmThreads) {
