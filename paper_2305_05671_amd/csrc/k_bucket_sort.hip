@@ -21,7 +21,7 @@
 //    order straight into the output (each slot line is read twice: for the
 //    key, then for the record).
 //  * bucket_sort_lds: buckets of up to 6144 records, the same algorithm with
-//    a 13-bit counting digit in one 512-thread block.
+//    a 13-bit counting digit in one 1024-thread block.
 //  * msd_split + seg_sort + big_gather: larger buckets, split by their most
 //    significant varying composite byte into pieces the small-bucket sort
 //    finishes, then copied out in order (records of at least 64 bytes).
@@ -578,6 +578,7 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
 // The small-bucket algorithm at a larger scale: one counting pass on a
 // 13-bit digit of the base-95 code over the bucket's code range, then the
 // per-bin orderings of bin_sort_core.
+constexpr uint32_t kMidThreads = 1024;  // 16 waves: the one block a CU holds (157 KB of LDS)
 constexpr uint32_t kMidBits = 13;
 
 template <uint32_t CAP, uint32_t THREADS>
@@ -1698,7 +1699,7 @@ hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32
                                     const uint64_t* offsets, uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out,
                                     hipStream_t st, uint32_t vk) {
   SortArgs a = sort_args(part, lay, rec_bytes, out);
-  bucket_sort_lds_kernel<kMidCap, 512><<<grid_for(n, kSmallCap + 1, 256), 512, 0, st>>>(
+  bucket_sort_lds_kernel<kMidCap, kMidThreads><<<grid_for(n, kSmallCap + 1, 256), kMidThreads, 0, st>>>(
       a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
       reinterpret_cast<const uint32_t*>(part + lay.mid_list), &a.ph->n_mid, B,
       reinterpret_cast<PartHeader*>(part + lay.header), vk);
@@ -1848,7 +1849,7 @@ hipError_t launch_bucket_sort_large_win(const WinJob* jobs, uint32_t njobs, cons
                                         uint32_t key_bytes, hipStream_t st) {
   if (njobs == 0) return hipSuccess;
   const uint32_t RW = rec_bytes / 4;
-  bucket_sort_lds_win_kernel<kMidCap, 512, true><<<njobs * g.mid, 512, 0, st>>>(jobs, g.mid, RW, key_bytes);
+  bucket_sort_lds_win_kernel<kMidCap, kMidThreads, true><<<njobs * g.mid, kMidThreads, 0, st>>>(jobs, g.mid, RW, key_bytes);
   // buckets of one repeated key first (as many blocks per job as the mid sort)
   equal_keys_win_kernel<<<njobs * g.mid, kEqThreads, 0, st>>>(jobs, g.mid, RW, key_bytes);
   if (rec_bytes < 64) {  // too little room for the split's buffers, stack and reference list
