@@ -629,6 +629,8 @@ constexpr uint32_t kScanThreads = 1024;
 constexpr uint32_t kScanWaves = kScanThreads / 64;
 constexpr uint32_t kScanSteps = 4;  // steps of 256 buckets whose loads are in flight together
 
+constexpr uint32_t kCapSteps = 8;  // steps of 256 buckets whose sample counts are loaded together
+
 __device__ __forceinline__ void capacity_body(const uint32_t* __restrict__ hist, uint64_t S, uint64_t n, uint32_t B,
                                               double scale, uint32_t* __restrict__ caps,
                                               uint32_t* __restrict__ rstart, uint32_t* __restrict__ counts,
@@ -650,20 +652,23 @@ __device__ __forceinline__ void capacity_body(const uint32_t* __restrict__ hist,
   };
   // region size of bucket j from its sample count h: h sample keys estimate
   // the bucket's mass as h / S with a standard deviation of about sqrt(h) / S,
-  // and the region covers two of them
+  // and the region covers two of them (the root in single precision: h is
+  // exact there, and FP64 square roots and divisions took most of this
+  // one-CU kernel's time)
+  const double per = (double)n / (double)S;
   auto size_of = [&](uint32_t j, uint32_t h) {
     const double hd = (double)h;
-    const double expect = (hd + 2.0 * sqrt(hd)) * (double)n / (double)S;
+    const double expect = (hd + 2.0 * (double)sqrtf((float)h)) * per;
     const double m = expect > ideal ? expect : ideal;
     return j < s1 ? ((uint32_t)ceil(scale * m) + 16u + 1u) & ~1u : 0u;
   };
   uint64_t s = 0;
-  for (uint32_t jb = s0; jb < s1; jb += 256 * kScanSteps) {
-    uint32_t h[kScanSteps][4];
+  for (uint32_t jb = s0; jb < s1; jb += 256 * kCapSteps) {
+    uint32_t h[kCapSteps][4];
 #pragma unroll
-    for (uint32_t u = 0; u < kScanSteps; ++u) load4(jb + 256 * u + 4 * l, h[u]);
+    for (uint32_t u = 0; u < kCapSteps; ++u) load4(jb + 256 * u + 4 * l, h[u]);
 #pragma unroll
-    for (uint32_t u = 0; u < kScanSteps; ++u)
+    for (uint32_t u = 0; u < kCapSteps; ++u)
 #pragma unroll
       for (uint32_t q = 0; q < 4; ++q) s += size_of(jb + 256 * u + 4 * l + q, h[u][q]);
   }
@@ -680,12 +685,12 @@ __device__ __forceinline__ void capacity_body(const uint32_t* __restrict__ hist,
   }
   __syncthreads();
   uint64_t run = sh[w];
-  for (uint32_t jb = s0; jb < s1; jb += 256 * kScanSteps) {
-    uint32_t h[kScanSteps][4];
+  for (uint32_t jb = s0; jb < s1; jb += 256 * kCapSteps) {
+    uint32_t h[kCapSteps][4];
 #pragma unroll
-    for (uint32_t u = 0; u < kScanSteps; ++u) load4(jb + 256 * u + 4 * l, h[u]);
+    for (uint32_t u = 0; u < kCapSteps; ++u) load4(jb + 256 * u + 4 * l, h[u]);
 #pragma unroll
-    for (uint32_t u = 0; u < kScanSteps; ++u) {
+    for (uint32_t u = 0; u < kCapSteps; ++u) {
       const uint32_t j = jb + 256 * u + 4 * l;
       uint32_t c[4];
 #pragma unroll

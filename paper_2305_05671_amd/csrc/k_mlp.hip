@@ -494,7 +494,7 @@ __global__ __launch_bounds__(256) void quantile_first_kernel(const uint64_t* __r
     first[L] = (uint32_t)S;
     hdr->mlp_L = L;
     hdr->spline_K = spline_segments(L);
-    hdr->max_sample_run = 0;
+    hdr->max_sample_run = S ? 1u : 0u;  // runs of one; longer ones are added by the sample statistics
     return;
   }
   const uint64_t q = ((uint64_t)j * S) / L;
@@ -621,8 +621,15 @@ __global__ __launch_bounds__(256) void mlp_cell_table_kernel(const MlpBlock* __r
   if (i <= L) cells[i] = lo;
 }
 
-// Per sample: its bucket under the equi-depth leaves (leaf found from first[]), and
-// the longest run of equal codes (no monotone bucketing can split a run).
+// The sample histogram under the equi-depth leaves, and the longest run of
+// equal codes (no monotone bucketing can split a run).  With one leaf per
+// bucket a leaf's count is its sample range, first[j + 1] - first[j] (thread
+// j); otherwise each sample finds its leaf (the last j with first[j] <= s) and
+// its bucket there, with one add per run of equal buckets within a wave (the
+// sample is sorted).  A run's length is found at its last sample, by a search
+// for its first only when the run is longer than one; each wave adds its
+// longest once, and only if it is longer than one (atomics on one address
+// serialise: one per wave over 10^6 samples took 0.17 ms).
 __global__ __launch_bounds__(256) void mlp_sample_stats_kernel(const uint64_t* __restrict__ e, uint64_t S,
                                                                uint32_t L, uint32_t B, const uint32_t* __restrict__ first,
                                                                const Leaf* __restrict__ leaves,
@@ -632,21 +639,33 @@ __global__ __launch_bounds__(256) void mlp_sample_stats_kernel(const uint64_t* _
   const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = s < S;
   const uint64_t c = e[in ? s : S - 1];
+  uint32_t run = 0;
   if (in && (s + 1 == S || e[s + 1] != c)) {
-    uint64_t lo = 0, hi = s;
-    while (lo < hi) {
-      const uint64_t mid = (lo + hi) >> 1;
-      if (e[mid] < c) lo = mid + 1; else hi = mid;
+    run = 1;
+    if (s > 0 && e[s - 1] == c) {
+      uint64_t lo = 0, hi = s - 1;  // the first position holding c; e[hi] == c
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (e[mid] < c) lo = mid + 1; else hi = mid;
+      }
+      run = (uint32_t)(s + 1 - lo);
     }
-    atomicMax(&hdr->max_sample_run, (uint32_t)(s + 1 - lo));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t o = __shfl_xor(run, off);
+    run = o > run ? o : run;
+  }
+  if (__lane_id() == 0 && run > 1) atomicMax(&hdr->max_sample_run, run);  // one address: only longer runs
+  if (L == B) {
+    if (s < L) hist[s] = first[s + 1] - first[s];
+    return;
   }
   uint32_t lo = 0, hi = L;  // last j with first[j] <= s
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
     if (first[mid] <= s) lo = mid; else hi = mid;
   }
-  // one add per run of equal buckets within the wave (the sample is sorted)
-  const uint32_t b = L == B ? lo : leaf_bucket(load_leaf(leaves, lo), c);  // one leaf per bucket: the leaf
+  const uint32_t b = leaf_bucket(load_leaf(leaves, lo), c);
   const uint32_t l = __lane_id();
   const uint32_t bl = __shfl_up(b, 1), br = __shfl_down(b, 1);
   const bool start = in && (l == 0 || bl != b);
@@ -695,19 +714,23 @@ __global__ __launch_bounds__(256) void mlp_net_hist_kernel(const MlpBlock* __res
 // lambda = S/B (about the largest of B Poisson(lambda) counts).  Under the
 // automatic choice a passing linear root is kept and the equi-depth leaves are
 // not fitted (mlp_skip).  One block.
-__global__ __launch_bounds__(256) void auto_gate_kernel(const uint32_t* __restrict__ hist_rmi, uint32_t B,
-                                                        uint64_t S, float accept_ratio, uint32_t kind,
-                                                        ModelHeader* __restrict__ hdr) {
-  __shared__ uint32_t mr[256];
+constexpr uint32_t kGateThreads = 1024;
+
+__global__ __launch_bounds__(kGateThreads) void auto_gate_kernel(const uint32_t* __restrict__ hist_rmi, uint32_t B,
+                                                                 uint64_t S, float accept_ratio, uint32_t kind,
+                                                                 ModelHeader* __restrict__ hdr) {
+  __shared__ uint32_t mr[kGateThreads / 64];
   uint32_t a = 0;
-  for (uint32_t j = threadIdx.x; j < B; j += 256) a = hist_rmi[j] > a ? hist_rmi[j] : a;
-  mr[threadIdx.x] = a;
-  __syncthreads();
-  for (uint32_t off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off && mr[threadIdx.x + off] > mr[threadIdx.x]) mr[threadIdx.x] = mr[threadIdx.x + off];
-    __syncthreads();
+#pragma unroll 4
+  for (uint32_t j = threadIdx.x; j < B; j += kGateThreads) a = hist_rmi[j] > a ? hist_rmi[j] : a;
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t x = __shfl_xor(a, off);
+    a = x > a ? x : a;
   }
+  if (__lane_id() == 0) mr[threadIdx.x >> 6] = a;
+  __syncthreads();
   if (threadIdx.x == 0) {
+    for (uint32_t w = 1; w < kGateThreads / 64; ++w) mr[0] = mr[w] > mr[0] ? mr[w] : mr[0];
     const double lambda = (double)S / (double)B;
     const double perfect = lambda + sqrt(2.0 * log((double)B) * lambda) + 1.0;
     const bool ok = (double)mr[0] <= (double)accept_ratio * perfect;
@@ -834,8 +857,9 @@ hipError_t launch_equi_depth_leaves(const uint64_t* e, uint64_t S, uint32_t L, u
   code_cell_kernel<<<(code_cells_for(L) + 1 + 255) / 256, 256, 0, st>>>(ms.bound, L, ms.ccells, hdr);
   hipError_t err = launch_fill_u32(ms.hist, B, 0u, st);
   if (err != hipSuccess) return err;
-  mlp_sample_stats_kernel<<<(uint32_t)((S + 255) / 256), 256, 0, st>>>(e, S, L, B, ms.first, ms.leaves, ms.hist,
-                                                                        hdr);
+  const uint64_t threads = S > L ? S : L;
+  mlp_sample_stats_kernel<<<(uint32_t)((threads + 255) / 256), 256, 0, st>>>(e, S, L, B, ms.first, ms.leaves,
+                                                                              ms.hist, hdr);
   return hipGetLastError();
 }
 
@@ -847,7 +871,7 @@ hipError_t launch_mlp_cell_table(const MlpState& ms, uint32_t L, hipStream_t st)
 
 hipError_t launch_auto_gate(const uint32_t* hist_rmi, uint32_t B, uint64_t S, float accept_ratio, uint32_t kind,
                             ModelHeader* hdr, hipStream_t st) {
-  auto_gate_kernel<<<1, 256, 0, st>>>(hist_rmi, B, S, accept_ratio, kind, hdr);
+  auto_gate_kernel<<<1, kGateThreads, 0, st>>>(hist_rmi, B, S, accept_ratio, kind, hdr);
   return hipGetLastError();
 }
 

@@ -503,7 +503,7 @@ hipError_t launch_exact_regions(const uint32_t* counts_all, uint32_t lo, uint32_
 // each step across the wave and writes the offsets.
 constexpr uint32_t kScanThreads = 1024;
 constexpr uint32_t kScanWaves = kScanThreads / 64;
-constexpr uint32_t kScanSteps = 4;  // steps of 256 buckets whose loads are in flight together
+constexpr uint32_t kScanSteps = 8;  // steps of 256 buckets whose loads are in flight together
 
 // counts: the partition's slot counters, cstride apart; with cstride > 1 the
 // dense counts the bucket sorts read go to dense.
@@ -514,6 +514,12 @@ __device__ __forceinline__ void scan_counts_body(const uint32_t* __restrict__ co
                                                  uint32_t* __restrict__ big_list, PartHeader* __restrict__ ph) {
   __shared__ uint64_t shc[kScanWaves + 1];
   __shared__ uint32_t shs[kScanWaves];
+  __shared__ uint32_t sh_nmid, sh_nbig;  // list lengths: LDS atomics (one global address would serialise them)
+  if (threadIdx.x == 0) {
+    sh_nmid = 0;
+    sh_nbig = 0;
+  }
+  __syncthreads();
   const uint32_t WS = ((B + kScanWaves - 1) / kScanWaves + 1023) & ~1023u;
   const uint32_t w = threadIdx.x >> 6, l = lane_id();
   const uint32_t s0 = w * WS, s1 = s0 + WS < B ? s0 + WS : B;  // empty when s0 >= B
@@ -557,10 +563,10 @@ __device__ __forceinline__ void scan_counts_body(const uint32_t* __restrict__ co
         if (cq > kSmallCap) {  // zero past the segment
           const uint32_t j = jb + 256 * u + 4 * l + q;
           if (cq <= kMidCap) {
-            mid_list[atomicAdd(&ph->n_mid, 1u)] = j;
+            mid_list[atomicAdd(&sh_nmid, 1u)] = j;
             mr += cq;
           } else {
-            big_list[atomicAdd(&ph->n_big, 1u)] = j;
+            big_list[atomicAdd(&sh_nbig, 1u)] = j;
             br += cq;
           }
         }
@@ -595,6 +601,8 @@ __device__ __forceinline__ void scan_counts_body(const uint32_t* __restrict__ co
       rs += x;
     }
     shc[kScanWaves] = rc;
+    ph->n_mid = sh_nmid;
+    ph->n_big = sh_nbig;
   }
   __syncthreads();
   uint64_t rc = shc[w];
