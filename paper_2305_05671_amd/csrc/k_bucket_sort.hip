@@ -625,18 +625,34 @@ __device__ __forceinline__ void bucket_sort_lds_body(
     br.rs = rstart[j];
     br.so = spill_off[j];
     br.out0 = offsets[j];
-    // 1. load the entries, and the range of their base-95 codes
+    // 1. load the entries (every thread's slot heads in flight together), and
+    //    the range of their base-95 codes
     uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
     uint64_t cmin = ~0ull, cmax = 0;
-    for (uint32_t p = threadIdx.x; p < br.n; p += THREADS) {
-      uint32_t sl = slot_of(br, p, spill_map, cap_slots);
-      uint4 c = composite(slots + (uint64_t)sl * W, K, vk);
-      ent[p] = c;
-      o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
-      a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
-      const uint64_t e = key_code(__builtin_bswap32(c.x), __builtin_bswap32(c.y));  // composite words are big-endian
-      cmin = e < cmin ? e : cmin;
-      cmax = e > cmax ? e : cmax;
+    constexpr uint32_t NL = (CAP / THREADS) % 3 == 0 ? 3 : 4;  // heads per thread in flight
+    for (uint32_t p0 = 0; p0 < br.n; p0 += NL * THREADS) {
+     uint4 hv[NL];
+#pragma unroll
+     for (uint32_t i = 0; i < NL; ++i) {
+      const uint32_t p = p0 + threadIdx.x + i * THREADS;
+      if (p < br.n)
+        hv[i] = *reinterpret_cast<const uint4*>(slots + (uint64_t)slot_of(br, p, spill_map, cap_slots) * W);
+     }
+#pragma unroll
+     for (uint32_t i = 0; i < NL; ++i) {
+      const uint32_t p = p0 + threadIdx.x + i * THREADS;
+      if (p < br.n) {
+        uint32_t r0 = hv[i].y, r1 = hv[i].z, r2 = hv[i].w;
+        virtual_key(r0, r1, r2, vk);
+        const uint4 c = composite_words(hv[i].x, r0, r1, r2, K);
+        ent[p] = c;
+        o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
+        a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+        const uint64_t e = key_code(r0, r1);
+        cmin = e < cmin ? e : cmin;
+        cmax = e > cmax ? e : cmax;
+      }
+     }
     }
     const uint4 diff = block_diff<THREADS>(o, a, sh_or, sh_and);  // syncs
     const uint32_t vary = vary_mask(diff);
@@ -744,6 +760,8 @@ constexpr uint32_t kEqCap = 16384;
 constexpr uint32_t kEqThreads = 1024;
 constexpr uint32_t kEqBits = 12;  // counting digit: 4096 bins of the index range
 
+constexpr uint32_t kEqLoads = 2;  // slot heads per thread in flight
+
 __device__ __forceinline__ void equal_keys_body(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
@@ -793,18 +811,32 @@ __device__ __forceinline__ void equal_keys_body(
       if (tid == 0) list2[atomicAdd(list2_n, 1u)] = j;
       continue;
     }
-    // 2. heads: the key words (OR / AND across the bucket), the indices and their range
+    // 2. heads: the key words (OR / AND across the bucket), the indices and
+    //    their range; kEqLoads heads per thread in flight together
     uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
     uint64_t imin = ~0ull, imax = 0;
-    for (uint32_t p = tid; p < n; p += kEqThreads) {
-      const uint32_t* sl = slots + (uint64_t)slot_of(br, p, spill_map, cap_slots) * W;
-      const uint4 c = composite(sl, K, vk);
-      o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
-      a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
-      const uint32_t x = sl[0];
-      idx[p] = x;
-      imin = x < imin ? x : imin;
-      imax = x > imax ? x : imax;
+    for (uint32_t p0 = 0; p0 < n; p0 += kEqLoads * kEqThreads) {
+      uint4 hv[kEqLoads];
+#pragma unroll
+      for (uint32_t i = 0; i < kEqLoads; ++i) {
+        const uint32_t p = p0 + tid + i * kEqThreads;
+        if (p < n) hv[i] = *reinterpret_cast<const uint4*>(slots + (uint64_t)slot_of(br, p, spill_map, cap_slots) * W);
+      }
+#pragma unroll
+      for (uint32_t i = 0; i < kEqLoads; ++i) {
+        const uint32_t p = p0 + tid + i * kEqThreads;
+        if (p < n) {
+          uint32_t r0 = hv[i].y, r1 = hv[i].z, r2 = hv[i].w;
+          virtual_key(r0, r1, r2, vk);
+          const uint4 c = composite_words(hv[i].x, r0, r1, r2, K);
+          o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
+          a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+          const uint32_t x = hv[i].x;
+          idx[p] = x;
+          imin = x < imin ? x : imin;
+          imax = x > imax ? x : imax;
+        }
+      }
     }
     const uint32_t vary = vary_mask(block_diff<kEqThreads>(o, a, sh_or, sh_and));  // syncs
     if (vary & key_mask) {  // the keys differ after all: the general split takes the bucket
