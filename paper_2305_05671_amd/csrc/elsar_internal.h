@@ -49,7 +49,8 @@ struct ModelHeader {   // device-resident root of a fitted model
   uint32_t max_rmi, max_eq, max_net, rmi_ok;
   float perfect;
   uint32_t cell_shift;  // equi-depth leaves: code-cell width 2^cell_shift (code_cell)
-  uint32_t pad_[2];
+  uint32_t cell_sub_used;  // entries of the code-cell table's sub-tables in use
+  uint32_t pad_;
 };
 
 // Monotone MLP root (8 -> 64 -> 64 -> 1), flat parameter order W1 (64x8),
@@ -227,10 +228,28 @@ __host__ __device__ __forceinline__ uint32_t spline_segments(uint32_t L) { retur
 // With about four cells per leaf most cells hold no boundary and the table
 // read alone names the leaf (against about 16 probes for a search over
 // segment knots then leaves).
+// Where the keys are dense in code space (the skewed law's per-byte peaks
+// put tens of boundaries in one cell: about four probes per record on
+// average), a cell with more than kCellDense boundaries has a sub-table of
+// 2^k cells of its own (2^k at least twice its boundaries, k at most
+// cell_shift): entry s counts the boundaries below its sub-cell s, exactly as
+// the cells do, so the search narrows to the boundaries of the code's
+// sub-cell.  Layout (32-bit words): per cell c a pair {ccells[c], info[c]},
+// info = (sub-table offset << 5) | k or 0 (no sub-table), for c = 0..NC (the
+// pair NC holds the boundary count only), then the sub-tables, at most
+// 4 L + NC + 1 words in all (2^k + 1 entries each, 2^k < 4 x the cell's
+// boundaries).
+constexpr uint32_t kCellDense = 3;
+
 __host__ __device__ __forceinline__ uint32_t code_cells_for(uint32_t L) {
   uint32_t nc = 1024;
   while (nc < 4u * L && nc < (1u << 18)) nc <<= 1;
   return nc;
+}
+
+__host__ __device__ __forceinline__ size_t cell_table_words(uint32_t L) {
+  const size_t nc = code_cells_for(L);
+  return 2 * (nc + 1) + 4 * (size_t)L + nc + 1;
 }
 
 __host__ __device__ __forceinline__ uint32_t code_cell(uint64_t e, uint64_t e0, uint32_t shift, uint32_t nc) {
@@ -238,11 +257,30 @@ __host__ __device__ __forceinline__ uint32_t code_cell(uint64_t e, uint64_t e0, 
   return d < nc ? (uint32_t)d : nc - 1;
 }
 
+// Sub-cell of a code in dense cell c (codes below bound[1] in sub-cell 0,
+// codes past the cell in its last).
+__host__ __device__ __forceinline__ uint32_t code_subcell(uint64_t e, uint64_t e0, uint32_t shift, uint32_t c,
+                                                          uint32_t k) {
+  const uint64_t d = e > e0 ? (e - e0) >> (shift - k) : 0ull;
+  const uint64_t rel = d - ((uint64_t)c << k);  // d >= c << k: the code's cell is c or it was clamped to c
+  return rel < (1ull << k) ? (uint32_t)rel : (1u << k) - 1u;
+}
+
 __device__ __forceinline__ uint32_t cell_exact_leaf(const uint32_t* __restrict__ ccells, uint32_t shift,
                                                     uint32_t nc, uint64_t e0, const uint64_t* __restrict__ bound,
                                                     uint64_t code) {
   const uint32_t c = code_cell(code, e0, shift, nc);
-  uint32_t a = ccells[c], b = ccells[c + 1] + 1;  // bound[a] <= code < bound[b] (bound[L] never read)
+  const uint2* cl = reinterpret_cast<const uint2*>(ccells);
+  const uint2 x = cl[c];
+  uint32_t a = x.x, b = cl[c + 1].x;
+  if (x.y) {
+    const uint32_t k = x.y & 31u;
+    const uint32_t* sub = ccells + 2 * ((size_t)nc + 1) + (x.y >> 5);
+    const uint32_t s = code_subcell(code, e0, shift, c, k);
+    a = sub[s];
+    b = sub[s + 1];
+  }
+  b += 1;  // bound[a] <= code < bound[b] (bound[L] never read)
   while (b - a > 1) {
     const uint32_t mid = (a + b) >> 1;
     if (bound[mid] <= code) a = mid; else b = mid;

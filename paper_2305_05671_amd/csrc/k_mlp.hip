@@ -32,7 +32,7 @@ inline size_t al(size_t x) { return (x + kA - 1) & ~(kA - 1); }
 
 size_t mlp_state_bytes(uint32_t L, uint32_t B) {
   return al(sizeof(MlpBlock)) + al((size_t)L * sizeof(Leaf)) + al(((size_t)L + 1) * 8) + al(((size_t)L + 1) * 4) +
-         2 * al((size_t)B * 4) + al(((size_t)spline_segments(L) + 1) * 8) + al(((size_t)code_cells_for(L) + 1) * 4) +
+         2 * al((size_t)B * 4) + al(((size_t)spline_segments(L) + 1) * 8) + al(cell_table_words(L) * 4) +
          al(((size_t)L + 1) * 4) +
          al((size_t)kMlpParams * 4) + al((size_t)kMlpParams * 8);
 }
@@ -54,7 +54,7 @@ void place_mlp_state(MlpState* s, void* base, uint32_t L, uint32_t B) {
   s->knots = reinterpret_cast<uint64_t*>(b);
   b += al(((size_t)spline_segments(L) + 1) * 8);
   s->ccells = reinterpret_cast<uint32_t*>(b);
-  b += al(((size_t)code_cells_for(L) + 1) * 4);
+  b += al(cell_table_words(L) * 4);
   s->cells = reinterpret_cast<uint32_t*>(b);
   b += al(((size_t)L + 1) * 4);
   s->master = reinterpret_cast<float*>(b);
@@ -578,7 +578,10 @@ __global__ __launch_bounds__(256) void code_cell_kernel(const uint64_t* __restri
   const uint32_t nc = code_cells_for(L);
   while ((range >> shift) >= nc) ++shift;
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c == 0) hdr->cell_shift = shift;
+  if (c == 0) {
+    hdr->cell_shift = shift;
+    hdr->cell_sub_used = 0;
+  }
   if (c > nc) return;
   uint32_t lo = 1, hi = L > 0 ? L : 1;  // first j in [1, L) whose cell is >= c (hi if none)
   while (lo < hi) {
@@ -586,7 +589,49 @@ __global__ __launch_bounds__(256) void code_cell_kernel(const uint64_t* __restri
     if (code_cell(bound[mid], e0, shift, nc) < c) lo = mid + 1;
     else hi = mid;
   }
-  ccells[c] = lo - 1;
+  reinterpret_cast<uint2*>(ccells)[c] = make_uint2(lo - 1, 0u);
+}
+
+// Sub-tables of the dense cells (cell_exact_leaf): one thread per cell; a
+// block's sub-tables are placed together (one atomic per block on the
+// header's counter), then each dense cell's thread walks its boundaries once:
+// entry s = boundaries below the cell + those of its sub-cells below s.
+__global__ __launch_bounds__(256) void code_subcell_kernel(const uint64_t* __restrict__ bound, uint32_t L,
+                                                           uint32_t* __restrict__ ccells,
+                                                           ModelHeader* __restrict__ hdr) {
+  if (hdr->mlp_skip) return;
+  __shared__ uint32_t sh_scan[256 / 64 + 1];
+  __shared__ uint32_t base;
+  const uint32_t nc = code_cells_for(L), shift = hdr->cell_shift;
+  const uint64_t e0 = L >= 2 ? bound[1] : 0ull;
+  uint2* cl = reinterpret_cast<uint2*>(ccells);
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t lo = 0, hi = 0, k = 0, size = 0;
+  if (c < nc) {
+    lo = cl[c].x;
+    hi = cl[c + 1].x;
+    if (hi - lo > kCellDense) {
+      k = 1;
+      while ((1u << k) < hi - lo) ++k;
+      ++k;  // at least two sub-cells per boundary
+      k = k < shift ? k : shift;
+      k = k < 16u ? k : 16u;
+      size = k ? (1u << k) + 1u : 0u;
+    }
+  }
+  uint32_t total;
+  const uint32_t off = block_exclusive_scan<uint32_t, 256>(size, sh_scan, &total);
+  if (threadIdx.x == 0 && total) base = atomicAdd(&hdr->cell_sub_used, total);
+  __syncthreads();
+  if (!size) return;
+  const uint32_t o = base + off;
+  uint32_t* sub = ccells + 2 * ((size_t)nc + 1) + o;
+  uint32_t i = lo + 1;  // the cell's boundaries are bound[lo + 1 .. hi]
+  for (uint32_t s = 0; s <= (1u << k); ++s) {
+    while (i <= hi && code_subcell(bound[i], e0, shift, c, k) < s) ++i;
+    sub[s] = i - 1;
+  }
+  cl[c].y = (o << 5) | k;
 }
 
 // Cell table of the MLP root.  Cell c of the network's output is [c/L,
@@ -855,6 +900,7 @@ hipError_t launch_equi_depth_leaves(const uint64_t* e, uint64_t S, uint32_t L, u
   mlp_leaf_fit_kernel<<<(L + 255) / 256, 256, 0, st>>>(e, S, L, B, ms.first, ms.leaves, ms.bound, hdr);
   spline_knots_kernel<<<(K + 1 + 255) / 256, 256, 0, st>>>(ms.bound, L, K, ms.knots, hdr);
   code_cell_kernel<<<(code_cells_for(L) + 1 + 255) / 256, 256, 0, st>>>(ms.bound, L, ms.ccells, hdr);
+  code_subcell_kernel<<<(code_cells_for(L) + 255) / 256, 256, 0, st>>>(ms.bound, L, ms.ccells, hdr);
   hipError_t err = launch_fill_u32(ms.hist, B, 0u, st);
   if (err != hipSuccess) return err;
   const uint64_t threads = S > L ? S : L;
