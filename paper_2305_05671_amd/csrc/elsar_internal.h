@@ -49,8 +49,7 @@ struct ModelHeader {   // device-resident root of a fitted model
   uint32_t max_rmi, max_eq, max_net, rmi_ok;
   float perfect;
   uint32_t cell_shift;  // equi-depth leaves: code-cell width 2^cell_shift (code_cell)
-  uint32_t cell_sub_used;  // entries of the code-cell table's sub-tables in use
-  uint32_t pad_;
+  uint32_t pad_[2];
 };
 
 // Monotone MLP root (8 -> 64 -> 64 -> 1), flat parameter order W1 (64x8),
@@ -236,9 +235,10 @@ __host__ __device__ __forceinline__ uint32_t spline_segments(uint32_t L) { retur
 // the cells do, so the search narrows to the boundaries of the code's
 // sub-cell.  Layout (32-bit words): per cell c a pair {ccells[c], info[c]},
 // info = (sub-table offset << 5) | k or 0 (no sub-table), for c = 0..NC (the
-// pair NC holds the boundary count only), then the sub-tables, at most
-// 4 L + NC + 1 words in all (2^k + 1 entries each, 2^k < 4 x the cell's
-// boundaries).
+// pair NC holds the boundary count only), then the sub-tables: cell c's at
+// offset 4 ccells[c] + c, 2^k + 1 <= 4 (ccells[c + 1] - ccells[c]) entries
+// (2^k < 4 x the cell's boundaries), so the tables never overlap and fit in
+// 4 L + NC + 1 words without any allocation step.
 constexpr uint32_t kCellDense = 3;
 
 __host__ __device__ __forceinline__ uint32_t code_cells_for(uint32_t L) {

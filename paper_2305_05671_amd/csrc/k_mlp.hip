@@ -578,10 +578,7 @@ __global__ __launch_bounds__(256) void code_cell_kernel(const uint64_t* __restri
   const uint32_t nc = code_cells_for(L);
   while ((range >> shift) >= nc) ++shift;
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c == 0) {
-    hdr->cell_shift = shift;
-    hdr->cell_sub_used = 0;
-  }
+  if (c == 0) hdr->cell_shift = shift;
   if (c > nc) return;
   uint32_t lo = 1, hi = L > 0 ? L : 1;  // first j in [1, L) whose cell is >= c (hi if none)
   while (lo < hi) {
@@ -592,47 +589,40 @@ __global__ __launch_bounds__(256) void code_cell_kernel(const uint64_t* __restri
   reinterpret_cast<uint2*>(ccells)[c] = make_uint2(lo - 1, 0u);
 }
 
-// Sub-tables of the dense cells (cell_exact_leaf): one thread per cell; a
-// block's sub-tables are placed together (one atomic per block on the
-// header's counter), then each dense cell's thread walks its boundaries once:
-// entry s = boundaries below the cell + those of its sub-cells below s.
+// Sub-tables of the dense cells (cell_exact_leaf): one wave per cell; entry s
+// (one lane each) = the boundaries below the cell + those of its sub-cells
+// below s, by a binary search over the cell's boundaries.
 __global__ __launch_bounds__(256) void code_subcell_kernel(const uint64_t* __restrict__ bound, uint32_t L,
                                                            uint32_t* __restrict__ ccells,
                                                            ModelHeader* __restrict__ hdr) {
   if (hdr->mlp_skip) return;
-  __shared__ uint32_t sh_scan[256 / 64 + 1];
-  __shared__ uint32_t base;
   const uint32_t nc = code_cells_for(L), shift = hdr->cell_shift;
-  const uint64_t e0 = L >= 2 ? bound[1] : 0ull;
+  const uint32_t c = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63u;
+  if (c >= nc) return;
   uint2* cl = reinterpret_cast<uint2*>(ccells);
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t lo = 0, hi = 0, k = 0, size = 0;
-  if (c < nc) {
-    lo = cl[c].x;
-    hi = cl[c + 1].x;
-    if (hi - lo > kCellDense) {
-      k = 1;
-      while ((1u << k) < hi - lo) ++k;
-      ++k;  // at least two sub-cells per boundary
-      k = k < shift ? k : shift;
-      k = k < 16u ? k : 16u;
-      size = k ? (1u << k) + 1u : 0u;
-    }
-  }
-  uint32_t total;
-  const uint32_t off = block_exclusive_scan<uint32_t, 256>(size, sh_scan, &total);
-  if (threadIdx.x == 0 && total) base = atomicAdd(&hdr->cell_sub_used, total);
-  __syncthreads();
-  if (!size) return;
-  const uint32_t o = base + off;
+  const uint32_t lo = cl[c].x, hi = cl[c + 1].x;  // the cell's boundaries are bound[lo + 1 .. hi]
+  if (hi - lo <= kCellDense) return;
+  uint32_t k = 1;
+  while ((1u << k) < hi - lo) ++k;
+  ++k;  // at least two sub-cells per boundary
+  k = k < shift ? k : shift;
+  k = k < 16u ? k : 16u;
+  if (k == 0) return;  // cells one code wide: nothing to split
+  const uint64_t e0 = L >= 2 ? bound[1] : 0ull;
+  const uint32_t o = 4 * lo + c;
   uint32_t* sub = ccells + 2 * ((size_t)nc + 1) + o;
-  uint32_t i = lo + 1;  // the cell's boundaries are bound[lo + 1 .. hi]
-  for (uint32_t s = 0; s <= (1u << k); ++s) {
-    while (i <= hi && code_subcell(bound[i], e0, shift, c, k) < s) ++i;
-    sub[s] = i - 1;
+  for (uint32_t s = lane; s <= (1u << k); s += 64) {
+    uint32_t a = lo + 1, b = hi + 1;  // first boundary of the cell in sub-cell s or above (b if none)
+    while (a < b) {
+      const uint32_t mid = (a + b) >> 1;
+      if (code_subcell(bound[mid], e0, shift, c, k) < s) a = mid + 1;
+      else b = mid;
+    }
+    sub[s] = a - 1;
   }
-  cl[c].y = (o << 5) | k;
+  if (lane == 0) cl[c].y = (o << 5) | k;
 }
+
 
 // Cell table of the MLP root.  Cell c of the network's output is [c/L,
 // (c+1)/L); cells[c] counts the leaves j whose boundary code bound[j] lands in
@@ -900,7 +890,7 @@ hipError_t launch_equi_depth_leaves(const uint64_t* e, uint64_t S, uint32_t L, u
   mlp_leaf_fit_kernel<<<(L + 255) / 256, 256, 0, st>>>(e, S, L, B, ms.first, ms.leaves, ms.bound, hdr);
   spline_knots_kernel<<<(K + 1 + 255) / 256, 256, 0, st>>>(ms.bound, L, K, ms.knots, hdr);
   code_cell_kernel<<<(code_cells_for(L) + 1 + 255) / 256, 256, 0, st>>>(ms.bound, L, ms.ccells, hdr);
-  code_subcell_kernel<<<(code_cells_for(L) + 255) / 256, 256, 0, st>>>(ms.bound, L, ms.ccells, hdr);
+  code_subcell_kernel<<<(code_cells_for(L) + 3) / 4, 256, 0, st>>>(ms.bound, L, ms.ccells, hdr);
   hipError_t err = launch_fill_u32(ms.hist, B, 0u, st);
   if (err != hipSuccess) return err;
   const uint64_t threads = S > L ? S : L;
