@@ -57,6 +57,35 @@ def test_sort_matches_oracle(env, kind, n, B, seed):
     _assert_same(_gpu_sort(env, recs, num_buckets=B, seed=seed), oracle.sort_records(recs))
 
 
+@pytest.mark.parametrize("n,B,kind", [
+    (300_000, 256, "SPLINE"),  # about 1170 records a bucket: the small-bucket kernel
+    (400_000, 128, "SPLINE"),  # about 3125: the mid-bucket kernel
+    (600_000, 16, "RMI"),      # far above the caps: the split's segments
+])
+def test_clustered_keys_refined_bins(env, n, B, kind):
+    """Keys clustered at every byte (the skewed law without its hot keys)
+    crowd the counting digit's bins, so each of these kernels takes its second,
+    finer counting pass; the order must stay exact."""
+    torch, elsar = env
+    recs = datagen.generate(datagen.spec("skewed", seed=31, hot_fraction=0.0, embed_idx=True), n)
+    got = _gpu_sort(env, recs, num_buckets=B, seed=31, kind=getattr(elsar, kind))
+    _assert_same(got, oracle.sort_records(recs))
+
+
+def test_batch_tiny_clustered_jobs(env):
+    """Jobs of at most 2048 records of the clustered law: the tiny-jobs kernel's
+    refined counting pass."""
+    torch, elsar = env
+    sizes = [2048, 1500, 700, 2000, 3]
+    recs = [datagen.generate(datagen.spec("skewed", seed=40 + i, hot_fraction=0.0), s) for i, s in enumerate(sizes)]
+    dev = [_to_dev(torch, r) for r in recs]
+    outs = [torch.empty_like(d) for d in dev]
+    elsar.sort_batch(dev, outs)
+    torch.cuda.synchronize()
+    for r, o in zip(recs, outs):
+        _assert_same(o.cpu().numpy().reshape(-1, R), oracle.sort_records(r))
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 100, 1000, 2047, 2048, 2049, 6144, 6145, 10_007, 65_537])
 def test_edge_sizes(env, n):
     recs = datagen.generate(datagen.spec("uniform", seed=n), n)
