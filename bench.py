@@ -86,12 +86,20 @@ def parse():
 
 
 def source_hash() -> str:
+    """Hash of the library's code: the HIP sources with comments and blank
+    space removed, so that an edit of a comment does not count as a kernel
+    change."""
     import hashlib
+    import re
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2305_05671_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(d, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(f.encode())
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

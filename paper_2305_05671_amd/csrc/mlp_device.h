@@ -2,14 +2,16 @@
 // helper and the evaluation shared by the cell-table, forward and partition
 // kernels, plus the leaf routers.
 //
-// Matrix-core layouts (one wave, 16x16 outputs): for
-// v_mfma_f32_16x16x16bf16_1k lane l holds A[l%16][4(l/16)+e],
-// B[4(l/16)+e][l%16] and D[4(l/16)+e][l%16] for e = 0..3; for gfx950's
+// Matrix-core layouts (one wave, 16x16 outputs): for gfx950's
 // v_mfma_f32_16x16x32_bf16 lane l holds A[l%16][8(l/16)+e] and
-// B[8(l/16)+e][l%16] for e = 0..7, D as above; for v_mfma_f32_16x16x4_f32
-// lane l holds A[l%16][l/16] and B[l/16][l%16], and D as above.  Training computes records x units (layer-1 units of record l%16
-// become the A fragments of the layer-2 product); evaluation computes units x
-// records (mlp_y64).
+// B[8(l/16)+e][l%16] for e = 0..7, and D[4(l/16)+e][l%16] for e = 0..3; for
+// v_mfma_f32_16x16x4_f32 lane l holds A[l%16][l/16] and B[l/16][l%16], D as
+// above.  The bfloat16 fragments are built as groups of four K-indices per
+// lane, 4(l/16)+e of a 16-wide K-step, and two K-steps' groups are joined
+// into the eight a 16x16x32 product takes (cat8_bf16): a contraction only
+// needs A and B to list K in the same order.  Training computes records x
+// units (layer-1 units of record l%16 become the A fragments of the layer-2
+// product); evaluation computes units x records (mlp_y64).
 #pragma once
 #include "elsar_internal.h"
 
