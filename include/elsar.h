@@ -174,9 +174,10 @@ elsar_status elsar_partition(const elsar_model* m, const void* d_records, uint64
  * sort is then in place) but must not overlap d_part.  d_part and
  * d_bucket_offsets are those elsar_partition took (same alignment checks).  The call uses d_part's
  * bookkeeping area as scratch; the records in d_part are left as they are,
- * except with keys longer than 12 bytes, whose run pass (Section 4's
- * last-mile ordering of the bytes past the encoded prefix) then reuses the
- * record area as scratch.  Asynchronous.
+ * so the call may be repeated on one partition (into the same or another
+ * output), except with keys longer than 12 bytes, whose run pass (Section
+ * 4's last-mile ordering of the bytes past the encoded prefix) then reuses
+ * the record area as scratch.  Asynchronous.
  */
 elsar_status elsar_sort_buckets(const elsar_model* m, void* d_part, size_t part_bytes, uint64_t n,
                                 const uint64_t* d_bucket_offsets, void* d_out, hipStream_t stream);
