@@ -627,7 +627,6 @@ constexpr uint32_t kScanThreads = 1024;
 // construction; such a bucket would get no region and all its records would
 // spill.
 constexpr uint32_t kScanWaves = kScanThreads / 64;
-constexpr uint32_t kScanSteps = 4;  // steps of 256 buckets whose loads are in flight together
 
 constexpr uint32_t kCapSteps = 8;  // steps of 256 buckets whose sample counts are loaded together
 
