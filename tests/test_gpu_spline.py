@@ -164,3 +164,26 @@ def test_hot_key_buckets_small_records_and_spill(env, rec_bytes, region_pct):
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().reshape(-1, rec_bytes), oracle.sort_records(recs))
 
+
+
+@pytest.mark.parametrize("fixed", [2, 4, 5, 6])
+def test_dense_code_cells(env, fixed):
+    """Keys whose first `fixed` bytes are one constant and whose later bytes
+    follow the clustered law: a narrow code range (a small cell shift) with
+    many boundaries per cell, so the cell table's sub-tables are built, some
+    with fewer sub-cells than their boundaries call for (the shift caps
+    them).  Counts bit-exact under exact routing, the sort byte-exact."""
+    torch, elsar = env
+    n, B = 1_000_000, 4096  # shifts 25, 12, 5 (20 sub-tables capped by it) and 0 (none possible)
+    recs = datagen.generate(datagen.spec("skewed", seed=50 + fixed, hot_fraction=0.0, embed_idx=True), n)
+    recs[:, :fixed] = np.frombuffer(b"PQRSTUVW"[:fixed], np.uint8)
+    m, part, offsets, d = _fit(env, recs, num_buckets=B, seed=fixed, kind=elsar.SPLINE)
+    assert m.info().kind_used == elsar.SPLINE
+    knots, bound, first = m.spline()
+    bk = oracle.routed_leaves(recs, bound)
+    _, want = oracle.counts_offsets(bk, B)
+    assert np.array_equal(offsets.cpu().numpy().astype(np.uint64), want)
+    out = torch.empty_like(d)
+    m.sort_buckets(part, offsets, n, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().reshape(-1, R), oracle.sort_records(recs))
