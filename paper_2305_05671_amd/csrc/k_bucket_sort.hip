@@ -589,9 +589,9 @@ __device__ __forceinline__ void bucket_sort_lds_body(
     uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
     uint32_t B, PartHeader* __restrict__ reset, uint32_t vk, uint32_t bid,
     uint32_t nblk) {
-  // the first kernel of the larger buckets' chain starts the split's counters
-  // and the equal-key kernel's hand-on list afresh (every call of the chain
-  // on a partition is then the same)
+  // the first kernel of the larger buckets' chain clears the split's counters
+  // and the list of buckets the equal-key kernel passes on, so every call of
+  // the chain on a partition is the same
   if (reset && bid == 0 && threadIdx.x < 5) {
     if (threadIdx.x < 4) reset->seg_n[threadIdx.x] = 0;
     else reset->n_big2 = 0;
