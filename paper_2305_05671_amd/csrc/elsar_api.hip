@@ -246,12 +246,12 @@ elsar_status do_fit(elsar_model* m, const void* d_records, uint64_t n, void* d_w
     }
     HIP_TRY(launch_equi_depth_leaves(sorted, S, m->Lm, m->B, m->hdr, m->ms, st));
     if (m->p.kind == ELSAR_MODEL_MLP) {
-      HIP_TRY(launch_mlp_cell_table(m->ms, m->Lm, st));
       HIP_TRY(launch_mlp_net_hist(m->ms, sorted, S, m->B, st));
     }
   }
   HIP_TRY(launch_decide_root(m->hist, m->has_mlp ? &m->ms : nullptr, m->B, S, m->p.accept_ratio, m->p.kind,
                              m->hdr, m->hist, st));
+  if (m->has_mlp && m->p.kind == ELSAR_MODEL_MLP) HIP_TRY(launch_mlp_cell_table(m->ms, m->Lm, m->hdr, st));
   m->n = n;
   return ELSAR_OK;
 }

@@ -442,8 +442,9 @@ hipError_t launch_long_key_fixup(uint8_t* out, uint64_t n, uint32_t rec_bytes, u
 // and the sample histogram under these leaves.
 hipError_t launch_equi_depth_leaves(const uint64_t* sorted_codes, uint64_t S, uint32_t L, uint32_t B,
                                     ModelHeader* hdr, const MlpState& ms, hipStream_t st);
-// The MLP root's cell table over its L leaves (after training and the leaves).
-hipError_t launch_mlp_cell_table(const MlpState& ms, uint32_t L, hipStream_t st);
+// The MLP root's cell table over its L leaves (after training, the leaves and
+// the choice of root; nothing is done unless the MLP root was chosen).
+hipError_t launch_mlp_cell_table(const MlpState& ms, uint32_t L, const ModelHeader* hdr, hipStream_t st);
 // Automatic kind: whether the linear root is kept (ModelHeader::mlp_skip);
 // other kinds clear the flag.
 hipError_t launch_auto_gate(const uint32_t* hist_rmi, uint32_t B, uint64_t S, float accept_ratio, uint32_t kind,

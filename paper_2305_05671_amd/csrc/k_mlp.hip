@@ -635,7 +635,9 @@ __global__ __launch_bounds__(256) void code_subcell_kernel(const uint64_t* __res
 // to the unbracketed search if rounding ever broke the order.
 __global__ __launch_bounds__(256) void mlp_cell_table_kernel(const MlpBlock* __restrict__ Mg,
                                                              const uint64_t* __restrict__ bound, uint32_t L,
-                                                             uint32_t* __restrict__ cells) {
+                                                             uint32_t* __restrict__ cells,
+                                                             const ModelHeader* __restrict__ hdr) {
+  if (hdr->kind_used != 1u) return;  // only the MLP root routes through it
   __shared__ MlpHead mh;
   load_head(Mg, mh);
   MlpFrags w;
@@ -899,9 +901,9 @@ hipError_t launch_equi_depth_leaves(const uint64_t* e, uint64_t S, uint32_t L, u
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_cell_table(const MlpState& ms, uint32_t L, hipStream_t st) {
+hipError_t launch_mlp_cell_table(const MlpState& ms, uint32_t L, const ModelHeader* hdr, hipStream_t st) {
   if (L == 0) return hipSuccess;
-  mlp_cell_table_kernel<<<(L + 1 + 255) / 256, 256, 0, st>>>(ms.M, ms.bound, L, ms.cells);
+  mlp_cell_table_kernel<<<(L + 1 + 255) / 256, 256, 0, st>>>(ms.M, ms.bound, L, ms.cells, hdr);
   return hipGetLastError();
 }
 
