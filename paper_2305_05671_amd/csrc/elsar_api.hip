@@ -1903,7 +1903,7 @@ elsar_status elsar_partition_stats_get(const elsar_model* m, const void* d_part,
   st->n = h.n;
   st->num_buckets = h.B;
   st->spill_count = h.spill_count;
-  st->mid_buckets = h.n_mid;
+  st->mid_buckets = h.n_mid + h.n_mid_hi;
   st->big_buckets = h.n_big;
   st->max_bucket = h.max_count;
   st->mid_records = h.mid_records;

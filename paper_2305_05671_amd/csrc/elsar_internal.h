@@ -20,6 +20,7 @@ constexpr uint32_t kSortKeyBytes = 12;  // the bucket sorts' entry holds key byt
 constexpr uint32_t kMinKeyBytes = 8;    // the code reads the first 8 key bytes
 constexpr uint32_t kSmallCap = 2048;    // largest bucket sorted by the small LDS kernel
 constexpr uint32_t kMidCap = 6144;      // largest bucket sorted by the large LDS kernel
+constexpr uint32_t kMidLoCap = 3072;    // its half-size instance (two blocks per CU) takes buckets up to here
 constexpr uint32_t kMaxBuckets = 1u << 21;
 
 struct Leaf {          // one RMI leaf: clamped line on the leaf-local code
@@ -78,14 +79,15 @@ struct PartHeader {    // device-resident state of one partition pass
   uint64_t cap_slots;   // slots reserved for bucket regions (upper bound)
   uint32_t B;
   uint32_t spill_count; // records that overflowed their region
-  uint32_t n_mid;       // buckets with kSmallCap < count <= kMidCap
+  uint32_t n_mid;       // buckets with kSmallCap < count <= kMidLoCap (listed from the start of mid_list)
   uint32_t n_big;       // buckets with count > kMidCap
   uint32_t max_count;
   uint32_t mid_records;  // records in the n_mid buckets
   uint32_t big_records;  // records in the n_big buckets
   uint32_t seg_n[4];     // split of the n_big buckets: segments, stack overflow flag, spare (2)
   uint32_t n_big2;       // of the n_big buckets, those the equal-key kernel leaves to the split
-  uint32_t pad[2];
+  uint32_t n_mid_hi;     // of the n_mid buckets, those above kMidLoCap (listed from the end of mid_list)
+  uint32_t pad;
 };
 
 // Byte offsets of the partition buffer's parts for n records and B buckets.

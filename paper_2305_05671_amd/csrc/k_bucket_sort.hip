@@ -576,10 +576,13 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_kernel(
 
 // ------------------------------------------- buckets of up to 6144 records --
 // The small-bucket algorithm at a larger scale: one counting pass on a
-// 13-bit digit of the base-95 code over the bucket's code range, then the
-// per-bin orderings of bin_sort_core.
+// 12-bit (up to 3072 entries) or 13-bit digit of the base-95 code over the
+// bucket's code range, then the per-bin orderings of bin_sort_core.  Two
+// instances take the mid list: buckets of up to kMidLoCap records (listed from
+// the start of mid_list, 76 KB of LDS, two 512-thread blocks per CU) and the
+// larger ones (listed from its end, 157 KB, one 1024-thread block per CU).
 constexpr uint32_t kMidThreads = 1024;  // 16 waves: the one block a CU holds (157 KB of LDS)
-constexpr uint32_t kMidBits = 13;
+constexpr uint32_t kMidLoThreads = 512;
 
 template <uint32_t CAP, uint32_t THREADS>
 __device__ __forceinline__ void bucket_sort_lds_body(
@@ -587,8 +590,9 @@ __device__ __forceinline__ void bucket_sort_lds_body(
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
     const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
     uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
-    uint32_t B, PartHeader* __restrict__ reset, uint32_t vk, uint32_t bid,
+    bool from_end, uint32_t B, PartHeader* __restrict__ reset, uint32_t vk, uint32_t bid,
     uint32_t nblk) {
+  constexpr uint32_t kMidBits = CAP <= kMidLoCap ? 12u : 13u;
   // the first kernel of the larger buckets' chain clears the split's counters
   // and the list of buckets the equal-key kernel passes on, so every call of
   // the chain on a partition is the same
@@ -616,7 +620,7 @@ __device__ __forceinline__ void bucket_sort_lds_body(
   const uint32_t W = slot_bytes_for(RW * 4) / 4;  // slot stride in dwords
   const uint32_t nitems = list ? *list_n : B;
   for (uint32_t it = bid; it < nitems; it += nblk) {
-    const uint32_t j = list ? list[it] : it;
+    const uint32_t j = list ? list[from_end ? B - 1 - it : it] : it;
     BucketRef br;
     br.n = counts[j];
     if (br.n == 0 || br.n > CAP) continue;
@@ -731,13 +735,13 @@ __device__ __forceinline__ void bucket_sort_lds_body(
 }
 
 template <uint32_t CAP, uint32_t THREADS>
-__global__ __launch_bounds__(THREADS) void bucket_sort_lds_kernel(
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(CAP == kMidLoCap ? 4 : 1))) void bucket_sort_lds_kernel(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps, const uint32_t* __restrict__ rstart,
     const uint32_t* __restrict__ spill_off, const uint32_t* __restrict__ spill_map,
     const uint32_t* __restrict__ slots, uint64_t cap_slots, const uint64_t* __restrict__ offsets, uint32_t RW,
     uint32_t K, uint32_t* __restrict__ out, const uint32_t* __restrict__ list, const uint32_t* __restrict__ list_n,
-    uint32_t B, PartHeader* __restrict__ reset, uint32_t vk) {
-  bucket_sort_lds_body<CAP, THREADS>(counts, caps, rstart, spill_off, spill_map, slots, cap_slots, offsets, RW, K, out, list, list_n, B, reset, vk, blockIdx.x, gridDim.x);
+    bool from_end, uint32_t B, PartHeader* __restrict__ reset, uint32_t vk) {
+  bucket_sort_lds_body<CAP, THREADS>(counts, caps, rstart, spill_off, spill_map, slots, cap_slots, offsets, RW, K, out, list, list_n, from_end, B, reset, vk, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------ big buckets of one repeated key --
@@ -1713,7 +1717,7 @@ hipError_t launch_bucket_sort_small(uint8_t* part, const PartLayout& lay, uint32
   } else {
     bucket_sort_lds_kernel<kSmallCap, 256><<<B, 256, 0, st>>>(a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots,
                                                                lay.cap_slots, offsets, a.RW, key_bytes, a.out,
-                                                               nullptr, nullptr, B, nullptr, vk);
+                                                               nullptr, nullptr, false, B, nullptr, vk);
   }
   return hipGetLastError();
 }
@@ -1731,11 +1735,14 @@ hipError_t launch_bucket_sort_large(uint8_t* part, const PartLayout& lay, uint32
                                     const uint64_t* offsets, uint32_t rec_bytes, uint32_t key_bytes, uint8_t* out,
                                     hipStream_t st, uint32_t vk) {
   SortArgs a = sort_args(part, lay, rec_bytes, out);
-  bucket_sort_lds_kernel<kMidCap, kMidThreads><<<grid_for(n, kSmallCap + 1, 256), kMidThreads, 0, st>>>(
-      a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
-      reinterpret_cast<const uint32_t*>(part + lay.mid_list), &a.ph->n_mid, B,
-      reinterpret_cast<PartHeader*>(part + lay.header), vk);
   PartHeader* ph = reinterpret_cast<PartHeader*>(part + lay.header);
+  const uint32_t* mid_list = reinterpret_cast<const uint32_t*>(part + lay.mid_list);
+  bucket_sort_lds_kernel<kMidLoCap, kMidLoThreads><<<grid_for(n, kSmallCap + 1, 512), kMidLoThreads, 0, st>>>(
+      a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
+      mid_list, &ph->n_mid, false, B, ph, vk);
+  bucket_sort_lds_kernel<kMidCap, kMidThreads><<<grid_for(n, kMidLoCap + 1, 256), kMidThreads, 0, st>>>(
+      a.counts, a.caps, a.rstart, a.soff, a.smap, a.slots, lay.cap_slots, offsets, a.RW, key_bytes, a.out,
+      mid_list, &ph->n_mid_hi, true, B, nullptr, vk);
   // buckets of one repeated key first; the others go on to big2
   uint32_t* big2 = reinterpret_cast<uint32_t*>(part + lay.big2_list);
   equal_keys_kernel<<<grid_for(n, kMidCap + 1, 256), kEqThreads, 0, st>>>(
@@ -1807,18 +1814,20 @@ __global__ __launch_bounds__(kSmThreads) void bucket_sort_small_win_kernel(const
                              blockIdx.x % G, G);
 }
 
-// MID: the buckets of the mid list (kSmallCap < count <= kMidCap); otherwise
-// every bucket up to kSmallCap records (records other than 100 bytes).
-template <uint32_t CAP, uint32_t THREADS, bool MID>
-__global__ __launch_bounds__(THREADS) void bucket_sort_lds_win_kernel(const WinJob* __restrict__ jobs, uint32_t G,
+// MID 1: the mid list's buckets of up to kMidLoCap records (from its start;
+// this first kernel of the chain also clears the split's counters); MID 2:
+// its larger ones (from its end); MID 0: every bucket up to kSmallCap records
+// (records other than 100 bytes).
+template <uint32_t CAP, uint32_t THREADS, int MID>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(CAP == kMidLoCap ? 4 : 1))) void bucket_sort_lds_win_kernel(const WinJob* __restrict__ jobs, uint32_t G,
                                                                       uint32_t RW, uint32_t K) {
   const WinJob& J = jobs[blockIdx.x / G];
   const WinRefs r = win_refs(J);
   bucket_sort_lds_body<CAP, THREADS>(r.counts, r.caps, r.rstart, r.soff, r.smap, r.slots, J.lay.cap_slots, J.offsets,
                                      RW, K, reinterpret_cast<uint32_t*>(J.out),
                                      MID ? reinterpret_cast<const uint32_t*>(J.part + J.lay.mid_list) : nullptr,
-                                     MID ? &r.ph->n_mid : nullptr, J.B, MID ? r.ph : nullptr, 0u,
-                                     blockIdx.x % G, G);
+                                     MID == 1 ? &r.ph->n_mid : (MID == 2 ? &r.ph->n_mid_hi : nullptr), MID == 2,
+                                     J.B, MID == 1 ? r.ph : nullptr, 0u, blockIdx.x % G, G);
 }
 
 __global__ __launch_bounds__(kEqThreads) void equal_keys_win_kernel(const WinJob* __restrict__ jobs, uint32_t G,
@@ -1873,7 +1882,7 @@ hipError_t launch_bucket_sort_small_win(const WinJob* jobs, uint32_t njobs, uint
   if (rec_bytes == 100)
     bucket_sort_small_win_kernel<25><<<njobs * G, kSmThreads, 0, st>>>(jobs, G, key_bytes);
   else
-    bucket_sort_lds_win_kernel<kSmallCap, 256, false><<<njobs * G, 256, 0, st>>>(jobs, G, rec_bytes / 4, key_bytes);
+    bucket_sort_lds_win_kernel<kSmallCap, 256, 0><<<njobs * G, 256, 0, st>>>(jobs, G, rec_bytes / 4, key_bytes);
   return hipGetLastError();
 }
 
@@ -1881,7 +1890,9 @@ hipError_t launch_bucket_sort_large_win(const WinJob* jobs, uint32_t njobs, cons
                                         uint32_t key_bytes, hipStream_t st) {
   if (njobs == 0) return hipSuccess;
   const uint32_t RW = rec_bytes / 4;
-  bucket_sort_lds_win_kernel<kMidCap, kMidThreads, true><<<njobs * g.mid, kMidThreads, 0, st>>>(jobs, g.mid, RW, key_bytes);
+  bucket_sort_lds_win_kernel<kMidLoCap, kMidLoThreads, 1><<<njobs * g.mid, kMidLoThreads, 0, st>>>(jobs, g.mid, RW,
+                                                                                                 key_bytes);
+  bucket_sort_lds_win_kernel<kMidCap, kMidThreads, 2><<<njobs * g.mid, kMidThreads, 0, st>>>(jobs, g.mid, RW, key_bytes);
   // buckets of one repeated key first (as many blocks per job as the mid sort)
   equal_keys_win_kernel<<<njobs * g.mid, kEqThreads, 0, st>>>(jobs, g.mid, RW, key_bytes);
   if (rec_bytes < 64) {  // too little room for the split's buffers, stack and reference list

@@ -733,6 +733,7 @@ __device__ __forceinline__ void capacity_body(const uint32_t* __restrict__ hist,
     ph->B = B;
     ph->spill_count = 0;
     ph->n_mid = 0;
+    ph->n_mid_hi = 0;
     ph->n_big = 0;
     ph->n_big2 = 0;
     ph->max_count = 0;

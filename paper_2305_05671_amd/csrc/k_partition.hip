@@ -475,6 +475,7 @@ __global__ __launch_bounds__(kExThreads) void exact_regions_kernel(const uint32_
     ph->B = nb;
     ph->spill_count = 0;
     ph->n_mid = 0;
+    ph->n_mid_hi = 0;
     ph->n_big = 0;
     ph->n_big2 = 0;
     ph->max_count = 0;
@@ -514,9 +515,10 @@ __device__ __forceinline__ void scan_counts_body(const uint32_t* __restrict__ co
                                                  uint32_t* __restrict__ big_list, PartHeader* __restrict__ ph) {
   __shared__ uint64_t shc[kScanWaves + 1];
   __shared__ uint32_t shs[kScanWaves];
-  __shared__ uint32_t sh_nmid, sh_nbig;  // list lengths: LDS atomics (one global address would serialise them)
+  __shared__ uint32_t sh_nmid, sh_nmid_hi, sh_nbig;  // list lengths: LDS atomics (one global address would serialise them)
   if (threadIdx.x == 0) {
     sh_nmid = 0;
+    sh_nmid_hi = 0;
     sh_nbig = 0;
   }
   __syncthreads();
@@ -562,8 +564,11 @@ __device__ __forceinline__ void scan_counts_body(const uint32_t* __restrict__ co
         m = cq > m ? cq : m;
         if (cq > kSmallCap) {  // zero past the segment
           const uint32_t j = jb + 256 * u + 4 * l + q;
-          if (cq <= kMidCap) {
+          if (cq <= kMidLoCap) {  // from the start of the list
             mid_list[atomicAdd(&sh_nmid, 1u)] = j;
+            mr += cq;
+          } else if (cq <= kMidCap) {  // from its end
+            mid_list[B - 1 - atomicAdd(&sh_nmid_hi, 1u)] = j;
             mr += cq;
           } else {
             big_list[atomicAdd(&sh_nbig, 1u)] = j;
@@ -602,6 +607,7 @@ __device__ __forceinline__ void scan_counts_body(const uint32_t* __restrict__ co
     }
     shc[kScanWaves] = rc;
     ph->n_mid = sh_nmid;
+    ph->n_mid_hi = sh_nmid_hi;
     ph->n_big = sh_nbig;
   }
   __syncthreads();
