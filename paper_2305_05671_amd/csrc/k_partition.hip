@@ -75,12 +75,16 @@ __device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const
   if (d < ndw) b[d] = R.tail;
 }
 
-// The records are read and the slots written with nontemporal loads and
-// stores: they stream through once, and marking them so keeps the routing
-// tables (leaves, boundaries, cell tables; a few hundred KB) resident in L2, where
-// every record's bucket search reads them (the spline root's partition went
-// from 8.6 to 8.0 ms at 100M skewed records, the linear root's from 5.7 to
-// 5.4 ms at 100M uniform ones).
+// The records are read with nontemporal loads, and the slots written with
+// nontemporal stores under the equi-depth and MLP roots: they stream through
+// once, and marking them so keeps the routing tables (boundaries, cell
+// tables; up to a few MB) resident in L2, where every record's bucket search
+// reads them (the spline root's partition went from 8.6 to 8.0 ms at 100M
+// skewed records, the linear root's from 5.7 to 5.4 ms at 100M uniform
+// ones).  The linear root's tables are small (4096 leaves, 128 KB), and its
+// slots go out as plain stores: 5.45 -> 5.35 ms at 100M uniform records
+// (plain loads as well: 5.7-6.2 ms; plain stores under the spline root:
+// 6.30 -> 6.45 ms on the skewed law).
 //
 // Software pipeline per block over its tiles t = bid, bid + nblk, ... (bid
 // and nblk: the block's index and the number of blocks working for the job):
@@ -143,8 +147,9 @@ __device__ __forceinline__ void partition_body(
     for (uint32_t q = threadIdx.x; q < total; q += kPartThreads) {
       uint32_t k = q / SC, c = q - k * SC;
       if (FILTER && dslot[k] == kNoSlot) continue;
-      __builtin_nontemporal_store(slot_chunk(b, RW, k, c, r0 + k),
-                                  reinterpret_cast<u32x4*>(slots) + (uint64_t)dslot[k] * SC + c);
+      u32x4* dst = reinterpret_cast<u32x4*>(slots) + (uint64_t)dslot[k] * SC + c;
+      if (ROOT == 0) *dst = slot_chunk(b, RW, k, c, r0 + k);  // the linear root: a 128 KB leaf table
+      else __builtin_nontemporal_store(slot_chunk(b, RW, k, c, r0 + k), dst);
     }
   };
 
