@@ -81,10 +81,12 @@ __device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const
 // tables; up to a few MB) resident in L2, where every record's bucket search
 // reads them (the spline root's partition went from 8.6 to 8.0 ms at 100M
 // skewed records, the linear root's from 5.7 to 5.4 ms at 100M uniform
-// ones).  The linear root's tables are small (4096 leaves, 128 KB), and its
-// slots go out as plain stores: 5.45 -> 5.35 ms at 100M uniform records
-// (plain loads as well: 5.7-6.2 ms; plain stores under the spline root:
-// 6.30 -> 6.45 ms on the skewed law).
+// ones).  The linear root's tables are small (4096 leaves, 128 KB), and for
+// one large job its slots go out as plain stores: 5.45 -> 5.35 ms at 100M
+// uniform records (plain loads as well: 5.7-6.2 ms; plain stores under the
+// spline root: 6.30 -> 6.45 ms on the skewed law; in the batch's windows:
+// 221.6 -> 225.6 ms, so they keep nontemporal stores, as does the host
+// tier's filtered pass).
 //
 // Software pipeline per block over its tiles t = bid, bid + nblk, ... (bid
 // and nblk: the block's index and the number of blocks working for the job):
@@ -103,7 +105,7 @@ __device__ __forceinline__ void store_tile_regs(uint32_t cnt, uint32_t RW, const
 // FILTER (host tier): the records are one chunk of a larger input whose first
 // record has index f.idx_base; only buckets f.lo .. f.hi-1 are placed (bucket
 // b at local bucket b - f.lo), the others are skipped.
-template <int RW_T, int ROOT, bool FILTER>
+template <int RW_T, int ROOT, bool FILTER, bool PLAIN_SLOTS = false>
 __device__ __forceinline__ void partition_body(
     const ModelHeader* __restrict__ hdr, const Leaf* __restrict__ leaves, const MlpBlock* __restrict__ mlp,
     const uint64_t* __restrict__ bound, const uint32_t* __restrict__ ccells, const uint32_t* __restrict__ cells,
@@ -148,7 +150,7 @@ __device__ __forceinline__ void partition_body(
       uint32_t k = q / SC, c = q - k * SC;
       if (FILTER && dslot[k] == kNoSlot) continue;
       u32x4* dst = reinterpret_cast<u32x4*>(slots) + (uint64_t)dslot[k] * SC + c;
-      if (ROOT == 0) *dst = slot_chunk(b, RW, k, c, r0 + k);  // the linear root: a 128 KB leaf table
+      if (PLAIN_SLOTS) *dst = slot_chunk(b, RW, k, c, r0 + k);
       else __builtin_nontemporal_store(slot_chunk(b, RW, k, c, r0 + k), dst);
     }
   };
@@ -250,8 +252,10 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(
     const uint8_t* __restrict__ recs, uint64_t n, uint32_t rw_rt, uint32_t* __restrict__ counts, const uint32_t* __restrict__ caps,
     const uint32_t* __restrict__ rstart, PartHeader* __restrict__ ph, uint2* __restrict__ spill_meta,
     uint4* __restrict__ slots, uint64_t cap_slots, PassFilter f, uint32_t vk, uint32_t cstride) {
-  partition_body<RW_T, ROOT, FILTER>(hdr, leaves, mlp, bound, ccells, cells, recs, n, rw_rt, counts, caps, rstart, ph,
-                                     spill_meta, slots, cap_slots, f, vk, cstride, blockIdx.x, gridDim.x);
+  // one job under the linear root: plain slot stores (see above)
+  partition_body<RW_T, ROOT, FILTER, ROOT == 0 && !FILTER>(hdr, leaves, mlp, bound, ccells, cells, recs, n, rw_rt,
+                                                           counts, caps, rstart, ph, spill_meta, slots, cap_slots, f,
+                                                           vk, cstride, blockIdx.x, gridDim.x);
 }
 
 // A window of a batch: G blocks per job.
