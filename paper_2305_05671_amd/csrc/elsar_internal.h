@@ -67,10 +67,14 @@ struct MlpHead {       // what the vector ALUs read: knots and the FP32 layers
   float b3;
   float pad[3];
 };
+// Rows of the bfloat16 W2 copies are kW2S entries apart (64 and a pad of 4):
+// the 16 lanes of a matrix-core fragment read 16 consecutive rows, which then
+// fall in different LDS banks where a block keeps the copies in LDS.
+constexpr uint32_t kW2S = 68;
 struct MlpBlock {      // evaluation copy of the parameters
   MlpHead h;
-  uint16_t W2bf[4096];   // bfloat16 W2[j][u], row-major
-  uint16_t W2bfT[4096];  // bfloat16 W2[j][u] at [u][j]
+  uint16_t W2bf[64 * kW2S];   // bfloat16 W2[j][u] at [j * kW2S + u]
+  uint16_t W2bfT[64 * kW2S];  // bfloat16 W2[j][u] at [u * kW2S + j]
 };
 static_assert(sizeof(MlpHead) % 8 == 0, "W2 copies stay 8-byte aligned");
 

@@ -106,8 +106,8 @@ __device__ __forceinline__ void publish_one(uint32_t p, float v, MlpBlock* __res
   else if (p < kOffB2) {
     const uint32_t j = (p - kOffW2) / 64, u = (p - kOffW2) % 64;
     const uint16_t b = f32_to_bf16(v);
-    M->W2bf[j * 64 + u] = b;
-    M->W2bfT[u * 64 + j] = b;
+    M->W2bf[j * kW2S + u] = b;
+    M->W2bfT[u * kW2S + j] = b;
   } else if (p < kOffW3) M->h.b2[p - kOffB2] = v;
   else if (p < kOffB3) M->h.w3[p - kOffW3] = v;
   else M->h.b3 = v;
@@ -135,13 +135,22 @@ constexpr uint32_t kRows = kMlpGradRows;
 constexpr uint32_t kChunks = kRows / (16 * kWaves);  // 16-row chunks per wave
 static_assert(kChunks >= 1 && kRows == 16 * kChunks * kWaves, "whole chunks per wave");
 
+// Row strides of the training arrays, padded so that the 16 lanes of a
+// matrix-core fragment, which read 16 consecutive rows, fall in different
+// LDS banks (unpadded, H1T and DZ2T rows are 512 and 256 bytes apart and the
+// 16 reads of a fragment hit one bank).
+constexpr uint32_t kH1S = kRows + 4;  // floats per H1T row
+constexpr uint32_t kDzS = 64 + 4;     // bf16 per DZ2 row
+constexpr uint32_t kDzTS = kRows + 4; // bf16 per DZ2T row
+
 struct TrainLds {
   MlpBlock M;
-  float H1T[64 * kRows];       // h1 (FP32), [unit][row]
-  uint16_t DZ2[kRows * 64];    // dL/dz2 (bf16), [row][j]
-  uint16_t DZ2T[64 * kRows];   // dL/dz2 (bf16), [j][row]
+  float H1T[64 * kH1S];        // h1 (FP32), [unit][row]
+  uint16_t DZ2[kRows * kDzS];  // dL/dz2 (bf16), [row][j]
+  uint16_t DZ2T[64 * kDzTS];   // dL/dz2 (bf16), [j][row]
   float PHI[kRows * 8];
   float T[kRows], DY[kRows];
+  float PW1[kWaves][9 * 64];   // each wave's dW1 ([k][u], k < 8) and db1 (k = 8) over its rows
   float G[kMlpParams];
   float loss;
 };
@@ -162,14 +171,14 @@ __device__ void step_grad(TrainLds& sm) {
 #pragma unroll
     for (uint32_t ks = 0; ks < 4; ++ks)
 #pragma unroll
-      for (uint32_t e = 0; e < 4; ++e) sm.H1T[(16 * ks + 4 * g + e) * kRows + r0 + r] = h1[4 * ks + e];
+      for (uint32_t e = 0; e < 4; ++e) sm.H1T[(16 * ks + 4 * g + e) * kH1S + r0 + r] = h1[4 * ks + e];
     float part[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (uint32_t ct = 0; ct < 4; ++ct) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (uint32_t s2 = 0; s2 < 2; ++s2) {  // K-steps 2s2 and 2s2+1 as one 16x16x32 product
-        const uint16_t* wr = sm.M.W2bf + (16 * ct + r) * 64 + 32 * s2 + 4 * g;
+        const uint16_t* wr = sm.M.W2bf + (16 * ct + r) * kW2S + 32 * s2 + 4 * g;
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cat8_bf16(a[2 * s2], a[2 * s2 + 1]),
                                                       cat8_bf16(load4_bf16(wr), load4_bf16(wr + 16)), acc, 0, 0, 0);
       }
@@ -214,8 +223,8 @@ __device__ void step_grad(TrainLds& sm) {
           gw3 = __builtin_fmaf(dy, v, gw3);
           gb2 += dz2;
           const uint16_t hz = f32_to_bf16(dz2);
-          sm.DZ2[row * 64 + col] = hz;
-          sm.DZ2T[col * kRows + row] = hz;
+          sm.DZ2[row * kDzS + col] = hz;
+          sm.DZ2T[col * kDzTS + row] = hz;
         }
       gw3 += __shfl_xor(gw3, 16);
       gw3 += __shfl_xor(gw3, 32);
@@ -235,8 +244,8 @@ __device__ void step_grad(TrainLds& sm) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (uint32_t s2 = 0; s2 < kRows / 32; ++s2) {  // rows 32s2 + 4g + e and 32s2 + 16 + 4g + e
-      const uint16_t* dz = sm.DZ2T + (16 * jt + r) * kRows + 32 * s2 + 4 * g;
-      const float* h = sm.H1T + (16 * ct + r) * kRows + 32 * s2 + 4 * g;
+      const uint16_t* dz = sm.DZ2T + (16 * jt + r) * kDzTS + 32 * s2 + 4 * g;
+      const float* h = sm.H1T + (16 * ct + r) * kH1S + 32 * s2 + 4 * g;
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cat8_bf16(load4_bf16(dz), load4_bf16(dz + 16)),
                                                     cat8_bf16(pack4_bf16(h[0], h[1], h[2], h[3]),
                                                               pack4_bf16(h[16], h[17], h[18], h[19])),
@@ -254,8 +263,8 @@ __device__ void step_grad(TrainLds& sm) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (uint32_t s2 = 0; s2 < 2; ++s2) {
-        const uint16_t* dz = sm.DZ2 + (r0 + r) * 64 + 32 * s2 + 4 * g;
-        const uint16_t* wt = sm.M.W2bfT + (16 * ct + r) * 64 + 32 * s2 + 4 * g;
+        const uint16_t* dz = sm.DZ2 + (r0 + r) * kDzS + 32 * s2 + 4 * g;
+        const uint16_t* wt = sm.M.W2bfT + (16 * ct + r) * kW2S + 32 * s2 + 4 * g;
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cat8_bf16(load4_bf16(dz), load4_bf16(dz + 16)),
                                                       cat8_bf16(load4_bf16(wt), load4_bf16(wt + 16)), acc, 0, 0, 0);
       }
@@ -264,7 +273,7 @@ __device__ void step_grad(TrainLds& sm) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const uint32_t row = r0 + 4 * g + e;
-        const float h = sm.H1T[u * kRows + row];
+        const float h = sm.H1T[u * kH1S + row];
         const float dz1 = acc[e] * h * (1.0f - h);
         gb += dz1;
 #pragma unroll
@@ -277,12 +286,21 @@ __device__ void step_grad(TrainLds& sm) {
         gw[k] += __shfl_xor(gw[k], 16);
         gw[k] += __shfl_xor(gw[k], 32);
       }
-      if (g == 0) {
-        atomicAdd(&sm.G[kOffB1 + u], gb);
+      if (g == 0) {  // this wave's share, summed over the waves below (no contended LDS atomics)
+        sm.PW1[w][8 * 64 + u] = gb;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) atomicAdd(&sm.G[kOffW1 + u * 8 + k], gw[k]);
+        for (int k = 0; k < 8; ++k) sm.PW1[w][k * 64 + u] = gw[k];
       }
     }
+  }
+  static_assert(kChunks == 1, "one chunk per wave: each wave writes its partials once");
+  __syncthreads();
+  for (uint32_t t = tid; t < 9 * 64; t += kTrainThreads) {
+    float v = 0.f;
+#pragma unroll
+    for (uint32_t ww = 0; ww < kWaves; ++ww) v += sm.PW1[ww][t];
+    const uint32_t k = t / 64, u = t % 64;
+    sm.G[k < 8 ? kOffW1 + u * 8 + k : kOffB1 + u] = v;
   }
   __syncthreads();
 }

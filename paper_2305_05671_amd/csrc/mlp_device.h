@@ -101,7 +101,7 @@ __device__ __forceinline__ void mlp_load_frags(const MlpBlock* __restrict__ Mg, 
   for (uint32_t ct = 0; ct < 4; ++ct)
 #pragma unroll
     for (uint32_t ks = 0; ks < 4; ++ks)
-      w.f[ct * 4 + ks] = load4_bf16(Mg->W2bf + (16 * ct + r) * 64 + 16 * ks + 4 * g);
+      w.f[ct * 4 + ks] = load4_bf16(Mg->W2bf + (16 * ct + r) * kW2S + 16 * ks + 4 * g);
 #pragma unroll
   for (uint32_t ks = 0; ks < 4; ++ks)
 #pragma unroll
