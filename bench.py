@@ -406,11 +406,12 @@ def compare_roots(args, elsar, torch):
     roots = [("rmi", "rmi", 1.5), ("auto", "auto", 1.5), ("mlp", "mlp", 1.5), ("mlp_forced", "mlp", 1e9)]
     plist = [(name, elsar.fit_params(num_buckets=wl["buckets"], seed=wl["seed"], kind=_kind(elsar, model),
                                      accept_ratio=ratio), model) for name, model, ratio in roots]
+    # the workspace first (see buffers() in main)
+    ws = torch.empty(max(elsar.sort_workspace_size(n, p) for _, p, _ in plist), dtype=torch.uint8, device="cuda")
     d_in = torch.empty(n * RECORD_BYTES, dtype=torch.uint8, device="cuda")
     datagen.generate_device(datagen.spec(wl["kind"], seed=wl["seed"]), d_in.data_ptr(), 0, n,
                             torch.cuda.current_stream().cuda_stream)
     d_out = torch.empty_like(d_in)
-    ws = torch.empty(max(elsar.sort_workspace_size(n, p) for _, p, _ in plist), dtype=torch.uint8, device="cuda")
     out = {"workload": wl["desc"], "steps": args.compare_steps, "warmup": 2}
     for name, params, model in plist:
         ms, tm = time_sorts(elsar, torch, n, params, d_in, d_out, ws, 2, args.compare_steps)
@@ -481,13 +482,19 @@ def main():
                               accept_ratio=args.accept_ratio, key_bytes=args.key_bytes)
 
     def buffers():
-        # the records straight into HBM by the GPU generator (byte-identical to
-        # the host generator), the output and the workspace
+        # the workspace, then the records straight into HBM by the GPU
+        # generator (byte-identical to the host generator) and the output.
+        # Allocated first, the workspace -- whose slot area the partition
+        # scatters into -- ran the partition at 5.35-5.37 ms in five of five
+        # allocations in one process; allocated after the records and the
+        # output, at 5.60-5.67 ms in four of five (5.37 once), the same
+        # virtual addresses each time, so the difference lies in how the
+        # memory behind them was placed.
+        ws = torch.empty(elsar.sort_workspace_size(n, params), dtype=torch.uint8, device="cuda")
         d_in = torch.empty(n * RECORD_BYTES, dtype=torch.uint8, device="cuda")
         datagen.generate_device(datagen.spec(wl["kind"], seed=wl["seed"], key_bytes=args.key_bytes), d_in.data_ptr(), 0, n,
                                 torch.cuda.current_stream().cuda_stream)
         d_out = torch.empty_like(d_in)
-        ws = torch.empty(elsar.sort_workspace_size(n, params), dtype=torch.uint8, device="cuda")
         return d_in, d_out, ws
 
     # A process's first large device allocations on a freshly started GPU ran
