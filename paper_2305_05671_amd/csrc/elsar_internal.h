@@ -230,12 +230,12 @@ __host__ __device__ __forceinline__ uint32_t spline_segments(uint32_t L) { retur
 // boundaries bound[1 .. L-1] in cells below c.  Cells are monotone in the
 // code, so a code of cell c lies in a leaf j with ccells[c] <= j <=
 // ccells[c + 1]: the search covers the boundaries that share the code's cell.
-// With about four cells per leaf most cells hold no boundary and the table
-// read alone names the leaf (against about 16 probes for a search over
-// segment knots then leaves).
-// Where the keys are dense in code space (the skewed law's per-byte peaks
-// put tens of boundaries in one cell: about four probes per record on
-// average), a cell with more than kCellDense boundaries has a sub-table of
+// There is about one cell per leaf (at least 1024, at most 2^18 cells):
+// where the codes are spread evenly a cell holds a boundary or two and one
+// or two probes name the leaf (against about 16 for a search over segment
+// knots then leaves).  Where the keys are dense in code space (the skewed
+// law's per-byte peaks put tens of boundaries in one cell), a cell with
+// more than kCellDense boundaries has a sub-table of
 // 2^k cells of its own (2^k at least twice its boundaries, k at most
 // cell_shift): entry s counts the boundaries below its sub-cell s, exactly as
 // the cells do, so the search narrows to the boundaries of the code's
@@ -249,7 +249,7 @@ constexpr uint32_t kCellDense = 3;
 
 __host__ __device__ __forceinline__ uint32_t code_cells_for(uint32_t L) {
   uint32_t nc = 1024;
-  while (nc < 4u * L && nc < (1u << 18)) nc <<= 1;
+  while (nc < L && nc < (1u << 18)) nc <<= 1;
   return nc;
 }
 

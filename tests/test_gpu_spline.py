@@ -166,17 +166,22 @@ def test_hot_key_buckets_small_records_and_spill(env, rec_bytes, region_pct):
 
 
 
-@pytest.mark.parametrize("fixed", [2, 4, 5, 6])
-def test_dense_code_cells(env, fixed):
-    """Keys whose first `fixed` bytes are one constant and whose later bytes
-    follow the clustered law: a narrow code range (a small cell shift) with
-    many boundaries per cell, so the cell table's sub-tables are built, some
-    with fewer sub-cells than their boundaries call for (the shift caps
-    them).  Counts bit-exact under exact routing, the sort byte-exact."""
+@pytest.mark.parametrize("fixed,narrow", [(2, 0), (4, 0), (5, 8), (5, 4), (6, 0)])
+def test_dense_code_cells(env, fixed, narrow):
+    """Keys whose first `fixed` bytes are one constant (and the next one of
+    `narrow` values) and whose later bytes follow the clustered law: a narrow
+    code range (a small cell shift) with many boundaries per cell, so the
+    cell table's sub-tables are built, some with fewer sub-cells than their
+    boundaries call for (the shift caps them).  Counts bit-exact under exact
+    routing, the sort byte-exact."""
     torch, elsar = env
-    n, B = 1_000_000, 4096  # shifts 25, 12, 5 (20 sub-tables capped by it) and 0 (none possible)
+    # cell shifts 27, 14, 5 (103 of 229 sub-tables capped by it), 3 (253 of
+    # 284) and 0 (no sub-table possible)
+    n, B = 1_000_000, 4096
     recs = datagen.generate(datagen.spec("skewed", seed=50 + fixed, hot_fraction=0.0, embed_idx=True), n)
     recs[:, :fixed] = np.frombuffer(b"PQRSTUVW"[:fixed], np.uint8)
+    if narrow:
+        recs[:, fixed] = 0x41 + recs[:, fixed] % narrow
     m, part, offsets, d = _fit(env, recs, num_buckets=B, seed=fixed, kind=elsar.SPLINE)
     assert m.info().kind_used == elsar.SPLINE
     knots, bound, first = m.spline()
