@@ -156,6 +156,7 @@ PartLayout part_layout(uint64_t n, uint32_t B, uint32_t R, uint32_t region_pct, 
   lay.mid_list = take((size_t)B * 4);
   lay.big_list = take((size_t)B * 4);
   lay.big2_list = take((size_t)B * 4);
+  lay.psum = take((size_t)(B + kScanChunk - 1) / kScanChunk * sizeof(ScanPart));
   lay.spill_meta = take((size_t)n * 8);
   lay.spill_map = take((size_t)n * 4);
   // split of buckets above the LDS caps: every split of c entries gives at most
@@ -996,6 +997,7 @@ PartLayout pass_layout(uint64_t P, uint32_t B, uint32_t R, uint32_t K) {
   lay.mid_list = take((size_t)B * 4);
   lay.big_list = take((size_t)B * 4);
   lay.big2_list = take((size_t)B * 4);
+  lay.psum = take((size_t)(B + kScanChunk - 1) / kScanChunk * sizeof(ScanPart));
   lay.spill_meta = take(0);
   lay.spill_map = take(0);
   lay.seg_leaf_cap = (uint32_t)std::min<uint64_t>(P / 32 + 4096, 0xFFFFFFFFull);

@@ -94,9 +94,21 @@ struct PartHeader {    // device-resident state of one partition pass
   uint32_t pad;
 };
 
+// From kScanMultiMin buckets up, the region sizes and the count scan of one
+// job run over chunks of kScanChunk buckets, one block each, in two launches;
+// a chunk's sums pass between them as a ScanPart.
+constexpr uint32_t kScanChunk = 4096;
+constexpr uint32_t kScanMultiMin = 16384;
+struct ScanPart {
+  uint64_t c;  // sizes or counts of the chunk's buckets
+  uint32_t s;  // their records beyond the regions
+  uint32_t pad;
+};
+
 // Byte offsets of the partition buffer's parts for n records and B buckets.
 struct PartLayout {
   size_t header, counts, caps, rstart, spill_off, mid_list, big_list;
+  size_t psum;       // one ScanPart per chunk of kScanChunk buckets
   size_t big2_list;  // the big buckets left to the split (keys not all equal, or above the equal-key cap)
   // The partition's slot counters: bucket j's at pcounts + 4 * j * cstride.
   // Returning atomics on counters packed 32 to a 128-byte line serialise per
@@ -208,12 +220,14 @@ __device__ __forceinline__ uint32_t rmi_leaf(float a0, float a1, uint32_t L, uin
   return (uint32_t)r;
 }
 
+// The clamp to [lo, hi] is written without branches (lo and hi are bucket ids,
+// exact in FP32, and y is finite): with an early return the compiler deferred
+// the load of hi behind the test on lo, a second dependent trip to L2 for
+// nearly every record.
 __device__ __forceinline__ uint32_t leaf_bucket(const Leaf& lf, uint64_t e) {
   uint64_t d = e >= lf.base ? e - lf.base : 0;
-  float y = floorf(__builtin_fmaf(lf.c, code_f32(d), lf.b));
-  if (y < (float)lf.lo) return lf.lo;
-  if (y > (float)lf.hi) return lf.hi;
-  return (uint32_t)y;
+  const float y = floorf(__builtin_fmaf(lf.c, code_f32(d), lf.b));
+  return (uint32_t)fminf(fmaxf(y, (float)lf.lo), (float)lf.hi);
 }
 
 // Spline root over equi-depth leaves: K segments of about L / K leaves each;

@@ -628,6 +628,32 @@ constexpr uint32_t kScanThreads = 1024;
 // spill.
 constexpr uint32_t kScanWaves = kScanThreads / 64;
 
+// Region size of a bucket with h sample keys: they estimate its mass as h / S
+// with a standard deviation of about sqrt(h) / S, and the region covers two of
+// them beyond the estimate, at least the ideal n / B, times the slack factor
+// (the root in single precision: h is exact there, and FP64 square roots and
+// divisions took most of the one-block kernel's time).  per = n / S.
+__device__ __forceinline__ uint32_t region_slots(uint32_t h, double per, double ideal, double scale) {
+  const double hd = (double)h;
+  const double expect = (hd + 2.0 * (double)sqrtf((float)h)) * per;
+  const double m = expect > ideal ? expect : ideal;
+  return ((uint32_t)ceil(scale * m) + 16u + 1u) & ~1u;
+}
+
+__device__ __forceinline__ void init_part_header(PartHeader* ph, uint64_t n, uint64_t cap_slots, uint32_t B) {
+  ph->n = n;
+  ph->cap_slots = cap_slots;
+  ph->B = B;
+  ph->spill_count = 0;
+  ph->n_mid = 0;
+  ph->n_mid_hi = 0;
+  ph->n_big = 0;
+  ph->n_big2 = 0;
+  ph->max_count = 0;
+  ph->mid_records = 0;
+  ph->big_records = 0;
+}
+
 constexpr uint32_t kCapSteps = 8;  // steps of 256 buckets whose sample counts are loaded together
 
 __device__ __forceinline__ void capacity_body(const uint32_t* __restrict__ hist, uint64_t S, uint64_t n, uint32_t B,
@@ -649,18 +675,8 @@ __device__ __forceinline__ void capacity_body(const uint32_t* __restrict__ hist,
       for (uint32_t q = 0; q < 4; ++q) h[q] = j + q < s1 ? hist[j + q] : 0u;
     }
   };
-  // region size of bucket j from its sample count h: h sample keys estimate
-  // the bucket's mass as h / S with a standard deviation of about sqrt(h) / S,
-  // and the region covers two of them (the root in single precision: h is
-  // exact there, and FP64 square roots and divisions took most of this
-  // one-CU kernel's time)
   const double per = (double)n / (double)S;
-  auto size_of = [&](uint32_t j, uint32_t h) {
-    const double hd = (double)h;
-    const double expect = (hd + 2.0 * (double)sqrtf((float)h)) * per;
-    const double m = expect > ideal ? expect : ideal;
-    return j < s1 ? ((uint32_t)ceil(scale * m) + 16u + 1u) & ~1u : 0u;
-  };
+  auto size_of = [&](uint32_t j, uint32_t h) { return j < s1 ? region_slots(h, per, ideal, scale) : 0u; };
   uint64_t s = 0;
   for (uint32_t jb = s0; jb < s1; jb += 256 * kCapSteps) {
     uint32_t h[kCapSteps][4];
@@ -727,19 +743,7 @@ __device__ __forceinline__ void capacity_body(const uint32_t* __restrict__ hist,
       run += shfl_u64(x, 63);  // the step's sum
     }
   }
-  if (threadIdx.x == 0) {
-    ph->n = n;
-    ph->cap_slots = cap_slots;
-    ph->B = B;
-    ph->spill_count = 0;
-    ph->n_mid = 0;
-    ph->n_mid_hi = 0;
-    ph->n_big = 0;
-    ph->n_big2 = 0;
-    ph->max_count = 0;
-    ph->mid_records = 0;
-    ph->big_records = 0;
-  }
+  if (threadIdx.x == 0) init_part_header(ph, n, cap_slots, B);
 }
 
 __global__ __launch_bounds__(kScanThreads) void capacity_kernel(const uint32_t* __restrict__ hist, uint64_t S,
@@ -766,8 +770,107 @@ hipError_t launch_capacities_win(const WinJob* jobs, uint32_t njobs, uint32_t re
   return hipGetLastError();
 }
 
+// Many buckets: the same sizes and starts in two launches over chunks of
+// kScanChunk buckets, thread i of a block taking buckets 4i .. 4i+3 of its
+// chunk.  The first writes the sizes into caps and each chunk's sum; the
+// second adds the sums of the chunks before its own to a block scan of its
+// sizes.  (One block took 41 us at 65536 buckets, bound by what one CU's
+// loads and stores can move.)
+__global__ __launch_bounds__(kScanThreads) void capacity_sizes_kernel(const uint32_t* __restrict__ hist, uint64_t S,
+                                                                      uint64_t n, uint32_t B, double scale,
+                                                                      uint32_t* __restrict__ caps,
+                                                                      ScanPart* __restrict__ psum,
+                                                                      PartHeader* __restrict__ ph,
+                                                                      uint64_t cap_slots) {
+  __shared__ uint64_t sh[kScanWaves + 1];
+  const uint32_t j = blockIdx.x * kScanChunk + 4 * threadIdx.x;
+  const double ideal = (double)n / (double)B, per = (double)n / (double)S;
+  uint32_t c[4] = {0u, 0u, 0u, 0u};
+  if (j + 4 <= B) {
+    const uint4 x = *reinterpret_cast<const uint4*>(hist + j);
+    c[0] = region_slots(x.x, per, ideal, scale);
+    c[1] = region_slots(x.y, per, ideal, scale);
+    c[2] = region_slots(x.z, per, ideal, scale);
+    c[3] = region_slots(x.w, per, ideal, scale);
+    *reinterpret_cast<uint4*>(caps + j) = make_uint4(c[0], c[1], c[2], c[3]);
+  } else {
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q)
+      if (j + q < B) caps[j + q] = c[q] = region_slots(hist[j + q], per, ideal, scale);
+  }
+  uint64_t tot;
+  block_exclusive_scan<uint64_t, kScanThreads>((uint64_t)c[0] + c[1] + c[2] + c[3], sh, &tot);
+  if (threadIdx.x == 0) {
+    psum[blockIdx.x].c = tot;
+    if (blockIdx.x == 0) init_part_header(ph, n, cap_slots, B);
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void capacity_starts_kernel(uint32_t B, uint32_t* __restrict__ caps,
+                                                                       uint32_t* __restrict__ rstart,
+                                                                       uint32_t* __restrict__ counts, uint32_t cstride,
+                                                                       const ScanPart* __restrict__ psum,
+                                                                       uint64_t cap_slots) {
+  __shared__ uint64_t sh[kScanWaves + 1];
+  const uint32_t j = blockIdx.x * kScanChunk + 4 * threadIdx.x;
+  uint64_t before = 0;  // the chunks ahead of this one
+  for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kScanThreads) before += psum[i].c;
+  uint64_t tot;
+  block_exclusive_scan<uint64_t, kScanThreads>(before, sh, &tot);
+  before = tot;
+  uint32_t c[4] = {0u, 0u, 0u, 0u};
+  if (j + 4 <= B) {
+    const uint4 x = *reinterpret_cast<const uint4*>(caps + j);
+    c[0] = x.x; c[1] = x.y; c[2] = x.z; c[3] = x.w;
+  } else {
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) c[q] = j + q < B ? caps[j + q] : 0u;
+  }
+  uint64_t r = before + block_exclusive_scan<uint64_t, kScanThreads>((uint64_t)c[0] + c[1] + c[2] + c[3], sh, &tot);
+  uint32_t cp[4], rp[4];
+#pragma unroll
+  for (uint32_t q = 0; q < 4; ++q) {
+    const bool fits = r + c[q] <= cap_slots;
+    cp[q] = fits ? c[q] : 0u;
+    rp[q] = fits ? (uint32_t)r : 0u;
+    r += c[q];
+  }
+  if (j + 4 <= B) {
+    *reinterpret_cast<uint4*>(caps + j) = make_uint4(cp[0], cp[1], cp[2], cp[3]);
+    *reinterpret_cast<uint4*>(rstart + j) = make_uint4(rp[0], rp[1], rp[2], rp[3]);
+    if (cstride == 1) {
+      *reinterpret_cast<uint4*>(counts + j) = make_uint4(0, 0, 0, 0);
+    } else {
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) counts[(uint64_t)(j + q) * cstride] = 0;
+    }
+  } else {
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      if (j + q < B) {
+        caps[j + q] = cp[q];
+        rstart[j + q] = rp[q];
+        counts[(uint64_t)(j + q) * cstride] = 0;
+      }
+    }
+  }
+}
+
 hipError_t launch_capacities(const uint32_t* hist, uint64_t S, uint64_t n, uint32_t B, uint32_t region_pct,
                              uint8_t* part, const PartLayout& lay, hipStream_t st) {
+  if (B >= kScanMultiMin) {
+    const uint32_t g = (B + kScanChunk - 1) / kScanChunk;
+    ScanPart* ps = reinterpret_cast<ScanPart*>(part + lay.psum);
+    capacity_sizes_kernel<<<g, kScanThreads, 0, st>>>(hist, S, n, B, region_pct / 100.0,
+                                                      reinterpret_cast<uint32_t*>(part + lay.caps), ps,
+                                                      reinterpret_cast<PartHeader*>(part + lay.header),
+                                                      lay.cap_slots);
+    capacity_starts_kernel<<<g, kScanThreads, 0, st>>>(B, reinterpret_cast<uint32_t*>(part + lay.caps),
+                                                       reinterpret_cast<uint32_t*>(part + lay.rstart),
+                                                       reinterpret_cast<uint32_t*>(part + lay.pcounts), lay.cstride,
+                                                       ps, lay.cap_slots);
+    return hipGetLastError();
+  }
   capacity_kernel<<<1, kScanThreads, 0, st>>>(hist, S, n, B, region_pct / 100.0,
                                               reinterpret_cast<uint32_t*>(part + lay.caps),
                                               reinterpret_cast<uint32_t*>(part + lay.rstart),

@@ -119,6 +119,7 @@ __device__ __forceinline__ void partition_body(
   extern __shared__ uint4 lds4[];                      // 2 tiles of kPartTile * RW dwords
   __shared__ uint32_t dst[2][kPartTile];
   constexpr bool MLP = ROOT == 1;
+  constexpr bool HOIST = ROOT == 0;
   if (hdr->kind_used != (uint32_t)ROOT) return;
   const uint32_t tile_dw = kPartTile * RW;
   const float a0 = hdr->a0, a1 = hdr->a1;
@@ -170,40 +171,78 @@ __device__ __forceinline__ void partition_body(
   for (;;) {
     const uint64_t tn = t + nblk;
     const bool have_next = tn < ntiles;
-    // 1. loads of the next tile
-    // (the last iteration reloads its own tile instead: no branch around the loads)
+    // 1. loads of the next tile (the last iteration reloads its own tile
+    //    instead: no branch around the loads), and 2. the bucket of each
+    //    record of tile t
     const uint64_t tl = have_next ? tn : t;
-    TileRegs R;
-    load_tile_regs<RV>(rec_dw, tl, tile_count(tl), RW, R);
-    // 2. bucket of each record of tile t and its slot reservation
     const uint32_t cnt = tile_count(t);
     uint32_t b = 0, s = 0;
-    if constexpr (MLP) {
-      // every lane takes part in the matrix products; lanes past the tile's
-      // end read stale tile bytes and discard the result
+    TileRegs R;
+    if constexpr (ROOT == 0) {
+      // Under the linear root the leaf line's load goes out before the next
+      // tile's loads and stays ahead of them (the scheduling barriers): loads
+      // complete in issue order, so the wait for the leaf does not include
+      // the wait for the tile (5.17 -> 5.14 ms at 100M uniform records).
+      // Lanes past the tile's end route stale bytes to a leaf in range and
+      // discard the result.
       const uint32_t* r = buf(cur) + threadIdx.x * RW;
       uint32_t r0 = r[0], r1 = r[1], r2 = vk ? r[2] : 0u;
       virtual_key(r0, r1, r2, vk);
       const uint64_t e = key_code(r0, r1);
-      const float y = mlp_y64(e, mh_, w2);
-      if (threadIdx.x < cnt) {
-        const uint32_t j = mlp_bracket_leaf(bound, cells, L, e, y);
-        b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
+      const Leaf lf = load_leaf(leaves, rmi_leaf(a0, a1, L, e));
+      __builtin_amdgcn_sched_barrier(0);
+      load_tile_regs<RV>(rec_dw, tl, tile_count(tl), RW, R);
+      __builtin_amdgcn_sched_barrier(0);
+      b = leaf_bucket(lf, e);
+    } else {
+      // the spline and MLP roots' searches overlap the next tile's loads
+      // (issued after the searches, the skewed law's whole sort took 13.4 ms
+      // instead of 12.1)
+      load_tile_regs<RV>(rec_dw, tl, tile_count(tl), RW, R);
+      uint64_t e = 0;
+      Leaf lf{};
+      if constexpr (MLP) {
+        // every lane takes part in the matrix products; lanes past the tile's
+        // end read stale tile bytes and discard the result
+        const uint32_t* r = buf(cur) + threadIdx.x * RW;
+        uint32_t r0 = r[0], r1 = r[1], r2 = vk ? r[2] : 0u;
+        virtual_key(r0, r1, r2, vk);
+        e = key_code(r0, r1);
+        const float y = mlp_y64(e, mh_, w2);
+        if (threadIdx.x < cnt) {
+          const uint32_t j = mlp_bracket_leaf(bound, cells, L, e, y);
+          if (leaf_is_bucket) b = j;
+          else lf = load_leaf(leaves, j);
+        }
+      } else if (threadIdx.x < cnt) {
+        const uint32_t* r = buf(cur) + threadIdx.x * RW;
+        uint32_t r0 = r[0], r1 = r[1], r2 = vk ? r[2] : 0u;
+        virtual_key(r0, r1, r2, vk);
+        e = key_code(r0, r1);
+        const uint32_t j = cell_exact_leaf(ccells, csh, cnc, ce0, bound, e);
+        if (leaf_is_bucket) b = j;
+        else lf = load_leaf(leaves, j);
       }
-    } else if (threadIdx.x < cnt) {
-      const uint32_t* r = buf(cur) + threadIdx.x * RW;
-      uint32_t r0 = r[0], r1 = r[1], r2 = vk ? r[2] : 0u;
-      virtual_key(r0, r1, r2, vk);
-      uint64_t e = key_code(r0, r1);
-      const uint32_t j = ROOT == 2 ? cell_exact_leaf(ccells, csh, cnc, ce0, bound, e) : rmi_leaf(a0, a1, L, e);
-      b = leaf_is_bucket ? j : leaf_bucket(load_leaf(leaves, j), e);
+      if (!leaf_is_bucket && threadIdx.x < cnt) b = leaf_bucket(lf, e);
     }
     bool keep = threadIdx.x < cnt;
     if (FILTER) {
       keep = keep && b >= f.lo && b < f.hi;
       b -= f.lo;
     }
-    if (keep) s = atomicAdd(&counts[(uint64_t)b * cstride], 1u);
+    // Under the linear root the region's size and start travel with the
+    // atomic: loaded after it returned, they were two more dependent trips to
+    // L2 (5.34 -> 5.17 ms at 100M uniform records).  Under the spline and MLP
+    // roots the same order measured slower (6.18 -> 6.5-6.7 ms on the skewed
+    // law), so they keep the loads after the atomic.
+    uint32_t cap = 0, rs = 0;
+    if (keep) {
+      if (HOIST) {
+        cap = caps[b];
+        rs = rstart[b];
+      }
+      s = atomicAdd(&counts[(uint64_t)b * cstride], 1u);
+    }
     // 3. the previous tile's slots, while the atomics are in flight
     if (have_prev) write_tile(tprev, buf(cur ^ 1), dst[cur ^ 1]);
     // 4. this tile's slots.  Overflowing records take spill positions from one
@@ -212,8 +251,8 @@ __device__ __forceinline__ void partition_body(
     uint32_t slot = kNoSlot, over = 0;
     bool spill = false;
     if (keep) {
-      const uint32_t cap = caps[b];
-      if (s < cap) slot = rstart[b] + s;
+      if (!HOIST) cap = caps[b];
+      if (s < cap) slot = (HOIST ? rs : rstart[b]) + s;
       else { spill = true; over = s - cap; }
     }
     const uint64_t spill_mask = __ballot(spill);
@@ -368,6 +407,7 @@ __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restric
                                                     uint64_t n, uint32_t RW, uint32_t* __restrict__ counts,
                                                     uint32_t vk) {
   constexpr bool MLP = ROOT == 1;
+  constexpr bool HOIST = ROOT == 0;
   if (hdr->kind_used != (uint32_t)ROOT) return;
   __shared__ typename std::conditional<MLP, MlpHead, uint32_t>::type mh_;
   MlpFrags w2;
@@ -693,8 +733,180 @@ hipError_t launch_scan_counts_win(const WinJob* jobs, uint32_t njobs, hipStream_
   return hipGetLastError();
 }
 
+// Many buckets: the same scan in two launches over chunks of kScanChunk
+// buckets, thread i of a block taking buckets 4i .. 4i+3 of its chunk.  The
+// first sums each chunk's counts and overflows and lists its large buckets
+// (one atomic per list and wave reserves the wave's entries); the second adds
+// the sums of the chunks before its own to a block scan of its counts.  (One
+// block took 41-51 us at 65536 buckets, bound by what one CU's loads and
+// stores can move.)
+__device__ __forceinline__ void load_chunk4(const uint32_t* __restrict__ counts, uint32_t cstride,
+                                            const uint32_t* __restrict__ caps, uint32_t B, uint32_t j, uint32_t c[4],
+                                            uint32_t k[4]) {
+  if (j + 4 <= B) {
+    const uint4 y = *reinterpret_cast<const uint4*>(caps + j);
+    k[0] = y.x; k[1] = y.y; k[2] = y.z; k[3] = y.w;
+    if (cstride == 1) {
+      const uint4 x = *reinterpret_cast<const uint4*>(counts + j);
+      c[0] = x.x; c[1] = x.y; c[2] = x.z; c[3] = x.w;
+    } else {
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) c[q] = counts[(uint64_t)(j + q) * cstride];
+    }
+  } else {
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      c[q] = j + q < B ? counts[(uint64_t)(j + q) * cstride] : 0u;
+      k[q] = j + q < B ? caps[j + q] : 0u;
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t overflow_of(uint32_t c, uint32_t k) { return c > k ? c - k : 0u; }
+
+__global__ __launch_bounds__(kScanThreads) void scan_sums_kernel(const uint32_t* __restrict__ counts, uint32_t cstride,
+                                                                 const uint32_t* __restrict__ caps, uint32_t B,
+                                                                 uint32_t* __restrict__ mid_list,
+                                                                 uint32_t* __restrict__ big_list,
+                                                                 PartHeader* __restrict__ ph,
+                                                                 ScanPart* __restrict__ psum) {
+  __shared__ uint64_t shc[kScanWaves];
+  __shared__ uint32_t shs[kScanWaves];
+  const uint32_t w = threadIdx.x >> 6, l = lane_id();
+  const uint32_t j = blockIdx.x * kScanChunk + 4 * threadIdx.x;
+  uint32_t c[4], k[4];
+  load_chunk4(counts, cstride, caps, B, j, c, k);
+  uint64_t sc = 0;
+  uint32_t ss = 0, m = 0, mr = 0, br = 0;
+  uint32_t nl = 0;  // this thread's list entries, 10 bits a list: mid, mid from the end, big
+#pragma unroll
+  for (uint32_t q = 0; q < 4; ++q) {
+    const uint32_t cq = c[q];  // zero past B
+    sc += cq;
+    ss += overflow_of(cq, k[q]);
+    m = cq > m ? cq : m;
+    if (cq > kSmallCap) {
+      if (cq <= kMidLoCap) { nl += 1u; mr += cq; }
+      else if (cq <= kMidCap) { nl += 1u << 10; mr += cq; }
+      else { nl += 1u << 20; br += cq; }
+    }
+  }
+  // at most 256 entries of a list per wave: the 10-bit fields never carry
+  const uint32_t incl = wave_inclusive_scan<uint32_t>(nl);
+  const uint32_t wtot = __shfl(incl, 63);
+  if (wtot) {
+    uint32_t b0 = 0, b1 = 0, b2 = 0;
+    if (l == 0) {
+      if (wtot & 1023u) b0 = atomicAdd(&ph->n_mid, wtot & 1023u);
+      if ((wtot >> 10) & 1023u) b1 = atomicAdd(&ph->n_mid_hi, (wtot >> 10) & 1023u);
+      if (wtot >> 20) b2 = atomicAdd(&ph->n_big, wtot >> 20);
+    }
+    const uint32_t ex = incl - nl;
+    b0 = __shfl(b0, 0) + (ex & 1023u);
+    b1 = __shfl(b1, 0) + ((ex >> 10) & 1023u);
+    b2 = __shfl(b2, 0) + (ex >> 20);
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      const uint32_t cq = c[q];
+      if (cq > kSmallCap) {
+        if (cq <= kMidLoCap) mid_list[b0++] = j + q;          // from the start of the list
+        else if (cq <= kMidCap) mid_list[B - 1 - b1++] = j + q;  // from its end
+        else big_list[b2++] = j + q;
+      }
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    sc += shfl_xor_u64(sc, off);
+    ss += __shfl_xor(ss, off);
+    mr += __shfl_xor(mr, off);
+    br += __shfl_xor(br, off);
+    const uint32_t mo = __shfl_xor(m, off);
+    m = mo > m ? mo : m;
+  }
+  if (l == 0) {
+    shc[w] = sc;
+    shs[w] = ss;
+    if (mr) atomicAdd(&ph->mid_records, mr);
+    if (br) atomicAdd(&ph->big_records, br);
+    if (m) atomicMax(&ph->max_count, m);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t tc = 0;
+    uint32_t ts = 0;
+    for (uint32_t i = 0; i < kScanWaves; ++i) {
+      tc += shc[i];
+      ts += shs[i];
+    }
+    psum[blockIdx.x].c = tc;
+    psum[blockIdx.x].s = ts;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_offsets_kernel(const uint32_t* __restrict__ counts,
+                                                                    uint32_t cstride, uint32_t* __restrict__ dense,
+                                                                    const uint32_t* __restrict__ caps, uint32_t B,
+                                                                    uint64_t* __restrict__ offsets,
+                                                                    uint32_t* __restrict__ spill_off,
+                                                                    const ScanPart* __restrict__ psum) {
+  __shared__ uint64_t shc[kScanWaves + 1];
+  __shared__ uint32_t shs[kScanWaves + 1];
+  const uint32_t j = blockIdx.x * kScanChunk + 4 * threadIdx.x;
+  uint64_t bc = 0;  // the chunks ahead of this one
+  uint32_t bs = 0;
+  for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kScanThreads) {
+    bc += psum[i].c;
+    bs += psum[i].s;
+  }
+  uint64_t tc, totc;
+  uint32_t ts, tots;
+  block_exclusive_scan<uint64_t, kScanThreads>(bc, shc, &tc);
+  block_exclusive_scan<uint32_t, kScanThreads>(bs, shs, &ts);
+  uint32_t c[4], k[4];
+  load_chunk4(counts, cstride, caps, B, j, c, k);
+  const uint64_t oc = (uint64_t)c[0] + c[1] + c[2] + c[3];
+  const uint32_t os = overflow_of(c[0], k[0]) + overflow_of(c[1], k[1]) + overflow_of(c[2], k[2]) +
+                      overflow_of(c[3], k[3]);
+  uint64_t r = tc + block_exclusive_scan<uint64_t, kScanThreads>(oc, shc, &totc);
+  uint32_t t = ts + block_exclusive_scan<uint32_t, kScanThreads>(os, shs, &tots);
+  uint32_t so[4];
+#pragma unroll
+  for (uint32_t q = 0; q < 4; ++q) {
+    if (j + q < B) offsets[j + q] = r;
+    so[q] = t;
+    r += c[q];
+    t += overflow_of(c[q], k[q]);
+  }
+  if (j + 4 <= B) {
+    *reinterpret_cast<uint4*>(spill_off + j) = make_uint4(so[0], so[1], so[2], so[3]);
+    if (cstride > 1) *reinterpret_cast<uint4*>(dense + j) = make_uint4(c[0], c[1], c[2], c[3]);
+  } else {
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q)
+      if (j + q < B) {
+        spill_off[j + q] = so[q];
+        if (cstride > 1) dense[j + q] = c[q];
+      }
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) offsets[B] = tc + totc;
+}
+
 hipError_t launch_scan_counts(uint8_t* part, const PartLayout& lay, uint32_t B, uint64_t* offsets,
                               hipStream_t st) {
+  if (B >= kScanMultiMin) {
+    const uint32_t g = (B + kScanChunk - 1) / kScanChunk;
+    const uint32_t* pc = reinterpret_cast<const uint32_t*>(part + lay.pcounts);
+    const uint32_t* caps = reinterpret_cast<const uint32_t*>(part + lay.caps);
+    ScanPart* ps = reinterpret_cast<ScanPart*>(part + lay.psum);
+    scan_sums_kernel<<<g, kScanThreads, 0, st>>>(pc, lay.cstride, caps, B,
+                                                 reinterpret_cast<uint32_t*>(part + lay.mid_list),
+                                                 reinterpret_cast<uint32_t*>(part + lay.big_list),
+                                                 reinterpret_cast<PartHeader*>(part + lay.header), ps);
+    scan_offsets_kernel<<<g, kScanThreads, 0, st>>>(pc, lay.cstride, reinterpret_cast<uint32_t*>(part + lay.counts),
+                                                    caps, B, offsets,
+                                                    reinterpret_cast<uint32_t*>(part + lay.spill_off), ps);
+    return hipGetLastError();
+  }
   scan_counts_kernel<<<1, kScanThreads, 0, st>>>(
       reinterpret_cast<const uint32_t*>(part + lay.pcounts), lay.cstride, reinterpret_cast<uint32_t*>(part + lay.counts),
       reinterpret_cast<const uint32_t*>(part + lay.caps), B,

@@ -1,11 +1,13 @@
 """GPU parity of the bookkeeping scans at bucket counts around their block
-decomposition: the region sizes and the offset scan give each wave a
-contiguous segment of buckets, walked 256 at a time, four buckets per lane.
-Bucket counts that are not multiples of four, that end just before or after
-a segment or a step, and the largest bucket count, must all give the
-offsets (Section 3.5's exclusive sums) that the oracle computes from the
-same bucket function, the same largest bucket and mid/big bucket tallies,
-and a byte-exact sort."""
+decomposition.  Below 16384 buckets the region sizes and the offset scan run
+in one block that gives each wave a contiguous segment of buckets, walked
+256 at a time, four buckets per lane; from 16384 up they run in two launches
+over chunks of 4096 buckets, one block each, the second adding the sums of
+the chunks ahead.  Bucket counts that are not multiples of four, that end
+just before or after a segment, a step or a chunk, and the largest bucket
+count, must all give the offsets (Section 3.5's exclusive sums) that the
+oracle computes from the same bucket function, the same largest bucket and
+mid/big bucket tallies, and a byte-exact sort."""
 import numpy as np
 import pytest
 
@@ -33,7 +35,9 @@ def env():
     ("uniform", 300_000, 1023),      # one segment less one bucket
     ("mixed", 300_000, 1025),        # one bucket into the second wave's segment
     ("uniform", 300_000, 16_383),    # every wave busy, the last one short
-    ("zipf", 300_000, 16_385),       # segments of 2048, the last wave nearly idle
+    ("skewed", 400_000, 16_384),     # the smallest chunked count: four full chunks
+    ("zipf", 300_000, 16_385),       # a fifth chunk of one bucket
+    ("mixed", 300_000, 20_479),      # the last chunk one bucket short
     ("uniform", 400_000, 65_537),
     ("skewed", 300_000, 1 << 21),    # the largest bucket count; most buckets empty
 ])
