@@ -254,8 +254,11 @@ __host__ __device__ __forceinline__ uint32_t spline_segments(uint32_t L) { retur
 // cell_shift): entry s counts the boundaries below its sub-cell s, exactly as
 // the cells do, so the search narrows to the boundaries of the code's
 // sub-cell.  Layout (32-bit words): per cell c a pair {ccells[c], info[c]},
-// info = (sub-table offset << 5) | k or 0 (no sub-table), for c = 0..NC (the
-// pair NC holds the boundary count only), then the sub-tables: cell c's at
+// info = (((sub-table offset << 5) | k) << 1) | 1 with a sub-table, else the
+// cell's own boundary count ccells[c + 1] - ccells[c] shifted left by one (so
+// a record in a cell without a sub-table reads one pair, not the next cell's
+// too: the compiler had deferred that load behind the test on info), for c =
+// 0..NC (the pair NC holds the boundary count only), then the sub-tables: cell c's at
 // offset 4 ccells[c] + c, 2^k + 1 <= 4 (ccells[c + 1] - ccells[c]) entries
 // (2^k < 4 x the cell's boundaries), so the tables never overlap and fit in
 // 4 L + NC + 1 words without any allocation step.
@@ -292,10 +295,10 @@ __device__ __forceinline__ uint32_t cell_exact_leaf(const uint32_t* __restrict__
   const uint32_t c = code_cell(code, e0, shift, nc);
   const uint2* cl = reinterpret_cast<const uint2*>(ccells);
   const uint2 x = cl[c];
-  uint32_t a = x.x, b = cl[c + 1].x;
-  if (x.y) {
-    const uint32_t k = x.y & 31u;
-    const uint32_t* sub = ccells + 2 * ((size_t)nc + 1) + (x.y >> 5);
+  uint32_t a = x.x, b = x.x + (x.y >> 1);
+  if (x.y & 1u) {
+    const uint32_t k = (x.y >> 1) & 31u;
+    const uint32_t* sub = ccells + 2 * ((size_t)nc + 1) + (x.y >> 6);
     const uint32_t s = code_subcell(code, e0, shift, c, k);
     a = sub[s];
     b = sub[s + 1];

@@ -441,23 +441,34 @@ __device__ __forceinline__ void bucket_sort_small_body(
   const uint32_t tid = threadIdx.x;
   const uint32_t j = bid;
   if (j >= B) return;
+  // the bucket's header words, loaded together before the test on its size
+  // (the empty asm statement takes them as operands, so the compiler cannot
+  // defer the other loads past the test: one round trip instead of three)
   BucketRef br;
   br.n = counts[j];
-  if (br.n == 0 || br.n > kSmCap) return;
   const uint32_t cap = caps[j];
-  br.nr = br.n < cap ? br.n : cap;
   br.rs = rstart[j];
   br.so = spill_off[j];
   br.out0 = offsets[j];
+  __asm__ volatile("" ::"s"(cap), "s"(br.rs), "s"(br.so), "s"(br.out0));
+  if (br.n == 0 || br.n > kSmCap) return;
+  br.nr = br.n < cap ? br.n : cap;
   const uint32_t n = br.n;
 
-  // 1. the first 16 bytes of every slot: index and key
-  uint4 v[AR];
+  // 1. the first 16 bytes of every slot: index and key.  The slots are found
+  //    first and the loads go out together, unconditionally (positions past
+  //    the bucket's end reload its last slot): a load under "p < n" was
+  //    waited for inside its branch, which made the four loads of a thread
+  //    four round trips.
+  uint32_t sl[AR];
 #pragma unroll
   for (uint32_t i = 0; i < AR; ++i) {
-    uint32_t p = tid + i * kSmThreads;
-    if (p < n) v[i] = slots[(uint64_t)slot_of(br, p, spill_map, cap_slots) * SC];
+    const uint32_t p = tid + i * kSmThreads;
+    sl[i] = slot_of(br, p < n ? p : n - 1, spill_map, cap_slots);
   }
+  uint4 v[AR];
+#pragma unroll
+  for (uint32_t i = 0; i < AR; ++i) v[i] = slots[(uint64_t)sl[i] * SC];
   if (vk) {
 #pragma unroll
     for (uint32_t i = 0; i < AR; ++i) virtual_key(v[i].y, v[i].z, v[i].w, vk);

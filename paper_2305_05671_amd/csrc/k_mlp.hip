@@ -607,9 +607,10 @@ __global__ __launch_bounds__(256) void code_cell_kernel(const uint64_t* __restri
   reinterpret_cast<uint2*>(ccells)[c] = make_uint2(lo - 1, 0u);
 }
 
-// Sub-tables of the dense cells (cell_exact_leaf): one wave per cell; entry s
-// (one lane each) = the boundaries below the cell + those of its sub-cells
-// below s, by a binary search over the cell's boundaries.
+// Info words of the cells and sub-tables of the dense ones (cell_exact_leaf):
+// one wave per cell; entry s (one lane each) = the boundaries below the cell +
+// those of its sub-cells below s, by a binary search over the cell's
+// boundaries.
 __global__ __launch_bounds__(256) void code_subcell_kernel(const uint64_t* __restrict__ bound, uint32_t L,
                                                            uint32_t* __restrict__ ccells,
                                                            ModelHeader* __restrict__ hdr) {
@@ -619,13 +620,16 @@ __global__ __launch_bounds__(256) void code_subcell_kernel(const uint64_t* __res
   if (c >= nc) return;
   uint2* cl = reinterpret_cast<uint2*>(ccells);
   const uint32_t lo = cl[c].x, hi = cl[c + 1].x;  // the cell's boundaries are bound[lo + 1 .. hi]
-  if (hi - lo <= kCellDense) return;
   uint32_t k = 1;
   while ((1u << k) < hi - lo) ++k;
   ++k;  // at least two sub-cells per boundary
   k = k < shift ? k : shift;
   k = k < 16u ? k : 16u;
-  if (k == 0) return;  // cells one code wide: nothing to split
+  // few boundaries, or cells one code wide (nothing to split): the count
+  if (hi - lo <= kCellDense || k == 0) {
+    if (lane == 0) cl[c].y = (hi - lo) << 1;
+    return;
+  }
   const uint64_t e0 = L >= 2 ? bound[1] : 0ull;
   const uint32_t o = 4 * lo + c;
   uint32_t* sub = ccells + 2 * ((size_t)nc + 1) + o;
@@ -638,7 +642,7 @@ __global__ __launch_bounds__(256) void code_subcell_kernel(const uint64_t* __res
     }
     sub[s] = a - 1;
   }
-  if (lane == 0) cl[c].y = (o << 5) | k;
+  if (lane == 0) cl[c].y = (((o << 5) | k) << 1) | 1u;
 }
 
 
