@@ -632,27 +632,33 @@ __device__ __forceinline__ void bucket_sort_lds_body(
   const uint32_t nitems = list ? *list_n : B;
   for (uint32_t it = bid; it < nitems; it += nblk) {
     const uint32_t j = list ? list[from_end ? B - 1 - it : it] : it;
+    // the header words together, before the test on the count (as in the
+    // small-bucket kernel)
     BucketRef br;
     br.n = counts[j];
-    if (br.n == 0 || br.n > CAP) continue;
     const uint32_t cap = caps[j];
-    br.nr = br.n < cap ? br.n : cap;
     br.rs = rstart[j];
     br.so = spill_off[j];
     br.out0 = offsets[j];
-    // 1. load the entries (every thread's slot heads in flight together), and
-    //    the range of their base-95 codes
+    __asm__ volatile("" ::"s"(cap), "s"(br.rs), "s"(br.so), "s"(br.out0));
+    if (br.n == 0 || br.n > CAP) continue;
+    br.nr = br.n < cap ? br.n : cap;
+    // 1. load the entries (every thread's slot heads in flight together, past
+    //    the bucket's end its last slot again), and the range of their
+    //    base-95 codes
     uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
     uint64_t cmin = ~0ull, cmax = 0;
     constexpr uint32_t NL = (CAP / THREADS) % 3 == 0 ? 3 : 4;  // heads per thread in flight
     for (uint32_t p0 = 0; p0 < br.n; p0 += NL * THREADS) {
-     uint4 hv[NL];
+     uint32_t sl[NL];
 #pragma unroll
      for (uint32_t i = 0; i < NL; ++i) {
       const uint32_t p = p0 + threadIdx.x + i * THREADS;
-      if (p < br.n)
-        hv[i] = *reinterpret_cast<const uint4*>(slots + (uint64_t)slot_of(br, p, spill_map, cap_slots) * W);
+      sl[i] = slot_of(br, p < br.n ? p : br.n - 1, spill_map, cap_slots);
      }
+     uint4 hv[NL];
+#pragma unroll
+     for (uint32_t i = 0; i < NL; ++i) hv[i] = *reinterpret_cast<const uint4*>(slots + (uint64_t)sl[i] * W);
 #pragma unroll
      for (uint32_t i = 0; i < NL; ++i) {
       const uint32_t p = p0 + threadIdx.x + i * THREADS;
@@ -831,12 +837,15 @@ __device__ __forceinline__ void equal_keys_body(
     uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
     uint64_t imin = ~0ull, imax = 0;
     for (uint32_t p0 = 0; p0 < n; p0 += kEqLoads * kEqThreads) {
-      uint4 hv[kEqLoads];
+      uint32_t sl[kEqLoads];
 #pragma unroll
       for (uint32_t i = 0; i < kEqLoads; ++i) {
         const uint32_t p = p0 + tid + i * kEqThreads;
-        if (p < n) hv[i] = *reinterpret_cast<const uint4*>(slots + (uint64_t)slot_of(br, p, spill_map, cap_slots) * W);
+        sl[i] = slot_of(br, p < n ? p : n - 1, spill_map, cap_slots);  // past the end: the last slot again
       }
+      uint4 hv[kEqLoads];
+#pragma unroll
+      for (uint32_t i = 0; i < kEqLoads; ++i) hv[i] = *reinterpret_cast<const uint4*>(slots + (uint64_t)sl[i] * W);
 #pragma unroll
       for (uint32_t i = 0; i < kEqLoads; ++i) {
         const uint32_t p = p0 + tid + i * kEqThreads;
@@ -1350,11 +1359,17 @@ __device__ __forceinline__ void seg_sort_body(const uint32_t* __restrict__ count
     const uint32_t* X = (sg.w ? Bf : A) + 5ull * sg.y;
     uint32_t* refs = out + offsets[sg.x] * RW + (uint64_t)(RW - 1) * nb + sg.y;
     uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
+    uint4 kv[AR];  // every key load in flight together (past the end: the last entry again)
+#pragma unroll
+    for (uint32_t i = 0; i < AR; ++i) {
+      const uint32_t q = tid + i * kSmThreads;
+      kv[i] = get_key(X, q < n ? q : n - 1);
+    }
 #pragma unroll
     for (uint32_t i = 0; i < AR; ++i) {
       const uint32_t q = tid + i * kSmThreads;
       if (q < n) {
-        const uint4 c = get_key(X, q);
+        const uint4 c = kv[i];
         cw[0][q] = c.x; cw[1][q] = c.y; cw[2][q] = c.z; cw[3][q] = c.w;
         o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
         a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
@@ -1508,11 +1523,20 @@ __global__ __launch_bounds__(kSmThreads) void tiny_jobs_kernel(const TinyJob* __
     }
     uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
     uint64_t cmin = ~0ull, cmax = 0;
+    uint32_t kr[AR][3];  // every key load in flight together (past the end: the last record again)
+#pragma unroll
+    for (uint32_t i = 0; i < AR; ++i) {
+      const uint32_t q = tid + i * kSmThreads;
+      const uint32_t* r = src + (uint64_t)(q < n ? q : n - 1) * RW;
+      kr[i][0] = r[0];
+      kr[i][1] = r[1];
+      kr[i][2] = r[2];
+    }
 #pragma unroll
     for (uint32_t i = 0; i < AR; ++i) {
       const uint32_t q = tid + i * kSmThreads;
       if (q < n) {
-        const uint32_t* r = src + (uint64_t)q * RW;
+        const uint32_t* r = kr[i];
         const uint4 c = composite_words(q, r[0], r[1], r[2], K);
         cw[0][q] = c.x; cw[1][q] = c.y; cw[2][q] = c.z; cw[3][q] = c.w;
         o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;

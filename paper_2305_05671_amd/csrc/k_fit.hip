@@ -54,11 +54,21 @@ __global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const uint64_
                                                                    uint32_t* __restrict__ tile_hist) {
   __shared__ uint32_t cnt[256];
   cnt[threadIdx.x] = 0;
-  __syncthreads();
-  uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
+  const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
+  // every load first, unconditionally (the index clamped to the last key):
+  // a load under "i < n" was waited for inside its branch, one round trip
+  // per key
+  uint64_t key[kRadixRounds];
+#pragma unroll
   for (int k = 0; k < kRadixRounds; ++k) {
-    uint64_t i = base + (uint64_t)k * kRadixThreads + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 0xFFu], 1u);
+    const uint64_t i = base + (uint64_t)k * kRadixThreads + threadIdx.x;
+    key[k] = keys[i < n ? i : n - 1];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kRadixRounds; ++k) {
+    const uint64_t i = base + (uint64_t)k * kRadixThreads + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(key[k] >> shift) & 0xFFu], 1u);
   }
   __syncthreads();
   tile_hist[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
@@ -110,21 +120,15 @@ __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(const uint
   uint64_t base = (uint64_t)blockIdx.x * kRadixTile + (uint64_t)w * 64 * kRadixRounds;
   uint64_t key[kRadixRounds];
   uint32_t loc[kRadixRounds];
+  // every load first, the tile's digit offsets included (the key index
+  // clamped to the last key; invalid lanes take no part below): issued
+  // inside the rank loop, each round's load was waited for before the next
+  // one went out
 #pragma unroll
   for (int r = 0; r < kRadixRounds; ++r) {
-    uint64_t i = base + (uint64_t)r * 64 + lane_id();
-    bool valid = i < n;
-    key[r] = valid ? in[i] : 0;
-    uint32_t d = (uint32_t)(key[r] >> shift) & 0xFFu;
-    uint64_t peers = match_digit8(d, valid);
-    uint32_t rank = __popcll(peers & lanemask_lt());
-    uint32_t prev = valid ? wc[w][d] : 0u;
-    loc[r] = prev + rank;
-    __builtin_amdgcn_wave_barrier();
-    if (valid && rank == 0) wc[w][d] = prev + (uint32_t)__popcll(peers);
-    __builtin_amdgcn_wave_barrier();
+    const uint64_t i = base + (uint64_t)r * 64 + lane_id();
+    key[r] = in[i < n ? i : n - 1];
   }
-  __syncthreads();
   uint32_t dtot, before = 0, total = 0;
   if (fused) {
     const uint32_t* h = tile_off + (uint64_t)threadIdx.x * ntiles;
@@ -137,6 +141,20 @@ __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(const uint
     before = tile_off[(uint64_t)threadIdx.x * ntiles + blockIdx.x];
     total = digit_tot[threadIdx.x];
   }
+#pragma unroll
+  for (int r = 0; r < kRadixRounds; ++r) {
+    uint64_t i = base + (uint64_t)r * 64 + lane_id();
+    bool valid = i < n;
+    uint32_t d = (uint32_t)(key[r] >> shift) & 0xFFu;
+    uint64_t peers = match_digit8(d, valid);
+    uint32_t rank = __popcll(peers & lanemask_lt());
+    uint32_t prev = valid ? wc[w][d] : 0u;
+    loc[r] = prev + rank;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == 0) wc[w][d] = prev + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
   uint32_t dbase = block_exclusive_scan<uint32_t, kRadixThreads>(total, sh, &dtot);
   {
     uint32_t d = threadIdx.x, run = 0;
@@ -665,15 +683,18 @@ __device__ __forceinline__ void capacity_body(const uint32_t* __restrict__ hist,
   const uint32_t WS = ((B + kScanWaves - 1) / kScanWaves + 1023) & ~1023u;
   const uint32_t w = threadIdx.x >> 6, l = lane_id();
   const uint32_t s0 = w * WS, s1 = s0 + WS < B ? s0 + WS : B;  // empty when s0 >= B
-  // sample counts of buckets j .. j+3 (zero past the segment)
+  // sample counts of buckets j .. j+3 (zero past the segment), one 16-byte
+  // load with no branch around it (a load inside a branch is waited for
+  // there, which made the steps' loads one round trip each): past the end of
+  // the histogram it reads its last vector again, and its 256-byte padding
+  // keeps that vector's tail in bounds
+  const uint32_t jlast = (B - 1) & ~3u;
   auto load4 = [&](uint32_t j, uint32_t h[4]) {
-    if (j + 4 <= s1) {
-      const uint4 x = *reinterpret_cast<const uint4*>(hist + j);
-      h[0] = x.x; h[1] = x.y; h[2] = x.z; h[3] = x.w;
-    } else {
-#pragma unroll
-      for (uint32_t q = 0; q < 4; ++q) h[q] = j + q < s1 ? hist[j + q] : 0u;
-    }
+    const uint4 x = *reinterpret_cast<const uint4*>(hist + (j < B ? j : jlast));
+    h[0] = j < s1 ? x.x : 0u;
+    h[1] = j + 1 < s1 ? x.y : 0u;
+    h[2] = j + 2 < s1 ? x.z : 0u;
+    h[3] = j + 3 < s1 ? x.w : 0u;
   };
   const double per = (double)n / (double)S;
   auto size_of = [&](uint32_t j, uint32_t h) { return j < s1 ? region_slots(h, per, ideal, scale) : 0u; };

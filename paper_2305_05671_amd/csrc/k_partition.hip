@@ -574,15 +574,18 @@ __device__ __forceinline__ void scan_counts_body(const uint32_t* __restrict__ co
   const uint32_t WS = ((B + kScanWaves - 1) / kScanWaves + 1023) & ~1023u;
   const uint32_t w = threadIdx.x >> 6, l = lane_id();
   const uint32_t s0 = w * WS, s1 = s0 + WS < B ? s0 + WS : B;  // empty when s0 >= B
-  // values of buckets j .. j+3 (zero past the segment)
+  // values of buckets j .. j+3 (zero past the segment), one 16-byte load
+  // with no branch around it (a load inside a branch is waited for there,
+  // which made the steps' loads one round trip each): past the end of the
+  // array it reads its last vector again, and the array's 256-byte padding
+  // keeps that vector's tail in bounds
+  const uint32_t jlast = (B - 1) & ~3u;
   auto load4 = [&](const uint32_t* src, uint32_t j, uint32_t v[4]) {
-    if (j + 4 <= s1) {
-      const uint4 x = *reinterpret_cast<const uint4*>(src + j);
-      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-    } else {
-#pragma unroll
-      for (uint32_t q = 0; q < 4; ++q) v[q] = j + q < s1 ? src[j + q] : 0u;
-    }
+    const uint4 x = *reinterpret_cast<const uint4*>(src + (j < B ? j : jlast));
+    v[0] = j < s1 ? x.x : 0u;
+    v[1] = j + 1 < s1 ? x.y : 0u;
+    v[2] = j + 2 < s1 ? x.z : 0u;
+    v[3] = j + 3 < s1 ? x.w : 0u;
   };
   // counts of buckets j .. j+3 (zero past the segment), wherever the counters sit
   auto loadc = [&](uint32_t j, uint32_t v[4]) {
@@ -590,7 +593,10 @@ __device__ __forceinline__ void scan_counts_body(const uint32_t* __restrict__ co
       load4(counts, j, v);
     } else {
 #pragma unroll
-      for (uint32_t q = 0; q < 4; ++q) v[q] = j + q < s1 ? counts[(uint64_t)(j + q) * cstride] : 0u;
+      for (uint32_t q = 0; q < 4; ++q) {
+        const uint32_t c = counts[(uint64_t)(j + q < B ? j + q : B - 1) * cstride];
+        v[q] = j + q < s1 ? c : 0u;
+      }
     }
   };
   auto over = [](uint32_t c, uint32_t k) { return c > k ? c - k : 0u; };
