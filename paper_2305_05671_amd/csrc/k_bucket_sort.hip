@@ -1140,6 +1140,7 @@ __global__ __launch_bounds__(kBigThreads) void bucket_sort_global_kernel(
 constexpr uint32_t kSegCap = kSmallCap;
 constexpr uint32_t kMsdThreads = 1024;
 constexpr uint32_t kMsdWaves = kMsdThreads / 64;
+constexpr uint32_t kMsdUnroll = 4;  // entries a thread loads together in a scatter step
 
 __device__ __forceinline__ uint32_t first_varying_byte(uint32_t vary) {  // vary != 0
   return (uint32_t)__builtin_ctz(vary);  // bit p = composite byte p, byte 0 most significant
@@ -1165,12 +1166,24 @@ __device__ void msd_scatter(MsdShared& sh, const uint32_t* __restrict__ X, uint3
   const uint32_t tid = threadIdx.x;
   if (tid < 256) sh.hist[tid] = 0;
   __syncthreads();
-  for (uint32_t i0 = 0; i0 < c; i0 += kMsdThreads) {
-    const uint32_t i = i0 + tid;
-    const bool valid = i < c;
-    const uint32_t d = valid ? digit_of(get_key(X, s + i), p) : 0u;
-    const uint64_t peers = match_digit8(d, valid);
-    if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&sh.hist[d], (uint32_t)__popcll(peers));
+  // kMsdUnroll entries a thread per step, their loads issued together before
+  // any is used (past the end: the last entry again, not counted); one entry
+  // a step, each step waited for its own load
+  for (uint32_t i0 = 0; i0 < c; i0 += kMsdUnroll * kMsdThreads) {
+    uint32_t dd[kMsdUnroll];
+#pragma unroll
+    for (uint32_t u = 0; u < kMsdUnroll; ++u) {
+      const uint32_t i = i0 + u * kMsdThreads + tid;
+      dd[u] = digit_of(get_key(X, s + (i < c ? i : c - 1)), p);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kMsdUnroll; ++u) {
+      const uint32_t i = i0 + u * kMsdThreads + tid;
+      const bool valid = i < c;
+      const uint32_t d = valid ? dd[u] : 0u;
+      const uint64_t peers = match_digit8(d, valid);
+      if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&sh.hist[d], (uint32_t)__popcll(peers));
+    }
   }
   __syncthreads();
   // exclusive scan of the 256 digit counts by the first four waves
@@ -1192,23 +1205,30 @@ __device__ void msd_scatter(MsdShared& sh, const uint32_t* __restrict__ X, uint3
     sh.cursor[tid] = sh.base[tid];
   }
   __syncthreads();
-  for (uint32_t i0 = 0; i0 < c; i0 += kMsdThreads) {
-    const uint32_t i = i0 + tid;
-    const bool valid = i < c;
-    uint32_t e0 = 0, e1 = 0, e2 = 0, e3 = 0, e4 = 0, d = 0;
-    if (valid) {
-      const uint32_t* src = X + 5ull * (s + i);
-      e0 = src[0]; e1 = src[1]; e2 = src[2]; e3 = src[3]; e4 = src[4];
-      d = digit_of(make_uint4(e0, e1, e2, e3), p);
+  for (uint32_t i0 = 0; i0 < c; i0 += kMsdUnroll * kMsdThreads) {
+    uint32_t e[kMsdUnroll][5];
+#pragma unroll
+    for (uint32_t u = 0; u < kMsdUnroll; ++u) {
+      const uint32_t i = i0 + u * kMsdThreads + tid;
+      const uint32_t* src = X + 5ull * (s + (i < c ? i : c - 1));
+#pragma unroll
+      for (uint32_t w = 0; w < 5; ++w) e[u][w] = src[w];
     }
-    const uint64_t peers = match_digit8(d, valid);
-    const uint32_t leader = peers ? (uint32_t)__builtin_ctzll(peers) : 0u;
-    uint32_t got = 0;
-    if (valid && lane_id() == leader) got = atomicAdd(&sh.cursor[d], (uint32_t)__popcll(peers));
-    got = __shfl(got, (int)leader);
-    if (valid) {
-      uint32_t* dst = Y + 5ull * (s + got + (uint32_t)__popcll(peers & lanemask_lt()));
-      dst[0] = e0; dst[1] = e1; dst[2] = e2; dst[3] = e3; dst[4] = e4;
+#pragma unroll
+    for (uint32_t u = 0; u < kMsdUnroll; ++u) {
+      const uint32_t i = i0 + u * kMsdThreads + tid;
+      const bool valid = i < c;
+      const uint32_t d = valid ? digit_of(make_uint4(e[u][0], e[u][1], e[u][2], e[u][3]), p) : 0u;
+      const uint64_t peers = match_digit8(d, valid);
+      const uint32_t leader = peers ? (uint32_t)__builtin_ctzll(peers) : 0u;
+      uint32_t got = 0;
+      if (valid && lane_id() == leader) got = atomicAdd(&sh.cursor[d], (uint32_t)__popcll(peers));
+      got = __shfl(got, (int)leader);
+      if (valid) {
+        uint32_t* dst = Y + 5ull * (s + got + (uint32_t)__popcll(peers & lanemask_lt()));
+#pragma unroll
+        for (uint32_t w = 0; w < 5; ++w) dst[w] = e[u][w];
+      }
     }
   }
   __syncthreads();
@@ -1282,12 +1302,30 @@ __device__ __forceinline__ void msd_split_body(
       sh.overflow = 0;
     }
     uint4 o = make_uint4(0, 0, 0, 0), a = make_uint4(~0u, ~0u, ~0u, ~0u);
-    for (uint32_t q = threadIdx.x; q < br.n; q += kMsdThreads) {
-      const uint32_t sl = slot_of(br, q, spill_map, cap_slots);
-      const uint4 c = composite(slots + (uint64_t)sl * W, K, vk);
-      put_entry(Bf, q, c, sl);
-      o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
-      a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+    // kMsdUnroll slot heads a thread per step, loaded together (past the end:
+    // the last slot again, not stored)
+    for (uint32_t q0 = 0; q0 < br.n; q0 += kMsdUnroll * kMsdThreads) {
+      uint32_t sl[kMsdUnroll];
+#pragma unroll
+      for (uint32_t u = 0; u < kMsdUnroll; ++u) {
+        const uint32_t q = q0 + u * kMsdThreads + threadIdx.x;
+        sl[u] = slot_of(br, q < br.n ? q : br.n - 1, spill_map, cap_slots);
+      }
+      uint4 hv[kMsdUnroll];
+#pragma unroll
+      for (uint32_t u = 0; u < kMsdUnroll; ++u) hv[u] = *reinterpret_cast<const uint4*>(slots + (uint64_t)sl[u] * W);
+#pragma unroll
+      for (uint32_t u = 0; u < kMsdUnroll; ++u) {
+        const uint32_t q = q0 + u * kMsdThreads + threadIdx.x;
+        if (q < br.n) {
+          uint32_t r0 = hv[u].y, r1 = hv[u].z, r2 = hv[u].w;
+          virtual_key(r0, r1, r2, vk);
+          const uint4 c = composite_words(hv[u].x, r0, r1, r2, K);
+          put_entry(Bf, q, c, sl[u]);
+          o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
+          a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+        }
+      }
     }
     uint32_t vary = varying_bytes<kMsdThreads>(o, a, sh.sh_or, sh.sh_and);  // syncs
     msd_scatter(sh, Bf, A, j, 0, br.n, first_varying_byte(vary), 0u, leaf, leaf_n, leaf_cap, stack, stack_cap);
@@ -1309,10 +1347,19 @@ __device__ __forceinline__ void msd_split_body(
       uint32_t* Y = sg.z ? A : Bf;
       o = make_uint4(0, 0, 0, 0);
       a = make_uint4(~0u, ~0u, ~0u, ~0u);
-      for (uint32_t q = threadIdx.x; q < sg.y; q += kMsdThreads) {
-        const uint4 c = get_key(X, sg.x + q);
-        o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
-        a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+      for (uint32_t q0 = 0; q0 < sg.y; q0 += kMsdUnroll * kMsdThreads) {
+        uint4 kv[kMsdUnroll];  // loaded together; past the piece's end its last entry again
+#pragma unroll
+        for (uint32_t u = 0; u < kMsdUnroll; ++u) {
+          const uint32_t q = q0 + u * kMsdThreads + threadIdx.x;
+          kv[u] = get_key(X, sg.x + (q < sg.y ? q : sg.y - 1));
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kMsdUnroll; ++u) {
+          const uint4 c = kv[u];  // a repeated entry changes neither the OR nor the AND
+          o.x |= c.x; o.y |= c.y; o.z |= c.z; o.w |= c.w;
+          a.x &= c.x; a.y &= c.y; a.z &= c.z; a.w &= c.w;
+        }
       }
       vary = varying_bytes<kMsdThreads>(o, a, sh.sh_or, sh.sh_and);
       msd_scatter(sh, X, Y, j, sg.x, sg.y, first_varying_byte(vary), sg.z ^ 1u, leaf, leaf_n, leaf_cap, stack,
