@@ -1859,12 +1859,16 @@ WinGrids window_grids(uint64_t nmax, uint32_t Bmax, uint32_t tiles_per_block) {
   const uint64_t ntiles = (nmax + 255) / 256;  // partition tiles of the largest job
   g.part = tiles_per_block ? (uint32_t)std::min<uint64_t>((ntiles + tiles_per_block - 1) / tiles_per_block, 1u << 16)
                            : partition_grid(nmax);
-  g.fixup = spill_fixup_grid(nmax);
+  // Per job, the kernels after the small-bucket sort loop over their lists
+  // with fewer blocks than one job of its size gets: a window launches them
+  // for all its jobs at once, so the GPU stays full, and the empty blocks of
+  // jobs with short lists (most of them) cost dispatch time
+  g.fixup = std::min<uint32_t>(spill_fixup_grid(nmax), 256);
   g.small = Bmax;
-  g.mid = grid_for(nmax, kSmallCap + 1, 256);
-  g.split = grid_for(nmax, kMidCap + 1, 512);
-  g.seg = grid_for(nmax, 1024, 2048);
-  g.gather = grid_for(nmax, kMidCap + 1, 512);
+  g.mid = grid_for(nmax, kSmallCap + 1, 64);
+  g.split = grid_for(nmax, kMidCap + 1, 128);
+  g.seg = grid_for(nmax, 1024, 256);
+  g.gather = grid_for(nmax, kMidCap + 1, 128);
   return g;
 }
 
