@@ -283,7 +283,8 @@ def _oracle_stats(elsar, m, recs, seed, B):
 
 @pytest.mark.parametrize("kind,sigma,n,B,seed", [("skewed", 6.0, 1_000_000, 1024, 2),
                                                  ("skewed", 16.0, 400_000, 1024, 3),
-                                                 ("uniform", 6.0, 500_000, 512, 4)])
+                                                 ("uniform", 6.0, 500_000, 512, 4),
+                                                 ("skewed", 6.0, 400_000, 1021, 5)])  # histogram tails
 def test_acceptance_statistics_and_decisions(env, kind, sigma, n, B, seed):
     # The device's acceptance statistics against the oracle's on the oracle's
     # sample, then the decisions with the threshold placed 5% either side of

@@ -77,7 +77,8 @@ def test_fitted_spline_model(env, kind, n, B, leaves, seed):
 
 
 @pytest.mark.parametrize("kind,n,B,seed", [
-    ("skewed", 300_000, 0, 2), ("zipf", 200_000, 256, 3), ("mixed", 150_000, 4096, 6), ("uniform", 100_000, 0, 7)])
+    ("skewed", 300_000, 0, 2), ("zipf", 200_000, 256, 3), ("mixed", 150_000, 4096, 6), ("uniform", 100_000, 0, 7),
+    ("skewed", 200_000, 1027, 8)])  # a bucket count that is not a multiple of four: the scans' tails
 def test_sort_with_spline_root_matches_oracle(env, kind, n, B, seed):
     torch, elsar = env
     recs = datagen.generate(datagen.spec(kind, seed=seed), n)
