@@ -1167,8 +1167,8 @@ __device__ void msd_scatter(MsdShared& sh, const uint32_t* __restrict__ X, uint3
   if (tid < 256) sh.hist[tid] = 0;
   __syncthreads();
   // kMsdUnroll entries a thread per step, their loads issued together before
-  // any is used (past the end: the last entry again, not counted); one entry
-  // a step, each step waited for its own load
+  // any is used (past the end: the last entry again, not counted); with one
+  // entry a step, every step had waited for its own load
   for (uint32_t i0 = 0; i0 < c; i0 += kMsdUnroll * kMsdThreads) {
     uint32_t dd[kMsdUnroll];
 #pragma unroll

@@ -407,7 +407,6 @@ __global__ __launch_bounds__(256) void count_kernel(const ModelHeader* __restric
                                                     uint64_t n, uint32_t RW, uint32_t* __restrict__ counts,
                                                     uint32_t vk) {
   constexpr bool MLP = ROOT == 1;
-  constexpr bool HOIST = ROOT == 0;
   if (hdr->kind_used != (uint32_t)ROOT) return;
   __shared__ typename std::conditional<MLP, MlpHead, uint32_t>::type mh_;
   MlpFrags w2;
