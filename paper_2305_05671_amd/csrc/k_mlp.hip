@@ -824,7 +824,7 @@ __global__ __launch_bounds__(kDecideThreads) void decide_root_kernel(const uint3
   __shared__ uint32_t mr[W], me[W], mn[W];
   __shared__ uint32_t use_eq;
   // the largest count of each histogram: four buckets a thread per step as
-  // 16-byte loads (the arrays are 256-byte aligned), one loop per array and
+  // 16-byte loads (the arrays start 16-byte aligned), one loop per array and
   // no branch around the loads, so that the unrolled steps' loads are in
   // flight together (one bucket at a time they took 31-47 us on one CU)
   const uint32_t B4 = B & ~3u;

@@ -576,8 +576,8 @@ __device__ __forceinline__ void scan_counts_body(const uint32_t* __restrict__ co
   // values of buckets j .. j+3 (zero past the segment), one 16-byte load
   // with no branch around it (a load inside a branch is waited for there,
   // which made the steps' loads one round trip each): past the end of the
-  // array it reads its last vector again, and the array's 256-byte padding
-  // keeps that vector's tail in bounds
+  // array it reads its last vector again, and the array's space, rounded up
+  // to a multiple of 256 bytes, keeps that vector's tail in bounds
   const uint32_t jlast = (B - 1) & ~3u;
   auto load4 = [&](const uint32_t* src, uint32_t j, uint32_t v[4]) {
     const uint4 x = *reinterpret_cast<const uint4*>(src + (j < B ? j : jlast));
